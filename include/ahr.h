@@ -1,0 +1,221 @@
+/*
+ * ahr.h -- C ABI of libahr, an MI355X (gfx950) implementation of the signed
+ * netlist graph filter at the heart of the area-hint refinement initializer
+ * of "Bridging the Initialization Gap: A Co-Optimization Framework for
+ * Mixed-Size Global Placement" (arXiv 2511.10073).
+ *
+ * The method (Section V of the paper):
+ *   - a placement instance is a graph G = (V, E) whose nodes are the objects
+ *     and whose nets are edges (Section IV, problem statement);
+ *   - a fixed macro is split into fixed nodes at its pin sites (Section V,
+ *     "Macro pin expansion");
+ *   - one virtual node per macro joined by negative edges to the movable
+ *     cells inside its footprint (Section V, "Macro virtual node");
+ *   - one virtual node per bin joined by signed, density-aware edges to the
+ *     movable cells in a detection window (Section V, "Bin virtual node");
+ *   - the refinement filter H_r = ((lambda_up I - L_hint)/lambda_up)^k with
+ *     lambda_up a Gershgorin bound (Section V, eq. "refine-filter");
+ *   - Algorithm 1: T_hint rounds of build / filter / relax (Section V);
+ *   - the half-perimeter wirelength that scores a placement.
+ *
+ * Readings of passages the paper leaves open (net model, signed degree,
+ * normalisation, window shape, pinning) are fixed the same way here and in
+ * the project's CPU oracle; each is named where it applies below.
+ *
+ * Conventions for every call:
+ *   - All array pointers are DEVICE pointers on the current HIP device unless
+ *     marked "host".  The caller owns them; the library never frees them and
+ *     keeps no pointer to them after the call returns, except the netlist
+ *     arrays a graph handle was built from (those must outlive the handle).
+ *   - Signals are row-major [rows][ncols] float32; ncols is 1, 2, 4 or 8.
+ *     Columns 2c and 2c+1 are the x and y of placement c.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on it unless documented as synchronous; calls that size
+ *     device memory from device-computed counts synchronise the stream.
+ *   - Every call returns an ahr_status.  Arguments are validated before any
+ *     device work is queued, so an AHR_EINVAL return leaves outputs untouched.
+ *     ahr_last_error() returns a message for the calling thread's last error.
+ *   - Index ranges are int32: more than 2^31 - 1 nodes, pins or graph entries
+ *     give AHR_EUNSUPPORTED.
+ *   - Results are deterministic: the same inputs give bit-identical outputs.
+ *   - Calls on one graph handle must not overlap (same or different streams).
+ */
+#ifndef AHR_H
+#define AHR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ahr_status;
+#define AHR_OK 0
+#define AHR_EINVAL (-1)          /* bad argument; nothing was launched        */
+#define AHR_ENOMEM (-2)          /* device allocation failed                   */
+#define AHR_EDEVICE (-3)         /* a HIP call failed                          */
+#define AHR_EUNSUPPORTED (-4)    /* valid but outside what this build handles  */
+
+/* node_flags bits */
+#define AHR_NODE_FIXED 1u
+#define AHR_NODE_MACRO 2u
+
+/* A netlist (Section IV: objects are nodes, nets are hyperedges).
+ * Instances are numbered 0..n_inst-1.  A movable standard cell has flags 0;
+ * a macro has AHR_NODE_MACRO (plus AHR_NODE_FIXED if fixed); an I/O pin has
+ * AHR_NODE_FIXED.  Net e holds pins net_ptr[e] .. net_ptr[e+1]-1. */
+typedef struct ahr_netlist {
+    int32_t n_inst;
+    int32_t n_nets;
+    int32_t n_pins;
+    int32_t reserved0;          /* must be 0 */
+    const int32_t* net_ptr;     /* [n_nets + 1], non-decreasing, net_ptr[0] = 0 */
+    const int32_t* pin_node;    /* [n_pins] instance of each pin, in [0, n_inst) */
+    const float* pin_off;       /* [n_pins][2] pin offset from the instance centre */
+    const float* net_w;         /* [n_nets] net weights, or NULL for all 1 */
+    const uint8_t* node_flags;  /* [n_inst] */
+    const float* node_size;     /* [n_inst][2] width, height */
+    float die[4];               /* host values: xl, yl, xh, yh (xl < xh, yl < yh) */
+} ahr_netlist;
+
+/* ahr_hint_params.flags */
+#define AHR_EXPAND_MACRO_PINS 1u  /* Section V, macro pin expansion (fixed macros) */
+#define AHR_MACRO_HINTS 2u        /* Section V, macro virtual nodes               */
+#define AHR_BIN_HINTS 4u          /* Section V, bin virtual nodes                 */
+#define AHR_ALL_HINTS 7u
+
+/* Area-hint parameters (Section V; the refinement block of the paper's
+ * parameter table: refine_num_bin_xy, detection_ratio, bin_capacity). */
+typedef struct ahr_hint_params {
+    int32_t nbx, nby;           /* numBin_x, numBin_y, each in [1, 4096] */
+    float detection_ratio;      /* window n = max(1, floor(ratio * numBin)), ratio in [0, 1] */
+    float bin_capacity;         /* C in phi_b = 2 sigmoid(mu (D_b - C)) - 1 */
+    float mu;                   /* mu > 0 */
+    int32_t clique_max;         /* nets with 2 <= p <= clique_max are cliques, larger ones stars; >= 1 */
+    uint32_t flags;             /* AHR_EXPAND_MACRO_PINS | AHR_MACRO_HINTS | AHR_BIN_HINTS */
+} ahr_hint_params;
+
+#define AHR_LAMBDA_GERSHGORIN 0
+#define AHR_LAMBDA_FIXED 1
+#define AHR_MAX_BANDS 4
+
+/* Polynomial filter out = sum_b alpha[b] T^k[b] X with T = I - L/lambda_up
+ * (Section V eq. "refine-filter"; a bank of such powers as in Section IV eq.
+ * "GiFt filter").  k[b] in [0, 64]; sigma >= 0 is the self-loop weight of
+ * Section IV (A_sigma = A + sigma I). */
+typedef struct ahr_filter_spec {
+    int32_t nbands;             /* 1..AHR_MAX_BANDS */
+    int32_t k[AHR_MAX_BANDS];
+    float alpha[AHR_MAX_BANDS];
+    float sigma;
+    int32_t lambda_mode;        /* AHR_LAMBDA_GERSHGORIN or AHR_LAMBDA_FIXED */
+    float lambda_fixed;         /* used when lambda_mode == AHR_LAMBDA_FIXED; >= 0 */
+} ahr_filter_spec;
+
+typedef struct ahr_graph ahr_graph;   /* opaque; owns its device memory */
+
+/* Sizes and node ranges of a built graph (host struct).  Canonical node
+ * order: instances [0, n_inst); macro pin nodes [first_mpin, first_star)
+ * in pin order; star nodes [first_star, first_mvirt) in net order; macro
+ * virtual nodes [first_mvirt, first_bvirt) in instance order; bin virtual
+ * nodes [first_bvirt, n_tot) row-major by (by, bx). */
+typedef struct ahr_graph_info {
+    int32_t n_inst, n_tot;
+    int32_t first_mpin, first_star, first_mvirt, first_bvirt;
+    int32_t nnz_net, nnz_hint;
+    int32_t n_hint_cells;       /* movable standard cells that carry hint edges */
+    int32_t n_long_rows;        /* rows the filter splits over several workgroups */
+    int32_t hint_version;       /* incremented by every hint (re)build */
+    int32_t reserved;
+} ahr_graph_info;
+
+/* Host buffers for ahr_graph_export; each pointer may be NULL to skip it.
+ * Sizes: net_row_ptr/hint_row_ptr [n_tot+1], net_col/net_q [nnz_net],
+ * hint_col/hint_val [nnz_hint], degree/scale [n_tot]. */
+typedef struct ahr_graph_host {
+    int32_t* net_row_ptr;
+    int32_t* net_col;
+    int64_t* net_q;             /* netlist weights in units of 2^-32 */
+    int32_t* hint_row_ptr;
+    int32_t* hint_col;
+    float* hint_val;
+    double* degree;             /* d_i = sum_j |A_ij| (+ sigma) of the last filter's operator */
+    float* scale;               /* s_i = (d_i)^-1/2, 0 for isolated rows */
+    float* lambda_up;           /* one value */
+} ahr_graph_host;
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* ahr_last_error(void);
+
+/* Library version, e.g. "ahr 0.1 gfx950". */
+const char* ahr_version(void);
+
+/* Build the graph of a netlist (Section V: macro pin expansion, then the
+ * clique/star net model -- reading: weight w/(p-1) per pin pair for
+ * 2 <= p <= clique_max, else a star node with w p/(p-1) per spoke -- with
+ * parallel edges summed exactly in units of 2^-32) and, if `g` is not
+ * NULL, the area hints of the placement held in columns 0 and 1 of `g`
+ * ([n_inst][ncols]).  The netlist arrays must stay valid and unchanged
+ * while the handle lives.  On success *out receives a handle the caller
+ * frees with ahr_graph_destroy.  Synchronises `stream`. */
+ahr_status ahr_graph_build(const ahr_netlist* nl, const ahr_hint_params* hp,
+                           const float* g, int32_t ncols, void* stream,
+                           ahr_graph** out);
+
+/* Rebuild the area hints (BuildLap of Algorithm 1: bin densities, phi_b,
+ * bin-window and macro-footprint edges) for the placement in columns 0 and
+ * 1 of `g` ([n_inst][ncols]).  Synchronises `stream`. */
+ahr_status ahr_graph_update_hints(ahr_graph* gr, const float* g, int32_t ncols,
+                                  void* stream);
+
+/* Sizes and node ranges (host struct; no device work). */
+ahr_status ahr_graph_get_info(const ahr_graph* gr, ahr_graph_info* info);
+
+/* Copy the graph to host buffers (synchronous; for tests).  Rows are in
+ * canonical node order.  Netlist rows list columns in ascending order;
+ * virtual rows list their cells grouped by bin (row-major), ascending
+ * within a bin -- the order the filter sums them in. */
+ahr_status ahr_graph_export(const ahr_graph* gr, ahr_graph_host* dst, void* stream);
+
+/* Free a graph and its device memory (synchronises the device). */
+void ahr_graph_destroy(ahr_graph* gr);
+
+/* Apply the polynomial filter of `spec` (Section V eq. "refine-filter";
+ * ComputeFilter and the product of Algorithm 1) to `in` ([n_inst][ncols]):
+ * the signal is first extended to the added nodes (macro pin node = macro
+ * centre + pin offset, star node = mean of its pins, macro virtual node =
+ * macro centre, bin virtual node = bin centre), the operator is normalised
+ * by absolute degrees d_i = sum_j |A_ij| + sigma (reading for signed
+ * graphs), lambda_up is the Gershgorin bound max_i (L_ii + sum_j |L_ij|)
+ * or lambda_fixed, and after the whole polynomial every fixed or virtual
+ * row is reset to its input.  Writes `out` ([n_inst][ncols]); `in` and
+ * `out` must not overlap.  Asynchronous. */
+ahr_status ahr_filter(ahr_graph* gr, const ahr_filter_spec* spec,
+                      const float* in, float* out, int32_t ncols, void* stream);
+
+/* Algorithm 1 (Section V): for r = 0 .. T_hint-1, rebuild the hints from
+ * columns 0 and 1 of g^(r), filter all columns, and relax
+ * g^(r+1) = (1 - gamma) g^(r) + gamma g~ on movable rows (fixed rows keep
+ * their input).  g0 and out are [n_inst][ncols] and may be the same
+ * buffer.  gamma in [0, 1], T_hint >= 0.  Synchronises `stream` once per
+ * round (hint sizes). */
+ahr_status ahr_refine(ahr_graph* gr, const ahr_filter_spec* spec, const float* g0,
+                      int32_t ncols, int32_t T_hint, float gamma, float* out,
+                      void* stream);
+
+/* Half-perimeter wirelength of the graph's netlist for every placement held
+ * in `g` ([n_inst][ncols], ncols even): for each column pair c,
+ * out[c] = sum over nets of (max - min) pin x + (max - min) pin y, pin
+ * position = instance position + pin offset, accumulated in float64 in a
+ * fixed order.  `out` is a device array of ncols/2 doubles.  Calls that
+ * overlap in time on one device race on a shared partial-sum buffer.
+ * Asynchronous. */
+ahr_status ahr_hpwl(const ahr_graph* gr, const float* g, int32_t ncols, double* out,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AHR_H */

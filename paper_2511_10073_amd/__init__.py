@@ -1,0 +1,213 @@
+"""Python binding of libahr, the MI355X signed netlist graph filter.
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch
+provides device memory and the current stream.  The library must have been
+built (``paper_2511_10073_amd.build``); importing it without ``libahr.so``
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libahr.so")
+
+FIXED = 1
+MACRO = 2
+EXPAND_MACRO_PINS = 1
+MACRO_HINTS = 2
+BIN_HINTS = 4
+ALL_HINTS = 7
+LAMBDA_GERSHGORIN = 0
+LAMBDA_FIXED = 1
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+
+
+class AhrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ahr error {code}: {msg}")
+        self.code = code
+
+
+class _Netlist(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("n_nets", ctypes.c_int32), ("n_pins", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("net_ptr", ctypes.c_void_p), ("pin_node", ctypes.c_void_p),
+                ("pin_off", ctypes.c_void_p), ("net_w", ctypes.c_void_p), ("node_flags", ctypes.c_void_p),
+                ("node_size", ctypes.c_void_p), ("die", ctypes.c_float * 4)]
+
+
+class _HintParams(ctypes.Structure):
+    _fields_ = [("nbx", ctypes.c_int32), ("nby", ctypes.c_int32), ("detection_ratio", ctypes.c_float),
+                ("bin_capacity", ctypes.c_float), ("mu", ctypes.c_float), ("clique_max", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class _FilterSpec(ctypes.Structure):
+    _fields_ = [("nbands", ctypes.c_int32), ("k", ctypes.c_int32 * 4), ("alpha", ctypes.c_float * 4),
+                ("sigma", ctypes.c_float), ("lambda_mode", ctypes.c_int32), ("lambda_fixed", ctypes.c_float)]
+
+
+class _GraphInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "n_inst", "n_tot", "first_mpin", "first_star", "first_mvirt", "first_bvirt", "nnz_net", "nnz_hint",
+        "n_hint_cells", "n_long_rows", "hint_version", "reserved")]
+
+
+class _GraphHost(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "net_row_ptr", "net_col", "net_q", "hint_row_ptr", "hint_col", "hint_val", "degree", "scale", "lambda_up")]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libahr.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2511_10073_amd.build.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.ahr_last_error.restype = ctypes.c_char_p
+    lib.ahr_version.restype = ctypes.c_char_p
+    sigs = {
+        "ahr_graph_build": [ctypes.POINTER(_Netlist), ctypes.POINTER(_HintParams), vp, i32, vp, ctypes.POINTER(vp)],
+        "ahr_graph_update_hints": [vp, vp, i32, vp],
+        "ahr_graph_get_info": [vp, ctypes.POINTER(_GraphInfo)],
+        "ahr_graph_export": [vp, ctypes.POINTER(_GraphHost), vp],
+        "ahr_filter": [vp, ctypes.POINTER(_FilterSpec), vp, vp, i32, vp],
+        "ahr_refine": [vp, ctypes.POINTER(_FilterSpec), vp, i32, i32, ctypes.c_float, vp, vp],
+        "ahr_hpwl": [vp, vp, i32, vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    lib.ahr_graph_destroy.argtypes = [vp]
+    lib.ahr_graph_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != OK:
+        raise AhrError(code, load().ahr_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Netlist:
+    """A netlist resident on the device (the arrays the C ABI points to)."""
+
+    def __init__(self, arrays: dict, device="cuda"):
+        dev = torch.device(device)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+        self.n_inst = int(arrays["n_inst"])
+        self.net_ptr = t(arrays["net_ptr"], torch.int32)
+        self.pin_node = t(arrays["pin_node"], torch.int32)
+        self.pin_off = t(arrays["pin_off"], torch.float32)
+        self.node_flags = t(arrays["node_flags"], torch.uint8)
+        self.node_size = t(arrays["node_size"], torch.float32)
+        nw = arrays.get("net_w")
+        self.net_w = None if nw is None else t(nw, torch.float32)
+        self.die = [float(v) for v in np.asarray(arrays["die"], np.float32)]
+        self.c = _Netlist(self.n_inst, self.net_ptr.numel() - 1, self.pin_node.numel(), 0,
+                          self.net_ptr.data_ptr(), self.pin_node.data_ptr() if self.pin_node.numel() else 0,
+                          self.pin_off.data_ptr(), self.net_w.data_ptr() if self.net_w is not None else 0,
+                          self.node_flags.data_ptr(), self.node_size.data_ptr(), (ctypes.c_float * 4)(*self.die))
+
+
+def hint_params(nbx=8, nby=8, detection_ratio=0.1, bin_capacity=1.0, mu=4.0, clique_max=10, flags=ALL_HINTS):
+    return _HintParams(nbx, nby, detection_ratio, bin_capacity, mu, clique_max, flags)
+
+
+def filter_spec(ks=(4,), alphas=(1.0,), sigma=0.0, lambda_mode=LAMBDA_GERSHGORIN, lambda_fixed=2.0):
+    ks, alphas = list(ks), list(alphas)
+    assert len(ks) == len(alphas) and 1 <= len(ks) <= 4
+    k = (ctypes.c_int32 * 4)(*(ks + [0] * (4 - len(ks))))
+    a = (ctypes.c_float * 4)(*(alphas + [0.0] * (4 - len(alphas))))
+    return _FilterSpec(len(ks), k, a, sigma, lambda_mode, lambda_fixed)
+
+
+class Graph:
+    """Owner of an ahr_graph handle (ahr_graph_build ... ahr_graph_destroy)."""
+
+    def __init__(self, netlist: Netlist, params, g=None, stream=None):
+        lib = load()
+        self.netlist = netlist
+        self.params = params
+        h = ctypes.c_void_p()
+        ncols = 0 if g is None else g.shape[1]
+        _check(lib.ahr_graph_build(ctypes.byref(netlist.c), ctypes.byref(params), _ptr(g), ncols,
+                                   _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().ahr_graph_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update_hints(self, g, stream=None):
+        _check(load().ahr_graph_update_hints(self.h, _ptr(g), g.shape[1], _stream(stream)))
+
+    def info(self) -> dict:
+        i = _GraphInfo()
+        _check(load().ahr_graph_get_info(self.h, ctypes.byref(i)))
+        return {n: getattr(i, n) for n, _ in _GraphInfo._fields_}
+
+    def export(self, stream=None) -> dict:
+        inf = self.info()
+        n, nn, nh = inf["n_tot"], inf["nnz_net"], inf["nnz_hint"]
+        out = dict(net_row_ptr=np.zeros(n + 1, np.int32), net_col=np.zeros(max(nn, 1), np.int32),
+                   net_q=np.zeros(max(nn, 1), np.int64), hint_row_ptr=np.zeros(n + 1, np.int32),
+                   hint_col=np.zeros(max(nh, 1), np.int32), hint_val=np.zeros(max(nh, 1), np.float32),
+                   degree=np.zeros(n, np.float64), scale=np.zeros(n, np.float32),
+                   lambda_up=np.zeros(1, np.float32))
+        h = _GraphHost(*[a.ctypes.data for a in out.values()])
+        _check(load().ahr_graph_export(self.h, ctypes.byref(h), _stream(stream)))
+        out["net_col"] = out["net_col"][:nn]
+        out["net_q"] = out["net_q"][:nn]
+        out["hint_col"] = out["hint_col"][:nh]
+        out["hint_val"] = out["hint_val"][:nh]
+        out["lambda_up"] = float(out["lambda_up"][0])
+        return out
+
+    def filter(self, spec, x, out=None, stream=None):
+        if out is None:
+            out = torch.empty_like(x)
+        _check(load().ahr_filter(self.h, ctypes.byref(spec), _ptr(x), _ptr(out), x.shape[1], _stream(stream)))
+        return out
+
+    def refine(self, spec, g0, T_hint, gamma, out=None, stream=None):
+        if out is None:
+            out = torch.empty_like(g0)
+        _check(load().ahr_refine(self.h, ctypes.byref(spec), _ptr(g0), g0.shape[1], T_hint, gamma, _ptr(out),
+                                 _stream(stream)))
+        return out
+
+    def hpwl(self, g, out=None, stream=None):
+        if out is None:
+            out = torch.empty(g.shape[1] // 2, dtype=torch.float64, device=g.device)
+        _check(load().ahr_hpwl(self.h, _ptr(g), g.shape[1], _ptr(out), _stream(stream)))
+        return out

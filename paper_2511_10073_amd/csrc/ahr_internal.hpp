@@ -1,0 +1,167 @@
+// Internal declarations shared by the libahr translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/ahr.h"
+
+namespace ahr {
+
+// ---------------------------------------------------------------- errors
+
+struct Error {
+    ahr_status code;
+    std::string msg;
+};
+
+void set_error(ahr_status code, const std::string& msg);
+ahr_status fail(ahr_status code, const std::string& msg);
+
+// Throws ahr::Error on a failed HIP call; the C entry points catch it.
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define AHR_HIP(call) ::ahr::hip_check((call), #call, __FILE__, __LINE__)
+#define AHR_LAUNCHED(name) ::ahr::hip_check(hipGetLastError(), name, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------- memory
+
+// Stream-ordered device allocation from a pool that keeps freed memory.
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;       // capacity in elements
+    void ensure(size_t need, hipStream_t s) {
+        if (need <= n && p) return;
+        if (p) dev_free(p, s);
+        size_t cap = need < 1 ? 1 : need;
+        p = static_cast<T*>(dev_alloc(cap * sizeof(T), s));
+        n = cap;
+    }
+    void release(hipStream_t s) {
+        if (p) dev_free(p, s);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+inline unsigned grid_for(int64_t n, int per_block) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return static_cast<unsigned>(g);
+}
+
+// ---------------------------------------------------------------- scan
+
+// out[0..n] = exclusive prefix sums of in[0..n-1] (out[n] = total).
+// Integer, so deterministic.  `tmp` must hold scan_tmp_elems(n) int64.
+size_t scan_tmp_elems(int64_t n);
+void scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+// Same, writes int32 (caller checked the total fits).
+void scan_i32_to_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+
+// list[rank[i]] = i for every i with flags[i] != 0 (rank = exclusive scan of flags).
+void list_rows(const int32_t* flags, const int32_t* rank, int32_t n, int32_t* list, hipStream_t s);
+// p[0..n) = v
+void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+// ---------------------------------------------------------------- graph
+
+struct Graph {
+    ahr_netlist nl;            // caller's device arrays (kept)
+    ahr_hint_params hp;
+    int32_t n_inst = 0, n_mpin = 0, n_star = 0, n_macro = 0, n_bins = 0;
+    int32_t first_mpin = 0, first_star = 0, first_mvirt = 0, first_bvirt = 0, n_tot = 0;
+    int32_t nnz_net = 0, nnz_hint = 0, n_hint_cells = 0;
+    int32_t hint_version = 0;
+    int32_t has_hints = 0;
+    int device = 0;
+
+    // netlist part (fixed for the life of the handle)
+    DevBuf<int32_t> pin_node_x;   // [n_pins] pin node after macro pin expansion
+    DevBuf<int32_t> mpin_owner;   // [n_mpin]
+    DevBuf<int32_t> mpin_pin;     // [n_mpin]
+    DevBuf<int32_t> star_net;     // [n_star]
+    DevBuf<int32_t> macro_ids;    // [n_macro] instance id of each macro (instance order)
+    DevBuf<int32_t> net_rp;       // [n_tot+1]
+    DevBuf<int32_t> net_col;      // [nnz_net]
+    DevBuf<int64_t> net_q;        // [nnz_net]
+    DevBuf<int2> net_ent;         // [nnz_net] (col, float bits of q * 2^-32)
+    DevBuf<int64_t> qdeg;         // [n_tot]
+    DevBuf<double> base_w;        // [n_inst] baseWeight
+    DevBuf<int32_t> big_nets;     // nets with more than a wave's worth of pins (HPWL)
+    int32_t n_big_nets = 0;
+
+    // hint part (per placement)
+    DevBuf<int32_t> cell_bin;     // [n_inst] bin of each hint cell, -1 otherwise
+    DevBuf<int32_t> bin_cnt;      // [n_bins] hint cells per bin
+    DevBuf<int32_t> bin_start;    // [n_bins+1]
+    DevBuf<int32_t> bin_cells;    // [n_hint_cells] hint cells grouped by bin, ascending
+    DevBuf<int64_t> bin_area_q;   // [n_bins] fixed-point area (2^-28 units)
+    DevBuf<double> phi;           // [n_bins]
+    DevBuf<int32_t> bm_start;     // [n_bins+1] macros whose (widened) span covers a bin
+    DevBuf<int32_t> bm_list;
+    DevBuf<int4> macro_span;      // [n_macro] widened bin span bx0, by0, bx1, by1
+    DevBuf<float4> macro_rect;    // [n_macro] cx, cy, w/2, h/2 (float32)
+    DevBuf<int32_t> hint_cnt;     // [n_tot]
+    DevBuf<int32_t> hint_rp;      // [n_tot+1]
+    DevBuf<int2> hint_ent;        // [nnz_hint] (col, float bits of weight)
+
+    // operator (per hint version and sigma)
+    DevBuf<double> deg;           // [n_tot]
+    DevBuf<float> scale;          // [n_tot]
+    DevBuf<double> lam;           // [1] lambda_up
+    double lam_host = 0.0;
+    int32_t norm_version = -1;
+    float norm_sigma = -1.f;
+    int32_t norm_mode = -1;
+    float norm_fixed = -1.f;
+
+    // row classes for the filter
+    DevBuf<int32_t> row_len;      // [n_tot] scratch
+    DevBuf<int32_t> long_rows;    // rows split over chunks, ascending
+    DevBuf<int32_t> long_chunk0;  // [n_long+1] first chunk of each long row
+    DevBuf<int32_t> chunk_row;    // [n_chunks] long-row index of each chunk
+    DevBuf<int32_t> long_done;    // [n_long] arrival counters (kept at 0 between hops)
+    DevBuf<double> partial;       // [n_chunks * 8]
+    int32_t n_long = 0, n_chunks = 0;
+    int32_t n_chunks_inst = 0;    // chunks of long rows below n_inst
+    int32_t rows_version = -1;
+
+    // filter work buffers
+    DevBuf<float> z0, z1, acc;    // [n_tot * C]
+    DevBuf<float> ga, gb, gt;     // [n_inst * C] refinement rounds
+
+    // scratch
+    DevBuf<int64_t> scan_tmp;
+    DevBuf<int32_t> i32a, i32b;
+    DevBuf<int64_t> i64a;
+    DevBuf<int32_t> counter;      // small device counters
+
+    ~Graph();
+};
+
+// netlist_build.hip
+void build_netlist(Graph& g, hipStream_t s);
+// hints.hip
+void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
+// filter.hip
+void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s);
+void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* out,
+                int32_t ncols, hipStream_t s);
+void relax(Graph& g, const float* gcur, const float* gt, float* gnext, int32_t ncols,
+           float gamma, hipStream_t s);
+// hpwl.hip
+void run_hpwl(const Graph& g, const float* pos, int32_t ncols, double* out, hipStream_t s);
+
+// Long rows: rows with more entries than this are split into chunks.
+constexpr int kLongRow = 4096;
+constexpr int kChunk = 2048;
+
+}  // namespace ahr

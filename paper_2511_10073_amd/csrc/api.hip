@@ -1,0 +1,291 @@
+// C entry points: argument validation, error capture, orchestration.
+#include <cmath>
+#include <cstring>
+
+#include "ahr_internal.hpp"
+
+namespace ahr {
+
+std::string& last_error_ref();
+
+Graph::~Graph() {
+    hipStream_t s = nullptr;
+    DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_rp, &net_col,
+                              &big_nets, &cell_bin, &bin_cnt, &bin_start, &bin_cells, &bm_start, &bm_list,
+                              &hint_cnt, &hint_rp, &row_len, &long_rows, &long_chunk0, &chunk_row, &long_done,
+                              &i32a, &i32b, &counter};
+    for (auto* b : i32) b->release(s);
+    net_q.release(s);
+    net_ent.release(s);
+    qdeg.release(s);
+    base_w.release(s);
+    bin_area_q.release(s);
+    phi.release(s);
+    macro_span.release(s);
+    macro_rect.release(s);
+    hint_ent.release(s);
+    deg.release(s);
+    scale.release(s);
+    lam.release(s);
+    partial.release(s);
+    z0.release(s);
+    z1.release(s);
+    acc.release(s);
+    ga.release(s);
+    gb.release(s);
+    gt.release(s);
+    scan_tmp.release(s);
+    i64a.release(s);
+    (void)hipStreamSynchronize(s);
+}
+
+}  // namespace ahr
+
+using ahr::Error;
+using ahr::fail;
+
+namespace {
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+bool ncols_ok(int32_t c) { return c == 1 || c == 2 || c == 4 || c == 8; }
+
+ahr_status check_netlist(const ahr_netlist* nl) {
+    if (!nl) return fail(AHR_EINVAL, "netlist is NULL");
+    if (nl->n_inst <= 0) return fail(AHR_EINVAL, "n_inst must be positive");
+    if (nl->n_nets < 0 || nl->n_pins < 0) return fail(AHR_EINVAL, "negative net or pin count");
+    if (nl->reserved0 != 0) return fail(AHR_EINVAL, "reserved0 must be 0");
+    if (!nl->net_ptr || !nl->node_flags || !nl->node_size || !nl->pin_off)
+        return fail(AHR_EINVAL, "net_ptr, node_flags, node_size and pin_off are required");
+    if (nl->n_pins > 0 && !nl->pin_node) return fail(AHR_EINVAL, "pin_node is NULL");
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(nl->die[k])) return fail(AHR_EINVAL, "die is not finite");
+    if (!(nl->die[0] < nl->die[2]) || !(nl->die[1] < nl->die[3])) return fail(AHR_EINVAL, "empty die");
+    return AHR_OK;
+}
+
+ahr_status check_hints(const ahr_hint_params* hp) {
+    if (!hp) return fail(AHR_EINVAL, "hint params are NULL");
+    if (hp->nbx < 1 || hp->nby < 1 || hp->nbx > 4096 || hp->nby > 4096) return fail(AHR_EINVAL, "nbx, nby in [1, 4096]");
+    if (static_cast<int64_t>(hp->nbx) * hp->nby > 16384)
+        return fail(AHR_EUNSUPPORTED, "at most 16384 bins (nbx * nby)");
+    if (!(hp->detection_ratio >= 0.f && hp->detection_ratio <= 1.f)) return fail(AHR_EINVAL, "detection_ratio in [0, 1]");
+    if (!(hp->mu > 0.f) || !std::isfinite(hp->mu)) return fail(AHR_EINVAL, "mu must be positive");
+    if (!std::isfinite(hp->bin_capacity)) return fail(AHR_EINVAL, "bin_capacity must be finite");
+    if (hp->clique_max < 1) return fail(AHR_EINVAL, "clique_max must be >= 1");
+    if (hp->flags & ~AHR_ALL_HINTS) return fail(AHR_EINVAL, "unknown hint flags");
+    return AHR_OK;
+}
+
+ahr_status check_spec(const ahr_filter_spec* sp) {
+    if (!sp) return fail(AHR_EINVAL, "filter spec is NULL");
+    if (sp->nbands < 1 || sp->nbands > AHR_MAX_BANDS) return fail(AHR_EINVAL, "nbands in [1, 4]");
+    for (int b = 0; b < sp->nbands; ++b) {
+        if (sp->k[b] < 0 || sp->k[b] > 64) return fail(AHR_EINVAL, "k in [0, 64]");
+        if (!std::isfinite(sp->alpha[b])) return fail(AHR_EINVAL, "alpha must be finite");
+    }
+    if (!(sp->sigma >= 0.f) || !std::isfinite(sp->sigma)) return fail(AHR_EINVAL, "sigma must be >= 0");
+    if (sp->lambda_mode != AHR_LAMBDA_GERSHGORIN && sp->lambda_mode != AHR_LAMBDA_FIXED)
+        return fail(AHR_EINVAL, "unknown lambda_mode");
+    if (sp->lambda_mode == AHR_LAMBDA_FIXED && !(sp->lambda_fixed >= 0.f && std::isfinite(sp->lambda_fixed)))
+        return fail(AHR_EINVAL, "lambda_fixed must be >= 0");
+    return AHR_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+template <class F>
+ahr_status guarded(F&& f) {
+    try {
+        ahr::set_error(AHR_OK, "");
+        return f();
+    } catch (const Error& e) {
+        return fail(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(AHR_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(AHR_EDEVICE, "unexpected exception");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ahr_version(void) { return "ahr 0.1 gfx950"; }
+
+const char* ahr_last_error(void) { return ahr::last_error_ref().c_str(); }
+
+ahr_status ahr_graph_build(const ahr_netlist* nl, const ahr_hint_params* hp, const float* g, int32_t ncols,
+                           void* stream, ahr_graph** out) {
+    ahr_status st;
+    if ((st = check_netlist(nl)) != AHR_OK) return st;
+    if ((st = check_hints(hp)) != AHR_OK) return st;
+    if (!out) return fail(AHR_EINVAL, "out is NULL");
+    if (g && (!ncols_ok(ncols) || ncols < 2)) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8 with a placement");
+    return guarded([&]() -> ahr_status {
+        hipStream_t s = as_stream(stream);
+        auto* gr = new ahr::Graph();
+        gr->nl = *nl;
+        gr->hp = *hp;
+        AHR_HIP(hipGetDevice(&gr->device));
+        try {
+            ahr::build_netlist(*gr, s);
+            if (g) {
+                ahr::build_hints(*gr, g, ncols, s);
+                AHR_HIP(hipStreamSynchronize(s));
+            }
+        } catch (...) {
+            delete gr;
+            throw;
+        }
+        *out = reinterpret_cast<ahr_graph*>(gr);
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_graph_update_hints(ahr_graph* h, const float* g, int32_t ncols, void* stream) {
+    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+    if (!g) return fail(AHR_EINVAL, "placement is NULL");
+    if (!ncols_ok(ncols) || ncols < 2) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
+    return guarded([&]() -> ahr_status {
+        auto* gr = reinterpret_cast<ahr::Graph*>(h);
+        hipStream_t s = as_stream(stream);
+        ahr::build_hints(*gr, g, ncols, s);
+        AHR_HIP(hipStreamSynchronize(s));
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
+    if (!h || !info) return fail(AHR_EINVAL, "NULL argument");
+    const auto* g = reinterpret_cast<const ahr::Graph*>(h);
+    std::memset(info, 0, sizeof *info);
+    info->n_inst = g->n_inst;
+    info->n_tot = g->n_tot;
+    info->first_mpin = g->first_mpin;
+    info->first_star = g->first_star;
+    info->first_mvirt = g->first_mvirt;
+    info->first_bvirt = g->first_bvirt;
+    info->nnz_net = g->nnz_net;
+    info->nnz_hint = g->has_hints ? g->nnz_hint : 0;
+    info->n_hint_cells = g->n_hint_cells;
+    info->n_long_rows = g->n_long;
+    info->hint_version = g->hint_version;
+    return AHR_OK;
+}
+
+ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* stream) {
+    if (!h || !dst) return fail(AHR_EINVAL, "NULL argument");
+    return guarded([&]() -> ahr_status {
+        const auto* g = reinterpret_cast<const ahr::Graph*>(h);
+        hipStream_t s = as_stream(stream);
+        const size_t N = static_cast<size_t>(g->n_tot);
+        auto cp = [&](void* d, const void* src, size_t bytes) {
+            if (d && bytes) AHR_HIP(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToHost, s));
+        };
+        cp(dst->net_row_ptr, g->net_rp.p, (N + 1) * sizeof(int32_t));
+        cp(dst->net_col, g->net_col.p, g->nnz_net * sizeof(int32_t));
+        cp(dst->net_q, g->net_q.p, g->nnz_net * sizeof(int64_t));
+        if (g->has_hints) {
+            cp(dst->hint_row_ptr, g->hint_rp.p, (N + 1) * sizeof(int32_t));
+            if ((dst->hint_col || dst->hint_val) && g->nnz_hint) {
+                std::vector<int2> ent(g->nnz_hint);
+                AHR_HIP(hipMemcpyAsync(ent.data(), g->hint_ent.p, g->nnz_hint * sizeof(int2), hipMemcpyDeviceToHost, s));
+                AHR_HIP(hipStreamSynchronize(s));
+                for (int32_t k = 0; k < g->nnz_hint; ++k) {
+                    if (dst->hint_col) dst->hint_col[k] = ent[k].x;
+                    if (dst->hint_val) std::memcpy(&dst->hint_val[k], &ent[k].y, sizeof(float));
+                }
+            }
+        } else if (dst->hint_row_ptr) {
+            std::memset(dst->hint_row_ptr, 0, (N + 1) * sizeof(int32_t));
+        }
+        if (g->norm_version >= 0) {
+            cp(dst->degree, g->deg.p, N * sizeof(double));
+            cp(dst->scale, g->scale.p, N * sizeof(float));
+            if (dst->lambda_up) {
+                double l = 0;
+                AHR_HIP(hipMemcpyAsync(&l, g->lam.p, sizeof l, hipMemcpyDeviceToHost, s));
+                AHR_HIP(hipStreamSynchronize(s));
+                *dst->lambda_up = static_cast<float>(l);
+            }
+        }
+        AHR_HIP(hipStreamSynchronize(s));
+        return AHR_OK;
+    });
+}
+
+void ahr_graph_destroy(ahr_graph* h) {
+    if (!h) return;
+    try {
+        delete reinterpret_cast<ahr::Graph*>(h);
+    } catch (...) {
+    }
+}
+
+ahr_status ahr_filter(ahr_graph* h, const ahr_filter_spec* spec, const float* in, float* out, int32_t ncols,
+                      void* stream) {
+    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+    ahr_status st;
+    if ((st = check_spec(spec)) != AHR_OK) return st;
+    if (!in || !out) return fail(AHR_EINVAL, "in/out is NULL");
+    if (!ncols_ok(ncols)) return fail(AHR_EINVAL, "ncols must be 1, 2, 4 or 8");
+    auto* gr = reinterpret_cast<ahr::Graph*>(h);
+    if (!gr->has_hints) return fail(AHR_EINVAL, "graph has no hints yet: build with a placement or update_hints");
+    size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
+    if (overlap(in, bytes, out, bytes)) return fail(AHR_EINVAL, "in and out overlap");
+    return guarded([&]() -> ahr_status {
+        ahr::run_filter(*gr, *spec, in, out, ncols, as_stream(stream));
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0, int32_t ncols, int32_t T_hint,
+                      float gamma, float* out, void* stream) {
+    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+    ahr_status st;
+    if ((st = check_spec(spec)) != AHR_OK) return st;
+    if (!g0 || !out) return fail(AHR_EINVAL, "g0/out is NULL");
+    if (!ncols_ok(ncols) || ncols < 2) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
+    if (T_hint < 0) return fail(AHR_EINVAL, "T_hint must be >= 0");
+    if (!(gamma >= 0.f && gamma <= 1.f)) return fail(AHR_EINVAL, "gamma in [0, 1]");
+    auto* gr = reinterpret_cast<ahr::Graph*>(h);
+    size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
+    if (g0 != out && overlap(g0, bytes, out, bytes)) return fail(AHR_EINVAL, "g0 and out partially overlap");
+    return guarded([&]() -> ahr_status {
+        hipStream_t s = as_stream(stream);
+        size_t n = static_cast<size_t>(gr->n_inst) * ncols;
+        if (T_hint == 0) {
+            if (g0 != out) AHR_HIP(hipMemcpyAsync(out, g0, bytes, hipMemcpyDeviceToDevice, s));
+            return AHR_OK;
+        }
+        gr->ga.ensure(n, s);
+        gr->gb.ensure(n, s);
+        gr->gt.ensure(n, s);
+        const float* cur = g0;
+        for (int r = 0; r < T_hint; ++r) {
+            float* next = (r == T_hint - 1) ? out : ((r & 1) ? gr->gb.p : gr->ga.p);
+            ahr::build_hints(*gr, cur, ncols, s);
+            ahr::run_filter(*gr, *spec, cur, gr->gt.p, ncols, s);
+            ahr::relax(*gr, cur, gr->gt.p, next, ncols, gamma, s);
+            cur = next;
+        }
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_hpwl(const ahr_graph* h, const float* g, int32_t ncols, double* out, void* stream) {
+    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+    if (!g || !out) return fail(AHR_EINVAL, "g/out is NULL");
+    if (ncols != 2 && ncols != 4 && ncols != 8) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
+    return guarded([&]() -> ahr_status {
+        ahr::run_hpwl(*reinterpret_cast<const ahr::Graph*>(h), g, ncols, out, as_stream(stream));
+        return AHR_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,777 @@
+// The refinement filter (Section V, eq. "refine-filter"):
+//   L = diag(nz) - S (A + sigma I) S,  S = diag(s), s_i = (d_i)^-1/2,
+//   d_i = sum_j |A_ij| + sigma (absolute degree: the reading for signed
+//   graphs that keeps L positive semi-definite),
+//   lambda_up = max_i (L_ii + sum_j |L_ij|) (Gershgorin), T = I - L/lambda_up,
+//   out = sum_b alpha_b T^{k_b} X, then fixed and virtual rows reset to X.
+//
+// The chain runs in scaled coordinates z = S y, where one hop is
+//   z'_i = c_i z_i + (s_i^2 / lambda) sum_j A_ij z_j,
+//   c_i  = 1 - (nz_i - sigma s_i^2) / lambda,
+// so a hop streams the unscaled adjacency once (8 bytes per entry: column and
+// float32 weight) and gathers one C-wide row of z per entry; nothing is
+// rescaled when the hints change.  Isolated rows (s_i = 0) are identity
+// rows and are recovered from the input at the end.
+//
+// Rows with up to kLongRow entries are handled by G lanes each; longer rows
+// (bin and macro virtual nodes, big-net stars) are split into kChunk-entry
+// chunks, one workgroup each, whose float64 partial sums the last arriving
+// workgroup adds in chunk order -- deterministic for any schedule.
+#include "ahr_internal.hpp"
+#include "device_util.hpp"
+
+namespace ahr {
+
+namespace {
+
+constexpr int kBT = 256;
+
+template <class T>
+T read_scalar(const T* dev, hipStream_t s) {
+    T v;
+    AHR_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    AHR_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+// ---------------------------------------------------------------- vectors
+
+template <int C>
+struct Vec {
+    float v[C];
+};
+
+template <int C>
+__device__ __forceinline__ Vec<C> vload(const float* p) {
+    Vec<C> r;
+    if constexpr (C == 1) {
+        r.v[0] = p[0];
+    } else if constexpr (C == 2) {
+        float2 t = *reinterpret_cast<const float2*>(p);
+        r.v[0] = t.x;
+        r.v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q) {
+            float4 t = reinterpret_cast<const float4*>(p)[q];
+            r.v[4 * q] = t.x;
+            r.v[4 * q + 1] = t.y;
+            r.v[4 * q + 2] = t.z;
+            r.v[4 * q + 3] = t.w;
+        }
+    }
+    return r;
+}
+
+template <int C>
+__device__ __forceinline__ void vstore(float* p, const Vec<C>& r) {
+    if constexpr (C == 1) {
+        p[0] = r.v[0];
+    } else if constexpr (C == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(r.v[0], r.v[1]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q)
+            reinterpret_cast<float4*>(p)[q] = make_float4(r.v[4 * q], r.v[4 * q + 1], r.v[4 * q + 2], r.v[4 * q + 3]);
+    }
+}
+
+// ---------------------------------------------------------------- row classes
+
+__global__ void k_row_len(int32_t n, const int32_t* __restrict__ net_rp, const int32_t* __restrict__ hint_rp,
+                          int32_t* __restrict__ is_long) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int len = (net_rp[r + 1] - net_rp[r]) + (hint_rp[r + 1] - hint_rp[r]);
+    is_long[r] = len > kLongRow ? 1 : 0;
+}
+
+__global__ void k_long_nchunks(int32_t n_long, const int32_t* __restrict__ rows, const int32_t* __restrict__ net_rp,
+                               const int32_t* __restrict__ hint_rp, int32_t* __restrict__ nch) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_long) return;
+    int r = rows[i];
+    int len = (net_rp[r + 1] - net_rp[r]) + (hint_rp[r + 1] - hint_rp[r]);
+    nch[i] = (len + kChunk - 1) / kChunk;
+}
+
+__global__ void k_chunk_rows(int32_t n_long, const int32_t* __restrict__ chunk0, int32_t* __restrict__ chunk_row) {
+    int i = blockIdx.x;
+    if (i >= n_long) return;
+    for (int c = chunk0[i] + threadIdx.x; c < chunk0[i + 1]; c += blockDim.x) chunk_row[c] = i;
+}
+
+struct RowRef {
+    const int32_t* net_rp;
+    const int2* net_ent;
+    const int32_t* hint_rp;
+    const int2* hint_ent;
+};
+
+// ---------------------------------------------------------------- degrees
+
+template <int G>
+__global__ void __launch_bounds__(kBT) k_deg_short(int32_t n, RowRef m, const int64_t* __restrict__ qdeg, double sigma,
+                                                   double* __restrict__ deg, float* __restrict__ scale) {
+    int64_t t = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    int64_t r = t / G;
+    int l = static_cast<int>(t & (G - 1));
+    if (r >= n) return;
+    int h0 = m.hint_rp[r], h1 = m.hint_rp[r + 1];
+    int len = (m.net_rp[r + 1] - m.net_rp[r]) + (h1 - h0);
+    if (len > kLongRow) return;
+    double a = 0;
+    for (int k = h0 + l; k < h1; k += G) a += fabs(static_cast<double>(bits_f(m.hint_ent[k].y)));
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (l == 0) {
+        double d = static_cast<double>(qdeg[r]) * 0x1p-32 + a + sigma;
+        deg[r] = d;
+        scale[r] = d > 0 ? static_cast<float>(1.0 / sqrt(d)) : 0.f;
+    }
+}
+
+__device__ __forceinline__ void chunk_range(int c, const int32_t* long_rows, const int32_t* chunk_row,
+                                            const int32_t* chunk0, const RowRef& m, int& r, int& li, int& k0, int& k1,
+                                            int& n0, int& ln, int& h0) {
+    li = chunk_row[c];
+    r = long_rows[li];
+    n0 = m.net_rp[r];
+    ln = m.net_rp[r + 1] - n0;
+    h0 = m.hint_rp[r];
+    int len = ln + (m.hint_rp[r + 1] - h0);
+    k0 = (c - chunk0[li]) * kChunk;
+    k1 = k0 + kChunk < len ? k0 + kChunk : len;
+}
+
+__global__ void __launch_bounds__(kBT) k_chunk_absdeg(RowRef m, const int32_t* __restrict__ long_rows,
+                                                      const int32_t* __restrict__ chunk_row,
+                                                      const int32_t* __restrict__ chunk0, double* __restrict__ partial) {
+    __shared__ double red[kBT / kWave];
+    int r, li, k0, k1, n0, ln, h0;
+    chunk_range(blockIdx.x, long_rows, chunk_row, chunk0, m, r, li, k0, k1, n0, ln, h0);
+    double a = 0;
+    for (int k = k0 + threadIdx.x; k < k1; k += kBT)
+        if (k >= ln) a += fabs(static_cast<double>(bits_f(m.hint_ent[h0 + k - ln].y)));
+    a = block_sum_f64<kBT>(a, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a;
+}
+
+__global__ void k_long_deg_final(int32_t n_long, const int32_t* __restrict__ long_rows,
+                                 const int32_t* __restrict__ chunk0, const double* __restrict__ partial,
+                                 const int64_t* __restrict__ qdeg, double sigma, double* __restrict__ deg,
+                                 float* __restrict__ scale) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_long) return;
+    int r = long_rows[i];
+    double a = 0;
+    for (int c = chunk0[i]; c < chunk0[i + 1]; ++c) a += partial[c];
+    double d = static_cast<double>(qdeg[r]) * 0x1p-32 + a + sigma;
+    deg[r] = d;
+    scale[r] = d > 0 ? static_cast<float>(1.0 / sqrt(d)) : 0.f;
+}
+
+// ---------------------------------------------------------------- Gershgorin
+
+__device__ __forceinline__ double diag_abs(float s, double d, double sigma) {
+    double nz = d > 0 ? 1.0 : 0.0;
+    double sd = static_cast<double>(s);
+    return fabs(nz - sigma * sd * sd);
+}
+
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
+    atomicMax(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBT) k_gersh_short(int32_t n, RowRef m, const double* __restrict__ deg,
+                                                     const float* __restrict__ scale, double sigma,
+                                                     double* __restrict__ lam) {
+    int64_t t = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    int64_t r = t / G;
+    int l = static_cast<int>(t & (G - 1));
+    if (r >= n) return;
+    int n0 = m.net_rp[r], n1 = m.net_rp[r + 1], h0 = m.hint_rp[r], h1 = m.hint_rp[r + 1];
+    if ((n1 - n0) + (h1 - h0) > kLongRow) return;
+    double a = 0;
+    for (int k = n0 + l; k < n1; k += G) {
+        int2 e = m.net_ent[k];
+        a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
+    }
+    for (int k = h0 + l; k < h1; k += G) {
+        int2 e = m.hint_ent[k];
+        a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (l == 0) {
+        float s = scale[r];
+        double rr = diag_abs(s, deg[r], sigma) + static_cast<double>(s) * a;
+        atomic_max_nonneg(lam, rr);
+    }
+}
+
+__global__ void __launch_bounds__(kBT) k_chunk_gersh(RowRef m, const int32_t* __restrict__ long_rows,
+                                                     const int32_t* __restrict__ chunk_row,
+                                                     const int32_t* __restrict__ chunk0, const float* __restrict__ scale,
+                                                     double* __restrict__ partial) {
+    __shared__ double red[kBT / kWave];
+    int r, li, k0, k1, n0, ln, h0;
+    chunk_range(blockIdx.x, long_rows, chunk_row, chunk0, m, r, li, k0, k1, n0, ln, h0);
+    double a = 0;
+    for (int k = k0 + threadIdx.x; k < k1; k += kBT) {
+        int2 e = k < ln ? m.net_ent[n0 + k] : m.hint_ent[h0 + k - ln];
+        a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
+    }
+    a = block_sum_f64<kBT>(a, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a;
+}
+
+__global__ void k_long_gersh_final(int32_t n_long, const int32_t* __restrict__ long_rows,
+                                   const int32_t* __restrict__ chunk0, const double* __restrict__ partial,
+                                   const double* __restrict__ deg, const float* __restrict__ scale, double sigma,
+                                   double* __restrict__ lam) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_long) return;
+    int r = long_rows[i];
+    double a = 0;
+    for (int c = chunk0[i]; c < chunk0[i + 1]; ++c) a += partial[c];
+    float s = scale[r];
+    atomic_max_nonneg(lam, diag_abs(s, deg[r], sigma) + static_cast<double>(s) * a);
+}
+
+__global__ void k_set_f64(double* p, double v) { *p = v; }
+
+// ---------------------------------------------------------------- signal
+
+struct ExpandArgs {
+    const float* in;          // [n_inst][C]
+    const float* scale;
+    float* z0;                // [n_tot][C]
+    float* acc;               // band at k = 0
+    float alpha0;
+    int band0;
+    int32_t n_inst, first_mpin, first_star, first_mvirt, first_bvirt, n_tot;
+    const int32_t* mpin_owner;
+    const int32_t* mpin_pin;
+    const float* pin_off;
+    const int32_t* star_net;
+    const int32_t* net_ptr;
+    const int32_t* pin_node;
+    const int32_t* pin_node_x;
+    const int32_t* macro_ids;
+    int nbx;
+    double xl, yl, bw, bh;
+};
+
+template <int C>
+__device__ __forceinline__ Vec<C> pin_value(const ExpandArgs& a, int p) {
+    int v = a.pin_node[p];
+    Vec<C> x = vload<C>(a.in + static_cast<int64_t>(v) * C);
+    if (a.pin_node_x[p] >= a.n_inst) {
+        float dx = a.pin_off[2 * p], dy = a.pin_off[2 * p + 1];
+#pragma unroll
+        for (int c = 0; c < C; ++c) x.v[c] += (c & 1) ? dy : dx;
+    }
+    return x;
+}
+
+template <int C>
+__device__ __forceinline__ void put_z(const ExpandArgs& a, int r, Vec<C> x) {
+    float s = a.scale[r];
+    Vec<C> z;
+#pragma unroll
+    for (int c = 0; c < C; ++c) z.v[c] = s * x.v[c];
+    vstore<C>(a.z0 + static_cast<int64_t>(r) * C, z);
+    if (a.band0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) z.v[c] *= a.alpha0;
+        vstore<C>(a.acc + static_cast<int64_t>(r) * C, z);
+    }
+}
+
+// Node values of the extended graph (macro pin node = macro centre + pin
+// offset, star node = mean of its pins, macro virtual node = macro centre,
+// bin virtual node = bin centre), scaled by s.  Stars with more than a
+// wave's worth of pins are left to k_expand_bigstar.
+template <int C>
+__global__ void __launch_bounds__(kBT) k_expand(ExpandArgs a) {
+    int64_t r64 = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    if (r64 >= a.n_tot) return;
+    int r = static_cast<int>(r64);
+    Vec<C> x;
+    if (r < a.n_inst) {
+        x = vload<C>(a.in + r64 * C);
+    } else if (r < a.first_star) {
+        int k = r - a.first_mpin;
+        x = pin_value<C>(a, a.mpin_pin[k]);
+    } else if (r < a.first_mvirt) {
+        int e = a.star_net[r - a.first_star];
+        int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
+        if (p1 - p0 > kWave) return;
+        double acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = 0;
+        for (int p = p0; p < p1; ++p) {
+            Vec<C> v = pin_value<C>(a, p);
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += v.v[c];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) x.v[c] = static_cast<float>(acc[c] / (p1 - p0));
+    } else if (r < a.first_bvirt) {
+        x = vload<C>(a.in + static_cast<int64_t>(a.macro_ids[r - a.first_mvirt]) * C);
+    } else {
+        int b = r - a.first_bvirt;
+        float cx = static_cast<float>(a.xl + (static_cast<double>(b % a.nbx) + 0.5) * a.bw);
+        float cy = static_cast<float>(a.yl + (static_cast<double>(b / a.nbx) + 0.5) * a.bh);
+#pragma unroll
+        for (int c = 0; c < C; ++c) x.v[c] = (c & 1) ? cy : cx;
+    }
+    put_z<C>(a, r, x);
+}
+
+// Mean over the pins of big star nets: one workgroup per star, lanes
+// stride the pins in float64, fixed reduction order.
+template <int C>
+__global__ void __launch_bounds__(kBT) k_expand_bigstar(ExpandArgs a, int32_t n_star) {
+    __shared__ double red[kBT / kWave];
+    int k = blockIdx.x;
+    int e = a.star_net[k];
+    int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
+    if (p1 - p0 <= kWave) return;
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    for (int p = p0 + threadIdx.x; p < p1; p += kBT) {
+        Vec<C> v = pin_value<C>(a, p);
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += v.v[c];
+    }
+    Vec<C> x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) x.v[c] = static_cast<float>(block_sum_f64<kBT>(acc[c], red) / (p1 - p0));
+    if (threadIdx.x == 0) put_z<C>(a, a.first_star + k, x);
+}
+
+// ---------------------------------------------------------------- hop
+
+struct HopArgs {
+    RowRef m;
+    const float* scale;
+    const double* lam;
+    double sigma;
+    const float* zin;
+    float* zout;
+    float* acc;
+    const float* gin;         // caller's input [n_inst][C]
+    float* out;               // caller's output [n_inst][C]
+    const uint8_t* flags;
+    int32_t n_rows;           // rows of the short path
+    int32_t n_chunk_blocks;   // chunk workgroups of this hop (placed first)
+    const int32_t* long_rows;
+    const int32_t* chunk_row;
+    const int32_t* chunk0;
+    int32_t* long_done;
+    double* partial;
+    int band;                 // 0: none, 1: acc = alpha z', 2: acc += alpha z'
+    float alpha;
+    int last;
+    float alpha_sum;
+};
+
+template <int C>
+__device__ __forceinline__ void epilogue(const HopArgs& a, int r, const Vec<C>& sum) {
+    int64_t o = static_cast<int64_t>(r) * C;
+    if (a.last && (a.flags[r] & AHR_NODE_FIXED)) {
+        vstore<C>(a.out + o, vload<C>(a.gin + o));
+        return;
+    }
+    float s = a.scale[r];
+    double lam = *a.lam;
+    float cr = 1.f, kr = 0.f;
+    if (lam > 0) {
+        double sd = s;
+        cr = static_cast<float>(1.0 - ((s > 0 ? 1.0 : 0.0) - a.sigma * sd * sd) / lam);
+        kr = static_cast<float>(sd * sd / lam);
+    }
+    Vec<C> z = vload<C>(a.zin + o);
+    Vec<C> zn;
+#pragma unroll
+    for (int c = 0; c < C; ++c) zn.v[c] = cr * z.v[c] + kr * sum.v[c];
+    if (a.last) {
+        Vec<C> tot;
+        if (a.band == 2) {
+            tot = vload<C>(a.acc + o);
+#pragma unroll
+            for (int c = 0; c < C; ++c) tot.v[c] += a.alpha * zn.v[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) tot.v[c] = a.alpha * zn.v[c];
+        }
+        Vec<C> y;
+        if (s > 0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) y.v[c] = tot.v[c] / s;
+        } else {
+            Vec<C> x = vload<C>(a.gin + o);
+#pragma unroll
+            for (int c = 0; c < C; ++c) y.v[c] = a.alpha_sum * x.v[c];
+        }
+        vstore<C>(a.out + o, y);
+        return;
+    }
+    vstore<C>(a.zout + o, zn);
+    if (a.band) {
+        Vec<C> t;
+        if (a.band == 2) {
+            t = vload<C>(a.acc + o);
+#pragma unroll
+            for (int c = 0; c < C; ++c) t.v[c] += a.alpha * zn.v[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) t.v[c] = a.alpha * zn.v[c];
+        }
+        vstore<C>(a.acc + o, t);
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void hop_chunk(const HopArgs& a) {
+    __shared__ double red[kBT / kWave];
+    int r, li, k0, k1, n0, ln, h0;
+    chunk_range(blockIdx.x, a.long_rows, a.chunk_row, a.chunk0, a.m, r, li, k0, k1, n0, ln, h0);
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    for (int k = k0 + threadIdx.x; k < k1; k += kBT) {
+        int2 e = k < ln ? a.m.net_ent[n0 + k] : a.m.hint_ent[h0 + k - ln];
+        Vec<C> v = vload<C>(a.zin + static_cast<int64_t>(e.x) * C);
+        double w = bits_f(e.y);
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += w * static_cast<double>(v.v[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = block_sum_f64<kBT>(acc[c], red);
+    if (threadIdx.x != 0) return;
+    double* part = a.partial + static_cast<int64_t>(blockIdx.x) * 8;
+#pragma unroll
+    for (int c = 0; c < C; ++c) part[c] = acc[c];
+    __threadfence();
+    int c0 = a.chunk0[li], nch = a.chunk0[li + 1] - c0;
+    int prev = atomicAdd(&a.long_done[li], 1);
+    if (prev != nch - 1) return;
+    __threadfence();
+    double tot[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) tot[c] = 0;
+    for (int q = c0; q < c0 + nch; ++q) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            tot[c] += __hip_atomic_load(a.partial + static_cast<int64_t>(q) * 8 + c, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    }
+    a.long_done[li] = 0;
+    Vec<C> sum;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sum.v[c] = static_cast<float>(tot[c]);
+    epilogue<C>(a, r, sum);
+}
+
+template <int C, int G>
+__global__ void __launch_bounds__(kBT) k_hop(HopArgs a) {
+    if (static_cast<int>(blockIdx.x) < a.n_chunk_blocks) {
+        hop_chunk<C>(a);
+        return;
+    }
+    int64_t t = static_cast<int64_t>(blockIdx.x - a.n_chunk_blocks) * kBT + threadIdx.x;
+    int64_t r64 = t / G;
+    int l = static_cast<int>(t & (G - 1));
+    if (r64 >= a.n_rows) return;
+    int r = static_cast<int>(r64);
+    int n0 = a.m.net_rp[r], n1 = a.m.net_rp[r + 1], h0 = a.m.hint_rp[r], h1 = a.m.hint_rp[r + 1];
+    if ((n1 - n0) + (h1 - h0) > kLongRow) return;
+    if (a.last && (a.flags[r] & AHR_NODE_FIXED)) {
+        if (l == 0) vstore<C>(a.out + r64 * C, vload<C>(a.gin + r64 * C));
+        return;
+    }
+    Vec<C> sum;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sum.v[c] = 0.f;
+    for (int k = n0 + l; k < n1; k += G) {
+        int2 e = a.m.net_ent[k];
+        Vec<C> v = vload<C>(a.zin + static_cast<int64_t>(e.x) * C);
+        float w = bits_f(e.y);
+#pragma unroll
+        for (int c = 0; c < C; ++c) sum.v[c] = __fmaf_rn(w, v.v[c], sum.v[c]);
+    }
+    for (int k = h0 + l; k < h1; k += G) {
+        int2 e = a.m.hint_ent[k];
+        Vec<C> v = vload<C>(a.zin + static_cast<int64_t>(e.x) * C);
+        float w = bits_f(e.y);
+#pragma unroll
+        for (int c = 0; c < C; ++c) sum.v[c] = __fmaf_rn(w, v.v[c], sum.v[c]);
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sum.v[c] += __shfl_xor(sum.v[c], o);
+    }
+    if (l == 0) epilogue<C>(a, r, sum);
+}
+
+// K = 0: out = (sum alpha) X on movable rows, X on fixed rows.
+template <int C>
+__global__ void k_identity(int32_t n_inst, const uint8_t* __restrict__ flags, const float* __restrict__ in,
+                           float* __restrict__ out, float alpha_sum) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= static_cast<int64_t>(n_inst) * C) return;
+    float v = in[i];
+    out[i] = (flags[i / C] & AHR_NODE_FIXED) ? v : alpha_sum * v;
+}
+
+template <int C>
+__global__ void k_relax(int32_t n_inst, const uint8_t* __restrict__ flags, const float* __restrict__ gc,
+                        const float* __restrict__ gt, float* __restrict__ gn, float gamma) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= static_cast<int64_t>(n_inst) * C) return;
+    float a = gc[i];
+    gn[i] = (flags[i / C] & AHR_NODE_FIXED) ? a : (1.0f - gamma) * a + gamma * gt[i];
+}
+
+template <int C, int G>
+void launch_hop(const HopArgs& a, hipStream_t s) {
+    int64_t blocks = a.n_chunk_blocks + grid_for(static_cast<int64_t>(a.n_rows) * G, kBT);
+    hipLaunchKernelGGL((k_hop<C, G>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s, a);
+    AHR_LAUNCHED("k_hop");
+}
+
+template <int C>
+void hop_dispatch(const HopArgs& a, int lanes, hipStream_t s) {
+    switch (lanes) {
+        case 1: launch_hop<C, 1>(a, s); break;
+        case 2: launch_hop<C, 2>(a, s); break;
+        case 4: launch_hop<C, 4>(a, s); break;
+        case 8: launch_hop<C, 8>(a, s); break;
+        case 16: launch_hop<C, 16>(a, s); break;
+        case 32: launch_hop<C, 32>(a, s); break;
+        default: launch_hop<C, 64>(a, s); break;
+    }
+}
+
+template <int C>
+void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s) {
+    const int64_t N = g.n_tot;
+    int kmax = 0;
+    float alpha_sum = 0.f;
+    for (int b = 0; b < spec.nbands; ++b) {
+        kmax = spec.k[b] > kmax ? spec.k[b] : kmax;
+        alpha_sum += spec.alpha[b];
+    }
+    if (kmax == 0) {
+        int64_t n = static_cast<int64_t>(g.n_inst) * C;
+        hipLaunchKernelGGL((k_identity<C>), dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.n_inst, g.nl.node_flags, in, out,
+                           alpha_sum);
+        AHR_LAUNCHED("k_identity");
+        return;
+    }
+    auto alpha_at = [&](int j, bool& is_band) {
+        float a = 0.f;
+        is_band = false;
+        for (int b = 0; b < spec.nbands; ++b)
+            if (spec.k[b] == j) {
+                a += spec.alpha[b];
+                is_band = true;
+            }
+        return a;
+    };
+    g.z0.ensure(static_cast<size_t>(N) * C, s);
+    g.z1.ensure(static_cast<size_t>(N) * C, s);
+    g.acc.ensure(static_cast<size_t>(N) * C, s);
+
+    bool b0;
+    float a0 = alpha_at(0, b0);
+    ExpandArgs e;
+    e.in = in;
+    e.scale = g.scale.p;
+    e.z0 = g.z0.p;
+    e.acc = g.acc.p;
+    e.alpha0 = a0;
+    e.band0 = b0 ? 1 : 0;
+    e.n_inst = g.n_inst;
+    e.first_mpin = g.first_mpin;
+    e.first_star = g.first_star;
+    e.first_mvirt = g.first_mvirt;
+    e.first_bvirt = g.first_bvirt;
+    e.n_tot = g.n_tot;
+    e.mpin_owner = g.mpin_owner.p;
+    e.mpin_pin = g.mpin_pin.p;
+    e.pin_off = g.nl.pin_off;
+    e.star_net = g.star_net.p;
+    e.net_ptr = g.nl.net_ptr;
+    e.pin_node = g.nl.pin_node;
+    e.pin_node_x = g.pin_node_x.p;
+    e.macro_ids = g.macro_ids.p;
+    e.nbx = g.hp.nbx;
+    e.xl = g.nl.die[0];
+    e.yl = g.nl.die[1];
+    e.bw = (static_cast<double>(g.nl.die[2]) - static_cast<double>(g.nl.die[0])) / g.hp.nbx;
+    e.bh = (static_cast<double>(g.nl.die[3]) - static_cast<double>(g.nl.die[1])) / g.hp.nby;
+    hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(N, kBT)), dim3(kBT), 0, s, e);
+    AHR_LAUNCHED("k_expand");
+    if (g.n_star)
+        hipLaunchKernelGGL((k_expand_bigstar<C>), dim3(g.n_star), dim3(kBT), 0, s, e, g.n_star);
+    AHR_LAUNCHED("k_expand_bigstar");
+
+    HopArgs h;
+    h.m = RowRef{g.net_rp.p, g.net_ent.p, g.hint_rp.p, g.hint_ent.p};
+    h.scale = g.scale.p;
+    h.lam = g.lam.p;
+    h.sigma = spec.sigma;
+    h.acc = g.acc.p;
+    h.gin = in;
+    h.out = out;
+    h.flags = g.nl.node_flags;
+    h.long_rows = g.long_rows.p;
+    h.chunk_row = g.chunk_row.p;
+    h.chunk0 = g.long_chunk0.p;
+    h.long_done = g.long_done.p;
+    h.partial = g.partial.p;
+    h.alpha_sum = alpha_sum;
+    bool has_acc = b0;
+    float* zin = g.z0.p;
+    float* zout = g.z1.p;
+    for (int j = 1; j <= kmax; ++j) {
+        bool isb;
+        float aj = alpha_at(j, isb);
+        h.zin = zin;
+        h.zout = zout;
+        h.last = j == kmax;
+        h.band = isb ? (has_acc ? 2 : 1) : 0;
+        h.alpha = aj;
+        h.n_rows = h.last ? g.n_inst : g.n_tot;
+        h.n_chunk_blocks = h.last ? g.n_chunks_inst : g.n_chunks;
+        hop_dispatch<C>(h, lanes, s);
+        has_acc = has_acc || isb;
+        float* t = zin;
+        zin = zout;
+        zout = t;
+    }
+}
+
+}  // namespace
+
+void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
+    if (g.norm_version == g.hint_version && g.norm_sigma == spec.sigma && g.norm_mode == spec.lambda_mode &&
+        g.norm_fixed == spec.lambda_fixed)
+        return;
+    const int32_t N = g.n_tot;
+    RowRef m{g.net_rp.p, g.net_ent.p, g.hint_rp.p, g.hint_ent.p};
+
+    if (g.rows_version != g.hint_version) {
+        DevBuf<int32_t> is_long, rank, nch;
+        is_long.ensure(static_cast<size_t>(N) + 1, s);
+        hipLaunchKernelGGL(k_row_len, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.net_rp.p, g.hint_rp.p, is_long.p);
+        AHR_LAUNCHED("k_row_len");
+        rank.ensure(static_cast<size_t>(N) + 1, s);
+        g.scan_tmp.ensure(scan_tmp_elems(N), s);
+        scan_i32_to_i32(is_long.p, rank.p, N, g.scan_tmp.p, s);
+        g.n_long = read_scalar(rank.p + N, s);
+        g.long_rows.ensure(static_cast<size_t>(g.n_long) + 1, s);
+        list_rows(is_long.p, rank.p, N, g.long_rows.p, s);
+        nch.ensure(static_cast<size_t>(g.n_long) + 1, s);
+        g.long_chunk0.ensure(static_cast<size_t>(g.n_long) + 1, s);
+        if (g.n_long) {
+            hipLaunchKernelGGL(k_long_nchunks, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long,
+                               g.long_rows.p, g.net_rp.p, g.hint_rp.p, nch.p);
+            AHR_LAUNCHED("k_long_nchunks");
+        }
+        g.scan_tmp.ensure(scan_tmp_elems(g.n_long), s);
+        scan_i32_to_i32(nch.p, g.long_chunk0.p, g.n_long, g.scan_tmp.p, s);
+        std::vector<int32_t> rows_h(g.n_long), c0_h(static_cast<size_t>(g.n_long) + 1);
+        AHR_HIP(hipMemcpyAsync(c0_h.data(), g.long_chunk0.p, sizeof(int32_t) * (g.n_long + 1), hipMemcpyDeviceToHost, s));
+        if (g.n_long)
+            AHR_HIP(hipMemcpyAsync(rows_h.data(), g.long_rows.p, sizeof(int32_t) * g.n_long, hipMemcpyDeviceToHost, s));
+        AHR_HIP(hipStreamSynchronize(s));
+        g.n_chunks = c0_h[g.n_long];
+        g.n_chunks_inst = 0;
+        for (int i = 0; i < g.n_long; ++i)
+            if (rows_h[i] < g.n_inst) g.n_chunks_inst = c0_h[i + 1];
+        g.chunk_row.ensure(static_cast<size_t>(g.n_chunks) + 1, s);
+        if (g.n_long) {
+            hipLaunchKernelGGL(k_chunk_rows, dim3(g.n_long), dim3(kBT), 0, s, g.n_long, g.long_chunk0.p, g.chunk_row.p);
+            AHR_LAUNCHED("k_chunk_rows");
+        }
+        g.long_done.ensure(static_cast<size_t>(g.n_long) + 1, s);
+        fill_i32(g.long_done.p, g.n_long + 1, 0, s);
+        g.partial.ensure(static_cast<size_t>(g.n_chunks) * 8 + 8, s);
+        g.rows_version = g.hint_version;
+    }
+
+    const double sigma = spec.sigma;
+    g.deg.ensure(static_cast<size_t>(N) + 1, s);
+    g.scale.ensure(static_cast<size_t>(N) + 1, s);
+    g.lam.ensure(1, s);
+    constexpr int G = 16;
+    hipLaunchKernelGGL(k_deg_short<G>, dim3(grid_for(static_cast<int64_t>(N) * G, kBT)), dim3(kBT), 0, s, N, m,
+                       g.qdeg.p, sigma, g.deg.p, g.scale.p);
+    AHR_LAUNCHED("k_deg_short");
+    if (g.n_long) {
+        hipLaunchKernelGGL(k_chunk_absdeg, dim3(g.n_chunks), dim3(kBT), 0, s, m, g.long_rows.p, g.chunk_row.p,
+                           g.long_chunk0.p, g.partial.p);
+        AHR_LAUNCHED("k_chunk_absdeg");
+        hipLaunchKernelGGL(k_long_deg_final, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long, g.long_rows.p,
+                           g.long_chunk0.p, g.partial.p, g.qdeg.p, sigma, g.deg.p, g.scale.p);
+        AHR_LAUNCHED("k_long_deg_final");
+    }
+    if (spec.lambda_mode == AHR_LAMBDA_FIXED) {
+        hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, s, g.lam.p, static_cast<double>(spec.lambda_fixed));
+        AHR_LAUNCHED("k_set_f64");
+    } else {
+        hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, s, g.lam.p, 0.0);
+        AHR_LAUNCHED("k_set_f64");
+        hipLaunchKernelGGL(k_gersh_short<G>, dim3(grid_for(static_cast<int64_t>(N) * G, kBT)), dim3(kBT), 0, s, N, m,
+                           g.deg.p, g.scale.p, sigma, g.lam.p);
+        AHR_LAUNCHED("k_gersh_short");
+        if (g.n_long) {
+            hipLaunchKernelGGL(k_chunk_gersh, dim3(g.n_chunks), dim3(kBT), 0, s, m, g.long_rows.p, g.chunk_row.p,
+                               g.long_chunk0.p, g.scale.p, g.partial.p);
+            AHR_LAUNCHED("k_chunk_gersh");
+            hipLaunchKernelGGL(k_long_gersh_final, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long,
+                               g.long_rows.p, g.long_chunk0.p, g.partial.p, g.deg.p, g.scale.p, sigma, g.lam.p);
+            AHR_LAUNCHED("k_long_gersh_final");
+        }
+    }
+    g.norm_version = g.hint_version;
+    g.norm_sigma = spec.sigma;
+    g.norm_mode = spec.lambda_mode;
+    g.norm_fixed = spec.lambda_fixed;
+}
+
+int g_hop_lanes = 8;   // lanes per short row (set by the tuner)
+
+void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int32_t ncols, hipStream_t s) {
+    normalise(g, spec, s);
+    int lanes = g_hop_lanes;
+    switch (ncols) {
+        case 1: filter_c<1>(g, spec, in, out, lanes, s); break;
+        case 2: filter_c<2>(g, spec, in, out, lanes, s); break;
+        case 4: filter_c<4>(g, spec, in, out, lanes, s); break;
+        case 8: filter_c<8>(g, spec, in, out, lanes, s); break;
+        default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
+    }
+}
+
+void relax(Graph& g, const float* gcur, const float* gt, float* gnext, int32_t ncols, float gamma, hipStream_t s) {
+    int64_t n = static_cast<int64_t>(g.n_inst) * ncols;
+    switch (ncols) {
+        case 1: hipLaunchKernelGGL(k_relax<1>, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.n_inst, g.nl.node_flags, gcur, gt, gnext, gamma); break;
+        case 2: hipLaunchKernelGGL(k_relax<2>, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.n_inst, g.nl.node_flags, gcur, gt, gnext, gamma); break;
+        case 4: hipLaunchKernelGGL(k_relax<4>, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.n_inst, g.nl.node_flags, gcur, gt, gnext, gamma); break;
+        case 8: hipLaunchKernelGGL(k_relax<8>, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.n_inst, g.nl.node_flags, gcur, gt, gnext, gamma); break;
+        default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
+    }
+    AHR_LAUNCHED("k_relax");
+}
+
+}  // namespace ahr

@@ -1,0 +1,541 @@
+// Netlist part of the graph: macro pin expansion (Section V, "Macro pin
+// expansion") and the clique/star net model with integer weights in units
+// of 2^-32, merged into a canonical CSR (rows ascending, columns strictly
+// ascending, parallel edges summed exactly).  Every structural step uses
+// integer counts, scans and sorts, so the result is bit-identical from run
+// to run and to any other exact implementation of the same definition.
+#include "ahr_internal.hpp"
+#include "device_util.hpp"
+
+namespace ahr {
+
+namespace {
+
+constexpr int kBT = 256;
+
+// Device-side validation of the caller's netlist arrays.  bad[0] gets a
+// nonzero code on the first violation found.
+__global__ void k_validate(const int32_t* __restrict__ net_ptr, int32_t n_nets, const int32_t* __restrict__ pin_node,
+                           int32_t n_pins, int32_t n_inst, int32_t* bad) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n_pins) {
+        int v = pin_node[i];
+        if (v < 0 || v >= n_inst) atomicCAS(bad, 0, 1);
+    }
+    if (i <= n_nets) {
+        int a = net_ptr[i];
+        if (i == 0 && a != 0) atomicCAS(bad, 0, 2);
+        if (i == n_nets && a != n_pins) atomicCAS(bad, 0, 3);
+        if (i < n_nets && net_ptr[i + 1] < a) atomicCAS(bad, 0, 4);
+    }
+}
+
+__global__ void k_mark_mpin(const int32_t* __restrict__ pin_node, const uint8_t* __restrict__ flags, int32_t n_pins,
+                            int32_t expand, int32_t* __restrict__ is_mp) {
+    int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n_pins) return;
+    uint8_t f = flags[pin_node[p]];
+    is_mp[p] = (expand && (f & AHR_NODE_FIXED) && (f & AHR_NODE_MACRO)) ? 1 : 0;
+}
+
+__global__ void k_pin_nodes(const int32_t* __restrict__ pin_node, const int32_t* __restrict__ is_mp,
+                            const int32_t* __restrict__ mp_rank, int32_t n_pins, int32_t n_inst,
+                            int32_t* __restrict__ pin_node_x, int32_t* __restrict__ mp_owner,
+                            int32_t* __restrict__ mp_pin) {
+    int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n_pins) return;
+    int v = pin_node[p];
+    if (is_mp[p]) {
+        int r = mp_rank[p];
+        pin_node_x[p] = n_inst + r;
+        mp_owner[r] = v;
+        mp_pin[r] = static_cast<int32_t>(p);
+    } else {
+        pin_node_x[p] = v;
+    }
+}
+
+__global__ void k_mark_star(const int32_t* __restrict__ net_ptr, int32_t n_nets, int32_t clique_max,
+                            int32_t* __restrict__ is_star, int32_t* __restrict__ is_big) {
+    int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n_nets) return;
+    int deg = net_ptr[e + 1] - net_ptr[e];
+    is_star[e] = deg > clique_max ? 1 : 0;
+    is_big[e] = deg > kWave ? 1 : 0;
+}
+
+__global__ void k_mark_macro(const uint8_t* __restrict__ flags, int32_t n, int32_t* __restrict__ out) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (flags[i] & AHR_NODE_MACRO) ? 1 : 0;
+}
+
+__device__ __forceinline__ int32_t net_of_pin(const int32_t* __restrict__ net_ptr, int32_t n_nets, int32_t p) {
+    // last e with net_ptr[e] <= p, skipping empty nets
+    int lo = 0, hi = n_nets;   // answer in [lo, hi)
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (net_ptr[mid] <= p) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Integer weight of one clique pair / one star spoke (units of 2^-32),
+// round-half-even of the float64 value, evaluated in this order:
+//   clique: (2^32 w) / (p - 1)     star: ((2^32 w) p) / (p - 1)
+__device__ __forceinline__ int64_t q_clique(float w, int p) {
+    double wq = static_cast<double>(w) * 4294967296.0;
+    return static_cast<int64_t>(__builtin_rint(wq / static_cast<double>(p - 1)));
+}
+__device__ __forceinline__ int64_t q_star(float w, int p) {
+    double wq = static_cast<double>(w) * 4294967296.0;
+    double num = wq * static_cast<double>(p);
+    return static_cast<int64_t>(__builtin_rint(num / static_cast<double>(p - 1)));
+}
+
+struct NetArgs {
+    const int32_t* net_ptr;
+    const int32_t* pin_x;
+    const float* net_w;
+    const int32_t* star_rank;
+    int32_t n_nets, n_pins, clique_max, first_star;
+};
+
+// Entries each row receives (parallel edges counted separately).
+__global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt) {
+    int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.n_pins) return;
+    int e = net_of_pin(a.net_ptr, a.n_nets, static_cast<int32_t>(p));
+    int lo = a.net_ptr[e], hi = a.net_ptr[e + 1];
+    int deg = hi - lo;
+    if (deg < 2) return;
+    int v = a.pin_x[p];
+    if (deg <= a.clique_max) {
+        int c = 0;
+        for (int b = lo; b < hi; ++b) c += (a.pin_x[b] != v) ? 1 : 0;
+        if (c) atomicAdd(&cnt[v], c);
+    } else {
+        atomicAdd(&cnt[v], 1);
+        if (p == lo) cnt[a.first_star + a.star_rank[e]] = deg;
+    }
+}
+
+__global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __restrict__ cursor,
+                          int32_t* __restrict__ dcol, int64_t* __restrict__ dq) {
+    int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.n_pins) return;
+    int e = net_of_pin(a.net_ptr, a.n_nets, static_cast<int32_t>(p));
+    int lo = a.net_ptr[e], hi = a.net_ptr[e + 1];
+    int deg = hi - lo;
+    if (deg < 2) return;
+    int v = a.pin_x[p];
+    float w = a.net_w ? a.net_w[e] : 1.0f;
+    if (deg <= a.clique_max) {
+        int64_t q = q_clique(w, deg);
+        for (int b = lo; b < hi; ++b) {
+            int u = a.pin_x[b];
+            if (u == v) continue;
+            int slot = atomicAdd(&cursor[v], 1);
+            int64_t k = rp[v] + slot;
+            dcol[k] = u;
+            dq[k] = q;
+        }
+    } else {
+        int64_t q = q_star(w, deg);
+        int z = a.first_star + a.star_rank[e];
+        int slot = atomicAdd(&cursor[v], 1);
+        int64_t k = rp[v] + slot;
+        dcol[k] = z;
+        dq[k] = q;
+        int64_t kz = rp[z] + (p - lo);
+        dcol[kz] = v;
+        dq[kz] = q;
+    }
+}
+
+// Row classes by entry count: 0 (<= 1), 1 (<= 16), 2 (<= 64), 3 (longer).
+__global__ void k_classify(const int32_t* __restrict__ cnt, int32_t n, int32_t* __restrict__ nclass,
+                           int32_t* __restrict__ lists, int32_t list_stride) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int c = cnt[r];
+    int k = c <= 1 ? 0 : (c <= 16 ? 1 : (c <= 64 ? 2 : 3));
+    int slot = atomicAdd(&nclass[k], 1);
+    lists[static_cast<int64_t>(k) * list_stride + slot] = static_cast<int32_t>(r);
+}
+
+// Rows with at most one entry: copy through.
+__global__ void k_sort_trivial(const int32_t* __restrict__ rows, int32_t nrows, const int32_t* __restrict__ cnt,
+                               const int64_t* __restrict__ rp, const int32_t* __restrict__ dcol,
+                               const int64_t* __restrict__ dq, int32_t* __restrict__ scol, int64_t* __restrict__ sq,
+                               int32_t* __restrict__ ucnt) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    int r = rows[i];
+    int c = cnt[r];
+    ucnt[r] = c;
+    if (c == 1) {
+        scol[rp[r]] = dcol[rp[r]];
+        sq[rp[r]] = dq[rp[r]];
+    }
+}
+
+// G lanes per row (G = 16 or 64): bitonic sort by column across the lanes,
+// then merge equal columns by exact integer sums.
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ rows, int32_t nrows,
+                                                    const int32_t* __restrict__ cnt, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ dcol, const int64_t* __restrict__ dq,
+                                                    int32_t* __restrict__ scol, int64_t* __restrict__ sq,
+                                                    int32_t* __restrict__ ucnt) {
+    int64_t gid = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
+    int l = threadIdx.x & (G - 1);
+    int lane = lane_id();
+    int gbase = lane - l;      // first lane of this group inside the wave
+    bool valid_row = gid < nrows;
+    int r = valid_row ? rows[gid] : 0;
+    int len = valid_row ? cnt[r] : 0;
+    int64_t base = valid_row ? rp[r] : 0;
+    int key = 0x7fffffff;
+    int64_t q = 0;
+    if (l < len) {
+        key = dcol[base + l];
+        q = dq[base + l];
+    }
+#pragma unroll
+    for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            int pk = __shfl_xor(key, j);
+            int64_t pq = __shfl_xor(q, j);
+            bool up = (l & k) == 0;
+            bool lower = (l & j) == 0;
+            bool take = lower ? (up ? (pk < key) : (pk > key)) : (up ? (pk > key) : (pk < key));
+            if (take) {
+                key = pk;
+                q = pq;
+            }
+        }
+    }
+    int prev = __shfl(key, gbase + (l > 0 ? l - 1 : 0));
+    bool head = (l < len) && (l == 0 || prev != key);
+    // run sums: a head adds the following lanes with the same column
+    int64_t sum = q;
+    bool open = head;
+    for (int t = 1; t < G; ++t) {
+        int src = gbase + (l + t < G ? l + t : l);
+        int k2 = __shfl(key, src);
+        int64_t q2 = __shfl(q, src);
+        if (open && l + t < len && k2 == key) sum += q2;
+        else open = false;
+    }
+    uint64_t hm = __ballot(head);
+    uint64_t gm = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+    uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    int idx = __popcll(hm & gm & lt);
+    if (head) {
+        scol[base + idx] = key;
+        sq[base + idx] = sum;
+    }
+    if (valid_row && l == 0) ucnt[r] = __popcll(hm & gm);
+}
+
+// One workgroup per long row: bitonic sort of (column, slot) keys in the
+// row's own segment of `tkey` (global memory; positions past the row end
+// act as +infinity), then an ordered merge of equal columns.
+__global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ cnt,
+                                                   const int64_t* __restrict__ rp, const int32_t* __restrict__ dcol,
+                                                   const int64_t* __restrict__ dq, uint64_t* __restrict__ tkey,
+                                                   int32_t* __restrict__ scol, int64_t* __restrict__ sq,
+                                                   int32_t* __restrict__ ucnt) {
+    __shared__ int red[kBT / kWave];
+    __shared__ int carry;
+    int r = rows[blockIdx.x];
+    int n = cnt[r];
+    int64_t base = rp[r];
+    uint64_t* key = tkey + base;
+    for (int k = threadIdx.x; k < n; k += kBT)
+        key[k] = (static_cast<uint64_t>(static_cast<uint32_t>(dcol[base + k])) << 32) | static_cast<uint32_t>(k);
+    int P = 1;
+    while (P < n) P <<= 1;
+    __threadfence_block();
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        int half = size >> 1;
+        // first comparator layer of a merge: mirror pairs
+        for (int i = threadIdx.x; i < P / 2; i += kBT) {
+            int blk = i / half, off = i % half;
+            int a = blk * size + off;
+            int b = blk * size + size - 1 - off;
+            if (b < n) {
+                uint64_t x = key[a], y = key[b];
+                if (y < x) { key[a] = y; key[b] = x; }
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        for (int h = half >> 1; h > 0; h >>= 1) {
+            for (int i = threadIdx.x; i < P / 2; i += kBT) {
+                int a = (i / h) * 2 * h + (i % h);
+                int b = a + h;
+                if (b < n) {
+                    uint64_t x = key[a], y = key[b];
+                    if (y < x) { key[a] = y; key[b] = x; }
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int t0 = 0; t0 < n; t0 += kBT) {
+        int k = t0 + threadIdx.x;
+        uint32_t col = 0;
+        bool head = false;
+        if (k < n) {
+            col = static_cast<uint32_t>(key[k] >> 32);
+            head = (k == 0) || (static_cast<uint32_t>(key[k - 1] >> 32) != col);
+        }
+        int tot;
+        int idx = block_rank<kBT>(head, red, &tot);
+        if (head) {
+            int64_t s = 0;
+            for (int m = k; m < n && static_cast<uint32_t>(key[m] >> 32) == col; ++m)
+                s += dq[base + static_cast<uint32_t>(key[m] & 0xffffffffu)];
+            scol[base + carry + idx] = static_cast<int32_t>(col);
+            sq[base + carry + idx] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ucnt[r] = carry;
+}
+
+// Copy merged rows to their final place, with the row weight sums.
+__global__ void k_compact(int32_t n_rows, const int64_t* __restrict__ rp, const int32_t* __restrict__ ucnt,
+                          const int32_t* __restrict__ net_rp, const int32_t* __restrict__ scol,
+                          const int64_t* __restrict__ sq, int32_t* __restrict__ col, int64_t* __restrict__ qv,
+                          int2* __restrict__ ent, int64_t* __restrict__ qdeg) {
+    // one wave per row, lanes stride the entries
+    int64_t r = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+    int l = lane_id();
+    if (r >= n_rows) return;
+    int n = ucnt[r];
+    int64_t src = rp[r];
+    int64_t dst = net_rp[r];
+    int64_t s = 0;
+    for (int k = l; k < n; k += kWave) {
+        int c = scol[src + k];
+        int64_t q = sq[src + k];
+        col[dst + k] = c;
+        qv[dst + k] = q;
+        ent[dst + k] = make_int2(c, f_bits(static_cast<float>(static_cast<double>(q) * 0x1p-32)));
+        s += q;
+    }
+    s = wave_sum(s);
+    if (l == 0) qdeg[r] = s;
+}
+
+__global__ void k_base_weight(int32_t n_inst, const int32_t* __restrict__ net_rp, const int64_t* __restrict__ qdeg,
+                              double* __restrict__ bw) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    int nnz = net_rp[i + 1] - net_rp[i];
+    int64_t q = qdeg[i];
+    bw[i] = (nnz > 0 && q != 0) ? (static_cast<double>(q) * 0x1p-32) / static_cast<double>(nnz) : 0.0;
+}
+
+template <class T>
+T read_scalar(const T* dev, hipStream_t s) {
+    T v;
+    AHR_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    AHR_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+// flags[0..n) -> ascending list of set indices; returns the count.
+int32_t list_from_flags(const int32_t* flags, int32_t n, DevBuf<int32_t>& rank, DevBuf<int32_t>& list,
+                        Graph& g, hipStream_t s) {
+    rank.ensure(static_cast<size_t>(n) + 1, s);
+    g.scan_tmp.ensure(scan_tmp_elems(n), s);
+    scan_i32_to_i32(flags, rank.p, n, g.scan_tmp.p, s);
+    int32_t cnt = read_scalar(rank.p + n, s);
+    list.ensure(static_cast<size_t>(cnt) + 1, s);
+    list_rows(flags, rank.p, n, list.p, s);
+    return cnt;
+}
+
+}  // namespace
+
+void build_netlist(Graph& g, hipStream_t s) {
+    const ahr_netlist& nl = g.nl;
+    const int32_t n_pins = nl.n_pins, n_nets = nl.n_nets, n_inst = nl.n_inst;
+    const ahr_hint_params& hp = g.hp;
+
+    // validate the device arrays
+    g.counter.ensure(8, s);
+    fill_i32(g.counter.p, 8, 0, s);
+    int64_t nv = (n_pins > n_nets + 1) ? n_pins : static_cast<int64_t>(n_nets) + 1;
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(nv, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets, nl.pin_node, n_pins,
+                       n_inst, g.counter.p);
+    AHR_LAUNCHED("k_validate");
+    int32_t bad = read_scalar(g.counter.p, s);
+    if (bad) {
+        static const char* why[] = {"", "pin_node out of [0, n_inst)", "net_ptr[0] != 0",
+                                    "net_ptr[n_nets] != n_pins", "net_ptr decreasing"};
+        throw Error{AHR_EINVAL, std::string("invalid netlist: ") + why[bad]};
+    }
+
+    // macro pin expansion
+    DevBuf<int32_t> is_mp, mp_rank;
+    is_mp.ensure(static_cast<size_t>(n_pins) + 1, s);
+    if (n_pins)
+        hipLaunchKernelGGL(k_mark_mpin, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, nl.pin_node, nl.node_flags,
+                           n_pins, (hp.flags & AHR_EXPAND_MACRO_PINS) ? 1 : 0, is_mp.p);
+    AHR_LAUNCHED("k_mark_mpin");
+    DevBuf<int32_t> mp_list;
+    g.n_mpin = list_from_flags(is_mp.p, n_pins, mp_rank, mp_list, g, s);
+    mp_list.release(s);
+    g.pin_node_x.ensure(static_cast<size_t>(n_pins) + 1, s);
+    g.mpin_owner.ensure(static_cast<size_t>(g.n_mpin) + 1, s);
+    g.mpin_pin.ensure(static_cast<size_t>(g.n_mpin) + 1, s);
+    if (n_pins)
+        hipLaunchKernelGGL(k_pin_nodes, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, nl.pin_node, is_mp.p, mp_rank.p,
+                           n_pins, n_inst, g.pin_node_x.p, g.mpin_owner.p, g.mpin_pin.p);
+    AHR_LAUNCHED("k_pin_nodes");
+    is_mp.release(s);
+    mp_rank.release(s);
+
+    // star nets and big nets
+    DevBuf<int32_t> is_star, is_big, star_rank, big_rank;
+    is_star.ensure(static_cast<size_t>(n_nets) + 1, s);
+    is_big.ensure(static_cast<size_t>(n_nets) + 1, s);
+    if (n_nets)
+        hipLaunchKernelGGL(k_mark_star, dim3(grid_for(n_nets, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets,
+                           hp.clique_max, is_star.p, is_big.p);
+    AHR_LAUNCHED("k_mark_star");
+    g.n_star = list_from_flags(is_star.p, n_nets, star_rank, g.star_net, g, s);
+    g.n_big_nets = list_from_flags(is_big.p, n_nets, big_rank, g.big_nets, g, s);
+    is_big.release(s);
+    big_rank.release(s);
+
+    // macros (instance order)
+    DevBuf<int32_t> is_mac, mac_rank;
+    is_mac.ensure(static_cast<size_t>(n_inst) + 1, s);
+    hipLaunchKernelGGL(k_mark_macro, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, nl.node_flags, n_inst, is_mac.p);
+    AHR_LAUNCHED("k_mark_macro");
+    g.n_macro = list_from_flags(is_mac.p, n_inst, mac_rank, g.macro_ids, g, s);
+    is_mac.release(s);
+    mac_rank.release(s);
+
+    // node ranges
+    int64_t first_mpin = n_inst;
+    int64_t first_star = first_mpin + g.n_mpin;
+    int64_t first_mvirt = first_star + g.n_star;
+    int64_t n_mv = (hp.flags & AHR_MACRO_HINTS) ? g.n_macro : 0;
+    int64_t first_bvirt = first_mvirt + n_mv;
+    int64_t n_bins = (hp.flags & AHR_BIN_HINTS) ? static_cast<int64_t>(hp.nbx) * hp.nby : 0;
+    int64_t n_tot = first_bvirt + n_bins;
+    if (n_tot >= INT32_MAX) throw Error{AHR_EUNSUPPORTED, "graph has 2^31 or more nodes"};
+    g.first_mpin = static_cast<int32_t>(first_mpin);
+    g.first_star = static_cast<int32_t>(first_star);
+    g.first_mvirt = static_cast<int32_t>(first_mvirt);
+    g.first_bvirt = static_cast<int32_t>(first_bvirt);
+    g.n_bins = static_cast<int32_t>(n_bins);
+    g.n_tot = static_cast<int32_t>(n_tot);
+    g.n_inst = n_inst;
+    const int32_t N = g.n_tot;
+
+    // entry counts per row, with parallel edges
+    NetArgs a{nl.net_ptr, g.pin_node_x.p, nl.net_w, star_rank.p, n_nets, n_pins, hp.clique_max, g.first_star};
+    DevBuf<int32_t> cnt;
+    cnt.ensure(static_cast<size_t>(N) + 1, s);
+    fill_i32(cnt.p, N + 1, 0, s);
+    if (n_pins)
+        hipLaunchKernelGGL(k_row_counts, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, cnt.p);
+    AHR_LAUNCHED("k_row_counts");
+    DevBuf<int64_t> rp;
+    rp.ensure(static_cast<size_t>(N) + 1, s);
+    g.scan_tmp.ensure(scan_tmp_elems(N), s);
+    scan_i32_to_i64(cnt.p, rp.p, N, g.scan_tmp.p, s);
+    int64_t nnz_dup = read_scalar(rp.p + N, s);
+    if (nnz_dup >= INT32_MAX) throw Error{AHR_EUNSUPPORTED, "netlist expands to 2^31 or more graph entries"};
+
+    DevBuf<int32_t> cursor, dcol, scol, ucnt;
+    DevBuf<int64_t> dq, sq;
+    cursor.ensure(static_cast<size_t>(N) + 1, s);
+    fill_i32(cursor.p, N + 1, 0, s);
+    dcol.ensure(static_cast<size_t>(nnz_dup) + 1, s);
+    dq.ensure(static_cast<size_t>(nnz_dup) + 1, s);
+    if (n_pins)
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, rp.p, cursor.p, dcol.p, dq.p);
+    AHR_LAUNCHED("k_scatter");
+    cursor.release(s);
+    is_star.release(s);
+    star_rank.release(s);
+
+    // per-row sort + merge
+    DevBuf<int32_t> nclass, lists;
+    nclass.ensure(4, s);
+    fill_i32(nclass.p, 4, 0, s);
+    lists.ensure(static_cast<size_t>(N) * 4 + 4, s);
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, cnt.p, N, nclass.p, lists.p, N);
+    AHR_LAUNCHED("k_classify");
+    int32_t ncls[4];
+    AHR_HIP(hipMemcpyAsync(ncls, nclass.p, sizeof ncls, hipMemcpyDeviceToHost, s));
+    AHR_HIP(hipStreamSynchronize(s));
+    scol.ensure(static_cast<size_t>(nnz_dup) + 1, s);
+    sq.ensure(static_cast<size_t>(nnz_dup) + 1, s);
+    ucnt.ensure(static_cast<size_t>(N) + 1, s);
+    fill_i32(ucnt.p, N + 1, 0, s);
+    if (ncls[0])
+        hipLaunchKernelGGL(k_sort_trivial, dim3(grid_for(ncls[0], kBT)), dim3(kBT), 0, s, lists.p, ncls[0], cnt.p,
+                           rp.p, dcol.p, dq.p, scol.p, sq.p, ucnt.p);
+    AHR_LAUNCHED("k_sort_trivial");
+    if (ncls[1])
+        hipLaunchKernelGGL(k_sort_group<16>, dim3(grid_for(static_cast<int64_t>(ncls[1]) * 16, kBT)), dim3(kBT), 0, s,
+                           lists.p + N, ncls[1], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p, ucnt.p);
+    AHR_LAUNCHED("k_sort_group16");
+    if (ncls[2])
+        hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 64, kBT)), dim3(kBT), 0, s,
+                           lists.p + 2 * static_cast<int64_t>(N), ncls[2], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
+                           ucnt.p);
+    AHR_LAUNCHED("k_sort_group64");
+    if (ncls[3]) {
+        DevBuf<uint64_t> tkey;
+        tkey.ensure(static_cast<size_t>(nnz_dup) + 1, s);
+        hipLaunchKernelGGL(k_sort_long, dim3(ncls[3]), dim3(kBT), 0, s, lists.p + 3 * static_cast<int64_t>(N), cnt.p,
+                           rp.p, dcol.p, dq.p, tkey.p, scol.p, sq.p, ucnt.p);
+        AHR_LAUNCHED("k_sort_long");
+        tkey.release(s);
+    }
+    dcol.release(s);
+    dq.release(s);
+    lists.release(s);
+    nclass.release(s);
+
+    // final CSR
+    g.net_rp.ensure(static_cast<size_t>(N) + 1, s);
+    scan_i32_to_i32(ucnt.p, g.net_rp.p, N, g.scan_tmp.p, s);
+    g.nnz_net = read_scalar(g.net_rp.p + N, s);
+    g.net_col.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
+    g.net_q.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
+    g.net_ent.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
+    g.qdeg.ensure(static_cast<size_t>(N) + 1, s);
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(static_cast<int64_t>(N) * kWave, kBT)), dim3(kBT), 0, s, N, rp.p,
+                       ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.net_ent.p, g.qdeg.p);
+    AHR_LAUNCHED("k_compact");
+    g.base_w.ensure(static_cast<size_t>(n_inst) + 1, s);
+    hipLaunchKernelGGL(k_base_weight, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.net_rp.p, g.qdeg.p,
+                       g.base_w.p);
+    AHR_LAUNCHED("k_base_weight");
+    scol.release(s);
+    sq.release(s);
+    ucnt.release(s);
+    cnt.release(s);
+    rp.release(s);
+    AHR_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace ahr

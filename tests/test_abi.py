@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every entry point include/ahr.h declares
+(CPU only: no compute call is made without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ahr.h")
+LIB = os.path.join(ROOT, "paper_2511_10073_amd", "libahr.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ahr_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for need in ["ahr_graph_build", "ahr_graph_update_hints", "ahr_filter", "ahr_refine", "ahr_hpwl",
+                 "ahr_graph_export", "ahr_graph_destroy", "ahr_last_error"]:
+        assert need in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libahr.so not built")
+def test_library_exports_every_declared_symbol():
+    import torch  # noqa: F401  (the HIP runtime torch ships is the one the library binds to)
+    lib = ctypes.CDLL(LIB)
+    for name in declared():
+        assert hasattr(lib, name), name
+    lib.ahr_version.restype = ctypes.c_char_p
+    assert lib.ahr_version().startswith(b"ahr")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libahr.so not built")
+def test_invalid_arguments_fail_before_any_device_work():
+    import paper_2511_10073_amd as A
+    lib = A.load()
+    h = ctypes.c_void_p()
+    # NULL netlist
+    assert lib.ahr_graph_build(None, None, None, 0, None, ctypes.byref(h)) == A.EINVAL
+    assert b"netlist" in lib.ahr_last_error()
+    nl = A._Netlist(10, 0, 0, 0, 0, 0, 0, 0, 0, 0, (ctypes.c_float * 4)(0, 0, 1, 1))
+    hp = A.hint_params()
+    assert lib.ahr_graph_build(ctypes.byref(nl), ctypes.byref(hp), None, 0, None, ctypes.byref(h)) == A.EINVAL
+    nl2 = A._Netlist(10, 0, 0, 0, 8, 0, 8, 0, 8, 8, (ctypes.c_float * 4)(0, 0, 1, 1))
+    bad = A.hint_params(nbx=0)
+    assert lib.ahr_graph_build(ctypes.byref(nl2), ctypes.byref(bad), None, 0, None, ctypes.byref(h)) == A.EINVAL
+    big = A.hint_params(nbx=256, nby=256)
+    assert lib.ahr_graph_build(ctypes.byref(nl2), ctypes.byref(big), None, 0, None,
+                               ctypes.byref(h)) == A.EUNSUPPORTED
+    spec = A.filter_spec(ks=(65,), alphas=(1.0,))
+    assert lib.ahr_filter(ctypes.c_void_p(8), ctypes.byref(spec), 8, 16, 2, None) == A.EINVAL
+    spec = A.filter_spec(ks=(4,), alphas=(1.0,))
+    assert lib.ahr_filter(None, ctypes.byref(spec), 8, 16, 2, None) == A.EINVAL
+    assert lib.ahr_hpwl(ctypes.c_void_p(8), 8, 3, 8, None) == A.EINVAL
+    assert lib.ahr_refine(ctypes.c_void_p(8), ctypes.byref(spec), 8, 2, 1, 1.5, 16, None) == A.EINVAL
