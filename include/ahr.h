@@ -214,6 +214,22 @@ ahr_status ahr_refine(ahr_graph* gr, const ahr_filter_spec* spec, const float* g
 ahr_status ahr_hpwl(const ahr_graph* gr, const float* g, int32_t ncols, double* out,
                     void* stream);
 
+/* Per-stage device time, measured with HIP events recorded on the stream
+ * each stage runs on (process-wide accumulators). */
+typedef struct ahr_profile {
+    double build_ms, hints_ms, norm_ms, expand_ms, hop_ms, relax_ms, hpwl_ms;
+    int64_t build_calls, hints_calls, norm_calls, expand_calls, hop_launches, relax_calls, hpwl_calls;
+    double hop_bytes;           /* algorithmic bytes of every timed hop launch (see ahr_filter) */
+} ahr_profile;
+
+/* Turn event timing on (1) or off (0) for subsequent calls.  Adds two event
+ * records per stage and per hop launch. */
+ahr_status ahr_profile_enable(int32_t on);
+
+/* Wait for the recorded events and return the accumulated times; reset = 1
+ * clears the accumulators.  Synchronises on the recorded events. */
+ahr_status ahr_profile_read(ahr_profile* out, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

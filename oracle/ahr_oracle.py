@@ -286,18 +286,25 @@ def bin_hint_edges(nl, grid: BinGrid, pos32, hint_cells, bw_cell, phis, ratio, f
 def macro_hint_edges(nl, pos32, hint_cells, bw_cell, macro_ids, first_macro_id):
     """Section V, "Macro virtual node with repulsive (negative) edges": each
     movable hint cell whose centre lies in macro m's closed footprint (reading
-    R6; tested in float32) gets w = -exp(-maxRatio_{i,m}) baseWeight_i."""
+    R6; tested in float32) gets w = -exp(-maxRatio_{i,m}) baseWeight_i.
+
+    Candidates are the cells whose x lies within the footprint's x-span plus a
+    margin (found on the cells sorted by x); the float32 test then decides."""
     size = nl["node_size"]
     x32 = pos32[hint_cells, 0].astype(np.float32)
     y32 = pos32[hint_cells, 1].astype(np.float32)
+    order = np.argsort(x32, kind="stable")
+    xs = x32[order].astype(np.float64)
     rows, cols, vals = [], [], []
     for k, m in enumerate(macro_ids):
         mx, my = np.float32(pos32[m, 0]), np.float32(pos32[m, 1])
         hw, hh = np.float32(size[m, 0]) * np.float32(0.5), np.float32(size[m, 1]) * np.float32(0.5)
-        dx32 = np.abs(x32 - mx)
-        dy32 = np.abs(y32 - my)
-        inside = (dx32 <= hw) & (dy32 <= hh)
-        i = hint_cells[inside]
+        margin = 1e-3 * (1.0 + abs(float(mx)) + float(hw))
+        lo = np.searchsorted(xs, float(mx) - float(hw) - margin, side="left")
+        hi = np.searchsorted(xs, float(mx) + float(hw) + margin, side="right")
+        cand = order[lo:hi]
+        inside = (np.abs(x32[cand] - mx) <= hw) & (np.abs(y32[cand] - my) <= hh)
+        i = np.sort(hint_cells[cand[inside]])
         if i.size == 0:
             continue
         dx = np.abs(pos32[i, 0].astype(np.float64) - float(mx))

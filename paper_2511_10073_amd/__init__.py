@@ -63,6 +63,14 @@ class _GraphHost(ctypes.Structure):
         "net_row_ptr", "net_col", "net_q", "hint_row_ptr", "hint_col", "hint_val", "degree", "scale", "lambda_up")]
 
 
+class _Profile(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_double) for n in ("build_ms", "hints_ms", "norm_ms", "expand_ms", "hop_ms",
+                                                 "relax_ms", "hpwl_ms")]
+                + [(n, ctypes.c_int64) for n in ("build_calls", "hints_calls", "norm_calls", "expand_calls",
+                                                  "hop_launches", "relax_calls", "hpwl_calls")]
+                + [("hop_bytes", ctypes.c_double)])
+
+
 _lib = None
 
 
@@ -90,6 +98,10 @@ def load() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int32
+    lib.ahr_profile_enable.argtypes = [i32]
+    lib.ahr_profile_enable.restype = ctypes.c_int32
+    lib.ahr_profile_read.argtypes = [ctypes.POINTER(_Profile), i32]
+    lib.ahr_profile_read.restype = ctypes.c_int32
     lib.ahr_graph_destroy.argtypes = [vp]
     lib.ahr_graph_destroy.restype = None
     _lib = lib
@@ -109,6 +121,17 @@ def _stream(stream=None):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def profile_enable(on: bool = True):
+    """Time every stage and hop launch with HIP events on its stream."""
+    _check(load().ahr_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    p = _Profile()
+    _check(load().ahr_profile_read(ctypes.byref(p), 1 if reset else 0))
+    return {n: getattr(p, n) for n, _ in _Profile._fields_}
 
 
 class Netlist:

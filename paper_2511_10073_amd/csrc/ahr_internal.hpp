@@ -71,6 +71,28 @@ void list_rows(const int32_t* flags, const int32_t* rank, int32_t n, int32_t* li
 // p[0..n) = v
 void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
+// ---------------------------------------------------------------- profiling
+
+enum Stage { kStageBuild, kStageHints, kStageNorm, kStageExpand, kStageHop, kStageRelax, kStageHpwl, kStageCount };
+
+bool profiling();
+
+// Records an event pair around its lifetime on stream s when profiling is on.
+class ProfScope {
+  public:
+    ProfScope(Stage st, hipStream_t s, double bytes = 0.0);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+  private:
+    int stage_;
+    hipStream_t s_;
+    double bytes_;
+    void* a_ = nullptr;
+    bool live_ = false;
+};
+
 // ---------------------------------------------------------------- graph
 
 struct Graph {
@@ -92,28 +114,38 @@ struct Graph {
     DevBuf<int32_t> net_rp;       // [n_tot+1]
     DevBuf<int32_t> net_col;      // [nnz_net]
     DevBuf<int64_t> net_q;        // [nnz_net]
-    DevBuf<int2> net_ent;         // [nnz_net] (col, float bits of q * 2^-32)
     DevBuf<int64_t> qdeg;         // [n_tot]
     DevBuf<double> base_w;        // [n_inst] baseWeight
     DevBuf<int32_t> big_nets;     // nets with more than a wave's worth of pins (HPWL)
     int32_t n_big_nets = 0;
 
     // hint part (per placement)
-    DevBuf<int32_t> cell_bin;     // [n_inst] bin of each hint cell, -1 otherwise
-    DevBuf<int32_t> bin_cnt;      // [n_bins] hint cells per bin
+    DevBuf<int32_t> cell_bin;     // [n_inst] by execution row: bin of a hint cell, -1 otherwise
     DevBuf<int32_t> bin_start;    // [n_bins+1]
-    DevBuf<int32_t> bin_cells;    // [n_hint_cells] hint cells grouped by bin, ascending
+    DevBuf<int32_t> bin_cells;    // [n_hint_cells] execution rows of hint cells by bin, ascending
     DevBuf<int64_t> bin_area_q;   // [n_bins] fixed-point area (2^-28 units)
     DevBuf<double> phi;           // [n_bins]
-    DevBuf<int32_t> bm_start;     // [n_bins+1] macros whose (widened) span covers a bin
+    DevBuf<int32_t> bm_start;     // [n_bins+1] macros whose bin span covers a bin
     DevBuf<int32_t> bm_list;
-    DevBuf<int4> macro_span;      // [n_macro] widened bin span bx0, by0, bx1, by1
+    DevBuf<int4> macro_span;      // [n_macro] bin span bx0, by0, bx1, by1 of the cells it can hold
     DevBuf<float4> macro_rect;    // [n_macro] cx, cy, w/2, h/2 (float32)
     DevBuf<int32_t> hint_cnt;     // [n_tot]
-    DevBuf<int32_t> hint_rp;      // [n_tot+1]
-    DevBuf<int2> hint_ent;        // [nnz_hint] (col, float bits of weight)
+    DevBuf<int32_t> nmac, nwin;   // [n_inst] per execution row: macros holding the cell, window size
+    DevBuf<int32_t> pair_off;     // [n_inst+1] first (cell, macro) pair of each row
+    DevBuf<int32_t> pair_row, pair_mac;
+    DevBuf<int32_t> mlist, mstart; // pairs grouped by macro
 
-    // operator (per hint version and sigma)
+    // execution layout: instance rows in spatial order (perm: exec -> id)
+    int32_t has_layout = 0;
+    DevBuf<int32_t> perm, iperm;  // [n_inst]
+    DevBuf<int32_t> xnet_rp;      // [n_tot+1]
+    DevBuf<int2> xnet_ent;        // [nnz_net]
+    DevBuf<int64_t> xqdeg;        // [n_tot]
+    DevBuf<int32_t> xhint_rp;     // [n_tot+1] hint rows, execution order
+    DevBuf<int2> xhint_ent;       // [nnz_hint] (column, float bits of the weight)
+    DevBuf<int32_t> lay_start;    // scratch
+
+    // operator (per hint version and sigma), rows in execution order
     DevBuf<double> deg;           // [n_tot]
     DevBuf<float> scale;          // [n_tot]
     DevBuf<double> lam;           // [1] lambda_up
@@ -128,10 +160,11 @@ struct Graph {
     DevBuf<int32_t> long_rows;    // rows split over chunks, ascending
     DevBuf<int32_t> long_chunk0;  // [n_long+1] first chunk of each long row
     DevBuf<int32_t> chunk_row;    // [n_chunks] long-row index of each chunk
-    DevBuf<int32_t> long_done;    // [n_long] arrival counters (kept at 0 between hops)
     DevBuf<double> partial;       // [n_chunks * 8]
     int32_t n_long = 0, n_chunks = 0;
     int32_t n_chunks_inst = 0;    // chunks of long rows below n_inst
+    int32_t n_long_inst = 0;      // long rows below n_inst
+    int64_t nnz_inst = 0;         // entries of rows below n_inst (netlist + hints)
     int32_t rows_version = -1;
 
     // filter work buffers
@@ -149,6 +182,14 @@ struct Graph {
 
 // netlist_build.hip
 void build_netlist(Graph& g, hipStream_t s);
+// Stable bucket sort: list = indices i in [0, n) with key[i] >= 0, grouped by
+// key, ascending within a key; start[k] = first position of key k
+// (start[nkeys] = count).  nkeys <= 16384.  Returns the count.
+int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
+                    DevBuf<int32_t>& start, hipStream_t s);
+// layout.hip: the execution order of instance rows (spatial) and the
+// permuted copy of the netlist rows the filter streams
+void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
 // hints.hip
 void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
 // filter.hip
@@ -160,8 +201,9 @@ void relax(Graph& g, const float* gcur, const float* gt, float* gnext, int32_t n
 // hpwl.hip
 void run_hpwl(const Graph& g, const float* pos, int32_t ncols, double* out, hipStream_t s);
 
-// Long rows: rows with more entries than this are split into chunks.
-constexpr int kLongRow = 4096;
+// Rows with more entries than kLongRow are summed by whole workgroups, in
+// chunks of kChunk entries; shorter rows by a few lanes each.
+constexpr int kLongRow = 128;
 constexpr int kChunk = 2048;
 
 }  // namespace ahr

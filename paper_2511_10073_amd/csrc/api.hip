@@ -11,19 +11,25 @@ std::string& last_error_ref();
 Graph::~Graph() {
     hipStream_t s = nullptr;
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_rp, &net_col,
-                              &big_nets, &cell_bin, &bin_cnt, &bin_start, &bin_cells, &bm_start, &bm_list,
-                              &hint_cnt, &hint_rp, &row_len, &long_rows, &long_chunk0, &chunk_row, &long_done,
-                              &i32a, &i32b, &counter};
+                              &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
+                              &nmac, &nwin, &pair_off, &pair_row, &pair_mac, &mlist, &mstart, &row_len,
+                              &long_rows, &long_chunk0, &chunk_row, &i32a, &i32b, &counter};
     for (auto* b : i32) b->release(s);
     net_q.release(s);
-    net_ent.release(s);
+    perm.release(s);
+    iperm.release(s);
+    xnet_rp.release(s);
+    xnet_ent.release(s);
+    xqdeg.release(s);
+    xhint_rp.release(s);
+    xhint_ent.release(s);
+    lay_start.release(s);
     qdeg.release(s);
     base_w.release(s);
     bin_area_q.release(s);
     phi.release(s);
     macro_span.release(s);
     macro_rect.release(s);
-    hint_ent.release(s);
     deg.release(s);
     scale.release(s);
     lam.release(s);
@@ -190,29 +196,56 @@ ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* strea
         cp(dst->net_row_ptr, g->net_rp.p, (N + 1) * sizeof(int32_t));
         cp(dst->net_col, g->net_col.p, g->nnz_net * sizeof(int32_t));
         cp(dst->net_q, g->net_q.p, g->nnz_net * sizeof(int64_t));
-        if (g->has_hints) {
-            cp(dst->hint_row_ptr, g->hint_rp.p, (N + 1) * sizeof(int32_t));
-            if ((dst->hint_col || dst->hint_val) && g->nnz_hint) {
-                std::vector<int2> ent(g->nnz_hint);
-                AHR_HIP(hipMemcpyAsync(ent.data(), g->hint_ent.p, g->nnz_hint * sizeof(int2), hipMemcpyDeviceToHost, s));
-                AHR_HIP(hipStreamSynchronize(s));
-                for (int32_t k = 0; k < g->nnz_hint; ++k) {
-                    if (dst->hint_col) dst->hint_col[k] = ent[k].x;
-                    if (dst->hint_val) std::memcpy(&dst->hint_val[k], &ent[k].y, sizeof(float));
+        if (g->has_hints && (dst->hint_row_ptr || dst->hint_col || dst->hint_val)) {
+            // hint rows live in execution order: return them in node order
+            std::vector<int32_t> xrp(N + 1), perm(g->n_inst);
+            std::vector<int2> ent(g->nnz_hint);
+            AHR_HIP(hipMemcpyAsync(xrp.data(), g->xhint_rp.p, (N + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipMemcpyAsync(perm.data(), g->perm.p, g->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            if (g->nnz_hint)
+                AHR_HIP(hipMemcpyAsync(ent.data(), g->xhint_ent.p, g->nnz_hint * sizeof(int2), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipStreamSynchronize(s));
+            const size_t ni = static_cast<size_t>(g->n_inst);
+            std::vector<int32_t> iperm(ni);
+            for (size_t r = 0; r < ni; ++r) iperm[perm[r]] = static_cast<int32_t>(r);
+            std::vector<int32_t> rp(N + 1, 0);
+            for (size_t c = 0; c < N; ++c) {
+                size_t r = c < ni ? static_cast<size_t>(iperm[c]) : c;
+                rp[c + 1] = rp[c] + (xrp[r + 1] - xrp[r]);
+            }
+            if (dst->hint_row_ptr) std::memcpy(dst->hint_row_ptr, rp.data(), (N + 1) * sizeof(int32_t));
+            for (size_t c = 0; c < N; ++c) {
+                size_t r = c < ni ? static_cast<size_t>(iperm[c]) : c;
+                for (int32_t k = xrp[r]; k < xrp[r + 1]; ++k) {
+                    int32_t o = rp[c] + (k - xrp[r]);
+                    int32_t col = ent[k].x;
+                    if (dst->hint_col) dst->hint_col[o] = col < g->n_inst ? perm[col] : col;
+                    if (dst->hint_val) std::memcpy(&dst->hint_val[o], &ent[k].y, sizeof(float));
                 }
             }
         } else if (dst->hint_row_ptr) {
             std::memset(dst->hint_row_ptr, 0, (N + 1) * sizeof(int32_t));
         }
-        if (g->norm_version >= 0) {
-            cp(dst->degree, g->deg.p, N * sizeof(double));
-            cp(dst->scale, g->scale.p, N * sizeof(float));
-            if (dst->lambda_up) {
-                double l = 0;
-                AHR_HIP(hipMemcpyAsync(&l, g->lam.p, sizeof l, hipMemcpyDeviceToHost, s));
-                AHR_HIP(hipStreamSynchronize(s));
-                *dst->lambda_up = static_cast<float>(l);
+        if (g->norm_version >= 0 && (dst->degree || dst->scale)) {
+            // operator arrays live in execution order; return them in node order
+            std::vector<double> d(N);
+            std::vector<float> sc(N);
+            std::vector<int32_t> perm(g->n_inst);
+            AHR_HIP(hipMemcpyAsync(d.data(), g->deg.p, N * sizeof(double), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipMemcpyAsync(sc.data(), g->scale.p, N * sizeof(float), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipMemcpyAsync(perm.data(), g->perm.p, g->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipStreamSynchronize(s));
+            for (size_t r = 0; r < N; ++r) {
+                size_t c = r < static_cast<size_t>(g->n_inst) ? static_cast<size_t>(perm[r]) : r;
+                if (dst->degree) dst->degree[c] = d[r];
+                if (dst->scale) dst->scale[c] = sc[r];
             }
+        }
+        if (g->norm_version >= 0 && dst->lambda_up) {
+            double l = 0;
+            AHR_HIP(hipMemcpyAsync(&l, g->lam.p, sizeof l, hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipStreamSynchronize(s));
+            *dst->lambda_up = static_cast<float>(l);
         }
         AHR_HIP(hipStreamSynchronize(s));
         return AHR_OK;

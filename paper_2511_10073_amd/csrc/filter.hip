@@ -15,8 +15,8 @@
 //
 // Rows with up to kLongRow entries are handled by G lanes each; longer rows
 // (bin and macro virtual nodes, big-net stars) are split into kChunk-entry
-// chunks, one workgroup each, whose float64 partial sums the last arriving
-// workgroup adds in chunk order -- deterministic for any schedule.
+// chunks, one workgroup each, whose float64 partial sums a small kernel adds
+// after the hop in a fixed order -- deterministic for any schedule.
 #include "ahr_internal.hpp"
 #include "device_util.hpp"
 
@@ -183,31 +183,46 @@ __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
     atomicMax(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)));
 }
 
+// Grid-stride over rows (G lanes per row); each workgroup keeps its running
+// maximum and issues one atomic at the end (the maximum is order-independent).
+constexpr int kGershGrid = 2048;
+
 template <int G>
 __global__ void __launch_bounds__(kBT) k_gersh_short(int32_t n, RowRef m, const double* __restrict__ deg,
                                                      const float* __restrict__ scale, double sigma,
                                                      double* __restrict__ lam) {
-    int64_t t = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
-    int64_t r = t / G;
-    int l = static_cast<int>(t & (G - 1));
-    if (r >= n) return;
-    int n0 = m.net_rp[r], n1 = m.net_rp[r + 1], h0 = m.hint_rp[r], h1 = m.hint_rp[r + 1];
-    if ((n1 - n0) + (h1 - h0) > kLongRow) return;
-    double a = 0;
-    for (int k = n0 + l; k < n1; k += G) {
-        int2 e = m.net_ent[k];
-        a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
-    }
-    for (int k = h0 + l; k < h1; k += G) {
-        int2 e = m.hint_ent[k];
-        a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
-    }
+    __shared__ double red[kBT / kWave];
+    const int l = threadIdx.x & (G - 1);
+    const int64_t stride = static_cast<int64_t>(kGershGrid) * (kBT / G);
+    double best = 0;
+    for (int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G; r < n; r += stride) {
+        int n0 = m.net_rp[r], n1 = m.net_rp[r + 1], h0 = m.hint_rp[r], h1 = m.hint_rp[r + 1];
+        if ((n1 - n0) + (h1 - h0) > kLongRow) continue;          // group-uniform
+        double a = 0;
+        for (int k = n0 + l; k < n1; k += G) {
+            int2 e = m.net_ent[k];
+            a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
+        }
+        for (int k = h0 + l; k < h1; k += G) {
+            int2 e = m.hint_ent[k];
+            a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
+        }
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) a += __shfl_xor(a, o);
-    if (l == 0) {
-        float s = scale[r];
-        double rr = diag_abs(s, deg[r], sigma) + static_cast<double>(s) * a;
-        atomic_max_nonneg(lam, rr);
+        for (int o = G / 2; o > 0; o >>= 1) a += __shfl_xor(a, o);
+        if (l == 0) {
+            float s = scale[r];
+            double rr = diag_abs(s, deg[r], sigma) + static_cast<double>(s) * a;
+            best = rr > best ? rr : best;
+        }
+    }
+    best = wave_max(best);
+    __syncthreads();
+    if (lane_id() == 0) red[wave_id()] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int w = 1; w < kBT / kWave; ++w) b = red[w] > b ? red[w] : b;
+        atomic_max_nonneg(lam, b);
     }
 }
 
@@ -245,7 +260,8 @@ __global__ void k_set_f64(double* p, double v) { *p = v; }
 // ---------------------------------------------------------------- signal
 
 struct ExpandArgs {
-    const float* in;          // [n_inst][C]
+    const float* in;          // [n_inst][C], instance order
+    const int32_t* perm;      // execution row -> instance
     const float* scale;
     float* z0;                // [n_tot][C]
     float* acc;               // band at k = 0
@@ -301,7 +317,7 @@ __global__ void __launch_bounds__(kBT) k_expand(ExpandArgs a) {
     int r = static_cast<int>(r64);
     Vec<C> x;
     if (r < a.n_inst) {
-        x = vload<C>(a.in + r64 * C);
+        x = vload<C>(a.in + static_cast<int64_t>(a.perm[r]) * C);
     } else if (r < a.first_star) {
         int k = r - a.first_mpin;
         x = pin_value<C>(a, a.mpin_pin[k]);
@@ -364,15 +380,15 @@ struct HopArgs {
     const float* zin;
     float* zout;
     float* acc;
-    const float* gin;         // caller's input [n_inst][C]
-    float* out;               // caller's output [n_inst][C]
+    const float* gin;         // caller's input [n_inst][C], instance order
+    float* out;               // caller's output [n_inst][C], instance order
     const uint8_t* flags;
+    const int32_t* perm;      // execution row -> instance
     int32_t n_rows;           // rows of the short path
     int32_t n_chunk_blocks;   // chunk workgroups of this hop (placed first)
     const int32_t* long_rows;
     const int32_t* chunk_row;
     const int32_t* chunk0;
-    int32_t* long_done;
     double* partial;
     int band;                 // 0: none, 1: acc = alpha z', 2: acc += alpha z'
     float alpha;
@@ -380,144 +396,195 @@ struct HopArgs {
     float alpha_sum;
 };
 
+// Operands of a row's epilogue, loaded before the row's gathers so their
+// latency overlaps them.
 template <int C>
-__device__ __forceinline__ void epilogue(const HopArgs& a, int r, const Vec<C>& sum) {
-    int64_t o = static_cast<int64_t>(r) * C;
-    if (a.last && (a.flags[r] & AHR_NODE_FIXED)) {
-        vstore<C>(a.out + o, vload<C>(a.gin + o));
+struct RowOps {
+    Vec<C> z, acc;
+    float s;
+    int inst;        // instance of the row (last hop)
+    uint8_t flag;
+};
+
+template <int C>
+__device__ __forceinline__ RowOps<C> row_ops(const HopArgs& a, int r) {
+    RowOps<C> o;
+    int64_t off = static_cast<int64_t>(r) * C;
+    o.s = a.scale[r];
+    o.z = vload<C>(a.zin + off);
+    if (a.band == 2) o.acc = vload<C>(a.acc + off);
+    o.inst = a.last ? a.perm[r] : r;
+    o.flag = a.last ? a.flags[o.inst] : 0;
+    return o;
+}
+
+template <int C>
+__device__ __forceinline__ void epilogue(const HopArgs& a, int r, const RowOps<C>& o, const Vec<C>& sum) {
+    const int64_t off = static_cast<int64_t>(r) * C;
+    const int64_t oc = static_cast<int64_t>(o.inst) * C;   // instance row of the output (last hop)
+    if (a.last && (o.flag & AHR_NODE_FIXED)) {
+        vstore<C>(a.out + oc, vload<C>(a.gin + oc));
         return;
     }
-    float s = a.scale[r];
-    double lam = *a.lam;
+    const float s = o.s;
+    const double lam = *a.lam;
     float cr = 1.f, kr = 0.f;
     if (lam > 0) {
         double sd = s;
         cr = static_cast<float>(1.0 - ((s > 0 ? 1.0 : 0.0) - a.sigma * sd * sd) / lam);
         kr = static_cast<float>(sd * sd / lam);
     }
-    Vec<C> z = vload<C>(a.zin + o);
     Vec<C> zn;
 #pragma unroll
-    for (int c = 0; c < C; ++c) zn.v[c] = cr * z.v[c] + kr * sum.v[c];
+    for (int c = 0; c < C; ++c) zn.v[c] = cr * o.z.v[c] + kr * sum.v[c];
     if (a.last) {
         Vec<C> tot;
-        if (a.band == 2) {
-            tot = vload<C>(a.acc + o);
 #pragma unroll
-            for (int c = 0; c < C; ++c) tot.v[c] += a.alpha * zn.v[c];
-        } else {
-#pragma unroll
-            for (int c = 0; c < C; ++c) tot.v[c] = a.alpha * zn.v[c];
-        }
+        for (int c = 0; c < C; ++c) tot.v[c] = (a.band == 2 ? o.acc.v[c] : 0.f) + a.alpha * zn.v[c];
         Vec<C> y;
         if (s > 0) {
 #pragma unroll
             for (int c = 0; c < C; ++c) y.v[c] = tot.v[c] / s;
         } else {
-            Vec<C> x = vload<C>(a.gin + o);
+            Vec<C> x = vload<C>(a.gin + oc);
 #pragma unroll
             for (int c = 0; c < C; ++c) y.v[c] = a.alpha_sum * x.v[c];
         }
-        vstore<C>(a.out + o, y);
+        vstore<C>(a.out + oc, y);
         return;
     }
-    vstore<C>(a.zout + o, zn);
+    vstore<C>(a.zout + off, zn);
     if (a.band) {
         Vec<C> t;
-        if (a.band == 2) {
-            t = vload<C>(a.acc + o);
 #pragma unroll
-            for (int c = 0; c < C; ++c) t.v[c] += a.alpha * zn.v[c];
-        } else {
-#pragma unroll
-            for (int c = 0; c < C; ++c) t.v[c] = a.alpha * zn.v[c];
-        }
-        vstore<C>(a.acc + o, t);
+        for (int c = 0; c < C; ++c) t.v[c] = (a.band == 2 ? o.acc.v[c] : 0.f) + a.alpha * zn.v[c];
+        vstore<C>(a.acc + off, t);
     }
 }
 
+// Entry k of row r's concatenated (netlist, hints) list; k is clamped into
+// the row by the caller.
+__device__ __forceinline__ int2 row_entry(const RowRef& m, int n0, int ln, int h0, int k) {
+    return k < ln ? m.net_ent[n0 + k] : m.hint_ent[h0 + k - ln];
+}
+
+// Sum of U entries per lane: all entry loads issue before any gather and all
+// gathers before any use, so each lane keeps 2U requests in flight.
+template <int C, int U, class Acc>
+__device__ __forceinline__ void gather_batch(const HopArgs& a, int n0, int ln, int h0, int len, int k0, int step,
+                                             Acc* acc) {
+    int2 e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int k = k0 + u * step;
+        int kc = k < len ? k : len - 1;
+        e[u] = row_entry(a.m, n0, ln, h0, kc);
+        if (k >= len) e[u].y = 0;                 // weight 0 for the clamped duplicates
+    }
+    Vec<C> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = vload<C>(a.zin + static_cast<int64_t>(e[u].x) * C);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float w = bits_f(e[u].y);
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += static_cast<Acc>(w) * static_cast<Acc>(v[u].v[c]);
+    }
+}
+
+// One chunk of a long row: the workgroup's float64 partial sum goes to
+// partial[chunk]; k_hop_long adds a row's partials after the launch ends (no
+// device-scope fence inside the hop: on this chip that is an L2 write-back).
 template <int C>
 __device__ __forceinline__ void hop_chunk(const HopArgs& a) {
     __shared__ double red[kBT / kWave];
     int r, li, k0, k1, n0, ln, h0;
     chunk_range(blockIdx.x, a.long_rows, a.chunk_row, a.chunk0, a.m, r, li, k0, k1, n0, ln, h0);
+    constexpr int U = kChunk / kBT;
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0;
-    for (int k = k0 + threadIdx.x; k < k1; k += kBT) {
-        int2 e = k < ln ? a.m.net_ent[n0 + k] : a.m.hint_ent[h0 + k - ln];
-        Vec<C> v = vload<C>(a.zin + static_cast<int64_t>(e.x) * C);
-        double w = bits_f(e.y);
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] += w * static_cast<double>(v.v[c]);
-    }
+    gather_batch<C, U, double>(a, n0, ln, h0, k1, k0 + threadIdx.x, kBT, acc);
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = block_sum_f64<kBT>(acc[c], red);
-    if (threadIdx.x != 0) return;
-    double* part = a.partial + static_cast<int64_t>(blockIdx.x) * 8;
+    if (threadIdx.x == 0) {
+        double* part = a.partial + static_cast<int64_t>(blockIdx.x) * 8;
 #pragma unroll
-    for (int c = 0; c < C; ++c) part[c] = acc[c];
-    __threadfence();
-    int c0 = a.chunk0[li], nch = a.chunk0[li + 1] - c0;
-    int prev = atomicAdd(&a.long_done[li], 1);
-    if (prev != nch - 1) return;
-    __threadfence();
+        for (int c = 0; c < C; ++c) part[c] = acc[c];
+    }
+}
+
+// Long rows after a hop: one wave per row adds its chunk partials (fixed
+// order: lanes stride the chunks, then a fixed butterfly) and applies the
+// row epilogue.
+template <int C>
+__global__ void __launch_bounds__(kBT) k_hop_long(HopArgs a, int32_t n_long_rows) {
+    const int64_t li = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / kWave;
+    if (li >= n_long_rows) return;
+    const int r = a.long_rows[li];
+    const int c0 = a.chunk0[li], c1 = a.chunk0[li + 1];
+    const int l = lane_id();
+    RowOps<C> ops;
+    if (l == 0) ops = row_ops<C>(a, r);
     double tot[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) tot[c] = 0;
-    for (int q = c0; q < c0 + nch; ++q) {
+    for (int q = c0 + l; q < c1; q += kWave) {
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            tot[c] += __hip_atomic_load(a.partial + static_cast<int64_t>(q) * 8 + c, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
+        for (int c = 0; c < C; ++c) tot[c] += a.partial[static_cast<int64_t>(q) * 8 + c];
     }
-    a.long_done[li] = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) tot[c] = wave_sum(tot[c]);
+    if (l != 0) return;
     Vec<C> sum;
 #pragma unroll
     for (int c = 0; c < C; ++c) sum.v[c] = static_cast<float>(tot[c]);
-    epilogue<C>(a, r, sum);
+    epilogue<C>(a, r, ops, sum);
 }
 
-template <int C, int G>
+// Workgroups of the short-row part are renumbered so that each XCD (blocks
+// are dealt round-robin over the 8 XCDs) takes one contiguous range of rows:
+// rows are in spatial order, so their gathers then share that XCD's L2.
+constexpr int kXcds = 8;
+
+// b in [0, nb), nb a multiple of kXcds: a bijection onto [0, nb) that gives
+// XCD x (blocks b with b % kXcds == x) the tiles [x nb/8, (x+1) nb/8).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+    int64_t per = nb / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+template <int C, int G, int U>
 __global__ void __launch_bounds__(kBT) k_hop(HopArgs a) {
     if (static_cast<int>(blockIdx.x) < a.n_chunk_blocks) {
         hop_chunk<C>(a);
         return;
     }
-    int64_t t = static_cast<int64_t>(blockIdx.x - a.n_chunk_blocks) * kBT + threadIdx.x;
-    int64_t r64 = t / G;
-    int l = static_cast<int>(t & (G - 1));
+    const int64_t nb = static_cast<int64_t>(gridDim.x) - a.n_chunk_blocks;     // a multiple of kXcds
+    const int64_t tile = xcd_tile(static_cast<int64_t>(blockIdx.x) - a.n_chunk_blocks, nb);
+    const int64_t r64 = (tile * kBT + threadIdx.x) / G;
+    const int l = static_cast<int>(threadIdx.x & (G - 1));
     if (r64 >= a.n_rows) return;
-    int r = static_cast<int>(r64);
-    int n0 = a.m.net_rp[r], n1 = a.m.net_rp[r + 1], h0 = a.m.hint_rp[r], h1 = a.m.hint_rp[r + 1];
-    if ((n1 - n0) + (h1 - h0) > kLongRow) return;
-    if (a.last && (a.flags[r] & AHR_NODE_FIXED)) {
-        if (l == 0) vstore<C>(a.out + r64 * C, vload<C>(a.gin + r64 * C));
-        return;
-    }
+    const int r = static_cast<int>(r64);
+    const int n0 = a.m.net_rp[r], ln = a.m.net_rp[r + 1] - n0;
+    const int h0 = a.m.hint_rp[r], lh = a.m.hint_rp[r + 1] - h0;
+    const int len = ln + lh;
+    if (len > kLongRow) return;
+    RowOps<C> ops;
+    if (l == 0) ops = row_ops<C>(a, r);
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.f;
+    for (int k0 = l; k0 < len; k0 += G * U) gather_batch<C, U, float>(a, n0, ln, h0, len, k0, G, acc);
     Vec<C> sum;
 #pragma unroll
-    for (int c = 0; c < C; ++c) sum.v[c] = 0.f;
-    for (int k = n0 + l; k < n1; k += G) {
-        int2 e = a.m.net_ent[k];
-        Vec<C> v = vload<C>(a.zin + static_cast<int64_t>(e.x) * C);
-        float w = bits_f(e.y);
-#pragma unroll
-        for (int c = 0; c < C; ++c) sum.v[c] = __fmaf_rn(w, v.v[c], sum.v[c]);
-    }
-    for (int k = h0 + l; k < h1; k += G) {
-        int2 e = a.m.hint_ent[k];
-        Vec<C> v = vload<C>(a.zin + static_cast<int64_t>(e.x) * C);
-        float w = bits_f(e.y);
-#pragma unroll
-        for (int c = 0; c < C; ++c) sum.v[c] = __fmaf_rn(w, v.v[c], sum.v[c]);
-    }
+    for (int c = 0; c < C; ++c) sum.v[c] = acc[c];
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) {
 #pragma unroll
         for (int c = 0; c < C; ++c) sum.v[c] += __shfl_xor(sum.v[c], o);
     }
-    if (l == 0) epilogue<C>(a, r, sum);
+    if (l == 0) epilogue<C>(a, r, ops, sum);
 }
 
 // K = 0: out = (sum alpha) X on movable rows, X on fixed rows.
@@ -540,22 +607,30 @@ __global__ void k_relax(int32_t n_inst, const uint8_t* __restrict__ flags, const
 }
 
 template <int C, int G>
-void launch_hop(const HopArgs& a, hipStream_t s) {
-    int64_t blocks = a.n_chunk_blocks + grid_for(static_cast<int64_t>(a.n_rows) * G, kBT);
-    hipLaunchKernelGGL((k_hop<C, G>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s, a);
+void launch_hop(const HopArgs& a, int32_t n_long_rows, hipStream_t s) {
+    constexpr int U = 32 / G > 0 ? (32 / G < 8 ? 32 / G : 8) : 1;   // entries per lane per batch
+    int64_t tiles = grid_for(static_cast<int64_t>(a.n_rows) * G, kBT);
+    tiles = (tiles + kXcds - 1) / kXcds * kXcds;                    // see xcd_tile
+    int64_t blocks = a.n_chunk_blocks + tiles;
+    hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U)>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s, a);
     AHR_LAUNCHED("k_hop");
+    if (n_long_rows > 0) {
+        hipLaunchKernelGGL(k_hop_long<C>, dim3(grid_for(static_cast<int64_t>(n_long_rows) * kWave, kBT)), dim3(kBT),
+                           0, s, a, n_long_rows);
+        AHR_LAUNCHED("k_hop_long");
+    }
 }
 
 template <int C>
-void hop_dispatch(const HopArgs& a, int lanes, hipStream_t s) {
+void hop_dispatch(const HopArgs& a, int lanes, int32_t n_long_rows, hipStream_t s) {
     switch (lanes) {
-        case 1: launch_hop<C, 1>(a, s); break;
-        case 2: launch_hop<C, 2>(a, s); break;
-        case 4: launch_hop<C, 4>(a, s); break;
-        case 8: launch_hop<C, 8>(a, s); break;
-        case 16: launch_hop<C, 16>(a, s); break;
-        case 32: launch_hop<C, 32>(a, s); break;
-        default: launch_hop<C, 64>(a, s); break;
+        case 1: launch_hop<C, 1>(a, n_long_rows, s); break;
+        case 2: launch_hop<C, 2>(a, n_long_rows, s); break;
+        case 4: launch_hop<C, 4>(a, n_long_rows, s); break;
+        case 8: launch_hop<C, 8>(a, n_long_rows, s); break;
+        case 16: launch_hop<C, 16>(a, n_long_rows, s); break;
+        case 32: launch_hop<C, 32>(a, n_long_rows, s); break;
+        default: launch_hop<C, 64>(a, n_long_rows, s); break;
     }
 }
 
@@ -593,6 +668,7 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
     float a0 = alpha_at(0, b0);
     ExpandArgs e;
     e.in = in;
+    e.perm = g.perm.p;
     e.scale = g.scale.p;
     e.z0 = g.z0.p;
     e.acc = g.acc.p;
@@ -617,14 +693,18 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
     e.yl = g.nl.die[1];
     e.bw = (static_cast<double>(g.nl.die[2]) - static_cast<double>(g.nl.die[0])) / g.hp.nbx;
     e.bh = (static_cast<double>(g.nl.die[3]) - static_cast<double>(g.nl.die[1])) / g.hp.nby;
-    hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(N, kBT)), dim3(kBT), 0, s, e);
-    AHR_LAUNCHED("k_expand");
-    if (g.n_star)
-        hipLaunchKernelGGL((k_expand_bigstar<C>), dim3(g.n_star), dim3(kBT), 0, s, e, g.n_star);
-    AHR_LAUNCHED("k_expand_bigstar");
+    {
+        ProfScope ps(kStageExpand, s);
+        hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(N, kBT)), dim3(kBT), 0, s, e);
+        AHR_LAUNCHED("k_expand");
+        if (g.n_star)
+            hipLaunchKernelGGL((k_expand_bigstar<C>), dim3(g.n_star), dim3(kBT), 0, s, e, g.n_star);
+        AHR_LAUNCHED("k_expand_bigstar");
+    }
 
     HopArgs h;
-    h.m = RowRef{g.net_rp.p, g.net_ent.p, g.hint_rp.p, g.hint_ent.p};
+    h.m = RowRef{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
+    h.perm = g.perm.p;
     h.scale = g.scale.p;
     h.lam = g.lam.p;
     h.sigma = spec.sigma;
@@ -635,7 +715,6 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
     h.long_rows = g.long_rows.p;
     h.chunk_row = g.chunk_row.p;
     h.chunk0 = g.long_chunk0.p;
-    h.long_done = g.long_done.p;
     h.partial = g.partial.p;
     h.alpha_sum = alpha_sum;
     bool has_acc = b0;
@@ -651,7 +730,19 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
         h.alpha = aj;
         h.n_rows = h.last ? g.n_inst : g.n_tot;
         h.n_chunk_blocks = h.last ? g.n_chunks_inst : g.n_chunks;
-        hop_dispatch<C>(h, lanes, s);
+        {
+            // algorithmic bytes: row pointers, (column, weight) entries, one read
+            // of the gathered signal, the row writes, the band accumulator
+            const double R = h.n_rows;
+            const double E = h.last ? static_cast<double>(g.nnz_inst)
+                                    : static_cast<double>(g.nnz_net) + static_cast<double>(g.nnz_hint);
+            double acc_b = 0;
+            if (h.band == 1) acc_b = h.last ? 0 : 4.0 * C * R;
+            if (h.band == 2) acc_b = h.last ? 4.0 * C * R : 8.0 * C * R;
+            double bytes = 4.0 * (R + 1) + 8.0 * E + 4.0 * C * static_cast<double>(N) + 4.0 * C * R + acc_b;
+            ProfScope ps(kStageHop, s, bytes);
+            hop_dispatch<C>(h, lanes, h.last ? g.n_long_inst : g.n_long, s);
+        }
         has_acc = has_acc || isb;
         float* t = zin;
         zin = zout;
@@ -665,13 +756,14 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     if (g.norm_version == g.hint_version && g.norm_sigma == spec.sigma && g.norm_mode == spec.lambda_mode &&
         g.norm_fixed == spec.lambda_fixed)
         return;
+    ProfScope ps(kStageNorm, s);
     const int32_t N = g.n_tot;
-    RowRef m{g.net_rp.p, g.net_ent.p, g.hint_rp.p, g.hint_ent.p};
+    RowRef m{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
 
     if (g.rows_version != g.hint_version) {
         DevBuf<int32_t> is_long, rank, nch;
         is_long.ensure(static_cast<size_t>(N) + 1, s);
-        hipLaunchKernelGGL(k_row_len, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.net_rp.p, g.hint_rp.p, is_long.p);
+        hipLaunchKernelGGL(k_row_len, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.xnet_rp.p, g.xhint_rp.p, is_long.p);
         AHR_LAUNCHED("k_row_len");
         rank.ensure(static_cast<size_t>(N) + 1, s);
         g.scan_tmp.ensure(scan_tmp_elems(N), s);
@@ -683,7 +775,7 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
         g.long_chunk0.ensure(static_cast<size_t>(g.n_long) + 1, s);
         if (g.n_long) {
             hipLaunchKernelGGL(k_long_nchunks, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long,
-                               g.long_rows.p, g.net_rp.p, g.hint_rp.p, nch.p);
+                               g.long_rows.p, g.xnet_rp.p, g.xhint_rp.p, nch.p);
             AHR_LAUNCHED("k_long_nchunks");
         }
         g.scan_tmp.ensure(scan_tmp_elems(g.n_long), s);
@@ -694,16 +786,20 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
             AHR_HIP(hipMemcpyAsync(rows_h.data(), g.long_rows.p, sizeof(int32_t) * g.n_long, hipMemcpyDeviceToHost, s));
         AHR_HIP(hipStreamSynchronize(s));
         g.n_chunks = c0_h[g.n_long];
+        int32_t at_inst[2];
+        AHR_HIP(hipMemcpyAsync(&at_inst[0], g.xnet_rp.p + g.n_inst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        AHR_HIP(hipMemcpyAsync(&at_inst[1], g.xhint_rp.p + g.n_inst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        AHR_HIP(hipStreamSynchronize(s));
+        g.nnz_inst = static_cast<int64_t>(at_inst[0]) + at_inst[1];
         g.n_chunks_inst = 0;
+        g.n_long_inst = 0;
         for (int i = 0; i < g.n_long; ++i)
-            if (rows_h[i] < g.n_inst) g.n_chunks_inst = c0_h[i + 1];
+            if (rows_h[i] < g.n_inst) g.n_chunks_inst = c0_h[i + 1], g.n_long_inst = i + 1;
         g.chunk_row.ensure(static_cast<size_t>(g.n_chunks) + 1, s);
         if (g.n_long) {
             hipLaunchKernelGGL(k_chunk_rows, dim3(g.n_long), dim3(kBT), 0, s, g.n_long, g.long_chunk0.p, g.chunk_row.p);
             AHR_LAUNCHED("k_chunk_rows");
         }
-        g.long_done.ensure(static_cast<size_t>(g.n_long) + 1, s);
-        fill_i32(g.long_done.p, g.n_long + 1, 0, s);
         g.partial.ensure(static_cast<size_t>(g.n_chunks) * 8 + 8, s);
         g.rows_version = g.hint_version;
     }
@@ -714,14 +810,14 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     g.lam.ensure(1, s);
     constexpr int G = 16;
     hipLaunchKernelGGL(k_deg_short<G>, dim3(grid_for(static_cast<int64_t>(N) * G, kBT)), dim3(kBT), 0, s, N, m,
-                       g.qdeg.p, sigma, g.deg.p, g.scale.p);
+                       g.xqdeg.p, sigma, g.deg.p, g.scale.p);
     AHR_LAUNCHED("k_deg_short");
     if (g.n_long) {
         hipLaunchKernelGGL(k_chunk_absdeg, dim3(g.n_chunks), dim3(kBT), 0, s, m, g.long_rows.p, g.chunk_row.p,
                            g.long_chunk0.p, g.partial.p);
         AHR_LAUNCHED("k_chunk_absdeg");
         hipLaunchKernelGGL(k_long_deg_final, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long, g.long_rows.p,
-                           g.long_chunk0.p, g.partial.p, g.qdeg.p, sigma, g.deg.p, g.scale.p);
+                           g.long_chunk0.p, g.partial.p, g.xqdeg.p, sigma, g.deg.p, g.scale.p);
         AHR_LAUNCHED("k_long_deg_final");
     }
     if (spec.lambda_mode == AHR_LAMBDA_FIXED) {
@@ -730,7 +826,7 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     } else {
         hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, s, g.lam.p, 0.0);
         AHR_LAUNCHED("k_set_f64");
-        hipLaunchKernelGGL(k_gersh_short<G>, dim3(grid_for(static_cast<int64_t>(N) * G, kBT)), dim3(kBT), 0, s, N, m,
+        hipLaunchKernelGGL(k_gersh_short<G>, dim3(kGershGrid), dim3(kBT), 0, s, N, m,
                            g.deg.p, g.scale.p, sigma, g.lam.p);
         AHR_LAUNCHED("k_gersh_short");
         if (g.n_long) {
@@ -763,6 +859,7 @@ void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* o
 }
 
 void relax(Graph& g, const float* gcur, const float* gt, float* gnext, int32_t ncols, float gamma, hipStream_t s) {
+    ProfScope ps(kStageRelax, s);
     int64_t n = static_cast<int64_t>(g.n_inst) * ncols;
     switch (ncols) {
         case 1: hipLaunchKernelGGL(k_relax<1>, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.n_inst, g.nl.node_flags, gcur, gt, gnext, gamma); break;

@@ -6,6 +6,8 @@
 // scans only, so the structure is exact and run-to-run identical; weights
 // are evaluated in float64 and stored as float32, by one function per edge
 // kind, so A_ij and A_ji are bit-identical.
+#include <algorithm>
+
 #include "ahr_internal.hpp"
 #include "device_util.hpp"
 
@@ -57,28 +59,50 @@ __device__ __forceinline__ float w_macro(float x, float y, float4 m, double bw_i
     return static_cast<float>(-exp(-r) * bw_i);
 }
 
-// Bin of every hint cell (-1 otherwise) and fixed-point cell area per bin.
+// Bin of every hint cell (-1 otherwise), indexed by execution row, and the
+// fixed-point cell area per bin.  Rows are in spatial order, so a
+// workgroup's cells fall in few bins: areas are summed in LDS first.
+constexpr int kCellBinRows = 16;     // rows per thread
+constexpr int kLdsBins = 4096;
+
 __global__ void __launch_bounds__(kBT) k_cell_bins(Grid gr, const float* __restrict__ pos, int ncols, int32_t n_inst,
-                                                   const uint8_t* __restrict__ flags, const float* __restrict__ size,
-                                                   const int64_t* __restrict__ qdeg, int with_density,
-                                                   int32_t* __restrict__ cell_bin,
+                                                   const int32_t* __restrict__ perm, const uint8_t* __restrict__ flags,
+                                                   const float* __restrict__ size, const int64_t* __restrict__ qdeg,
+                                                   int with_density, int32_t* __restrict__ cell_bin,
                                                    unsigned long long* __restrict__ area_q) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
-    if (i >= n_inst) return;
-    uint8_t f = flags[i];
-    int b = -1;
-    if (is_std_movable(f)) {
-        float x = pos[i * ncols], y = pos[i * ncols + 1];
-        int bx = bin_coord(x, gr.xl32, gr.bw32, gr.nbx);
-        int by = bin_coord(y, gr.yl32, gr.bh32, gr.nby);
-        int bb = by * gr.nbx + bx;
-        if (with_density) {
-            double a = static_cast<double>(size[2 * i]) * static_cast<double>(size[2 * i + 1]);
-            atomicAdd(&area_q[bb], static_cast<unsigned long long>(static_cast<int64_t>(__builtin_rint(a * kAreaQ))));
+    __shared__ unsigned long long h[kLdsBins];
+    const int nbins = gr.nbx * gr.nby;
+    const bool lds = nbins <= kLdsBins;
+    if (lds && with_density)
+        for (int b = threadIdx.x; b < nbins; b += kBT) h[b] = 0ull;
+    __syncthreads();
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kBT * kCellBinRows;
+    for (int t = 0; t < kCellBinRows; ++t) {
+        int64_t r = base + static_cast<int64_t>(t) * kBT + threadIdx.x;
+        if (r >= n_inst) break;
+        int i = perm[r];
+        uint8_t f = flags[i];
+        int b = -1;
+        if (is_std_movable(f)) {
+            float x = pos[static_cast<int64_t>(i) * ncols], y = pos[static_cast<int64_t>(i) * ncols + 1];
+            int bx = bin_coord(x, gr.xl32, gr.bw32, gr.nbx);
+            int by = bin_coord(y, gr.yl32, gr.bh32, gr.nby);
+            int bb = by * gr.nbx + bx;
+            if (with_density) {
+                double a = static_cast<double>(size[2 * i]) * static_cast<double>(size[2 * i + 1]);
+                unsigned long long q = static_cast<unsigned long long>(static_cast<int64_t>(__builtin_rint(a * kAreaQ)));
+                if (lds) atomicAdd(&h[bb], q);
+                else atomicAdd(&area_q[bb], q);
+            }
+            if (qdeg[i] > 0) b = bb;
         }
-        if (qdeg[i] > 0) b = bb;
+        cell_bin[r] = b;
     }
-    cell_bin[i] = b;
+    if (lds && with_density) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < nbins; b += kBT)
+            if (h[b]) atomicAdd(&area_q[b], h[b]);
+    }
 }
 
 // Stable bucket sort, pass 1: hint cells per (bin, tile), bin-major.
@@ -138,7 +162,16 @@ __global__ void k_bin_start(const int32_t* __restrict__ off, int nbins, int32_t 
     if (b == nbins) bin_start[b] = total;
 }
 
-// Macro footprint (float32), its widened bin span, and its exact area per bin.
+__device__ __forceinline__ float outward(float c, float h) {
+    double v = static_cast<double>(c) + static_cast<double>(h) * (1.0 + 0x1p-20);
+    float f = static_cast<float>(v);
+    if (h < 0 && static_cast<double>(f) > v) f = nextafterf(f, -INFINITY);
+    if (h >= 0 && static_cast<double>(f) < v) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+// Macro footprint (float32), the bin span of the cells it can hold, and its
+// exact area per bin.
 __global__ void k_macros(Grid gr, const float* __restrict__ pos, int ncols, const int32_t* __restrict__ macro_ids,
                          int32_t n_macro, const float* __restrict__ size, int with_density, float4* __restrict__ rect,
                          int4* __restrict__ span, unsigned long long* __restrict__ area_q) {
@@ -149,12 +182,14 @@ __global__ void k_macros(Grid gr, const float* __restrict__ pos, int ncols, cons
     float w = size[2 * m], h = size[2 * m + 1];
     float4 r = make_float4(cx, cy, w * 0.5f, h * 0.5f);
     rect[k] = r;
-    int bx0 = bin_coord(cx - r.z, gr.xl32, gr.bw32, gr.nbx) - 1;
-    int bx1 = bin_coord(cx + r.z, gr.xl32, gr.bw32, gr.nbx) + 1;
-    int by0 = bin_coord(cy - r.w, gr.yl32, gr.bh32, gr.nby) - 1;
-    int by1 = bin_coord(cy + r.w, gr.yl32, gr.bh32, gr.nby) + 1;
-    span[k] = make_int4(bx0 < 0 ? 0 : bx0, by0 < 0 ? 0 : by0, bx1 >= gr.nbx ? gr.nbx - 1 : bx1,
-                        by1 >= gr.nby ? gr.nby - 1 : by1);
+    // Any x with fl(|x - cx|) <= w/2 has |x - cx| < (w/2)(1 + 2^-23), so the
+    // span of [cx - (w/2)(1 + 2^-20), cx + (w/2)(1 + 2^-20)], rounded outward
+    // to float32, holds the bin of every cell the footprint test accepts
+    // (bin_coord is monotone).
+    span[k] = make_int4(bin_coord(outward(cx, -r.z), gr.xl32, gr.bw32, gr.nbx),
+                        bin_coord(outward(cy, -r.w), gr.yl32, gr.bh32, gr.nby),
+                        bin_coord(outward(cx, r.z), gr.xl32, gr.bw32, gr.nbx),
+                        bin_coord(outward(cy, r.w), gr.yl32, gr.bh32, gr.nby));
     if (!with_density) return;
     // exact overlap of the footprint with every bin it touches (float64)
     double dcx = cx, dcy = cy, dw = w, dh = h;
@@ -217,15 +252,16 @@ struct HintArgs {
     int32_t n_inst, n_macro, nbins;
     int32_t first_mvirt, first_bvirt;
     int macro_hints, bin_hints;
-    const int32_t* cell_bin;
+    const int32_t* perm;          // execution row -> instance
+    const int32_t* cell_bin;      // by execution row
     const int32_t* bin_start;
-    const int32_t* bin_cells;
+    const int32_t* bin_cells;     // execution rows by bin
     const int32_t* bm_start;
     const int32_t* bm_list;
     const float4* rect;
     const int4* span;
     const double* phi;
-    const double* base_w;
+    const double* base_w;         // by instance
 };
 
 __device__ __forceinline__ void window(const Grid& gr, int b, int& x0, int& x1, int& y0, int& y1) {
@@ -236,83 +272,55 @@ __device__ __forceinline__ void window(const Grid& gr, int b, int& x0, int& x1, 
     y1 = by + gr.hy >= gr.nby ? gr.nby - 1 : by + gr.hy;
 }
 
-// Hint entries of every cell row (pass 1: count, pass 2: write).
-__global__ void __launch_bounds__(kBT) k_cell_rows(HintArgs a, int32_t* __restrict__ cnt,
-                                                   const int32_t* __restrict__ rp, int2* __restrict__ ent) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
-    if (i >= a.n_inst) return;
-    int b = a.cell_bin[i];
+// Per hint cell (execution row): the macros whose footprint holds it and the
+// size of its bin window.  With `pairs`, also lists its (row, macro) pairs at
+// pair_off[r] in ascending macro order.
+__global__ void __launch_bounds__(kBT) k_cell_count(HintArgs a, int32_t* __restrict__ nmac,
+                                                    int32_t* __restrict__ nwin, const int32_t* __restrict__ pair_off,
+                                                    int32_t* __restrict__ pair_row, int32_t* __restrict__ pair_mac) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    if (r >= a.n_inst) return;
+    int b = a.cell_bin[r];
     if (b < 0) {
-        if (cnt) cnt[i] = 0;
+        if (nmac) nmac[r] = 0, nwin[r] = 0;
         return;
     }
-    float x = a.pos[i * a.ncols], y = a.pos[i * a.ncols + 1];
-    double bwi = a.base_w[i];
     int n = 0;
-    int64_t o = ent ? rp[i] : 0;
     if (a.macro_hints) {
+        int i = a.perm[r];
+        float x = a.pos[static_cast<int64_t>(i) * a.ncols], y = a.pos[static_cast<int64_t>(i) * a.ncols + 1];
+        int o = pair_row ? pair_off[r] : 0;
         for (int t = a.bm_start[b]; t < a.bm_start[b + 1]; ++t) {
             int k = a.bm_list[t];
-            float4 m = a.rect[k];
-            if (inside(x, y, m)) {
-                if (ent) ent[o + n] = make_int2(a.first_mvirt + k, f_bits(w_macro(x, y, m, bwi)));
+            if (inside(x, y, a.rect[k])) {
+                if (pair_row) {
+                    pair_row[o + n] = static_cast<int32_t>(r);
+                    pair_mac[o + n] = k;
+                }
                 ++n;
             }
         }
     }
-    if (a.bin_hints) {
+    if (nmac) {
+        nmac[r] = n;
         int x0, x1, y0, y1;
         window(a.gr, b, x0, x1, y0, y1);
-        if (ent) {
-            for (int by = y0; by <= y1; ++by)
-                for (int bx = x0; bx <= x1; ++bx) {
-                    int bb = by * a.gr.nbx + bx;
-                    ent[o + n] = make_int2(a.first_bvirt + bb, f_bits(w_bin(a.gr, x, y, bb, a.phi, bwi)));
-                    ++n;
-                }
-        } else {
-            n += (x1 - x0 + 1) * (y1 - y0 + 1);
-        }
+        nwin[r] = a.bin_hints ? (x1 - x0 + 1) * (y1 - y0 + 1) : 0;
     }
-    if (cnt) cnt[i] = n;
 }
 
-// Macro virtual rows: one workgroup per macro walks the cells of the bins in
-// its span (row-major bins, ascending cells) and keeps those inside.
-__global__ void __launch_bounds__(kBT) k_macro_rows(HintArgs a, int32_t* __restrict__ cnt,
-                                                    const int32_t* __restrict__ rp, int2* __restrict__ ent) {
-    __shared__ int red[kBT / kWave];
-    int k = blockIdx.x;
-    float4 m = a.rect[k];
-    int4 sp = a.span[k];
-    int row = a.first_mvirt + k;
-    int64_t o = ent ? rp[row] : 0;
-    int carry = 0;
-    for (int by = sp.y; by <= sp.w; ++by)
-        for (int bx = sp.x; bx <= sp.z; ++bx) {
-            int b = by * a.gr.nbx + bx;
-            int s0 = a.bin_start[b], s1 = a.bin_start[b + 1];
-            for (int t0 = s0; t0 < s1; t0 += kBT) {
-                int t = t0 + threadIdx.x;
-                int c = -1;
-                bool f = false;
-                float x = 0, y = 0;
-                if (t < s1) {
-                    c = a.bin_cells[t];
-                    x = a.pos[static_cast<int64_t>(c) * a.ncols];
-                    y = a.pos[static_cast<int64_t>(c) * a.ncols + 1];
-                    f = inside(x, y, m);
-                }
-                int tot;
-                int idx = block_rank<kBT>(f, red, &tot);
-                if (ent && f) ent[o + carry + idx] = make_int2(c, f_bits(w_macro(x, y, m, a.base_w[c])));
-                carry += tot;
-            }
-        }
-    if (cnt && threadIdx.x == 0) cnt[row] = carry;
+__global__ void k_cell_hint_cnt(int32_t n_inst, const int32_t* __restrict__ nmac, const int32_t* __restrict__ nwin,
+                                int32_t* __restrict__ cnt) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < n_inst) cnt[r] = nmac[r] + nwin[r];
 }
 
-// Bin virtual rows: the cells of every bin in the window, row-major bins.
+__global__ void k_macro_row_cnt(int32_t n_macro, int32_t first_mvirt, const int32_t* __restrict__ mstart,
+                                int32_t* __restrict__ cnt) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_macro) cnt[first_mvirt + k] = mstart[k + 1] - mstart[k];
+}
+
 __global__ void k_bin_row_counts(HintArgs a, int32_t* __restrict__ cnt) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= a.nbins) return;
@@ -327,22 +335,78 @@ __global__ void k_bin_row_counts(HintArgs a, int32_t* __restrict__ cnt) {
     cnt[a.first_bvirt + b] = n;
 }
 
-__global__ void __launch_bounds__(kBT) k_bin_rows(HintArgs a, const int32_t* __restrict__ rp, int2* __restrict__ ent) {
-    int b = blockIdx.x;
-    int x0, x1, y0, y1;
-    window(a.gr, b, x0, x1, y0, y1);
-    int64_t o = rp[a.first_bvirt + b];
-    for (int by = y0; by <= y1; ++by)
-        for (int bx = x0; bx <= x1; ++bx) {
-            int bb = by * a.gr.nbx + bx;
-            int s0 = a.bin_start[bb], s1 = a.bin_start[bb + 1];
-            for (int t = s0 + threadIdx.x; t < s1; t += kBT) {
-                int c = a.bin_cells[t];
-                float x = a.pos[static_cast<int64_t>(c) * a.ncols], y = a.pos[static_cast<int64_t>(c) * a.ncols + 1];
-                ent[o + (t - s0)] = make_int2(c, f_bits(w_bin(a.gr, x, y, b, a.phi, a.base_w[c])));
+// Cell rows: macro entries (ascending macro) then window bins (row-major).
+__global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ pair_off,
+                                                   const int32_t* __restrict__ pair_mac, int2* __restrict__ ent) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    if (r >= a.n_inst) return;
+    int b = a.cell_bin[r];
+    if (b < 0) return;
+    int i = a.perm[r];
+    float x = a.pos[static_cast<int64_t>(i) * a.ncols], y = a.pos[static_cast<int64_t>(i) * a.ncols + 1];
+    double bwi = a.base_w[i];
+    int64_t o = rp[r];
+    int n = 0;
+    for (int p = pair_off[r]; p < pair_off[r + 1]; ++p) {
+        int k = pair_mac[p];
+        ent[o + n++] = make_int2(a.first_mvirt + k, f_bits(w_macro(x, y, a.rect[k], bwi)));
+    }
+    if (a.bin_hints) {
+        int x0, x1, y0, y1;
+        window(a.gr, b, x0, x1, y0, y1);
+        for (int by = y0; by <= y1; ++by)
+            for (int bx = x0; bx <= x1; ++bx) {
+                int bb = by * a.gr.nbx + bx;
+                ent[o + n++] = make_int2(a.first_bvirt + bb, f_bits(w_bin(a.gr, x, y, bb, a.phi, bwi)));
             }
-            o += s1 - s0;
-        }
+    }
+}
+
+// Macro virtual rows: the transpose of the cell->macro pairs (pairs grouped
+// by macro, ascending row); each weight is the cell-side entry's value.
+__global__ void k_macro_fill(int32_t n_pairs, int32_t first_mvirt, const int32_t* __restrict__ mlist,
+                             const int32_t* __restrict__ mstart, const int32_t* __restrict__ pair_row,
+                             const int32_t* __restrict__ pair_mac, const int32_t* __restrict__ pair_off,
+                             const int32_t* __restrict__ rp, int2* __restrict__ ent) {
+    int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_pairs) return;
+    int p = mlist[t];
+    int row = pair_row[p];
+    int k = pair_mac[p];
+    int w = ent[rp[row] + (p - pair_off[row])].y;
+    ent[rp[first_mvirt + k] + (t - mstart[k])] = make_int2(row, w);
+}
+
+// Bin virtual rows: one workgroup per (bin row, window position) copies the
+// cells of that window bin (ascending rows) with the cell-side weights.
+__global__ void __launch_bounds__(kBT) k_bin_fill(HintArgs a, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ nmac, int2* __restrict__ ent) {
+    int b = blockIdx.x;
+    int w = blockIdx.y;
+    int ww = 2 * a.gr.hx + 1;
+    int dx = w % ww - a.gr.hx, dy = w / ww - a.gr.hy;
+    int bx = b % a.gr.nbx, by = b / a.gr.nbx;
+    int tx = bx + dx, ty = by + dy;
+    if (tx < 0 || tx >= a.gr.nbx || ty < 0 || ty >= a.gr.nby) return;
+    int64_t o = rp[a.first_bvirt + b];
+    for (int v = 0; v < w; ++v) {
+        int ux = bx + v % ww - a.gr.hx, uy = by + v / ww - a.gr.hy;
+        if (ux < 0 || ux >= a.gr.nbx || uy < 0 || uy >= a.gr.nby) continue;
+        int ub = uy * a.gr.nbx + ux;
+        o += a.bin_start[ub + 1] - a.bin_start[ub];
+    }
+    int bb = ty * a.gr.nbx + tx;
+    // position of bin b inside the clipped window of bb (row-major)
+    int x0, x1, y0, y1;
+    window(a.gr, bb, x0, x1, y0, y1);
+    int widx = (by - y0) * (x1 - x0 + 1) + (bx - x0);
+    int s0 = a.bin_start[bb], s1 = a.bin_start[bb + 1];
+    for (int t = s0 + threadIdx.x; t < s1; t += kBT) {
+        int row = a.bin_cells[t];
+        int wv = ent[rp[row] + nmac[row] + widx].y;
+        ent[o + (t - s0)] = make_int2(row, wv);
+    }
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t n) {
@@ -358,6 +422,41 @@ T read_scalar(const T* dev, hipStream_t s) {
     return v;
 }
 
+}  // namespace
+
+int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
+                    DevBuf<int32_t>& start, hipStream_t s) {
+    if (nkeys > kMaxBins) throw Error{AHR_EUNSUPPORTED, "too many buckets (at most 16384 bins or macros)"};
+    if (n == 0) {
+        list.ensure(1, s);
+        start.ensure(static_cast<size_t>(nkeys) + 1, s);
+        fill_i32(start.p, nkeys + 1, 0, s);
+        return 0;
+    }
+    int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(n) + kTileCells - 1) / kTileCells);
+    int64_t hn = static_cast<int64_t>(nkeys) * ntiles;
+    g.i32a.ensure(static_cast<size_t>(hn) + 1, s);
+    g.i32b.ensure(static_cast<size_t>(hn) + 1, s);
+    hipLaunchKernelGGL(k_bucket_count, dim3(ntiles), dim3(kWave), 0, s, key, n, nkeys, ntiles, g.i32a.p);
+    AHR_LAUNCHED("k_bucket_count");
+    g.scan_tmp.ensure(scan_tmp_elems(hn), s);
+    scan_i32_to_i32(g.i32a.p, g.i32b.p, hn, g.scan_tmp.p, s);
+    int32_t total = read_scalar(g.i32b.p + hn, s);
+    list.ensure(static_cast<size_t>(total) + 1, s);
+    int bits = 0;
+    while ((1 << bits) < nkeys) ++bits;
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(ntiles), dim3(kWave), 0, s, key, n, nkeys, bits, ntiles, g.i32b.p,
+                       list.p);
+    AHR_LAUNCHED("k_bucket_scatter");
+    start.ensure(static_cast<size_t>(nkeys) + 1, s);
+    hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nkeys + 1, kBT)), dim3(kBT), 0, s, g.i32b.p, nkeys, ntiles, total,
+                       start.p);
+    AHR_LAUNCHED("k_bin_start");
+    return total;
+}
+
+namespace {
+
 int window_half(float ratio, int nb) {
     // n = max(1, floor(ratio * numBin)) in float32; the window spans +-floor(n/2)
     float p = ratio * static_cast<float>(nb);
@@ -369,20 +468,22 @@ int window_half(float ratio, int nb) {
 }  // namespace
 
 void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
+    ProfScope ps(kStageHints, s);
     const ahr_hint_params& hp = g.hp;
     const int macro_hints = (hp.flags & AHR_MACRO_HINTS) ? 1 : 0;
     const int bin_hints = (hp.flags & AHR_BIN_HINTS) ? 1 : 0;
     const int32_t N = g.n_tot, n_inst = g.n_inst;
+    if (!g.has_layout) set_layout(g, pos, ncols, s);
     g.hint_cnt.ensure(static_cast<size_t>(N) + 1, s);
-    g.hint_rp.ensure(static_cast<size_t>(N) + 1, s);
+    g.xhint_rp.ensure(static_cast<size_t>(N) + 1, s);
     fill_i32(g.hint_cnt.p, N + 1, 0, s);
     g.hint_version++;
     g.has_hints = 1;
     if (!macro_hints && !bin_hints) {
-        fill_i32(g.hint_rp.p, N + 1, 0, s);
+        fill_i32(g.xhint_rp.p, N + 1, 0, s);
         g.nnz_hint = 0;
         g.n_hint_cells = 0;
-        g.hint_ent.ensure(1, s);
+        g.xhint_ent.ensure(1, s);
         AHR_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -402,40 +503,22 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     gr.hy = window_half(hp.detection_ratio, hp.nby);
     const int nbins = hp.nbx * hp.nby;
 
-    // 1. cell bins and cell areas
+    // 1. cell bins (execution rows) and cell areas
     g.cell_bin.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.bin_area_q.ensure(static_cast<size_t>(nbins) + 1, s);
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s,
                        reinterpret_cast<unsigned long long*>(g.bin_area_q.p), static_cast<int64_t>(nbins));
     AHR_LAUNCHED("k_fill_u64");
-    hipLaunchKernelGGL(k_cell_bins, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, gr, pos, ncols, n_inst,
-                       g.nl.node_flags, g.nl.node_size, g.qdeg.p, bin_hints, g.cell_bin.p,
+    hipLaunchKernelGGL(k_cell_bins, dim3(grid_for(n_inst, kBT * kCellBinRows)), dim3(kBT), 0, s, gr, pos, ncols,
+                       n_inst, g.perm.p, g.nl.node_flags, g.nl.node_size, g.qdeg.p, bin_hints, g.cell_bin.p,
                        reinterpret_cast<unsigned long long*>(g.bin_area_q.p));
     AHR_LAUNCHED("k_cell_bins");
 
-    // 2. hint cells grouped by bin, ascending ids (stable bucket sort)
-    int32_t ntiles = static_cast<int32_t>((n_inst + kTileCells - 1) / kTileCells);
-    int64_t hn = static_cast<int64_t>(nbins) * ntiles;
-    g.i32a.ensure(static_cast<size_t>(hn) + 1, s);
-    g.i32b.ensure(static_cast<size_t>(hn) + 1, s);
-    hipLaunchKernelGGL(k_bucket_count, dim3(ntiles), dim3(kWave), 0, s, g.cell_bin.p, n_inst, nbins, ntiles, g.i32a.p);
-    AHR_LAUNCHED("k_bucket_count");
-    g.scan_tmp.ensure(scan_tmp_elems(hn), s);
-    scan_i32_to_i32(g.i32a.p, g.i32b.p, hn, g.scan_tmp.p, s);
-    g.n_hint_cells = read_scalar(g.i32b.p + hn, s);
-    g.bin_cells.ensure(static_cast<size_t>(g.n_hint_cells) + 1, s);
-    int bits = 0;
-    while ((1 << bits) < nbins) ++bits;
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(ntiles), dim3(kWave), 0, s, g.cell_bin.p, n_inst, nbins, bits, ntiles,
-                       g.i32b.p, g.bin_cells.p);
-    AHR_LAUNCHED("k_bucket_scatter");
-    g.bin_start.ensure(static_cast<size_t>(nbins) + 1, s);
-    hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nbins + 1, kBT)), dim3(kBT), 0, s, g.i32b.p, nbins, ntiles,
-                       g.n_hint_cells, g.bin_start.p);
-    AHR_LAUNCHED("k_bin_start");
+    // 2. hint cells grouped by bin, ascending execution rows (stable bucket sort)
+    g.n_hint_cells = bucket_sort(g, g.cell_bin.p, n_inst, nbins, g.bin_cells, g.bin_start, s);
 
-    // 3. macros: footprints, spans, areas
-    const int32_t n_macro = macro_hints || bin_hints ? g.n_macro : 0;
+    // 3. macros: footprints, spans, areas; phi
+    const int32_t n_macro = g.n_macro;
     g.macro_rect.ensure(static_cast<size_t>(n_macro) + 1, s);
     g.macro_span.ensure(static_cast<size_t>(n_macro) + 1, s);
     if (n_macro)
@@ -452,13 +535,15 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     }
 
     // 4. macros per bin
+    const int use_macros = macro_hints && n_macro > 0;
     g.bm_start.ensure(static_cast<size_t>(nbins) + 1, s);
-    if (macro_hints && n_macro) {
+    if (use_macros) {
         DevBuf<int32_t> bmc;
         bmc.ensure(static_cast<size_t>(nbins) + 1, s);
         hipLaunchKernelGGL(k_bin_macros, dim3(nbins), dim3(kBT), 0, s, hp.nbx, g.macro_span.p, n_macro,
                            static_cast<const int32_t*>(nullptr), bmc.p, static_cast<int32_t*>(nullptr));
         AHR_LAUNCHED("k_bin_macros count");
+        g.scan_tmp.ensure(scan_tmp_elems(nbins), s);
         scan_i32_to_i32(bmc.p, g.bm_start.p, nbins, g.scan_tmp.p, s);
         int32_t nbm = read_scalar(g.bm_start.p + nbins, s);
         g.bm_list.ensure(static_cast<size_t>(nbm) + 1, s);
@@ -480,8 +565,9 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     a.nbins = nbins;
     a.first_mvirt = g.first_mvirt;
     a.first_bvirt = g.first_bvirt;
-    a.macro_hints = macro_hints && n_macro > 0;
+    a.macro_hints = use_macros;
     a.bin_hints = bin_hints;
+    a.perm = g.perm.p;
     a.cell_bin = g.cell_bin.p;
     a.bin_start = g.bin_start.p;
     a.bin_cells = g.bin_cells.p;
@@ -492,14 +578,38 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     a.phi = g.phi.p;
     a.base_w = g.base_w.p;
 
-    // 5. row counts, offsets, entries
-    hipLaunchKernelGGL(k_cell_rows, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a, g.hint_cnt.p,
-                       static_cast<const int32_t*>(nullptr), static_cast<int2*>(nullptr));
-    AHR_LAUNCHED("k_cell_rows count");
-    if (a.macro_hints) {
-        hipLaunchKernelGGL(k_macro_rows, dim3(n_macro), dim3(kBT), 0, s, a, g.hint_cnt.p,
-                           static_cast<const int32_t*>(nullptr), static_cast<int2*>(nullptr));
-        AHR_LAUNCHED("k_macro_rows count");
+    // 5. per cell: macros holding it, window size; (cell, macro) pairs
+    g.nmac.ensure(static_cast<size_t>(n_inst) + 1, s);
+    g.nwin.ensure(static_cast<size_t>(n_inst) + 1, s);
+    hipLaunchKernelGGL(k_cell_count, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a, g.nmac.p, g.nwin.p,
+                       static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+                       static_cast<int32_t*>(nullptr));
+    AHR_LAUNCHED("k_cell_count");
+    g.pair_off.ensure(static_cast<size_t>(n_inst) + 1, s);
+    g.scan_tmp.ensure(scan_tmp_elems(std::max<int64_t>(N, n_inst)), s);
+    scan_i32_to_i32(g.nmac.p, g.pair_off.p, n_inst, g.scan_tmp.p, s);
+    int32_t n_pairs = read_scalar(g.pair_off.p + n_inst, s);
+    g.pair_row.ensure(static_cast<size_t>(n_pairs) + 1, s);
+    g.pair_mac.ensure(static_cast<size_t>(n_pairs) + 1, s);
+    if (n_pairs) {
+        hipLaunchKernelGGL(k_cell_count, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a,
+                           static_cast<int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+                           static_cast<const int32_t*>(g.pair_off.p), g.pair_row.p, g.pair_mac.p);
+        AHR_LAUNCHED("k_cell_count pairs");
+    }
+    // pairs grouped by macro, ascending row: the macro virtual rows
+    int32_t n_sorted = 0;
+    if (use_macros) n_sorted = bucket_sort(g, g.pair_mac.p, n_pairs, n_macro, g.mlist, g.mstart, s);
+    if (n_sorted != (use_macros ? n_pairs : 0)) throw Error{AHR_EDEVICE, "macro pair sort lost entries"};
+
+    // 6. row counts and offsets (execution order)
+    hipLaunchKernelGGL(k_cell_hint_cnt, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.nmac.p, g.nwin.p,
+                       g.hint_cnt.p);
+    AHR_LAUNCHED("k_cell_hint_cnt");
+    if (use_macros) {
+        hipLaunchKernelGGL(k_macro_row_cnt, dim3(grid_for(n_macro, kBT)), dim3(kBT), 0, s, n_macro, g.first_mvirt,
+                           g.mstart.p, g.hint_cnt.p);
+        AHR_LAUNCHED("k_macro_row_cnt");
     }
     if (bin_hints) {
         hipLaunchKernelGGL(k_bin_row_counts, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s, a, g.hint_cnt.p);
@@ -507,27 +617,31 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     }
     DevBuf<int64_t> rp64;
     rp64.ensure(static_cast<size_t>(N) + 1, s);
-    g.scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i64(g.hint_cnt.p, rp64.p, N, g.scan_tmp.p, s);
     int64_t nnz = read_scalar(rp64.p + N, s);
     rp64.release(s);
     if (nnz + static_cast<int64_t>(g.nnz_net) >= INT32_MAX)
         throw Error{AHR_EUNSUPPORTED, "graph with hints has 2^31 or more entries"};
-    scan_i32_to_i32(g.hint_cnt.p, g.hint_rp.p, N, g.scan_tmp.p, s);
+    scan_i32_to_i32(g.hint_cnt.p, g.xhint_rp.p, N, g.scan_tmp.p, s);
     g.nnz_hint = static_cast<int32_t>(nnz);
-    g.hint_ent.ensure(static_cast<size_t>(nnz) + 1, s);
-    hipLaunchKernelGGL(k_cell_rows, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a, static_cast<int32_t*>(nullptr),
-                       static_cast<const int32_t*>(g.hint_rp.p), g.hint_ent.p);
-    AHR_LAUNCHED("k_cell_rows fill");
-    if (a.macro_hints) {
-        hipLaunchKernelGGL(k_macro_rows, dim3(n_macro), dim3(kBT), 0, s, a, static_cast<int32_t*>(nullptr),
-                           static_cast<const int32_t*>(g.hint_rp.p), g.hint_ent.p);
-        AHR_LAUNCHED("k_macro_rows fill");
+    g.xhint_ent.ensure(static_cast<size_t>(nnz) + 1, s);
+
+    // 7. entries: cell rows first (their weights are reused), then virtual rows
+    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a,
+                       static_cast<const int32_t*>(g.xhint_rp.p), static_cast<const int32_t*>(g.pair_off.p),
+                       static_cast<const int32_t*>(g.pair_mac.p), g.xhint_ent.p);
+    AHR_LAUNCHED("k_cell_fill");
+    if (use_macros && n_pairs) {
+        hipLaunchKernelGGL(k_macro_fill, dim3(grid_for(n_pairs, kBT)), dim3(kBT), 0, s, n_pairs, g.first_mvirt,
+                           g.mlist.p, g.mstart.p, g.pair_row.p, g.pair_mac.p, g.pair_off.p, g.xhint_rp.p,
+                           g.xhint_ent.p);
+        AHR_LAUNCHED("k_macro_fill");
     }
     if (bin_hints) {
-        hipLaunchKernelGGL(k_bin_rows, dim3(nbins), dim3(kBT), 0, s, a, static_cast<const int32_t*>(g.hint_rp.p),
-                           g.hint_ent.p);
-        AHR_LAUNCHED("k_bin_rows");
+        dim3 grid(nbins, (2 * gr.hx + 1) * (2 * gr.hy + 1));
+        hipLaunchKernelGGL(k_bin_fill, grid, dim3(kBT), 0, s, a, static_cast<const int32_t*>(g.xhint_rp.p),
+                           static_cast<const int32_t*>(g.nmac.p), g.xhint_ent.p);
+        AHR_LAUNCHED("k_bin_fill");
     }
 }
 

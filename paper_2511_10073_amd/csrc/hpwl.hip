@@ -159,6 +159,7 @@ void hpwl_p(const Graph& g, const float* pos, int32_t ncols, double* out, hipStr
 }  // namespace
 
 void run_hpwl(const Graph& g, const float* pos, int32_t ncols, double* out, hipStream_t s) {
+    ProfScope ps(kStageHpwl, s);
     switch (ncols) {
         case 2: hpwl_p<1>(g, pos, ncols, out, s); break;
         case 4: hpwl_p<2>(g, pos, ncols, out, s); break;

@@ -153,14 +153,11 @@ __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __
 }
 
 // Row classes by entry count: 0 (<= 1), 1 (<= 16), 2 (<= 64), 3 (longer).
-__global__ void k_classify(const int32_t* __restrict__ cnt, int32_t n, int32_t* __restrict__ nclass,
-                           int32_t* __restrict__ lists, int32_t list_stride) {
+__device__ __forceinline__ int row_class(int c) { return c <= 1 ? 0 : (c <= 16 ? 1 : (c <= 64 ? 2 : 3)); }
+
+__global__ void k_class_flags(const int32_t* __restrict__ cnt, int32_t n, int k, int32_t* __restrict__ flag) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    int c = cnt[r];
-    int k = c <= 1 ? 0 : (c <= 16 ? 1 : (c <= 64 ? 2 : 3));
-    int slot = atomicAdd(&nclass[k], 1);
-    lists[static_cast<int64_t>(k) * list_stride + slot] = static_cast<int32_t>(r);
+    if (r < n) flag[r] = row_class(cnt[r]) == k ? 1 : 0;
 }
 
 // Rows with at most one entry: copy through.
@@ -312,28 +309,30 @@ __global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ r
     if (threadIdx.x == 0) ucnt[r] = carry;
 }
 
-// Copy merged rows to their final place, with the row weight sums.
-__global__ void k_compact(int32_t n_rows, const int64_t* __restrict__ rp, const int32_t* __restrict__ ucnt,
-                          const int32_t* __restrict__ net_rp, const int32_t* __restrict__ scol,
-                          const int64_t* __restrict__ sq, int32_t* __restrict__ col, int64_t* __restrict__ qv,
-                          int2* __restrict__ ent, int64_t* __restrict__ qdeg) {
-    // one wave per row, lanes stride the entries
-    int64_t r = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-    int l = lane_id();
+// Copy merged rows to their final place, with the row weight sums
+// (16 lanes per row).
+__global__ void __launch_bounds__(kBT) k_compact(int32_t n_rows, const int64_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ucnt, const int32_t* __restrict__ net_rp,
+                                                 const int32_t* __restrict__ scol, const int64_t* __restrict__ sq,
+                                                 int32_t* __restrict__ col, int64_t* __restrict__ qv,
+                                                 int64_t* __restrict__ qdeg) {
+    constexpr int G = 16;
+    int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
+    int l = threadIdx.x & (G - 1);
     if (r >= n_rows) return;
     int n = ucnt[r];
     int64_t src = rp[r];
     int64_t dst = net_rp[r];
     int64_t s = 0;
-    for (int k = l; k < n; k += kWave) {
+    for (int k = l; k < n; k += G) {
         int c = scol[src + k];
         int64_t q = sq[src + k];
         col[dst + k] = c;
         qv[dst + k] = q;
-        ent[dst + k] = make_int2(c, f_bits(static_cast<float>(static_cast<double>(q) * 0x1p-32)));
         s += q;
     }
-    s = wave_sum(s);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (l == 0) qdeg[r] = s;
 }
 
@@ -369,6 +368,7 @@ int32_t list_from_flags(const int32_t* flags, int32_t n, DevBuf<int32_t>& rank, 
 }  // namespace
 
 void build_netlist(Graph& g, hipStream_t s) {
+    ProfScope ps(kStageBuild, s);
     const ahr_netlist& nl = g.nl;
     const int32_t n_pins = nl.n_pins, n_nets = nl.n_nets, n_inst = nl.n_inst;
     const ahr_hint_params& hp = g.hp;
@@ -426,6 +426,8 @@ void build_netlist(Graph& g, hipStream_t s) {
     hipLaunchKernelGGL(k_mark_macro, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, nl.node_flags, n_inst, is_mac.p);
     AHR_LAUNCHED("k_mark_macro");
     g.n_macro = list_from_flags(is_mac.p, n_inst, mac_rank, g.macro_ids, g, s);
+    if ((hp.flags & AHR_MACRO_HINTS) && g.n_macro > 16384)
+        throw Error{AHR_EUNSUPPORTED, "macro hints support at most 16384 macros"};
     is_mac.release(s);
     mac_rank.release(s);
 
@@ -475,16 +477,22 @@ void build_netlist(Graph& g, hipStream_t s) {
     is_star.release(s);
     star_rank.release(s);
 
-    // per-row sort + merge
-    DevBuf<int32_t> nclass, lists;
-    nclass.ensure(4, s);
-    fill_i32(nclass.p, 4, 0, s);
+    // per-row sort + merge; rows grouped by length class (ascending lists)
+    DevBuf<int32_t> lists, cflag, crank;
     lists.ensure(static_cast<size_t>(N) * 4 + 4, s);
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, cnt.p, N, nclass.p, lists.p, N);
-    AHR_LAUNCHED("k_classify");
+    cflag.ensure(static_cast<size_t>(N) + 1, s);
     int32_t ncls[4];
-    AHR_HIP(hipMemcpyAsync(ncls, nclass.p, sizeof ncls, hipMemcpyDeviceToHost, s));
-    AHR_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < 4; ++k) {
+        hipLaunchKernelGGL(k_class_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, cnt.p, N, k, cflag.p);
+        AHR_LAUNCHED("k_class_flags");
+        crank.ensure(static_cast<size_t>(N) + 1, s);
+        g.scan_tmp.ensure(scan_tmp_elems(N), s);
+        scan_i32_to_i32(cflag.p, crank.p, N, g.scan_tmp.p, s);
+        ncls[k] = read_scalar(crank.p + N, s);
+        list_rows(cflag.p, crank.p, N, lists.p + static_cast<int64_t>(k) * N, s);
+    }
+    cflag.release(s);
+    crank.release(s);
     scol.ensure(static_cast<size_t>(nnz_dup) + 1, s);
     sq.ensure(static_cast<size_t>(nnz_dup) + 1, s);
     ucnt.ensure(static_cast<size_t>(N) + 1, s);
@@ -513,7 +521,6 @@ void build_netlist(Graph& g, hipStream_t s) {
     dcol.release(s);
     dq.release(s);
     lists.release(s);
-    nclass.release(s);
 
     // final CSR
     g.net_rp.ensure(static_cast<size_t>(N) + 1, s);
@@ -521,10 +528,9 @@ void build_netlist(Graph& g, hipStream_t s) {
     g.nnz_net = read_scalar(g.net_rp.p + N, s);
     g.net_col.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.net_q.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
-    g.net_ent.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.qdeg.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(static_cast<int64_t>(N) * kWave, kBT)), dim3(kBT), 0, s, N, rp.p,
-                       ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.net_ent.p, g.qdeg.p);
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(static_cast<int64_t>(N) * 16, kBT)), dim3(kBT), 0, s, N, rp.p,
+                       ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
     AHR_LAUNCHED("k_compact");
     g.base_w.ensure(static_cast<size_t>(n_inst) + 1, s);
     hipLaunchKernelGGL(k_base_weight, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.net_rp.p, g.qdeg.p,

@@ -230,10 +230,12 @@ def generate(cfg: NetlistConfig) -> dict:
         lattice that maps std cells onto the die; every std cell lies on at
         least one net; each macro pin and each I/O joins one net anchored near
         it; instance ids are a seeded random permutation;
-      * initial signal: ``ncols/2`` independent (x, y) draws for movable
-        objects from a centre-concentrated normal (sd = die side / 6, clipped
-        to the die) -- the centre-heavy shape a low-pass initial placement
-        has; fixed objects sit at their fixed positions.
+      * initial signal: ``ncols/2`` (x, y) column pairs; movable cells sit at
+        a centre-concentrated warp of the hidden lattice (normal quantiles,
+        sd = die side / 6) plus independent noise of one lattice spacing per
+        pair, so connected cells are near each other and crowd the centre --
+        the shape of a low-pass (GSP) initial placement; macros (movable or
+        fixed) and I/O sit at their drawn positions.
     """
     rng = np.random.default_rng(cfg.seed)
     n_std, n_mac, n_io = cfg.n_std, cfg.n_macro, cfg.n_io
@@ -374,25 +376,23 @@ def generate(cfg: NetlistConfig) -> dict:
     fixed_pos = fixed_pos_old[inv]
     pin_node = perm[all_node]
 
-    # initial signal
+    # initial signal: a centre-concentrated warp of the hidden lattice (normal
+    # quantiles, sd = die side / 6) plus independent noise per column pair
+    from scipy.special import ndtri
     ncols = cfg.ncols
-    g0 = np.zeros((n_inst, ncols), dtype=np.float64)
-    movable = (node_flags & FIXED) == 0
-    nm = int(movable.sum())
+    g0_old = np.zeros((n_inst, ncols), dtype=np.float64)
+    kx = np.arange(n_std) % lat_w
+    ky = np.arange(n_std) // lat_w
     sd = die_side / 6.0
+    wx = sd * ndtri((kx + 0.5) / lat_w)
+    wy = sd * ndtri((ky + 0.5) / lat_h)
+    jitter = die_side / max(lat_w, 1)
     for c in range(ncols // 2):
-        xy = rng.normal(0.0, sd, (nm, 2))
-        xy = np.clip(xy, -half, half)
-        g0[movable, 2 * c] = xy[:, 0]
-        g0[movable, 2 * c + 1] = xy[:, 1]
-        g0[~movable, 2 * c] = fixed_pos[~movable, 0]
-        g0[~movable, 2 * c + 1] = fixed_pos[~movable, 1]
-    if cfg.movable_macros:
-        # movable macros start at their drawn positions in every column pair
-        mm = (node_flags & MACRO) != 0
-        for c in range(ncols // 2):
-            g0[mm, 2 * c] = fixed_pos[mm, 0]
-            g0[mm, 2 * c + 1] = fixed_pos[mm, 1]
+        g0_old[:n_std, 2 * c] = np.clip(wx + rng.normal(0.0, jitter, n_std), -half, half)
+        g0_old[:n_std, 2 * c + 1] = np.clip(wy + rng.normal(0.0, jitter, n_std), -half, half)
+        g0_old[n_std:, 2 * c] = fixed_pos_old[n_std:, 0]
+        g0_old[n_std:, 2 * c + 1] = fixed_pos_old[n_std:, 1]
+    g0 = g0_old[inv]
 
     return dict(
         name=cfg.name,
