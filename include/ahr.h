@@ -214,6 +214,22 @@ ahr_status ahr_refine(ahr_graph* gr, const ahr_filter_spec* spec, const float* g
 ahr_status ahr_hpwl(const ahr_graph* gr, const float* g, int32_t ncols, double* out,
                     void* stream);
 
+/* Return the device memory that freed graphs left in the library's cache
+ * to the driver (graph builds reuse cached blocks).  Synchronises on the
+ * frees still in flight. */
+ahr_status ahr_memory_trim(void);
+
+/* Launch shape of the filter's SpMM hop (process-wide; the batched path's
+ * autotuner sets it): lanes_per_row in {1, 2, 4, 8, 16, 32, 64} lanes of a
+ * wavefront share one row of up to 128 entries (0 keeps the current
+ * value); nontemporal = 1 streams the adjacency with non-temporal loads so
+ * the L2 keeps the gathered signal rows (-1 keeps the current value).
+ * Results do not depend on the lanes (each row's sum is a fixed butterfly
+ * over its lanes' partial sums, so they may differ in the last bits between
+ * settings but are deterministic for each). */
+ahr_status ahr_filter_tune(int32_t lanes_per_row, int32_t nontemporal);
+ahr_status ahr_filter_get_tune(int32_t* lanes_per_row, int32_t* nontemporal);
+
 /* Per-stage device time, measured with HIP events recorded on the stream
  * each stage runs on (process-wide accumulators). */
 typedef struct ahr_profile {

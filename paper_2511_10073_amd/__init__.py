@@ -98,6 +98,10 @@ def load() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int32
+    lib.ahr_filter_tune.argtypes = [i32, i32]
+    lib.ahr_filter_tune.restype = ctypes.c_int32
+    lib.ahr_filter_get_tune.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.ahr_filter_get_tune.restype = ctypes.c_int32
     lib.ahr_profile_enable.argtypes = [i32]
     lib.ahr_profile_enable.restype = ctypes.c_int32
     lib.ahr_profile_read.argtypes = [ctypes.POINTER(_Profile), i32]
@@ -121,6 +125,17 @@ def _stream(stream=None):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def filter_tune(lanes_per_row: int = 0, nontemporal: int = -1):
+    """Set the hop launch shape (0 / -1 keep the current values)."""
+    _check(load().ahr_filter_tune(lanes_per_row, nontemporal))
+
+
+def filter_get_tune() -> tuple:
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().ahr_filter_get_tune(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def profile_enable(on: bool = True):

@@ -65,11 +65,16 @@ size_t scan_tmp_elems(int64_t n);
 void scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 // Same, writes int32 (caller checked the total fits).
 void scan_i32_to_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+// int32 scan that returns the exact int64 total (one synchronisation); the
+// int32 output is only meaningful when the total is below 2^31.
+int64_t scan_i32_checked(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 
 // list[rank[i]] = i for every i with flags[i] != 0 (rank = exclusive scan of flags).
 void list_rows(const int32_t* flags, const int32_t* rank, int32_t n, int32_t* list, hipStream_t s);
 // p[0..n) = v
 void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// host[k] = *src[k] for up to 8 device int32 scalars, with one synchronisation
+void read_scalars(const std::vector<const int32_t*>& src, int32_t* host, hipStream_t s);
 
 // ---------------------------------------------------------------- profiling
 
@@ -134,6 +139,8 @@ struct Graph {
     DevBuf<int32_t> pair_off;     // [n_inst+1] first (cell, macro) pair of each row
     DevBuf<int32_t> pair_row, pair_mac;
     DevBuf<int32_t> mlist, mstart; // pairs grouped by macro
+    DevBuf<int32_t> bin_rank;     // [n_inst] position of a hint cell in bin_cells
+    DevBuf<int32_t> wpre;         // [n_bins * window slots] offsets of the slots in bin rows
 
     // execution layout: instance rows in spatial order (perm: exec -> id)
     int32_t has_layout = 0;
@@ -184,9 +191,10 @@ struct Graph {
 void build_netlist(Graph& g, hipStream_t s);
 // Stable bucket sort: list = indices i in [0, n) with key[i] >= 0, grouped by
 // key, ascending within a key; start[k] = first position of key k
-// (start[nkeys] = count).  nkeys <= 16384.  Returns the count.
+// (start[nkeys] = count).  nkeys <= 16384.  list holds n entries.  Returns
+// the count when read_total (one synchronisation), else -1.
 int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
-                    DevBuf<int32_t>& start, hipStream_t s);
+                    DevBuf<int32_t>& start, hipStream_t s, bool read_total = true);
 // layout.hip: the execution order of instance rows (spatial) and the
 // permuted copy of the netlist rows the filter streams
 void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s);

@@ -7,12 +7,14 @@
 namespace ahr {
 
 std::string& last_error_ref();
+extern int g_hop_lanes;
+extern int g_hop_nt;
 
 Graph::~Graph() {
     hipStream_t s = nullptr;
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_rp, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
-                              &nmac, &nwin, &pair_off, &pair_row, &pair_mac, &mlist, &mstart, &row_len,
+                              &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart, &row_len,
                               &long_rows, &long_chunk0, &chunk_row, &i32a, &i32b, &counter};
     for (auto* b : i32) b->release(s);
     net_q.release(s);
@@ -309,6 +311,23 @@ ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0
         }
         return AHR_OK;
     });
+}
+
+ahr_status ahr_filter_tune(int32_t lanes_per_row, int32_t nontemporal) {
+    if (lanes_per_row != 0) {
+        if (lanes_per_row < 1 || lanes_per_row > 64 || (lanes_per_row & (lanes_per_row - 1)))
+            return fail(AHR_EINVAL, "lanes_per_row must be a power of two in [1, 64], or 0 to keep it");
+        ahr::g_hop_lanes = lanes_per_row;
+    }
+    if (nontemporal >= 0) ahr::g_hop_nt = nontemporal ? 1 : 0;
+    return AHR_OK;
+}
+
+ahr_status ahr_filter_get_tune(int32_t* lanes_per_row, int32_t* nontemporal) {
+    if (!lanes_per_row || !nontemporal) return fail(AHR_EINVAL, "NULL argument");
+    *lanes_per_row = ahr::g_hop_lanes;
+    *nontemporal = ahr::g_hop_nt;
+    return AHR_OK;
 }
 
 ahr_status ahr_hpwl(const ahr_graph* h, const float* g, int32_t ncols, double* out, void* stream) {

@@ -1,5 +1,7 @@
 // Errors, the stream-ordered allocator and the integer prefix scan.
+#include <map>
 #include <mutex>
+#include <unordered_map>
 
 #include "ahr_internal.hpp"
 #include "device_util.hpp"
@@ -26,39 +28,95 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 }
 
 // ---------------------------------------------------------------- allocator
+//
+// A caching allocator: freed device blocks are kept (per device, by size
+// class) and handed out again, so the graph builds of an initializer loop
+// allocate from the driver only the first time.  A block freed on one
+// stream and reused on another is ordered behind the frees' stream by an
+// event wait.  ahr_memory_trim() returns the cache to the driver.
 
-static std::once_flag g_pool_once[64];
+namespace {
 
-static void prepare_pool(int dev) {
-    // Keep freed blocks in the device's default pool so repeated graph
-    // builds reuse memory instead of returning it to the driver.
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+struct Block {
+    void* p;
+    size_t bytes;
+    hipStream_t stream;
+    hipEvent_t done;      // recorded on `stream` when the block was freed
+    int device;
+};
+
+std::mutex g_alloc_mu;
+std::multimap<size_t, Block> g_free;                  // by size class
+std::unordered_map<void*, std::pair<size_t, int>> g_live;   // ptr -> (size class, device)
+
+size_t size_class(size_t b) {
+    b = b < 256 ? 256 : b;
+    if (b <= (size_t(1) << 20)) {
+        size_t c = 256;
+        while (c < b) c <<= 1;
+        return c;
     }
-    (void)hipGetLastError();
+    const size_t mib = size_t(1) << 20;
+    size_t c = (b + mib - 1) / mib * mib;
+    // round large blocks up to 1/8 steps of their power of two to bound the classes
+    size_t top = mib;
+    while (top < c) top <<= 1;
+    size_t step = top / 8 > mib ? top / 8 : mib;
+    return (c + step - 1) / step * step;
 }
+
+}  // namespace
 
 void* dev_alloc(size_t bytes, hipStream_t s) {
     int dev = 0;
     AHR_HIP(hipGetDevice(&dev));
-    if (dev >= 0 && dev < 64) std::call_once(g_pool_once[dev], prepare_pool, dev);
+    const size_t cls = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        for (auto it = g_free.lower_bound(cls); it != g_free.end() && it->first == cls; ++it) {
+            if (it->second.device != dev) continue;
+            Block b = it->second;
+            g_free.erase(it);
+            if (b.stream != s) AHR_HIP(hipStreamWaitEvent(s, b.done, 0));
+            (void)hipEventDestroy(b.done);
+            g_live[b.p] = {cls, dev};
+            return b.p;
+        }
+    }
     void* p = nullptr;
-    size_t b = bytes ? bytes : 1;
-    b = (b + 255) & ~size_t(255);
-    hipError_t e = hipMallocAsync(&p, b, s);
+    hipError_t e = hipMalloc(&p, cls);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ahr_memory_trim();
+        e = hipMalloc(&p, cls);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         char buf[160];
-        snprintf(buf, sizeof buf, "device allocation of %zu bytes failed: %s", b, hipGetErrorString(e));
+        snprintf(buf, sizeof buf, "device allocation of %zu bytes failed: %s", cls, hipGetErrorString(e));
         throw Error{AHR_ENOMEM, buf};
     }
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_live[p] = {cls, dev};
     return p;
 }
 
 void dev_free(void* p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;
+    Block b{p, it->second.first, s, nullptr, it->second.second};
+    g_live.erase(it);
+    if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(b.done, s) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        if (b.done) (void)hipEventDestroy(b.done);
+        (void)hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+        (void)hipEventRecord(b.done, nullptr);
+    }
+    g_free.emplace(b.bytes, b);
 }
 
 // ---------------------------------------------------------------- scan
@@ -146,6 +204,19 @@ void scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, h
     scan_impl<int32_t, int64_t>(in, out, n, tmp, s);
 }
 
+int64_t scan_i32_checked(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+    if (n == 0) {
+        AHR_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+        return 0;
+    }
+    scan_impl<int32_t, int32_t>(in, out, n, tmp, s);
+    int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    int64_t total = 0;
+    AHR_HIP(hipMemcpyAsync(&total, tmp + ntiles, sizeof total, hipMemcpyDeviceToHost, s));
+    AHR_HIP(hipStreamSynchronize(s));
+    return total;
+}
+
 void scan_i32_to_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
     if (n == 0) {
         AHR_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
@@ -168,6 +239,34 @@ void list_rows(const int32_t* flags, const int32_t* rank, int32_t n, int32_t* li
     AHR_LAUNCHED("k_list_rows");
 }
 
+struct PtrPack {
+    const int32_t* p[8];
+};
+
+__global__ void k_gather_scalars(PtrPack src, int n, int32_t* dst) {
+    int i = threadIdx.x;
+    if (i < n) dst[i] = *src.p[i];
+}
+
+void read_scalars(const std::vector<const int32_t*>& src, int32_t* host, hipStream_t s) {
+    if (src.empty()) return;
+    if (src.size() > 8) throw Error{AHR_EDEVICE, "read_scalars: at most 8"};
+    static thread_local int32_t* dbuf = nullptr;
+    static thread_local int dbuf_dev = -1;
+    int dev = 0;
+    AHR_HIP(hipGetDevice(&dev));
+    if (!dbuf || dbuf_dev != dev) {
+        AHR_HIP(hipMalloc(&dbuf, 8 * sizeof(int32_t)));
+        dbuf_dev = dev;
+    }
+    PtrPack pk{};
+    for (size_t k = 0; k < src.size(); ++k) pk.p[k] = src[k];
+    hipLaunchKernelGGL(k_gather_scalars, dim3(1), dim3(64), 0, s, pk, static_cast<int>(src.size()), dbuf);
+    AHR_LAUNCHED("k_gather_scalars");
+    AHR_HIP(hipMemcpyAsync(host, dbuf, src.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    AHR_HIP(hipStreamSynchronize(s));
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -180,3 +279,18 @@ void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 }
 
 }  // namespace ahr
+
+extern "C" ahr_status ahr_memory_trim(void) {
+    std::lock_guard<std::mutex> lk(ahr::g_alloc_mu);
+    for (auto& kv : ahr::g_free) {
+        (void)hipEventSynchronize(kv.second.done);
+        (void)hipEventDestroy(kv.second.done);
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(kv.second.device);
+        (void)hipFree(kv.second.p);
+        (void)hipSetDevice(cur);
+    }
+    ahr::g_free.clear();
+    return AHR_OK;
+}

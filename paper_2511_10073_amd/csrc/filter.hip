@@ -22,6 +22,9 @@
 
 namespace ahr {
 
+extern int g_hop_lanes;   // lanes per short row of a hop
+extern int g_hop_nt;      // stream the entries with non-temporal loads
+
 namespace {
 
 constexpr int kBT = 256;
@@ -183,9 +186,11 @@ __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
     atomicMax(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)));
 }
 
-// Grid-stride over rows (G lanes per row); each workgroup keeps its running
-// maximum and issues one atomic at the end (the maximum is order-independent).
+// Grid-stride over rows (G lanes per row, kGU entries per lane per batch);
+// each workgroup keeps its running maximum and issues one atomic at the end
+// (the maximum is order-independent).
 constexpr int kGershGrid = 2048;
+constexpr int kGU = 4;
 
 template <int G>
 __global__ void __launch_bounds__(kBT) k_gersh_short(int32_t n, RowRef m, const double* __restrict__ deg,
@@ -198,14 +203,22 @@ __global__ void __launch_bounds__(kBT) k_gersh_short(int32_t n, RowRef m, const 
     for (int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G; r < n; r += stride) {
         int n0 = m.net_rp[r], n1 = m.net_rp[r + 1], h0 = m.hint_rp[r], h1 = m.hint_rp[r + 1];
         if ((n1 - n0) + (h1 - h0) > kLongRow) continue;          // group-uniform
+        const int ln = n1 - n0, len = ln + (h1 - h0);
         double a = 0;
-        for (int k = n0 + l; k < n1; k += G) {
-            int2 e = m.net_ent[k];
-            a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
-        }
-        for (int k = h0 + l; k < h1; k += G) {
-            int2 e = m.hint_ent[k];
-            a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
+        for (int k0 = l; k0 < len; k0 += G * kGU) {
+            int2 e[kGU];
+            float sc[kGU];
+#pragma unroll
+            for (int u = 0; u < kGU; ++u) {
+                int k = k0 + u * G;
+                int kc = k < len ? k : len - 1;
+                e[u] = kc < ln ? m.net_ent[n0 + kc] : m.hint_ent[h0 + kc - ln];
+                if (k >= len) e[u].y = 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kGU; ++u) sc[u] = scale[e[u].x];
+#pragma unroll
+            for (int u = 0; u < kGU; ++u) a += fabs(static_cast<double>(bits_f(e[u].y))) * static_cast<double>(sc[u]);
         }
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) a += __shfl_xor(a, o);
@@ -463,14 +476,22 @@ __device__ __forceinline__ void epilogue(const HopArgs& a, int r, const RowOps<C
 }
 
 // Entry k of row r's concatenated (netlist, hints) list; k is clamped into
-// the row by the caller.
+// the row by the caller.  The entries are streamed once per hop, so they
+// are loaded non-temporally to leave the L2 to the gathered signal rows.
+template <bool NT>
 __device__ __forceinline__ int2 row_entry(const RowRef& m, int n0, int ln, int h0, int k) {
-    return k < ln ? m.net_ent[n0 + k] : m.hint_ent[h0 + k - ln];
+    const int2* p = k < ln ? m.net_ent + n0 + k : m.hint_ent + h0 + k - ln;
+    if constexpr (NT) {
+        long long v = __builtin_nontemporal_load(reinterpret_cast<const long long*>(p));
+        return make_int2(static_cast<int>(v & 0xffffffffll), static_cast<int>(v >> 32));
+    } else {
+        return *p;
+    }
 }
 
 // Sum of U entries per lane: all entry loads issue before any gather and all
 // gathers before any use, so each lane keeps 2U requests in flight.
-template <int C, int U, class Acc>
+template <int C, int U, class Acc, bool NT>
 __device__ __forceinline__ void gather_batch(const HopArgs& a, int n0, int ln, int h0, int len, int k0, int step,
                                              Acc* acc) {
     int2 e[U];
@@ -478,7 +499,7 @@ __device__ __forceinline__ void gather_batch(const HopArgs& a, int n0, int ln, i
     for (int u = 0; u < U; ++u) {
         int k = k0 + u * step;
         int kc = k < len ? k : len - 1;
-        e[u] = row_entry(a.m, n0, ln, h0, kc);
+        e[u] = row_entry<NT>(a.m, n0, ln, h0, kc);
         if (k >= len) e[u].y = 0;                 // weight 0 for the clamped duplicates
     }
     Vec<C> v[U];
@@ -495,7 +516,7 @@ __device__ __forceinline__ void gather_batch(const HopArgs& a, int n0, int ln, i
 // One chunk of a long row: the workgroup's float64 partial sum goes to
 // partial[chunk]; k_hop_long adds a row's partials after the launch ends (no
 // device-scope fence inside the hop: on this chip that is an L2 write-back).
-template <int C>
+template <int C, bool NT>
 __device__ __forceinline__ void hop_chunk(const HopArgs& a) {
     __shared__ double red[kBT / kWave];
     int r, li, k0, k1, n0, ln, h0;
@@ -504,7 +525,7 @@ __device__ __forceinline__ void hop_chunk(const HopArgs& a) {
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0;
-    gather_batch<C, U, double>(a, n0, ln, h0, k1, k0 + threadIdx.x, kBT, acc);
+    gather_batch<C, U, double, NT>(a, n0, ln, h0, k1, k0 + threadIdx.x, kBT, acc);
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = block_sum_f64<kBT>(acc[c], red);
     if (threadIdx.x == 0) {
@@ -554,10 +575,10 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
     return (b % kXcds) * per + b / kXcds;
 }
 
-template <int C, int G, int U>
+template <int C, int G, int U, bool NT>
 __global__ void __launch_bounds__(kBT) k_hop(HopArgs a) {
     if (static_cast<int>(blockIdx.x) < a.n_chunk_blocks) {
-        hop_chunk<C>(a);
+        hop_chunk<C, NT>(a);
         return;
     }
     const int64_t nb = static_cast<int64_t>(gridDim.x) - a.n_chunk_blocks;     // a multiple of kXcds
@@ -575,7 +596,7 @@ __global__ void __launch_bounds__(kBT) k_hop(HopArgs a) {
     float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.f;
-    for (int k0 = l; k0 < len; k0 += G * U) gather_batch<C, U, float>(a, n0, ln, h0, len, k0, G, acc);
+    for (int k0 = l; k0 < len; k0 += G * U) gather_batch<C, U, float, NT>(a, n0, ln, h0, len, k0, G, acc);
     Vec<C> sum;
 #pragma unroll
     for (int c = 0; c < C; ++c) sum.v[c] = acc[c];
@@ -612,7 +633,11 @@ void launch_hop(const HopArgs& a, int32_t n_long_rows, hipStream_t s) {
     int64_t tiles = grid_for(static_cast<int64_t>(a.n_rows) * G, kBT);
     tiles = (tiles + kXcds - 1) / kXcds * kXcds;                    // see xcd_tile
     int64_t blocks = a.n_chunk_blocks + tiles;
-    hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U)>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s, a);
+    if (g_hop_nt)
+        hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), true>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), false>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s,
+                           a);
     AHR_LAUNCHED("k_hop");
     if (n_long_rows > 0) {
         hipLaunchKernelGGL(k_hop_long<C>, dim3(grid_for(static_cast<int64_t>(n_long_rows) * kWave, kBT)), dim3(kBT),
@@ -768,7 +793,11 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
         rank.ensure(static_cast<size_t>(N) + 1, s);
         g.scan_tmp.ensure(scan_tmp_elems(N), s);
         scan_i32_to_i32(is_long.p, rank.p, N, g.scan_tmp.p, s);
-        g.n_long = read_scalar(rank.p + N, s);
+        int32_t t1[4];
+        read_scalars({rank.p + N, rank.p + g.n_inst, g.xnet_rp.p + g.n_inst, g.xhint_rp.p + g.n_inst}, t1, s);
+        g.n_long = t1[0];
+        g.n_long_inst = t1[1];
+        g.nnz_inst = static_cast<int64_t>(t1[2]) + t1[3];
         g.long_rows.ensure(static_cast<size_t>(g.n_long) + 1, s);
         list_rows(is_long.p, rank.p, N, g.long_rows.p, s);
         nch.ensure(static_cast<size_t>(g.n_long) + 1, s);
@@ -780,21 +809,10 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
         }
         g.scan_tmp.ensure(scan_tmp_elems(g.n_long), s);
         scan_i32_to_i32(nch.p, g.long_chunk0.p, g.n_long, g.scan_tmp.p, s);
-        std::vector<int32_t> rows_h(g.n_long), c0_h(static_cast<size_t>(g.n_long) + 1);
-        AHR_HIP(hipMemcpyAsync(c0_h.data(), g.long_chunk0.p, sizeof(int32_t) * (g.n_long + 1), hipMemcpyDeviceToHost, s));
-        if (g.n_long)
-            AHR_HIP(hipMemcpyAsync(rows_h.data(), g.long_rows.p, sizeof(int32_t) * g.n_long, hipMemcpyDeviceToHost, s));
-        AHR_HIP(hipStreamSynchronize(s));
-        g.n_chunks = c0_h[g.n_long];
-        int32_t at_inst[2];
-        AHR_HIP(hipMemcpyAsync(&at_inst[0], g.xnet_rp.p + g.n_inst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        AHR_HIP(hipMemcpyAsync(&at_inst[1], g.xhint_rp.p + g.n_inst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        AHR_HIP(hipStreamSynchronize(s));
-        g.nnz_inst = static_cast<int64_t>(at_inst[0]) + at_inst[1];
-        g.n_chunks_inst = 0;
-        g.n_long_inst = 0;
-        for (int i = 0; i < g.n_long; ++i)
-            if (rows_h[i] < g.n_inst) g.n_chunks_inst = c0_h[i + 1], g.n_long_inst = i + 1;
+        int32_t t2[2];
+        read_scalars({g.long_chunk0.p + g.n_long, g.long_chunk0.p + g.n_long_inst}, t2, s);
+        g.n_chunks = t2[0];
+        g.n_chunks_inst = t2[1];
         g.chunk_row.ensure(static_cast<size_t>(g.n_chunks) + 1, s);
         if (g.n_long) {
             hipLaunchKernelGGL(k_chunk_rows, dim3(g.n_long), dim3(kBT), 0, s, g.n_long, g.long_chunk0.p, g.chunk_row.p);
@@ -808,7 +826,7 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     g.deg.ensure(static_cast<size_t>(N) + 1, s);
     g.scale.ensure(static_cast<size_t>(N) + 1, s);
     g.lam.ensure(1, s);
-    constexpr int G = 16;
+    constexpr int G = 4;
     hipLaunchKernelGGL(k_deg_short<G>, dim3(grid_for(static_cast<int64_t>(N) * G, kBT)), dim3(kBT), 0, s, N, m,
                        g.xqdeg.p, sigma, g.deg.p, g.scale.p);
     AHR_LAUNCHED("k_deg_short");
@@ -844,7 +862,8 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     g.norm_fixed = spec.lambda_fixed;
 }
 
-int g_hop_lanes = 8;   // lanes per short row (set by the tuner)
+int g_hop_lanes = 2;   // lanes per short row (set by the tuner)
+int g_hop_nt = 0;      // non-temporal entry loads
 
 void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int32_t ncols, hipStream_t s) {
     normalise(g, spec, s);

@@ -155,11 +155,11 @@ __global__ void __launch_bounds__(kWave) k_bucket_scatter(const int32_t* __restr
     }
 }
 
-__global__ void k_bin_start(const int32_t* __restrict__ off, int nbins, int32_t ntiles, int32_t total,
-                            int32_t* __restrict__ bin_start) {
+__global__ void k_bin_start(const int32_t* __restrict__ off, int nbins, int32_t ntiles,
+                            const int32_t* __restrict__ total, int32_t* __restrict__ bin_start) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < nbins) bin_start[b] = off[static_cast<int64_t>(b) * ntiles];
-    if (b == nbins) bin_start[b] = total;
+    if (b == nbins) bin_start[b] = *total;
 }
 
 __device__ __forceinline__ float outward(float c, float h) {
@@ -336,9 +336,15 @@ __global__ void k_bin_row_counts(HintArgs a, int32_t* __restrict__ cnt) {
 }
 
 // Cell rows: macro entries (ascending macro) then window bins (row-major).
+// Each bin entry is also written, with the same float, into the bin's own
+// row: bin row b lists the cells of its window bins slot by slot (row-major),
+// ascending execution rows within a slot; wpre[b][slot] is the slot's offset
+// and rank[r] the cell's position in its bin's list.
 __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ pair_off,
-                                                   const int32_t* __restrict__ pair_mac, int2* __restrict__ ent) {
+                                                   const int32_t* __restrict__ pair_mac,
+                                                   const int32_t* __restrict__ rank, const int32_t* __restrict__ wpre,
+                                                   int2* __restrict__ ent) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
     if (r >= a.n_inst) return;
     int b = a.cell_bin[r];
@@ -353,13 +359,44 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
         ent[o + n++] = make_int2(a.first_mvirt + k, f_bits(w_macro(x, y, a.rect[k], bwi)));
     }
     if (a.bin_hints) {
+        const int ww = 2 * a.gr.hx + 1, wh = 2 * a.gr.hy + 1;
+        const int bx = b % a.gr.nbx, by = b / a.gr.nbx;
+        const int my = rank[r] - a.bin_start[b];
         int x0, x1, y0, y1;
         window(a.gr, b, x0, x1, y0, y1);
-        for (int by = y0; by <= y1; ++by)
-            for (int bx = x0; bx <= x1; ++bx) {
-                int bb = by * a.gr.nbx + bx;
-                ent[o + n++] = make_int2(a.first_bvirt + bb, f_bits(w_bin(a.gr, x, y, bb, a.phi, bwi)));
+        for (int ty = y0; ty <= y1; ++ty)
+            for (int tx = x0; tx <= x1; ++tx) {
+                int bb = ty * a.gr.nbx + tx;
+                int w = f_bits(w_bin(a.gr, x, y, bb, a.phi, bwi));
+                ent[o + n++] = make_int2(a.first_bvirt + bb, w);
+                // slot of this cell's bin inside the window of bb
+                int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
+                int64_t q = rp[a.first_bvirt + bb] + wpre[static_cast<int64_t>(bb) * ww * wh + slot] + my;
+                ent[q] = make_int2(static_cast<int>(r), w);
             }
+    }
+}
+
+// rank[bin_cells[t]] = t
+__global__ void k_bin_rank(int32_t n, const int32_t* __restrict__ bin_cells, int32_t* __restrict__ rank) {
+    int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < n) rank[bin_cells[t]] = static_cast<int32_t>(t);
+}
+
+// wpre[b][slot]: entries of bin row b before window slot `slot` (row-major,
+// out-of-grid slots empty).
+__global__ void k_window_prefix(HintArgs a, int32_t* __restrict__ wpre) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nbins) return;
+    const int ww = 2 * a.gr.hx + 1, wh = 2 * a.gr.hy + 1;
+    const int bx = b % a.gr.nbx, by = b / a.gr.nbx;
+    int acc = 0;
+    for (int w = 0; w < ww * wh; ++w) {
+        wpre[static_cast<int64_t>(b) * ww * wh + w] = acc;
+        int tx = bx + w % ww - a.gr.hx, ty = by + w / ww - a.gr.hy;
+        if (tx < 0 || tx >= a.gr.nbx || ty < 0 || ty >= a.gr.nby) continue;
+        int bb = ty * a.gr.nbx + tx;
+        acc += a.bin_start[bb + 1] - a.bin_start[bb];
     }
 }
 
@@ -378,37 +415,6 @@ __global__ void k_macro_fill(int32_t n_pairs, int32_t first_mvirt, const int32_t
     ent[rp[first_mvirt + k] + (t - mstart[k])] = make_int2(row, w);
 }
 
-// Bin virtual rows: one workgroup per (bin row, window position) copies the
-// cells of that window bin (ascending rows) with the cell-side weights.
-__global__ void __launch_bounds__(kBT) k_bin_fill(HintArgs a, const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ nmac, int2* __restrict__ ent) {
-    int b = blockIdx.x;
-    int w = blockIdx.y;
-    int ww = 2 * a.gr.hx + 1;
-    int dx = w % ww - a.gr.hx, dy = w / ww - a.gr.hy;
-    int bx = b % a.gr.nbx, by = b / a.gr.nbx;
-    int tx = bx + dx, ty = by + dy;
-    if (tx < 0 || tx >= a.gr.nbx || ty < 0 || ty >= a.gr.nby) return;
-    int64_t o = rp[a.first_bvirt + b];
-    for (int v = 0; v < w; ++v) {
-        int ux = bx + v % ww - a.gr.hx, uy = by + v / ww - a.gr.hy;
-        if (ux < 0 || ux >= a.gr.nbx || uy < 0 || uy >= a.gr.nby) continue;
-        int ub = uy * a.gr.nbx + ux;
-        o += a.bin_start[ub + 1] - a.bin_start[ub];
-    }
-    int bb = ty * a.gr.nbx + tx;
-    // position of bin b inside the clipped window of bb (row-major)
-    int x0, x1, y0, y1;
-    window(a.gr, bb, x0, x1, y0, y1);
-    int widx = (by - y0) * (x1 - x0 + 1) + (bx - x0);
-    int s0 = a.bin_start[bb], s1 = a.bin_start[bb + 1];
-    for (int t = s0 + threadIdx.x; t < s1; t += kBT) {
-        int row = a.bin_cells[t];
-        int wv = ent[rp[row] + nmac[row] + widx].y;
-        ent[o + (t - s0)] = make_int2(row, wv);
-    }
-}
-
 __global__ void k_fill_u64(unsigned long long* p, int64_t n) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
@@ -425,11 +431,11 @@ T read_scalar(const T* dev, hipStream_t s) {
 }  // namespace
 
 int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
-                    DevBuf<int32_t>& start, hipStream_t s) {
+                    DevBuf<int32_t>& start, hipStream_t s, bool read_total) {
     if (nkeys > kMaxBins) throw Error{AHR_EUNSUPPORTED, "too many buckets (at most 16384 bins or macros)"};
+    list.ensure(static_cast<size_t>(n) + 1, s);
+    start.ensure(static_cast<size_t>(nkeys) + 1, s);
     if (n == 0) {
-        list.ensure(1, s);
-        start.ensure(static_cast<size_t>(nkeys) + 1, s);
         fill_i32(start.p, nkeys + 1, 0, s);
         return 0;
     }
@@ -441,18 +447,16 @@ int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<i
     AHR_LAUNCHED("k_bucket_count");
     g.scan_tmp.ensure(scan_tmp_elems(hn), s);
     scan_i32_to_i32(g.i32a.p, g.i32b.p, hn, g.scan_tmp.p, s);
-    int32_t total = read_scalar(g.i32b.p + hn, s);
-    list.ensure(static_cast<size_t>(total) + 1, s);
     int bits = 0;
     while ((1 << bits) < nkeys) ++bits;
     hipLaunchKernelGGL(k_bucket_scatter, dim3(ntiles), dim3(kWave), 0, s, key, n, nkeys, bits, ntiles, g.i32b.p,
                        list.p);
     AHR_LAUNCHED("k_bucket_scatter");
-    start.ensure(static_cast<size_t>(nkeys) + 1, s);
-    hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nkeys + 1, kBT)), dim3(kBT), 0, s, g.i32b.p, nkeys, ntiles, total,
-                       start.p);
+    hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nkeys + 1, kBT)), dim3(kBT), 0, s, g.i32b.p, nkeys, ntiles,
+                       g.i32b.p + hn, start.p);
     AHR_LAUNCHED("k_bin_start");
-    return total;
+    if (!read_total) return -1;
+    return read_scalar(start.p + nkeys, s);
 }
 
 namespace {
@@ -515,7 +519,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     AHR_LAUNCHED("k_cell_bins");
 
     // 2. hint cells grouped by bin, ascending execution rows (stable bucket sort)
-    g.n_hint_cells = bucket_sort(g, g.cell_bin.p, n_inst, nbins, g.bin_cells, g.bin_start, s);
+    bucket_sort(g, g.cell_bin.p, n_inst, nbins, g.bin_cells, g.bin_start, s, false);
 
     // 3. macros: footprints, spans, areas; phi
     const int32_t n_macro = g.n_macro;
@@ -588,7 +592,10 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.pair_off.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(std::max<int64_t>(N, n_inst)), s);
     scan_i32_to_i32(g.nmac.p, g.pair_off.p, n_inst, g.scan_tmp.p, s);
-    int32_t n_pairs = read_scalar(g.pair_off.p + n_inst, s);
+    int32_t tot[2];
+    read_scalars({g.pair_off.p + n_inst, g.bin_start.p + nbins}, tot, s);
+    const int32_t n_pairs = tot[0];
+    g.n_hint_cells = tot[1];
     g.pair_row.ensure(static_cast<size_t>(n_pairs) + 1, s);
     g.pair_mac.ensure(static_cast<size_t>(n_pairs) + 1, s);
     if (n_pairs) {
@@ -598,9 +605,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         AHR_LAUNCHED("k_cell_count pairs");
     }
     // pairs grouped by macro, ascending row: the macro virtual rows
-    int32_t n_sorted = 0;
-    if (use_macros) n_sorted = bucket_sort(g, g.pair_mac.p, n_pairs, n_macro, g.mlist, g.mstart, s);
-    if (n_sorted != (use_macros ? n_pairs : 0)) throw Error{AHR_EDEVICE, "macro pair sort lost entries"};
+    if (use_macros) bucket_sort(g, g.pair_mac.p, n_pairs, n_macro, g.mlist, g.mstart, s, false);
 
     // 6. row counts and offsets (execution order)
     hipLaunchKernelGGL(k_cell_hint_cnt, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.nmac.p, g.nwin.p,
@@ -615,33 +620,34 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         hipLaunchKernelGGL(k_bin_row_counts, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s, a, g.hint_cnt.p);
         AHR_LAUNCHED("k_bin_row_counts");
     }
-    DevBuf<int64_t> rp64;
-    rp64.ensure(static_cast<size_t>(N) + 1, s);
-    scan_i32_to_i64(g.hint_cnt.p, rp64.p, N, g.scan_tmp.p, s);
-    int64_t nnz = read_scalar(rp64.p + N, s);
-    rp64.release(s);
+    const int64_t nnz = scan_i32_checked(g.hint_cnt.p, g.xhint_rp.p, N, g.scan_tmp.p, s);
     if (nnz + static_cast<int64_t>(g.nnz_net) >= INT32_MAX)
         throw Error{AHR_EUNSUPPORTED, "graph with hints has 2^31 or more entries"};
-    scan_i32_to_i32(g.hint_cnt.p, g.xhint_rp.p, N, g.scan_tmp.p, s);
     g.nnz_hint = static_cast<int32_t>(nnz);
     g.xhint_ent.ensure(static_cast<size_t>(nnz) + 1, s);
 
     // 7. entries: cell rows first (their weights are reused), then virtual rows
+    const int wslots = (2 * gr.hx + 1) * (2 * gr.hy + 1);
+    if (bin_hints) {
+        g.bin_rank.ensure(static_cast<size_t>(n_inst) + 1, s);
+        g.wpre.ensure(static_cast<size_t>(nbins) * wslots + 1, s);
+        if (g.n_hint_cells)
+            hipLaunchKernelGGL(k_bin_rank, dim3(grid_for(g.n_hint_cells, kBT)), dim3(kBT), 0, s, g.n_hint_cells,
+                               g.bin_cells.p, g.bin_rank.p);
+        AHR_LAUNCHED("k_bin_rank");
+        hipLaunchKernelGGL(k_window_prefix, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s, a, g.wpre.p);
+        AHR_LAUNCHED("k_window_prefix");
+    }
     hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a,
                        static_cast<const int32_t*>(g.xhint_rp.p), static_cast<const int32_t*>(g.pair_off.p),
-                       static_cast<const int32_t*>(g.pair_mac.p), g.xhint_ent.p);
+                       static_cast<const int32_t*>(g.pair_mac.p), static_cast<const int32_t*>(g.bin_rank.p),
+                       static_cast<const int32_t*>(g.wpre.p), g.xhint_ent.p);
     AHR_LAUNCHED("k_cell_fill");
     if (use_macros && n_pairs) {
         hipLaunchKernelGGL(k_macro_fill, dim3(grid_for(n_pairs, kBT)), dim3(kBT), 0, s, n_pairs, g.first_mvirt,
                            g.mlist.p, g.mstart.p, g.pair_row.p, g.pair_mac.p, g.pair_off.p, g.xhint_rp.p,
                            g.xhint_ent.p);
         AHR_LAUNCHED("k_macro_fill");
-    }
-    if (bin_hints) {
-        dim3 grid(nbins, (2 * gr.hx + 1) * (2 * gr.hy + 1));
-        hipLaunchKernelGGL(k_bin_fill, grid, dim3(kBT), 0, s, a, static_cast<const int32_t*>(g.xhint_rp.p),
-                           static_cast<const int32_t*>(g.nmac.p), g.xhint_ent.p);
-        AHR_LAUNCHED("k_bin_fill");
     }
 }
 

@@ -53,24 +53,30 @@ __global__ void k_exec_lens(int32_t n_tot, int32_t n_inst, const int32_t* __rest
     len[r] = rp[s + 1] - rp[s];
 }
 
-// A wave per row copies the canonical netlist row with renumbered columns
-// and float32 weights; the row's integer weight sum moves along.
-__global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
-                                                  const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ col, const int64_t* __restrict__ q,
-                                                  const int64_t* __restrict__ qdeg, const int32_t* __restrict__ xrp,
-                                                  int2* __restrict__ xent, int64_t* __restrict__ xqdeg) {
-    constexpr int G = 64;
-    int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
-    int l = threadIdx.x & (G - 1);
-    if (r >= n_tot) return;
-    int s = src_row(static_cast<int>(r), n_inst, perm);
-    int a = rp[s], n = rp[s + 1] - a;
-    int o = xrp[r];
-    for (int k = l; k < n; k += G)
-        xent[o + k] = make_int2(map_col(col[a + k], n_inst, iperm),
-                                f_bits(static_cast<float>(static_cast<double>(q[a + k]) * 0x1p-32)));
-    if (l == 0) xqdeg[r] = qdeg[s];
+// One thread per execution-order entry: find its row (binary search over
+// the execution row pointers), copy the canonical entry with its column
+// renumbered and its weight as float32.  Entry-parallel, so rows of any
+// length cost the same per entry.
+__global__ void k_exec_net(int32_t nnz, int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
+                           const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
+                           const int32_t* __restrict__ col, const int64_t* __restrict__ q,
+                           const int32_t* __restrict__ xrp, int2* __restrict__ xent) {
+    int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    int lo = 0, hi = n_tot;     // row r with xrp[r] <= k < xrp[r+1]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (xrp[mid] <= k) lo = mid; else hi = mid;
+    }
+    int s = src_row(lo, n_inst, perm);
+    int a = rp[s] + static_cast<int>(k - xrp[lo]);
+    xent[k] = make_int2(map_col(col[a], n_inst, iperm), f_bits(static_cast<float>(static_cast<double>(q[a]) * 0x1p-32)));
+}
+
+__global__ void k_exec_qdeg(int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
+                            const int64_t* __restrict__ qdeg, int64_t* __restrict__ xqdeg) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < n_tot) xqdeg[r] = qdeg[src_row(static_cast<int>(r), n_inst, perm)];
 }
 
 }  // namespace
@@ -85,8 +91,7 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     hipLaunchKernelGGL(k_layout_keys, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, pos, ncols, n, g.nl.die[0],
                        g.nl.die[1], sx, sy, key.p);
     AHR_LAUNCHED("k_layout_keys");
-    int32_t cnt = bucket_sort(g, key.p, n, 1 << (2 * kGridBits), g.perm, g.lay_start, s);
-    if (cnt != n) throw Error{AHR_EDEVICE, "layout sort lost instances"};
+    bucket_sort(g, key.p, n, 1 << (2 * kGridBits), g.perm, g.lay_start, s, false);   // every key >= 0
     key.release(s);
     g.iperm.ensure(static_cast<size_t>(n) + 1, s);
     hipLaunchKernelGGL(k_iperm, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.perm.p, n, g.iperm.p);
@@ -102,10 +107,12 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     len.release(s);
     g.xnet_ent.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 64, kBT)), dim3(kBT), 0, s, N, n,
-                       g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.qdeg.p, g.xnet_rp.p, g.xnet_ent.p,
-                       g.xqdeg.p);
+    if (g.nnz_net)
+        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(g.nnz_net, kBT)), dim3(kBT), 0, s, g.nnz_net, N, n, g.perm.p,
+                           g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
     AHR_LAUNCHED("k_exec_net");
+    hipLaunchKernelGGL(k_exec_qdeg, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, n, g.perm.p, g.qdeg.p, g.xqdeg.p);
+    AHR_LAUNCHED("k_exec_qdeg");
     g.has_layout = 1;
 }
 

@@ -4,6 +4,8 @@
 // ascending, parallel edges summed exactly).  Every structural step uses
 // integer counts, scans and sorts, so the result is bit-identical from run
 // to run and to any other exact implementation of the same definition.
+#include <algorithm>
+
 #include "ahr_internal.hpp"
 #include "device_util.hpp"
 
@@ -214,22 +216,28 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
         }
     }
     int prev = __shfl(key, gbase + (l > 0 ? l - 1 : 0));
+    int next = __shfl(key, gbase + (l + 1 < G ? l + 1 : l));
     bool head = (l < len) && (l == 0 || prev != key);
-    // run sums: a head adds the following lanes with the same column
-    int64_t sum = q;
-    bool open = head;
-    for (int t = 1; t < G; ++t) {
-        int src = gbase + (l + t < G ? l + t : l);
-        int k2 = __shfl(key, src);
-        int64_t q2 = __shfl(q, src);
-        if (open && l + t < len && k2 == key) sum += q2;
-        else open = false;
+    bool tail = (l < len) && (l + 1 == len || next != key);
+    // run sums from exact int64 prefix sums: sum = pre[l] - pre[start - 1]
+    int64_t pre = q;
+    int start = head ? l : 0;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        int64_t pu = __shfl(pre, gbase + (l >= d ? l - d : l));
+        int su = __shfl(start, gbase + (l >= d ? l - d : l));
+        if (l >= d) {
+            pre += pu;
+            start = su > start ? su : start;
+        }
     }
+    int64_t before = __shfl(pre, gbase + (start > 0 ? start - 1 : 0));
+    int64_t sum = pre - (start > 0 ? before : 0);
     uint64_t hm = __ballot(head);
     uint64_t gm = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
-    uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;
-    int idx = __popcll(hm & gm & lt);
-    if (head) {
+    uint64_t below_start = (gbase + start) ? (~0ull >> (kWave - (gbase + start))) : 0ull;
+    int idx = __popcll(hm & gm & below_start);
+    if (tail) {
         scol[base + idx] = key;
         sq[base + idx] = sum;
     }
@@ -353,18 +361,6 @@ T read_scalar(const T* dev, hipStream_t s) {
     return v;
 }
 
-// flags[0..n) -> ascending list of set indices; returns the count.
-int32_t list_from_flags(const int32_t* flags, int32_t n, DevBuf<int32_t>& rank, DevBuf<int32_t>& list,
-                        Graph& g, hipStream_t s) {
-    rank.ensure(static_cast<size_t>(n) + 1, s);
-    g.scan_tmp.ensure(scan_tmp_elems(n), s);
-    scan_i32_to_i32(flags, rank.p, n, g.scan_tmp.p, s);
-    int32_t cnt = read_scalar(rank.p + n, s);
-    list.ensure(static_cast<size_t>(cnt) + 1, s);
-    list_rows(flags, rank.p, n, list.p, s);
-    return cnt;
-}
-
 }  // namespace
 
 void build_netlist(Graph& g, hipStream_t s) {
@@ -387,16 +383,45 @@ void build_netlist(Graph& g, hipStream_t s) {
         throw Error{AHR_EINVAL, std::string("invalid netlist: ") + why[bad]};
     }
 
-    // macro pin expansion
-    DevBuf<int32_t> is_mp, mp_rank;
+    // flags of macro pins, star nets, big nets, macros; their ranks; one read of the four counts
+    DevBuf<int32_t> is_mp, mp_rank, is_star, star_rank, is_big, big_rank, is_mac, mac_rank;
     is_mp.ensure(static_cast<size_t>(n_pins) + 1, s);
+    is_star.ensure(static_cast<size_t>(n_nets) + 1, s);
+    is_big.ensure(static_cast<size_t>(n_nets) + 1, s);
+    is_mac.ensure(static_cast<size_t>(n_inst) + 1, s);
     if (n_pins)
         hipLaunchKernelGGL(k_mark_mpin, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, nl.pin_node, nl.node_flags,
                            n_pins, (hp.flags & AHR_EXPAND_MACRO_PINS) ? 1 : 0, is_mp.p);
     AHR_LAUNCHED("k_mark_mpin");
-    DevBuf<int32_t> mp_list;
-    g.n_mpin = list_from_flags(is_mp.p, n_pins, mp_rank, mp_list, g, s);
-    mp_list.release(s);
+    if (n_nets)
+        hipLaunchKernelGGL(k_mark_star, dim3(grid_for(n_nets, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets,
+                           hp.clique_max, is_star.p, is_big.p);
+    AHR_LAUNCHED("k_mark_star");
+    hipLaunchKernelGGL(k_mark_macro, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, nl.node_flags, n_inst, is_mac.p);
+    AHR_LAUNCHED("k_mark_macro");
+    mp_rank.ensure(static_cast<size_t>(n_pins) + 1, s);
+    star_rank.ensure(static_cast<size_t>(n_nets) + 1, s);
+    big_rank.ensure(static_cast<size_t>(n_nets) + 1, s);
+    mac_rank.ensure(static_cast<size_t>(n_inst) + 1, s);
+    g.scan_tmp.ensure(scan_tmp_elems(std::max<int64_t>(std::max<int64_t>(n_pins, n_nets), n_inst)), s);
+    scan_i32_to_i32(is_mp.p, mp_rank.p, n_pins, g.scan_tmp.p, s);
+    scan_i32_to_i32(is_star.p, star_rank.p, n_nets, g.scan_tmp.p, s);
+    scan_i32_to_i32(is_big.p, big_rank.p, n_nets, g.scan_tmp.p, s);
+    scan_i32_to_i32(is_mac.p, mac_rank.p, n_inst, g.scan_tmp.p, s);
+    int32_t cnt4[4];
+    read_scalars({mp_rank.p + n_pins, star_rank.p + n_nets, big_rank.p + n_nets, mac_rank.p + n_inst}, cnt4, s);
+    g.n_mpin = cnt4[0];
+    g.n_star = cnt4[1];
+    g.n_big_nets = cnt4[2];
+    g.n_macro = cnt4[3];
+    if ((hp.flags & AHR_MACRO_HINTS) && g.n_macro > 16384)
+        throw Error{AHR_EUNSUPPORTED, "macro hints support at most 16384 macros"};
+    g.star_net.ensure(static_cast<size_t>(g.n_star) + 1, s);
+    g.big_nets.ensure(static_cast<size_t>(g.n_big_nets) + 1, s);
+    g.macro_ids.ensure(static_cast<size_t>(g.n_macro) + 1, s);
+    list_rows(is_star.p, star_rank.p, n_nets, g.star_net.p, s);
+    list_rows(is_big.p, big_rank.p, n_nets, g.big_nets.p, s);
+    list_rows(is_mac.p, mac_rank.p, n_inst, g.macro_ids.p, s);
     g.pin_node_x.ensure(static_cast<size_t>(n_pins) + 1, s);
     g.mpin_owner.ensure(static_cast<size_t>(g.n_mpin) + 1, s);
     g.mpin_pin.ensure(static_cast<size_t>(g.n_mpin) + 1, s);
@@ -406,28 +431,8 @@ void build_netlist(Graph& g, hipStream_t s) {
     AHR_LAUNCHED("k_pin_nodes");
     is_mp.release(s);
     mp_rank.release(s);
-
-    // star nets and big nets
-    DevBuf<int32_t> is_star, is_big, star_rank, big_rank;
-    is_star.ensure(static_cast<size_t>(n_nets) + 1, s);
-    is_big.ensure(static_cast<size_t>(n_nets) + 1, s);
-    if (n_nets)
-        hipLaunchKernelGGL(k_mark_star, dim3(grid_for(n_nets, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets,
-                           hp.clique_max, is_star.p, is_big.p);
-    AHR_LAUNCHED("k_mark_star");
-    g.n_star = list_from_flags(is_star.p, n_nets, star_rank, g.star_net, g, s);
-    g.n_big_nets = list_from_flags(is_big.p, n_nets, big_rank, g.big_nets, g, s);
     is_big.release(s);
     big_rank.release(s);
-
-    // macros (instance order)
-    DevBuf<int32_t> is_mac, mac_rank;
-    is_mac.ensure(static_cast<size_t>(n_inst) + 1, s);
-    hipLaunchKernelGGL(k_mark_macro, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, nl.node_flags, n_inst, is_mac.p);
-    AHR_LAUNCHED("k_mark_macro");
-    g.n_macro = list_from_flags(is_mac.p, n_inst, mac_rank, g.macro_ids, g, s);
-    if ((hp.flags & AHR_MACRO_HINTS) && g.n_macro > 16384)
-        throw Error{AHR_EUNSUPPORTED, "macro hints support at most 16384 macros"};
     is_mac.release(s);
     mac_rank.release(s);
 
@@ -480,17 +485,23 @@ void build_netlist(Graph& g, hipStream_t s) {
     // per-row sort + merge; rows grouped by length class (ascending lists)
     DevBuf<int32_t> lists, cflag, crank;
     lists.ensure(static_cast<size_t>(N) * 4 + 4, s);
-    cflag.ensure(static_cast<size_t>(N) + 1, s);
-    int32_t ncls[4];
+    cflag.ensure(static_cast<size_t>(N) * 4 + 4, s);
+    crank.ensure(static_cast<size_t>(N) * 4 + 4, s);
+    g.scan_tmp.ensure(scan_tmp_elems(N), s);
     for (int k = 0; k < 4; ++k) {
-        hipLaunchKernelGGL(k_class_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, cnt.p, N, k, cflag.p);
+        hipLaunchKernelGGL(k_class_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, cnt.p, N, k,
+                           cflag.p + static_cast<int64_t>(k) * (N + 1));
         AHR_LAUNCHED("k_class_flags");
-        crank.ensure(static_cast<size_t>(N) + 1, s);
-        g.scan_tmp.ensure(scan_tmp_elems(N), s);
-        scan_i32_to_i32(cflag.p, crank.p, N, g.scan_tmp.p, s);
-        ncls[k] = read_scalar(crank.p + N, s);
-        list_rows(cflag.p, crank.p, N, lists.p + static_cast<int64_t>(k) * N, s);
+        scan_i32_to_i32(cflag.p + static_cast<int64_t>(k) * (N + 1), crank.p + static_cast<int64_t>(k) * (N + 1), N,
+                        g.scan_tmp.p, s);
     }
+    int32_t ncls[4];
+    read_scalars({crank.p + N, crank.p + (N + 1) + N, crank.p + 2 * static_cast<int64_t>(N + 1) + N,
+                  crank.p + 3 * static_cast<int64_t>(N + 1) + N},
+                 ncls, s);
+    for (int k = 0; k < 4; ++k)
+        list_rows(cflag.p + static_cast<int64_t>(k) * (N + 1), crank.p + static_cast<int64_t>(k) * (N + 1), N,
+                  lists.p + static_cast<int64_t>(k) * N, s);
     cflag.release(s);
     crank.release(s);
     scol.ensure(static_cast<size_t>(nnz_dup) + 1, s);
@@ -524,8 +535,7 @@ void build_netlist(Graph& g, hipStream_t s) {
 
     // final CSR
     g.net_rp.ensure(static_cast<size_t>(N) + 1, s);
-    scan_i32_to_i32(ucnt.p, g.net_rp.p, N, g.scan_tmp.p, s);
-    g.nnz_net = read_scalar(g.net_rp.p + N, s);
+    g.nnz_net = static_cast<int32_t>(scan_i32_checked(ucnt.p, g.net_rp.p, N, g.scan_tmp.p, s));
     g.net_col.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.net_q.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.qdeg.ensure(static_cast<size_t>(N) + 1, s);
