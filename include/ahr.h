@@ -214,6 +214,63 @@ ahr_status ahr_refine(ahr_graph* gr, const ahr_filter_spec* spec, const float* g
 ahr_status ahr_hpwl(const ahr_graph* gr, const float* g, int32_t ncols, double* out,
                     void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the filter (a project addition; the paper has no
+ * learned component).  It approximates the polynomial filter of `spec` from
+ * three powers of the same operator: for every instance row i and column c,
+ *   h_j = (T^j X)[i,c] (j = 1, 2, 3, unpinned), m_c / s_c = mean / standard
+ *   deviation of h_3 over movable rows,
+ *   f = [(h1-h3)/s_c, (h2-h3)/s_c, (h3-m_c)/s_c, log1p(d_i), hsum_i/d_i]
+ *   (d_i the absolute degree, hsum_i the signed sum of the row's hint weights),
+ *   o = w3 . relu(W2 relu(W1 f + b1) + b2) + b3,
+ *   y = beta[0] h1 + beta[1] h2 + beta[2] h3 + s_c o; fixed rows keep their input.
+ * The network is evaluated with bfloat16 operands (features, weights, hidden
+ * activations; round to nearest even) and float32 accumulation on the matrix
+ * cores.  Parameters are one float32 device vector of AHR_MLP_NPARAM values:
+ * W1[64][8] (features 5..7 unused), b1[64], W2[64][64], b2[64], w3[64], b3.
+ * ------------------------------------------------------------------------ */
+#define AHR_MLP_HIDDEN 64
+#define AHR_MLP_FEATURES 5
+#define AHR_MLP_FEATURE_STRIDE 8
+#define AHR_MLP_NPARAM 4801
+
+typedef struct ahr_mlp {
+    const float* params;        /* device [AHR_MLP_NPARAM] */
+    float beta[3];              /* weights of h1, h2, h3 */
+    int32_t validated;          /* 0: the model missed its validation bound; the plain filter runs */
+} ahr_mlp;
+
+/* The learned filter: same operator normalisation as ahr_filter (sigma,
+ * lambda from `spec`), three hops, features, MLP.  If model->validated is 0
+ * the plain ahr_filter(spec) runs instead and *used_fallback (host, may be
+ * NULL) is set to 1, else 0.  in/out [n_inst][ncols], no overlap. */
+ahr_status ahr_filter_learned(ahr_graph* gr, const ahr_filter_spec* spec, const ahr_mlp* model,
+                              const float* in, float* out, int32_t ncols, int32_t* used_fallback,
+                              void* stream);
+
+/* Training data of the surrogate: for the signal `in` ([n_inst][ncols]),
+ * writes feats [n_inst*ncols][AHR_MLP_FEATURE_STRIDE] (instance order, row
+ * i*ncols + c), hops [3][n_inst][ncols] (h1, h2, h3) and stats [2][ncols]
+ * (m_c, s_c).  Any output may be NULL. */
+ahr_status ahr_filter_features(ahr_graph* gr, const ahr_filter_spec* spec, const float* in, int32_t ncols,
+                               float* feats, float* hops, float* stats, void* stream);
+
+/* o[k] = MLP(feats[k]) for n feature rows (stride AHR_MLP_FEATURE_STRIDE),
+ * matrix-core evaluation as above. */
+ahr_status ahr_mlp_forward(const float* params, const float* feats, int64_t n, float* o, void* stream);
+
+/* Training: *loss (device double, may be NULL) = mean_k (MLP(feats[k]) -
+ * target[k])^2 and grad (device [AHR_MLP_NPARAM]) its gradient, float32
+ * forward with the inference's bfloat16 rounding points, straight-through
+ * gradients, fixed-order (deterministic) reductions. */
+ahr_status ahr_mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n,
+                             float* grad, double* loss, void* stream);
+
+/* One Adam step (step >= 1) on params with moments m, v (all device
+ * [AHR_MLP_NPARAM]). */
+ahr_status ahr_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr,
+                        float beta1, float beta2, float eps, void* stream);
+
 /* Return the device memory that freed graphs left in the library's cache
  * to the driver (graph builds reuse cached blocks).  Synchronises on the
  * frees still in flight. */
@@ -236,6 +293,8 @@ typedef struct ahr_profile {
     double build_ms, hints_ms, norm_ms, expand_ms, hop_ms, relax_ms, hpwl_ms;
     int64_t build_calls, hints_calls, norm_calls, expand_calls, hop_launches, relax_calls, hpwl_calls;
     double hop_bytes;           /* algorithmic bytes of every timed hop launch (see ahr_filter) */
+    double mlp_ms;              /* learned-filter MLP kernel */
+    int64_t mlp_calls;
 } ahr_profile;
 
 /* Turn event timing on (1) or off (0) for subsequent calls.  Adds two event

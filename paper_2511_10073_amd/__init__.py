@@ -68,7 +68,15 @@ class _Profile(ctypes.Structure):
                                                  "relax_ms", "hpwl_ms")]
                 + [(n, ctypes.c_int64) for n in ("build_calls", "hints_calls", "norm_calls", "expand_calls",
                                                   "hop_launches", "relax_calls", "hpwl_calls")]
-                + [("hop_bytes", ctypes.c_double)])
+                + [("hop_bytes", ctypes.c_double), ("mlp_ms", ctypes.c_double), ("mlp_calls", ctypes.c_int64)])
+
+
+class _Mlp(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("beta", ctypes.c_float * 3), ("validated", ctypes.c_int32)]
+
+
+MLP_NPARAM = 4801
+MLP_FEATURE_STRIDE = 8
 
 
 _lib = None
@@ -93,6 +101,12 @@ def load() -> ctypes.CDLL:
         "ahr_filter": [vp, ctypes.POINTER(_FilterSpec), vp, vp, i32, vp],
         "ahr_refine": [vp, ctypes.POINTER(_FilterSpec), vp, i32, i32, ctypes.c_float, vp, vp],
         "ahr_hpwl": [vp, vp, i32, vp, vp],
+        "ahr_filter_learned": [vp, ctypes.POINTER(_FilterSpec), ctypes.POINTER(_Mlp), vp, vp, i32,
+                               ctypes.POINTER(i32), vp],
+        "ahr_filter_features": [vp, ctypes.POINTER(_FilterSpec), vp, i32, vp, vp, vp, vp],
+        "ahr_mlp_forward": [vp, vp, ctypes.c_int64, vp, vp],
+        "ahr_mlp_loss_grad": [vp, vp, vp, ctypes.c_int64, vp, vp, vp],
+        "ahr_mlp_adam": [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -147,6 +161,45 @@ def profile_read(reset: bool = True) -> dict:
     p = _Profile()
     _check(load().ahr_profile_read(ctypes.byref(p), 1 if reset else 0))
     return {n: getattr(p, n) for n, _ in _Profile._fields_}
+
+
+def mlp_forward(params, feats, out=None, stream=None):
+    """o = MLP(feats) for feature rows feats [n, 8] (matrix-core evaluation)."""
+    n = feats.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=feats.device)
+    _check(load().ahr_mlp_forward(_ptr(params), _ptr(feats), n, _ptr(out), _stream(stream)))
+    return out
+
+
+def mlp_loss_grad(params, feats, target, grad=None, loss=None, stream=None):
+    """(grad, loss) of mean (MLP(feats) - target)^2; both stay on the device."""
+    n = feats.shape[0]
+    if grad is None:
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=params.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=params.device)
+    _check(load().ahr_mlp_loss_grad(_ptr(params), _ptr(feats), _ptr(target), n, _ptr(grad), _ptr(loss),
+                                    _stream(stream)))
+    return grad, loss
+
+
+def mlp_adam(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().ahr_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), step, lr, beta1, beta2, eps,
+                               _stream(stream)))
+
+
+class Mlp:
+    """A learned-filter model: float32 parameters on the device, the linear
+    weights beta of the three hops, and whether it met its validation bound."""
+
+    def __init__(self, params, beta=(0.0, 0.0, 1.0), validated=True):
+        self.params = params
+        self.beta = tuple(float(b) for b in beta)
+        self.validated = bool(validated)
+
+    def c(self):
+        return _Mlp(self.params.data_ptr(), (ctypes.c_float * 3)(*self.beta), 1 if self.validated else 0)
 
 
 class Netlist:
@@ -243,6 +296,26 @@ class Graph:
         _check(load().ahr_refine(self.h, ctypes.byref(spec), _ptr(g0), g0.shape[1], T_hint, gamma, _ptr(out),
                                  _stream(stream)))
         return out
+
+    def filter_learned(self, spec, model, x, out=None, stream=None):
+        """(out, used_fallback) of the learned filter."""
+        if out is None:
+            out = torch.empty_like(x)
+        fb = ctypes.c_int32(-1)
+        mc = model.c()
+        _check(load().ahr_filter_learned(self.h, ctypes.byref(spec), ctypes.byref(mc), _ptr(x), _ptr(out),
+                                         x.shape[1], ctypes.byref(fb), _stream(stream)))
+        return out, bool(fb.value)
+
+    def features(self, spec, x, stream=None):
+        """(feats [n*C, 8], hops [3, n, C], stats [2, C]) of the surrogate for signal x."""
+        n, C = x.shape
+        feats = torch.empty((n * C, MLP_FEATURE_STRIDE), dtype=torch.float32, device=x.device)
+        hops = torch.empty((3, n, C), dtype=torch.float32, device=x.device)
+        stats = torch.empty((2, C), dtype=torch.float32, device=x.device)
+        _check(load().ahr_filter_features(self.h, ctypes.byref(spec), _ptr(x), C, _ptr(feats), _ptr(hops),
+                                          _ptr(stats), _stream(stream)))
+        return feats, hops, stats
 
     def hpwl(self, g, out=None, stream=None):
         if out is None:

@@ -78,7 +78,8 @@ void read_scalars(const std::vector<const int32_t*>& src, int32_t* host, hipStre
 
 // ---------------------------------------------------------------- profiling
 
-enum Stage { kStageBuild, kStageHints, kStageNorm, kStageExpand, kStageHop, kStageRelax, kStageHpwl, kStageCount };
+enum Stage { kStageBuild, kStageHints, kStageNorm, kStageExpand, kStageHop, kStageRelax, kStageHpwl, kStageMlp,
+             kStageCount };
 
 bool profiling();
 
@@ -155,6 +156,7 @@ struct Graph {
     // operator (per hint version and sigma), rows in execution order
     DevBuf<double> deg;           // [n_tot]
     DevBuf<float> scale;          // [n_tot]
+    DevBuf<float> hsum;           // [n_tot] signed sum of the row's hint weights
     DevBuf<double> lam;           // [1] lambda_up
     double lam_host = 0.0;
     int32_t norm_version = -1;
@@ -176,6 +178,7 @@ struct Graph {
 
     // filter work buffers
     DevBuf<float> z0, z1, acc;    // [n_tot * C]
+    DevBuf<float> zh[3];          // [n_tot * C] hops 1..3 of the learned path (scaled coordinates)
     DevBuf<float> ga, gb, gt;     // [n_inst * C] refinement rounds
 
     // scratch
@@ -206,8 +209,18 @@ void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* o
                 int32_t ncols, hipStream_t s);
 void relax(Graph& g, const float* gcur, const float* gt, float* gnext, int32_t ncols,
            float gamma, hipStream_t s);
+// normalise + the unpinned chain T X, T^2 X, T^3 X into g.zh (scaled coordinates)
+void run_hops(Graph& g, const ahr_filter_spec& spec, const float* in, int32_t ncols, hipStream_t s);
 // hpwl.hip
 void run_hpwl(const Graph& g, const float* pos, int32_t ncols, double* out, hipStream_t s);
+// mlp.hip
+void run_learned(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[3], const float* in,
+                 float* out, int32_t ncols, float* feats, float* hops, float* stats, hipStream_t s);
+void mlp_forward(const float* params, const float* feats, int64_t n, float* o, hipStream_t s);
+void mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n, float* grad,
+                   double* loss, hipStream_t s);
+void mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr, float b1, float b2,
+              float eps, hipStream_t s);
 
 // Rows with more entries than kLongRow are summed by whole workgroups, in
 // chunks of kChunk entries; shorter rows by a few lanes each.

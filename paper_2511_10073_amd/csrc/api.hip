@@ -34,6 +34,8 @@ Graph::~Graph() {
     macro_rect.release(s);
     deg.release(s);
     scale.release(s);
+    hsum.release(s);
+    for (auto& z : zh) z.release(s);
     lam.release(s);
     partial.release(s);
     z0.release(s);
@@ -309,6 +311,83 @@ ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0
             ahr::relax(*gr, cur, gr->gt.p, next, ncols, gamma, s);
             cur = next;
         }
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_filter_learned(ahr_graph* h, const ahr_filter_spec* spec, const ahr_mlp* model, const float* in,
+                              float* out, int32_t ncols, int32_t* used_fallback, void* stream) {
+    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+    ahr_status st;
+    if ((st = check_spec(spec)) != AHR_OK) return st;
+    if (!model || !model->params) return fail(AHR_EINVAL, "model is NULL");
+    if (!in || !out) return fail(AHR_EINVAL, "in/out is NULL");
+    if (!ncols_ok(ncols)) return fail(AHR_EINVAL, "ncols must be 1, 2, 4 or 8");
+    auto* gr = reinterpret_cast<ahr::Graph*>(h);
+    if (!gr->has_hints) return fail(AHR_EINVAL, "graph has no hints yet: build with a placement or update_hints");
+    size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
+    if (overlap(in, bytes, out, bytes)) return fail(AHR_EINVAL, "in and out overlap");
+    return guarded([&]() -> ahr_status {
+        hipStream_t s = as_stream(stream);
+        if (!model->validated) {
+            ahr::run_filter(*gr, *spec, in, out, ncols, s);
+            if (used_fallback) *used_fallback = 1;
+            return AHR_OK;
+        }
+        ahr::run_learned(*gr, *spec, model->params, model->beta, in, out, ncols, nullptr, nullptr, nullptr, s);
+        if (used_fallback) *used_fallback = 0;
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_filter_features(ahr_graph* h, const ahr_filter_spec* spec, const float* in, int32_t ncols,
+                               float* feats, float* hops, float* stats, void* stream) {
+    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+    ahr_status st;
+    if ((st = check_spec(spec)) != AHR_OK) return st;
+    if (!in) return fail(AHR_EINVAL, "in is NULL");
+    if (!ncols_ok(ncols)) return fail(AHR_EINVAL, "ncols must be 1, 2, 4 or 8");
+    auto* gr = reinterpret_cast<ahr::Graph*>(h);
+    if (!gr->has_hints) return fail(AHR_EINVAL, "graph has no hints yet: build with a placement or update_hints");
+    return guarded([&]() -> ahr_status {
+        static const float zero_beta[3] = {0.f, 0.f, 0.f};
+        ahr::DevBuf<float> p;
+        hipStream_t s = as_stream(stream);
+        p.ensure(AHR_MLP_NPARAM, s);
+        AHR_HIP(hipMemsetAsync(p.p, 0, AHR_MLP_NPARAM * sizeof(float), s));
+        ahr::run_learned(*gr, *spec, p.p, zero_beta, in, nullptr, ncols, feats, hops, stats, s);
+        p.release(s);
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_mlp_forward(const float* params, const float* feats, int64_t n, float* o, void* stream) {
+    if (!params || !o || (n > 0 && !feats)) return fail(AHR_EINVAL, "NULL argument");
+    if (n < 0) return fail(AHR_EINVAL, "n must be >= 0");
+    return guarded([&]() -> ahr_status {
+        ahr::mlp_forward(params, feats, n, o, as_stream(stream));
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n, float* grad,
+                             double* loss, void* stream) {
+    if (!params || !grad || (n > 0 && (!feats || !target))) return fail(AHR_EINVAL, "NULL argument");
+    if (n < 0) return fail(AHR_EINVAL, "n must be >= 0");
+    return guarded([&]() -> ahr_status {
+        ahr::mlp_loss_grad(params, feats, target, n, grad, loss, as_stream(stream));
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
+                        float beta2, float eps, void* stream) {
+    if (!params || !m || !v || !grad) return fail(AHR_EINVAL, "NULL argument");
+    if (step < 1) return fail(AHR_EINVAL, "step must be >= 1");
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(AHR_EINVAL, "bad Adam hyper-parameters");
+    return guarded([&]() -> ahr_status {
+        ahr::mlp_adam(params, m, v, grad, step, lr, beta1, beta2, eps, as_stream(stream));
         return AHR_OK;
     });
 }

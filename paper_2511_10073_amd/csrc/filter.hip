@@ -113,9 +113,13 @@ struct RowRef {
 
 // ---------------------------------------------------------------- degrees
 
+// Degree d_i = qdeg_i 2^-32 + sum_j |hint_ij| + sigma, scale s_i = d_i^-1/2,
+// and the signed sum of the row's hint weights (a feature of the learned
+// surrogate).
 template <int G>
 __global__ void __launch_bounds__(kBT) k_deg_short(int32_t n, RowRef m, const int64_t* __restrict__ qdeg, double sigma,
-                                                   double* __restrict__ deg, float* __restrict__ scale) {
+                                                   double* __restrict__ deg, float* __restrict__ scale,
+                                                   float* __restrict__ hsum) {
     int64_t t = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
     int64_t r = t / G;
     int l = static_cast<int>(t & (G - 1));
@@ -123,14 +127,22 @@ __global__ void __launch_bounds__(kBT) k_deg_short(int32_t n, RowRef m, const in
     int h0 = m.hint_rp[r], h1 = m.hint_rp[r + 1];
     int len = (m.net_rp[r + 1] - m.net_rp[r]) + (h1 - h0);
     if (len > kLongRow) return;
-    double a = 0;
-    for (int k = h0 + l; k < h1; k += G) a += fabs(static_cast<double>(bits_f(m.hint_ent[k].y)));
+    double a = 0, sg = 0;
+    for (int k = h0 + l; k < h1; k += G) {
+        double w = static_cast<double>(bits_f(m.hint_ent[k].y));
+        a += fabs(w);
+        sg += w;
+    }
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    for (int o = G / 2; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        sg += __shfl_xor(sg, o);
+    }
     if (l == 0) {
         double d = static_cast<double>(qdeg[r]) * 0x1p-32 + a + sigma;
         deg[r] = d;
         scale[r] = d > 0 ? static_cast<float>(1.0 / sqrt(d)) : 0.f;
+        hsum[r] = static_cast<float>(sg);
     }
 }
 
@@ -153,25 +165,37 @@ __global__ void __launch_bounds__(kBT) k_chunk_absdeg(RowRef m, const int32_t* _
     __shared__ double red[kBT / kWave];
     int r, li, k0, k1, n0, ln, h0;
     chunk_range(blockIdx.x, long_rows, chunk_row, chunk0, m, r, li, k0, k1, n0, ln, h0);
-    double a = 0;
+    double a = 0, sg = 0;
     for (int k = k0 + threadIdx.x; k < k1; k += kBT)
-        if (k >= ln) a += fabs(static_cast<double>(bits_f(m.hint_ent[h0 + k - ln].y)));
+        if (k >= ln) {
+            double w = static_cast<double>(bits_f(m.hint_ent[h0 + k - ln].y));
+            a += fabs(w);
+            sg += w;
+        }
     a = block_sum_f64<kBT>(a, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = a;
+    sg = block_sum_f64<kBT>(sg, red);
+    if (threadIdx.x == 0) {
+        partial[static_cast<int64_t>(blockIdx.x) * 8] = a;
+        partial[static_cast<int64_t>(blockIdx.x) * 8 + 1] = sg;
+    }
 }
 
 __global__ void k_long_deg_final(int32_t n_long, const int32_t* __restrict__ long_rows,
                                  const int32_t* __restrict__ chunk0, const double* __restrict__ partial,
                                  const int64_t* __restrict__ qdeg, double sigma, double* __restrict__ deg,
-                                 float* __restrict__ scale) {
+                                 float* __restrict__ scale, float* __restrict__ hsum) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_long) return;
     int r = long_rows[i];
-    double a = 0;
-    for (int c = chunk0[i]; c < chunk0[i + 1]; ++c) a += partial[c];
+    double a = 0, sg = 0;
+    for (int c = chunk0[i]; c < chunk0[i + 1]; ++c) {
+        a += partial[static_cast<int64_t>(c) * 8];
+        sg += partial[static_cast<int64_t>(c) * 8 + 1];
+    }
     double d = static_cast<double>(qdeg[r]) * 0x1p-32 + a + sigma;
     deg[r] = d;
     scale[r] = d > 0 ? static_cast<float>(1.0 / sqrt(d)) : 0.f;
+    hsum[r] = static_cast<float>(sg);
 }
 
 // ---------------------------------------------------------------- Gershgorin
@@ -252,7 +276,7 @@ __global__ void __launch_bounds__(kBT) k_chunk_gersh(RowRef m, const int32_t* __
         a += fabs(static_cast<double>(bits_f(e.y))) * static_cast<double>(scale[e.x]);
     }
     a = block_sum_f64<kBT>(a, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = a;
+    if (threadIdx.x == 0) partial[static_cast<int64_t>(blockIdx.x) * 8] = a;
 }
 
 __global__ void k_long_gersh_final(int32_t n_long, const int32_t* __restrict__ long_rows,
@@ -263,7 +287,7 @@ __global__ void k_long_gersh_final(int32_t n_long, const int32_t* __restrict__ l
     if (i >= n_long) return;
     int r = long_rows[i];
     double a = 0;
-    for (int c = chunk0[i]; c < chunk0[i + 1]; ++c) a += partial[c];
+    for (int c = chunk0[i]; c < chunk0[i + 1]; ++c) a += partial[static_cast<int64_t>(c) * 8];
     float s = scale[r];
     atomic_max_nonneg(lam, diag_abs(s, deg[r], sigma) + static_cast<double>(s) * a);
 }
@@ -660,6 +684,106 @@ void hop_dispatch(const HopArgs& a, int lanes, int32_t n_long_rows, hipStream_t 
 }
 
 template <int C>
+void expand_signal(Graph& g, const float* in, bool band0, float alpha0, hipStream_t s) {
+    const int64_t N = g.n_tot;
+    ExpandArgs e;
+    e.in = in;
+    e.perm = g.perm.p;
+    e.scale = g.scale.p;
+    e.z0 = g.z0.p;
+    e.acc = g.acc.p;
+    e.alpha0 = alpha0;
+    e.band0 = band0 ? 1 : 0;
+    e.n_inst = g.n_inst;
+    e.first_mpin = g.first_mpin;
+    e.first_star = g.first_star;
+    e.first_mvirt = g.first_mvirt;
+    e.first_bvirt = g.first_bvirt;
+    e.n_tot = g.n_tot;
+    e.mpin_owner = g.mpin_owner.p;
+    e.mpin_pin = g.mpin_pin.p;
+    e.pin_off = g.nl.pin_off;
+    e.star_net = g.star_net.p;
+    e.net_ptr = g.nl.net_ptr;
+    e.pin_node = g.nl.pin_node;
+    e.pin_node_x = g.pin_node_x.p;
+    e.macro_ids = g.macro_ids.p;
+    e.nbx = g.hp.nbx;
+    e.xl = g.nl.die[0];
+    e.yl = g.nl.die[1];
+    e.bw = (static_cast<double>(g.nl.die[2]) - static_cast<double>(g.nl.die[0])) / g.hp.nbx;
+    e.bh = (static_cast<double>(g.nl.die[3]) - static_cast<double>(g.nl.die[1])) / g.hp.nby;
+    ProfScope ps(kStageExpand, s);
+    hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(N, kBT)), dim3(kBT), 0, s, e);
+    AHR_LAUNCHED("k_expand");
+    if (g.n_star)
+        hipLaunchKernelGGL((k_expand_bigstar<C>), dim3(g.n_star), dim3(kBT), 0, s, e, g.n_star);
+    AHR_LAUNCHED("k_expand_bigstar");
+}
+
+HopArgs hop_args(Graph& g, const ahr_filter_spec& spec, const float* in, float* out) {
+    HopArgs h;
+    h.m = RowRef{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
+    h.perm = g.perm.p;
+    h.scale = g.scale.p;
+    h.lam = g.lam.p;
+    h.sigma = spec.sigma;
+    h.acc = g.acc.p;
+    h.gin = in;
+    h.out = out;
+    h.flags = g.nl.node_flags;
+    h.long_rows = g.long_rows.p;
+    h.chunk_row = g.chunk_row.p;
+    h.chunk0 = g.long_chunk0.p;
+    h.partial = g.partial.p;
+    h.alpha_sum = 0.f;
+    h.band = 0;
+    h.alpha = 0.f;
+    h.last = 0;
+    h.zin = nullptr;
+    h.zout = nullptr;
+    h.n_rows = 0;
+    h.n_chunk_blocks = 0;
+    return h;
+}
+
+// Algorithmic bytes of one hop launch: row pointers, (column, weight)
+// entries, one read of the gathered signal, the row writes, the band
+// accumulator.
+double hop_bytes(const Graph& g, const HopArgs& h, int C) {
+    const double R = h.n_rows;
+    const double E = h.n_rows < g.n_tot ? static_cast<double>(g.nnz_inst)
+                                        : static_cast<double>(g.nnz_net) + static_cast<double>(g.nnz_hint);
+    double acc_b = 0;
+    if (h.band == 1) acc_b = h.last ? 0 : 4.0 * C * R;
+    if (h.band == 2) acc_b = h.last ? 4.0 * C * R : 8.0 * C * R;
+    return 4.0 * (R + 1) + 8.0 * E + 4.0 * C * static_cast<double>(g.n_tot) + 4.0 * C * R + acc_b;
+}
+
+// The unpinned chain y_j = T^j X for j = 1..3 (scaled coordinates, into
+// g.zh[j-1]); the third hop only for the instance rows.
+template <int C>
+void hops_c(Graph& g, const ahr_filter_spec& spec, const float* in, int lanes, hipStream_t s) {
+    const int64_t N = g.n_tot;
+    g.z0.ensure(static_cast<size_t>(N) * C, s);
+    g.acc.ensure(static_cast<size_t>(N) * C, s);
+    for (auto& z : g.zh) z.ensure(static_cast<size_t>(N) * C, s);
+    expand_signal<C>(g, in, false, 0.f, s);
+    HopArgs h = hop_args(g, spec, in, nullptr);
+    const float* zin = g.z0.p;
+    for (int j = 0; j < 3; ++j) {
+        h.zin = zin;
+        h.zout = g.zh[j].p;
+        const bool inst_only = j == 2;
+        h.n_rows = inst_only ? g.n_inst : g.n_tot;
+        h.n_chunk_blocks = inst_only ? g.n_chunks_inst : g.n_chunks;
+        ProfScope ps(kStageHop, s, hop_bytes(g, h, C));
+        hop_dispatch<C>(h, lanes, inst_only ? g.n_long_inst : g.n_long, s);
+        zin = g.zh[j].p;
+    }
+}
+
+template <int C>
 void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s) {
     const int64_t N = g.n_tot;
     int kmax = 0;
@@ -691,56 +815,9 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
 
     bool b0;
     float a0 = alpha_at(0, b0);
-    ExpandArgs e;
-    e.in = in;
-    e.perm = g.perm.p;
-    e.scale = g.scale.p;
-    e.z0 = g.z0.p;
-    e.acc = g.acc.p;
-    e.alpha0 = a0;
-    e.band0 = b0 ? 1 : 0;
-    e.n_inst = g.n_inst;
-    e.first_mpin = g.first_mpin;
-    e.first_star = g.first_star;
-    e.first_mvirt = g.first_mvirt;
-    e.first_bvirt = g.first_bvirt;
-    e.n_tot = g.n_tot;
-    e.mpin_owner = g.mpin_owner.p;
-    e.mpin_pin = g.mpin_pin.p;
-    e.pin_off = g.nl.pin_off;
-    e.star_net = g.star_net.p;
-    e.net_ptr = g.nl.net_ptr;
-    e.pin_node = g.nl.pin_node;
-    e.pin_node_x = g.pin_node_x.p;
-    e.macro_ids = g.macro_ids.p;
-    e.nbx = g.hp.nbx;
-    e.xl = g.nl.die[0];
-    e.yl = g.nl.die[1];
-    e.bw = (static_cast<double>(g.nl.die[2]) - static_cast<double>(g.nl.die[0])) / g.hp.nbx;
-    e.bh = (static_cast<double>(g.nl.die[3]) - static_cast<double>(g.nl.die[1])) / g.hp.nby;
-    {
-        ProfScope ps(kStageExpand, s);
-        hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(N, kBT)), dim3(kBT), 0, s, e);
-        AHR_LAUNCHED("k_expand");
-        if (g.n_star)
-            hipLaunchKernelGGL((k_expand_bigstar<C>), dim3(g.n_star), dim3(kBT), 0, s, e, g.n_star);
-        AHR_LAUNCHED("k_expand_bigstar");
-    }
+    expand_signal<C>(g, in, b0, a0, s);
 
-    HopArgs h;
-    h.m = RowRef{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
-    h.perm = g.perm.p;
-    h.scale = g.scale.p;
-    h.lam = g.lam.p;
-    h.sigma = spec.sigma;
-    h.acc = g.acc.p;
-    h.gin = in;
-    h.out = out;
-    h.flags = g.nl.node_flags;
-    h.long_rows = g.long_rows.p;
-    h.chunk_row = g.chunk_row.p;
-    h.chunk0 = g.long_chunk0.p;
-    h.partial = g.partial.p;
+    HopArgs h = hop_args(g, spec, in, out);
     h.alpha_sum = alpha_sum;
     bool has_acc = b0;
     float* zin = g.z0.p;
@@ -756,16 +833,7 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
         h.n_rows = h.last ? g.n_inst : g.n_tot;
         h.n_chunk_blocks = h.last ? g.n_chunks_inst : g.n_chunks;
         {
-            // algorithmic bytes: row pointers, (column, weight) entries, one read
-            // of the gathered signal, the row writes, the band accumulator
-            const double R = h.n_rows;
-            const double E = h.last ? static_cast<double>(g.nnz_inst)
-                                    : static_cast<double>(g.nnz_net) + static_cast<double>(g.nnz_hint);
-            double acc_b = 0;
-            if (h.band == 1) acc_b = h.last ? 0 : 4.0 * C * R;
-            if (h.band == 2) acc_b = h.last ? 4.0 * C * R : 8.0 * C * R;
-            double bytes = 4.0 * (R + 1) + 8.0 * E + 4.0 * C * static_cast<double>(N) + 4.0 * C * R + acc_b;
-            ProfScope ps(kStageHop, s, bytes);
+            ProfScope ps(kStageHop, s, hop_bytes(g, h, C));
             hop_dispatch<C>(h, lanes, h.last ? g.n_long_inst : g.n_long, s);
         }
         has_acc = has_acc || isb;
@@ -825,17 +893,18 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     const double sigma = spec.sigma;
     g.deg.ensure(static_cast<size_t>(N) + 1, s);
     g.scale.ensure(static_cast<size_t>(N) + 1, s);
+    g.hsum.ensure(static_cast<size_t>(N) + 1, s);
     g.lam.ensure(1, s);
     constexpr int G = 4;
     hipLaunchKernelGGL(k_deg_short<G>, dim3(grid_for(static_cast<int64_t>(N) * G, kBT)), dim3(kBT), 0, s, N, m,
-                       g.xqdeg.p, sigma, g.deg.p, g.scale.p);
+                       g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
     AHR_LAUNCHED("k_deg_short");
     if (g.n_long) {
         hipLaunchKernelGGL(k_chunk_absdeg, dim3(g.n_chunks), dim3(kBT), 0, s, m, g.long_rows.p, g.chunk_row.p,
                            g.long_chunk0.p, g.partial.p);
         AHR_LAUNCHED("k_chunk_absdeg");
         hipLaunchKernelGGL(k_long_deg_final, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long, g.long_rows.p,
-                           g.long_chunk0.p, g.partial.p, g.xqdeg.p, sigma, g.deg.p, g.scale.p);
+                           g.long_chunk0.p, g.partial.p, g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
         AHR_LAUNCHED("k_long_deg_final");
     }
     if (spec.lambda_mode == AHR_LAMBDA_FIXED) {
@@ -873,6 +942,18 @@ void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* o
         case 2: filter_c<2>(g, spec, in, out, lanes, s); break;
         case 4: filter_c<4>(g, spec, in, out, lanes, s); break;
         case 8: filter_c<8>(g, spec, in, out, lanes, s); break;
+        default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
+    }
+}
+
+void run_hops(Graph& g, const ahr_filter_spec& spec, const float* in, int32_t ncols, hipStream_t s) {
+    normalise(g, spec, s);
+    int lanes = g_hop_lanes;
+    switch (ncols) {
+        case 1: hops_c<1>(g, spec, in, lanes, s); break;
+        case 2: hops_c<2>(g, spec, in, lanes, s); break;
+        case 4: hops_c<4>(g, spec, in, lanes, s); break;
+        case 8: hops_c<8>(g, spec, in, lanes, s); break;
         default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
     }
 }

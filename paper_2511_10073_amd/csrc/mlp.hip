@@ -1,0 +1,526 @@
+// Learned surrogate of the refinement filter (a project addition; the
+// paper has no learned component).  For every (instance row, column):
+//   h_j = (T^j X) for j = 1..3, m_c / s_c = mean / std of h_3 over movable rows,
+//   f = [(h1 - h3)/s_c, (h2 - h3)/s_c, (h3 - m_c)/s_c, log1p(d), hsum/d],
+//   o = w3 . relu(W2 relu(W1 f + b1) + b2) + b3,
+//   y = beta_1 h1 + beta_2 h2 + beta_3 h3 + s_c o   (fixed rows keep their input).
+//
+// Inference runs the three layers on the matrix cores: 16 samples per
+// wavefront, bfloat16 operands, float32 accumulation
+// (v_mfma_f32_16x16x16_bf16).  Every layer is computed transposed
+// (hidden x samples), so the accumulator layout of one layer -- lane l holds
+// rows 4(l/16)..4(l/16)+3 of column l%16 -- is exactly the B-operand layout of
+// the next, and no data moves between lanes.  Training runs forward and
+// backward in float32 with the same bfloat16 rounding points (weights,
+// features and hidden activations), gradients straight through the
+// rounding, accumulated per workgroup in a fixed order and reduced in a
+// fixed order.
+#include <algorithm>
+
+#include "ahr_internal.hpp"
+#include "device_util.hpp"
+
+namespace ahr {
+
+namespace {
+
+constexpr int kBT = 256;
+constexpr int kH = AHR_MLP_HIDDEN;      // 64
+constexpr int kFP = 8;                  // padded feature count
+constexpr int kNP = AHR_MLP_NPARAM;     // 4801
+constexpr int oW1 = 0, oB1 = kH * kFP, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH, oB3 = oW3 + kH;
+static_assert(oB3 + 1 == kNP, "parameter layout");
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// float32 -> bfloat16, round to nearest even
+__device__ __forceinline__ short bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<short>(u >> 16);
+}
+__device__ __forceinline__ float bf16_round(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+
+// ---------------------------------------------------------------- inference
+
+struct MlpRegs {
+    v4s w1[4];        // A tiles of W1 (hidden 16m.., features 0..15)
+    v4s w2[16];       // A tiles of W2 (out 16n.., in 16m..), index 4n + m
+    v4s w3[4];        // A tiles with w3 in row 0
+    float b1[16], b2[16];
+    float b3;
+};
+
+__device__ __forceinline__ void load_mlp(const float* __restrict__ P, MlpRegs& R) {
+    const int l = lane_id(), i = l & 15, g = l >> 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int k = 4 * g + j;
+            R.w1[m][j] = k < kFP ? bf16_bits(P[oW1 + (16 * m + i) * kFP + k]) : static_cast<short>(0);
+            R.w3[m][j] = i == 0 ? bf16_bits(P[oW3 + 16 * m + k]) : static_cast<short>(0);
+            R.b1[4 * m + j] = P[oB1 + 16 * m + k];
+            R.b2[4 * m + j] = P[oB2 + 16 * m + k];
+        }
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) R.w2[4 * n + m][j] = bf16_bits(P[oW2 + (16 * n + i) * kH + 16 * m + 4 * g + j]);
+    R.b3 = P[oB3];
+}
+
+// One tile of 16 samples.  f holds features 4(l/16)..4(l/16)+3 of sample
+// l%16; the result is valid in lanes 0..15 (sample = lane).
+__device__ __forceinline__ float mlp_tile(const MlpRegs& R, const float f[4]) {
+    v4s x;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = bf16_bits(f[j]);
+    v4s a1[4], a2[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[m], x, acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float v = acc[j] + R.b1[4 * m + j];
+            a1[m][j] = bf16_bits(v > 0.f ? v : 0.f);
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w2[4 * n + m], a1[m], acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float v = acc[j] + R.b2[4 * n + j];
+            a2[n][j] = bf16_bits(v > 0.f ? v : 0.f);
+        }
+    }
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w3[m], a2[m], acc, 0, 0, 0);
+    return acc[0] + R.b3;
+}
+
+// o[s] for a flat list of feature rows feats[n][8].
+__global__ void __launch_bounds__(kBT) k_mlp_forward(const float* __restrict__ P, const float* __restrict__ feats,
+                                                     int64_t n, float* __restrict__ o) {
+    MlpRegs R;
+    load_mlp(P, R);
+    const int l = lane_id(), g = l >> 4;
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBT / kWave);
+    const int64_t ntiles = (n + 15) / 16;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * (kBT / kWave) + wave_id(); t < ntiles; t += waves) {
+        const int64_t smp = t * 16 + (l & 15);
+        float f[4] = {0.f, 0.f, 0.f, 0.f};
+        if (smp < n && g < 2) {
+            float4 v = reinterpret_cast<const float4*>(feats + smp * kFP)[g];
+            f[0] = v.x, f[1] = v.y, f[2] = v.z, f[3] = v.w;
+        }
+        float r = mlp_tile(R, f);
+        if (l < 16 && smp < n) o[smp] = r;
+    }
+}
+
+// Signal value h of (execution row, column) from the scaled chain z.
+__device__ __forceinline__ float unscale(const float* z, int C, int r, int c, float s, const float* in,
+                                         const int32_t* perm) {
+    return s > 0.f ? z[static_cast<int64_t>(r) * C + c] / s : in[static_cast<int64_t>(perm[r]) * C + c];
+}
+
+struct LearnArgs {
+    const float* z1;
+    const float* z2;
+    const float* z3;
+    const float* scale;
+    const double* deg;
+    const float* hsum;
+    const float* stats;     // [2][C]: mean, std of h3
+    const float* in;
+    float* out;
+    float* feats;           // optional [n_inst * C][8], instance order
+    float* hops;            // optional [3][n_inst][C], instance order
+    const uint8_t* flags;
+    const int32_t* perm;
+    const float* params;
+    float beta0, beta1, beta2;
+    int32_t n_inst;
+    int write_out;
+};
+
+// Features of sample (execution row r, column c): lane group g computes
+// features 4g..4g+3.
+__device__ __forceinline__ void sample_features(const LearnArgs& a, int C, int r, int c, int g, float f[4], float h[3]) {
+    const float s = a.scale[r];
+    h[0] = unscale(a.z1, C, r, c, s, a.in, a.perm);
+    h[1] = unscale(a.z2, C, r, c, s, a.in, a.perm);
+    h[2] = unscale(a.z3, C, r, c, s, a.in, a.perm);
+    const float mc = a.stats[c], sc = a.stats[C + c];
+    const double d = a.deg[r];
+    if (g == 0) {
+        f[0] = (h[0] - h[2]) / sc;
+        f[1] = (h[1] - h[2]) / sc;
+        f[2] = (h[2] - mc) / sc;
+        f[3] = static_cast<float>(log1p(d));
+    } else if (g == 1) {
+        f[0] = d > 0 ? static_cast<float>(static_cast<double>(a.hsum[r]) / d) : 0.f;
+        f[1] = f[2] = f[3] = 0.f;
+    } else {
+        f[0] = f[1] = f[2] = f[3] = 0.f;
+    }
+}
+
+// The learned filter over the instance rows: 16 samples (16/C rows x C
+// columns) per wavefront tile.
+template <int C>
+__global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
+    MlpRegs R;
+    load_mlp(a.params, R);
+    const int l = lane_id(), g = l >> 4, sl = l & 15;
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBT / kWave);
+    const int64_t ntiles = (static_cast<int64_t>(a.n_inst) * C + 15) / 16;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * (kBT / kWave) + wave_id(); t < ntiles; t += waves) {
+        const int64_t smp = t * 16 + sl;
+        const int r = static_cast<int>(smp / C), c = static_cast<int>(smp % C);
+        const bool valid = r < a.n_inst;
+        float f[4] = {0.f, 0.f, 0.f, 0.f}, h[3] = {0.f, 0.f, 0.f};
+        if (valid) sample_features(a, C, r, c, g, f, h);
+        float o = mlp_tile(R, f);
+        if (l >= 16 || !valid) continue;
+        const int inst = a.perm[r];
+        const int64_t oc = static_cast<int64_t>(inst) * C + c;
+        if (a.feats) {
+            float* fp = a.feats + (static_cast<int64_t>(inst) * C + c) * kFP;
+            fp[0] = f[0], fp[1] = f[1], fp[2] = f[2], fp[3] = f[3];
+            fp[5] = fp[6] = fp[7] = 0.f;
+        }
+        if (a.hops) {
+            const int64_t nc = static_cast<int64_t>(a.n_inst) * C;
+            a.hops[oc] = h[0];
+            a.hops[nc + oc] = h[1];
+            a.hops[2 * nc + oc] = h[2];
+        }
+        if (a.write_out) {
+            float y = a.beta0 * h[0] + a.beta1 * h[1] + a.beta2 * h[2] + a.stats[C + c] * o;
+            a.out[oc] = (a.flags[inst] & AHR_NODE_FIXED) ? a.in[oc] : y;
+        }
+    }
+}
+
+// Feature 4 (lane group 1) of every sample, for the exported feature rows.
+template <int C>
+__global__ void k_feature4(LearnArgs a) {
+    int64_t smp = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (smp >= static_cast<int64_t>(a.n_inst) * C) return;
+    const int r = static_cast<int>(smp / C), c = static_cast<int>(smp % C);
+    float f[4], h[3];
+    sample_features(a, C, r, c, 1, f, h);
+    a.feats[(static_cast<int64_t>(a.perm[r]) * C + c) * kFP + 4] = f[0];
+}
+
+// Column statistics of h3 over movable instance rows (two passes, fixed
+// grid, float64 partials added in a fixed order).
+constexpr int kStatGrid = 512;
+
+template <int C>
+__global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, const float* __restrict__ mean, double* __restrict__ part) {
+    __shared__ double red[kBT / kWave];
+    double acc[C + 1];
+#pragma unroll
+    for (int c = 0; c <= C; ++c) acc[c] = 0;
+    for (int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x; r < a.n_inst;
+         r += static_cast<int64_t>(kStatGrid) * kBT) {
+        int inst = a.perm[r];
+        if (a.flags[inst] & AHR_NODE_FIXED) continue;
+        float s = a.scale[r];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            double h = unscale(a.z3, C, static_cast<int>(r), c, s, a.in, a.perm);
+            if (mean) {
+                double d = h - mean[c];
+                acc[c] += d * d;
+            } else {
+                acc[c] += h;
+            }
+        }
+        acc[C] += 1.0;
+    }
+#pragma unroll
+    for (int c = 0; c <= C; ++c) {
+        double v = block_sum_f64<kBT>(acc[c], red);
+        if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * (C + 1) + c] = v;
+    }
+}
+
+template <int C>
+__global__ void k_colstat_final(const double* __restrict__ part, float* __restrict__ stats, int second) {
+    int c = threadIdx.x;
+    if (c >= C) return;
+    double s = 0, n = 0;
+    for (int b = 0; b < kStatGrid; ++b) {
+        s += part[b * (C + 1) + c];
+        n += part[b * (C + 1) + C];
+    }
+    if (!second) {
+        stats[c] = n > 0 ? static_cast<float>(s / n) : 0.f;
+    } else {
+        double sd = n > 0 ? sqrt(s / n) : 0.0;
+        stats[C + c] = sd > 0 ? static_cast<float>(sd) : 1.f;
+    }
+}
+
+// ---------------------------------------------------------------- training
+
+constexpr int kTS = 32;           // samples per tile
+constexpr int kGradGrid = 240;    // workgroups (fixed: fixes the summation order)
+
+__global__ void __launch_bounds__(kBT) k_mlp_grad(const float* __restrict__ P, const float* __restrict__ feats,
+                                                  const float* __restrict__ target, int64_t n, float inv_n,
+                                                  float* __restrict__ part, double* __restrict__ loss_part) {
+    __shared__ float W1q[kH * kFP], W2q[kH * kH], w3q[kH], b1[kH], b2[kH];
+    __shared__ float X[kTS][kFP];
+    __shared__ float Z1[kTS][kH], A1[kTS][kH], Z2[kTS][kH], D2[kTS][kH];
+    __shared__ float dO[kTS];
+    __shared__ double red[kBT / kWave];
+    const int t = threadIdx.x;
+    for (int e = t; e < kH * kFP; e += kBT) W1q[e] = bf16_round(P[oW1 + e]);
+    for (int e = t; e < kH * kH; e += kBT) W2q[e] = bf16_round(P[oW2 + e]);
+    if (t < kH) {
+        w3q[t] = bf16_round(P[oW3 + t]);
+        b1[t] = P[oB1 + t];
+        b2[t] = P[oB2 + t];
+    }
+    const float b3 = P[oB3];
+    float gW2[16], gW1[2], gv = 0.f;     // gv: gb1 / gb2 / gw3 / gb3 entry of this thread
+    for (int q = 0; q < 16; ++q) gW2[q] = 0.f;
+    gW1[0] = gW1[1] = 0.f;
+    double loss = 0;
+    __syncthreads();
+    const int64_t ntiles = (n + kTS - 1) / kTS;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += kGradGrid) {
+        const int64_t s0 = tile * kTS;
+        {
+            int s = t / kFP, f = t % kFP;
+            int64_t smp = s0 + s;
+            X[s][f] = smp < n ? bf16_round(feats[smp * kFP + f]) : 0.f;
+        }
+        __syncthreads();
+        for (int q = 0; q < 8; ++q) {
+            int e = t + kBT * q, s = e / kH, h = e % kH;
+            float z = b1[h];
+            for (int f = 0; f < kFP; ++f) z = __fmaf_rn(X[s][f], W1q[h * kFP + f], z);
+            Z1[s][h] = z;
+            A1[s][h] = bf16_round(z > 0.f ? z : 0.f);
+        }
+        __syncthreads();
+        for (int q = 0; q < 8; ++q) {
+            int e = t + kBT * q, s = e / kH, h = e % kH;
+            float z = b2[h];
+            for (int k = 0; k < kH; ++k) z = __fmaf_rn(A1[s][k], W2q[h * kH + k], z);
+            Z2[s][h] = z;
+        }
+        __syncthreads();
+        if (t < kTS) {
+            int64_t smp = s0 + t;
+            float o = b3;
+            for (int h = 0; h < kH; ++h) {
+                float z = Z2[t][h];
+                o = __fmaf_rn(bf16_round(z > 0.f ? z : 0.f), w3q[h], o);
+            }
+            if (smp < n) {
+                float e = o - target[smp];
+                loss += static_cast<double>(e) * e;
+                dO[t] = 2.f * e * inv_n;
+            } else {
+                dO[t] = 0.f;
+            }
+        }
+        __syncthreads();
+        for (int q = 0; q < 8; ++q) {
+            int e = t + kBT * q, s = e / kH, h = e % kH;
+            D2[s][h] = Z2[s][h] > 0.f ? dO[s] * w3q[h] : 0.f;
+        }
+        __syncthreads();
+        for (int q = 0; q < 16; ++q) {
+            int e = t + kBT * q, h = e / kH, k = e % kH;
+            float a = gW2[q];
+            for (int s = 0; s < kTS; ++s) a = __fmaf_rn(D2[s][h], A1[s][k], a);
+            gW2[q] = a;
+        }
+        if (t >= kH && t < 2 * kH) {
+            for (int s = 0; s < kTS; ++s) gv += D2[s][t - kH];
+        } else if (t >= 2 * kH && t < 3 * kH) {
+            int h = t - 2 * kH;
+            for (int s = 0; s < kTS; ++s) {
+                float z = Z2[s][h];
+                gv = __fmaf_rn(dO[s], bf16_round(z > 0.f ? z : 0.f), gv);
+            }
+        } else if (t == 3 * kH) {
+            for (int s = 0; s < kTS; ++s) gv += dO[s];
+        }
+        __syncthreads();
+        // dz1 = (W2^T dz2) masked by z1 > 0, into Z2 (no longer needed)
+        for (int q = 0; q < 8; ++q) {
+            int e = t + kBT * q, s = e / kH, k = e % kH;
+            float a = 0.f;
+            for (int h = 0; h < kH; ++h) a = __fmaf_rn(D2[s][h], W2q[h * kH + k], a);
+            Z2[s][k] = Z1[s][k] > 0.f ? a : 0.f;
+        }
+        __syncthreads();
+        for (int q = 0; q < 2; ++q) {
+            int e = t + kBT * q, h = e / kFP, f = e % kFP;
+            float a = gW1[q];
+            for (int s = 0; s < kTS; ++s) a = __fmaf_rn(Z2[s][h], X[s][f], a);
+            gW1[q] = a;
+        }
+        if (t < kH)
+            for (int s = 0; s < kTS; ++s) gv += Z2[s][t];
+        __syncthreads();
+    }
+    float* pb = part + static_cast<int64_t>(blockIdx.x) * kNP;
+    for (int q = 0; q < 16; ++q) pb[oW2 + t + kBT * q] = gW2[q];
+    for (int q = 0; q < 2; ++q) pb[oW1 + t + kBT * q] = gW1[q];
+    if (t < kH) pb[oB1 + t] = gv;
+    else if (t < 2 * kH) pb[oB2 + t - kH] = gv;
+    else if (t < 3 * kH) pb[oW3 + t - 2 * kH] = gv;
+    else if (t == 3 * kH) pb[oB3] = gv;
+    double ls = block_sum_f64<kBT>(loss, red);
+    if (t == 0) loss_part[blockIdx.x] = ls;
+}
+
+__global__ void k_mlp_grad_final(const float* __restrict__ part, const double* __restrict__ loss_part, double inv_n,
+                                 float* __restrict__ grad, double* __restrict__ loss) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kNP) {
+        float a = 0.f;
+        for (int b = 0; b < kGradGrid; ++b) a += part[static_cast<int64_t>(b) * kNP + p];
+        grad[p] = a;
+    }
+    if (p == 0 && loss) {
+        double s = 0;
+        for (int b = 0; b < kGradGrid; ++b) s += loss_part[b];
+        *loss = s * inv_n;
+    }
+}
+
+__global__ void k_adam(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNP) return;
+    float gp = g[p];
+    float mp = b1 * m[p] + (1.f - b1) * gp;
+    float vp = b2 * v[p] + (1.f - b2) * gp * gp;
+    m[p] = mp;
+    v[p] = vp;
+    P[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + eps);
+}
+
+template <int C>
+void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[3], const float* in,
+               float* out, float* feats, float* hops, float* stats_out, hipStream_t s) {
+    run_hops(g, spec, in, C, s);
+    LearnArgs a;
+    a.z1 = g.zh[0].p;
+    a.z2 = g.zh[1].p;
+    a.z3 = g.zh[2].p;
+    a.scale = g.scale.p;
+    a.deg = g.deg.p;
+    a.hsum = g.hsum.p;
+    a.in = in;
+    a.out = out;
+    a.feats = feats;
+    a.hops = hops;
+    a.flags = g.nl.node_flags;
+    a.perm = g.perm.p;
+    a.params = params;
+    a.beta0 = beta[0];
+    a.beta1 = beta[1];
+    a.beta2 = beta[2];
+    a.n_inst = g.n_inst;
+    a.write_out = out != nullptr;
+    DevBuf<double> part;
+    DevBuf<float> stats;
+    part.ensure(static_cast<size_t>(kStatGrid) * (C + 1), s);
+    stats.ensure(2 * C, s);
+    a.stats = stats.p;
+    hipLaunchKernelGGL((k_colstat<C>), dim3(kStatGrid), dim3(kBT), 0, s, a, static_cast<const float*>(nullptr), part.p);
+    AHR_LAUNCHED("k_colstat");
+    hipLaunchKernelGGL((k_colstat_final<C>), dim3(1), dim3(64), 0, s, part.p, stats.p, 0);
+    AHR_LAUNCHED("k_colstat_final");
+    hipLaunchKernelGGL((k_colstat<C>), dim3(kStatGrid), dim3(kBT), 0, s, a, static_cast<const float*>(stats.p), part.p);
+    AHR_LAUNCHED("k_colstat");
+    hipLaunchKernelGGL((k_colstat_final<C>), dim3(1), dim3(64), 0, s, part.p, stats.p, 1);
+    AHR_LAUNCHED("k_colstat_final");
+    if (stats_out) AHR_HIP(hipMemcpyAsync(stats_out, stats.p, 2 * C * sizeof(float), hipMemcpyDeviceToDevice, s));
+    {
+        ProfScope ps(kStageMlp, s);
+        const int64_t ntiles = (static_cast<int64_t>(g.n_inst) * C + 15) / 16;
+        const int64_t blocks = std::min<int64_t>((ntiles + 3) / 4, 256 * 16);
+        hipLaunchKernelGGL((k_mlp_learned<C>), dim3(static_cast<unsigned>(blocks < 1 ? 1 : blocks)), dim3(kBT), 0, s,
+                           a);
+        AHR_LAUNCHED("k_mlp_learned");
+    }
+    if (feats) {
+        const int64_t ns = static_cast<int64_t>(g.n_inst) * C;
+        hipLaunchKernelGGL((k_feature4<C>), dim3(grid_for(ns, kBT)), dim3(kBT), 0, s, a);
+        AHR_LAUNCHED("k_feature4");
+    }
+    part.release(s);
+    stats.release(s);
+}
+
+}  // namespace
+
+void run_learned(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[3], const float* in,
+                 float* out, int32_t ncols, float* feats, float* hops, float* stats, hipStream_t s) {
+    switch (ncols) {
+        case 1: learned_c<1>(g, spec, params, beta, in, out, feats, hops, stats, s); break;
+        case 2: learned_c<2>(g, spec, params, beta, in, out, feats, hops, stats, s); break;
+        case 4: learned_c<4>(g, spec, params, beta, in, out, feats, hops, stats, s); break;
+        case 8: learned_c<8>(g, spec, params, beta, in, out, feats, hops, stats, s); break;
+        default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
+    }
+}
+
+void mlp_forward(const float* params, const float* feats, int64_t n, float* o, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t ntiles = (n + 15) / 16;
+    const int64_t blocks = std::min<int64_t>((ntiles + 3) / 4, 256 * 16);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s, params, feats, n, o);
+    AHR_LAUNCHED("k_mlp_forward");
+}
+
+void mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n, float* grad,
+                   double* loss, hipStream_t s) {
+    DevBuf<float> part;
+    DevBuf<double> lpart;
+    part.ensure(static_cast<size_t>(kGradGrid) * kNP, s);
+    lpart.ensure(kGradGrid, s);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(kGradGrid), dim3(kBT), 0, s, params, feats, target, n,
+                       n > 0 ? 1.f / static_cast<float>(n) : 0.f, part.p, lpart.p);
+    AHR_LAUNCHED("k_mlp_grad");
+    hipLaunchKernelGGL(k_mlp_grad_final, dim3(grid_for(kNP, kBT)), dim3(kBT), 0, s, part.p, lpart.p,
+                       n > 0 ? 1.0 / static_cast<double>(n) : 0.0, grad, loss);
+    AHR_LAUNCHED("k_mlp_grad_final");
+    part.release(s);
+    lpart.release(s);
+}
+
+void mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr, float b1, float b2,
+              float eps, hipStream_t s) {
+    const float c1 = 1.f - powf(b1, static_cast<float>(step));
+    const float c2 = 1.f - powf(b2, static_cast<float>(step));
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(kNP, kBT)), dim3(kBT), 0, s, params, m, v, grad, lr, b1, b2, eps, c1, c2);
+    AHR_LAUNCHED("k_adam");
+}
+
+}  // namespace ahr

@@ -96,6 +96,8 @@ ahr_status ahr_profile_read(ahr_profile* out, int32_t reset) {
             *cnt[k] = ahr::g_count[k];
         }
         out->hop_bytes = ahr::g_bytes[ahr::kStageHop];
+        out->mlp_ms = ahr::g_ms[ahr::kStageMlp];
+        out->mlp_calls = ahr::g_count[ahr::kStageMlp];
         if (reset) {
             for (int k = 0; k < ahr::kStageCount; ++k) ahr::g_ms[k] = 0, ahr::g_count[k] = 0, ahr::g_bytes[k] = 0;
         }
