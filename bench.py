@@ -10,7 +10,9 @@ synthetic and resident in HBM before timing starts.
 
 Prints one JSON line.  The roofline entry is for the dominant kernel (the
 SpMM hop): algorithmic bytes per launch over its average duration, measured
-with HIP events recorded on the stream the hops run on.
+with HIP events recorded on the stream the hops run on.  The line also holds
+the plain filter and its learned surrogate side by side on the same graph
+(device time per call, hop traffic, relative error, HPWL).
 """
 from __future__ import annotations
 
@@ -24,6 +26,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MODEL = os.path.join(ROOT, "paper_2511_10073_amd", "weights", "surrogate_bank248.json")
+FILTER_SRC = os.path.join(ROOT, "paper_2511_10073_amd", "csrc", "filter.hip")
+
+# HBM bytes per k_hop launch on large-2.2M from two rocprofv3 counter passes
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
+# copy; valid only for the filter source they were taken with.
+HOP_TRAFFIC = {"workload": "large-2.2M",
+               "filter_sha256": "561b01d7cf4d0cecd0dc8f6de9923fc4debe594607763810033b4fad54bcef72",
+               "bytes_per_launch": 1674150768,
+               "source": "profiles/k_hop_large-2.2M_hbm_traffic.md"}
+
+
+def hop_traffic(workload):
+    import hashlib
+    with open(FILTER_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if workload != HOP_TRAFFIC["workload"] or sha != HOP_TRAFFIC["filter_sha256"]:
+        return None
+    return HOP_TRAFFIC["bytes_per_launch"]
+
 
 WORKLOADS = {
     # name: (netlist config attribute, bins, filter bank)
@@ -42,6 +64,7 @@ def parse():
     ap.add_argument("--rounds", type=int, default=3, help="T_hint")
     ap.add_argument("--gamma", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
@@ -77,6 +100,62 @@ def cpu_baseline(nl, bins, spec_o, rounds):
             "sample": (f"one refinement round (graph build {t1 - t0:.1f} s + order-8 bank filter "
                        f"{t2 - t1:.1f} s) and HPWL ({t3 - t2:.1f} s) of the same workload, "
                        f"round extrapolated to T_hint={rounds}; numpy/scipy, single thread")}
+
+
+def learned_vs_plain(A, torch, np, nl, net, params, spec, g0, reps):
+    """The plain order-8 bank filter and its learned surrogate on the graph
+    of the initial placement: device time of one filter call each (HIP
+    events on the launch stream, mean of `reps` calls), the bytes their hops
+    move, the learned output's centred relative error against the plain one
+    over the movable instance rows, and the HPWL of both outputs."""
+    if not os.path.exists(MODEL):
+        return {"error": f"no trained model at {os.path.relpath(MODEL, ROOT)}"}
+    model = A.Mlp.load(MODEL)
+    gr = A.Graph(net, params, g0)
+    y = torch.empty_like(g0)
+    yl = torch.empty_like(g0)
+    fb = []
+
+    def plain():
+        gr.filter(spec, g0, out=y)
+
+    def learned():
+        fb.append(gr.filter_learned(spec, model, g0, out=yl)[1])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        A.profile_read(reset=True)
+        A.profile_enable(True)
+        fn()
+        torch.cuda.synchronize()
+        A.profile_enable(False)
+        prof = A.profile_read(reset=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        return {"ms": round(ms, 4), "hop_launches": prof["hop_launches"], "hop_bytes": int(prof["hop_bytes"]),
+                "hop_gbs": round(prof["hop_bytes"] / (ms * 1e-3) / 1e9, 1), "mlp_ms": round(prof["mlp_ms"], 4)}
+
+    tp = timed(plain)
+    tl = timed(learned)
+    h_p = gr.hpwl(y).cpu().numpy()
+    h_l = gr.hpwl(yl).cpu().numpy()
+    gr.close()
+    mov = np.flatnonzero((nl["node_flags"][:int(nl["n_inst"])] & 1) == 0)
+    a = yl.cpu().numpy().astype(np.float64)[mov]
+    b = y.cpu().numpy().astype(np.float64)[mov]
+    rel = float(np.linalg.norm(a - b) / np.linalg.norm(b - b.mean(axis=0)))
+    return {"plain": tp, "learned": tl, "speedup": round(tp["ms"] / tl["ms"], 3), "rel_err": rel,
+            "hpwl_plain": [float(v) for v in h_p], "hpwl_learned": [float(v) for v in h_l],
+            "hpwl_delta": float(np.max(np.abs(h_l - h_p) / h_p)), "used_fallback": bool(fb[-1]),
+            "model": {"file": os.path.relpath(MODEL, ROOT), "validated": model.validated,
+                      "heldout_rel_err_mean": model.summary.get("rel_err_mean")},
+            "bounds": {"rel_err": 1e-3, "hpwl_delta": 2e-3}}
 
 
 def main():
@@ -163,13 +242,15 @@ def main():
                    "ncols": ncols, "T_hint": args.rounds, "gamma": args.gamma},
         "roofline": {"bound": "hbm", "kernel": "k_hop (SpMM hop)", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(hop_avg_ms * 1e3, 2),
+                     "traffic": hop_traffic(args.workload), "avg_launch_us": round(hop_avg_ms * 1e3, 2),
                      "algorithmic_bytes_per_launch": int(hop_bytes), "launches": prof["hop_launches"]},
         "stages_ms_per_step": per_step,
         "filter_phase_gbs": round(prof["hop_bytes"] / args.steps / (filt_ms * 1e-3) / 1e9, 1) if filt_ms else None,
         "hpwl": [float(v) for v in hp.cpu().numpy()],
         "generator_s": round(gen_s, 1),
     }
+    if not args.no_learned:
+        rec["learned_vs_plain"] = learned_vs_plain(A, torch, np, nl, net, params, spec, g0, reps=10)
     if not args.no_cpu_baseline:
         from oracle import ahr_oracle as O
         rec["cpu_baseline"] = cpu_baseline(nl, bins, O.FilterSpec(ks=ks, alphas=alphas), args.rounds)

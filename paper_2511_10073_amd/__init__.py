@@ -201,6 +201,19 @@ class Mlp:
     def c(self):
         return _Mlp(self.params.data_ptr(), (ctypes.c_float * 3)(*self.beta), 1 if self.validated else 0)
 
+    @classmethod
+    def load(cls, path, device="cuda"):
+        """A model written by the trainer (JSON; nothing in it is executed)."""
+        import json
+        with open(path) as f:
+            doc = json.load(f)
+        if doc.get("format") != "ahr-mlp-1" or int(doc["nparam"]) != MLP_NPARAM:
+            raise ValueError(f"{path}: not a model of this network shape")
+        p = torch.tensor(np.asarray(doc["params"], np.float32)).to(device)
+        m = cls(p, doc["beta"], doc["validated"])
+        m.summary = doc.get("summary", {})
+        return m
+
 
 class Netlist:
     """A netlist resident on the device (the arrays the C ABI points to)."""

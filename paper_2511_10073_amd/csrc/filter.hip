@@ -651,18 +651,25 @@ __global__ void k_relax(int32_t n_inst, const uint8_t* __restrict__ flags, const
     gn[i] = (flags[i / C] & AHR_NODE_FIXED) ? a : (1.0f - gamma) * a + gamma * gt[i];
 }
 
+// The profiled hop time brackets the k_hop launch alone (the chunk
+// partials' k_hop_long is not part of it), so that it matches a kernel trace
+// of k_hop; `bytes` are the algorithmic bytes of the whole hop.
 template <int C, int G>
-void launch_hop(const HopArgs& a, int32_t n_long_rows, hipStream_t s) {
+void launch_hop(const HopArgs& a, int32_t n_long_rows, double bytes, hipStream_t s) {
     constexpr int U = 32 / G > 0 ? (32 / G < 8 ? 32 / G : 8) : 1;   // entries per lane per batch
     int64_t tiles = grid_for(static_cast<int64_t>(a.n_rows) * G, kBT);
     tiles = (tiles + kXcds - 1) / kXcds * kXcds;                    // see xcd_tile
     int64_t blocks = a.n_chunk_blocks + tiles;
-    if (g_hop_nt)
-        hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), true>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), false>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s,
-                           a);
-    AHR_LAUNCHED("k_hop");
+    {
+        ProfScope ps(kStageHop, s, bytes);
+        if (g_hop_nt)
+            hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), true>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0,
+                               s, a);
+        else
+            hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), false>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0,
+                               s, a);
+        AHR_LAUNCHED("k_hop");
+    }
     if (n_long_rows > 0) {
         hipLaunchKernelGGL(k_hop_long<C>, dim3(grid_for(static_cast<int64_t>(n_long_rows) * kWave, kBT)), dim3(kBT),
                            0, s, a, n_long_rows);
@@ -671,15 +678,15 @@ void launch_hop(const HopArgs& a, int32_t n_long_rows, hipStream_t s) {
 }
 
 template <int C>
-void hop_dispatch(const HopArgs& a, int lanes, int32_t n_long_rows, hipStream_t s) {
+void hop_dispatch(const HopArgs& a, int lanes, int32_t n_long_rows, double bytes, hipStream_t s) {
     switch (lanes) {
-        case 1: launch_hop<C, 1>(a, n_long_rows, s); break;
-        case 2: launch_hop<C, 2>(a, n_long_rows, s); break;
-        case 4: launch_hop<C, 4>(a, n_long_rows, s); break;
-        case 8: launch_hop<C, 8>(a, n_long_rows, s); break;
-        case 16: launch_hop<C, 16>(a, n_long_rows, s); break;
-        case 32: launch_hop<C, 32>(a, n_long_rows, s); break;
-        default: launch_hop<C, 64>(a, n_long_rows, s); break;
+        case 1: launch_hop<C, 1>(a, n_long_rows, bytes, s); break;
+        case 2: launch_hop<C, 2>(a, n_long_rows, bytes, s); break;
+        case 4: launch_hop<C, 4>(a, n_long_rows, bytes, s); break;
+        case 8: launch_hop<C, 8>(a, n_long_rows, bytes, s); break;
+        case 16: launch_hop<C, 16>(a, n_long_rows, bytes, s); break;
+        case 32: launch_hop<C, 32>(a, n_long_rows, bytes, s); break;
+        default: launch_hop<C, 64>(a, n_long_rows, bytes, s); break;
     }
 }
 
@@ -777,8 +784,7 @@ void hops_c(Graph& g, const ahr_filter_spec& spec, const float* in, int lanes, h
         const bool inst_only = j == 2;
         h.n_rows = inst_only ? g.n_inst : g.n_tot;
         h.n_chunk_blocks = inst_only ? g.n_chunks_inst : g.n_chunks;
-        ProfScope ps(kStageHop, s, hop_bytes(g, h, C));
-        hop_dispatch<C>(h, lanes, inst_only ? g.n_long_inst : g.n_long, s);
+        hop_dispatch<C>(h, lanes, inst_only ? g.n_long_inst : g.n_long, hop_bytes(g, h, C), s);
         zin = g.zh[j].p;
     }
 }
@@ -832,10 +838,7 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
         h.alpha = aj;
         h.n_rows = h.last ? g.n_inst : g.n_tot;
         h.n_chunk_blocks = h.last ? g.n_chunks_inst : g.n_chunks;
-        {
-            ProfScope ps(kStageHop, s, hop_bytes(g, h, C));
-            hop_dispatch<C>(h, lanes, h.last ? g.n_long_inst : g.n_long, s);
-        }
+        hop_dispatch<C>(h, lanes, h.last ? g.n_long_inst : g.n_long, hop_bytes(g, h, C), s);
         has_acc = has_acc || isb;
         float* t = zin;
         zin = zout;

@@ -8,13 +8,17 @@ loop.
 Usage (the workload this was built for, 200 training and 20 held-out
 netlists of the mid-210k shape):
 
-    python -m paper_2511_10073_amd.train --train 200 --heldout 20 --out mlp.npz
+    python -m paper_2511_10073_amd.train --train 200 --heldout 20
+
+The result is written as JSON (parameters, beta, the validation flag and a
+summary of the held-out evaluation) and read back with `Mlp.load`.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -24,6 +28,7 @@ from . import (MLP_NPARAM, Graph, Mlp, Netlist, filter_spec, hint_params, mlp_ad
 
 HIDDEN = 64
 FEAT_PAD = 8
+DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate_bank248.json")
 W3_OFF = HIDDEN * FEAT_PAD + HIDDEN + HIDDEN * HIDDEN + HIDDEN
 B3_OFF = W3_OFF + HIDDEN
 
@@ -96,11 +101,12 @@ def train_mlp(F, R, steps=1000, lr=3e-3, seed=0, log=None):
     P = init_params(seed).to(F.device)
     m = torch.zeros_like(P)
     v = torch.zeros_like(P)
+    t0 = time.time()
     for k in range(1, steps + 1):
         g, loss = mlp_loss_grad(P, F, Rn)
         mlp_adam(P, m, v, g, k, lr * 0.5 * (1 + math.cos(math.pi * k / steps)))
-        if log and (k % 200 == 0 or k == 1):
-            log(f"step {k} loss {float(loss.cpu()):.4e}")
+        if log and (k % 100 == 0 or k == 1):
+            log(f"step {k} loss {float(loss.cpu()):.4e} ({time.time() - t0:.1f} s)")
     _, loss = mlp_loss_grad(P, F, Rn)
     p = P.cpu().numpy()
     p[W3_OFF:W3_OFF + HIDDEN] *= sigma
@@ -143,7 +149,7 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--rows", type=int, default=20000, help="movable rows sampled per training netlist")
     ap.add_argument("--tol", type=float, default=1e-3, help="validation bound on the mean held-out error")
-    ap.add_argument("--out", default="mlp.npz")
+    ap.add_argument("--out", default=DEFAULT_MODEL)
     args = ap.parse_args()
     spec = filter_spec((2, 4, 8), (0.2, 0.3, 0.5))
     params = hint_params(nbx=32, nby=32)
@@ -173,9 +179,19 @@ def main():
                    rel_err_mean=float(e.mean()), rel_err_max=float(e.max()),
                    rel_err_linear_mean=float(el.mean()), gain=float(el.mean() - e.mean()),
                    hpwl_delta_max=float(hd.max()), validated=validated, tol=args.tol)
-    np.savez(args.out, params=P.cpu().numpy(), beta=np.asarray(beta, np.float32), validated=validated,
-             summary=json.dumps(summary))
+    save_model(args.out, P, beta, validated, summary)
     print(json.dumps(summary), flush=True)
+
+
+def save_model(path, P, beta, validated, summary):
+    """Write a model as JSON: float32 parameters (exact decimal round trip),
+    beta, the validation flag and the training summary."""
+    p = P.cpu().numpy().astype(np.float32)
+    doc = dict(format="ahr-mlp-1", hidden=HIDDEN, feat_pad=FEAT_PAD, nparam=int(p.size),
+               params=[float(v) for v in p], beta=[float(np.float32(b)) for b in beta], validated=bool(validated),
+               summary=summary)
+    with open(path, "w") as f:
+        json.dump(doc, f)
 
 
 if __name__ == "__main__":

@@ -57,3 +57,19 @@ def test_invalid_arguments_fail_before_any_device_work():
     assert lib.ahr_filter(None, ctypes.byref(spec), 8, 16, 2, None) == A.EINVAL
     assert lib.ahr_hpwl(ctypes.c_void_p(8), 8, 3, 8, None) == A.EINVAL
     assert lib.ahr_refine(ctypes.c_void_p(8), ctypes.byref(spec), 8, 2, 1, 1.5, 16, None) == A.EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libahr.so not built")
+def test_profile_read_fills_every_field():
+    """With no stage recorded, reading the profile makes no device call and
+    sets every field of the struct, including the last stage's."""
+    import paper_2511_10073_amd as A
+    lib = A.load()
+    p = A._Profile()
+    for name, ty in A._Profile._fields_:
+        setattr(p, name, 7 if ty is ctypes.c_int64 else 7.0)
+    assert lib.ahr_profile_enable(0) == A.OK
+    assert lib.ahr_profile_read(ctypes.byref(p), 1) == A.OK
+    for name, _ in A._Profile._fields_:
+        assert getattr(p, name) == 0, name
+    assert lib.ahr_profile_read(None, 1) == A.EINVAL
