@@ -287,6 +287,67 @@ ahr_status ahr_memory_trim(void);
 ahr_status ahr_filter_tune(int32_t lanes_per_row, int32_t nontemporal);
 ahr_status ahr_filter_get_tune(int32_t* lanes_per_row, int32_t* nontemporal);
 
+/* ---------------------------------------------------------------------------
+ * Batched filter (a project addition; the paper filters one netlist at a
+ * time).  Many netlists of uneven size are built once (graph and area hints
+ * each, as ahr_graph_build) and laid out as one block-diagonal operator,
+ * each block with its own lambda_up; one ahr_batch_filter call then applies
+ * the filter bank of ahr_filter (Section V, eq. "refine-filter", banked as
+ * in Section IV eq. "GiFt filter") to all of them with one launch per
+ * power of T, captured once as a HIP graph and replayed.
+ *
+ * Signals are the members' instance rows concatenated in member order:
+ * member g's rows start at row sum_{h<g} nls[h].n_inst, row-major with
+ * ncols columns.  For the same lanes_per_row every member's output is
+ * bit-identical to ahr_filter on that member alone (each column's sums run
+ * in the same order for every column tile).
+ */
+typedef struct ahr_batch ahr_batch;    /* opaque; owns its device memory and member graphs */
+
+typedef struct ahr_batch_info {
+    int32_t n_graphs;
+    int32_t n_inst;             /* instance rows of all members */
+    int32_t n_tot;              /* rows of the batched operator */
+    int32_t n_long_rows;        /* rows summed by whole workgroups */
+    int64_t nnz_net, nnz_hint;  /* entries of the batched netlist and hint lists */
+    int32_t n_captured;         /* captured call shapes held (at most 16, least recently used dropped) */
+    int32_t reserved;
+} ahr_batch_info;
+
+/* Build n member graphs from host arrays nls[n], hps[n] (device pointers
+ * inside, owned by the caller and kept) and the concatenated placement pos
+ * (device, [sum n_inst][ncols], ncols in {2, 4, 8}; columns 0, 1 are used
+ * for the area hints).  Synchronises on `stream`.  EINVAL on a bad member
+ * (the message names it) before any device work; EUNSUPPORTED when the
+ * batch reaches 2^31 rows or list entries. */
+ahr_status ahr_batch_build(const ahr_netlist* nls, const ahr_hint_params* hps, int32_t n, const float* pos,
+                           int32_t ncols, void* stream, ahr_batch** out);
+ahr_status ahr_batch_get_info(const ahr_batch* b, ahr_batch_info* info);
+
+/* Filter every member: in, out device [sum n_inst][ncols], not
+ * overlapping; fixed rows of out = in.  use_graph = 1 replays (capturing on
+ * first use) the HIP graph of this (spec, ncols, launch shape, in, out);
+ * 0 launches the same kernels directly.  Asynchronous on `stream` once
+ * captured (capturing synchronises once).  The member operators are
+ * normalised for spec on first use and whenever sigma or lambda_mode
+ * change. */
+ahr_status ahr_batch_filter(ahr_batch* b, const ahr_filter_spec* spec, const float* in, float* out, int32_t ncols,
+                            int32_t use_graph, void* stream);
+
+/* Launch shape for ncols columns: lanes_per_row (power of two in [1, 64];
+ * 0 = the process-wide ahr_filter_tune value) and col_tile (columns per
+ * hop pass: a power of two dividing ncols; 0 = ncols). */
+ahr_status ahr_batch_set_config(ahr_batch* b, int32_t ncols, int32_t lanes_per_row, int32_t col_tile);
+ahr_status ahr_batch_get_config(const ahr_batch* b, int32_t ncols, int32_t* lanes_per_row, int32_t* col_tile);
+
+/* Time every (lanes_per_row in {1..32}, col_tile dividing ncols) on a
+ * library-owned input (captured, warmed, mean of 3 replays), keep the
+ * fastest as the batch's configuration for ncols and return it (each
+ * output pointer may be NULL).  Synchronises on `stream`. */
+ahr_status ahr_batch_autotune(ahr_batch* b, const ahr_filter_spec* spec, int32_t ncols, void* stream,
+                              int32_t* lanes_per_row, int32_t* col_tile, float* best_ms);
+void ahr_batch_destroy(ahr_batch* b);
+
 /* Per-stage device time, measured with HIP events recorded on the stream
  * each stage runs on (process-wide accumulators). */
 typedef struct ahr_profile {

@@ -63,6 +63,12 @@ class _GraphHost(ctypes.Structure):
         "net_row_ptr", "net_col", "net_q", "hint_row_ptr", "hint_col", "hint_val", "degree", "scale", "lambda_up")]
 
 
+class _BatchInfo(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int32) for n in ("n_graphs", "n_inst", "n_tot", "n_long_rows")]
+                + [(n, ctypes.c_int64) for n in ("nnz_net", "nnz_hint")]
+                + [(n, ctypes.c_int32) for n in ("n_captured", "reserved")])
+
+
 class _Profile(ctypes.Structure):
     _fields_ = ([(n, ctypes.c_double) for n in ("build_ms", "hints_ms", "norm_ms", "expand_ms", "hop_ms",
                                                  "relax_ms", "hpwl_ms")]
@@ -107,6 +113,13 @@ def load() -> ctypes.CDLL:
         "ahr_mlp_forward": [vp, vp, ctypes.c_int64, vp, vp],
         "ahr_mlp_loss_grad": [vp, vp, vp, ctypes.c_int64, vp, vp, vp],
         "ahr_mlp_adam": [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp],
+        "ahr_batch_build": [vp, vp, i32, vp, i32, vp, ctypes.POINTER(vp)],
+        "ahr_batch_get_info": [vp, ctypes.POINTER(_BatchInfo)],
+        "ahr_batch_filter": [vp, ctypes.POINTER(_FilterSpec), vp, vp, i32, i32, vp],
+        "ahr_batch_set_config": [vp, i32, i32, i32],
+        "ahr_batch_get_config": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "ahr_batch_autotune": [vp, ctypes.POINTER(_FilterSpec), i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                               ctypes.POINTER(ctypes.c_float)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -122,6 +135,8 @@ def load() -> ctypes.CDLL:
     lib.ahr_profile_read.restype = ctypes.c_int32
     lib.ahr_graph_destroy.argtypes = [vp]
     lib.ahr_graph_destroy.restype = None
+    lib.ahr_batch_destroy.argtypes = [vp]
+    lib.ahr_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -335,3 +350,64 @@ class Graph:
             out = torch.empty(g.shape[1] // 2, dtype=torch.float64, device=g.device)
         _check(load().ahr_hpwl(self.h, _ptr(g), g.shape[1], _ptr(out), _stream(stream)))
         return out
+
+
+class Batch:
+    """Owner of an ahr_batch handle: many netlists filtered as one
+    block-diagonal operator (ahr_batch_build ... ahr_batch_destroy).
+
+    `pos` is the members' placements concatenated in member order
+    ([sum n_inst, C] on the device); filter inputs and outputs use the same
+    layout.  `params` is one hint-parameter struct or one per member."""
+
+    def __init__(self, netlists, params, pos, stream=None):
+        lib = load()
+        self.netlists = list(netlists)
+        n = len(self.netlists)
+        if not isinstance(params, (list, tuple)):
+            params = [params] * n
+        self._nls = (_Netlist * n)(*[nl.c for nl in self.netlists])
+        self._hps = (_HintParams * n)(*params)
+        self.offsets = np.concatenate([[0], np.cumsum([nl.n_inst for nl in self.netlists])]).astype(np.int64)
+        h = ctypes.c_void_p()
+        _check(lib.ahr_batch_build(ctypes.cast(self._nls, ctypes.c_void_p), ctypes.cast(self._hps, ctypes.c_void_p),
+                                   n, _ptr(pos), pos.shape[1], _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().ahr_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = _BatchInfo()
+        _check(load().ahr_batch_get_info(self.h, ctypes.byref(i)))
+        return {n: getattr(i, n) for n, _ in _BatchInfo._fields_}
+
+    def filter(self, spec, x, out=None, use_graph=True, stream=None):
+        if out is None:
+            out = torch.empty_like(x)
+        _check(load().ahr_batch_filter(self.h, ctypes.byref(spec), _ptr(x), _ptr(out), x.shape[1],
+                                       1 if use_graph else 0, _stream(stream)))
+        return out
+
+    def set_config(self, ncols, lanes_per_row=0, col_tile=0):
+        _check(load().ahr_batch_set_config(self.h, ncols, lanes_per_row, col_tile))
+
+    def get_config(self, ncols):
+        lanes, ct = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().ahr_batch_get_config(self.h, ncols, ctypes.byref(lanes), ctypes.byref(ct)))
+        return lanes.value, ct.value
+
+    def autotune(self, spec, ncols, stream=None):
+        """(lanes_per_row, col_tile, ms) of the fastest launch shape, now the batch's configuration."""
+        lanes, ct, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        _check(load().ahr_batch_autotune(self.h, ctypes.byref(spec), ncols, _stream(stream), ctypes.byref(lanes),
+                                         ctypes.byref(ct), ctypes.byref(ms)))
+        return lanes.value, ct.value, ms.value

@@ -82,6 +82,9 @@ enum Stage { kStageBuild, kStageHints, kStageNorm, kStageExpand, kStageHop, kSta
              kStageCount };
 
 bool profiling();
+// While set (on this thread), ProfScope records nothing: used around HIP
+// graph capture, where event records would become graph nodes.
+void set_capture(bool on);
 
 // Records an event pair around its lifetime on stream s when profiling is on.
 class ProfScope {
@@ -226,5 +229,97 @@ void mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step
 // chunks of kChunk entries; shorter rows by a few lanes each.
 constexpr int kLongRow = 128;
 constexpr int kChunk = 2048;
+
+// ---------------------------------------------------------------- filter chain
+
+// Coefficients of one hop in scaled coordinates (Section V, eq.
+// "refine-filter" with T = I - L / lambda_up):
+//   z'_i = cr_i z_i + kr_i sum_j A_ij z_j,
+//   cr_i = 1 - (nz_i - sigma s_i^2) / lambda,  kr_i = s_i^2 / lambda,
+// evaluated in float64 and rounded once; T = I when lambda = 0.
+__host__ __device__ inline void hop_coef(float s, double lam, double sigma, float& cr, float& kr) {
+    cr = 1.f;
+    kr = 0.f;
+    if (lam > 0) {
+        double sd = s;
+        cr = static_cast<float>(1.0 - ((s > 0 ? 1.0 : 0.0) - sigma * sd * sd) / lam);
+        kr = static_cast<float>(sd * sd / lam);
+    }
+}
+
+// Signal expansion of one graph: instance rows from the caller's signal,
+// macro pin nodes (macro centre + pin offset), star nodes (mean of their
+// pins), macro and bin virtual nodes (macro and bin centres), scaled by s.
+// Local row r lands in z row  r < n_inst ? row_inst0 + r : row_aux0 + r - n_inst,
+// and z is stored as C/ct column tiles [tile][rows][ct] tile_stride apart.
+struct ExpandArgs {
+    const float* in;          // [n_inst][C], instance order (in_base + in_off in batched launches)
+    int64_t in_off;
+    const int32_t* perm;      // execution row -> instance
+    const float* scale;
+    float* z0;
+    float* acc;               // band at k = 0
+    float alpha0;
+    int32_t band0;
+    int32_t n_inst, first_mpin, first_star, first_mvirt, first_bvirt, n_tot;
+    int32_t row_inst0, row_aux0;
+    int32_t ct;
+    int64_t tile_stride;
+    const int32_t* mpin_owner;
+    const int32_t* mpin_pin;
+    const float* pin_off;
+    const int32_t* star_net;
+    const int32_t* net_ptr;
+    const int32_t* pin_node;
+    const int32_t* pin_node_x;
+    const int32_t* macro_ids;
+    int32_t nbx;
+    double xl, yl, bw, bh;
+};
+
+// The rows of one operator as the hop chain sees them (one graph, or many
+// graphs concatenated block-diagonally).
+struct ChainView {
+    const int32_t* net_rp;
+    const int2* net_ent;
+    const int32_t* hint_rp;
+    const int2* hint_ent;
+    const float* scale;
+    const float2* coef;       // per-row (cr, kr), or null: from *lam
+    const double* lam;
+    double sigma;
+    const uint8_t* flags;     // instance flags, instance order
+    const int32_t* perm;      // execution row -> instance
+    const int32_t* long_rows;
+    const int32_t* chunk_row;
+    const int32_t* chunk0;
+    double* partial;
+    int32_t n_tot, n_inst, n_long, n_long_inst, n_chunks, n_chunks_inst;
+    int64_t nnz_inst, nnz_all;
+    float* z0;
+    float* z1;
+    float* acc;
+};
+
+// Long rows (more than kLongRow entries) of an operator with rows
+// [0, N), instance rows first: their list, chunk offsets and chunk owners,
+// and a partial-sum buffer for C <= 8 columns.
+void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, DevBuf<int32_t>& long_rows,
+                 DevBuf<int32_t>& long_chunk0, DevBuf<int32_t>& chunk_row, DevBuf<double>& partial, int32_t& n_long,
+                 int32_t& n_long_inst, int32_t& n_chunks, int32_t& n_chunks_inst, int64_t& nnz_inst,
+                 DevBuf<int64_t>& scan_tmp, hipStream_t s);
+// The expansion descriptor of graph g (in, z0, acc, bands and the row
+// placement are filled in by the caller).
+ExpandArgs expand_args(const Graph& g);
+// Expansion of many graphs in two launches: descriptors d[0..ng) on the
+// device, blk0 / sblk0 the first workgroup of each graph (rows, big stars).
+void expand_batch(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, const int32_t* sblk0,
+                  int32_t n_star_blocks, int32_t ng, const float* in, int32_t ncols, hipStream_t s);
+// Hops 1..k_max of the filter bank on an expanded signal (z0 and, for a
+// band at k = 0, acc hold it), with lanes per short row and column tiles of
+// ct columns; the last hop writes out (instance order, fixed rows = in).
+void run_chain(const ChainView& v, const ahr_filter_spec& spec, const float* in, float* out, int32_t ncols,
+               int lanes, int ct, hipStream_t s);
+int32_t spec_kmax(const ahr_filter_spec& spec, float* alpha_sum);
 
 }  // namespace ahr

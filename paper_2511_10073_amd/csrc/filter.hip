@@ -296,27 +296,6 @@ __global__ void k_set_f64(double* p, double v) { *p = v; }
 
 // ---------------------------------------------------------------- signal
 
-struct ExpandArgs {
-    const float* in;          // [n_inst][C], instance order
-    const int32_t* perm;      // execution row -> instance
-    const float* scale;
-    float* z0;                // [n_tot][C]
-    float* acc;               // band at k = 0
-    float alpha0;
-    int band0;
-    int32_t n_inst, first_mpin, first_star, first_mvirt, first_bvirt, n_tot;
-    const int32_t* mpin_owner;
-    const int32_t* mpin_pin;
-    const float* pin_off;
-    const int32_t* star_net;
-    const int32_t* net_ptr;
-    const int32_t* pin_node;
-    const int32_t* pin_node_x;
-    const int32_t* macro_ids;
-    int nbx;
-    double xl, yl, bw, bh;
-};
-
 template <int C>
 __device__ __forceinline__ Vec<C> pin_value(const ExpandArgs& a, int p) {
     int v = a.pin_node[p];
@@ -332,26 +311,31 @@ __device__ __forceinline__ Vec<C> pin_value(const ExpandArgs& a, int p) {
 template <int C>
 __device__ __forceinline__ void put_z(const ExpandArgs& a, int r, Vec<C> x) {
     float s = a.scale[r];
-    Vec<C> z;
+    const int64_t row = r < a.n_inst ? static_cast<int64_t>(a.row_inst0) + r
+                                     : static_cast<int64_t>(a.row_aux0) + (r - a.n_inst);
+    Vec<C> z, t;
 #pragma unroll
-    for (int c = 0; c < C; ++c) z.v[c] = s * x.v[c];
-    vstore<C>(a.z0 + static_cast<int64_t>(r) * C, z);
-    if (a.band0) {
+    for (int c = 0; c < C; ++c) {
+        z.v[c] = s * x.v[c];
+        t.v[c] = z.v[c] * a.alpha0;
+    }
+    if (a.ct == C) {
+        vstore<C>(a.z0 + row * C, z);
+        if (a.band0) vstore<C>(a.acc + row * C, t);
+        return;
+    }
 #pragma unroll
-        for (int c = 0; c < C; ++c) z.v[c] *= a.alpha0;
-        vstore<C>(a.acc + static_cast<int64_t>(r) * C, z);
+    for (int c = 0; c < C; ++c) {
+        const int64_t i = (c / a.ct) * a.tile_stride + row * a.ct + (c % a.ct);
+        a.z0[i] = z.v[c];
+        if (a.band0) a.acc[i] = t.v[c];
     }
 }
 
-// Node values of the extended graph (macro pin node = macro centre + pin
-// offset, star node = mean of its pins, macro virtual node = macro centre,
-// bin virtual node = bin centre), scaled by s.  Stars with more than a
-// wave's worth of pins are left to k_expand_bigstar.
+// One row of the extended graph.  Stars with more than a wave's worth of
+// pins are left to expand_bigstar.
 template <int C>
-__global__ void __launch_bounds__(kBT) k_expand(ExpandArgs a) {
-    int64_t r64 = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
-    if (r64 >= a.n_tot) return;
-    int r = static_cast<int>(r64);
+__device__ __forceinline__ void expand_row(const ExpandArgs& a, int r) {
     Vec<C> x;
     if (r < a.n_inst) {
         x = vload<C>(a.in + static_cast<int64_t>(a.perm[r]) * C);
@@ -384,12 +368,11 @@ __global__ void __launch_bounds__(kBT) k_expand(ExpandArgs a) {
     put_z<C>(a, r, x);
 }
 
-// Mean over the pins of big star nets: one workgroup per star, lanes
-// stride the pins in float64, fixed reduction order.
+// Mean over the pins of big star k: one workgroup, lanes stride the pins
+// in float64, fixed reduction order.
 template <int C>
-__global__ void __launch_bounds__(kBT) k_expand_bigstar(ExpandArgs a, int32_t n_star) {
+__device__ __forceinline__ void expand_bigstar(const ExpandArgs& a, int k) {
     __shared__ double red[kBT / kWave];
-    int k = blockIdx.x;
     int e = a.star_net[k];
     int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
     if (p1 - p0 <= kWave) return;
@@ -407,11 +390,54 @@ __global__ void __launch_bounds__(kBT) k_expand_bigstar(ExpandArgs a, int32_t n_
     if (threadIdx.x == 0) put_z<C>(a, a.first_star + k, x);
 }
 
+template <int C>
+__global__ void __launch_bounds__(kBT) k_expand(ExpandArgs a) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    if (r < a.n_tot) expand_row<C>(a, static_cast<int>(r));
+}
+
+template <int C>
+__global__ void __launch_bounds__(kBT) k_expand_bigstar(ExpandArgs a, int32_t n_star) {
+    expand_bigstar<C>(a, blockIdx.x);
+}
+
+// Graph of workgroup b in a batched launch: the last g with first[g] <= b.
+__device__ __forceinline__ int owner_of(const int32_t* __restrict__ first, int32_t ng, int32_t b) {
+    int lo = 0, hi = ng;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int C>
+__global__ void __launch_bounds__(kBT) k_expand_batch(const ExpandArgs* __restrict__ d, const int32_t* __restrict__ blk0,
+                                                      int32_t ng, const float* __restrict__ in) {
+    const int g = owner_of(blk0, ng, blockIdx.x);
+    ExpandArgs a = d[g];
+    a.in = in + a.in_off;
+    int64_t r = static_cast<int64_t>(blockIdx.x - blk0[g]) * kBT + threadIdx.x;
+    if (r < a.n_tot) expand_row<C>(a, static_cast<int>(r));
+}
+
+template <int C>
+__global__ void __launch_bounds__(kBT) k_expand_bigstar_batch(const ExpandArgs* __restrict__ d,
+                                                              const int32_t* __restrict__ sblk0, int32_t ng,
+                                                              const float* __restrict__ in) {
+    const int g = owner_of(sblk0, ng, blockIdx.x);
+    ExpandArgs a = d[g];
+    a.in = in + a.in_off;
+    expand_bigstar<C>(a, blockIdx.x - sblk0[g]);
+}
+
 // ---------------------------------------------------------------- hop
 
 struct HopArgs {
     RowRef m;
     const float* scale;
+    const float2* coef;       // per-row hop coefficients, or null: from *lam
     const double* lam;
     double sigma;
     const float* zin;
@@ -431,7 +457,24 @@ struct HopArgs {
     float alpha;
     int last;
     float alpha_sum;
+    int64_t tile_stride;      // elements between column tiles of zin / zout / acc
+    int32_t ldo;              // columns of the caller's in / out rows
+    int32_t col0;             // first caller column of this launch's tile (set per workgroup)
 };
+
+// Column tile blockIdx.y of a launch: C columns starting at col0 = y C;
+// the signal buffers hold one [rows][C] block per tile.
+template <int C>
+__device__ __forceinline__ HopArgs tile_args(const HopArgs& a0) {
+    HopArgs a = a0;
+    const int64_t t = blockIdx.y;
+    a.zin += t * a.tile_stride;
+    a.zout += t * a.tile_stride;
+    a.acc += t * a.tile_stride;
+    a.col0 = static_cast<int32_t>(t) * C;
+    a.partial += t * C;
+    return a;
+}
 
 // Operands of a row's epilogue, loaded before the row's gathers so their
 // latency overlaps them.
@@ -439,6 +482,7 @@ template <int C>
 struct RowOps {
     Vec<C> z, acc;
     float s;
+    float2 k;        // (cr, kr) when the launch carries per-row coefficients
     int inst;        // instance of the row (last hop)
     uint8_t flag;
 };
@@ -448,6 +492,7 @@ __device__ __forceinline__ RowOps<C> row_ops(const HopArgs& a, int r) {
     RowOps<C> o;
     int64_t off = static_cast<int64_t>(r) * C;
     o.s = a.scale[r];
+    if (a.coef) o.k = a.coef[r];
     o.z = vload<C>(a.zin + off);
     if (a.band == 2) o.acc = vload<C>(a.acc + off);
     o.inst = a.last ? a.perm[r] : r;
@@ -458,18 +503,18 @@ __device__ __forceinline__ RowOps<C> row_ops(const HopArgs& a, int r) {
 template <int C>
 __device__ __forceinline__ void epilogue(const HopArgs& a, int r, const RowOps<C>& o, const Vec<C>& sum) {
     const int64_t off = static_cast<int64_t>(r) * C;
-    const int64_t oc = static_cast<int64_t>(o.inst) * C;   // instance row of the output (last hop)
+    const int64_t oc = static_cast<int64_t>(o.inst) * a.ldo + a.col0;   // caller row of the output (last hop)
     if (a.last && (o.flag & AHR_NODE_FIXED)) {
         vstore<C>(a.out + oc, vload<C>(a.gin + oc));
         return;
     }
     const float s = o.s;
-    const double lam = *a.lam;
-    float cr = 1.f, kr = 0.f;
-    if (lam > 0) {
-        double sd = s;
-        cr = static_cast<float>(1.0 - ((s > 0 ? 1.0 : 0.0) - a.sigma * sd * sd) / lam);
-        kr = static_cast<float>(sd * sd / lam);
+    float cr, kr;
+    if (a.coef) {
+        cr = o.k.x;
+        kr = o.k.y;
+    } else {
+        hop_coef(s, *a.lam, a.sigma, cr, kr);
     }
     Vec<C> zn;
 #pragma unroll
@@ -541,7 +586,7 @@ __device__ __forceinline__ void gather_batch(const HopArgs& a, int n0, int ln, i
 // partial[chunk]; k_hop_long adds a row's partials after the launch ends (no
 // device-scope fence inside the hop: on this chip that is an L2 write-back).
 template <int C, bool NT>
-__device__ __forceinline__ void hop_chunk(const HopArgs& a) {
+__device__ __forceinline__ void hop_chunk(const HopArgs& a) {   // a: tile-adjusted
     __shared__ double red[kBT / kWave];
     int r, li, k0, k1, n0, ln, h0;
     chunk_range(blockIdx.x, a.long_rows, a.chunk_row, a.chunk0, a.m, r, li, k0, k1, n0, ln, h0);
@@ -563,7 +608,8 @@ __device__ __forceinline__ void hop_chunk(const HopArgs& a) {
 // order: lanes stride the chunks, then a fixed butterfly) and applies the
 // row epilogue.
 template <int C>
-__global__ void __launch_bounds__(kBT) k_hop_long(HopArgs a, int32_t n_long_rows) {
+__global__ void __launch_bounds__(kBT) k_hop_long(HopArgs a0, int32_t n_long_rows) {
+    const HopArgs a = tile_args<C>(a0);
     const int64_t li = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / kWave;
     if (li >= n_long_rows) return;
     const int r = a.long_rows[li];
@@ -600,7 +646,8 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 }
 
 template <int C, int G, int U, bool NT>
-__global__ void __launch_bounds__(kBT) k_hop(HopArgs a) {
+__global__ void __launch_bounds__(kBT) k_hop(HopArgs a0) {
+    const HopArgs a = tile_args<C>(a0);
     if (static_cast<int>(blockIdx.x) < a.n_chunk_blocks) {
         hop_chunk<C, NT>(a);
         return;
@@ -653,60 +700,313 @@ __global__ void k_relax(int32_t n_inst, const uint8_t* __restrict__ flags, const
 
 // The profiled hop time brackets the k_hop launch alone (the chunk
 // partials' k_hop_long is not part of it), so that it matches a kernel trace
-// of k_hop; `bytes` are the algorithmic bytes of the whole hop.
+// of k_hop; `bytes` are the algorithmic bytes of the whole hop.  ntiles
+// column tiles of C columns each run as blockIdx.y.
 template <int C, int G>
-void launch_hop(const HopArgs& a, int32_t n_long_rows, double bytes, hipStream_t s) {
+void launch_hop(const HopArgs& a, int32_t n_long_rows, double bytes, int ntiles, hipStream_t s) {
     constexpr int U = 32 / G > 0 ? (32 / G < 8 ? 32 / G : 8) : 1;   // entries per lane per batch
     int64_t tiles = grid_for(static_cast<int64_t>(a.n_rows) * G, kBT);
     tiles = (tiles + kXcds - 1) / kXcds * kXcds;                    // see xcd_tile
     int64_t blocks = a.n_chunk_blocks + tiles;
+    const dim3 grid(static_cast<unsigned>(blocks), static_cast<unsigned>(ntiles));
     {
         ProfScope ps(kStageHop, s, bytes);
         if (g_hop_nt)
-            hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), true>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0,
-                               s, a);
+            hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), true>), grid, dim3(kBT), 0, s, a);
         else
-            hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), false>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0,
-                               s, a);
+            hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), false>), grid, dim3(kBT), 0, s, a);
         AHR_LAUNCHED("k_hop");
     }
     if (n_long_rows > 0) {
-        hipLaunchKernelGGL(k_hop_long<C>, dim3(grid_for(static_cast<int64_t>(n_long_rows) * kWave, kBT)), dim3(kBT),
-                           0, s, a, n_long_rows);
+        hipLaunchKernelGGL(k_hop_long<C>,
+                           dim3(grid_for(static_cast<int64_t>(n_long_rows) * kWave, kBT), static_cast<unsigned>(ntiles)),
+                           dim3(kBT), 0, s, a, n_long_rows);
         AHR_LAUNCHED("k_hop_long");
     }
 }
 
 template <int C>
-void hop_dispatch(const HopArgs& a, int lanes, int32_t n_long_rows, double bytes, hipStream_t s) {
+void hop_dispatch(const HopArgs& a, int lanes, int32_t n_long_rows, double bytes, int ntiles, hipStream_t s) {
     switch (lanes) {
-        case 1: launch_hop<C, 1>(a, n_long_rows, bytes, s); break;
-        case 2: launch_hop<C, 2>(a, n_long_rows, bytes, s); break;
-        case 4: launch_hop<C, 4>(a, n_long_rows, bytes, s); break;
-        case 8: launch_hop<C, 8>(a, n_long_rows, bytes, s); break;
-        case 16: launch_hop<C, 16>(a, n_long_rows, bytes, s); break;
-        case 32: launch_hop<C, 32>(a, n_long_rows, bytes, s); break;
-        default: launch_hop<C, 64>(a, n_long_rows, bytes, s); break;
+        case 1: launch_hop<C, 1>(a, n_long_rows, bytes, ntiles, s); break;
+        case 2: launch_hop<C, 2>(a, n_long_rows, bytes, ntiles, s); break;
+        case 4: launch_hop<C, 4>(a, n_long_rows, bytes, ntiles, s); break;
+        case 8: launch_hop<C, 8>(a, n_long_rows, bytes, ntiles, s); break;
+        case 16: launch_hop<C, 16>(a, n_long_rows, bytes, ntiles, s); break;
+        case 32: launch_hop<C, 32>(a, n_long_rows, bytes, ntiles, s); break;
+        default: launch_hop<C, 64>(a, n_long_rows, bytes, ntiles, s); break;
     }
 }
 
 template <int C>
 void expand_signal(Graph& g, const float* in, bool band0, float alpha0, hipStream_t s) {
-    const int64_t N = g.n_tot;
-    ExpandArgs e;
+    ExpandArgs e = expand_args(g);
     e.in = in;
-    e.perm = g.perm.p;
-    e.scale = g.scale.p;
     e.z0 = g.z0.p;
     e.acc = g.acc.p;
     e.alpha0 = alpha0;
     e.band0 = band0 ? 1 : 0;
+    e.ct = C;
+    e.tile_stride = static_cast<int64_t>(g.n_tot) * C;
+    ProfScope ps(kStageExpand, s);
+    hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(g.n_tot, kBT)), dim3(kBT), 0, s, e);
+    AHR_LAUNCHED("k_expand");
+    if (g.n_star)
+        hipLaunchKernelGGL((k_expand_bigstar<C>), dim3(g.n_star), dim3(kBT), 0, s, e, g.n_star);
+    AHR_LAUNCHED("k_expand_bigstar");
+}
+
+ChainView chain_view(Graph& g, const ahr_filter_spec& spec) {
+    ChainView v;
+    v.net_rp = g.xnet_rp.p;
+    v.net_ent = g.xnet_ent.p;
+    v.hint_rp = g.xhint_rp.p;
+    v.hint_ent = g.xhint_ent.p;
+    v.scale = g.scale.p;
+    v.coef = nullptr;
+    v.lam = g.lam.p;
+    v.sigma = spec.sigma;
+    v.flags = g.nl.node_flags;
+    v.perm = g.perm.p;
+    v.long_rows = g.long_rows.p;
+    v.chunk_row = g.chunk_row.p;
+    v.chunk0 = g.long_chunk0.p;
+    v.partial = g.partial.p;
+    v.n_tot = g.n_tot;
+    v.n_inst = g.n_inst;
+    v.n_long = g.n_long;
+    v.n_long_inst = g.n_long_inst;
+    v.n_chunks = g.n_chunks;
+    v.n_chunks_inst = g.n_chunks_inst;
+    v.nnz_inst = g.nnz_inst;
+    v.nnz_all = static_cast<int64_t>(g.nnz_net) + g.nnz_hint;
+    v.z0 = g.z0.p;
+    v.z1 = g.z1.p;
+    v.acc = g.acc.p;
+    return v;
+}
+
+HopArgs hop_args(const ChainView& v, const float* in, float* out, int ncols) {
+    HopArgs h;
+    h.m = RowRef{v.net_rp, v.net_ent, v.hint_rp, v.hint_ent};
+    h.perm = v.perm;
+    h.scale = v.scale;
+    h.coef = v.coef;
+    h.lam = v.lam;
+    h.sigma = v.sigma;
+    h.acc = v.acc;
+    h.gin = in;
+    h.out = out;
+    h.flags = v.flags;
+    h.long_rows = v.long_rows;
+    h.chunk_row = v.chunk_row;
+    h.chunk0 = v.chunk0;
+    h.partial = v.partial;
+    h.alpha_sum = 0.f;
+    h.band = 0;
+    h.alpha = 0.f;
+    h.last = 0;
+    h.zin = nullptr;
+    h.zout = nullptr;
+    h.n_rows = 0;
+    h.n_chunk_blocks = 0;
+    h.tile_stride = 0;
+    h.ldo = ncols;
+    h.col0 = 0;
+    return h;
+}
+
+// Algorithmic bytes of one hop launch over C columns: row pointers,
+// (column, weight) entries, one read of the gathered signal, the row
+// writes, the band accumulator.
+double hop_bytes(const ChainView& v, const HopArgs& h, int C) {
+    const double R = h.n_rows;
+    const double E = h.n_rows < v.n_tot ? static_cast<double>(v.nnz_inst) : static_cast<double>(v.nnz_all);
+    double acc_b = 0;
+    if (h.band == 1) acc_b = h.last ? 0 : 4.0 * C * R;
+    if (h.band == 2) acc_b = h.last ? 4.0 * C * R : 8.0 * C * R;
+    return 4.0 * (R + 1) + 8.0 * E + 4.0 * C * static_cast<double>(v.n_tot) + 4.0 * C * R + acc_b;
+}
+
+// The unpinned chain y_j = T^j X for j = 1..3 (scaled coordinates, into
+// g.zh[j-1]); the third hop only for the instance rows.
+template <int C>
+void hops_c(Graph& g, const ahr_filter_spec& spec, const float* in, int lanes, hipStream_t s) {
+    const int64_t N = g.n_tot;
+    g.z0.ensure(static_cast<size_t>(N) * C, s);
+    g.acc.ensure(static_cast<size_t>(N) * C, s);
+    for (auto& z : g.zh) z.ensure(static_cast<size_t>(N) * C, s);
+    expand_signal<C>(g, in, false, 0.f, s);
+    const ChainView v = chain_view(g, spec);
+    HopArgs h = hop_args(v, in, nullptr, C);
+    const float* zin = g.z0.p;
+    for (int j = 0; j < 3; ++j) {
+        h.zin = zin;
+        h.zout = g.zh[j].p;
+        const bool inst_only = j == 2;
+        h.n_rows = inst_only ? g.n_inst : g.n_tot;
+        h.n_chunk_blocks = inst_only ? g.n_chunks_inst : g.n_chunks;
+        hop_dispatch<C>(h, lanes, inst_only ? g.n_long_inst : g.n_long, hop_bytes(v, h, C), 1, s);
+        zin = g.zh[j].p;
+    }
+}
+
+// Weight of power j in the bank (sum over bands with k_b = j).
+float alpha_at(const ahr_filter_spec& spec, int j, bool& is_band) {
+    float a = 0.f;
+    is_band = false;
+    for (int b = 0; b < spec.nbands; ++b)
+        if (spec.k[b] == j) {
+            a += spec.alpha[b];
+            is_band = true;
+        }
+    return a;
+}
+
+// Hops 1..k_max over column tiles of CT columns (C / CT tiles).
+template <int C, int CT>
+void chain_c(const ChainView& v, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s) {
+    float alpha_sum = 0.f;
+    const int kmax = spec_kmax(spec, &alpha_sum);
+    bool b0;
+    alpha_at(spec, 0, b0);
+    HopArgs h = hop_args(v, in, out, C);
+    h.alpha_sum = alpha_sum;
+    h.tile_stride = static_cast<int64_t>(v.n_tot) * CT;
+    bool has_acc = b0;
+    float* zin = v.z0;
+    float* zout = v.z1;
+    for (int j = 1; j <= kmax; ++j) {
+        bool isb;
+        float aj = alpha_at(spec, j, isb);
+        h.zin = zin;
+        h.zout = zout;
+        h.last = j == kmax;
+        h.band = isb ? (has_acc ? 2 : 1) : 0;
+        h.alpha = aj;
+        h.n_rows = h.last ? v.n_inst : v.n_tot;
+        h.n_chunk_blocks = h.last ? v.n_chunks_inst : v.n_chunks;
+        hop_dispatch<CT>(h, lanes, h.last ? v.n_long_inst : v.n_long, hop_bytes(v, h, C), C / CT, s);
+        has_acc = has_acc || isb;
+        float* t = zin;
+        zin = zout;
+        zout = t;
+    }
+}
+
+template <int C>
+void chain_tiles(const ChainView& v, const ahr_filter_spec& spec, const float* in, float* out, int lanes, int ct,
+                 hipStream_t s) {
+    if (ct == C) return chain_c<C, C>(v, spec, in, out, lanes, s);
+    if constexpr (C >= 2) {
+        if (ct == 1) return chain_c<C, 1>(v, spec, in, out, lanes, s);
+    }
+    if constexpr (C >= 4) {
+        if (ct == 2) return chain_c<C, 2>(v, spec, in, out, lanes, s);
+    }
+    if constexpr (C >= 8) {
+        if (ct == 4) return chain_c<C, 4>(v, spec, in, out, lanes, s);
+    }
+    throw Error{AHR_EINVAL, "column tile must divide the column count"};
+}
+
+template <int C>
+void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s) {
+    const int64_t N = g.n_tot;
+    float alpha_sum = 0.f;
+    const int kmax = spec_kmax(spec, &alpha_sum);
+    if (kmax == 0) {
+        int64_t n = static_cast<int64_t>(g.n_inst) * C;
+        hipLaunchKernelGGL((k_identity<C>), dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.n_inst, g.nl.node_flags, in, out,
+                           alpha_sum);
+        AHR_LAUNCHED("k_identity");
+        return;
+    }
+    g.z0.ensure(static_cast<size_t>(N) * C, s);
+    g.z1.ensure(static_cast<size_t>(N) * C, s);
+    g.acc.ensure(static_cast<size_t>(N) * C, s);
+    bool b0;
+    float a0 = alpha_at(spec, 0, b0);
+    expand_signal<C>(g, in, b0, a0, s);
+    chain_c<C, C>(chain_view(g, spec), spec, in, out, lanes, s);
+}
+
+template <int C>
+void expand_batch_c(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, const int32_t* sblk0,
+                    int32_t n_star_blocks, int32_t ng, const float* in, hipStream_t s) {
+    hipLaunchKernelGGL((k_expand_batch<C>), dim3(static_cast<unsigned>(n_blocks)), dim3(kBT), 0, s, d, blk0, ng, in);
+    AHR_LAUNCHED("k_expand_batch");
+    if (n_star_blocks > 0) {
+        hipLaunchKernelGGL((k_expand_bigstar_batch<C>), dim3(static_cast<unsigned>(n_star_blocks)), dim3(kBT), 0, s, d,
+                           sblk0, ng, in);
+        AHR_LAUNCHED("k_expand_bigstar_batch");
+    }
+}
+
+}  // namespace
+
+void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, DevBuf<int32_t>& long_rows,
+                 DevBuf<int32_t>& long_chunk0, DevBuf<int32_t>& chunk_row, DevBuf<double>& partial, int32_t& n_long,
+                 int32_t& n_long_inst, int32_t& n_chunks, int32_t& n_chunks_inst, int64_t& nnz_inst,
+                 DevBuf<int64_t>& scan_tmp, hipStream_t s) {
+    DevBuf<int32_t> is_long, rank, nch;
+    is_long.ensure(static_cast<size_t>(N) + 1, s);
+    hipLaunchKernelGGL(k_row_len, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, net_rp, hint_rp, is_long.p);
+    AHR_LAUNCHED("k_row_len");
+    rank.ensure(static_cast<size_t>(N) + 1, s);
+    scan_tmp.ensure(scan_tmp_elems(N), s);
+    scan_i32_to_i32(is_long.p, rank.p, N, scan_tmp.p, s);
+    int32_t t1[4];
+    read_scalars({rank.p + N, rank.p + n_inst, net_rp + n_inst, hint_rp + n_inst}, t1, s);
+    n_long = t1[0];
+    n_long_inst = t1[1];
+    nnz_inst = static_cast<int64_t>(t1[2]) + t1[3];
+    long_rows.ensure(static_cast<size_t>(n_long) + 1, s);
+    list_rows(is_long.p, rank.p, N, long_rows.p, s);
+    nch.ensure(static_cast<size_t>(n_long) + 1, s);
+    long_chunk0.ensure(static_cast<size_t>(n_long) + 1, s);
+    if (n_long) {
+        hipLaunchKernelGGL(k_long_nchunks, dim3(grid_for(n_long, kBT)), dim3(kBT), 0, s, n_long, long_rows.p, net_rp,
+                           hint_rp, nch.p);
+        AHR_LAUNCHED("k_long_nchunks");
+    }
+    scan_tmp.ensure(scan_tmp_elems(n_long), s);
+    scan_i32_to_i32(nch.p, long_chunk0.p, n_long, scan_tmp.p, s);
+    int32_t t2[2];
+    read_scalars({long_chunk0.p + n_long, long_chunk0.p + n_long_inst}, t2, s);
+    n_chunks = t2[0];
+    n_chunks_inst = t2[1];
+    chunk_row.ensure(static_cast<size_t>(n_chunks) + 1, s);
+    if (n_long) {
+        hipLaunchKernelGGL(k_chunk_rows, dim3(n_long), dim3(kBT), 0, s, n_long, long_chunk0.p, chunk_row.p);
+        AHR_LAUNCHED("k_chunk_rows");
+    }
+    partial.ensure(static_cast<size_t>(n_chunks) * 8 + 8, s);
+    is_long.release(s);
+    rank.release(s);
+    nch.release(s);
+}
+
+ExpandArgs expand_args(const Graph& g) {
+    ExpandArgs e;
+    e.in = nullptr;
+    e.in_off = 0;
+    e.perm = g.perm.p;
+    e.scale = g.scale.p;
+    e.z0 = nullptr;
+    e.acc = nullptr;
+    e.alpha0 = 0.f;
+    e.band0 = 0;
     e.n_inst = g.n_inst;
     e.first_mpin = g.first_mpin;
     e.first_star = g.first_star;
     e.first_mvirt = g.first_mvirt;
     e.first_bvirt = g.first_bvirt;
     e.n_tot = g.n_tot;
+    e.row_inst0 = 0;
+    e.row_aux0 = g.n_inst;
+    e.ct = 1;
+    e.tile_stride = 0;
     e.mpin_owner = g.mpin_owner.p;
     e.mpin_pin = g.mpin_pin.p;
     e.pin_off = g.nl.pin_off;
@@ -720,133 +1020,41 @@ void expand_signal(Graph& g, const float* in, bool band0, float alpha0, hipStrea
     e.yl = g.nl.die[1];
     e.bw = (static_cast<double>(g.nl.die[2]) - static_cast<double>(g.nl.die[0])) / g.hp.nbx;
     e.bh = (static_cast<double>(g.nl.die[3]) - static_cast<double>(g.nl.die[1])) / g.hp.nby;
-    ProfScope ps(kStageExpand, s);
-    hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(N, kBT)), dim3(kBT), 0, s, e);
-    AHR_LAUNCHED("k_expand");
-    if (g.n_star)
-        hipLaunchKernelGGL((k_expand_bigstar<C>), dim3(g.n_star), dim3(kBT), 0, s, e, g.n_star);
-    AHR_LAUNCHED("k_expand_bigstar");
+    return e;
 }
 
-HopArgs hop_args(Graph& g, const ahr_filter_spec& spec, const float* in, float* out) {
-    HopArgs h;
-    h.m = RowRef{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
-    h.perm = g.perm.p;
-    h.scale = g.scale.p;
-    h.lam = g.lam.p;
-    h.sigma = spec.sigma;
-    h.acc = g.acc.p;
-    h.gin = in;
-    h.out = out;
-    h.flags = g.nl.node_flags;
-    h.long_rows = g.long_rows.p;
-    h.chunk_row = g.chunk_row.p;
-    h.chunk0 = g.long_chunk0.p;
-    h.partial = g.partial.p;
-    h.alpha_sum = 0.f;
-    h.band = 0;
-    h.alpha = 0.f;
-    h.last = 0;
-    h.zin = nullptr;
-    h.zout = nullptr;
-    h.n_rows = 0;
-    h.n_chunk_blocks = 0;
-    return h;
-}
-
-// Algorithmic bytes of one hop launch: row pointers, (column, weight)
-// entries, one read of the gathered signal, the row writes, the band
-// accumulator.
-double hop_bytes(const Graph& g, const HopArgs& h, int C) {
-    const double R = h.n_rows;
-    const double E = h.n_rows < g.n_tot ? static_cast<double>(g.nnz_inst)
-                                        : static_cast<double>(g.nnz_net) + static_cast<double>(g.nnz_hint);
-    double acc_b = 0;
-    if (h.band == 1) acc_b = h.last ? 0 : 4.0 * C * R;
-    if (h.band == 2) acc_b = h.last ? 4.0 * C * R : 8.0 * C * R;
-    return 4.0 * (R + 1) + 8.0 * E + 4.0 * C * static_cast<double>(g.n_tot) + 4.0 * C * R + acc_b;
-}
-
-// The unpinned chain y_j = T^j X for j = 1..3 (scaled coordinates, into
-// g.zh[j-1]); the third hop only for the instance rows.
-template <int C>
-void hops_c(Graph& g, const ahr_filter_spec& spec, const float* in, int lanes, hipStream_t s) {
-    const int64_t N = g.n_tot;
-    g.z0.ensure(static_cast<size_t>(N) * C, s);
-    g.acc.ensure(static_cast<size_t>(N) * C, s);
-    for (auto& z : g.zh) z.ensure(static_cast<size_t>(N) * C, s);
-    expand_signal<C>(g, in, false, 0.f, s);
-    HopArgs h = hop_args(g, spec, in, nullptr);
-    const float* zin = g.z0.p;
-    for (int j = 0; j < 3; ++j) {
-        h.zin = zin;
-        h.zout = g.zh[j].p;
-        const bool inst_only = j == 2;
-        h.n_rows = inst_only ? g.n_inst : g.n_tot;
-        h.n_chunk_blocks = inst_only ? g.n_chunks_inst : g.n_chunks;
-        hop_dispatch<C>(h, lanes, inst_only ? g.n_long_inst : g.n_long, hop_bytes(g, h, C), s);
-        zin = g.zh[j].p;
+void expand_batch(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, const int32_t* sblk0,
+                  int32_t n_star_blocks, int32_t ng, const float* in, int32_t ncols, hipStream_t s) {
+    switch (ncols) {
+        case 1: expand_batch_c<1>(d, blk0, n_blocks, sblk0, n_star_blocks, ng, in, s); break;
+        case 2: expand_batch_c<2>(d, blk0, n_blocks, sblk0, n_star_blocks, ng, in, s); break;
+        case 4: expand_batch_c<4>(d, blk0, n_blocks, sblk0, n_star_blocks, ng, in, s); break;
+        case 8: expand_batch_c<8>(d, blk0, n_blocks, sblk0, n_star_blocks, ng, in, s); break;
+        default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
     }
 }
 
-template <int C>
-void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s) {
-    const int64_t N = g.n_tot;
-    int kmax = 0;
-    float alpha_sum = 0.f;
+void run_chain(const ChainView& v, const ahr_filter_spec& spec, const float* in, float* out, int32_t ncols, int lanes,
+               int ct, hipStream_t s) {
+    switch (ncols) {
+        case 1: chain_tiles<1>(v, spec, in, out, lanes, ct, s); break;
+        case 2: chain_tiles<2>(v, spec, in, out, lanes, ct, s); break;
+        case 4: chain_tiles<4>(v, spec, in, out, lanes, ct, s); break;
+        case 8: chain_tiles<8>(v, spec, in, out, lanes, ct, s); break;
+        default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
+    }
+}
+
+int32_t spec_kmax(const ahr_filter_spec& spec, float* alpha_sum) {
+    int32_t kmax = 0;
+    float as = 0.f;
     for (int b = 0; b < spec.nbands; ++b) {
         kmax = spec.k[b] > kmax ? spec.k[b] : kmax;
-        alpha_sum += spec.alpha[b];
+        as += spec.alpha[b];
     }
-    if (kmax == 0) {
-        int64_t n = static_cast<int64_t>(g.n_inst) * C;
-        hipLaunchKernelGGL((k_identity<C>), dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.n_inst, g.nl.node_flags, in, out,
-                           alpha_sum);
-        AHR_LAUNCHED("k_identity");
-        return;
-    }
-    auto alpha_at = [&](int j, bool& is_band) {
-        float a = 0.f;
-        is_band = false;
-        for (int b = 0; b < spec.nbands; ++b)
-            if (spec.k[b] == j) {
-                a += spec.alpha[b];
-                is_band = true;
-            }
-        return a;
-    };
-    g.z0.ensure(static_cast<size_t>(N) * C, s);
-    g.z1.ensure(static_cast<size_t>(N) * C, s);
-    g.acc.ensure(static_cast<size_t>(N) * C, s);
-
-    bool b0;
-    float a0 = alpha_at(0, b0);
-    expand_signal<C>(g, in, b0, a0, s);
-
-    HopArgs h = hop_args(g, spec, in, out);
-    h.alpha_sum = alpha_sum;
-    bool has_acc = b0;
-    float* zin = g.z0.p;
-    float* zout = g.z1.p;
-    for (int j = 1; j <= kmax; ++j) {
-        bool isb;
-        float aj = alpha_at(j, isb);
-        h.zin = zin;
-        h.zout = zout;
-        h.last = j == kmax;
-        h.band = isb ? (has_acc ? 2 : 1) : 0;
-        h.alpha = aj;
-        h.n_rows = h.last ? g.n_inst : g.n_tot;
-        h.n_chunk_blocks = h.last ? g.n_chunks_inst : g.n_chunks;
-        hop_dispatch<C>(h, lanes, h.last ? g.n_long_inst : g.n_long, hop_bytes(g, h, C), s);
-        has_acc = has_acc || isb;
-        float* t = zin;
-        zin = zout;
-        zout = t;
-    }
+    if (alpha_sum) *alpha_sum = as;
+    return kmax;
 }
-
-}  // namespace
 
 void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     if (g.norm_version == g.hint_version && g.norm_sigma == spec.sigma && g.norm_mode == spec.lambda_mode &&
@@ -857,39 +1065,8 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     RowRef m{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
 
     if (g.rows_version != g.hint_version) {
-        DevBuf<int32_t> is_long, rank, nch;
-        is_long.ensure(static_cast<size_t>(N) + 1, s);
-        hipLaunchKernelGGL(k_row_len, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.xnet_rp.p, g.xhint_rp.p, is_long.p);
-        AHR_LAUNCHED("k_row_len");
-        rank.ensure(static_cast<size_t>(N) + 1, s);
-        g.scan_tmp.ensure(scan_tmp_elems(N), s);
-        scan_i32_to_i32(is_long.p, rank.p, N, g.scan_tmp.p, s);
-        int32_t t1[4];
-        read_scalars({rank.p + N, rank.p + g.n_inst, g.xnet_rp.p + g.n_inst, g.xhint_rp.p + g.n_inst}, t1, s);
-        g.n_long = t1[0];
-        g.n_long_inst = t1[1];
-        g.nnz_inst = static_cast<int64_t>(t1[2]) + t1[3];
-        g.long_rows.ensure(static_cast<size_t>(g.n_long) + 1, s);
-        list_rows(is_long.p, rank.p, N, g.long_rows.p, s);
-        nch.ensure(static_cast<size_t>(g.n_long) + 1, s);
-        g.long_chunk0.ensure(static_cast<size_t>(g.n_long) + 1, s);
-        if (g.n_long) {
-            hipLaunchKernelGGL(k_long_nchunks, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long,
-                               g.long_rows.p, g.xnet_rp.p, g.xhint_rp.p, nch.p);
-            AHR_LAUNCHED("k_long_nchunks");
-        }
-        g.scan_tmp.ensure(scan_tmp_elems(g.n_long), s);
-        scan_i32_to_i32(nch.p, g.long_chunk0.p, g.n_long, g.scan_tmp.p, s);
-        int32_t t2[2];
-        read_scalars({g.long_chunk0.p + g.n_long, g.long_chunk0.p + g.n_long_inst}, t2, s);
-        g.n_chunks = t2[0];
-        g.n_chunks_inst = t2[1];
-        g.chunk_row.ensure(static_cast<size_t>(g.n_chunks) + 1, s);
-        if (g.n_long) {
-            hipLaunchKernelGGL(k_chunk_rows, dim3(g.n_long), dim3(kBT), 0, s, g.n_long, g.long_chunk0.p, g.chunk_row.p);
-            AHR_LAUNCHED("k_chunk_rows");
-        }
-        g.partial.ensure(static_cast<size_t>(g.n_chunks) * 8 + 8, s);
+        row_classes(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, g.long_rows, g.long_chunk0, g.chunk_row, g.partial,
+                    g.n_long, g.n_long_inst, g.n_chunks, g.n_chunks_inst, g.nnz_inst, g.scan_tmp, s);
         g.rows_version = g.hint_version;
     }
 

@@ -50,10 +50,14 @@ void drain_locked() {
 
 }  // namespace
 
-bool profiling() { return g_on; }
+thread_local bool t_capture = false;
+
+bool profiling() { return g_on && !t_capture; }
+
+void set_capture(bool on) { t_capture = on; }
 
 ProfScope::ProfScope(Stage st, hipStream_t s, double bytes) : stage_(st), s_(s), bytes_(bytes) {
-    if (!g_on) return;
+    if (!g_on || t_capture) return;
     std::lock_guard<std::mutex> lk(g_mu);
     a_ = take_event();
     AHR_HIP(hipEventRecord(static_cast<hipEvent_t>(a_), s));
