@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--gamma", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-netlist filter")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
@@ -156,6 +157,79 @@ def learned_vs_plain(A, torch, np, nl, net, params, spec, g0, reps):
             "model": {"file": os.path.relpath(MODEL, ROOT), "validated": model.validated,
                       "heldout_rel_err_mean": model.summary.get("rel_err_mean")},
             "bounds": {"rel_err": 1e-3, "hpwl_delta": 2e-3}}
+
+
+def batch_bins(n_inst):
+    """Bin grid of a batch member: about 200 cells per bin, 8x8 to 32x32."""
+    b = int(round((n_inst / 200.0) ** 0.5))
+    return min(32, max(8, b))
+
+
+def batched(A, torch, np, N, spec, reps):
+    """The batched workload: 64 netlists of 5k-200k cells (log-uniform,
+    2-5 % macros) filtered with the order-8 bank on 4 columns in one
+    replayed HIP graph, with the launch shape the tuner picks.  Compared
+    with filtering the members one after another (single-graph calls, same
+    launch shape); the two outputs must be bit-identical."""
+    t0 = time.perf_counter()
+    members = N.batch_sizes()
+    nls = [N.generate(N.batch_member(*m)) for m in members]
+    gen_s = time.perf_counter() - t0
+    nets = [A.Netlist(nl) for nl in nls]
+    params = [A.hint_params(nbx=batch_bins(nl["n_inst"]), nby=batch_bins(nl["n_inst"])) for nl in nls]
+    pos = torch.as_tensor(np.concatenate([nl["g0"] for nl in nls])).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = A.Batch(nets, params, pos)
+    build_s = time.perf_counter() - t0
+    lanes, ct, tune_ms = b.autotune(spec, pos.shape[1])
+    out = torch.empty_like(pos)
+    # algorithmic hop bytes of one call (direct launch, profiled)
+    b.filter(spec, pos, out=out, use_graph=False)
+    torch.cuda.synchronize()
+    A.profile_read(reset=True)
+    A.profile_enable(True)
+    b.filter(spec, pos, out=out, use_graph=False)
+    torch.cuda.synchronize()
+    A.profile_enable(False)
+    prof = A.profile_read(reset=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(2):
+        b.filter(spec, pos, out=out)
+    ev[0].record()
+    for _ in range(reps):
+        b.filter(spec, pos, out=out)
+    ev[1].record()
+    # the same work one member at a time
+    saved = A.filter_get_tune()
+    A.filter_tune(lanes, -1)
+    graphs = [A.Graph(net, p, pos[lo:hi]) for net, p, lo, hi in zip(nets, params, b.offsets[:-1], b.offsets[1:])]
+    xs = [pos[lo:hi].contiguous() for lo, hi in zip(b.offsets[:-1], b.offsets[1:])]
+    ys = [torch.empty_like(x) for x in xs]
+    for g, x, y in zip(graphs, xs, ys):
+        g.filter(spec, x, out=y)
+    ev[2].record()
+    for _ in range(reps):
+        for g, x, y in zip(graphs, xs, ys):
+            g.filter(spec, x, out=y)
+    ev[3].record()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out, torch.cat(ys)))
+    A.filter_tune(*saved)
+    for g in graphs:
+        g.close()
+    inf = b.info()
+    b.close()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    seq_ms = ev[2].elapsed_time(ev[3]) / reps
+    return {"n_graphs": inf["n_graphs"], "n_inst": inf["n_inst"], "n_tot": inf["n_tot"],
+            "nnz": inf["nnz_net"] + inf["nnz_hint"], "cells_min": int(min(nl["n_inst"] for nl in nls)),
+            "cells_max": int(max(nl["n_inst"] for nl in nls)), "ncols": int(pos.shape[1]),
+            "tuned": {"lanes_per_row": lanes, "col_tile": ct, "ms": round(tune_ms, 4)},
+            "ms": round(ms, 4), "hop_bytes": int(prof["hop_bytes"]),
+            "gbs": round(prof["hop_bytes"] / (ms * 1e-3) / 1e9, 1),
+            "members_one_by_one_ms": round(seq_ms, 4), "speedup": round(seq_ms / ms, 3),
+            "bit_identical_to_members": same, "build_s": round(build_s, 2), "generator_s": round(gen_s, 1)}
 
 
 def main():
@@ -251,6 +325,8 @@ def main():
     }
     if not args.no_learned:
         rec["learned_vs_plain"] = learned_vs_plain(A, torch, np, nl, net, params, spec, g0, reps=10)
+    if not args.no_batched:
+        rec["batched"] = batched(A, torch, np, N, spec, reps=10)
     if not args.no_cpu_baseline:
         from oracle import ahr_oracle as O
         rec["cpu_baseline"] = cpu_baseline(nl, bins, O.FilterSpec(ks=ks, alphas=alphas), args.rounds)
