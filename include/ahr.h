@@ -281,9 +281,13 @@ ahr_status ahr_memory_trim(void);
  * wavefront share one row of up to 128 entries (0 keeps the current
  * value); nontemporal = 1 streams the adjacency with non-temporal loads so
  * the L2 keeps the gathered signal rows (-1 keeps the current value).
- * Results do not depend on the lanes (each row's sum is a fixed butterfly
- * over its lanes' partial sums, so they may differ in the last bits between
- * settings but are deterministic for each). */
+ * lanes_per_row = AHR_HOP_ROW_BLOCK selects the row-block form instead:
+ * one workgroup per block of consecutive short rows (at most 256 rows and
+ * 1151 entries) streams the block's entries with coalesced loads, stages
+ * the weighted products in LDS and adds each row's products in entry
+ * order.  Each setting is deterministic; settings differ from each other
+ * in the last bits only (the summation order of a row changes). */
+#define AHR_HOP_ROW_BLOCK 256     /* lanes_per_row value selecting the row-block hop */
 ahr_status ahr_filter_tune(int32_t lanes_per_row, int32_t nontemporal);
 ahr_status ahr_filter_get_tune(int32_t* lanes_per_row, int32_t* nontemporal);
 

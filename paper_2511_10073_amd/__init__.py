@@ -22,6 +22,7 @@ EXPAND_MACRO_PINS = 1
 MACRO_HINTS = 2
 BIN_HINTS = 4
 ALL_HINTS = 7
+HOP_ROW_BLOCK = 256       # lanes_per_row value selecting the row-block hop
 LAMBDA_GERSHGORIN = 0
 LAMBDA_FIXED = 1
 

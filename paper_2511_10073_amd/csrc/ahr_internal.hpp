@@ -104,6 +104,36 @@ class ProfScope {
 
 // ---------------------------------------------------------------- graph
 
+// Rows with more entries than kLongRow are summed by whole workgroups, in
+// chunks of kChunk entries; the other rows are grouped into row blocks of
+// consecutive rows (at most kRbRows rows and kRbEntries + kLongRow
+// entries, never across a long row or the instance boundary) for the
+// LDS-staged hop.
+constexpr int kLongRow = 128;
+constexpr int kChunk = 2048;
+constexpr int kRbRows = 256;
+constexpr int kRbEntries = 1024;
+
+struct RowClasses {
+    DevBuf<int32_t> long_rows;    // rows split over chunks, ascending
+    DevBuf<int32_t> long_chunk0;  // [n_long+1] first chunk of each long row
+    DevBuf<int32_t> chunk_row;    // [n_chunks] long-row index of each chunk
+    DevBuf<double> partial;       // [n_chunks * 8]
+    DevBuf<int4> rb;              // [2 n_rb] row blocks: (r0, r1, net_lo, net_hi), (hint_lo, hint_hi, -, -)
+    int32_t n_long = 0, n_long_inst = 0;      // long rows, those below n_inst
+    int32_t n_chunks = 0, n_chunks_inst = 0;  // chunks, those of long rows below n_inst
+    int32_t n_rb = 0, n_rb_inst = 0;          // row blocks, those below n_inst
+    int32_t has_rb = 0;                       // row blocks built (on first use of the row-block hop)
+    int64_t nnz_inst = 0;                     // entries of rows below n_inst (netlist + hints)
+    void release(hipStream_t s) {
+        long_rows.release(s);
+        long_chunk0.release(s);
+        chunk_row.release(s);
+        partial.release(s);
+        rb.release(s);
+    }
+};
+
 struct Graph {
     ahr_netlist nl;            // caller's device arrays (kept)
     ahr_hint_params hp;
@@ -167,16 +197,10 @@ struct Graph {
     int32_t norm_mode = -1;
     float norm_fixed = -1.f;
 
+    DevBuf<float2> coef;          // [n_tot] hop coefficients (cr, kr) of each row (see hop_coef)
+
     // row classes for the filter
-    DevBuf<int32_t> row_len;      // [n_tot] scratch
-    DevBuf<int32_t> long_rows;    // rows split over chunks, ascending
-    DevBuf<int32_t> long_chunk0;  // [n_long+1] first chunk of each long row
-    DevBuf<int32_t> chunk_row;    // [n_chunks] long-row index of each chunk
-    DevBuf<double> partial;       // [n_chunks * 8]
-    int32_t n_long = 0, n_chunks = 0;
-    int32_t n_chunks_inst = 0;    // chunks of long rows below n_inst
-    int32_t n_long_inst = 0;      // long rows below n_inst
-    int64_t nnz_inst = 0;         // entries of rows below n_inst (netlist + hints)
+    RowClasses rc;
     int32_t rows_version = -1;
 
     // filter work buffers
@@ -224,11 +248,6 @@ void mlp_loss_grad(const float* params, const float* feats, const float* target,
                    double* loss, hipStream_t s);
 void mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr, float b1, float b2,
               float eps, hipStream_t s);
-
-// Rows with more entries than kLongRow are summed by whole workgroups, in
-// chunks of kChunk entries; shorter rows by a few lanes each.
-constexpr int kLongRow = 128;
-constexpr int kChunk = 2048;
 
 // ---------------------------------------------------------------- filter chain
 
@@ -294,20 +313,24 @@ struct ChainView {
     const int32_t* chunk_row;
     const int32_t* chunk0;
     double* partial;
-    int32_t n_tot, n_inst, n_long, n_long_inst, n_chunks, n_chunks_inst;
+    const int4* rb;
+    int32_t n_tot, n_inst, n_long, n_long_inst, n_chunks, n_chunks_inst, n_rb, n_rb_inst;
     int64_t nnz_inst, nnz_all;
     float* z0;
     float* z1;
     float* acc;
 };
 
-// Long rows (more than kLongRow entries) of an operator with rows
-// [0, N), instance rows first: their list, chunk offsets and chunk owners,
-// and a partial-sum buffer for C <= 8 columns.
-void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, DevBuf<int32_t>& long_rows,
-                 DevBuf<int32_t>& long_chunk0, DevBuf<int32_t>& chunk_row, DevBuf<double>& partial, int32_t& n_long,
-                 int32_t& n_long_inst, int32_t& n_chunks, int32_t& n_chunks_inst, int64_t& nnz_inst,
+// Row classes of an operator with rows [0, N), instance rows first: the
+// long rows (more than kLongRow entries) with their chunks and a
+// partial-sum buffer for C <= 8 columns.  Resets the row blocks.
+void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,
                  DevBuf<int64_t>& scan_tmp, hipStream_t s);
+// The row blocks of the short rows (for the row-block hop), if not built.
+void row_blocks(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,
+                DevBuf<int64_t>& scan_tmp, hipStream_t s);
+// Hop coefficients (cr, kr) of rows [0, n) from scale and lambda (device).
+void hop_coefs(int32_t n, const float* scale, const double* lam, double sigma, float2* coef, hipStream_t s);
 // The expansion descriptor of graph g (in, z0, acc, bands and the row
 // placement are filled in by the caller).
 ExpandArgs expand_args(const Graph& g);

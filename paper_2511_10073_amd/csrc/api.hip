@@ -14,8 +14,8 @@ Graph::~Graph() {
     hipStream_t s = nullptr;
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_rp, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
-                              &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart, &row_len,
-                              &long_rows, &long_chunk0, &chunk_row, &i32a, &i32b, &counter};
+                              &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart,
+                              &i32a, &i32b, &counter};
     for (auto* b : i32) b->release(s);
     net_q.release(s);
     perm.release(s);
@@ -37,7 +37,8 @@ Graph::~Graph() {
     hsum.release(s);
     for (auto& z : zh) z.release(s);
     lam.release(s);
-    partial.release(s);
+    coef.release(s);
+    rc.release(s);
     z0.release(s);
     z1.release(s);
     acc.release(s);
@@ -183,7 +184,7 @@ ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
     info->nnz_net = g->nnz_net;
     info->nnz_hint = g->has_hints ? g->nnz_hint : 0;
     info->n_hint_cells = g->n_hint_cells;
-    info->n_long_rows = g->n_long;
+    info->n_long_rows = g->rc.n_long;
     info->hint_version = g->hint_version;
     return AHR_OK;
 }
@@ -394,8 +395,10 @@ ahr_status ahr_mlp_adam(float* params, float* m, float* v, const float* grad, in
 
 ahr_status ahr_filter_tune(int32_t lanes_per_row, int32_t nontemporal) {
     if (lanes_per_row != 0) {
-        if (lanes_per_row < 1 || lanes_per_row > 64 || (lanes_per_row & (lanes_per_row - 1)))
-            return fail(AHR_EINVAL, "lanes_per_row must be a power of two in [1, 64], or 0 to keep it");
+        if (lanes_per_row != AHR_HOP_ROW_BLOCK &&
+            (lanes_per_row < 1 || lanes_per_row > 64 || (lanes_per_row & (lanes_per_row - 1))))
+            return fail(AHR_EINVAL,
+                        "lanes_per_row must be a power of two in [1, 64], AHR_HOP_ROW_BLOCK, or 0 to keep it");
         ahr::g_hop_lanes = lanes_per_row;
     }
     if (nontemporal >= 0) ahr::g_hop_nt = nontemporal ? 1 : 0;

@@ -133,10 +133,7 @@ struct Batch {
     ahr_filter_spec op_spec;
     bool op_valid = false;
 
-    DevBuf<int32_t> long_rows, long_chunk0, chunk_row;
-    DevBuf<double> partial;
-    int32_t n_long = 0, n_long_inst = 0, n_chunks = 0, n_chunks_inst = 0;
-    int64_t nnz_inst = 0;
+    RowClasses rc;
 
     DevBuf<int32_t> blk0, sblk0;          // first expansion workgroup of each graph (rows, big stars)
     int32_t n_blocks = 0, n_star_blocks = 0;
@@ -176,17 +173,20 @@ ChainView batch_view(Batch& b, const ahr_filter_spec& spec) {
     v.sigma = spec.sigma;
     v.flags = b.flags.p;
     v.perm = b.perm.p;
-    v.long_rows = b.long_rows.p;
-    v.chunk_row = b.chunk_row.p;
-    v.chunk0 = b.long_chunk0.p;
-    v.partial = b.partial.p;
+    v.long_rows = b.rc.long_rows.p;
+    v.chunk_row = b.rc.chunk_row.p;
+    v.chunk0 = b.rc.long_chunk0.p;
+    v.partial = b.rc.partial.p;
+    v.rb = b.rc.rb.p;
     v.n_tot = b.n_tot;
     v.n_inst = b.n_inst;
-    v.n_long = b.n_long;
-    v.n_long_inst = b.n_long_inst;
-    v.n_chunks = b.n_chunks;
-    v.n_chunks_inst = b.n_chunks_inst;
-    v.nnz_inst = b.nnz_inst;
+    v.n_long = b.rc.n_long;
+    v.n_long_inst = b.rc.n_long_inst;
+    v.n_chunks = b.rc.n_chunks;
+    v.n_chunks_inst = b.rc.n_chunks_inst;
+    v.n_rb = b.rc.n_rb;
+    v.n_rb_inst = b.rc.n_rb_inst;
+    v.nnz_inst = b.rc.nnz_inst;
     v.nnz_all = b.nnz_net + b.nnz_hint;
     v.z0 = b.z0.p;
     v.z1 = b.z1.p;
@@ -263,6 +263,7 @@ void batch_filter(Batch& b, const ahr_filter_spec& spec, const float* in, float*
         AHR_LAUNCHED("k_batch_identity");
         return;
     }
+    if (lanes == AHR_HOP_ROW_BLOCK) row_blocks(b.net_rp.p, b.hint_rp.p, b.n_tot, b.n_inst, b.rc, b.scan_tmp, s);
     const size_t nz = static_cast<size_t>(b.n_tot) * C;
     b.z0.ensure(nz, s);
     b.z1.ensure(nz, s);
@@ -351,10 +352,7 @@ Batch::~Batch() {
     flags.release(s);
     scale.release(s);
     coef.release(s);
-    long_rows.release(s);
-    long_chunk0.release(s);
-    chunk_row.release(s);
-    partial.release(s);
+    rc.release(s);
     blk0.release(s);
     sblk0.release(s);
     z0.release(s);
@@ -425,8 +423,7 @@ void batch_assemble(Batch& b, hipStream_t s) {
     b.scale.ensure(static_cast<size_t>(b.n_tot) + 1, s);
     b.coef.ensure(static_cast<size_t>(b.n_tot) + 1, s);
     b.op_version.assign(n, -1);
-    row_classes(b.net_rp.p, b.hint_rp.p, b.n_tot, b.n_inst, b.long_rows, b.long_chunk0, b.chunk_row, b.partial,
-                b.n_long, b.n_long_inst, b.n_chunks, b.n_chunks_inst, b.nnz_inst, b.scan_tmp, s);
+    row_classes(b.net_rp.p, b.hint_rp.p, b.n_tot, b.n_inst, b.rc, b.scan_tmp, s);
     std::vector<int32_t> blk(n + 1, 0), sblk(n + 1, 0);
     for (size_t i = 0; i < n; ++i) {
         blk[i + 1] = blk[i] + static_cast<int32_t>(grid_for(b.g[i]->n_tot, kBT));
@@ -450,7 +447,7 @@ namespace {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 bool ncols_ok(int32_t c) { return c == 1 || c == 2 || c == 4 || c == 8; }
-bool pow2_lanes(int32_t l) { return l >= 1 && l <= 64 && (l & (l - 1)) == 0; }
+bool pow2_lanes(int32_t l) { return l == AHR_HOP_ROW_BLOCK || (l >= 1 && l <= 64 && (l & (l - 1)) == 0); }
 bool tile_ok(int32_t C, int32_t ct) { return ct >= 1 && ct <= C && C % ct == 0 && (ct & (ct - 1)) == 0; }
 
 template <class F>
@@ -524,7 +521,7 @@ ahr_status ahr_batch_get_info(const ahr_batch* h, ahr_batch_info* info) {
     info->n_tot = b->n_tot;
     info->nnz_net = b->nnz_net;
     info->nnz_hint = b->nnz_hint;
-    info->n_long_rows = b->n_long;
+    info->n_long_rows = b->rc.n_long;
     info->n_captured = static_cast<int32_t>(b->cache.size());
     return AHR_OK;
 }
@@ -599,7 +596,8 @@ ahr_status ahr_batch_autotune(ahr_batch* h, const ahr_filter_spec* spec, int32_t
         int best_l = 0, best_t = 0;
         std::vector<ahr::Captured*> before = b->cache;
         try {
-            for (int lanes = 1; lanes <= 32; lanes <<= 1)
+            const int cand[] = {1, 2, 4, 8, 16, 32, AHR_HOP_ROW_BLOCK};
+            for (int lanes : cand)
                 for (int ct = ncols; ct >= 1; ct >>= 1) {
                     ahr::batch_filter(*b, *spec, in.p, out.p, ncols, true, lanes, ct, s);   // capture + warm
                     ahr::batch_filter(*b, *spec, in.p, out.p, ncols, true, lanes, ct, s);

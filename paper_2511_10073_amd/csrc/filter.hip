@@ -111,6 +111,52 @@ struct RowRef {
     const int2* hint_ent;
 };
 
+// Row blocks: a short row starts a block when it is the first row, the
+// first instance or auxiliary row, follows a long row, or when its combined
+// entry offset (netlist + hints) or its index enters a new window of
+// kRbEntries entries / kRbRows rows; it ends one when the next row starts
+// one or is long.  A block so has at most kRbRows rows and fewer than
+// kRbEntries + kLongRow entries.
+__device__ __forceinline__ bool rb_break(int32_t r, int32_t n_inst, const int32_t* net_rp, const int32_t* hint_rp) {
+    // is there a block boundary between rows r - 1 and r (both short)?
+    const int64_t c1 = static_cast<int64_t>(net_rp[r]) + hint_rp[r];
+    const int64_t c0 = static_cast<int64_t>(net_rp[r - 1]) + hint_rp[r - 1];
+    return r == n_inst || c1 / kRbEntries != c0 / kRbEntries || r / kRbRows != (r - 1) / kRbRows;
+}
+
+__global__ void k_rb_marks(int32_t n, int32_t n_inst, const int32_t* __restrict__ net_rp,
+                           const int32_t* __restrict__ hint_rp, const int32_t* __restrict__ is_long,
+                           int32_t* __restrict__ start, int32_t* __restrict__ end) {
+    int64_t r64 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r64 >= n) return;
+    const int32_t r = static_cast<int32_t>(r64);
+    int32_t st = 0, en = 0;
+    if (!is_long[r]) {
+        st = (r == 0 || is_long[r - 1] || rb_break(r, n_inst, net_rp, hint_rp)) ? 1 : 0;
+        en = (r == n - 1 || is_long[r + 1] || rb_break(r + 1, n_inst, net_rp, hint_rp)) ? 1 : 0;
+    }
+    start[r] = st;
+    end[r] = en;
+}
+
+__global__ void k_rb_desc(int32_t n_rb, const int32_t* __restrict__ starts, const int32_t* __restrict__ ends,
+                          const int32_t* __restrict__ net_rp, const int32_t* __restrict__ hint_rp, int4* __restrict__ rb) {
+    int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n_rb) return;
+    const int32_t r0 = starts[k], r1 = ends[k] + 1;
+    rb[2 * k] = make_int4(r0, r1, net_rp[r0], net_rp[r1]);
+    rb[2 * k + 1] = make_int4(hint_rp[r0], hint_rp[r1], 0, 0);
+}
+
+__global__ void k_coef(int32_t n, const float* __restrict__ scale, const double* __restrict__ lam, double sigma,
+                       float2* __restrict__ coef) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    float cr, kr;
+    hop_coef(scale[r], *lam, sigma, cr, kr);
+    coef[r] = make_float2(cr, kr);
+}
+
 // ---------------------------------------------------------------- degrees
 
 // Degree d_i = qdeg_i 2^-32 + sum_j |hint_ij| + sigma, scale s_i = d_i^-1/2,
@@ -453,6 +499,8 @@ struct HopArgs {
     const int32_t* chunk_row;
     const int32_t* chunk0;
     double* partial;
+    const int4* rb;           // row blocks (two int4 each)
+    int32_t n_rb;             // row blocks of this hop (placed after the chunk workgroups)
     int band;                 // 0: none, 1: acc = alpha z', 2: acc += alpha z'
     float alpha;
     int last;
@@ -679,6 +727,94 @@ __global__ void __launch_bounds__(kBT) k_hop(HopArgs a0) {
     if (l == 0) epilogue<C>(a, r, ops, sum);
 }
 
+// Row-block form of the hop: one workgroup per block of consecutive short
+// rows.  Its entries are two contiguous ranges (netlist, hints), streamed
+// with coalesced loads, kRbUnroll per thread in flight, each gathering its
+// neighbour's C values; the weighted products go to LDS, and one thread per
+// row adds its row's products in entry order (netlist, then hints) and
+// applies the epilogue.
+constexpr int kRbCap = kRbEntries + kLongRow;
+constexpr int kRbUnroll = (kRbCap + kBT - 1) / kBT;
+
+template <int C, bool NT>
+__device__ __forceinline__ void hop_row_block(const HopArgs& a, int blk) {
+    __shared__ __align__(16) float prod[kRbCap * C];
+    __shared__ int32_t nrp[kRbRows + 1], hrp[kRbRows + 1];   // row starts in prod; [nr] = the block's end
+    const int4 d0 = a.rb[2 * blk], d1 = a.rb[2 * blk + 1];
+    const int r0 = d0.x, nr = d0.y - d0.x;
+    const int net_lo = d0.z, en = d0.w - d0.z;
+    const int hint_lo = d1.x, e = en + (d1.y - d1.x);
+    const int t = threadIdx.x;
+    int2 ent[kRbUnroll];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+        const int k = t + u * kBT;
+        if (k < e) {
+            const int2* p = k < en ? a.m.net_ent + net_lo + k : a.m.hint_ent + hint_lo + (k - en);
+            if constexpr (NT) {
+                long long v = __builtin_nontemporal_load(reinterpret_cast<const long long*>(p));
+                ent[u] = make_int2(static_cast<int>(v & 0xffffffffll), static_cast<int>(v >> 32));
+            } else {
+                ent[u] = *p;
+            }
+        }
+    }
+    RowOps<C> ops;
+    if (t < nr) ops = row_ops<C>(a, r0 + t);
+    if (t < nr) {
+        nrp[t] = a.m.net_rp[r0 + t] - net_lo;
+        hrp[t] = a.m.hint_rp[r0 + t] - hint_lo + en;
+    }
+    if (t == 0) {              // a block may have kRbRows = blockDim.x rows: its end comes from the descriptor
+        nrp[nr] = en;
+        hrp[nr] = e;
+    }
+    Vec<C> v[kRbUnroll];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u)
+        if (t + u * kBT < e) v[u] = vload<C>(a.zin + static_cast<int64_t>(ent[u].x) * C);
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+        const int k = t + u * kBT;
+        if (k < e) {
+            const float w = bits_f(ent[u].y);
+            Vec<C> q;
+#pragma unroll
+            for (int c = 0; c < C; ++c) q.v[c] = w * v[u].v[c];
+            vstore<C>(prod + k * C, q);
+        }
+    }
+    __syncthreads();
+    if (t >= nr) return;
+    Vec<C> sum;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sum.v[c] = 0.f;
+    for (int k = nrp[t]; k < nrp[t + 1]; ++k) {
+        Vec<C> q = vload<C>(prod + k * C);
+#pragma unroll
+        for (int c = 0; c < C; ++c) sum.v[c] += q.v[c];
+    }
+    for (int k = hrp[t]; k < hrp[t + 1]; ++k) {
+        Vec<C> q = vload<C>(prod + k * C);
+#pragma unroll
+        for (int c = 0; c < C; ++c) sum.v[c] += q.v[c];
+    }
+    epilogue<C>(a, r0 + t, ops, sum);
+}
+
+template <int C, bool NT>
+__global__ void __launch_bounds__(kBT) k_hop_rb(HopArgs a0) {
+    const HopArgs a = tile_args<C>(a0);
+    if (static_cast<int>(blockIdx.x) < a.n_chunk_blocks) {
+        hop_chunk<C, NT>(a);
+        return;
+    }
+    const int64_t nb = static_cast<int64_t>(gridDim.x) - a.n_chunk_blocks;     // a multiple of kXcds
+    const int64_t blk = xcd_tile(static_cast<int64_t>(blockIdx.x) - a.n_chunk_blocks, nb);
+    if (blk >= a.n_rb) return;
+    hop_row_block<C, NT>(a, static_cast<int>(blk));
+}
+
 // K = 0: out = (sum alpha) X on movable rows, X on fixed rows.
 template <int C>
 __global__ void k_identity(int32_t n_inst, const uint8_t* __restrict__ flags, const float* __restrict__ in,
@@ -704,7 +840,7 @@ __global__ void k_relax(int32_t n_inst, const uint8_t* __restrict__ flags, const
 // column tiles of C columns each run as blockIdx.y.
 template <int C, int G>
 void launch_hop(const HopArgs& a, int32_t n_long_rows, double bytes, int ntiles, hipStream_t s) {
-    constexpr int U = 32 / G > 0 ? (32 / G < 8 ? 32 / G : 8) : 1;   // entries per lane per batch
+    constexpr int U = 16 / G > 8 ? 8 : (16 / G < 1 ? 1 : 16 / G);   // entries per lane per batch (16 per row, at most 8)
     int64_t tiles = grid_for(static_cast<int64_t>(a.n_rows) * G, kBT);
     tiles = (tiles + kXcds - 1) / kXcds * kXcds;                    // see xcd_tile
     int64_t blocks = a.n_chunk_blocks + tiles;
@@ -712,10 +848,31 @@ void launch_hop(const HopArgs& a, int32_t n_long_rows, double bytes, int ntiles,
     {
         ProfScope ps(kStageHop, s, bytes);
         if (g_hop_nt)
-            hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), true>), grid, dim3(kBT), 0, s, a);
+            hipLaunchKernelGGL((k_hop<C, G, U, true>), grid, dim3(kBT), 0, s, a);
         else
-            hipLaunchKernelGGL((k_hop<C, G, (U < 1 ? 1 : U), false>), grid, dim3(kBT), 0, s, a);
+            hipLaunchKernelGGL((k_hop<C, G, U, false>), grid, dim3(kBT), 0, s, a);
         AHR_LAUNCHED("k_hop");
+    }
+    if (n_long_rows > 0) {
+        hipLaunchKernelGGL(k_hop_long<C>,
+                           dim3(grid_for(static_cast<int64_t>(n_long_rows) * kWave, kBT), static_cast<unsigned>(ntiles)),
+                           dim3(kBT), 0, s, a, n_long_rows);
+        AHR_LAUNCHED("k_hop_long");
+    }
+}
+
+template <int C>
+void launch_hop_rb(const HopArgs& a, int32_t n_long_rows, double bytes, int ntiles, hipStream_t s) {
+    int64_t tiles = (static_cast<int64_t>(a.n_rb) + kXcds - 1) / kXcds * kXcds;   // see xcd_tile
+    if (tiles < kXcds) tiles = kXcds;
+    const dim3 grid(static_cast<unsigned>(a.n_chunk_blocks + tiles), static_cast<unsigned>(ntiles));
+    {
+        ProfScope ps(kStageHop, s, bytes);
+        if (g_hop_nt)
+            hipLaunchKernelGGL((k_hop_rb<C, true>), grid, dim3(kBT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_hop_rb<C, false>), grid, dim3(kBT), 0, s, a);
+        AHR_LAUNCHED("k_hop_rb");
     }
     if (n_long_rows > 0) {
         hipLaunchKernelGGL(k_hop_long<C>,
@@ -728,6 +885,7 @@ void launch_hop(const HopArgs& a, int32_t n_long_rows, double bytes, int ntiles,
 template <int C>
 void hop_dispatch(const HopArgs& a, int lanes, int32_t n_long_rows, double bytes, int ntiles, hipStream_t s) {
     switch (lanes) {
+        case AHR_HOP_ROW_BLOCK: launch_hop_rb<C>(a, n_long_rows, bytes, ntiles, s); break;
         case 1: launch_hop<C, 1>(a, n_long_rows, bytes, ntiles, s); break;
         case 2: launch_hop<C, 2>(a, n_long_rows, bytes, ntiles, s); break;
         case 4: launch_hop<C, 4>(a, n_long_rows, bytes, ntiles, s); break;
@@ -763,22 +921,25 @@ ChainView chain_view(Graph& g, const ahr_filter_spec& spec) {
     v.hint_rp = g.xhint_rp.p;
     v.hint_ent = g.xhint_ent.p;
     v.scale = g.scale.p;
-    v.coef = nullptr;
+    v.coef = g.coef.p;
     v.lam = g.lam.p;
     v.sigma = spec.sigma;
     v.flags = g.nl.node_flags;
     v.perm = g.perm.p;
-    v.long_rows = g.long_rows.p;
-    v.chunk_row = g.chunk_row.p;
-    v.chunk0 = g.long_chunk0.p;
-    v.partial = g.partial.p;
+    v.long_rows = g.rc.long_rows.p;
+    v.chunk_row = g.rc.chunk_row.p;
+    v.chunk0 = g.rc.long_chunk0.p;
+    v.partial = g.rc.partial.p;
+    v.rb = g.rc.rb.p;
     v.n_tot = g.n_tot;
     v.n_inst = g.n_inst;
-    v.n_long = g.n_long;
-    v.n_long_inst = g.n_long_inst;
-    v.n_chunks = g.n_chunks;
-    v.n_chunks_inst = g.n_chunks_inst;
-    v.nnz_inst = g.nnz_inst;
+    v.n_long = g.rc.n_long;
+    v.n_long_inst = g.rc.n_long_inst;
+    v.n_chunks = g.rc.n_chunks;
+    v.n_chunks_inst = g.rc.n_chunks_inst;
+    v.n_rb = g.rc.n_rb;
+    v.n_rb_inst = g.rc.n_rb_inst;
+    v.nnz_inst = g.rc.nnz_inst;
     v.nnz_all = static_cast<int64_t>(g.nnz_net) + g.nnz_hint;
     v.z0 = g.z0.p;
     v.z1 = g.z1.p;
@@ -802,6 +963,8 @@ HopArgs hop_args(const ChainView& v, const float* in, float* out, int ncols) {
     h.chunk_row = v.chunk_row;
     h.chunk0 = v.chunk0;
     h.partial = v.partial;
+    h.rb = v.rb;
+    h.n_rb = 0;
     h.alpha_sum = 0.f;
     h.band = 0;
     h.alpha = 0.f;
@@ -844,9 +1007,10 @@ void hops_c(Graph& g, const ahr_filter_spec& spec, const float* in, int lanes, h
         h.zin = zin;
         h.zout = g.zh[j].p;
         const bool inst_only = j == 2;
-        h.n_rows = inst_only ? g.n_inst : g.n_tot;
-        h.n_chunk_blocks = inst_only ? g.n_chunks_inst : g.n_chunks;
-        hop_dispatch<C>(h, lanes, inst_only ? g.n_long_inst : g.n_long, hop_bytes(v, h, C), 1, s);
+        h.n_rows = inst_only ? v.n_inst : v.n_tot;
+        h.n_chunk_blocks = inst_only ? v.n_chunks_inst : v.n_chunks;
+        h.n_rb = inst_only ? v.n_rb_inst : v.n_rb;
+        hop_dispatch<C>(h, lanes, inst_only ? v.n_long_inst : v.n_long, hop_bytes(v, h, C), 1, s);
         zin = g.zh[j].p;
     }
 }
@@ -886,6 +1050,7 @@ void chain_c(const ChainView& v, const ahr_filter_spec& spec, const float* in, f
         h.alpha = aj;
         h.n_rows = h.last ? v.n_inst : v.n_tot;
         h.n_chunk_blocks = h.last ? v.n_chunks_inst : v.n_chunks;
+        h.n_rb = h.last ? v.n_rb_inst : v.n_rb;
         hop_dispatch<CT>(h, lanes, h.last ? v.n_long_inst : v.n_long, hop_bytes(v, h, C), C / CT, s);
         has_acc = has_acc || isb;
         float* t = zin;
@@ -945,46 +1110,88 @@ void expand_batch_c(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, 
 
 }  // namespace
 
-void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, DevBuf<int32_t>& long_rows,
-                 DevBuf<int32_t>& long_chunk0, DevBuf<int32_t>& chunk_row, DevBuf<double>& partial, int32_t& n_long,
-                 int32_t& n_long_inst, int32_t& n_chunks, int32_t& n_chunks_inst, int64_t& nnz_inst,
+void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,
                  DevBuf<int64_t>& scan_tmp, hipStream_t s) {
     DevBuf<int32_t> is_long, rank, nch;
-    is_long.ensure(static_cast<size_t>(N) + 1, s);
+    const size_t n1 = static_cast<size_t>(N) + 1;
+    is_long.ensure(n1, s);
     hipLaunchKernelGGL(k_row_len, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, net_rp, hint_rp, is_long.p);
     AHR_LAUNCHED("k_row_len");
-    rank.ensure(static_cast<size_t>(N) + 1, s);
+    rank.ensure(n1, s);
     scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i32(is_long.p, rank.p, N, scan_tmp.p, s);
     int32_t t1[4];
     read_scalars({rank.p + N, rank.p + n_inst, net_rp + n_inst, hint_rp + n_inst}, t1, s);
-    n_long = t1[0];
-    n_long_inst = t1[1];
-    nnz_inst = static_cast<int64_t>(t1[2]) + t1[3];
-    long_rows.ensure(static_cast<size_t>(n_long) + 1, s);
-    list_rows(is_long.p, rank.p, N, long_rows.p, s);
-    nch.ensure(static_cast<size_t>(n_long) + 1, s);
-    long_chunk0.ensure(static_cast<size_t>(n_long) + 1, s);
-    if (n_long) {
-        hipLaunchKernelGGL(k_long_nchunks, dim3(grid_for(n_long, kBT)), dim3(kBT), 0, s, n_long, long_rows.p, net_rp,
-                           hint_rp, nch.p);
+    rc.n_long = t1[0];
+    rc.n_long_inst = t1[1];
+    rc.nnz_inst = static_cast<int64_t>(t1[2]) + t1[3];
+    rc.has_rb = 0;
+    rc.long_rows.ensure(static_cast<size_t>(rc.n_long) + 1, s);
+    list_rows(is_long.p, rank.p, N, rc.long_rows.p, s);
+    nch.ensure(static_cast<size_t>(rc.n_long) + 1, s);
+    rc.long_chunk0.ensure(static_cast<size_t>(rc.n_long) + 1, s);
+    if (rc.n_long) {
+        hipLaunchKernelGGL(k_long_nchunks, dim3(grid_for(rc.n_long, kBT)), dim3(kBT), 0, s, rc.n_long,
+                           rc.long_rows.p, net_rp, hint_rp, nch.p);
         AHR_LAUNCHED("k_long_nchunks");
     }
-    scan_tmp.ensure(scan_tmp_elems(n_long), s);
-    scan_i32_to_i32(nch.p, long_chunk0.p, n_long, scan_tmp.p, s);
+    scan_tmp.ensure(scan_tmp_elems(rc.n_long), s);
+    scan_i32_to_i32(nch.p, rc.long_chunk0.p, rc.n_long, scan_tmp.p, s);
     int32_t t2[2];
-    read_scalars({long_chunk0.p + n_long, long_chunk0.p + n_long_inst}, t2, s);
-    n_chunks = t2[0];
-    n_chunks_inst = t2[1];
-    chunk_row.ensure(static_cast<size_t>(n_chunks) + 1, s);
-    if (n_long) {
-        hipLaunchKernelGGL(k_chunk_rows, dim3(n_long), dim3(kBT), 0, s, n_long, long_chunk0.p, chunk_row.p);
+    read_scalars({rc.long_chunk0.p + rc.n_long, rc.long_chunk0.p + rc.n_long_inst}, t2, s);
+    rc.n_chunks = t2[0];
+    rc.n_chunks_inst = t2[1];
+    rc.chunk_row.ensure(static_cast<size_t>(rc.n_chunks) + 1, s);
+    if (rc.n_long) {
+        hipLaunchKernelGGL(k_chunk_rows, dim3(rc.n_long), dim3(kBT), 0, s, rc.n_long, rc.long_chunk0.p,
+                           rc.chunk_row.p);
         AHR_LAUNCHED("k_chunk_rows");
     }
-    partial.ensure(static_cast<size_t>(n_chunks) * 8 + 8, s);
+    rc.partial.ensure(static_cast<size_t>(rc.n_chunks) * 8 + 8, s);
     is_long.release(s);
     rank.release(s);
     nch.release(s);
+}
+
+void row_blocks(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,
+                DevBuf<int64_t>& scan_tmp, hipStream_t s) {
+    if (rc.has_rb) return;
+    DevBuf<int32_t> is_long, st, en, srank, erank, starts, ends;
+    const size_t n1 = static_cast<size_t>(N) + 1;
+    is_long.ensure(n1, s);
+    hipLaunchKernelGGL(k_row_len, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, net_rp, hint_rp, is_long.p);
+    AHR_LAUNCHED("k_row_len");
+    st.ensure(n1, s);
+    en.ensure(n1, s);
+    hipLaunchKernelGGL(k_rb_marks, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, n_inst, net_rp, hint_rp, is_long.p, st.p,
+                       en.p);
+    AHR_LAUNCHED("k_rb_marks");
+    srank.ensure(n1, s);
+    erank.ensure(n1, s);
+    scan_tmp.ensure(scan_tmp_elems(N), s);
+    scan_i32_to_i32(st.p, srank.p, N, scan_tmp.p, s);
+    scan_i32_to_i32(en.p, erank.p, N, scan_tmp.p, s);
+    int32_t t[2];
+    read_scalars({srank.p + N, srank.p + n_inst}, t, s);
+    rc.n_rb = t[0];
+    rc.n_rb_inst = t[1];
+    starts.ensure(static_cast<size_t>(rc.n_rb) + 1, s);
+    ends.ensure(static_cast<size_t>(rc.n_rb) + 1, s);
+    list_rows(st.p, srank.p, N, starts.p, s);
+    list_rows(en.p, erank.p, N, ends.p, s);
+    rc.rb.ensure(2 * static_cast<size_t>(rc.n_rb) + 2, s);
+    if (rc.n_rb) {
+        hipLaunchKernelGGL(k_rb_desc, dim3(grid_for(rc.n_rb, kBT)), dim3(kBT), 0, s, rc.n_rb, starts.p, ends.p, net_rp,
+                           hint_rp, rc.rb.p);
+        AHR_LAUNCHED("k_rb_desc");
+    }
+    rc.has_rb = 1;
+    for (auto* b : {&is_long, &st, &en, &srank, &erank, &starts, &ends}) b->release(s);
+}
+
+void hop_coefs(int32_t n, const float* scale, const double* lam, double sigma, float2* coef, hipStream_t s) {
+    hipLaunchKernelGGL(k_coef, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, n, scale, lam, sigma, coef);
+    AHR_LAUNCHED("k_coef");
 }
 
 ExpandArgs expand_args(const Graph& g) {
@@ -1065,8 +1272,7 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     RowRef m{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
 
     if (g.rows_version != g.hint_version) {
-        row_classes(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, g.long_rows, g.long_chunk0, g.chunk_row, g.partial,
-                    g.n_long, g.n_long_inst, g.n_chunks, g.n_chunks_inst, g.nnz_inst, g.scan_tmp, s);
+        row_classes(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, g.rc, g.scan_tmp, s);
         g.rows_version = g.hint_version;
     }
 
@@ -1079,12 +1285,12 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     hipLaunchKernelGGL(k_deg_short<G>, dim3(grid_for(static_cast<int64_t>(N) * G, kBT)), dim3(kBT), 0, s, N, m,
                        g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
     AHR_LAUNCHED("k_deg_short");
-    if (g.n_long) {
-        hipLaunchKernelGGL(k_chunk_absdeg, dim3(g.n_chunks), dim3(kBT), 0, s, m, g.long_rows.p, g.chunk_row.p,
-                           g.long_chunk0.p, g.partial.p);
+    if (g.rc.n_long) {
+        hipLaunchKernelGGL(k_chunk_absdeg, dim3(g.rc.n_chunks), dim3(kBT), 0, s, m, g.rc.long_rows.p, g.rc.chunk_row.p,
+                           g.rc.long_chunk0.p, g.rc.partial.p);
         AHR_LAUNCHED("k_chunk_absdeg");
-        hipLaunchKernelGGL(k_long_deg_final, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long, g.long_rows.p,
-                           g.long_chunk0.p, g.partial.p, g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
+        hipLaunchKernelGGL(k_long_deg_final, dim3(grid_for(g.rc.n_long, kBT)), dim3(kBT), 0, s, g.rc.n_long, g.rc.long_rows.p,
+                           g.rc.long_chunk0.p, g.rc.partial.p, g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
         AHR_LAUNCHED("k_long_deg_final");
     }
     if (spec.lambda_mode == AHR_LAMBDA_FIXED) {
@@ -1096,27 +1302,30 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
         hipLaunchKernelGGL(k_gersh_short<G>, dim3(kGershGrid), dim3(kBT), 0, s, N, m,
                            g.deg.p, g.scale.p, sigma, g.lam.p);
         AHR_LAUNCHED("k_gersh_short");
-        if (g.n_long) {
-            hipLaunchKernelGGL(k_chunk_gersh, dim3(g.n_chunks), dim3(kBT), 0, s, m, g.long_rows.p, g.chunk_row.p,
-                               g.long_chunk0.p, g.scale.p, g.partial.p);
+        if (g.rc.n_long) {
+            hipLaunchKernelGGL(k_chunk_gersh, dim3(g.rc.n_chunks), dim3(kBT), 0, s, m, g.rc.long_rows.p, g.rc.chunk_row.p,
+                               g.rc.long_chunk0.p, g.scale.p, g.rc.partial.p);
             AHR_LAUNCHED("k_chunk_gersh");
-            hipLaunchKernelGGL(k_long_gersh_final, dim3(grid_for(g.n_long, kBT)), dim3(kBT), 0, s, g.n_long,
-                               g.long_rows.p, g.long_chunk0.p, g.partial.p, g.deg.p, g.scale.p, sigma, g.lam.p);
+            hipLaunchKernelGGL(k_long_gersh_final, dim3(grid_for(g.rc.n_long, kBT)), dim3(kBT), 0, s, g.rc.n_long,
+                               g.rc.long_rows.p, g.rc.long_chunk0.p, g.rc.partial.p, g.deg.p, g.scale.p, sigma, g.lam.p);
             AHR_LAUNCHED("k_long_gersh_final");
         }
     }
+    g.coef.ensure(static_cast<size_t>(N) + 1, s);
+    hop_coefs(N, g.scale.p, g.lam.p, sigma, g.coef.p, s);
     g.norm_version = g.hint_version;
     g.norm_sigma = spec.sigma;
     g.norm_mode = spec.lambda_mode;
     g.norm_fixed = spec.lambda_fixed;
 }
 
-int g_hop_lanes = 2;   // lanes per short row (set by the tuner)
+int g_hop_lanes = 4;   // lanes per short row (set by the tuner)
 int g_hop_nt = 0;      // non-temporal entry loads
 
 void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int32_t ncols, hipStream_t s) {
     normalise(g, spec, s);
     int lanes = g_hop_lanes;
+    if (lanes == AHR_HOP_ROW_BLOCK) row_blocks(g.xnet_rp.p, g.xhint_rp.p, g.n_tot, g.n_inst, g.rc, g.scan_tmp, s);
     switch (ncols) {
         case 1: filter_c<1>(g, spec, in, out, lanes, s); break;
         case 2: filter_c<2>(g, spec, in, out, lanes, s); break;
@@ -1129,6 +1338,7 @@ void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* o
 void run_hops(Graph& g, const ahr_filter_spec& spec, const float* in, int32_t ncols, hipStream_t s) {
     normalise(g, spec, s);
     int lanes = g_hop_lanes;
+    if (lanes == AHR_HOP_ROW_BLOCK) row_blocks(g.xnet_rp.p, g.xhint_rp.p, g.n_tot, g.n_inst, g.rc, g.scan_tmp, s);
     switch (ncols) {
         case 1: hops_c<1>(g, spec, in, lanes, s); break;
         case 2: hops_c<2>(g, spec, in, lanes, s); break;

@@ -53,24 +53,45 @@ __global__ void k_exec_lens(int32_t n_tot, int32_t n_inst, const int32_t* __rest
     len[r] = rp[s + 1] - rp[s];
 }
 
-// One thread per execution-order entry: find its row (binary search over
-// the execution row pointers), copy the canonical entry with its column
-// renumbered and its weight as float32.  Entry-parallel, so rows of any
-// length cost the same per entry.
-__global__ void k_exec_net(int32_t nnz, int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
-                           const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
-                           const int32_t* __restrict__ col, const int64_t* __restrict__ q,
-                           const int32_t* __restrict__ xrp, int2* __restrict__ xent) {
-    int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= nnz) return;
-    int lo = 0, hi = n_tot;     // row r with xrp[r] <= k < xrp[r+1]
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (xrp[mid] <= k) lo = mid; else hi = mid;
-    }
-    int s = src_row(lo, n_inst, perm);
-    int a = rp[s] + static_cast<int>(k - xrp[lo]);
-    xent[k] = make_int2(map_col(col[a], n_inst, iperm), f_bits(static_cast<float>(static_cast<double>(q[a]) * 0x1p-32)));
+// Execution-order netlist rows: each row copies its canonical row's
+// entries (order kept) with columns renumbered and weights as float32.
+// G lanes per row of at most kShortRow entries; one workgroup per longer
+// row (k_exec_net_long).
+constexpr int kShortRow = 64;
+
+__device__ __forceinline__ int2 exec_entry(int32_t c, int64_t q, int n_inst, const int32_t* iperm) {
+    return make_int2(map_col(c, n_inst, iperm), f_bits(static_cast<float>(static_cast<double>(q) * 0x1p-32)));
+}
+
+__global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col, const int64_t* __restrict__ q,
+                                                  const int32_t* __restrict__ xrp, int2* __restrict__ xent) {
+    constexpr int G = 8;
+    int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
+    int l = threadIdx.x & (G - 1);
+    if (r >= n_tot) return;
+    int d = xrp[r], len = xrp[r + 1] - d;
+    if (len > kShortRow) return;                           // group-uniform
+    int a = rp[src_row(static_cast<int>(r), n_inst, perm)];
+    for (int k = l; k < len; k += G) xent[d + k] = exec_entry(col[a + k], q[a + k], n_inst, iperm);
+}
+
+__global__ void __launch_bounds__(kBT) k_exec_net_long(const int32_t* __restrict__ rows, int32_t n_inst,
+                                                       const int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ iperm,
+                                                       const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                       const int64_t* __restrict__ q, const int32_t* __restrict__ xrp,
+                                                       int2* __restrict__ xent) {
+    const int r = rows[blockIdx.x];
+    const int d = xrp[r], len = xrp[r + 1] - d;
+    const int a = rp[src_row(r, n_inst, perm)];
+    for (int k = threadIdx.x; k < len; k += kBT) xent[d + k] = exec_entry(col[a + k], q[a + k], n_inst, iperm);
+}
+
+__global__ void k_long_flags(int32_t n_tot, const int32_t* __restrict__ xrp, int32_t* __restrict__ flag) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < n_tot) flag[r] = (xrp[r + 1] - xrp[r] > kShortRow) ? 1 : 0;
 }
 
 __global__ void k_exec_qdeg(int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
@@ -107,10 +128,29 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     len.release(s);
     g.xnet_ent.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
-    if (g.nnz_net)
-        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(g.nnz_net, kBT)), dim3(kBT), 0, s, g.nnz_net, N, n, g.perm.p,
-                           g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
-    AHR_LAUNCHED("k_exec_net");
+    if (g.nnz_net) {
+        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N, n,
+                           g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
+        AHR_LAUNCHED("k_exec_net");
+        DevBuf<int32_t> flag, rank, rows;
+        flag.ensure(static_cast<size_t>(N) + 1, s);
+        rank.ensure(static_cast<size_t>(N) + 1, s);
+        hipLaunchKernelGGL(k_long_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.xnet_rp.p, flag.p);
+        AHR_LAUNCHED("k_long_flags");
+        scan_i32_to_i32(flag.p, rank.p, N, g.scan_tmp.p, s);
+        int32_t n_long = 0;
+        read_scalars({rank.p + N}, &n_long, s);
+        if (n_long) {
+            rows.ensure(static_cast<size_t>(n_long) + 1, s);
+            list_rows(flag.p, rank.p, N, rows.p, s);
+            hipLaunchKernelGGL(k_exec_net_long, dim3(n_long), dim3(kBT), 0, s, rows.p, n, g.perm.p, g.iperm.p,
+                               g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
+            AHR_LAUNCHED("k_exec_net_long");
+        }
+        flag.release(s);
+        rank.release(s);
+        rows.release(s);
+    }
     hipLaunchKernelGGL(k_exec_qdeg, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, n, g.perm.p, g.qdeg.p, g.xqdeg.p);
     AHR_LAUNCHED("k_exec_qdeg");
     g.has_layout = 1;

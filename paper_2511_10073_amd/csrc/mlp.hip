@@ -34,17 +34,9 @@ static_assert(oB3 + 1 == kNP, "parameter layout");
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// float32 -> bfloat16, round to nearest even
-__device__ __forceinline__ short bf16_bits(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<short>(u >> 16);
-}
-__device__ __forceinline__ float bf16_round(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xFFFF0000u);
-}
+// float32 -> bfloat16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ short bf16_bits(float x) { return __builtin_bit_cast(short, static_cast<__bf16>(x)); }
+__device__ __forceinline__ float bf16_round(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
 
 // ---------------------------------------------------------------- inference
 
@@ -84,31 +76,26 @@ __device__ __forceinline__ float mlp_tile(const MlpRegs& R, const float f[4]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) x[j] = bf16_bits(f[j]);
     v4s a1[4], a2[4];
+    // each layer's accumulator starts at its bias (float32)
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        v4f acc = {R.b1[4 * m], R.b1[4 * m + 1], R.b1[4 * m + 2], R.b1[4 * m + 3]};
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[m], x, acc, 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float v = acc[j] + R.b1[4 * m + j];
-            a1[m][j] = bf16_bits(v > 0.f ? v : 0.f);
-        }
+        for (int j = 0; j < 4; ++j) a1[m][j] = bf16_bits(acc[j] > 0.f ? acc[j] : 0.f);
     }
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        v4f acc = {R.b2[4 * n], R.b2[4 * n + 1], R.b2[4 * n + 2], R.b2[4 * n + 3]};
 #pragma unroll
         for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w2[4 * n + m], a1[m], acc, 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float v = acc[j] + R.b2[4 * n + j];
-            a2[n][j] = bf16_bits(v > 0.f ? v : 0.f);
-        }
+        for (int j = 0; j < 4; ++j) a2[n][j] = bf16_bits(acc[j] > 0.f ? acc[j] : 0.f);
     }
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    v4f acc = {R.b3, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w3[m], a2[m], acc, 0, 0, 0);
-    return acc[0] + R.b3;
+    return acc[0];
 }
 
 // o[s] for a flat list of feature rows feats[n][8].
@@ -131,10 +118,11 @@ __global__ void __launch_bounds__(kBT) k_mlp_forward(const float* __restrict__ P
     }
 }
 
-// Signal value h of (execution row, column) from the scaled chain z.
-__device__ __forceinline__ float unscale(const float* z, int C, int r, int c, float s, const float* in,
+// Signal value h of (execution row, column) from the scaled chain z
+// (inv_s = 1 / s of the row; 0 for an isolated row, whose value is its input).
+__device__ __forceinline__ float unscale(const float* z, int C, int r, int c, float inv_s, const float* in,
                                          const int32_t* perm) {
-    return s > 0.f ? z[static_cast<int64_t>(r) * C + c] / s : in[static_cast<int64_t>(perm[r]) * C + c];
+    return inv_s > 0.f ? z[static_cast<int64_t>(r) * C + c] * inv_s : in[static_cast<int64_t>(perm[r]) * C + c];
 }
 
 struct LearnArgs {
@@ -145,6 +133,7 @@ struct LearnArgs {
     const double* deg;
     const float* hsum;
     const float* stats;     // [2][C]: mean, std of h3
+    const float4* rowf;     // [n_inst] per execution row: 1/s, log1p(d), hsum/d
     const float* in;
     float* out;
     float* feats;           // optional [n_inst * C][8], instance order
@@ -157,74 +146,104 @@ struct LearnArgs {
     int write_out;
 };
 
-// Features of sample (execution row r, column c): lane group g computes
-// features 4g..4g+3.
-__device__ __forceinline__ void sample_features(const LearnArgs& a, int C, int r, int c, int g, float f[4], float h[3]) {
-    const float s = a.scale[r];
-    h[0] = unscale(a.z1, C, r, c, s, a.in, a.perm);
-    h[1] = unscale(a.z2, C, r, c, s, a.in, a.perm);
-    h[2] = unscale(a.z3, C, r, c, s, a.in, a.perm);
-    const float mc = a.stats[c], sc = a.stats[C + c];
-    const double d = a.deg[r];
-    if (g == 0) {
-        f[0] = (h[0] - h[2]) / sc;
-        f[1] = (h[1] - h[2]) / sc;
-        f[2] = (h[2] - mc) / sc;
-        f[3] = static_cast<float>(log1p(d));
-    } else if (g == 1) {
-        f[0] = d > 0 ? static_cast<float>(static_cast<double>(a.hsum[r]) / d) : 0.f;
-        f[1] = f[2] = f[3] = 0.f;
-    } else {
-        f[0] = f[1] = f[2] = f[3] = 0.f;
+// Per-row inputs of the features, once per row instead of once per column:
+// 1/s, log1p(d), hsum/d (the last two in float64, then rounded).
+__global__ void k_row_feat(int32_t n, const float* __restrict__ scale, const double* __restrict__ deg,
+                           const float* __restrict__ hsum, float4* __restrict__ rowf) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const float s = scale[r];
+    const double d = deg[r];
+    rowf[r] = make_float4(s > 0.f ? 1.f / s : 0.f, static_cast<float>(log1p(d)),
+                          d > 0 ? static_cast<float>(static_cast<double>(hsum[r]) / d) : 0.f, 0.f);
+}
+
+// Inputs of one tile's sample for lane group 0 (the hops, for features
+// 0..3 and the epilogue) or group 1 (the row values, for feature 4); the
+// other groups feed zeros.
+struct TileIn {
+    float h[3];
+    float4 rf;
+};
+
+template <int C>
+__device__ __forceinline__ TileIn tile_load(const LearnArgs& a, int64_t smp, int g) {
+    TileIn t;
+    const int64_t r = smp / C;
+    const int c = static_cast<int>(smp % C);
+    t.h[0] = t.h[1] = t.h[2] = 0.f;
+    t.rf = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r < a.n_inst && g < 2) {
+        t.rf = a.rowf[r];
+        if (g == 0) {
+            const int rr = static_cast<int>(r);
+            t.h[0] = unscale(a.z1, C, rr, c, t.rf.x, a.in, a.perm);
+            t.h[1] = unscale(a.z2, C, rr, c, t.rf.x, a.in, a.perm);
+            t.h[2] = unscale(a.z3, C, rr, c, t.rf.x, a.in, a.perm);
+        }
     }
+    return t;
 }
 
 // The learned filter over the instance rows: 16 samples (16/C rows x C
-// columns) per wavefront tile.
+// columns) per wavefront tile.  A lane's column is the same in every tile
+// (16 % C == 0), so its column statistics are loaded once; the next tile's
+// inputs are loaded while the current one runs through the network.
 template <int C>
 __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
     MlpRegs R;
     load_mlp(a.params, R);
     const int l = lane_id(), g = l >> 4, sl = l & 15;
+    const int c = sl % C;
+    const float mc = a.stats[c], sc = a.stats[C + c], inv_sc = 1.f / sc;
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBT / kWave);
     const int64_t ntiles = (static_cast<int64_t>(a.n_inst) * C + 15) / 16;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * (kBT / kWave) + wave_id(); t < ntiles; t += waves) {
-        const int64_t smp = t * 16 + sl;
-        const int r = static_cast<int>(smp / C), c = static_cast<int>(smp % C);
-        const bool valid = r < a.n_inst;
-        float f[4] = {0.f, 0.f, 0.f, 0.f}, h[3] = {0.f, 0.f, 0.f};
-        if (valid) sample_features(a, C, r, c, g, f, h);
-        float o = mlp_tile(R, f);
-        if (l >= 16 || !valid) continue;
-        const int inst = a.perm[r];
-        const int64_t oc = static_cast<int64_t>(inst) * C + c;
-        if (a.feats) {
-            float* fp = a.feats + (static_cast<int64_t>(inst) * C + c) * kFP;
-            fp[0] = f[0], fp[1] = f[1], fp[2] = f[2], fp[3] = f[3];
-            fp[5] = fp[6] = fp[7] = 0.f;
+    int64_t t = static_cast<int64_t>(blockIdx.x) * (kBT / kWave) + wave_id();
+    TileIn cur = tile_load<C>(a, t * 16 + sl, g);
+    for (; t < ntiles; t += waves) {
+        const TileIn nxt = tile_load<C>(a, (t + waves) * 16 + sl, g);
+        float f[4];
+        if (g == 0) {
+            f[0] = (cur.h[0] - cur.h[2]) * inv_sc;
+            f[1] = (cur.h[1] - cur.h[2]) * inv_sc;
+            f[2] = (cur.h[2] - mc) * inv_sc;
+            f[3] = cur.rf.y;
+        } else {
+            f[0] = g == 1 ? cur.rf.z : 0.f;
+            f[1] = f[2] = f[3] = 0.f;
         }
-        if (a.hops) {
-            const int64_t nc = static_cast<int64_t>(a.n_inst) * C;
-            a.hops[oc] = h[0];
-            a.hops[nc + oc] = h[1];
-            a.hops[2 * nc + oc] = h[2];
+        const float o = mlp_tile(R, f);
+        const int64_t r = (t * 16 + sl) / C;
+        if (l < 16 && r < a.n_inst) {
+            const int inst = a.perm[r];
+            const int64_t oc = static_cast<int64_t>(inst) * C + c;
+            if (a.feats) {
+                float* fp = a.feats + oc * kFP;
+                fp[0] = f[0], fp[1] = f[1], fp[2] = f[2], fp[3] = f[3];
+                fp[5] = fp[6] = fp[7] = 0.f;
+            }
+            if (a.hops) {
+                const int64_t nc = static_cast<int64_t>(a.n_inst) * C;
+                a.hops[oc] = cur.h[0];
+                a.hops[nc + oc] = cur.h[1];
+                a.hops[2 * nc + oc] = cur.h[2];
+            }
+            if (a.write_out) {
+                float y = a.beta0 * cur.h[0] + a.beta1 * cur.h[1] + a.beta2 * cur.h[2] + sc * o;
+                a.out[oc] = (a.flags[inst] & AHR_NODE_FIXED) ? a.in[oc] : y;
+            }
         }
-        if (a.write_out) {
-            float y = a.beta0 * h[0] + a.beta1 * h[1] + a.beta2 * h[2] + a.stats[C + c] * o;
-            a.out[oc] = (a.flags[inst] & AHR_NODE_FIXED) ? a.in[oc] : y;
-        }
+        cur = nxt;
     }
 }
 
-// Feature 4 (lane group 1) of every sample, for the exported feature rows.
+// Feature 4 of every sample, for the exported feature rows.
 template <int C>
 __global__ void k_feature4(LearnArgs a) {
     int64_t smp = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (smp >= static_cast<int64_t>(a.n_inst) * C) return;
     const int r = static_cast<int>(smp / C), c = static_cast<int>(smp % C);
-    float f[4], h[3];
-    sample_features(a, C, r, c, 1, f, h);
-    a.feats[(static_cast<int64_t>(a.perm[r]) * C + c) * kFP + 4] = f[0];
+    a.feats[(static_cast<int64_t>(a.perm[r]) * C + c) * kFP + 4] = a.rowf[r].z;
 }
 
 // Column statistics of h3 over movable instance rows (two passes, fixed
@@ -241,10 +260,10 @@ __global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, const float* __res
          r += static_cast<int64_t>(kStatGrid) * kBT) {
         int inst = a.perm[r];
         if (a.flags[inst] & AHR_NODE_FIXED) continue;
-        float s = a.scale[r];
+        const float inv_s = a.rowf[r].x;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            double h = unscale(a.z3, C, static_cast<int>(r), c, s, a.in, a.perm);
+            double h = unscale(a.z3, C, static_cast<int>(r), c, inv_s, a.in, a.perm);
             if (mean) {
                 double d = h - mean[c];
                 acc[c] += d * d;
@@ -449,9 +468,15 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     a.write_out = out != nullptr;
     DevBuf<double> part;
     DevBuf<float> stats;
+    DevBuf<float4> rowf;
     part.ensure(static_cast<size_t>(kStatGrid) * (C + 1), s);
     stats.ensure(2 * C, s);
+    rowf.ensure(static_cast<size_t>(g.n_inst) + 1, s);
     a.stats = stats.p;
+    a.rowf = rowf.p;
+    hipLaunchKernelGGL(k_row_feat, dim3(grid_for(g.n_inst, kBT)), dim3(kBT), 0, s, g.n_inst, g.scale.p, g.deg.p,
+                       g.hsum.p, rowf.p);
+    AHR_LAUNCHED("k_row_feat");
     hipLaunchKernelGGL((k_colstat<C>), dim3(kStatGrid), dim3(kBT), 0, s, a, static_cast<const float*>(nullptr), part.p);
     AHR_LAUNCHED("k_colstat");
     hipLaunchKernelGGL((k_colstat_final<C>), dim3(1), dim3(64), 0, s, part.p, stats.p, 0);
@@ -476,6 +501,7 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     }
     part.release(s);
     stats.release(s);
+    rowf.release(s);
 }
 
 }  // namespace

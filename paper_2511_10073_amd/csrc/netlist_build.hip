@@ -71,14 +71,20 @@ __global__ void k_mark_macro(const uint8_t* __restrict__ flags, int32_t n, int32
     if (i < n) out[i] = (flags[i] & AHR_NODE_MACRO) ? 1 : 0;
 }
 
-__device__ __forceinline__ int32_t net_of_pin(const int32_t* __restrict__ net_ptr, int32_t n_nets, int32_t p) {
-    // last e with net_ptr[e] <= p, skipping empty nets
-    int lo = 0, hi = n_nets;   // answer in [lo, hi)
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (net_ptr[mid] <= p) lo = mid; else hi = mid;
-    }
-    return lo;
+// Net of every pin: one thread per net of at most a wave's worth of pins,
+// one workgroup per bigger net (k_pin_net_big over the big-net list).
+__global__ void k_pin_net(const int32_t* __restrict__ net_ptr, int32_t n_nets, int32_t* __restrict__ pin_net) {
+    int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n_nets) return;
+    const int lo = net_ptr[e], hi = net_ptr[e + 1];
+    if (hi - lo > kWave) return;
+    for (int p = lo; p < hi; ++p) pin_net[p] = static_cast<int32_t>(e);
+}
+
+__global__ void k_pin_net_big(const int32_t* __restrict__ big, const int32_t* __restrict__ net_ptr,
+                              int32_t* __restrict__ pin_net) {
+    const int e = big[blockIdx.x];
+    for (int p = net_ptr[e] + threadIdx.x; p < net_ptr[e + 1]; p += blockDim.x) pin_net[p] = e;
 }
 
 // Integer weight of one clique pair / one star spoke (units of 2^-32),
@@ -96,6 +102,7 @@ __device__ __forceinline__ int64_t q_star(float w, int p) {
 
 struct NetArgs {
     const int32_t* net_ptr;
+    const int32_t* pin_net;
     const int32_t* pin_x;
     const float* net_w;
     const int32_t* star_rank;
@@ -106,7 +113,7 @@ struct NetArgs {
 __global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt) {
     int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_pins) return;
-    int e = net_of_pin(a.net_ptr, a.n_nets, static_cast<int32_t>(p));
+    int e = a.pin_net[p];
     int lo = a.net_ptr[e], hi = a.net_ptr[e + 1];
     int deg = hi - lo;
     if (deg < 2) return;
@@ -121,11 +128,14 @@ __global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt) {
     }
 }
 
+// Raw entries: each pin reserves its whole run of its row's slots with one
+// atomic (the run order inside a row does not matter: rows are sorted by
+// column and equal columns merged by exact integer sums afterwards).
 __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __restrict__ cursor,
                           int32_t* __restrict__ dcol, int64_t* __restrict__ dq) {
     int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_pins) return;
-    int e = net_of_pin(a.net_ptr, a.n_nets, static_cast<int32_t>(p));
+    int e = a.pin_net[p];
     int lo = a.net_ptr[e], hi = a.net_ptr[e + 1];
     int deg = hi - lo;
     if (deg < 2) return;
@@ -133,19 +143,21 @@ __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __
     float w = a.net_w ? a.net_w[e] : 1.0f;
     if (deg <= a.clique_max) {
         int64_t q = q_clique(w, deg);
+        int c = 0;
+        for (int b = lo; b < hi; ++b) c += (a.pin_x[b] != v) ? 1 : 0;
+        if (!c) return;
+        int64_t k = rp[v] + atomicAdd(&cursor[v], c);
         for (int b = lo; b < hi; ++b) {
             int u = a.pin_x[b];
             if (u == v) continue;
-            int slot = atomicAdd(&cursor[v], 1);
-            int64_t k = rp[v] + slot;
             dcol[k] = u;
             dq[k] = q;
+            ++k;
         }
     } else {
         int64_t q = q_star(w, deg);
         int z = a.first_star + a.star_rank[e];
-        int slot = atomicAdd(&cursor[v], 1);
-        int64_t k = rp[v] + slot;
+        int64_t k = rp[v] + atomicAdd(&cursor[v], 1);
         dcol[k] = z;
         dq[k] = q;
         int64_t kz = rp[z] + (p - lo);
@@ -244,24 +256,27 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
     if (valid_row && l == 0) ucnt[r] = __popcll(hm & gm);
 }
 
-// One workgroup per long row: bitonic sort of (column, slot) keys in the
-// row's own segment of `tkey` (global memory; positions past the row end
-// act as +infinity), then an ordered merge of equal columns.
+// One workgroup per long row: bitonic sort of (column, slot) keys --
+// in LDS when the padded row fits `lds_keys` (dynamic shared memory),
+// otherwise in the row's own segment of `tkey` (global memory) -- with
+// positions past the row end acting as +infinity, then an ordered merge of
+// equal columns.
 __global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ cnt,
                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ dcol,
                                                    const int64_t* __restrict__ dq, uint64_t* __restrict__ tkey,
                                                    int32_t* __restrict__ scol, int64_t* __restrict__ sq,
-                                                   int32_t* __restrict__ ucnt) {
+                                                   int32_t* __restrict__ ucnt, int lds_keys) {
+    extern __shared__ uint64_t lkey[];
     __shared__ int red[kBT / kWave];
     __shared__ int carry;
     int r = rows[blockIdx.x];
     int n = cnt[r];
     int64_t base = rp[r];
-    uint64_t* key = tkey + base;
-    for (int k = threadIdx.x; k < n; k += kBT)
-        key[k] = (static_cast<uint64_t>(static_cast<uint32_t>(dcol[base + k])) << 32) | static_cast<uint32_t>(k);
     int P = 1;
     while (P < n) P <<= 1;
+    uint64_t* key = P <= lds_keys ? lkey : tkey + base;
+    for (int k = threadIdx.x; k < n; k += kBT)
+        key[k] = (static_cast<uint64_t>(static_cast<uint32_t>(dcol[base + k])) << 32) | static_cast<uint32_t>(k);
     __threadfence_block();
     __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
@@ -317,17 +332,20 @@ __global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ r
     if (threadIdx.x == 0) ucnt[r] = carry;
 }
 
-// Copy merged rows to their final place, with the row weight sums
-// (16 lanes per row).
-__global__ void __launch_bounds__(kBT) k_compact(int32_t n_rows, const int64_t* __restrict__ rp,
-                                                 const int32_t* __restrict__ ucnt, const int32_t* __restrict__ net_rp,
-                                                 const int32_t* __restrict__ scol, const int64_t* __restrict__ sq,
-                                                 int32_t* __restrict__ col, int64_t* __restrict__ qv,
-                                                 int64_t* __restrict__ qdeg) {
-    constexpr int G = 16;
+// Copy merged rows to their final place, with the row weight sums: G
+// lanes per row for rows of at most kShortRaw raw entries, one workgroup
+// per longer row (k_compact_long).
+constexpr int kShortRaw = 64;
+
+__global__ void __launch_bounds__(kBT) k_compact(int32_t n_rows, const int32_t* __restrict__ cnt,
+                                                 const int64_t* __restrict__ rp, const int32_t* __restrict__ ucnt,
+                                                 const int32_t* __restrict__ net_rp, const int32_t* __restrict__ scol,
+                                                 const int64_t* __restrict__ sq, int32_t* __restrict__ col,
+                                                 int64_t* __restrict__ qv, int64_t* __restrict__ qdeg) {
+    constexpr int G = 8;
     int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
     int l = threadIdx.x & (G - 1);
-    if (r >= n_rows) return;
+    if (r >= n_rows || cnt[r] > kShortRaw) return;     // group-uniform
     int n = ucnt[r];
     int64_t src = rp[r];
     int64_t dst = net_rp[r];
@@ -344,6 +362,33 @@ __global__ void __launch_bounds__(kBT) k_compact(int32_t n_rows, const int64_t* 
     if (l == 0) qdeg[r] = s;
 }
 
+__global__ void __launch_bounds__(kBT) k_compact_long(const int32_t* __restrict__ rows,
+                                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ ucnt,
+                                                      const int32_t* __restrict__ net_rp,
+                                                      const int32_t* __restrict__ scol, const int64_t* __restrict__ sq,
+                                                      int32_t* __restrict__ col, int64_t* __restrict__ qv,
+                                                      int64_t* __restrict__ qdeg) {
+    __shared__ int64_t red[kBT / kWave];
+    const int r = rows[blockIdx.x];
+    const int n = ucnt[r];
+    const int64_t src = rp[r], dst = net_rp[r];
+    int64_t s = 0;
+    for (int k = threadIdx.x; k < n; k += kBT) {
+        int64_t q = sq[src + k];
+        col[dst + k] = scol[src + k];
+        qv[dst + k] = q;
+        s += q;
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) red[wave_id()] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kBT / kWave; ++w) t += red[w];
+        qdeg[r] = t;
+    }
+}
+
 __global__ void k_base_weight(int32_t n_inst, const int32_t* __restrict__ net_rp, const int64_t* __restrict__ qdeg,
                               double* __restrict__ bw) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -351,6 +396,20 @@ __global__ void k_base_weight(int32_t n_inst, const int32_t* __restrict__ net_rp
     int nnz = net_rp[i + 1] - net_rp[i];
     int64_t q = qdeg[i];
     bw[i] = (nnz > 0 && q != 0) ? (static_cast<double>(q) * 0x1p-32) / static_cast<double>(nnz) : 0.0;
+}
+
+// Keys of a long row that one workgroup sorts in LDS: the largest power of
+// two whose keys fit the per-workgroup shared memory with 1 KiB to spare.
+int sort_lds_keys(int device) {
+    static int cached[64] = {0};
+    if (device >= 0 && device < 64 && cached[device]) return cached[device];
+    hipDeviceProp_t prop;
+    AHR_HIP(hipGetDeviceProperties(&prop, device));
+    size_t avail = prop.sharedMemPerBlock > 1024 ? prop.sharedMemPerBlock - 1024 : 0;
+    int k = 1;
+    while (static_cast<size_t>(k) * 2 * sizeof(uint64_t) <= avail && k < (1 << 16)) k <<= 1;
+    if (device >= 0 && device < 64) cached[device] = k;
+    return k;
 }
 
 template <class T>
@@ -454,8 +513,18 @@ void build_netlist(Graph& g, hipStream_t s) {
     g.n_inst = n_inst;
     const int32_t N = g.n_tot;
 
-    // entry counts per row, with parallel edges
-    NetArgs a{nl.net_ptr, g.pin_node_x.p, nl.net_w, star_rank.p, n_nets, n_pins, hp.clique_max, g.first_star};
+    // net of every pin, then entry counts per row (parallel edges counted)
+    DevBuf<int32_t> pin_net;
+    pin_net.ensure(static_cast<size_t>(n_pins) + 1, s);
+    if (n_nets)
+        hipLaunchKernelGGL(k_pin_net, dim3(grid_for(n_nets, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets, pin_net.p);
+    AHR_LAUNCHED("k_pin_net");
+    if (g.n_big_nets) {
+        hipLaunchKernelGGL(k_pin_net_big, dim3(g.n_big_nets), dim3(kBT), 0, s, g.big_nets.p, nl.net_ptr, pin_net.p);
+        AHR_LAUNCHED("k_pin_net_big");
+    }
+    NetArgs a{nl.net_ptr, pin_net.p, g.pin_node_x.p, nl.net_w, star_rank.p, n_nets, n_pins, hp.clique_max,
+              g.first_star};
     DevBuf<int32_t> cnt;
     cnt.ensure(static_cast<size_t>(N) + 1, s);
     fill_i32(cnt.p, N + 1, 0, s);
@@ -479,6 +548,7 @@ void build_netlist(Graph& g, hipStream_t s) {
         hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, rp.p, cursor.p, dcol.p, dq.p);
     AHR_LAUNCHED("k_scatter");
     cursor.release(s);
+    pin_net.release(s);
     is_star.release(s);
     star_rank.release(s);
 
@@ -524,14 +594,15 @@ void build_netlist(Graph& g, hipStream_t s) {
     if (ncls[3]) {
         DevBuf<uint64_t> tkey;
         tkey.ensure(static_cast<size_t>(nnz_dup) + 1, s);
-        hipLaunchKernelGGL(k_sort_long, dim3(ncls[3]), dim3(kBT), 0, s, lists.p + 3 * static_cast<int64_t>(N), cnt.p,
-                           rp.p, dcol.p, dq.p, tkey.p, scol.p, sq.p, ucnt.p);
+        const int lds_keys = sort_lds_keys(g.device);
+        hipLaunchKernelGGL(k_sort_long, dim3(ncls[3]), dim3(kBT), static_cast<size_t>(lds_keys) * sizeof(uint64_t), s,
+                           lists.p + 3 * static_cast<int64_t>(N), cnt.p, rp.p, dcol.p, dq.p, tkey.p, scol.p, sq.p,
+                           ucnt.p, lds_keys);
         AHR_LAUNCHED("k_sort_long");
         tkey.release(s);
     }
     dcol.release(s);
     dq.release(s);
-    lists.release(s);
 
     // final CSR
     g.net_rp.ensure(static_cast<size_t>(N) + 1, s);
@@ -539,9 +610,15 @@ void build_netlist(Graph& g, hipStream_t s) {
     g.net_col.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.net_q.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.qdeg.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(static_cast<int64_t>(N) * 16, kBT)), dim3(kBT), 0, s, N, rp.p,
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N, cnt.p, rp.p,
                        ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
     AHR_LAUNCHED("k_compact");
+    if (ncls[3]) {
+        hipLaunchKernelGGL(k_compact_long, dim3(ncls[3]), dim3(kBT), 0, s, lists.p + 3 * static_cast<int64_t>(N), rp.p,
+                           ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
+        AHR_LAUNCHED("k_compact_long");
+    }
+    lists.release(s);
     g.base_w.ensure(static_cast<size_t>(n_inst) + 1, s);
     hipLaunchKernelGGL(k_base_weight, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.net_rp.p, g.qdeg.p,
                        g.base_w.p);

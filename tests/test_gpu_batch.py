@@ -82,9 +82,10 @@ def test_info(batch):
 
 
 @pytest.mark.parametrize("C", [2, 4, 8])
-@pytest.mark.parametrize("lanes", [1, 2, 4, 16, 64])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 16, 64, "row-block"])
 def test_batched_equals_members_bit_exact(batch, C, lanes):
     b = batch["b"]
+    lanes = A.HOP_ROW_BLOCK if lanes == "row-block" else lanes
     spec = U.to_c_spec(A, BANK)
     x = signal(batch, C)
     A.filter_tune(lanes, -1)
@@ -155,7 +156,7 @@ def test_autotune_sets_a_valid_config(batch):
     spec = U.to_c_spec(A, BANK)
     lanes, ct, ms = b.autotune(spec, 4)
     print(f"tuned: lanes {lanes} tile {ct} {ms:.3f} ms")
-    assert lanes in (1, 2, 4, 8, 16, 32) and ct in (1, 2, 4) and ms > 0
+    assert lanes in (1, 2, 4, 8, 16, 32, A.HOP_ROW_BLOCK) and ct in (1, 2, 4) and ms > 0
     assert b.get_config(4) == (lanes, ct)
     x = signal(batch, 4)
     A.filter_tune(lanes, -1)

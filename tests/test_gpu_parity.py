@@ -126,6 +126,30 @@ def test_filter_is_deterministic(case):
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
+@pytest.mark.parametrize("lanes", [1, 8, 64, "row-block"])
+def test_hop_forms_match_oracle(case, lanes):
+    """Every launch form of the hop (lanes per row, or the LDS-staged row
+    blocks) gives the oracle's filter within the FP32 bound, deterministically."""
+    nl, og, gr = case["nl"], case["og"], case["gr"]
+    saved = A.filter_get_tune()
+    A.filter_tune(A.HOP_ROW_BLOCK if lanes == "row-block" else lanes, -1)
+    try:
+        spec = U.spec32(O.FilterSpec(ks=(2, 4, 8), alphas=(0.2, 0.3, 0.5)))
+        mov = U.movable_rows(nl)
+        for C in (1, 4, 8):
+            G = np.repeat(nl["g0"][:, :2], 4, axis=1)[:, :C].copy()
+            G[mov] += np.random.default_rng(C).normal(0, 1, (mov.sum(), C)).astype(np.float32)
+            ref = O.apply_filter(nl, og, spec, G)
+            x = torch.as_tensor(G).cuda()
+            out = gr.filter(U.to_c_spec(A, spec), x)
+            again = gr.filter(U.to_c_spec(A, spec), x)
+            assert torch.equal(out, again)
+            err = U.rel_err(out.cpu().numpy(), ref, mov)
+            assert err <= FILTER_TOL, (C, err)
+    finally:
+        A.filter_tune(*saved)
+
+
 def test_hpwl_matches_oracle(case):
     nl, gr, gpos = case["nl"], case["gr"], case["gpos"]
     C = gpos.shape[1]
