@@ -113,6 +113,12 @@ constexpr int kLongRow = 128;
 constexpr int kChunk = 2048;
 constexpr int kRbRows = 256;
 constexpr int kRbEntries = 1024;
+// Star nodes are averaged over their pins by their row's thread up to
+// kStarInline pins, by kStarLanes lanes up to kStarMid pins, and by a whole
+// workgroup above (listed per graph in big_stars).
+constexpr int kStarInline = 8;
+constexpr int kStarMid = 256;
+constexpr int kStarLanes = 8;
 
 struct RowClasses {
     DevBuf<int32_t> long_rows;    // rows split over chunks, ascending
@@ -157,6 +163,8 @@ struct Graph {
     DevBuf<double> base_w;        // [n_inst] baseWeight
     DevBuf<int32_t> big_nets;     // nets with more than a wave's worth of pins (HPWL)
     int32_t n_big_nets = 0;
+    DevBuf<int32_t> big_stars;    // star indices (0-based) of nets with more than kStarMid pins
+    int32_t n_big_stars = 0;
 
     // hint part (per placement)
     DevBuf<int32_t> cell_bin;     // [n_inst] by execution row: bin of a hint cell, -1 otherwise
@@ -335,9 +343,12 @@ void hop_coefs(int32_t n, const float* scale, const double* lam, double sigma, f
 // placement are filled in by the caller).
 ExpandArgs expand_args(const Graph& g);
 // Expansion of many graphs in two launches: descriptors d[0..ng) on the
-// device, blk0 / sblk0 the first workgroup of each graph (rows, big stars).
-void expand_batch(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, const int32_t* sblk0,
-                  int32_t n_star_blocks, int32_t ng, const float* in, int32_t ncols, hipStream_t s);
+// device; blk0[g] the first row workgroup of graph g (n_blocks in all),
+// sfirst[g] the first star of graph g (n_star stars in all); big_stars the
+// batch star indices of the stars with more than kStarMid pins.
+void expand_batch(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, const int32_t* sfirst,
+                  int32_t n_star, const int32_t* big_stars, int32_t n_big_stars, int32_t ng, const float* in,
+                  int32_t ncols, hipStream_t s);
 // Hops 1..k_max of the filter bank on an expanded signal (z0 and, for a
 // band at k = 0, acc hold it), with lanes per short row and column tiles of
 // ct columns; the last hop writes out (instance order, fixed rows = in).

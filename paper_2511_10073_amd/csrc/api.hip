@@ -15,7 +15,7 @@ Graph::~Graph() {
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_rp, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
                               &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart,
-                              &i32a, &i32b, &counter};
+                              &big_stars, &i32a, &i32b, &counter};
     for (auto* b : i32) b->release(s);
     net_q.release(s);
     perm.release(s);

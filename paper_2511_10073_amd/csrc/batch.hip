@@ -135,8 +135,10 @@ struct Batch {
 
     RowClasses rc;
 
-    DevBuf<int32_t> blk0, sblk0;          // first expansion workgroup of each graph (rows, big stars)
-    int32_t n_blocks = 0, n_star_blocks = 0;
+    DevBuf<int32_t> blk0, sblk0;          // first expansion workgroup of each graph's rows; first star of each graph
+    int32_t n_blocks = 0, n_star_blocks = 0;   // row workgroups, stars
+    DevBuf<int32_t> big_stars;            // batch star indices of the stars with more than kStarMid pins
+    int32_t n_big_stars = 0;
 
     DevBuf<float> z0, z1, acc;
     DevBuf<int64_t> scan_tmp;
@@ -243,7 +245,8 @@ void ensure_operator(Batch& b, const ahr_filter_spec& spec, hipStream_t s) {
 
 void enqueue(Batch& b, const ExpandArgs* desc, const ahr_filter_spec& spec, const float* in, float* out, int32_t C,
              int lanes, int ct, hipStream_t s) {
-    expand_batch(desc, b.blk0.p, b.n_blocks, b.sblk0.p, b.n_star_blocks, static_cast<int32_t>(b.g.size()), in, C, s);
+    expand_batch(desc, b.blk0.p, b.n_blocks, b.sblk0.p, b.n_star_blocks, b.big_stars.p, b.n_big_stars,
+                 static_cast<int32_t>(b.g.size()), in, C, s);
     run_chain(batch_view(b, spec), spec, in, out, C, lanes, ct, s);
 }
 
@@ -355,6 +358,7 @@ Batch::~Batch() {
     rc.release(s);
     blk0.release(s);
     sblk0.release(s);
+    big_stars.release(s);
     z0.release(s);
     z1.release(s);
     acc.release(s);
@@ -435,6 +439,20 @@ void batch_assemble(Batch& b, hipStream_t s) {
     b.sblk0.ensure(n + 1, s);
     AHR_HIP(hipMemcpyAsync(b.blk0.p, blk.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
     AHR_HIP(hipMemcpyAsync(b.sblk0.p, sblk.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // big stars of every member, as batch star indices
+    std::vector<int32_t> big;
+    for (size_t i = 0; i < n; ++i) {
+        Graph& g = *b.g[i];
+        if (!g.n_big_stars) continue;
+        std::vector<int32_t> loc(g.n_big_stars);
+        AHR_HIP(hipMemcpyAsync(loc.data(), g.big_stars.p, loc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        AHR_HIP(hipStreamSynchronize(s));
+        for (int32_t k : loc) big.push_back(sblk[i] + k);
+    }
+    b.n_big_stars = static_cast<int32_t>(big.size());
+    b.big_stars.ensure(big.size() + 1, s);
+    if (!big.empty())
+        AHR_HIP(hipMemcpyAsync(b.big_stars.p, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     AHR_HIP(hipStreamSynchronize(s));
 }
 

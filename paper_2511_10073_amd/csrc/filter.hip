@@ -378,8 +378,9 @@ __device__ __forceinline__ void put_z(const ExpandArgs& a, int r, Vec<C> x) {
     }
 }
 
-// One row of the extended graph.  Stars with more than a wave's worth of
-// pins are left to expand_bigstar.
+
+// One row of the extended graph.  Stars with more than kStarInline pins are
+// left to expand_bigstar.
 template <int C>
 __device__ __forceinline__ void expand_row(const ExpandArgs& a, int r) {
     Vec<C> x;
@@ -391,7 +392,7 @@ __device__ __forceinline__ void expand_row(const ExpandArgs& a, int r) {
     } else if (r < a.first_mvirt) {
         int e = a.star_net[r - a.first_star];
         int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
-        if (p1 - p0 > kWave) return;
+        if (p1 - p0 > kStarInline) return;
         double acc[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = 0;
@@ -414,21 +415,66 @@ __device__ __forceinline__ void expand_row(const ExpandArgs& a, int r) {
     put_z<C>(a, r, x);
 }
 
-// Mean over the pins of big star k: one workgroup, lanes stride the pins
-// in float64, fixed reduction order.
-template <int C>
-__device__ __forceinline__ void expand_bigstar(const ExpandArgs& a, int k) {
-    __shared__ double red[kBT / kWave];
-    int e = a.star_net[k];
-    int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
-    if (p1 - p0 <= kWave) return;
+// Mean over the pins of star k (kStarInline < pins <= kStarMid): G lanes
+// (a G-aligned group) stride the pins in float64, B pins per lane in
+// flight, fixed butterfly reduction.
+template <int C, int G>
+__device__ __forceinline__ void expand_star(const ExpandArgs& a, int k) {
+    const int e = a.star_net[k];
+    const int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
+    const int deg = p1 - p0;
+    if (deg <= kStarInline || deg > kStarMid) return;   // group-uniform
+    const int l = threadIdx.x & (G - 1);
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0;
-    for (int p = p0 + threadIdx.x; p < p1; p += kBT) {
-        Vec<C> v = pin_value<C>(a, p);
+    constexpr int B = 8;
+    for (int p = p0 + l; p < p1; p += B * G) {
+        Vec<C> v[B];
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] += v.v[c];
+        for (int u = 0; u < B; ++u)
+            if (p + u * G < p1) v[u] = pin_value<C>(a, p + u * G);
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (p + u * G < p1) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] += v[u].v[c];
+            }
+    }
+    Vec<C> x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double t = acc[c];
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        x.v[c] = static_cast<float>(t / deg);
+    }
+    if (l == 0) put_z<C>(a, a.first_star + k, x);
+}
+
+// Mean over the pins of a big star (more than kStarMid pins): the whole
+// workgroup strides the pins in float64, B pins per lane in flight, then a
+// fixed-order block reduction.
+template <int C>
+__device__ __forceinline__ void expand_big_star(const ExpandArgs& a, int k) {
+    __shared__ double red[kBT / kWave];
+    const int e = a.star_net[k];
+    const int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    constexpr int B = 8;
+    for (int p = p0 + static_cast<int>(threadIdx.x); p < p1; p += B * kBT) {
+        Vec<C> v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (p + u * kBT < p1) v[u] = pin_value<C>(a, p + u * kBT);
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (p + u * kBT < p1) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] += v[u].v[c];
+            }
     }
     Vec<C> x;
 #pragma unroll
@@ -442,9 +488,17 @@ __global__ void __launch_bounds__(kBT) k_expand(ExpandArgs a) {
     if (r < a.n_tot) expand_row<C>(a, static_cast<int>(r));
 }
 
+// G lanes per star (mid-size stars; the others exit).
+template <int C, int G>
+__global__ void __launch_bounds__(kBT) k_expand_star(ExpandArgs a, int32_t n_star) {
+    const int64_t k = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
+    if (k < n_star) expand_star<C, G>(a, static_cast<int>(k));
+}
+
+// One workgroup per listed big star.
 template <int C>
-__global__ void __launch_bounds__(kBT) k_expand_bigstar(ExpandArgs a, int32_t n_star) {
-    expand_bigstar<C>(a, blockIdx.x);
+__global__ void __launch_bounds__(kBT) k_expand_big_star(ExpandArgs a, const int32_t* __restrict__ big) {
+    expand_big_star<C>(a, big[blockIdx.x]);
 }
 
 // Graph of workgroup b in a batched launch: the last g with first[g] <= b.
@@ -468,14 +522,31 @@ __global__ void __launch_bounds__(kBT) k_expand_batch(const ExpandArgs* __restri
     if (r < a.n_tot) expand_row<C>(a, static_cast<int>(r));
 }
 
-template <int C>
-__global__ void __launch_bounds__(kBT) k_expand_bigstar_batch(const ExpandArgs* __restrict__ d,
-                                                              const int32_t* __restrict__ sblk0, int32_t ng,
-                                                              const float* __restrict__ in) {
-    const int g = owner_of(sblk0, ng, blockIdx.x);
+// G lanes per star of the batch: group w of the launch is star
+// w - sfirst[g] of member g (sfirst: first star of each member, prefix sums).
+template <int C, int G>
+__global__ void __launch_bounds__(kBT) k_expand_star_batch(const ExpandArgs* __restrict__ d,
+                                                           const int32_t* __restrict__ sfirst, int32_t ng,
+                                                           int32_t n_star, const float* __restrict__ in) {
+    const int64_t w = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
+    if (w >= n_star) return;
+    const int g = owner_of(sfirst, ng, static_cast<int32_t>(w));
     ExpandArgs a = d[g];
     a.in = in + a.in_off;
-    expand_bigstar<C>(a, blockIdx.x - sblk0[g]);
+    expand_star<C, G>(a, static_cast<int>(w) - sfirst[g]);
+}
+
+// One workgroup per big star of the batch (batch star indices).
+template <int C>
+__global__ void __launch_bounds__(kBT) k_expand_big_star_batch(const ExpandArgs* __restrict__ d,
+                                                               const int32_t* __restrict__ sfirst, int32_t ng,
+                                                               const int32_t* __restrict__ big,
+                                                               const float* __restrict__ in) {
+    const int w = big[blockIdx.x];
+    const int g = owner_of(sfirst, ng, w);
+    ExpandArgs a = d[g];
+    a.in = in + a.in_off;
+    expand_big_star<C>(a, w - sfirst[g]);
 }
 
 // ---------------------------------------------------------------- hop
@@ -909,9 +980,16 @@ void expand_signal(Graph& g, const float* in, bool band0, float alpha0, hipStrea
     ProfScope ps(kStageExpand, s);
     hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(g.n_tot, kBT)), dim3(kBT), 0, s, e);
     AHR_LAUNCHED("k_expand");
-    if (g.n_star)
-        hipLaunchKernelGGL((k_expand_bigstar<C>), dim3(g.n_star), dim3(kBT), 0, s, e, g.n_star);
-    AHR_LAUNCHED("k_expand_bigstar");
+    if (g.n_star) {
+        hipLaunchKernelGGL((k_expand_star<C, kStarLanes>),
+                           dim3(grid_for(static_cast<int64_t>(g.n_star) * kStarLanes, kBT)), dim3(kBT), 0, s, e,
+                           g.n_star);
+        AHR_LAUNCHED("k_expand_star");
+        if (g.n_big_stars) {
+            hipLaunchKernelGGL((k_expand_big_star<C>), dim3(g.n_big_stars), dim3(kBT), 0, s, e, g.big_stars.p);
+            AHR_LAUNCHED("k_expand_big_star");
+        }
+    }
 }
 
 ChainView chain_view(Graph& g, const ahr_filter_spec& spec) {
@@ -1098,13 +1176,20 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
 
 template <int C>
 void expand_batch_c(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, const int32_t* sblk0,
-                    int32_t n_star_blocks, int32_t ng, const float* in, hipStream_t s) {
+                    int32_t n_star_blocks, const int32_t* big, int32_t n_big, int32_t ng, const float* in,
+                    hipStream_t s) {
     hipLaunchKernelGGL((k_expand_batch<C>), dim3(static_cast<unsigned>(n_blocks)), dim3(kBT), 0, s, d, blk0, ng, in);
     AHR_LAUNCHED("k_expand_batch");
-    if (n_star_blocks > 0) {
-        hipLaunchKernelGGL((k_expand_bigstar_batch<C>), dim3(static_cast<unsigned>(n_star_blocks)), dim3(kBT), 0, s, d,
-                           sblk0, ng, in);
-        AHR_LAUNCHED("k_expand_bigstar_batch");
+    if (n_star_blocks > 0) {     // here: the total star count of the batch
+        hipLaunchKernelGGL((k_expand_star_batch<C, kStarLanes>),
+                           dim3(grid_for(static_cast<int64_t>(n_star_blocks) * kStarLanes, kBT)), dim3(kBT), 0, s, d,
+                           sblk0, ng, n_star_blocks, in);
+        AHR_LAUNCHED("k_expand_star_batch");
+        if (n_big) {
+            hipLaunchKernelGGL((k_expand_big_star_batch<C>), dim3(static_cast<unsigned>(n_big)), dim3(kBT), 0, s, d,
+                               sblk0, ng, big, in);
+            AHR_LAUNCHED("k_expand_big_star_batch");
+        }
     }
 }
 
@@ -1231,12 +1316,13 @@ ExpandArgs expand_args(const Graph& g) {
 }
 
 void expand_batch(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, const int32_t* sblk0,
-                  int32_t n_star_blocks, int32_t ng, const float* in, int32_t ncols, hipStream_t s) {
+                  int32_t n_star_blocks, const int32_t* big, int32_t n_big, int32_t ng, const float* in,
+                  int32_t ncols, hipStream_t s) {
     switch (ncols) {
-        case 1: expand_batch_c<1>(d, blk0, n_blocks, sblk0, n_star_blocks, ng, in, s); break;
-        case 2: expand_batch_c<2>(d, blk0, n_blocks, sblk0, n_star_blocks, ng, in, s); break;
-        case 4: expand_batch_c<4>(d, blk0, n_blocks, sblk0, n_star_blocks, ng, in, s); break;
-        case 8: expand_batch_c<8>(d, blk0, n_blocks, sblk0, n_star_blocks, ng, in, s); break;
+        case 1: expand_batch_c<1>(d, blk0, n_blocks, sblk0, n_star_blocks, big, n_big, ng, in, s); break;
+        case 2: expand_batch_c<2>(d, blk0, n_blocks, sblk0, n_star_blocks, big, n_big, ng, in, s); break;
+        case 4: expand_batch_c<4>(d, blk0, n_blocks, sblk0, n_star_blocks, big, n_big, ng, in, s); break;
+        case 8: expand_batch_c<8>(d, blk0, n_blocks, sblk0, n_star_blocks, big, n_big, ng, in, s); break;
         default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
     }
 }

@@ -61,8 +61,10 @@ __device__ __forceinline__ float w_macro(float x, float y, float4 m, double bw_i
 
 // Bin of every hint cell (-1 otherwise), indexed by execution row, and the
 // fixed-point cell area per bin.  Rows are in spatial order, so a
-// workgroup's cells fall in few bins: areas are summed in LDS first.
-constexpr int kCellBinRows = 16;     // rows per thread
+// workgroup's cells fall in few bins: areas are summed in LDS first
+// (dynamic, nbins counters when nbins <= kLdsBins; integer areas, so the
+// sums do not depend on the order).
+constexpr int kCellBinRows = 4;      // rows per thread
 constexpr int kLdsBins = 4096;
 
 __global__ void __launch_bounds__(kBT) k_cell_bins(Grid gr, const float* __restrict__ pos, int ncols, int32_t n_inst,
@@ -70,11 +72,11 @@ __global__ void __launch_bounds__(kBT) k_cell_bins(Grid gr, const float* __restr
                                                    const float* __restrict__ size, const int64_t* __restrict__ qdeg,
                                                    int with_density, int32_t* __restrict__ cell_bin,
                                                    unsigned long long* __restrict__ area_q) {
-    __shared__ unsigned long long h[kLdsBins];
+    extern __shared__ unsigned long long area_lds[];
     const int nbins = gr.nbx * gr.nby;
     const bool lds = nbins <= kLdsBins;
     if (lds && with_density)
-        for (int b = threadIdx.x; b < nbins; b += kBT) h[b] = 0ull;
+        for (int b = threadIdx.x; b < nbins; b += kBT) area_lds[b] = 0ull;
     __syncthreads();
     int64_t base = static_cast<int64_t>(blockIdx.x) * kBT * kCellBinRows;
     for (int t = 0; t < kCellBinRows; ++t) {
@@ -91,7 +93,7 @@ __global__ void __launch_bounds__(kBT) k_cell_bins(Grid gr, const float* __restr
             if (with_density) {
                 double a = static_cast<double>(size[2 * i]) * static_cast<double>(size[2 * i + 1]);
                 unsigned long long q = static_cast<unsigned long long>(static_cast<int64_t>(__builtin_rint(a * kAreaQ)));
-                if (lds) atomicAdd(&h[bb], q);
+                if (lds) atomicAdd(&area_lds[bb], q);
                 else atomicAdd(&area_q[bb], q);
             }
             if (qdeg[i] > 0) b = bb;
@@ -101,14 +103,14 @@ __global__ void __launch_bounds__(kBT) k_cell_bins(Grid gr, const float* __restr
     if (lds && with_density) {
         __syncthreads();
         for (int b = threadIdx.x; b < nbins; b += kBT)
-            if (h[b]) atomicAdd(&area_q[b], h[b]);
+            if (area_lds[b]) atomicAdd(&area_q[b], area_lds[b]);
     }
 }
 
 // Stable bucket sort, pass 1: hint cells per (bin, tile), bin-major.
 __global__ void __launch_bounds__(kWave) k_bucket_count(const int32_t* __restrict__ cell_bin, int32_t n, int nbins,
                                                         int32_t ntiles, int32_t* __restrict__ hist) {
-    __shared__ int32_t h[kMaxBins];
+    extern __shared__ int32_t h[];     // nbins counters (dynamic: occupancy follows the key count)
     for (int b = threadIdx.x; b < nbins; b += kWave) h[b] = 0;
     __syncthreads();
     int64_t base = static_cast<int64_t>(blockIdx.x) * kTileCells;
@@ -128,7 +130,7 @@ __global__ void __launch_bounds__(kWave) k_bucket_count(const int32_t* __restric
 __global__ void __launch_bounds__(kWave) k_bucket_scatter(const int32_t* __restrict__ cell_bin, int32_t n, int nbins,
                                                           int bits, int32_t ntiles, const int32_t* __restrict__ off,
                                                           int32_t* __restrict__ out) {
-    __shared__ int32_t run[kMaxBins];
+    extern __shared__ int32_t run[];   // nbins cursors (dynamic)
     for (int b = threadIdx.x; b < nbins; b += kWave) run[b] = off[static_cast<int64_t>(b) * ntiles + blockIdx.x];
     __syncthreads();
     int l = threadIdx.x;
@@ -443,13 +445,14 @@ int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<i
     int64_t hn = static_cast<int64_t>(nkeys) * ntiles;
     g.i32a.ensure(static_cast<size_t>(hn) + 1, s);
     g.i32b.ensure(static_cast<size_t>(hn) + 1, s);
-    hipLaunchKernelGGL(k_bucket_count, dim3(ntiles), dim3(kWave), 0, s, key, n, nkeys, ntiles, g.i32a.p);
+    const size_t lds = static_cast<size_t>(nkeys) * sizeof(int32_t);
+    hipLaunchKernelGGL(k_bucket_count, dim3(ntiles), dim3(kWave), lds, s, key, n, nkeys, ntiles, g.i32a.p);
     AHR_LAUNCHED("k_bucket_count");
     g.scan_tmp.ensure(scan_tmp_elems(hn), s);
     scan_i32_to_i32(g.i32a.p, g.i32b.p, hn, g.scan_tmp.p, s);
     int bits = 0;
     while ((1 << bits) < nkeys) ++bits;
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(ntiles), dim3(kWave), 0, s, key, n, nkeys, bits, ntiles, g.i32b.p,
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(ntiles), dim3(kWave), lds, s, key, n, nkeys, bits, ntiles, g.i32b.p,
                        list.p);
     AHR_LAUNCHED("k_bucket_scatter");
     hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nkeys + 1, kBT)), dim3(kBT), 0, s, g.i32b.p, nkeys, ntiles,
@@ -513,7 +516,8 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s,
                        reinterpret_cast<unsigned long long*>(g.bin_area_q.p), static_cast<int64_t>(nbins));
     AHR_LAUNCHED("k_fill_u64");
-    hipLaunchKernelGGL(k_cell_bins, dim3(grid_for(n_inst, kBT * kCellBinRows)), dim3(kBT), 0, s, gr, pos, ncols,
+    const size_t bins_lds = nbins <= kLdsBins ? static_cast<size_t>(nbins) * sizeof(unsigned long long) : 0;
+    hipLaunchKernelGGL(k_cell_bins, dim3(grid_for(n_inst, kBT * kCellBinRows)), dim3(kBT), bins_lds, s, gr, pos, ncols,
                        n_inst, g.perm.p, g.nl.node_flags, g.nl.node_size, g.qdeg.p, bin_hints, g.cell_bin.p,
                        reinterpret_cast<unsigned long long*>(g.bin_area_q.p));
     AHR_LAUNCHED("k_cell_bins");
@@ -549,7 +553,10 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         AHR_LAUNCHED("k_bin_macros count");
         g.scan_tmp.ensure(scan_tmp_elems(nbins), s);
         scan_i32_to_i32(bmc.p, g.bm_start.p, nbins, g.scan_tmp.p, s);
-        int32_t nbm = read_scalar(g.bm_start.p + nbins, s);
+        // every (bin, macro) pair at most once: size the list by that bound
+        // unless it is large, and only then read the exact count
+        const int64_t bound = static_cast<int64_t>(n_macro) * nbins;
+        const int64_t nbm = bound <= (int64_t(1) << 24) ? bound : read_scalar(g.bm_start.p + nbins, s);
         g.bm_list.ensure(static_cast<size_t>(nbm) + 1, s);
         hipLaunchKernelGGL(k_bin_macros, dim3(nbins), dim3(kBT), 0, s, hp.nbx, g.macro_span.p, n_macro,
                            static_cast<const int32_t*>(g.bm_start.p), static_cast<int32_t*>(nullptr), g.bm_list.p);

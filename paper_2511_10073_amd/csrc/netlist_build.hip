@@ -66,6 +66,14 @@ __global__ void k_mark_star(const int32_t* __restrict__ net_ptr, int32_t n_nets,
     is_big[e] = deg > kWave ? 1 : 0;
 }
 
+__global__ void k_mark_big_star(const int32_t* __restrict__ star_net, const int32_t* __restrict__ net_ptr,
+                                int32_t n_star, int32_t* __restrict__ flag) {
+    int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n_star) return;
+    int e = star_net[k];
+    flag[k] = (net_ptr[e + 1] - net_ptr[e] > kStarMid) ? 1 : 0;
+}
+
 __global__ void k_mark_macro(const uint8_t* __restrict__ flags, int32_t n, int32_t* __restrict__ out) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (flags[i] & AHR_NODE_MACRO) ? 1 : 0;
@@ -481,6 +489,23 @@ void build_netlist(Graph& g, hipStream_t s) {
     list_rows(is_star.p, star_rank.p, n_nets, g.star_net.p, s);
     list_rows(is_big.p, big_rank.p, n_nets, g.big_nets.p, s);
     list_rows(is_mac.p, mac_rank.p, n_inst, g.macro_ids.p, s);
+    {   // stars averaged by a whole workgroup
+        DevBuf<int32_t> flag, rank;
+        flag.ensure(static_cast<size_t>(g.n_star) + 1, s);
+        rank.ensure(static_cast<size_t>(g.n_star) + 1, s);
+        if (g.n_star) {
+            hipLaunchKernelGGL(k_mark_big_star, dim3(grid_for(g.n_star, kBT)), dim3(kBT), 0, s, g.star_net.p,
+                               nl.net_ptr, g.n_star, flag.p);
+            AHR_LAUNCHED("k_mark_big_star");
+        }
+        g.scan_tmp.ensure(scan_tmp_elems(g.n_star), s);
+        scan_i32_to_i32(flag.p, rank.p, g.n_star, g.scan_tmp.p, s);
+        read_scalars({rank.p + g.n_star}, &g.n_big_stars, s);
+        g.big_stars.ensure(static_cast<size_t>(g.n_big_stars) + 1, s);
+        list_rows(flag.p, rank.p, g.n_star, g.big_stars.p, s);
+        flag.release(s);
+        rank.release(s);
+    }
     g.pin_node_x.ensure(static_cast<size_t>(n_pins) + 1, s);
     g.mpin_owner.ensure(static_cast<size_t>(g.n_mpin) + 1, s);
     g.mpin_pin.ensure(static_cast<size_t>(g.n_mpin) + 1, s);
