@@ -159,6 +159,41 @@ def learned_vs_plain(A, torch, np, nl, net, params, spec, g0, reps):
             "bounds": {"rel_err": 1e-3, "hpwl_delta": 2e-3}}
 
 
+def learned_initializer(A, torch, np, nl, net, params, spec, g0, rounds, gamma, steps, plain_ms, plain_out,
+                        plain_hpwl):
+    """The same initializer step with the learned filter in every round of
+    Algorithm 1 (graph build + T_hint rounds + HPWL), timed like the plain
+    step, and its final placement and HPWL against the plain step's."""
+    if not os.path.exists(MODEL):
+        return {"error": f"no trained model at {os.path.relpath(MODEL, ROOT)}"}
+    model = A.Mlp.load(MODEL)
+    out = torch.empty_like(g0)
+    hp = torch.empty_like(plain_hpwl)
+    fb = []
+
+    def step():
+        gr = A.Graph(net, params, None)
+        fb.append(gr.refine_learned(spec, model, g0, rounds, gamma, out=out)[1])
+        gr.hpwl(out, out=hp)
+        gr.close()
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    mov = np.flatnonzero((nl["node_flags"][:int(nl["n_inst"])] & 1) == 0)
+    a = out.cpu().numpy().astype(np.float64)[mov]
+    b = plain_out.cpu().numpy().astype(np.float64)[mov]
+    h_l, h_p = hp.cpu().numpy(), plain_hpwl.cpu().numpy()
+    return {"ms": round(ms, 3), "speedup_vs_plain": round(plain_ms / ms, 3),
+            "rel_err_vs_plain": float(np.linalg.norm(a - b) / np.linalg.norm(b - b.mean(axis=0))),
+            "hpwl": [float(v) for v in h_l], "hpwl_delta": float(np.max(np.abs(h_l - h_p) / h_p)),
+            "used_fallback": bool(fb[-1])}
+
+
 def batch_bins(n_inst):
     """Bin grid of a batch member: about 200 cells per bin, 8x8 to 32x32."""
     b = int(round((n_inst / 200.0) ** 0.5))
@@ -325,6 +360,8 @@ def main():
     }
     if not args.no_learned:
         rec["learned_vs_plain"] = learned_vs_plain(A, torch, np, nl, net, params, spec, g0, reps=10)
+        rec["learned_initializer"] = learned_initializer(A, torch, np, nl, net, params, spec, g0, args.rounds,
+                                                         args.gamma, args.steps, ms, out, hp)
     if not args.no_batched:
         rec["batched"] = batched(A, torch, np, N, spec, reps=10)
     if not args.no_cpu_baseline:

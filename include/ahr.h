@@ -248,6 +248,16 @@ ahr_status ahr_filter_learned(ahr_graph* gr, const ahr_filter_spec* spec, const 
                               const float* in, float* out, int32_t ncols, int32_t* used_fallback,
                               void* stream);
 
+/* Algorithm 1 (as ahr_refine) with the learned filter in place of the
+ * plain one in every round: hints rebuilt from the current placement, the
+ * surrogate (3 hops + the per-node network, see ahr_filter_learned) applied,
+ * then the relaxation g <- (1 - gamma) g + gamma g~ on movable rows.  An
+ * unvalidated model runs the plain filter instead (*used_fallback = 1).  A
+ * project addition: the paper's Algorithm 1 uses the filter of Section V. */
+ahr_status ahr_refine_learned(ahr_graph* gr, const ahr_filter_spec* spec, const ahr_mlp* model, const float* g0,
+                              int32_t ncols, int32_t T_hint, float gamma, float* out, int32_t* used_fallback,
+                              void* stream);
+
 /* Training data of the surrogate: for the signal `in` ([n_inst][ncols]),
  * writes feats [n_inst*ncols][AHR_MLP_FEATURE_STRIDE] (instance order, row
  * i*ncols + c), hops [3][n_inst][ncols] (h1, h2, h3) and stats [2][ncols]

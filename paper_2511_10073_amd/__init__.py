@@ -111,6 +111,8 @@ def load() -> ctypes.CDLL:
         "ahr_filter_learned": [vp, ctypes.POINTER(_FilterSpec), ctypes.POINTER(_Mlp), vp, vp, i32,
                                ctypes.POINTER(i32), vp],
         "ahr_filter_features": [vp, ctypes.POINTER(_FilterSpec), vp, i32, vp, vp, vp, vp],
+        "ahr_refine_learned": [vp, ctypes.POINTER(_FilterSpec), ctypes.POINTER(_Mlp), vp, i32, i32, ctypes.c_float, vp,
+                               ctypes.POINTER(i32), vp],
         "ahr_mlp_forward": [vp, vp, ctypes.c_int64, vp, vp],
         "ahr_mlp_loss_grad": [vp, vp, vp, ctypes.c_int64, vp, vp, vp],
         "ahr_mlp_adam": [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp],
@@ -325,6 +327,16 @@ class Graph:
         _check(load().ahr_refine(self.h, ctypes.byref(spec), _ptr(g0), g0.shape[1], T_hint, gamma, _ptr(out),
                                  _stream(stream)))
         return out
+
+    def refine_learned(self, spec, model, g0, T_hint, gamma, out=None, stream=None):
+        """(out, used_fallback) of Algorithm 1 with the learned filter."""
+        if out is None:
+            out = torch.empty_like(g0)
+        fb = ctypes.c_int32(-1)
+        mc = model.c()
+        _check(load().ahr_refine_learned(self.h, ctypes.byref(spec), ctypes.byref(mc), _ptr(g0), g0.shape[1], T_hint,
+                                         gamma, _ptr(out), ctypes.byref(fb), _stream(stream)))
+        return out, bool(fb.value)
 
     def filter_learned(self, spec, model, x, out=None, stream=None):
         """(out, used_fallback) of the learned filter."""

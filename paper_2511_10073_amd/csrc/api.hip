@@ -316,6 +316,47 @@ ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0
     });
 }
 
+ahr_status ahr_refine_learned(ahr_graph* h, const ahr_filter_spec* spec, const ahr_mlp* model, const float* g0,
+                              int32_t ncols, int32_t T_hint, float gamma, float* out, int32_t* used_fallback,
+                              void* stream) {
+    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+    ahr_status st;
+    if ((st = check_spec(spec)) != AHR_OK) return st;
+    if (!model || !model->params) return fail(AHR_EINVAL, "model is NULL");
+    if (!g0 || !out) return fail(AHR_EINVAL, "g0/out is NULL");
+    if (!ncols_ok(ncols) || ncols < 2) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
+    if (T_hint < 0) return fail(AHR_EINVAL, "T_hint must be >= 0");
+    if (!(gamma >= 0.f && gamma <= 1.f)) return fail(AHR_EINVAL, "gamma in [0, 1]");
+    auto* gr = reinterpret_cast<ahr::Graph*>(h);
+    size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
+    if (g0 != out && overlap(g0, bytes, out, bytes)) return fail(AHR_EINVAL, "g0 and out partially overlap");
+    return guarded([&]() -> ahr_status {
+        hipStream_t s = as_stream(stream);
+        size_t n = static_cast<size_t>(gr->n_inst) * ncols;
+        if (used_fallback) *used_fallback = model->validated ? 0 : 1;
+        if (T_hint == 0) {
+            if (g0 != out) AHR_HIP(hipMemcpyAsync(out, g0, bytes, hipMemcpyDeviceToDevice, s));
+            return AHR_OK;
+        }
+        gr->ga.ensure(n, s);
+        gr->gb.ensure(n, s);
+        gr->gt.ensure(n, s);
+        const float* cur = g0;
+        for (int r = 0; r < T_hint; ++r) {
+            float* next = (r == T_hint - 1) ? out : ((r & 1) ? gr->gb.p : gr->ga.p);
+            ahr::build_hints(*gr, cur, ncols, s);
+            if (model->validated)
+                ahr::run_learned(*gr, *spec, model->params, model->beta, cur, gr->gt.p, ncols, nullptr, nullptr,
+                                 nullptr, s);
+            else
+                ahr::run_filter(*gr, *spec, cur, gr->gt.p, ncols, s);
+            ahr::relax(*gr, cur, gr->gt.p, next, ncols, gamma, s);
+            cur = next;
+        }
+        return AHR_OK;
+    });
+}
+
 ahr_status ahr_filter_learned(ahr_graph* h, const ahr_filter_spec* spec, const ahr_mlp* model, const float* in,
                               float* out, int32_t ncols, int32_t* used_fallback, void* stream) {
     if (!h) return fail(AHR_EINVAL, "graph is NULL");

@@ -74,7 +74,7 @@ def small():
     net = A.Netlist(nl)
     x = torch.as_tensor(nl["g0"]).cuda()
     gr = A.Graph(net, U.to_c_params(A, p), x)
-    yield dict(nl=nl, og=og, gr=gr, x=x)
+    yield dict(nl=nl, og=og, gr=gr, x=x, p=p)
     gr.close()
 
 
@@ -158,3 +158,35 @@ def test_network_gains_over_linear_hops():
     print(f"held-out rel err: linear {res['rel_err_linear']:.4e}  mlp {res['rel_err']:.4e}  "
           f"hpwl delta {res['hpwl_delta']:.2e}  loss {loss:.4e}")
     assert res["rel_err"] < res["rel_err_linear"]
+
+
+def test_refine_learned_round_by_round(small):
+    """Algorithm 1 with the learned filter: every round equals the oracle's
+    hints on the GPU's own placement, the oracle's learned filter and the
+    relaxation; an unvalidated model reproduces the plain refinement."""
+    nl, gr, x, p = small["nl"], small["gr"], small["x"], small["p"]
+    params = rand_params(11, 0.3)
+    beta = (0.1, 0.3, 0.6)
+    model = A.Mlp(torch.as_tensor(params).cuda(), beta, True)
+    spec = U.to_c_spec(A, BANK)
+    gamma = 0.5
+    mov = U.movable_rows(nl)
+    cur = x.clone()
+    for r in range(2):
+        nxt, fb = gr.refine_learned(spec, model, cur, 1, gamma)
+        assert not fb
+        G = cur.cpu().numpy().astype(np.float64)
+        og = O.build_graph(nl, p, cur.cpu().numpy()[:, :2])
+        y = M.learned_filter(nl, og, params, beta, cur.cpu().numpy())
+        ref = G.copy()
+        ref[mov] = (1 - gamma) * G[mov] + gamma * y[mov]
+        got = nxt.cpu().numpy()
+        err = U.rel_err(got, ref, mov)
+        print(f"round {r}: rel err {err:.3e}")
+        assert err <= 1e-4, (r, err)
+        assert np.array_equal(got[~mov], cur.cpu().numpy()[~mov])
+        cur = nxt
+    off = A.Mlp(model.params, beta, False)
+    a, fb = gr.refine_learned(spec, off, x, 2, gamma)
+    assert fb
+    assert torch.equal(a, gr.refine(spec, x, 2, gamma))
