@@ -33,8 +33,8 @@ FILTER_SRC = os.path.join(ROOT, "paper_2511_10073_amd", "csrc", "filter.hip")
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the filter source they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "filter_sha256": "561b01d7cf4d0cecd0dc8f6de9923fc4debe594607763810033b4fad54bcef72",
-               "bytes_per_launch": 1674150768,
+               "filter_sha256": "594cc273693cca23400f7dc0bdba4f90e25f2df9a344c4ba24215d73f17279b4",
+               "bytes_per_launch": 1689535770,
                "source": "profiles/k_hop_large-2.2M_hbm_traffic.md"}
 
 
