@@ -72,7 +72,7 @@ typedef struct ahr_netlist {
     int32_t reserved0;          /* must be 0 */
     const int32_t* net_ptr;     /* [n_nets + 1], non-decreasing, net_ptr[0] = 0 */
     const int32_t* pin_node;    /* [n_pins] instance of each pin, in [0, n_inst) */
-    const float* pin_off;       /* [n_pins][2] pin offset from the instance centre */
+    const float* pin_off;       /* [n_pins][2] pin offset from the instance centre (may be NULL if n_pins = 0) */
     const float* net_w;         /* [n_nets] net weights, or NULL for all 1 */
     const uint8_t* node_flags;  /* [n_inst] */
     const float* node_size;     /* [n_inst][2] width, height */

@@ -66,9 +66,9 @@ ahr_status check_netlist(const ahr_netlist* nl) {
     if (nl->n_inst <= 0) return fail(AHR_EINVAL, "n_inst must be positive");
     if (nl->n_nets < 0 || nl->n_pins < 0) return fail(AHR_EINVAL, "negative net or pin count");
     if (nl->reserved0 != 0) return fail(AHR_EINVAL, "reserved0 must be 0");
-    if (!nl->net_ptr || !nl->node_flags || !nl->node_size || !nl->pin_off)
-        return fail(AHR_EINVAL, "net_ptr, node_flags, node_size and pin_off are required");
-    if (nl->n_pins > 0 && !nl->pin_node) return fail(AHR_EINVAL, "pin_node is NULL");
+    if (!nl->net_ptr || !nl->node_flags || !nl->node_size)
+        return fail(AHR_EINVAL, "net_ptr, node_flags and node_size are required");
+    if (nl->n_pins > 0 && (!nl->pin_node || !nl->pin_off)) return fail(AHR_EINVAL, "pin_node/pin_off is NULL");
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(nl->die[k])) return fail(AHR_EINVAL, "die is not finite");
     if (!(nl->die[0] < nl->die[2]) || !(nl->die[1] < nl->die[3])) return fail(AHR_EINVAL, "empty die");

@@ -495,7 +495,7 @@ ahr_status ahr_batch_build(const ahr_netlist* nls, const ahr_hint_params* hps, i
     for (int32_t i = 0; i < n; ++i) {
         const ahr_netlist& nl = nls[i];
         if (nl.n_inst <= 0 || nl.n_nets < 0 || nl.n_pins < 0 || !nl.net_ptr || !nl.node_flags || !nl.node_size ||
-            !nl.pin_off || (nl.n_pins > 0 && !nl.pin_node) || nl.reserved0 != 0)
+            (nl.n_pins > 0 && (!nl.pin_node || !nl.pin_off)) || nl.reserved0 != 0)
             return fail(AHR_EINVAL, "netlist " + std::to_string(i) + " is invalid");
         if (!(nl.die[0] < nl.die[2]) || !(nl.die[1] < nl.die[3])) return fail(AHR_EINVAL, "empty die");
         const ahr_hint_params& hp = hps[i];
