@@ -1,0 +1,129 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (default hop shape, 32 x 32 bins, the order-8 bank on 4
+columns), through the C ABI against the FP64 oracle:
+
+- mid-210k: netlist CSR bit-exact, hint structure exact on every row, filter
+  within 1e-5 centred relative error, HPWL;
+- large-2.2M: netlist CSR bit-exact (all 28.7M entries), hint rows exact on
+  a seeded sample of 5,000 rows, filter within 1e-5 over every movable row,
+  HPWL;
+- the 64-member batched workload (2.83M instances) in its tuned shape: each
+  member's slice bit-identical to the single-graph filter, the two smallest
+  members within 1e-5 of the oracle.
+
+The oracle builds and filters the full graphs on the host (tens of seconds
+for large-2.2M)."""
+import numpy as np
+import pytest
+import torch
+
+import gpu_common as U
+from oracle import ahr_oracle as O
+from synth import netlist as N
+
+pytestmark = pytest.mark.gpu
+
+A = pytest.importorskip("paper_2511_10073_amd")
+
+FILTER_TOL = 1e-5
+BANK = O.FilterSpec(ks=(2, 4, 8), alphas=(0.2, 0.3, 0.5))
+
+
+def pick_rows(rp, col, val, rows):
+    """Entries of the given rows, ordered by (row, column)."""
+    rp = np.asarray(rp, np.int64)
+    starts, lens = rp[rows], rp[rows + 1] - rp[rows]
+    idx = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(lens.sum())
+    r = np.repeat(rows, lens)
+    c, v = np.asarray(col)[idx], np.asarray(val)[idx]
+    o = np.lexsort((c, r))
+    return r[o], c[o], v[o]
+
+
+def hint_rows_equal(ex, og, rows):
+    r1, c1, v1 = pick_rows(ex["hint_row_ptr"], ex["hint_col"], ex["hint_val"], rows)
+    r0, c0, v0 = pick_rows(og.hint_row_ptr, og.hint_col, og.hint_val, rows)
+    assert np.array_equal(r1, r0) and np.array_equal(c1, c0)
+    assert np.all(np.abs(v1.astype(np.float64) - v0) <= 2.0 ** -22 * np.abs(v0))
+
+
+@pytest.mark.parametrize("cfg_name", ["MID", "LARGE"])
+def test_full_size_matches_oracle(cfg_name):
+    cfg = getattr(N, cfg_name)
+    nl = N.generate(cfg)
+    p = U.params32(O.HintParams(nbx=32, nby=32))
+    spec = U.spec32(BANK)
+    print(f"[{cfg.name}] n_inst={nl['n_inst']} pins={nl['pin_node'].size}", flush=True)
+    net = A.Netlist(nl)
+    x = torch.as_tensor(nl["g0"]).cuda()
+    gr = A.Graph(net, U.to_c_params(A, p), x)
+    try:
+        out = gr.filter(U.to_c_spec(A, spec), x).cpu().numpy()
+        hp = gr.hpwl(x).cpu().numpy()
+        ex = gr.export()
+    finally:
+        gr.close()
+    og = O.build_graph(nl, p, nl["g0"][:, :2])
+    print(f"[{cfg.name}] oracle graph built: n_tot={og.n_tot}", flush=True)
+    assert np.array_equal(ex["net_row_ptr"], og.net_row_ptr.astype(np.int32))
+    assert np.array_equal(ex["net_col"], og.net_col.astype(np.int32))
+    assert np.array_equal(ex["net_q"], og.net_q)
+    assert np.array_equal(ex["hint_row_ptr"], og.hint_row_ptr.astype(np.int32))
+    rng = np.random.default_rng(17)
+    if cfg_name == "MID":
+        rows = np.arange(og.n_tot)
+    else:   # a sample of cell rows and of the (long) macro and bin virtual rows
+        rows = np.concatenate([rng.choice(og.first_mvirt, 5000, replace=False),
+                               rng.choice(np.arange(og.first_mvirt, og.first_bvirt), 500, replace=False),
+                               rng.choice(np.arange(og.first_bvirt, og.n_tot), 64, replace=False)])
+        rows = np.unique(rows)
+    hint_rows_equal(ex, og, rows)
+    ref = O.apply_filter(nl, og, spec, nl["g0"])
+    print(f"[{cfg.name}] oracle filter done", flush=True)
+    mov = U.movable_rows(nl)
+    err = U.rel_err(out, ref, mov)
+    print(f"[{cfg.name}] filter rel err {err:.3e}", flush=True)
+    assert err <= FILTER_TOL
+    assert np.array_equal(out[~mov], nl["g0"][~mov])
+    ref_hp, _ = O.hpwl(nl, nl["g0"])
+    assert np.allclose(hp, ref_hp, rtol=1e-12, atol=0)
+
+
+def test_full_batched_workload():
+    """The 64-member batched workload of the benchmark (5k-200k cells each),
+    in its tuned launch shape: every member's slice is bit-identical to the
+    single-graph filter on that member with the same shape, and the two
+    smallest members are within the FP32 bound of the oracle."""
+    members = N.batch_sizes()
+    nls = [N.generate(N.batch_member(*m)) for m in members]
+    bins = [min(32, max(8, int(round((nl["n_inst"] / 200.0) ** 0.5)))) for nl in nls]
+    ps = [U.params32(O.HintParams(nbx=b, nby=b)) for b in bins]
+    nets = [A.Netlist(nl) for nl in nls]
+    pos = torch.as_tensor(np.concatenate([nl["g0"] for nl in nls])).cuda()
+    spec = U.spec32(BANK)
+    cs = U.to_c_spec(A, spec)
+    b = A.Batch(nets, [U.to_c_params(A, p) for p in ps], pos)
+    saved = A.filter_get_tune()
+    try:
+        lanes, ct, ms = b.autotune(cs, 4)
+        print(f"[batched] {len(nls)} members, {int(pos.shape[0])} instances: lanes {lanes} tile {ct} {ms:.3f} ms",
+              flush=True)
+        out = b.filter(cs, pos)
+        A.filter_tune(lanes, -1)
+        for i, (net, nl, p) in enumerate(zip(nets, nls, ps)):
+            lo, hi = b.offsets[i], b.offsets[i + 1]
+            gr = A.Graph(net, U.to_c_params(A, p), pos[lo:hi].contiguous())
+            alone = gr.filter(cs, pos[lo:hi].contiguous())
+            gr.close()
+            assert torch.equal(out[lo:hi], alone), i
+        y = out.cpu().numpy()
+        for i in np.argsort([nl["n_inst"] for nl in nls])[:2]:
+            nl, p = nls[i], ps[i]
+            og = O.build_graph(nl, p, nl["g0"][:, :2])
+            ref = O.apply_filter(nl, og, spec, nl["g0"])
+            err = U.rel_err(y[b.offsets[i]:b.offsets[i + 1]], ref, U.movable_rows(nl))
+            print(f"[batched] member {i} ({nl['n_inst']} instances) rel err {err:.3e}", flush=True)
+            assert err <= FILTER_TOL
+    finally:
+        A.filter_tune(*saved)
+        b.close()
