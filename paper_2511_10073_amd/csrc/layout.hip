@@ -1,10 +1,16 @@
 // Execution layout of the filter.  Instance ids arrive in netlist order,
 // which carries no locality, so neighbour gathers of the SpMM hop would each
 // touch a different cache line.  The filter therefore streams rows in an
-// execution order: instances sorted by a stable bucket sort on the Z-order
-// (Morton) key of their position on a 128 x 128 grid over the die, columns
+// execution order: instances sorted by a stable sort on the Hilbert-curve
+// index of their position on a 1024 x 1024 grid over the die, columns
 // renumbered to match; added nodes (macro pins, stars, virtual nodes) keep
-// their canonical ids.  The netlist rows are copied into that order (entry
+// their canonical ids.  Consecutive rows are then spatial neighbours, so the
+// rows of one workgroup gather from few, shared cache lines, and every
+// aligned power-of-two block of the grid (a bin of a 2^k x 2^k bin grid) is
+// one contiguous range of rows.  Inside each aligned window of 64 rows (the
+// rows of one workgroup of the hop) the rows are then ordered by netlist
+// row length, so the rows that share a wave need about the same number of
+// entry batches and the window stays one spatial neighbourhood.  The netlist rows are copied into that order (entry
 // order within a row kept, so the summation order is fixed by the inputs);
 // the hint rows are built in it directly.  The canonical netlist CSR stays
 // for export; the order is set once per graph from the first placement seen.
@@ -16,17 +22,32 @@ namespace ahr {
 namespace {
 
 constexpr int kBT = 256;
-constexpr int kGridBits = 7;     // 128 x 128 layout grid -> 14-bit keys
+constexpr int kGridBits = 10;    // 1024 x 1024 layout grid -> 20-bit keys
+constexpr int kDigitBits = 10;   // sorted as two stable 10-bit digit passes
 
-__device__ __forceinline__ int interleave7(int x, int y) {
-    int k = 0;
-#pragma unroll
-    for (int b = 0; b < kGridBits; ++b) k |= (((x >> b) & 1) << (2 * b)) | (((y >> b) & 1) << (2 * b + 1));
-    return k;
+// Hilbert-curve index of grid cell (x, y) on the 2^kGridBits square grid:
+// at each level the quadrant's position along the curve, then the cell's
+// coordinates reflected into that quadrant's orientation.
+__device__ __forceinline__ int hilbert_index(int x, int y) {
+    int d = 0;
+    for (int s = 1 << (kGridBits - 1); s > 0; s >>= 1) {
+        const int rx = (x & s) ? 1 : 0, ry = (y & s) ? 1 : 0;
+        d += s * s * ((3 * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = s - 1 - x;
+                y = s - 1 - y;
+            }
+            const int t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
 }
 
 __global__ void k_layout_keys(const float* __restrict__ pos, int ncols, int32_t n, float xl, float yl, float sx,
-                              float sy, int32_t* __restrict__ key) {
+                              float sy, int32_t* __restrict__ key, int32_t* __restrict__ lo) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int m = (1 << kGridBits) - 1;
@@ -34,7 +55,50 @@ __global__ void k_layout_keys(const float* __restrict__ pos, int ncols, int32_t 
     float fy = floorf((pos[i * ncols + 1] - yl) * sy);
     int gx = !(fx > 0.f) ? 0 : (fx >= static_cast<float>(m) ? m : static_cast<int>(fx));
     int gy = !(fy > 0.f) ? 0 : (fy >= static_cast<float>(m) ? m : static_cast<int>(fy));
-    key[i] = interleave7(gx, gy);
+    const int k = hilbert_index(gx, gy);
+    key[i] = k;
+    lo[i] = k & ((1 << kDigitBits) - 1);
+}
+
+// Second digit pass: the high digit of the key of each element of the
+// first pass's order.
+__global__ void k_high_digit(int32_t n, const int32_t* __restrict__ key, const int32_t* __restrict__ order,
+                             int32_t* __restrict__ hi) {
+    int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j < n) hi[j] = key[order[j]] >> kDigitBits;
+}
+
+__global__ void k_compose(int32_t n, const int32_t* __restrict__ first, const int32_t* __restrict__ second,
+                          int32_t* __restrict__ perm) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < n) perm[r] = first[second[r]];
+}
+
+// Stable sort of each aligned window of kLenWindow positions of `in` by the
+// netlist row length of its instance (one wave per window): the rank of an
+// element is the number of elements of its window with a smaller length, or
+// the same length and an earlier position.
+constexpr int kLenWindow = 64;
+
+__global__ void __launch_bounds__(kLenWindow) k_window_sort(int32_t n, const int32_t* __restrict__ in,
+                                                            const int32_t* __restrict__ net_rp,
+                                                            int32_t* __restrict__ out) {
+    __shared__ int32_t wlen[kLenWindow];
+    const int t = threadIdx.x;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * kLenWindow + t;
+    int32_t id = 0, len = INT32_MAX;                 // positions past n sort last and are not written
+    if (j < n) {
+        id = in[j];
+        len = net_rp[id + 1] - net_rp[id];
+    }
+    wlen[t] = len;
+    __syncthreads();
+    int rank = 0;
+    for (int u = 0; u < kLenWindow; ++u) {
+        const int32_t o = wlen[u];
+        rank += (o < len || (o == len && u < t)) ? 1 : 0;
+    }
+    if (j < n) out[static_cast<int64_t>(blockIdx.x) * kLenWindow + rank] = id;
 }
 
 __global__ void k_iperm(const int32_t* __restrict__ perm, int32_t n, int32_t* __restrict__ iperm) {
@@ -104,16 +168,31 @@ __global__ void k_exec_qdeg(int32_t n_tot, int32_t n_inst, const int32_t* __rest
 
 void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     const int32_t n = g.n_inst, N = g.n_tot;
-    DevBuf<int32_t> key;
+    DevBuf<int32_t> key, digit, first, second;
     key.ensure(static_cast<size_t>(n) + 1, s);
+    digit.ensure(static_cast<size_t>(n) + 1, s);
     const float side = static_cast<float>(1 << kGridBits);
     float sx = side / (g.nl.die[2] - g.nl.die[0]);
     float sy = side / (g.nl.die[3] - g.nl.die[1]);
     hipLaunchKernelGGL(k_layout_keys, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, pos, ncols, n, g.nl.die[0],
-                       g.nl.die[1], sx, sy, key.p);
+                       g.nl.die[1], sx, sy, key.p, digit.p);
     AHR_LAUNCHED("k_layout_keys");
-    bucket_sort(g, key.p, n, 1 << (2 * kGridBits), g.perm, g.lay_start, s, false);   // every key >= 0
+    // LSD radix sort, both passes stable: by the low digit, then by the high
+    // digit of that order; ties keep instance order
+    bucket_sort(g, digit.p, n, 1 << kDigitBits, first, g.lay_start, s, false);
+    hipLaunchKernelGGL(k_high_digit, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, n, key.p, first.p, digit.p);
+    AHR_LAUNCHED("k_high_digit");
+    bucket_sort(g, digit.p, n, 1 << (2 * kGridBits - kDigitBits), second, g.lay_start, s, false);
+    g.perm.ensure(static_cast<size_t>(n) + 1, s);
+    hipLaunchKernelGGL(k_compose, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, n, first.p, second.p, key.p);
+    AHR_LAUNCHED("k_compose");
+    hipLaunchKernelGGL(k_window_sort, dim3(grid_for(n, kLenWindow)), dim3(kLenWindow), 0, s, n, key.p, g.net_rp.p,
+                       g.perm.p);
+    AHR_LAUNCHED("k_window_sort");
     key.release(s);
+    digit.release(s);
+    first.release(s);
+    second.release(s);
     g.iperm.ensure(static_cast<size_t>(n) + 1, s);
     hipLaunchKernelGGL(k_iperm, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.perm.p, n, g.iperm.p);
     AHR_LAUNCHED("k_iperm");
