@@ -341,45 +341,66 @@ __global__ void k_bin_row_counts(HintArgs a, int32_t* __restrict__ cnt) {
 // Each bin entry is also written, with the same float, into the bin's own
 // row: bin row b lists the cells of its window bins slot by slot (row-major),
 // ascending execution rows within a slot; wpre[b][slot] is the slot's offset
-// and rank[r] the cell's position in its bin's list.
+// and rank[r] the cell's position in its bin's list.  One thread per cell:
+// the bin-row stores of a wave are then consecutive slots of one bin row.
+// The workgroup's cell rows are one contiguous range of entries; they are
+// assembled in LDS (up to kFillCap entries; any further ones are stored
+// directly) and stored with coalesced writes.
+constexpr int kFillCap = 16 * kBT;
+
 __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ pair_off,
                                                    const int32_t* __restrict__ pair_mac,
                                                    const int32_t* __restrict__ rank, const int32_t* __restrict__ wpre,
                                                    int2* __restrict__ ent) {
-    int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
-    if (r >= a.n_inst) return;
-    int b = a.cell_bin[r];
-    if (b < 0) return;
-    int i = a.perm[r];
-    float x = a.pos[static_cast<int64_t>(i) * a.ncols], y = a.pos[static_cast<int64_t>(i) * a.ncols + 1];
-    double bwi = a.base_w[i];
-    int64_t o = rp[r];
-    int n = 0;
-    for (int p = pair_off[r]; p < pair_off[r + 1]; ++p) {
-        int k = pair_mac[p];
-        ent[o + n++] = make_int2(a.first_mvirt + k, f_bits(w_macro(x, y, a.rect[k], bwi)));
-    }
-    if (a.bin_hints) {
-        const int ww = 2 * a.gr.hx + 1, wh = 2 * a.gr.hy + 1;
-        const int bx = b % a.gr.nbx, by = b / a.gr.nbx;
-        const int my = rank[r] - a.bin_start[b];
-        int x0, x1, y0, y1;
-        window(a.gr, b, x0, x1, y0, y1);
-        for (int ty = y0; ty <= y1; ++ty)
-            for (int tx = x0; tx <= x1; ++tx) {
-                int bb = ty * a.gr.nbx + tx;
-                int w = f_bits(w_bin(a.gr, x, y, bb, a.phi, bwi));
-                ent[o + n++] = make_int2(a.first_bvirt + bb, w);
-                // slot of this cell's bin inside the window of bb
-                int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
-                int64_t q = rp[a.first_bvirt + bb] + wpre[static_cast<int64_t>(bb) * ww * wh + slot] + my;
-                ent[q] = make_int2(static_cast<int>(r), w);
+    __shared__ int2 stage[kFillCap];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBT;
+    const int64_t r = r0 + threadIdx.x;
+    const int64_t rend = r0 + kBT < a.n_inst ? r0 + kBT : a.n_inst;
+    const int64_t e0 = rp[r0], e1 = rp[rend];       // the workgroup's cell-row entries
+    if (r < a.n_inst) {
+        const int b = a.cell_bin[r];
+        if (b >= 0) {
+            const int i = a.perm[r];
+            const float x = a.pos[static_cast<int64_t>(i) * a.ncols], y = a.pos[static_cast<int64_t>(i) * a.ncols + 1];
+            const double bwi = a.base_w[i];
+            const int64_t o = rp[r] - e0;
+            int n = 0;
+            auto put = [&](int2 v) {
+                const int64_t k = o + n++;
+                if (k < kFillCap)
+                    stage[k] = v;
+                else
+                    ent[e0 + k] = v;
+            };
+            for (int p = pair_off[r]; p < pair_off[r + 1]; ++p) {
+                int k = pair_mac[p];
+                put(make_int2(a.first_mvirt + k, f_bits(w_macro(x, y, a.rect[k], bwi))));
             }
+            if (a.bin_hints) {
+                const int ww = 2 * a.gr.hx + 1, wh = 2 * a.gr.hy + 1;
+                const int bx = b % a.gr.nbx, by = b / a.gr.nbx;
+                const int my = rank[r] - a.bin_start[b];
+                int x0, x1, y0, y1;
+                window(a.gr, b, x0, x1, y0, y1);
+                for (int ty = y0; ty <= y1; ++ty)
+                    for (int tx = x0; tx <= x1; ++tx) {
+                        int bb = ty * a.gr.nbx + tx;
+                        int w = f_bits(w_bin(a.gr, x, y, bb, a.phi, bwi));
+                        put(make_int2(a.first_bvirt + bb, w));
+                        // slot of this cell's bin inside the window of bb
+                        int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
+                        int64_t q = rp[a.first_bvirt + bb] + wpre[static_cast<int64_t>(bb) * ww * wh + slot] + my;
+                        ent[q] = make_int2(static_cast<int>(r), w);
+                    }
+            }
+        }
     }
+    __syncthreads();
+    const int64_t nst = e1 - e0 < kFillCap ? e1 - e0 : kFillCap;
+    for (int64_t k = threadIdx.x; k < nst; k += kBT) ent[e0 + k] = stage[k];
 }
 
-// rank[bin_cells[t]] = t
 __global__ void k_bin_rank(int32_t n, const int32_t* __restrict__ bin_cells, int32_t* __restrict__ rank) {
     int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t < n) rank[bin_cells[t]] = static_cast<int32_t>(t);
