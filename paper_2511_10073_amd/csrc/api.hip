@@ -28,6 +28,9 @@ Graph::~Graph() {
     lay_start.release(s);
     qdeg.release(s);
     base_w.release(s);
+    xcell.release(s);
+    xbase_w.release(s);
+    xpos.release(s);
     bin_area_q.release(s);
     phi.release(s);
     macro_span.release(s);

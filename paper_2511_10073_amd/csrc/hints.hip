@@ -59,18 +59,41 @@ __device__ __forceinline__ float w_macro(float x, float y, float4 m, double bw_i
     return static_cast<float>(-exp(-r) * bw_i);
 }
 
-// Bin of every hint cell (-1 otherwise), indexed by execution row, and the
-// fixed-point cell area per bin.  Rows are in spatial order, so a
-// workgroup's cells fall in few bins: areas are summed in LDS first
-// (dynamic, nbins counters when nbins <= kLdsBins; integer areas, so the
-// sums do not depend on the order).
+// Per execution row, once per graph: the cell's fixed-point area times 4
+// plus its class (0: not a movable standard cell, 1: movable standard cell
+// without nets, 2: movable standard cell with nets, a hint cell), and its
+// baseWeight; the per-round kernels then read them in row order.
+constexpr int64_t kCellOther = 0, kCellStd = 1, kCellHint = 2;
+
+__global__ void k_exec_cells(int32_t n_inst, const int32_t* __restrict__ perm, const uint8_t* __restrict__ flags,
+                             const float* __restrict__ size, const int64_t* __restrict__ qdeg,
+                             const double* __restrict__ base_w, int64_t* __restrict__ xcell,
+                             double* __restrict__ xbase_w) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n_inst) return;
+    const int i = perm[r];
+    int64_t c = kCellOther;
+    if (is_std_movable(flags[i])) {
+        double a = static_cast<double>(size[2 * i]) * static_cast<double>(size[2 * i + 1]);
+        int64_t q = static_cast<int64_t>(__builtin_rint(a * kAreaQ));
+        c = q * 4 + (qdeg[i] > 0 ? kCellHint : kCellStd);
+    }
+    xcell[r] = c;
+    xbase_w[r] = base_w[i];
+}
+
+// Bin of every hint cell (-1 otherwise), indexed by execution row, the
+// fixed-point cell area per bin, and the placement in row order (xpos).
+// Rows are in spatial order, so a workgroup's cells fall in few bins: areas
+// are summed in LDS first (dynamic, nbins counters when nbins <= kLdsBins;
+// integer areas, so the sums do not depend on the order).
 constexpr int kCellBinRows = 4;      // rows per thread
 constexpr int kLdsBins = 4096;
 
 __global__ void __launch_bounds__(kBT) k_cell_bins(Grid gr, const float* __restrict__ pos, int ncols, int32_t n_inst,
-                                                   const int32_t* __restrict__ perm, const uint8_t* __restrict__ flags,
-                                                   const float* __restrict__ size, const int64_t* __restrict__ qdeg,
-                                                   int with_density, int32_t* __restrict__ cell_bin,
+                                                   const int32_t* __restrict__ perm,
+                                                   const int64_t* __restrict__ xcell, int with_density,
+                                                   int32_t* __restrict__ cell_bin, float2* __restrict__ xpos,
                                                    unsigned long long* __restrict__ area_q) {
     extern __shared__ unsigned long long area_lds[];
     const int nbins = gr.nbx * gr.nby;
@@ -82,21 +105,21 @@ __global__ void __launch_bounds__(kBT) k_cell_bins(Grid gr, const float* __restr
     for (int t = 0; t < kCellBinRows; ++t) {
         int64_t r = base + static_cast<int64_t>(t) * kBT + threadIdx.x;
         if (r >= n_inst) break;
-        int i = perm[r];
-        uint8_t f = flags[i];
+        const int i = perm[r];
+        const float x = pos[static_cast<int64_t>(i) * ncols], y = pos[static_cast<int64_t>(i) * ncols + 1];
+        xpos[r] = make_float2(x, y);
+        const int64_t c = xcell[r];
         int b = -1;
-        if (is_std_movable(f)) {
-            float x = pos[static_cast<int64_t>(i) * ncols], y = pos[static_cast<int64_t>(i) * ncols + 1];
+        if ((c & 3) != kCellOther) {
             int bx = bin_coord(x, gr.xl32, gr.bw32, gr.nbx);
             int by = bin_coord(y, gr.yl32, gr.bh32, gr.nby);
             int bb = by * gr.nbx + bx;
             if (with_density) {
-                double a = static_cast<double>(size[2 * i]) * static_cast<double>(size[2 * i + 1]);
-                unsigned long long q = static_cast<unsigned long long>(static_cast<int64_t>(__builtin_rint(a * kAreaQ)));
+                unsigned long long q = static_cast<unsigned long long>(c >> 2);
                 if (lds) atomicAdd(&area_lds[bb], q);
                 else atomicAdd(&area_q[bb], q);
             }
-            if (qdeg[i] > 0) b = bb;
+            if ((c & 3) == kCellHint) b = bb;
         }
         cell_bin[r] = b;
     }
@@ -264,6 +287,8 @@ struct HintArgs {
     const int4* span;
     const double* phi;
     const double* base_w;         // by instance
+    const float2* xpos;           // by execution row
+    const double* xbase_w;        // by execution row
 };
 
 __device__ __forceinline__ void window(const Grid& gr, int b, int& x0, int& x1, int& y0, int& y1) {
@@ -289,8 +314,8 @@ __global__ void __launch_bounds__(kBT) k_cell_count(HintArgs a, int32_t* __restr
     }
     int n = 0;
     if (a.macro_hints) {
-        int i = a.perm[r];
-        float x = a.pos[static_cast<int64_t>(i) * a.ncols], y = a.pos[static_cast<int64_t>(i) * a.ncols + 1];
+        const float2 xy = a.xpos[r];
+        const float x = xy.x, y = xy.y;
         int o = pair_row ? pair_off[r] : 0;
         for (int t = a.bm_start[b]; t < a.bm_start[b + 1]; ++t) {
             int k = a.bm_list[t];
@@ -361,9 +386,9 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
     if (r < a.n_inst) {
         const int b = a.cell_bin[r];
         if (b >= 0) {
-            const int i = a.perm[r];
-            const float x = a.pos[static_cast<int64_t>(i) * a.ncols], y = a.pos[static_cast<int64_t>(i) * a.ncols + 1];
-            const double bwi = a.base_w[i];
+            const float2 xy = a.xpos[r];
+            const float x = xy.x, y = xy.y;
+            const double bwi = a.xbase_w[r];
             const int64_t o = rp[r] - e0;
             int n = 0;
             auto put = [&](int2 v) {
@@ -531,7 +556,16 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     gr.hy = window_half(hp.detection_ratio, hp.nby);
     const int nbins = hp.nbx * hp.nby;
 
-    // 1. cell bins (execution rows) and cell areas
+    // 1. cell bins (execution rows), cell areas, positions in row order
+    if (!g.has_xcell) {
+        g.xcell.ensure(static_cast<size_t>(n_inst) + 1, s);
+        g.xbase_w.ensure(static_cast<size_t>(n_inst) + 1, s);
+        hipLaunchKernelGGL(k_exec_cells, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.perm.p,
+                           g.nl.node_flags, g.nl.node_size, g.qdeg.p, g.base_w.p, g.xcell.p, g.xbase_w.p);
+        AHR_LAUNCHED("k_exec_cells");
+        g.has_xcell = 1;
+    }
+    g.xpos.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.cell_bin.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.bin_area_q.ensure(static_cast<size_t>(nbins) + 1, s);
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s,
@@ -539,7 +573,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     AHR_LAUNCHED("k_fill_u64");
     const size_t bins_lds = nbins <= kLdsBins ? static_cast<size_t>(nbins) * sizeof(unsigned long long) : 0;
     hipLaunchKernelGGL(k_cell_bins, dim3(grid_for(n_inst, kBT * kCellBinRows)), dim3(kBT), bins_lds, s, gr, pos, ncols,
-                       n_inst, g.perm.p, g.nl.node_flags, g.nl.node_size, g.qdeg.p, bin_hints, g.cell_bin.p,
+                       n_inst, g.perm.p, g.xcell.p, bin_hints, g.cell_bin.p, g.xpos.p,
                        reinterpret_cast<unsigned long long*>(g.bin_area_q.p));
     AHR_LAUNCHED("k_cell_bins");
 
@@ -609,6 +643,8 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     a.span = g.macro_span.p;
     a.phi = g.phi.p;
     a.base_w = g.base_w.p;
+    a.xpos = g.xpos.p;
+    a.xbase_w = g.xbase_w.p;
 
     // 5. per cell: macros holding it, window size; (cell, macro) pairs
     g.nmac.ensure(static_cast<size_t>(n_inst) + 1, s);

@@ -174,8 +174,12 @@ __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __
     }
 }
 
-// Row classes by entry count: 0 (<= 1), 1 (<= 16), 2 (<= 64), 3 (longer).
-__device__ __forceinline__ int row_class(int c) { return c <= 1 ? 0 : (c <= 16 ? 1 : (c <= 64 ? 2 : 3)); }
+// Row classes by entry count: 0 (<= 1), 1 (<= 16), 2 (<= 32), 3 (<= 64),
+// 4 (longer); classes 1-3 are sorted by 16, 32 and 64 lanes per row.
+constexpr int kSortClasses = 5;
+__device__ __forceinline__ int row_class(int c) {
+    return c <= 1 ? 0 : (c <= 16 ? 1 : (c <= 32 ? 2 : (c <= 64 ? 3 : 4)));
+}
 
 __global__ void k_class_flags(const int32_t* __restrict__ cnt, int32_t n, int k, int32_t* __restrict__ flag) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -198,7 +202,7 @@ __global__ void k_sort_trivial(const int32_t* __restrict__ rows, int32_t nrows, 
     }
 }
 
-// G lanes per row (G = 16 or 64): bitonic sort by column across the lanes,
+// G lanes per row (G = 16, 32 or 64): bitonic sort by column across the lanes,
 // then merge equal columns by exact integer sums.
 template <int G>
 __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ rows, int32_t nrows,
@@ -264,18 +268,22 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
     if (valid_row && l == 0) ucnt[r] = __popcll(hm & gm);
 }
 
-// One workgroup per long row: bitonic sort of (column, slot) keys --
+// One workgroup of kLongBT threads per long row (star rows reach 10^4
+// entries, so the rows' sorts are spread over many lanes): bitonic sort of
+// (column, slot) keys --
 // in LDS when the padded row fits `lds_keys` (dynamic shared memory),
 // otherwise in the row's own segment of `tkey` (global memory) -- with
 // positions past the row end acting as +infinity, then an ordered merge of
 // equal columns.
-__global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ cnt,
+constexpr int kLongBT = 1024;
+
+__global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ cnt,
                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ dcol,
                                                    const int64_t* __restrict__ dq, uint64_t* __restrict__ tkey,
                                                    int32_t* __restrict__ scol, int64_t* __restrict__ sq,
                                                    int32_t* __restrict__ ucnt, int lds_keys) {
     extern __shared__ uint64_t lkey[];
-    __shared__ int red[kBT / kWave];
+    __shared__ int red[kLongBT / kWave];
     __shared__ int carry;
     int r = rows[blockIdx.x];
     int n = cnt[r];
@@ -283,14 +291,14 @@ __global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ r
     int P = 1;
     while (P < n) P <<= 1;
     uint64_t* key = P <= lds_keys ? lkey : tkey + base;
-    for (int k = threadIdx.x; k < n; k += kBT)
+    for (int k = threadIdx.x; k < n; k += kLongBT)
         key[k] = (static_cast<uint64_t>(static_cast<uint32_t>(dcol[base + k])) << 32) | static_cast<uint32_t>(k);
     __threadfence_block();
     __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
         int half = size >> 1;
         // first comparator layer of a merge: mirror pairs
-        for (int i = threadIdx.x; i < P / 2; i += kBT) {
+        for (int i = threadIdx.x; i < P / 2; i += kLongBT) {
             int blk = i / half, off = i % half;
             int a = blk * size + off;
             int b = blk * size + size - 1 - off;
@@ -302,7 +310,7 @@ __global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ r
         __threadfence_block();
         __syncthreads();
         for (int h = half >> 1; h > 0; h >>= 1) {
-            for (int i = threadIdx.x; i < P / 2; i += kBT) {
+            for (int i = threadIdx.x; i < P / 2; i += kLongBT) {
                 int a = (i / h) * 2 * h + (i % h);
                 int b = a + h;
                 if (b < n) {
@@ -316,7 +324,7 @@ __global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ r
     }
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int t0 = 0; t0 < n; t0 += kBT) {
+    for (int t0 = 0; t0 < n; t0 += kLongBT) {
         int k = t0 + threadIdx.x;
         uint32_t col = 0;
         bool head = false;
@@ -325,7 +333,7 @@ __global__ void __launch_bounds__(kBT) k_sort_long(const int32_t* __restrict__ r
             head = (k == 0) || (static_cast<uint32_t>(key[k - 1] >> 32) != col);
         }
         int tot;
-        int idx = block_rank<kBT>(head, red, &tot);
+        int idx = block_rank<kLongBT>(head, red, &tot);
         if (head) {
             int64_t s = 0;
             for (int m = k; m < n && static_cast<uint32_t>(key[m] >> 32) == col; ++m)
@@ -578,23 +586,24 @@ void build_netlist(Graph& g, hipStream_t s) {
     star_rank.release(s);
 
     // per-row sort + merge; rows grouped by length class (ascending lists)
+    constexpr int K = kSortClasses;
     DevBuf<int32_t> lists, cflag, crank;
-    lists.ensure(static_cast<size_t>(N) * 4 + 4, s);
-    cflag.ensure(static_cast<size_t>(N) * 4 + 4, s);
-    crank.ensure(static_cast<size_t>(N) * 4 + 4, s);
+    lists.ensure(static_cast<size_t>(N) * K + K, s);
+    cflag.ensure(static_cast<size_t>(N + 1) * K, s);
+    crank.ensure(static_cast<size_t>(N + 1) * K, s);
     g.scan_tmp.ensure(scan_tmp_elems(N), s);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < K; ++k) {
         hipLaunchKernelGGL(k_class_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, cnt.p, N, k,
                            cflag.p + static_cast<int64_t>(k) * (N + 1));
         AHR_LAUNCHED("k_class_flags");
         scan_i32_to_i32(cflag.p + static_cast<int64_t>(k) * (N + 1), crank.p + static_cast<int64_t>(k) * (N + 1), N,
                         g.scan_tmp.p, s);
     }
-    int32_t ncls[4];
+    int32_t ncls[K];
     read_scalars({crank.p + N, crank.p + (N + 1) + N, crank.p + 2 * static_cast<int64_t>(N + 1) + N,
-                  crank.p + 3 * static_cast<int64_t>(N + 1) + N},
+                  crank.p + 3 * static_cast<int64_t>(N + 1) + N, crank.p + 4 * static_cast<int64_t>(N + 1) + N},
                  ncls, s);
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < K; ++k)
         list_rows(cflag.p + static_cast<int64_t>(k) * (N + 1), crank.p + static_cast<int64_t>(k) * (N + 1), N,
                   lists.p + static_cast<int64_t>(k) * N, s);
     cflag.release(s);
@@ -612,16 +621,21 @@ void build_netlist(Graph& g, hipStream_t s) {
                            lists.p + N, ncls[1], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p, ucnt.p);
     AHR_LAUNCHED("k_sort_group16");
     if (ncls[2])
-        hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 64, kBT)), dim3(kBT), 0, s,
+        hipLaunchKernelGGL(k_sort_group<32>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 32, kBT)), dim3(kBT), 0, s,
                            lists.p + 2 * static_cast<int64_t>(N), ncls[2], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
                            ucnt.p);
+    AHR_LAUNCHED("k_sort_group32");
+    if (ncls[3])
+        hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[3]) * 64, kBT)), dim3(kBT), 0, s,
+                           lists.p + 3 * static_cast<int64_t>(N), ncls[3], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
+                           ucnt.p);
     AHR_LAUNCHED("k_sort_group64");
-    if (ncls[3]) {
+    if (ncls[4]) {
         DevBuf<uint64_t> tkey;
         tkey.ensure(static_cast<size_t>(nnz_dup) + 1, s);
         const int lds_keys = sort_lds_keys(g.device);
-        hipLaunchKernelGGL(k_sort_long, dim3(ncls[3]), dim3(kBT), static_cast<size_t>(lds_keys) * sizeof(uint64_t), s,
-                           lists.p + 3 * static_cast<int64_t>(N), cnt.p, rp.p, dcol.p, dq.p, tkey.p, scol.p, sq.p,
+        hipLaunchKernelGGL(k_sort_long, dim3(ncls[4]), dim3(kLongBT), static_cast<size_t>(lds_keys) * sizeof(uint64_t), s,
+                           lists.p + 4 * static_cast<int64_t>(N), cnt.p, rp.p, dcol.p, dq.p, tkey.p, scol.p, sq.p,
                            ucnt.p, lds_keys);
         AHR_LAUNCHED("k_sort_long");
         tkey.release(s);
@@ -638,8 +652,8 @@ void build_netlist(Graph& g, hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N, cnt.p, rp.p,
                        ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
     AHR_LAUNCHED("k_compact");
-    if (ncls[3]) {
-        hipLaunchKernelGGL(k_compact_long, dim3(ncls[3]), dim3(kBT), 0, s, lists.p + 3 * static_cast<int64_t>(N), rp.p,
+    if (ncls[4]) {
+        hipLaunchKernelGGL(k_compact_long, dim3(ncls[4]), dim3(kBT), 0, s, lists.p + 4 * static_cast<int64_t>(N), rp.p,
                            ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
         AHR_LAUNCHED("k_compact_long");
     }
