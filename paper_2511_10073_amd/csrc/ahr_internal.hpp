@@ -1,6 +1,8 @@
 // Internal declarations shared by the libahr translation units.
 #pragma once
 
+#include <initializer_list>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -68,6 +70,9 @@ void scan_i32_to_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, h
 // int32 scan that returns the exact int64 total (one synchronisation); the
 // int32 output is only meaningful when the total is below 2^31.
 int64_t scan_i32_checked(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+// The same scan without reading its total: returns the device address of the
+// int64 total (valid until tmp is reused), for a later combined read.
+const int64_t* scan_i32_total(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 
 // list[rank[i]] = i for every i with flags[i] != 0 (rank = exclusive scan of flags).
 void list_rows(const int32_t* flags, const int32_t* rank, int32_t n, int32_t* list, hipStream_t s);
@@ -75,6 +80,16 @@ void list_rows(const int32_t* flags, const int32_t* rank, int32_t n, int32_t* li
 void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // host[k] = *src[k] for up to 8 device int32 scalars, with one synchronisation
 void read_scalars(const std::vector<const int32_t*>& src, int32_t* host, hipStream_t s);
+// Device scalars of 4 (wide = 0) or 8 (wide = 1) bytes, read in one synchronisation.
+struct DevWord {
+    const void* p;
+    int wide;
+};
+void read_words(std::initializer_list<DevWord> src, int64_t* out, hipStream_t s);
+// One device scalar (synchronises the stream).
+int32_t read_i32(const int32_t* src, hipStream_t s);
+int64_t read_i64(const int64_t* src, hipStream_t s);
+double read_f64(const double* src, hipStream_t s);
 
 // ---------------------------------------------------------------- profiling
 

@@ -1,4 +1,5 @@
 // Errors, the stream-ordered allocator and the integer prefix scan.
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -204,6 +205,19 @@ void scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, h
     scan_impl<int32_t, int64_t>(in, out, n, tmp, s);
 }
 
+__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+
+const int64_t* scan_i32_total(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+    if (n == 0) {
+        AHR_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, tmp);
+        AHR_LAUNCHED("k_zero_i64");
+        return tmp;
+    }
+    scan_impl<int32_t, int32_t>(in, out, n, tmp, s);
+    return tmp + (n + kScanTile - 1) / kScanTile;
+}
+
 int64_t scan_i32_checked(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
     if (n == 0) {
         AHR_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
@@ -211,10 +225,7 @@ int64_t scan_i32_checked(const int32_t* in, int32_t* out, int64_t n, int64_t* tm
     }
     scan_impl<int32_t, int32_t>(in, out, n, tmp, s);
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;
-    int64_t total = 0;
-    AHR_HIP(hipMemcpyAsync(&total, tmp + ntiles, sizeof total, hipMemcpyDeviceToHost, s));
-    AHR_HIP(hipStreamSynchronize(s));
-    return total;
+    return read_i64(tmp + ntiles, s);
 }
 
 void scan_i32_to_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
@@ -240,31 +251,84 @@ void list_rows(const int32_t* flags, const int32_t* rank, int32_t n, int32_t* li
 }
 
 struct PtrPack {
-    const int32_t* p[8];
+    const void* p[8];
+    int wide[8];    // 8-byte source word
 };
 
-__global__ void k_gather_scalars(PtrPack src, int n, int32_t* dst) {
+// Small reads go straight into pinned, coherent host memory: one gather
+// kernel and one stream synchronisation, no copy.
+__global__ void k_gather_scalars(PtrPack src, int n, int64_t* dst) {
     int i = threadIdx.x;
-    if (i < n) dst[i] = *src.p[i];
+    if (i < n)
+        dst[i] = src.wide[i] ? *static_cast<const int64_t*>(src.p[i])
+                             : static_cast<int64_t>(*static_cast<const int32_t*>(src.p[i]));
+}
+
+namespace {
+
+int64_t* host_words(int dev) {
+    static thread_local int64_t* buf[64] = {nullptr};
+    if (dev < 0 || dev >= 64) throw Error{AHR_EDEVICE, "device ordinal out of range"};
+    if (!buf[dev]) AHR_HIP(hipHostMalloc(reinterpret_cast<void**>(&buf[dev]), 8 * sizeof(int64_t),
+                                         hipHostMallocCoherent));
+    return buf[dev];
+}
+
+void read_words(const PtrPack& pk, int n, int64_t* out, hipStream_t s) {
+    int dev = 0;
+    AHR_HIP(hipGetDevice(&dev));
+    int64_t* hw = host_words(dev);
+    hipLaunchKernelGGL(k_gather_scalars, dim3(1), dim3(64), 0, s, pk, n, hw);
+    AHR_LAUNCHED("k_gather_scalars");
+    AHR_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < n; ++k) out[k] = hw[k];
+}
+
+}  // namespace
+
+void read_words(std::initializer_list<DevWord> src, int64_t* out, hipStream_t s) {
+    if (src.size() == 0) return;
+    if (src.size() > 8) throw Error{AHR_EDEVICE, "read_words: at most 8"};
+    PtrPack pk{};
+    int k = 0;
+    for (const DevWord& w : src) {
+        pk.p[k] = w.p;
+        pk.wide[k] = w.wide;
+        ++k;
+    }
+    read_words(pk, k, out, s);
 }
 
 void read_scalars(const std::vector<const int32_t*>& src, int32_t* host, hipStream_t s) {
     if (src.empty()) return;
     if (src.size() > 8) throw Error{AHR_EDEVICE, "read_scalars: at most 8"};
-    static thread_local int32_t* dbuf = nullptr;
-    static thread_local int dbuf_dev = -1;
-    int dev = 0;
-    AHR_HIP(hipGetDevice(&dev));
-    if (!dbuf || dbuf_dev != dev) {
-        AHR_HIP(hipMalloc(&dbuf, 8 * sizeof(int32_t)));
-        dbuf_dev = dev;
-    }
     PtrPack pk{};
     for (size_t k = 0; k < src.size(); ++k) pk.p[k] = src[k];
-    hipLaunchKernelGGL(k_gather_scalars, dim3(1), dim3(64), 0, s, pk, static_cast<int>(src.size()), dbuf);
-    AHR_LAUNCHED("k_gather_scalars");
-    AHR_HIP(hipMemcpyAsync(host, dbuf, src.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    AHR_HIP(hipStreamSynchronize(s));
+    int64_t w[8];
+    read_words(pk, static_cast<int>(src.size()), w, s);
+    for (size_t k = 0; k < src.size(); ++k) host[k] = static_cast<int32_t>(w[k]);
+}
+
+int64_t read_i64(const int64_t* src, hipStream_t s) {
+    PtrPack pk{};
+    pk.p[0] = src;
+    pk.wide[0] = 1;
+    int64_t w = 0;
+    read_words(pk, 1, &w, s);
+    return w;
+}
+
+int32_t read_i32(const int32_t* src, hipStream_t s) {
+    int32_t v = 0;
+    read_scalars({src}, &v, s);
+    return v;
+}
+
+double read_f64(const double* src, hipStream_t s) {
+    const int64_t w = read_i64(reinterpret_cast<const int64_t*>(src), s);
+    double d;
+    std::memcpy(&d, &w, sizeof d);
+    return d;
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {

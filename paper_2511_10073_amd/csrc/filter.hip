@@ -29,14 +29,6 @@ namespace {
 
 constexpr int kBT = 256;
 
-template <class T>
-T read_scalar(const T* dev, hipStream_t s) {
-    T v;
-    AHR_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
-    AHR_HIP(hipStreamSynchronize(s));
-    return v;
-}
-
 // ---------------------------------------------------------------- vectors
 
 template <int C>
@@ -89,13 +81,24 @@ __global__ void k_row_len(int32_t n, const int32_t* __restrict__ net_rp, const i
     is_long[r] = len > kLongRow ? 1 : 0;
 }
 
-__global__ void k_long_nchunks(int32_t n_long, const int32_t* __restrict__ rows, const int32_t* __restrict__ net_rp,
-                               const int32_t* __restrict__ hint_rp, int32_t* __restrict__ nch) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_long) return;
-    int r = rows[i];
+// Long-row flag and chunk count of every row (0 for short rows).
+__global__ void k_row_chunks(int32_t n, const int32_t* __restrict__ net_rp, const int32_t* __restrict__ hint_rp,
+                             int32_t* __restrict__ is_long, int32_t* __restrict__ nch) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
     int len = (net_rp[r + 1] - net_rp[r]) + (hint_rp[r + 1] - hint_rp[r]);
-    nch[i] = (len + kChunk - 1) / kChunk;
+    bool lg = len > kLongRow;
+    is_long[r] = lg ? 1 : 0;
+    nch[r] = lg ? (len + kChunk - 1) / kChunk : 0;
+}
+
+// First chunk of each long row from the row-indexed chunk offsets; the
+// entry past the last row holds the chunk total.
+__global__ void k_long_chunk0(int32_t n_long, const int32_t* __restrict__ rows, const int32_t* __restrict__ cscan,
+                              int32_t n_chunks, int32_t* __restrict__ chunk0) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_long) chunk0[i] = cscan[rows[i]];
+    if (i == n_long) chunk0[i] = n_chunks;
 }
 
 __global__ void k_chunk_rows(int32_t n_long, const int32_t* __restrict__ chunk0, int32_t* __restrict__ chunk_row) {
@@ -1197,35 +1200,31 @@ void expand_batch_c(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, 
 
 void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,
                  DevBuf<int64_t>& scan_tmp, hipStream_t s) {
-    DevBuf<int32_t> is_long, rank, nch;
+    DevBuf<int32_t> is_long, rank, nch, cscan;
     const size_t n1 = static_cast<size_t>(N) + 1;
     is_long.ensure(n1, s);
-    hipLaunchKernelGGL(k_row_len, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, net_rp, hint_rp, is_long.p);
-    AHR_LAUNCHED("k_row_len");
+    nch.ensure(n1, s);
+    hipLaunchKernelGGL(k_row_chunks, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, net_rp, hint_rp, is_long.p, nch.p);
+    AHR_LAUNCHED("k_row_chunks");
     rank.ensure(n1, s);
+    cscan.ensure(n1, s);
     scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i32(is_long.p, rank.p, N, scan_tmp.p, s);
-    int32_t t1[4];
-    read_scalars({rank.p + N, rank.p + n_inst, net_rp + n_inst, hint_rp + n_inst}, t1, s);
-    rc.n_long = t1[0];
-    rc.n_long_inst = t1[1];
-    rc.nnz_inst = static_cast<int64_t>(t1[2]) + t1[3];
+    scan_i32_to_i32(nch.p, cscan.p, N, scan_tmp.p, s);
+    int32_t t[6];
+    read_scalars({rank.p + N, rank.p + n_inst, cscan.p + N, cscan.p + n_inst, net_rp + n_inst, hint_rp + n_inst}, t, s);
+    rc.n_long = t[0];
+    rc.n_long_inst = t[1];
+    rc.n_chunks = t[2];
+    rc.n_chunks_inst = t[3];
+    rc.nnz_inst = static_cast<int64_t>(t[4]) + t[5];
     rc.has_rb = 0;
     rc.long_rows.ensure(static_cast<size_t>(rc.n_long) + 1, s);
     list_rows(is_long.p, rank.p, N, rc.long_rows.p, s);
-    nch.ensure(static_cast<size_t>(rc.n_long) + 1, s);
     rc.long_chunk0.ensure(static_cast<size_t>(rc.n_long) + 1, s);
-    if (rc.n_long) {
-        hipLaunchKernelGGL(k_long_nchunks, dim3(grid_for(rc.n_long, kBT)), dim3(kBT), 0, s, rc.n_long,
-                           rc.long_rows.p, net_rp, hint_rp, nch.p);
-        AHR_LAUNCHED("k_long_nchunks");
-    }
-    scan_tmp.ensure(scan_tmp_elems(rc.n_long), s);
-    scan_i32_to_i32(nch.p, rc.long_chunk0.p, rc.n_long, scan_tmp.p, s);
-    int32_t t2[2];
-    read_scalars({rc.long_chunk0.p + rc.n_long, rc.long_chunk0.p + rc.n_long_inst}, t2, s);
-    rc.n_chunks = t2[0];
-    rc.n_chunks_inst = t2[1];
+    hipLaunchKernelGGL(k_long_chunk0, dim3(grid_for(static_cast<int64_t>(rc.n_long) + 1, kBT)), dim3(kBT), 0, s,
+                       rc.n_long, rc.long_rows.p, cscan.p, rc.n_chunks, rc.long_chunk0.p);
+    AHR_LAUNCHED("k_long_chunk0");
     rc.chunk_row.ensure(static_cast<size_t>(rc.n_chunks) + 1, s);
     if (rc.n_long) {
         hipLaunchKernelGGL(k_chunk_rows, dim3(rc.n_long), dim3(kBT), 0, s, rc.n_long, rc.long_chunk0.p,
@@ -1236,6 +1235,7 @@ void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32
     is_long.release(s);
     rank.release(s);
     nch.release(s);
+    cscan.release(s);
 }
 
 void row_blocks(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,

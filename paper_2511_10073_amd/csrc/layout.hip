@@ -141,16 +141,24 @@ __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_inst,
     for (int k = l; k < len; k += G) xent[d + k] = exec_entry(col[a + k], q[a + k], n_inst, iperm);
 }
 
-__global__ void __launch_bounds__(kBT) k_exec_net_long(const int32_t* __restrict__ rows, int32_t n_inst,
+// One workgroup per longer row; the workgroups stride over the list of
+// long rows, whose length they read from the device (*n_long).
+constexpr int kLongRowGrid = 512;
+
+__global__ void __launch_bounds__(kBT) k_exec_net_long(const int32_t* __restrict__ rows,
+                                                       const int32_t* __restrict__ n_long, int32_t n_inst,
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ iperm,
                                                        const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                        const int64_t* __restrict__ q, const int32_t* __restrict__ xrp,
                                                        int2* __restrict__ xent) {
-    const int r = rows[blockIdx.x];
-    const int d = xrp[r], len = xrp[r + 1] - d;
-    const int a = rp[src_row(r, n_inst, perm)];
-    for (int k = threadIdx.x; k < len; k += kBT) xent[d + k] = exec_entry(col[a + k], q[a + k], n_inst, iperm);
+    const int nl = *n_long;
+    for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+        const int r = rows[li];
+        const int d = xrp[r], len = xrp[r + 1] - d;
+        const int a = rp[src_row(r, n_inst, perm)];
+        for (int k = threadIdx.x; k < len; k += kBT) xent[d + k] = exec_entry(col[a + k], q[a + k], n_inst, iperm);
+    }
 }
 
 __global__ void k_long_flags(int32_t n_tot, const int32_t* __restrict__ xrp, int32_t* __restrict__ flag) {
@@ -217,15 +225,11 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         hipLaunchKernelGGL(k_long_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.xnet_rp.p, flag.p);
         AHR_LAUNCHED("k_long_flags");
         scan_i32_to_i32(flag.p, rank.p, N, g.scan_tmp.p, s);
-        int32_t n_long = 0;
-        read_scalars({rank.p + N}, &n_long, s);
-        if (n_long) {
-            rows.ensure(static_cast<size_t>(n_long) + 1, s);
-            list_rows(flag.p, rank.p, N, rows.p, s);
-            hipLaunchKernelGGL(k_exec_net_long, dim3(n_long), dim3(kBT), 0, s, rows.p, n, g.perm.p, g.iperm.p,
-                               g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
-            AHR_LAUNCHED("k_exec_net_long");
-        }
+        rows.ensure(static_cast<size_t>(N) + 1, s);
+        list_rows(flag.p, rank.p, N, rows.p, s);
+        hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s, rows.p, rank.p + N, n, g.perm.p,
+                           g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
+        AHR_LAUNCHED("k_exec_net_long");
         flag.release(s);
         rank.release(s);
         rows.release(s);

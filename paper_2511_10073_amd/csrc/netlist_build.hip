@@ -57,21 +57,24 @@ __global__ void k_pin_nodes(const int32_t* __restrict__ pin_node, const int32_t*
     }
 }
 
+// Per net: star (more than clique_max pins), big (more pins than a wave),
+// big star (a star whose spokes a whole workgroup averages).
 __global__ void k_mark_star(const int32_t* __restrict__ net_ptr, int32_t n_nets, int32_t clique_max,
-                            int32_t* __restrict__ is_star, int32_t* __restrict__ is_big) {
+                            int32_t* __restrict__ is_star, int32_t* __restrict__ is_big,
+                            int32_t* __restrict__ is_big_star) {
     int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= n_nets) return;
     int deg = net_ptr[e + 1] - net_ptr[e];
     is_star[e] = deg > clique_max ? 1 : 0;
     is_big[e] = deg > kWave ? 1 : 0;
+    is_big_star[e] = (deg > clique_max && deg > kStarMid) ? 1 : 0;
 }
 
-__global__ void k_mark_big_star(const int32_t* __restrict__ star_net, const int32_t* __restrict__ net_ptr,
-                                int32_t n_star, int32_t* __restrict__ flag) {
-    int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= n_star) return;
-    int e = star_net[k];
-    flag[k] = (net_ptr[e + 1] - net_ptr[e] > kStarMid) ? 1 : 0;
+// Star index (rank among the stars) of every big-star net, ascending.
+__global__ void k_list_big_stars(const int32_t* __restrict__ flag, const int32_t* __restrict__ rank,
+                                 const int32_t* __restrict__ star_rank, int32_t n_nets, int32_t* __restrict__ out) {
+    int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < n_nets && flag[e]) out[rank[e]] = star_rank[e];
 }
 
 __global__ void k_mark_macro(const uint8_t* __restrict__ flags, int32_t n, int32_t* __restrict__ out) {
@@ -181,9 +184,9 @@ __device__ __forceinline__ int row_class(int c) {
     return c <= 1 ? 0 : (c <= 16 ? 1 : (c <= 32 ? 2 : (c <= 64 ? 3 : 4)));
 }
 
-__global__ void k_class_flags(const int32_t* __restrict__ cnt, int32_t n, int k, int32_t* __restrict__ flag) {
+__global__ void k_class_keys(const int32_t* __restrict__ cnt, int32_t n, int32_t* __restrict__ key) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r < n) flag[r] = row_class(cnt[r]) == k ? 1 : 0;
+    if (r < n) key[r] = row_class(cnt[r]);
 }
 
 // Rows with at most one entry: copy through.
@@ -428,14 +431,6 @@ int sort_lds_keys(int device) {
     return k;
 }
 
-template <class T>
-T read_scalar(const T* dev, hipStream_t s) {
-    T v;
-    AHR_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
-    AHR_HIP(hipStreamSynchronize(s));
-    return v;
-}
-
 }  // namespace
 
 void build_netlist(Graph& g, hipStream_t s) {
@@ -451,7 +446,7 @@ void build_netlist(Graph& g, hipStream_t s) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(nv, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets, nl.pin_node, n_pins,
                        n_inst, g.counter.p);
     AHR_LAUNCHED("k_validate");
-    int32_t bad = read_scalar(g.counter.p, s);
+    int32_t bad = read_i32(g.counter.p, s);
     if (bad) {
         static const char* why[] = {"", "pin_node out of [0, n_inst)", "net_ptr[0] != 0",
                                     "net_ptr[n_nets] != n_pins", "net_ptr decreasing"};
@@ -459,10 +454,11 @@ void build_netlist(Graph& g, hipStream_t s) {
     }
 
     // flags of macro pins, star nets, big nets, macros; their ranks; one read of the four counts
-    DevBuf<int32_t> is_mp, mp_rank, is_star, star_rank, is_big, big_rank, is_mac, mac_rank;
+    DevBuf<int32_t> is_mp, mp_rank, is_star, star_rank, is_big, big_rank, is_mac, mac_rank, is_bs, bs_rank;
     is_mp.ensure(static_cast<size_t>(n_pins) + 1, s);
     is_star.ensure(static_cast<size_t>(n_nets) + 1, s);
     is_big.ensure(static_cast<size_t>(n_nets) + 1, s);
+    is_bs.ensure(static_cast<size_t>(n_nets) + 1, s);
     is_mac.ensure(static_cast<size_t>(n_inst) + 1, s);
     if (n_pins)
         hipLaunchKernelGGL(k_mark_mpin, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, nl.pin_node, nl.node_flags,
@@ -470,25 +466,30 @@ void build_netlist(Graph& g, hipStream_t s) {
     AHR_LAUNCHED("k_mark_mpin");
     if (n_nets)
         hipLaunchKernelGGL(k_mark_star, dim3(grid_for(n_nets, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets,
-                           hp.clique_max, is_star.p, is_big.p);
+                           hp.clique_max, is_star.p, is_big.p, is_bs.p);
     AHR_LAUNCHED("k_mark_star");
     hipLaunchKernelGGL(k_mark_macro, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, nl.node_flags, n_inst, is_mac.p);
     AHR_LAUNCHED("k_mark_macro");
     mp_rank.ensure(static_cast<size_t>(n_pins) + 1, s);
     star_rank.ensure(static_cast<size_t>(n_nets) + 1, s);
     big_rank.ensure(static_cast<size_t>(n_nets) + 1, s);
+    bs_rank.ensure(static_cast<size_t>(n_nets) + 1, s);
     mac_rank.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(std::max<int64_t>(std::max<int64_t>(n_pins, n_nets), n_inst)), s);
     scan_i32_to_i32(is_mp.p, mp_rank.p, n_pins, g.scan_tmp.p, s);
     scan_i32_to_i32(is_star.p, star_rank.p, n_nets, g.scan_tmp.p, s);
     scan_i32_to_i32(is_big.p, big_rank.p, n_nets, g.scan_tmp.p, s);
     scan_i32_to_i32(is_mac.p, mac_rank.p, n_inst, g.scan_tmp.p, s);
-    int32_t cnt4[4];
-    read_scalars({mp_rank.p + n_pins, star_rank.p + n_nets, big_rank.p + n_nets, mac_rank.p + n_inst}, cnt4, s);
-    g.n_mpin = cnt4[0];
-    g.n_star = cnt4[1];
-    g.n_big_nets = cnt4[2];
-    g.n_macro = cnt4[3];
+    scan_i32_to_i32(is_bs.p, bs_rank.p, n_nets, g.scan_tmp.p, s);
+    int32_t cnt5[5];
+    read_scalars({mp_rank.p + n_pins, star_rank.p + n_nets, big_rank.p + n_nets, mac_rank.p + n_inst,
+                  bs_rank.p + n_nets},
+                 cnt5, s);
+    g.n_mpin = cnt5[0];
+    g.n_star = cnt5[1];
+    g.n_big_nets = cnt5[2];
+    g.n_macro = cnt5[3];
+    g.n_big_stars = cnt5[4];
     if ((hp.flags & AHR_MACRO_HINTS) && g.n_macro > 16384)
         throw Error{AHR_EUNSUPPORTED, "macro hints support at most 16384 macros"};
     g.star_net.ensure(static_cast<size_t>(g.n_star) + 1, s);
@@ -497,23 +498,14 @@ void build_netlist(Graph& g, hipStream_t s) {
     list_rows(is_star.p, star_rank.p, n_nets, g.star_net.p, s);
     list_rows(is_big.p, big_rank.p, n_nets, g.big_nets.p, s);
     list_rows(is_mac.p, mac_rank.p, n_inst, g.macro_ids.p, s);
-    {   // stars averaged by a whole workgroup
-        DevBuf<int32_t> flag, rank;
-        flag.ensure(static_cast<size_t>(g.n_star) + 1, s);
-        rank.ensure(static_cast<size_t>(g.n_star) + 1, s);
-        if (g.n_star) {
-            hipLaunchKernelGGL(k_mark_big_star, dim3(grid_for(g.n_star, kBT)), dim3(kBT), 0, s, g.star_net.p,
-                               nl.net_ptr, g.n_star, flag.p);
-            AHR_LAUNCHED("k_mark_big_star");
-        }
-        g.scan_tmp.ensure(scan_tmp_elems(g.n_star), s);
-        scan_i32_to_i32(flag.p, rank.p, g.n_star, g.scan_tmp.p, s);
-        read_scalars({rank.p + g.n_star}, &g.n_big_stars, s);
-        g.big_stars.ensure(static_cast<size_t>(g.n_big_stars) + 1, s);
-        list_rows(flag.p, rank.p, g.n_star, g.big_stars.p, s);
-        flag.release(s);
-        rank.release(s);
-    }
+    // stars averaged by a whole workgroup
+    g.big_stars.ensure(static_cast<size_t>(g.n_big_stars) + 1, s);
+    if (n_nets)
+        hipLaunchKernelGGL(k_list_big_stars, dim3(grid_for(n_nets, kBT)), dim3(kBT), 0, s, is_bs.p, bs_rank.p,
+                           star_rank.p, n_nets, g.big_stars.p);
+    AHR_LAUNCHED("k_list_big_stars");
+    is_bs.release(s);
+    bs_rank.release(s);
     g.pin_node_x.ensure(static_cast<size_t>(n_pins) + 1, s);
     g.mpin_owner.ensure(static_cast<size_t>(g.n_mpin) + 1, s);
     g.mpin_pin.ensure(static_cast<size_t>(g.n_mpin) + 1, s);
@@ -568,8 +560,28 @@ void build_netlist(Graph& g, hipStream_t s) {
     rp.ensure(static_cast<size_t>(N) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i64(cnt.p, rp.p, N, g.scan_tmp.p, s);
-    int64_t nnz_dup = read_scalar(rp.p + N, s);
+    // rows grouped by length class (ascending rows within a class), read
+    // with the raw entry total
+    constexpr int K = kSortClasses;
+    DevBuf<int32_t> ckey, lists, cstart;
+    ckey.ensure(static_cast<size_t>(N) + 1, s);
+    hipLaunchKernelGGL(k_class_keys, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, cnt.p, N, ckey.p);
+    AHR_LAUNCHED("k_class_keys");
+    bucket_sort(g, ckey.p, N, K, lists, cstart, s, false);
+    ckey.release(s);
+    int64_t w[K + 2];
+    read_words({{rp.p + N, 1}, {cstart.p, 0}, {cstart.p + 1, 0}, {cstart.p + 2, 0}, {cstart.p + 3, 0},
+                {cstart.p + 4, 0}, {cstart.p + 5, 0}},
+               w, s);
+    static_assert(K == 5, "class starts read above");
+    const int64_t nnz_dup = w[0];
     if (nnz_dup >= INT32_MAX) throw Error{AHR_EUNSUPPORTED, "netlist expands to 2^31 or more graph entries"};
+    int32_t ncls[K];
+    const int32_t* cls[K];
+    for (int k = 0; k < K; ++k) {
+        ncls[k] = static_cast<int32_t>(w[2 + k] - w[1 + k]);
+        cls[k] = lists.p + w[1 + k];
+    }
 
     DevBuf<int32_t> cursor, dcol, scol, ucnt;
     DevBuf<int64_t> dq, sq;
@@ -585,49 +597,27 @@ void build_netlist(Graph& g, hipStream_t s) {
     is_star.release(s);
     star_rank.release(s);
 
-    // per-row sort + merge; rows grouped by length class (ascending lists)
-    constexpr int K = kSortClasses;
-    DevBuf<int32_t> lists, cflag, crank;
-    lists.ensure(static_cast<size_t>(N) * K + K, s);
-    cflag.ensure(static_cast<size_t>(N + 1) * K, s);
-    crank.ensure(static_cast<size_t>(N + 1) * K, s);
-    g.scan_tmp.ensure(scan_tmp_elems(N), s);
-    for (int k = 0; k < K; ++k) {
-        hipLaunchKernelGGL(k_class_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, cnt.p, N, k,
-                           cflag.p + static_cast<int64_t>(k) * (N + 1));
-        AHR_LAUNCHED("k_class_flags");
-        scan_i32_to_i32(cflag.p + static_cast<int64_t>(k) * (N + 1), crank.p + static_cast<int64_t>(k) * (N + 1), N,
-                        g.scan_tmp.p, s);
-    }
-    int32_t ncls[K];
-    read_scalars({crank.p + N, crank.p + (N + 1) + N, crank.p + 2 * static_cast<int64_t>(N + 1) + N,
-                  crank.p + 3 * static_cast<int64_t>(N + 1) + N, crank.p + 4 * static_cast<int64_t>(N + 1) + N},
-                 ncls, s);
-    for (int k = 0; k < K; ++k)
-        list_rows(cflag.p + static_cast<int64_t>(k) * (N + 1), crank.p + static_cast<int64_t>(k) * (N + 1), N,
-                  lists.p + static_cast<int64_t>(k) * N, s);
-    cflag.release(s);
-    crank.release(s);
+    // per-row sort + merge by length class
     scol.ensure(static_cast<size_t>(nnz_dup) + 1, s);
     sq.ensure(static_cast<size_t>(nnz_dup) + 1, s);
     ucnt.ensure(static_cast<size_t>(N) + 1, s);
     fill_i32(ucnt.p, N + 1, 0, s);
     if (ncls[0])
-        hipLaunchKernelGGL(k_sort_trivial, dim3(grid_for(ncls[0], kBT)), dim3(kBT), 0, s, lists.p, ncls[0], cnt.p,
+        hipLaunchKernelGGL(k_sort_trivial, dim3(grid_for(ncls[0], kBT)), dim3(kBT), 0, s, cls[0], ncls[0], cnt.p,
                            rp.p, dcol.p, dq.p, scol.p, sq.p, ucnt.p);
     AHR_LAUNCHED("k_sort_trivial");
     if (ncls[1])
         hipLaunchKernelGGL(k_sort_group<16>, dim3(grid_for(static_cast<int64_t>(ncls[1]) * 16, kBT)), dim3(kBT), 0, s,
-                           lists.p + N, ncls[1], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p, ucnt.p);
+                           cls[1], ncls[1], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p, ucnt.p);
     AHR_LAUNCHED("k_sort_group16");
     if (ncls[2])
         hipLaunchKernelGGL(k_sort_group<32>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 32, kBT)), dim3(kBT), 0, s,
-                           lists.p + 2 * static_cast<int64_t>(N), ncls[2], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
+                           cls[2], ncls[2], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
                            ucnt.p);
     AHR_LAUNCHED("k_sort_group32");
     if (ncls[3])
         hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[3]) * 64, kBT)), dim3(kBT), 0, s,
-                           lists.p + 3 * static_cast<int64_t>(N), ncls[3], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
+                           cls[3], ncls[3], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
                            ucnt.p);
     AHR_LAUNCHED("k_sort_group64");
     if (ncls[4]) {
@@ -635,7 +625,7 @@ void build_netlist(Graph& g, hipStream_t s) {
         tkey.ensure(static_cast<size_t>(nnz_dup) + 1, s);
         const int lds_keys = sort_lds_keys(g.device);
         hipLaunchKernelGGL(k_sort_long, dim3(ncls[4]), dim3(kLongBT), static_cast<size_t>(lds_keys) * sizeof(uint64_t), s,
-                           lists.p + 4 * static_cast<int64_t>(N), cnt.p, rp.p, dcol.p, dq.p, tkey.p, scol.p, sq.p,
+                           cls[4], cnt.p, rp.p, dcol.p, dq.p, tkey.p, scol.p, sq.p,
                            ucnt.p, lds_keys);
         AHR_LAUNCHED("k_sort_long");
         tkey.release(s);
@@ -653,11 +643,12 @@ void build_netlist(Graph& g, hipStream_t s) {
                        ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
     AHR_LAUNCHED("k_compact");
     if (ncls[4]) {
-        hipLaunchKernelGGL(k_compact_long, dim3(ncls[4]), dim3(kBT), 0, s, lists.p + 4 * static_cast<int64_t>(N), rp.p,
+        hipLaunchKernelGGL(k_compact_long, dim3(ncls[4]), dim3(kBT), 0, s, cls[4], rp.p,
                            ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
         AHR_LAUNCHED("k_compact_long");
     }
     lists.release(s);
+    cstart.release(s);
     g.base_w.ensure(static_cast<size_t>(n_inst) + 1, s);
     hipLaunchKernelGGL(k_base_weight, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.net_rp.p, g.qdeg.p,
                        g.base_w.p);
@@ -667,7 +658,6 @@ void build_netlist(Graph& g, hipStream_t s) {
     ucnt.release(s);
     cnt.release(s);
     rp.release(s);
-    AHR_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace ahr
