@@ -34,7 +34,9 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 // class) and handed out again, so the graph builds of an initializer loop
 // allocate from the driver only the first time.  A block freed on one
 // stream and reused on another is ordered behind the frees' stream by an
-// event wait.  ahr_memory_trim() returns the cache to the driver.
+// event wait; the events are recycled through a per-device pool, so a free
+// and a reuse cost one event record and no event creation.
+// ahr_memory_trim() returns the cache to the driver.
 
 namespace {
 
@@ -49,6 +51,27 @@ struct Block {
 std::mutex g_alloc_mu;
 std::multimap<size_t, Block> g_free;                  // by size class
 std::unordered_map<void*, std::pair<size_t, int>> g_live;   // ptr -> (size class, device)
+std::unordered_map<int, std::vector<hipEvent_t>> g_events;  // idle events per device
+
+// Both under g_alloc_mu.  take_event returns null if no event can be made.
+hipEvent_t take_event(int dev) {
+    auto& v = g_events[dev];
+    if (!v.empty()) {
+        hipEvent_t e = v.back();
+        v.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+void give_event(int dev, hipEvent_t e) {
+    if (e) g_events[dev].push_back(e);
+}
 
 size_t size_class(size_t b) {
     b = b < 256 ? 256 : b;
@@ -79,7 +102,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
             Block b = it->second;
             g_free.erase(it);
             if (b.stream != s) AHR_HIP(hipStreamWaitEvent(s, b.done, 0));
-            (void)hipEventDestroy(b.done);
+            give_event(dev, b.done);
             g_live[b.p] = {cls, dev};
             return b.p;
         }
@@ -109,8 +132,10 @@ void dev_free(void* p, hipStream_t s) {
     if (it == g_live.end()) return;
     Block b{p, it->second.first, s, nullptr, it->second.second};
     g_live.erase(it);
-    if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(b.done, s) != hipSuccess) {
+    int dev = b.device;
+    (void)hipGetDevice(&dev);
+    b.done = take_event(dev);
+    if (!b.done || hipEventRecord(b.done, s) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipStreamSynchronize(s);
         if (b.done) (void)hipEventDestroy(b.done);
@@ -356,5 +381,8 @@ extern "C" ahr_status ahr_memory_trim(void) {
         (void)hipSetDevice(cur);
     }
     ahr::g_free.clear();
+    for (auto& kv : ahr::g_events)
+        for (hipEvent_t e : kv.second) (void)hipEventDestroy(e);
+    ahr::g_events.clear();
     return AHR_OK;
 }
