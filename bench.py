@@ -27,22 +27,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MODEL = os.path.join(ROOT, "paper_2511_10073_amd", "weights", "surrogate_bank248.json")
-FILTER_SRC = os.path.join(ROOT, "paper_2511_10073_amd", "csrc", "filter.hip")
+# The hop kernels and the execution layout whose gathers they serve.
+HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("filter.hip", "layout.hip")]
 
 # HBM bytes per k_hop launch on large-2.2M from two rocprofv3 counter passes
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
-# copy; valid only for the filter source they were taken with.
+# copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "filter_sha256": "594cc273693cca23400f7dc0bdba4f90e25f2df9a344c4ba24215d73f17279b4",
-               "bytes_per_launch": 1689535770,
+               "sources_sha256": "777866c486fb1ca4fd43c7f8aa073035d8f32e024cd8aa95844693f9dc828676",
+               "bytes_per_launch": 1647129896,
                "source": "profiles/k_hop_large-2.2M_hbm_traffic.md"}
 
 
-def hop_traffic(workload):
+def hop_sources_sha():
     import hashlib
-    with open(FILTER_SRC, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if workload != HOP_TRAFFIC["workload"] or sha != HOP_TRAFFIC["filter_sha256"]:
+    h = hashlib.sha256()
+    for p in HOP_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def hop_traffic(workload):
+    if workload != HOP_TRAFFIC["workload"] or hop_sources_sha() != HOP_TRAFFIC["sources_sha256"]:
         return None
     return HOP_TRAFFIC["bytes_per_launch"]
 
