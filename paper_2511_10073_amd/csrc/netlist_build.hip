@@ -111,6 +111,22 @@ __device__ __forceinline__ int64_t q_star(float w, int p) {
     return static_cast<int64_t>(__builtin_rint(num / static_cast<double>(p - 1)));
 }
 
+// A raw (unsorted, unmerged) entry: column and integer weight, one 16-byte
+// store per entry in the scatter and one load in the sorts.
+struct alignas(16) RawEnt {
+    int32_t col;
+    int32_t pad;
+    int64_t q;
+};
+
+__device__ __forceinline__ RawEnt raw_ent(int32_t col, int64_t q) {
+    RawEnt e;
+    e.col = col;
+    e.pad = 0;
+    e.q = q;
+    return e;
+}
+
 struct NetArgs {
     const int32_t* net_ptr;
     const int32_t* pin_net;
@@ -143,7 +159,7 @@ __global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt) {
 // atomic (the run order inside a row does not matter: rows are sorted by
 // column and equal columns merged by exact integer sums afterwards).
 __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __restrict__ cursor,
-                          int32_t* __restrict__ dcol, int64_t* __restrict__ dq) {
+                          RawEnt* __restrict__ raw) {
     int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_pins) return;
     int e = a.pin_net[p];
@@ -161,19 +177,16 @@ __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __
         for (int b = lo; b < hi; ++b) {
             int u = a.pin_x[b];
             if (u == v) continue;
-            dcol[k] = u;
-            dq[k] = q;
+            raw[k] = raw_ent(u, q);
             ++k;
         }
     } else {
         int64_t q = q_star(w, deg);
         int z = a.first_star + a.star_rank[e];
         int64_t k = rp[v] + atomicAdd(&cursor[v], 1);
-        dcol[k] = z;
-        dq[k] = q;
+        raw[k] = raw_ent(z, q);
         int64_t kz = rp[z] + (p - lo);
-        dcol[kz] = v;
-        dq[kz] = q;
+        raw[kz] = raw_ent(v, q);
     }
 }
 
@@ -191,8 +204,8 @@ __global__ void k_class_keys(const int32_t* __restrict__ cnt, int32_t n, int32_t
 
 // Rows with at most one entry: copy through.
 __global__ void k_sort_trivial(const int32_t* __restrict__ rows, int32_t nrows, const int32_t* __restrict__ cnt,
-                               const int64_t* __restrict__ rp, const int32_t* __restrict__ dcol,
-                               const int64_t* __restrict__ dq, int32_t* __restrict__ scol, int64_t* __restrict__ sq,
+                               const int64_t* __restrict__ rp, const RawEnt* __restrict__ raw,
+                               int32_t* __restrict__ scol, int64_t* __restrict__ sq,
                                int32_t* __restrict__ ucnt) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= nrows) return;
@@ -200,8 +213,9 @@ __global__ void k_sort_trivial(const int32_t* __restrict__ rows, int32_t nrows, 
     int c = cnt[r];
     ucnt[r] = c;
     if (c == 1) {
-        scol[rp[r]] = dcol[rp[r]];
-        sq[rp[r]] = dq[rp[r]];
+        const RawEnt e = raw[rp[r]];
+        scol[rp[r]] = e.col;
+        sq[rp[r]] = e.q;
     }
 }
 
@@ -210,7 +224,7 @@ __global__ void k_sort_trivial(const int32_t* __restrict__ rows, int32_t nrows, 
 template <int G>
 __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ rows, int32_t nrows,
                                                     const int32_t* __restrict__ cnt, const int64_t* __restrict__ rp,
-                                                    const int32_t* __restrict__ dcol, const int64_t* __restrict__ dq,
+                                                    const RawEnt* __restrict__ raw,
                                                     int32_t* __restrict__ scol, int64_t* __restrict__ sq,
                                                     int32_t* __restrict__ ucnt) {
     int64_t gid = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
@@ -224,8 +238,9 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
     int key = 0x7fffffff;
     int64_t q = 0;
     if (l < len) {
-        key = dcol[base + l];
-        q = dq[base + l];
+        const RawEnt e = raw[base + l];
+        key = e.col;
+        q = e.q;
     }
 #pragma unroll
     for (int k = 2; k <= G; k <<= 1) {
@@ -281,8 +296,8 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
 constexpr int kLongBT = 1024;
 
 __global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ cnt,
-                                                   const int64_t* __restrict__ rp, const int32_t* __restrict__ dcol,
-                                                   const int64_t* __restrict__ dq, uint64_t* __restrict__ tkey,
+                                                   const int64_t* __restrict__ rp, const RawEnt* __restrict__ raw,
+                                                   uint64_t* __restrict__ tkey,
                                                    int32_t* __restrict__ scol, int64_t* __restrict__ sq,
                                                    int32_t* __restrict__ ucnt, int lds_keys) {
     extern __shared__ uint64_t lkey[];
@@ -295,7 +310,7 @@ __global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict
     while (P < n) P <<= 1;
     uint64_t* key = P <= lds_keys ? lkey : tkey + base;
     for (int k = threadIdx.x; k < n; k += kLongBT)
-        key[k] = (static_cast<uint64_t>(static_cast<uint32_t>(dcol[base + k])) << 32) | static_cast<uint32_t>(k);
+        key[k] = (static_cast<uint64_t>(static_cast<uint32_t>(raw[base + k].col)) << 32) | static_cast<uint32_t>(k);
     __threadfence_block();
     __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
@@ -340,7 +355,7 @@ __global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict
         if (head) {
             int64_t s = 0;
             for (int m = k; m < n && static_cast<uint32_t>(key[m] >> 32) == col; ++m)
-                s += dq[base + static_cast<uint32_t>(key[m] & 0xffffffffu)];
+                s += raw[base + static_cast<uint32_t>(key[m] & 0xffffffffu)].q;
             scol[base + carry + idx] = static_cast<int32_t>(col);
             sq[base + carry + idx] = s;
         }
@@ -583,14 +598,14 @@ void build_netlist(Graph& g, hipStream_t s) {
         cls[k] = lists.p + w[1 + k];
     }
 
-    DevBuf<int32_t> cursor, dcol, scol, ucnt;
-    DevBuf<int64_t> dq, sq;
+    DevBuf<int32_t> cursor, scol, ucnt;
+    DevBuf<RawEnt> raw;
+    DevBuf<int64_t> sq;
     cursor.ensure(static_cast<size_t>(N) + 1, s);
     fill_i32(cursor.p, N + 1, 0, s);
-    dcol.ensure(static_cast<size_t>(nnz_dup) + 1, s);
-    dq.ensure(static_cast<size_t>(nnz_dup) + 1, s);
+    raw.ensure(static_cast<size_t>(nnz_dup) + 1, s);
     if (n_pins)
-        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, rp.p, cursor.p, dcol.p, dq.p);
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, rp.p, cursor.p, raw.p);
     AHR_LAUNCHED("k_scatter");
     cursor.release(s);
     pin_net.release(s);
@@ -604,20 +619,20 @@ void build_netlist(Graph& g, hipStream_t s) {
     fill_i32(ucnt.p, N + 1, 0, s);
     if (ncls[0])
         hipLaunchKernelGGL(k_sort_trivial, dim3(grid_for(ncls[0], kBT)), dim3(kBT), 0, s, cls[0], ncls[0], cnt.p,
-                           rp.p, dcol.p, dq.p, scol.p, sq.p, ucnt.p);
+                           rp.p, raw.p, scol.p, sq.p, ucnt.p);
     AHR_LAUNCHED("k_sort_trivial");
     if (ncls[1])
         hipLaunchKernelGGL(k_sort_group<16>, dim3(grid_for(static_cast<int64_t>(ncls[1]) * 16, kBT)), dim3(kBT), 0, s,
-                           cls[1], ncls[1], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p, ucnt.p);
+                           cls[1], ncls[1], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p);
     AHR_LAUNCHED("k_sort_group16");
     if (ncls[2])
         hipLaunchKernelGGL(k_sort_group<32>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 32, kBT)), dim3(kBT), 0, s,
-                           cls[2], ncls[2], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
+                           cls[2], ncls[2], cnt.p, rp.p, raw.p, scol.p, sq.p,
                            ucnt.p);
     AHR_LAUNCHED("k_sort_group32");
     if (ncls[3])
         hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[3]) * 64, kBT)), dim3(kBT), 0, s,
-                           cls[3], ncls[3], cnt.p, rp.p, dcol.p, dq.p, scol.p, sq.p,
+                           cls[3], ncls[3], cnt.p, rp.p, raw.p, scol.p, sq.p,
                            ucnt.p);
     AHR_LAUNCHED("k_sort_group64");
     if (ncls[4]) {
@@ -625,13 +640,12 @@ void build_netlist(Graph& g, hipStream_t s) {
         tkey.ensure(static_cast<size_t>(nnz_dup) + 1, s);
         const int lds_keys = sort_lds_keys(g.device);
         hipLaunchKernelGGL(k_sort_long, dim3(ncls[4]), dim3(kLongBT), static_cast<size_t>(lds_keys) * sizeof(uint64_t), s,
-                           cls[4], cnt.p, rp.p, dcol.p, dq.p, tkey.p, scol.p, sq.p,
+                           cls[4], cnt.p, rp.p, raw.p, tkey.p, scol.p, sq.p,
                            ucnt.p, lds_keys);
         AHR_LAUNCHED("k_sort_long");
         tkey.release(s);
     }
-    dcol.release(s);
-    dq.release(s);
+    raw.release(s);
 
     // final CSR
     g.net_rp.ensure(static_cast<size_t>(N) + 1, s);
