@@ -300,13 +300,11 @@ __device__ __forceinline__ void window(const Grid& gr, int b, int& x0, int& x1, 
 }
 
 // Per hint cell (execution row): the macros whose footprint holds it and the
-// size of its bin window; with `mcnt`, each such macro's count of cells is
-// incremented.  With `pairs`, also lists its (row, macro) pairs at
-// pair_off[r] in ascending macro order.
+// size of its bin window.  With `pairs`, also lists its (row, macro) pairs
+// at pair_off[r] in ascending macro order.
 __global__ void __launch_bounds__(kBT) k_cell_count(HintArgs a, int32_t* __restrict__ nmac,
                                                     int32_t* __restrict__ nwin, const int32_t* __restrict__ pair_off,
-                                                    int32_t* __restrict__ pair_row, int32_t* __restrict__ pair_mac,
-                                                    int32_t* __restrict__ mcnt) {
+                                                    int32_t* __restrict__ pair_row, int32_t* __restrict__ pair_mac) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
     if (r >= a.n_inst) return;
     int b = a.cell_bin[r];
@@ -326,7 +324,6 @@ __global__ void __launch_bounds__(kBT) k_cell_count(HintArgs a, int32_t* __restr
                     pair_row[o + n] = static_cast<int32_t>(r);
                     pair_mac[o + n] = k;
                 }
-                if (mcnt) atomicAdd(&mcnt[k], 1);
                 ++n;
             }
         }
@@ -345,10 +342,10 @@ __global__ void k_cell_hint_cnt(int32_t n_inst, const int32_t* __restrict__ nmac
     if (r < n_inst) cnt[r] = nmac[r] + nwin[r];
 }
 
-__global__ void k_macro_row_cnt(int32_t n_macro, int32_t first_mvirt, const int32_t* __restrict__ mcnt,
+__global__ void k_macro_row_cnt(int32_t n_macro, int32_t first_mvirt, const int32_t* __restrict__ mstart,
                                 int32_t* __restrict__ cnt) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n_macro) cnt[first_mvirt + k] = mcnt[k];
+    if (k < n_macro) cnt[first_mvirt + k] = mstart[k + 1] - mstart[k];
 }
 
 __global__ void k_bin_row_counts(HintArgs a, int32_t* __restrict__ cnt) {
@@ -641,58 +638,49 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     a.xpos = g.xpos.p;
     a.xbase_w = g.xbase_w.p;
 
-    // 5. per cell: macros holding it, window size; cells per macro
+    // 5. per cell: macros holding it, window size; (cell, macro) pairs
     g.nmac.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.nwin.ensure(static_cast<size_t>(n_inst) + 1, s);
-    DevBuf<int32_t> mcnt;
-    if (use_macros) {
-        mcnt.ensure(static_cast<size_t>(n_macro) + 1, s);
-        fill_i32(mcnt.p, n_macro + 1, 0, s);
-    }
     hipLaunchKernelGGL(k_cell_count, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a, g.nmac.p, g.nwin.p,
                        static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
-                       static_cast<int32_t*>(nullptr), use_macros ? mcnt.p : static_cast<int32_t*>(nullptr));
+                       static_cast<int32_t*>(nullptr));
     AHR_LAUNCHED("k_cell_count");
     g.pair_off.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(std::max<int64_t>(N, n_inst)), s);
     scan_i32_to_i32(g.nmac.p, g.pair_off.p, n_inst, g.scan_tmp.p, s);
+    int32_t tot[2];
+    read_scalars({g.pair_off.p + n_inst, g.bin_start.p + nbins}, tot, s);
+    const int32_t n_pairs = tot[0];
+    g.n_hint_cells = tot[1];
+    g.pair_row.ensure(static_cast<size_t>(n_pairs) + 1, s);
+    g.pair_mac.ensure(static_cast<size_t>(n_pairs) + 1, s);
+    if (n_pairs) {
+        hipLaunchKernelGGL(k_cell_count, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a,
+                           static_cast<int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+                           static_cast<const int32_t*>(g.pair_off.p), g.pair_row.p, g.pair_mac.p);
+        AHR_LAUNCHED("k_cell_count pairs");
+    }
+    // pairs grouped by macro, ascending row: the macro virtual rows
+    if (use_macros) bucket_sort(g, g.pair_mac.p, n_pairs, n_macro, g.mlist, g.mstart, s, false);
 
-    // 6. row counts and offsets (execution order); one read of the totals
+    // 6. row counts and offsets (execution order)
     hipLaunchKernelGGL(k_cell_hint_cnt, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.nmac.p, g.nwin.p,
                        g.hint_cnt.p);
     AHR_LAUNCHED("k_cell_hint_cnt");
     if (use_macros) {
         hipLaunchKernelGGL(k_macro_row_cnt, dim3(grid_for(n_macro, kBT)), dim3(kBT), 0, s, n_macro, g.first_mvirt,
-                           mcnt.p, g.hint_cnt.p);
+                           g.mstart.p, g.hint_cnt.p);
         AHR_LAUNCHED("k_macro_row_cnt");
     }
     if (bin_hints) {
         hipLaunchKernelGGL(k_bin_row_counts, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s, a, g.hint_cnt.p);
         AHR_LAUNCHED("k_bin_row_counts");
     }
-    const int64_t* nnz_dev = scan_i32_total(g.hint_cnt.p, g.xhint_rp.p, N, g.scan_tmp.p, s);
-    int64_t tot[3];
-    read_words({{g.pair_off.p + n_inst, 0}, {g.bin_start.p + nbins, 0}, {nnz_dev, 1}}, tot, s);
-    mcnt.release(s);
-    const int32_t n_pairs = static_cast<int32_t>(tot[0]);
-    g.n_hint_cells = static_cast<int32_t>(tot[1]);
-    const int64_t nnz = tot[2];
+    const int64_t nnz = scan_i32_checked(g.hint_cnt.p, g.xhint_rp.p, N, g.scan_tmp.p, s);
     if (nnz + static_cast<int64_t>(g.nnz_net) >= INT32_MAX)
         throw Error{AHR_EUNSUPPORTED, "graph with hints has 2^31 or more entries"};
     g.nnz_hint = static_cast<int32_t>(nnz);
     g.xhint_ent.ensure(static_cast<size_t>(nnz) + 1, s);
-
-    // (cell, macro) pairs, then grouped by macro, ascending row: the macro virtual rows
-    g.pair_row.ensure(static_cast<size_t>(n_pairs) + 1, s);
-    g.pair_mac.ensure(static_cast<size_t>(n_pairs) + 1, s);
-    if (n_pairs) {
-        hipLaunchKernelGGL(k_cell_count, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, a,
-                           static_cast<int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
-                           static_cast<const int32_t*>(g.pair_off.p), g.pair_row.p, g.pair_mac.p,
-                           static_cast<int32_t*>(nullptr));
-        AHR_LAUNCHED("k_cell_count pairs");
-    }
-    if (use_macros) bucket_sort(g, g.pair_mac.p, n_pairs, n_macro, g.mlist, g.mstart, s, false);
 
     // 7. entries: cell rows first (their weights are reused), then virtual rows
     const int wslots = (2 * gr.hx + 1) * (2 * gr.hy + 1);
