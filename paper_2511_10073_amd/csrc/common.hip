@@ -211,11 +211,55 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_scan(const Tin* __restric
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = static_cast<Tout>(sums[ntiles]);
 }
 
+// Up to kDirectTiles tiles, the tile offsets are not scanned by a separate
+// kernel: each workgroup of the final pass adds up the sums of the tiles
+// before it (a few KB of cached reads), and workgroup 0 adds all of them for
+// the total.
+constexpr int64_t kDirectTiles = 4096;
+
+template <class Tin, class Tout>
+__global__ void __launch_bounds__(kScanThreads) k_tile_scan_direct(const Tin* __restrict__ in, int64_t n,
+                                                                   int64_t* __restrict__ sums, int64_t ntiles,
+                                                                   Tout* __restrict__ out) {
+    __shared__ int64_t red[kScanThreads / 64];
+    const int64_t upto = blockIdx.x == 0 ? ntiles : static_cast<int64_t>(blockIdx.x);
+    int64_t pre = 0;
+    for (int64_t j = threadIdx.x; j < upto; j += kScanThreads) pre += sums[j];
+    pre = block_sum_i64<kScanThreads>(pre, red);
+    const int64_t tile_off = blockIdx.x == 0 ? 0 : pre;
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
+    int64_t v[kScanItems];
+    int64_t local = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? static_cast<int64_t>(in[i]) : 0;
+        local += v[k];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan_i64<kScanThreads>(local, red, &tot);
+    int64_t run = tile_off + ex;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = static_cast<Tout>(run);
+        run += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sums[ntiles] = pre;
+        out[n] = static_cast<Tout>(pre);
+    }
+}
+
 template <class Tin, class Tout>
 static void scan_impl(const Tin* in, Tout* out, int64_t n, int64_t* tmp, hipStream_t s) {
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;   // n > 0
     hipLaunchKernelGGL((k_tile_sums<Tin>), dim3(ntiles), dim3(kScanThreads), 0, s, in, n, tmp);
     AHR_LAUNCHED("k_tile_sums");
+    if (ntiles <= kDirectTiles) {
+        hipLaunchKernelGGL((k_tile_scan_direct<Tin, Tout>), dim3(ntiles), dim3(kScanThreads), 0, s, in, n, tmp, ntiles,
+                           out);
+        AHR_LAUNCHED("k_tile_scan_direct");
+        return;
+    }
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tmp, ntiles);
     AHR_LAUNCHED("k_scan_sums");
     hipLaunchKernelGGL((k_tile_scan<Tin, Tout>), dim3(ntiles), dim3(kScanThreads), 0, s, in, n, tmp, ntiles, out);

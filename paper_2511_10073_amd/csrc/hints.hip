@@ -137,32 +137,61 @@ __global__ void __launch_bounds__(kWave) k_bucket_count(const int32_t* __restric
     for (int b = threadIdx.x; b < nbins; b += kWave) h[b] = 0;
     __syncthreads();
     int64_t base = static_cast<int64_t>(blockIdx.x) * kTileCells;
+    int key[kTileIters];       // the tile's keys, all loads in flight together
+#pragma unroll
     for (int t = 0; t < kTileIters; ++t) {
         int64_t i = base + t * kWave + threadIdx.x;
-        if (i < n) {
-            int b = cell_bin[i];
-            if (b >= 0) atomicAdd(&h[b], 1);
-        }
+        key[t] = i < n ? cell_bin[i] : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < kTileIters; ++t)
+        if (key[t] >= 0) atomicAdd(&h[key[t]], 1);
+    __syncthreads();
+    // tile-major: this tile's counters are one contiguous row
+    for (int b = threadIdx.x; b < nbins; b += kWave) hist[static_cast<int64_t>(blockIdx.x) * nbins + b] = h[b];
+}
+
+// out[c][r] = in[r][c] for an rows x cols int32 matrix, through 32 x 32 LDS tiles.
+constexpr int kTr = 32;
+__global__ void __launch_bounds__(kTr * 8) k_transpose_i32(const int32_t* __restrict__ in, int64_t rows,
+                                                            int64_t cols, int32_t* __restrict__ out) {
+    __shared__ int32_t t[kTr][kTr + 1];
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kTr, r0 = static_cast<int64_t>(blockIdx.y) * kTr;
+    const int tx = threadIdx.x % kTr, ty = threadIdx.x / kTr;
+    for (int k = ty; k < kTr; k += 8) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) t[k][tx] = in[r * cols + c];
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += kWave) hist[static_cast<int64_t>(b) * ntiles + blockIdx.x] = h[b];
+    for (int k = ty; k < kTr; k += 8) {
+        const int64_t c = c0 + k, r = r0 + tx;
+        if (r < rows && c < cols) out[c * rows + r] = t[tx][k];
+    }
 }
 
 // Pass 2: place every hint cell at offset(bin, tile) + rank among the
-// tile's earlier cells of the same bin (lanes in id order, tiles in order).
+// tile's earlier cells of the same bin (lanes in id order, tiles in order);
+// off is tile-major, like the counts.
 __global__ void __launch_bounds__(kWave) k_bucket_scatter(const int32_t* __restrict__ cell_bin, int32_t n, int nbins,
                                                           int bits, int32_t ntiles, const int32_t* __restrict__ off,
                                                           int32_t* __restrict__ out) {
     extern __shared__ int32_t run[];   // nbins cursors (dynamic)
-    for (int b = threadIdx.x; b < nbins; b += kWave) run[b] = off[static_cast<int64_t>(b) * ntiles + blockIdx.x];
+    for (int b = threadIdx.x; b < nbins; b += kWave) run[b] = off[static_cast<int64_t>(blockIdx.x) * nbins + b];
     __syncthreads();
     int l = threadIdx.x;
     uint64_t lt = l ? (~0ull >> (kWave - l)) : 0ull;
     uint64_t gt = (l == kWave - 1) ? 0ull : (~0ull << (l + 1));
     int64_t base = static_cast<int64_t>(blockIdx.x) * kTileCells;
+    int key[kTileIters];       // the tile's keys, all loads in flight together
+#pragma unroll
     for (int t = 0; t < kTileIters; ++t) {
         int64_t i = base + t * kWave + l;
-        int b = (i < n) ? cell_bin[i] : -1;
+        key[t] = i < n ? cell_bin[i] : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < kTileIters; ++t) {
+        int64_t i = base + t * kWave + l;
+        int b = key[t];
         bool valid = b >= 0;
         uint64_t peer = __ballot(valid);
         for (int k = 0; k < bits; ++k) {
@@ -484,17 +513,25 @@ int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<i
     g.i32a.ensure(static_cast<size_t>(hn) + 1, s);
     g.i32b.ensure(static_cast<size_t>(hn) + 1, s);
     const size_t lds = static_cast<size_t>(nkeys) * sizeof(int32_t);
+    // counts tile-major (i32a) -> bucket-major (i32b) -> exclusive scan in
+    // bucket-then-tile order (i32a, total at [hn]) -> tile-major offsets (i32b)
     hipLaunchKernelGGL(k_bucket_count, dim3(ntiles), dim3(kWave), lds, s, key, n, nkeys, ntiles, g.i32a.p);
     AHR_LAUNCHED("k_bucket_count");
+    hipLaunchKernelGGL(k_transpose_i32, dim3((nkeys + kTr - 1) / kTr, (ntiles + kTr - 1) / kTr), dim3(kTr * 8), 0, s,
+                       g.i32a.p, static_cast<int64_t>(ntiles), static_cast<int64_t>(nkeys), g.i32b.p);
+    AHR_LAUNCHED("k_transpose_i32");
     g.scan_tmp.ensure(scan_tmp_elems(hn), s);
-    scan_i32_to_i32(g.i32a.p, g.i32b.p, hn, g.scan_tmp.p, s);
+    scan_i32_to_i32(g.i32b.p, g.i32a.p, hn, g.scan_tmp.p, s);
+    hipLaunchKernelGGL(k_transpose_i32, dim3((ntiles + kTr - 1) / kTr, (nkeys + kTr - 1) / kTr), dim3(kTr * 8), 0, s,
+                       g.i32a.p, static_cast<int64_t>(nkeys), static_cast<int64_t>(ntiles), g.i32b.p);
+    AHR_LAUNCHED("k_transpose_i32");
     int bits = 0;
     while ((1 << bits) < nkeys) ++bits;
     hipLaunchKernelGGL(k_bucket_scatter, dim3(ntiles), dim3(kWave), lds, s, key, n, nkeys, bits, ntiles, g.i32b.p,
                        list.p);
     AHR_LAUNCHED("k_bucket_scatter");
-    hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nkeys + 1, kBT)), dim3(kBT), 0, s, g.i32b.p, nkeys, ntiles,
-                       g.i32b.p + hn, start.p);
+    hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nkeys + 1, kBT)), dim3(kBT), 0, s, g.i32a.p, nkeys, ntiles,
+                       g.i32a.p + hn, start.p);
     AHR_LAUNCHED("k_bin_start");
     if (!read_total) return -1;
     return read_i32(start.p + nkeys, s);
