@@ -201,6 +201,9 @@ struct Graph {
     DevBuf<int64_t> xcell;        // [n_inst] per execution row: cell area (2^-28 units) * 4 + cell class
     DevBuf<double> xbase_w;       // [n_inst] per execution row: baseWeight
     DevBuf<float2> xpos;          // [n_inst] per execution row: the current placement's (x, y)
+    DevBuf<double> xhabs;         // [n_inst] per execution row: sum of |hint weight| (hint_version habs_version)
+    DevBuf<float> xhsg;           // [n_inst] per execution row: signed sum of the hint weights
+    int32_t habs_version = -1;
     int32_t has_xcell = 0;
 
     // execution layout: instance rows in spatial order (perm: exec -> id)

@@ -31,6 +31,8 @@ Graph::~Graph() {
     xcell.release(s);
     xbase_w.release(s);
     xpos.release(s);
+    xhabs.release(s);
+    xhsg.release(s);
     bin_area_q.release(s);
     phi.release(s);
     macro_span.release(s);

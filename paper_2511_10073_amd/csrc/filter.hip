@@ -166,11 +166,11 @@ __global__ void k_coef(int32_t n, const float* __restrict__ scale, const double*
 // and the signed sum of the row's hint weights (a feature of the learned
 // surrogate).
 template <int G>
-__global__ void __launch_bounds__(kBT) k_deg_short(int32_t n, RowRef m, const int64_t* __restrict__ qdeg, double sigma,
-                                                   double* __restrict__ deg, float* __restrict__ scale,
+__global__ void __launch_bounds__(kBT) k_deg_short(int32_t r0, int32_t n, RowRef m, const int64_t* __restrict__ qdeg,
+                                                   double sigma, double* __restrict__ deg, float* __restrict__ scale,
                                                    float* __restrict__ hsum) {
     int64_t t = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
-    int64_t r = t / G;
+    int64_t r = r0 + t / G;
     int l = static_cast<int>(t & (G - 1));
     if (r >= n) return;
     int h0 = m.hint_rp[r], h1 = m.hint_rp[r + 1];
@@ -193,6 +193,21 @@ __global__ void __launch_bounds__(kBT) k_deg_short(int32_t n, RowRef m, const in
         scale[r] = d > 0 ? static_cast<float>(1.0 / sqrt(d)) : 0.f;
         hsum[r] = static_cast<float>(sg);
     }
+}
+
+// The same for the short cell rows, from the hint sums the hint build
+// formed for every cell.
+__global__ void k_deg_cells(int32_t n_inst, RowRef m, const int64_t* __restrict__ qdeg,
+                            const double* __restrict__ habs, const float* __restrict__ hsg, double sigma,
+                            double* __restrict__ deg, float* __restrict__ scale, float* __restrict__ hsum) {
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n_inst) return;
+    int len = (m.net_rp[r + 1] - m.net_rp[r]) + (m.hint_rp[r + 1] - m.hint_rp[r]);
+    if (len > kLongRow) return;
+    double d = static_cast<double>(qdeg[r]) * 0x1p-32 + habs[r] + sigma;
+    deg[r] = d;
+    scale[r] = d > 0 ? static_cast<float>(1.0 / sqrt(d)) : 0.f;
+    hsum[r] = hsg[r];
 }
 
 __device__ __forceinline__ void chunk_range(int c, const int32_t* long_rows, const int32_t* chunk_row,
@@ -1368,9 +1383,19 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     g.hsum.ensure(static_cast<size_t>(N) + 1, s);
     g.lam.ensure(1, s);
     constexpr int G = 4;
-    hipLaunchKernelGGL(k_deg_short<G>, dim3(grid_for(static_cast<int64_t>(N) * G, kBT)), dim3(kBT), 0, s, N, m,
-                       g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
-    AHR_LAUNCHED("k_deg_short");
+    // cell rows from the hint build's sums when it formed them for this
+    // hint version, then the other rows from their entries
+    const int32_t r0 = g.habs_version == g.hint_version ? g.n_inst : 0;
+    if (r0) {
+        hipLaunchKernelGGL(k_deg_cells, dim3(grid_for(r0, kBT)), dim3(kBT), 0, s, r0, m, g.xqdeg.p, g.xhabs.p,
+                           g.xhsg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
+        AHR_LAUNCHED("k_deg_cells");
+    }
+    if (N > r0) {
+        hipLaunchKernelGGL(k_deg_short<G>, dim3(grid_for(static_cast<int64_t>(N - r0) * G, kBT)), dim3(kBT), 0, s, r0,
+                           N, m, g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
+        AHR_LAUNCHED("k_deg_short");
+    }
     if (g.rc.n_long) {
         hipLaunchKernelGGL(k_chunk_absdeg, dim3(g.rc.n_chunks), dim3(kBT), 0, s, m, g.rc.long_rows.p, g.rc.chunk_row.p,
                            g.rc.long_chunk0.p, g.rc.partial.p);

@@ -318,6 +318,8 @@ struct HintArgs {
     const double* base_w;         // by instance
     const float2* xpos;           // by execution row
     const double* xbase_w;        // by execution row
+    double* habs;                 // by execution row: sum of |weight| of the cell's hint entries
+    float* hsg;                   // by execution row: their signed sum
 };
 
 __device__ __forceinline__ void window(const Grid& gr, int b, int& x0, int& x1, int& y0, int& y1) {
@@ -399,7 +401,9 @@ __global__ void k_bin_row_counts(HintArgs a, int32_t* __restrict__ cnt) {
 // the bin-row stores of a wave are then consecutive slots of one bin row.
 // The workgroup's cell rows are one contiguous range of entries; they are
 // assembled in LDS (up to kFillCap entries; any further ones are stored
-// directly) and stored with coalesced writes.
+// directly) and stored with coalesced writes.  Each cell's sums of |w| and
+// of w over its hint entries (its hint degree and the signed hint sum) are
+// formed on the way, in float64.
 constexpr int kFillCap = 16 * kBT;
 
 __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __restrict__ rp,
@@ -412,6 +416,7 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
     const int64_t r = r0 + threadIdx.x;
     const int64_t rend = r0 + kBT < a.n_inst ? r0 + kBT : a.n_inst;
     const int64_t e0 = rp[r0], e1 = rp[rend];       // the workgroup's cell-row entries
+    double ha = 0.0, hs = 0.0;
     if (r < a.n_inst) {
         const int b = a.cell_bin[r];
         if (b >= 0) {
@@ -429,7 +434,10 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
             };
             for (int p = pair_off[r]; p < pair_off[r + 1]; ++p) {
                 int k = pair_mac[p];
-                put(make_int2(a.first_mvirt + k, f_bits(w_macro(x, y, a.rect[k], bwi))));
+                const float wm = w_macro(x, y, a.rect[k], bwi);
+                ha += fabs(static_cast<double>(wm));
+                hs += static_cast<double>(wm);
+                put(make_int2(a.first_mvirt + k, f_bits(wm)));
             }
             if (a.bin_hints) {
                 const int ww = 2 * a.gr.hx + 1, wh = 2 * a.gr.hy + 1;
@@ -440,7 +448,10 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
                 for (int ty = y0; ty <= y1; ++ty)
                     for (int tx = x0; tx <= x1; ++tx) {
                         int bb = ty * a.gr.nbx + tx;
-                        int w = f_bits(w_bin(a.gr, x, y, bb, a.phi, bwi));
+                        const float wb = w_bin(a.gr, x, y, bb, a.phi, bwi);
+                        ha += fabs(static_cast<double>(wb));
+                        hs += static_cast<double>(wb);
+                        int w = f_bits(wb);
                         put(make_int2(a.first_bvirt + bb, w));
                         // slot of this cell's bin inside the window of bb
                         int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
@@ -449,6 +460,10 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
                     }
             }
         }
+    }
+    if (r < a.n_inst) {
+        a.habs[r] = ha;
+        a.hsg[r] = static_cast<float>(hs);
     }
     __syncthreads();
     const int64_t nst = e1 - e0 < kFillCap ? e1 - e0 : kFillCap;
@@ -674,6 +689,10 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     a.base_w = g.base_w.p;
     a.xpos = g.xpos.p;
     a.xbase_w = g.xbase_w.p;
+    g.xhabs.ensure(static_cast<size_t>(n_inst) + 1, s);
+    g.xhsg.ensure(static_cast<size_t>(n_inst) + 1, s);
+    a.habs = g.xhabs.p;
+    a.hsg = g.xhsg.p;
 
     // 5. per cell: macros holding it, window size; (cell, macro) pairs
     g.nmac.ensure(static_cast<size_t>(n_inst) + 1, s);
@@ -736,6 +755,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
                        static_cast<const int32_t*>(g.pair_mac.p), static_cast<const int32_t*>(g.bin_rank.p),
                        static_cast<const int32_t*>(g.wpre.p), g.xhint_ent.p);
     AHR_LAUNCHED("k_cell_fill");
+    g.habs_version = g.hint_version;
     if (use_macros && n_pairs) {
         hipLaunchKernelGGL(k_macro_fill, dim3(grid_for(n_pairs, kBT)), dim3(kBT), 0, s, n_pairs, g.first_mvirt,
                            g.mlist.p, g.mstart.p, g.pair_row.p, g.pair_mac.p, g.pair_off.p, g.xhint_rp.p,
