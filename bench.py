@@ -34,8 +34,8 @@ HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("fil
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "sources_sha256": "777866c486fb1ca4fd43c7f8aa073035d8f32e024cd8aa95844693f9dc828676",
-               "bytes_per_launch": 1647129896,
+               "sources_sha256": "902cb14840d28169b97dee9bca776a4130180dc01e86be79f063abbc72300034",
+               "bytes_per_launch": 1647021900,
                "source": "profiles/k_hop_large-2.2M_hbm_traffic.md"}
 
 
