@@ -204,6 +204,7 @@ struct Graph {
     DevBuf<double> xhabs;         // [n_inst] per execution row: sum of |hint weight| (hint_version habs_version)
     DevBuf<float> xhsg;           // [n_inst] per execution row: signed sum of the hint weights
     int32_t habs_version = -1;
+    DevBuf<double> gmax;          // first-hop Gershgorin maxima (per workgroup, then per long row)
     int32_t has_xcell = 0;
 
     // execution layout: instance rows in spatial order (perm: exec -> id)

@@ -33,6 +33,7 @@ Graph::~Graph() {
     xpos.release(s);
     xhabs.release(s);
     xhsg.release(s);
+    gmax.release(s);
     bin_area_q.release(s);
     phi.release(s);
     macro_span.release(s);

@@ -904,6 +904,210 @@ __global__ void __launch_bounds__(kBT) k_hop_rb(HopArgs a0) {
     hop_row_block<C, NT>(a, static_cast<int>(blk));
 }
 
+// ------------------------------------------------ first hop with lambda_up
+//
+// When lambda_up is the Gershgorin bound and not yet known, the first hop
+// also forms every row's Gershgorin sum sum_j |A_ij| s_j while it streams
+// the entries (gathering s_j beside z_j), so the bound costs no pass of its
+// own.  The hop's epilogue needs lambda_up, so the rows' neighbour sums are
+// stored unscaled in zout and the epilogue runs after the bound is reduced
+// (k_hop1_epi).  Entry order, clamping and sums are those of k_hop and of
+// k_gersh_short / k_chunk_gersh, so the results are the same bits.
+
+template <int C, int U>
+__device__ __forceinline__ void gather_batch_gersh(const HopArgs& a, int n0, int ln, int h0, int len, int k0, int step,
+                                                   float* acc, double& ag) {
+    int2 e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int k = k0 + u * step;
+        int kc = k < len ? k : len - 1;
+        e[u] = row_entry<false>(a.m, n0, ln, h0, kc);
+        if (k >= len) e[u].y = 0;
+    }
+    Vec<C> v[U];
+    float sc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        v[u] = vload<C>(a.zin + static_cast<int64_t>(e[u].x) * C);
+        sc[u] = a.scale[e[u].x];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float w = bits_f(e[u].y);
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += w * v[u].v[c];
+        ag += fabs(static_cast<double>(w)) * static_cast<double>(sc[u]);
+    }
+}
+
+// One chunk of a long row: float64 partials of the C neighbour sums at
+// partial[chunk * 8 + c] and of the Gershgorin sum at partial[chunk * 8 + C].
+template <int C>
+__device__ __forceinline__ void hop1_chunk(const HopArgs& a) {
+    __shared__ double red[kBT / kWave];
+    int r, li, k0, k1, n0, ln, h0;
+    chunk_range(blockIdx.x, a.long_rows, a.chunk_row, a.chunk0, a.m, r, li, k0, k1, n0, ln, h0);
+    constexpr int U = kChunk / kBT;
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    double ag = 0;
+    {
+        int2 e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int k = k0 + static_cast<int>(threadIdx.x) + u * kBT;
+            int kc = k < k1 ? k : k1 - 1;
+            e[u] = row_entry<false>(a.m, n0, ln, h0, kc);
+            if (k >= k1) e[u].y = 0;
+        }
+        Vec<C> v[U];
+        float sc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = vload<C>(a.zin + static_cast<int64_t>(e[u].x) * C);
+            sc[u] = a.scale[e[u].x];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double w = static_cast<double>(bits_f(e[u].y));
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += w * static_cast<double>(v[u].v[c]);
+            ag += fabs(w) * static_cast<double>(sc[u]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = block_sum_f64<kBT>(acc[c], red);
+    ag = block_sum_f64<kBT>(ag, red);
+    if (threadIdx.x == 0) {
+        double* part = a.partial + static_cast<int64_t>(blockIdx.x) * 8;
+#pragma unroll
+        for (int c = 0; c < C; ++c) part[c] = acc[c];
+        part[C] = ag;
+    }
+}
+
+// Chunk workgroups first, then short-row tiles (G lanes per row, XCD-dealt
+// as in k_hop); every thread reaches the workgroup's maximum, which goes to
+// wgmax[tile].
+template <int C, int G, int U>
+__global__ void __launch_bounds__(kBT) k_hop1_gersh(HopArgs a, const double* __restrict__ deg,
+                                                    double* __restrict__ wgmax) {
+    __shared__ double red[kBT / kWave];
+    if (static_cast<int>(blockIdx.x) < a.n_chunk_blocks) {
+        hop1_chunk<C>(a);
+        return;
+    }
+    const int64_t nb = static_cast<int64_t>(gridDim.x) - a.n_chunk_blocks;     // a multiple of kXcds
+    const int64_t tile = xcd_tile(static_cast<int64_t>(blockIdx.x) - a.n_chunk_blocks, nb);
+    const int64_t r64 = (tile * kBT + threadIdx.x) / G;
+    const int l = static_cast<int>(threadIdx.x & (G - 1));
+    bool valid = r64 < a.n_rows;
+    const int r = valid ? static_cast<int>(r64) : 0;
+    int n0 = 0, ln = 0, h0 = 0, len = 0;
+    if (valid) {
+        n0 = a.m.net_rp[r];
+        ln = a.m.net_rp[r + 1] - n0;
+        h0 = a.m.hint_rp[r];
+        len = ln + (a.m.hint_rp[r + 1] - h0);
+        if (len > kLongRow) valid = false;                 // group-uniform: chunk workgroups
+    }
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.f;
+    double ag = 0;
+    if (valid)
+        for (int k0 = l; k0 < len; k0 += G * U) gather_batch_gersh<C, U>(a, n0, ln, h0, len, k0, G, acc, ag);
+    Vec<C> sum;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sum.v[c] = acc[c];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sum.v[c] += __shfl_xor(sum.v[c], o);
+        ag += __shfl_xor(ag, o);
+    }
+    double gv = 0;
+    if (valid && l == 0) {
+        vstore<C>(a.zout + static_cast<int64_t>(r) * C, sum);
+        const float sr = a.scale[r];
+        gv = diag_abs(sr, deg[r], a.sigma) + static_cast<double>(sr) * ag;
+    }
+    gv = wave_max(gv);
+    __syncthreads();
+    if (lane_id() == 0) red[wave_id()] = gv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int w = 1; w < kBT / kWave; ++w) b = red[w] > b ? red[w] : b;
+        wgmax[tile] = b;
+    }
+}
+
+// Long rows: one wave per row adds its chunk partials (fixed order, as
+// k_hop_long), stores the unscaled neighbour sum in zout, and puts the
+// row's Gershgorin value (its chunks added in order, as k_long_gersh_final)
+// in lmax[li].
+template <int C>
+__global__ void __launch_bounds__(kBT) k_hop1_long(HopArgs a, int32_t n_long, const double* __restrict__ deg,
+                                                   double* __restrict__ lmax) {
+    const int64_t li = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / kWave;
+    if (li >= n_long) return;
+    const int r = a.long_rows[li];
+    const int c0 = a.chunk0[li], c1 = a.chunk0[li + 1];
+    const int l = lane_id();
+    double tot[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) tot[c] = 0;
+    for (int q = c0 + l; q < c1; q += kWave) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) tot[c] += a.partial[static_cast<int64_t>(q) * 8 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) tot[c] = wave_sum(tot[c]);
+    if (l != 0) return;
+    Vec<C> sum;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sum.v[c] = static_cast<float>(tot[c]);
+    vstore<C>(a.zout + static_cast<int64_t>(r) * C, sum);
+    double g = 0;
+    for (int q = c0; q < c1; ++q) g += a.partial[static_cast<int64_t>(q) * 8 + C];
+    const float sr = a.scale[r];
+    lmax[li] = diag_abs(sr, deg[r], a.sigma) + static_cast<double>(sr) * g;
+}
+
+// lambda_up = the largest of the workgroup and long-row maxima (0 if none).
+__global__ void __launch_bounds__(1024) k_lam_reduce(const double* __restrict__ wgmax, int64_t nwg,
+                                                     const double* __restrict__ lmax, int32_t n_long,
+                                                     double* __restrict__ lam) {
+    __shared__ double red[1024 / kWave];
+    double b = 0;
+    for (int64_t i = threadIdx.x; i < nwg; i += 1024) b = wgmax[i] > b ? wgmax[i] : b;
+    for (int64_t i = threadIdx.x; i < n_long; i += 1024) b = lmax[i] > b ? lmax[i] : b;
+    b = wave_max(b);
+    __syncthreads();
+    if (lane_id() == 0) red[wave_id()] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < 1024 / kWave; ++w) m = red[w] > m ? red[w] : m;
+        *lam = m;
+    }
+}
+
+// The first hop's epilogue once lambda_up and the coefficients are known:
+// zout holds the rows' unscaled neighbour sums.
+template <int C>
+__global__ void __launch_bounds__(kBT) k_hop1_epi(HopArgs a) {
+    const int64_t r64 = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    if (r64 >= a.n_rows) return;
+    const int r = static_cast<int>(r64);
+    const RowOps<C> ops = row_ops<C>(a, r);
+    const Vec<C> sum = vload<C>(a.zout + static_cast<int64_t>(r) * C);
+    epilogue<C>(a, r, ops, sum);
+}
+
 // K = 0: out = (sum alpha) X on movable rows, X on fixed rows.
 template <int C>
 __global__ void k_identity(int32_t n_inst, const uint8_t* __restrict__ flags, const float* __restrict__ in,
@@ -1123,9 +1327,40 @@ float alpha_at(const ahr_filter_spec& spec, int j, bool& is_band) {
     return a;
 }
 
-// Hops 1..k_max over column tiles of CT columns (C / CT tiles).
+// What the first hop needs to form lambda_up itself (k_hop1_gersh).
+struct Hop1Gersh {
+    const double* deg;
+    double* gmax;       // one slot per short-row workgroup, then one per long row
+    double* lam;
+    float2* coef;
+};
+
+// The first hop with the Gershgorin bound (4 lanes per short row).
+template <int C>
+void hop1_gersh(const ChainView& v, HopArgs h, const Hop1Gersh& f, hipStream_t s) {
+    constexpr int G = 4, U = 4;
+    int64_t tiles = grid_for(static_cast<int64_t>(h.n_rows) * G, kBT);
+    tiles = (tiles + kXcds - 1) / kXcds * kXcds;                    // see xcd_tile
+    hipLaunchKernelGGL((k_hop1_gersh<C, G, U>), dim3(static_cast<unsigned>(h.n_chunk_blocks + tiles)), dim3(kBT), 0,
+                       s, h, f.deg, f.gmax);
+    AHR_LAUNCHED("k_hop1_gersh");
+    if (v.n_long > 0) {
+        hipLaunchKernelGGL(k_hop1_long<C>, dim3(grid_for(static_cast<int64_t>(v.n_long) * kWave, kBT)), dim3(kBT), 0, s,
+                           h, v.n_long, f.deg, f.gmax + tiles);
+        AHR_LAUNCHED("k_hop1_long");
+    }
+    hipLaunchKernelGGL(k_lam_reduce, dim3(1), dim3(1024), 0, s, f.gmax, tiles, f.gmax + tiles, v.n_long, f.lam);
+    AHR_LAUNCHED("k_lam_reduce");
+    hop_coefs(v.n_tot, v.scale, f.lam, v.sigma, f.coef, s);
+    hipLaunchKernelGGL(k_hop1_epi<C>, dim3(grid_for(h.n_rows, kBT)), dim3(kBT), 0, s, h);
+    AHR_LAUNCHED("k_hop1_epi");
+}
+
+// Hops 1..k_max over column tiles of CT columns (C / CT tiles); with f, the
+// first hop also forms lambda_up (needs CT = C <= 4, k_max >= 2).
 template <int C, int CT>
-void chain_c(const ChainView& v, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s) {
+void chain_c(const ChainView& v, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s,
+             const Hop1Gersh* f = nullptr) {
     float alpha_sum = 0.f;
     const int kmax = spec_kmax(spec, &alpha_sum);
     bool b0;
@@ -1147,7 +1382,16 @@ void chain_c(const ChainView& v, const ahr_filter_spec& spec, const float* in, f
         h.n_rows = h.last ? v.n_inst : v.n_tot;
         h.n_chunk_blocks = h.last ? v.n_chunks_inst : v.n_chunks;
         h.n_rb = h.last ? v.n_rb_inst : v.n_rb;
-        hop_dispatch<CT>(h, lanes, h.last ? v.n_long_inst : v.n_long, hop_bytes(v, h, C), C / CT, s);
+        if (f && j == 1) {
+            if constexpr (CT == C && C <= 4) {
+                ProfScope ps(kStageNorm, s);
+                hop1_gersh<C>(v, h, *f, s);
+            } else {
+                throw Error{AHR_EINVAL, "first-hop bound needs one column tile of at most 4 columns"};
+            }
+        } else {
+            hop_dispatch<CT>(h, lanes, h.last ? v.n_long_inst : v.n_long, hop_bytes(v, h, C), C / CT, s);
+        }
         has_acc = has_acc || isb;
         float* t = zin;
         zin = zout;
@@ -1172,7 +1416,8 @@ void chain_tiles(const ChainView& v, const ahr_filter_spec& spec, const float* i
 }
 
 template <int C>
-void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s) {
+void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int lanes, hipStream_t s,
+              bool hop1_bound = false) {
     const int64_t N = g.n_tot;
     float alpha_sum = 0.f;
     const int kmax = spec_kmax(spec, &alpha_sum);
@@ -1189,7 +1434,12 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
     bool b0;
     float a0 = alpha_at(spec, 0, b0);
     expand_signal<C>(g, in, b0, a0, s);
-    chain_c<C, C>(chain_view(g, spec), spec, in, out, lanes, s);
+    if (hop1_bound) {
+        const Hop1Gersh f{g.deg.p, g.gmax.p, g.lam.p, g.coef.p};
+        chain_c<C, C>(chain_view(g, spec), spec, in, out, lanes, s, &f);
+    } else {
+        chain_c<C, C>(chain_view(g, spec), spec, in, out, lanes, s);
+    }
 }
 
 template <int C>
@@ -1364,11 +1614,22 @@ int32_t spec_kmax(const ahr_filter_spec& spec, float* alpha_sum) {
     return kmax;
 }
 
-void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
-    if (g.norm_version == g.hint_version && g.norm_sigma == spec.sigma && g.norm_mode == spec.lambda_mode &&
-        g.norm_fixed == spec.lambda_fixed)
-        return;
-    ProfScope ps(kStageNorm, s);
+namespace {
+
+bool norm_current(const Graph& g, const ahr_filter_spec& spec) {
+    return g.norm_version == g.hint_version && g.norm_sigma == spec.sigma && g.norm_mode == spec.lambda_mode &&
+           g.norm_fixed == spec.lambda_fixed;
+}
+
+void norm_done(Graph& g, const ahr_filter_spec& spec) {
+    g.norm_version = g.hint_version;
+    g.norm_sigma = spec.sigma;
+    g.norm_mode = spec.lambda_mode;
+    g.norm_fixed = spec.lambda_fixed;
+}
+
+// Row classes, degrees, scales and hint sums of the operator.
+void normalise_degrees(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     const int32_t N = g.n_tot;
     RowRef m{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
 
@@ -1382,6 +1643,7 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     g.scale.ensure(static_cast<size_t>(N) + 1, s);
     g.hsum.ensure(static_cast<size_t>(N) + 1, s);
     g.lam.ensure(1, s);
+    g.coef.ensure(static_cast<size_t>(N) + 1, s);
     constexpr int G = 4;
     // cell rows from the hint build's sums when it formed them for this
     // hint version, then the other rows from their entries
@@ -1404,6 +1666,18 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
                            g.rc.long_chunk0.p, g.rc.partial.p, g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
         AHR_LAUNCHED("k_long_deg_final");
     }
+}
+
+}  // namespace
+
+void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
+    if (norm_current(g, spec)) return;
+    ProfScope ps(kStageNorm, s);
+    const int32_t N = g.n_tot;
+    RowRef m{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
+    normalise_degrees(g, spec, s);
+    const double sigma = spec.sigma;
+    constexpr int G = 4;
     if (spec.lambda_mode == AHR_LAMBDA_FIXED) {
         hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, s, g.lam.p, static_cast<double>(spec.lambda_fixed));
         AHR_LAUNCHED("k_set_f64");
@@ -1422,28 +1696,38 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
             AHR_LAUNCHED("k_long_gersh_final");
         }
     }
-    g.coef.ensure(static_cast<size_t>(N) + 1, s);
     hop_coefs(N, g.scale.p, g.lam.p, sigma, g.coef.p, s);
-    g.norm_version = g.hint_version;
-    g.norm_sigma = spec.sigma;
-    g.norm_mode = spec.lambda_mode;
-    g.norm_fixed = spec.lambda_fixed;
+    norm_done(g, spec);
 }
 
 int g_hop_lanes = 4;   // lanes per short row (set by the tuner)
 int g_hop_nt = 0;      // non-temporal entry loads
 
 void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int32_t ncols, hipStream_t s) {
-    normalise(g, spec, s);
     int lanes = g_hop_lanes;
+    // a first filter on new hints with the Gershgorin bound forms the bound
+    // in its first hop (4-lane form, at most 4 columns, order >= 2)
+    const bool hop1_bound = !norm_current(g, spec) && spec.lambda_mode != AHR_LAMBDA_FIXED && lanes == 4 &&
+                            ncols <= 4 && spec_kmax(spec, nullptr) >= 2;
+    if (hop1_bound) {
+        {
+            ProfScope ps(kStageNorm, s);
+            normalise_degrees(g, spec, s);
+        }
+        const int64_t tiles = (grid_for(static_cast<int64_t>(g.n_tot) * 4, kBT) + kXcds - 1) / kXcds * kXcds;
+        g.gmax.ensure(static_cast<size_t>(tiles + g.rc.n_long) + 1, s);
+    } else {
+        normalise(g, spec, s);
+    }
     if (lanes == AHR_HOP_ROW_BLOCK) row_blocks(g.xnet_rp.p, g.xhint_rp.p, g.n_tot, g.n_inst, g.rc, g.scan_tmp, s);
     switch (ncols) {
-        case 1: filter_c<1>(g, spec, in, out, lanes, s); break;
-        case 2: filter_c<2>(g, spec, in, out, lanes, s); break;
-        case 4: filter_c<4>(g, spec, in, out, lanes, s); break;
-        case 8: filter_c<8>(g, spec, in, out, lanes, s); break;
+        case 1: filter_c<1>(g, spec, in, out, lanes, s, hop1_bound); break;
+        case 2: filter_c<2>(g, spec, in, out, lanes, s, hop1_bound); break;
+        case 4: filter_c<4>(g, spec, in, out, lanes, s, hop1_bound); break;
+        case 8: filter_c<8>(g, spec, in, out, lanes, s, false); break;
         default: throw Error{AHR_EUNSUPPORTED, "ncols must be 1, 2, 4 or 8"};
     }
+    if (hop1_bound) norm_done(g, spec);
 }
 
 void run_hops(Graph& g, const ahr_filter_spec& spec, const float* in, int32_t ncols, hipStream_t s) {

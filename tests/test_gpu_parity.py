@@ -181,3 +181,32 @@ def test_refine_round_by_round(case):
         cur = nxt
     full = gr.refine(cs, gpos, 3, gamma).cpu().numpy()
     assert np.array_equal(full.view(np.uint32), cur.cpu().numpy().view(np.uint32))
+
+
+@pytest.mark.parametrize("name", ["small-4col", "long-rows"])
+def test_first_hop_bound_same_bits(name):
+    """The first filter on new hints forms lambda_up inside its first hop;
+    a second filter on the same graph uses the bound already formed by it
+    and the plain first hop.  Both outputs and lambda_up must agree bit for
+    bit, and match the oracle."""
+    cfg, p = {c[0]: (c[1], c[2]) for c in CASES}[name]
+    nl = N.generate(cfg)
+    p = U.params32(p)
+    spec = U.spec32(O.FilterSpec(ks=(2, 4, 8), alphas=(0.2, 0.3, 0.5)))
+    cs = U.to_c_spec(A, spec)
+    saved = A.filter_get_tune()
+    A.filter_tune(4, -1)
+    net, gr, gpos = device_setup(nl, p)
+    try:
+        y1 = gr.filter(cs, gpos).clone()
+        lam1 = gr.export()["lambda_up"]
+        y2 = gr.filter(cs, gpos)
+        lam2 = gr.export()["lambda_up"]
+        assert lam1 == lam2
+        assert torch.equal(y1, y2)
+        og = O.build_graph(nl, p, nl["g0"][:, :2])
+        ref = O.apply_filter(nl, og, spec, nl["g0"])
+        assert U.rel_err(y1.cpu().numpy(), ref, U.movable_rows(nl)) <= FILTER_TOL
+    finally:
+        gr.close()
+        A.filter_tune(*saved)
