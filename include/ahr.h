@@ -372,8 +372,9 @@ typedef struct ahr_profile {
     int64_t mlp_calls;
 } ahr_profile;
 
-/* Turn event timing on (1) or off (0) for subsequent calls.  Adds two event
- * records per stage and per hop launch. */
+/* Event timing for subsequent calls: 0 off, 1 every stage and hop launch
+ * (two event records each), 2 hop launches only (the least added work, for
+ * timing the hop inside a timed run).  AHR_EINVAL for other values. */
 ahr_status ahr_profile_enable(int32_t on);
 
 /* Wait for the recorded events and return the accumulated times; reset = 1

@@ -170,9 +170,10 @@ def filter_get_tune() -> tuple:
     return a.value, b.value
 
 
-def profile_enable(on: bool = True):
-    """Time every stage and hop launch with HIP events on its stream."""
-    _check(load().ahr_profile_enable(1 if on else 0))
+def profile_enable(on=True, hops_only=False):
+    """Time every stage and hop launch with HIP events on its stream (with
+    hops_only, the hop launches alone)."""
+    _check(load().ahr_profile_enable((2 if hops_only else 1) if on else 0))
 
 
 def profile_read(reset: bool = True) -> dict:

@@ -16,7 +16,7 @@ struct Pending {
 };
 
 std::mutex g_mu;
-bool g_on = false;
+int g_on = 0;       // 0 off, 1 every stage, 2 hop launches only
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_free;
 double g_ms[kStageCount] = {};
@@ -52,12 +52,12 @@ void drain_locked() {
 
 thread_local bool t_capture = false;
 
-bool profiling() { return g_on && !t_capture; }
+bool profiling() { return g_on != 0 && !t_capture; }
 
 void set_capture(bool on) { t_capture = on; }
 
 ProfScope::ProfScope(Stage st, hipStream_t s, double bytes) : stage_(st), s_(s), bytes_(bytes) {
-    if (!g_on || t_capture) return;
+    if (!g_on || t_capture || (g_on == 2 && st != kStageHop)) return;
     std::lock_guard<std::mutex> lk(g_mu);
     a_ = take_event();
     AHR_HIP(hipEventRecord(static_cast<hipEvent_t>(a_), s));
@@ -82,7 +82,8 @@ extern "C" {
 
 ahr_status ahr_profile_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(ahr::g_mu);
-    ahr::g_on = on != 0;
+    if (on < 0 || on > 2) return ahr::fail(AHR_EINVAL, "on must be 0, 1 or 2");
+    ahr::g_on = on;
     return AHR_OK;
 }
 

@@ -73,3 +73,16 @@ def test_profile_read_fills_every_field():
     for name, _ in A._Profile._fields_:
         assert getattr(p, name) == 0, name
     assert lib.ahr_profile_read(None, 1) == A.EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libahr.so not built")
+def test_profile_levels():
+    """Profiling accepts 0 (off), 1 (every stage) and 2 (hop launches only),
+    and rejects other values."""
+    import paper_2511_10073_amd as A
+    lib = A.load()
+    for on in (1, 2, 0):
+        assert lib.ahr_profile_enable(on) == A.OK
+    for on in (-1, 3):
+        assert lib.ahr_profile_enable(on) == A.EINVAL
+    assert lib.ahr_profile_enable(0) == A.OK
