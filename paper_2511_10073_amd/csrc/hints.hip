@@ -65,13 +65,15 @@ __device__ __forceinline__ float w_macro(float x, float y, float4 m, double bw_i
 // baseWeight; the per-round kernels then read them in row order.
 constexpr int64_t kCellOther = 0, kCellStd = 1, kCellHint = 2;
 
-__global__ void k_exec_cells(int32_t n_inst, const int32_t* __restrict__ perm, const uint8_t* __restrict__ flags,
+// One thread per instance, in instance order (coalesced reads), storing to
+// its execution row (two scattered stores instead of four scattered loads).
+__global__ void k_exec_cells(int32_t n_inst, const int32_t* __restrict__ iperm, const uint8_t* __restrict__ flags,
                              const float* __restrict__ size, const int64_t* __restrict__ qdeg,
                              const double* __restrict__ base_w, int64_t* __restrict__ xcell,
                              double* __restrict__ xbase_w) {
-    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n_inst) return;
-    const int i = perm[r];
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    const int r = iperm[i];
     int64_t c = kCellOther;
     if (is_std_movable(flags[i])) {
         double a = static_cast<double>(size[2 * i]) * static_cast<double>(size[2 * i + 1]);
@@ -604,7 +606,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     if (!g.has_xcell) {
         g.xcell.ensure(static_cast<size_t>(n_inst) + 1, s);
         g.xbase_w.ensure(static_cast<size_t>(n_inst) + 1, s);
-        hipLaunchKernelGGL(k_exec_cells, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.perm.p,
+        hipLaunchKernelGGL(k_exec_cells, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.iperm.p,
                            g.nl.node_flags, g.nl.node_size, g.qdeg.p, g.base_w.p, g.xcell.p, g.xbase_w.p);
         AHR_LAUNCHED("k_exec_cells");
         g.has_xcell = 1;
