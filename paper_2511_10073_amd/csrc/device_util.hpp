@@ -9,6 +9,12 @@ namespace ahr {
 
 constexpr int kWave = 64;
 
+// A pointer into device global memory (address space 1).  Loads through it
+// are global loads even where the address was formed as an integer, which
+// would otherwise give flat loads that also count against the LDS counter.
+template <class T>
+using GlobalPtr = const __attribute__((address_space(1))) T*;
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
 

@@ -360,14 +360,18 @@ __global__ void k_set_f64(double* p, double v) { *p = v; }
 
 // ---------------------------------------------------------------- signal
 
+// Every load unconditional and the macro-pin offset selected, so that
+// callers can have several pins in flight.
 template <int C>
 __device__ __forceinline__ Vec<C> pin_value(const ExpandArgs& a, int p) {
     int v = a.pin_node[p];
     Vec<C> x = vload<C>(a.in + static_cast<int64_t>(v) * C);
-    if (a.pin_node_x[p] >= a.n_inst) {
-        float dx = a.pin_off[2 * p], dy = a.pin_off[2 * p + 1];
+    const bool mp = a.pin_node_x[p] >= a.n_inst;
+    const float dx = a.pin_off[2 * p], dy = a.pin_off[2 * p + 1];
 #pragma unroll
-        for (int c = 0; c < C; ++c) x.v[c] += (c & 1) ? dy : dx;
+    for (int c = 0; c < C; ++c) {
+        const float t = x.v[c] + ((c & 1) ? dy : dx);
+        x.v[c] = mp ? t : x.v[c];
     }
     return x;
 }
@@ -450,8 +454,7 @@ __device__ __forceinline__ void expand_star(const ExpandArgs& a, int k) {
     for (int p = p0 + l; p < p1; p += B * G) {
         Vec<C> v[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u)
-            if (p + u * G < p1) v[u] = pin_value<C>(a, p + u * G);
+        for (int u = 0; u < B; ++u) v[u] = pin_value<C>(a, p + u * G < p1 ? p + u * G : p1 - 1);   // clamped
 #pragma unroll
         for (int u = 0; u < B; ++u)
             if (p + u * G < p1) {
@@ -485,8 +488,7 @@ __device__ __forceinline__ void expand_big_star(const ExpandArgs& a, int k) {
     for (int p = p0 + static_cast<int>(threadIdx.x); p < p1; p += B * kBT) {
         Vec<C> v[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u)
-            if (p + u * kBT < p1) v[u] = pin_value<C>(a, p + u * kBT);
+        for (int u = 0; u < B; ++u) v[u] = pin_value<C>(a, p + u * kBT < p1 ? p + u * kBT : p1 - 1);   // clamped
 #pragma unroll
         for (int u = 0; u < B; ++u)
             if (p + u * kBT < p1) {
@@ -834,19 +836,30 @@ __device__ __forceinline__ void hop_row_block(const HopArgs& a, int blk) {
     const int net_lo = d0.z, en = d0.w - d0.z;
     const int hint_lo = d1.x, e = en + (d1.y - d1.x);
     const int t = threadIdx.x;
+    // Every load unconditional, so that all are in flight together (a load
+    // under a branch is waited for where the branch joins): loads past the
+    // block's end read its last entry, and an empty block reads the first
+    // netlist entry (both entry arrays hold one more than their count) and
+    // then uses column 0.  The address is picked with masks, not a select the
+    // compiler may turn into a branch.
     int2 ent[kRbUnroll];
+    const int elast = e > 0 ? e - 1 : 0;
+    const uint64_t live = e > 0 ? ~0ull : 0ull;
+    const uint64_t nbase = reinterpret_cast<uint64_t>(a.m.net_ent) + static_cast<uint64_t>(net_lo) * sizeof(int2);
+    const uint64_t hbase = reinterpret_cast<uint64_t>(a.m.hint_ent) +
+                           (static_cast<uint64_t>(hint_lo) - static_cast<uint64_t>(en)) * sizeof(int2);
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-        const int k = t + u * kBT;
-        if (k < e) {
-            const int2* p = k < en ? a.m.net_ent + net_lo + k : a.m.hint_ent + hint_lo + (k - en);
-            if constexpr (NT) {
-                long long v = __builtin_nontemporal_load(reinterpret_cast<const long long*>(p));
-                ent[u] = make_int2(static_cast<int>(v & 0xffffffffll), static_cast<int>(v >> 32));
-            } else {
-                ent[u] = *p;
-            }
-        }
+        const int k = t + u * kBT < e ? t + u * kBT : elast;
+        const uint64_t onnet = (k < en ? ~0ull : 0ull) | ~live;
+        const uint64_t at = ((nbase + static_cast<uint64_t>(k) * sizeof(int2)) & onnet & live) |
+                            (reinterpret_cast<uint64_t>(a.m.net_ent) & ~live) |
+                            ((hbase + static_cast<uint64_t>(k) * sizeof(int2)) & ~onnet);
+        const GlobalPtr<long long> p = reinterpret_cast<GlobalPtr<long long>>(at);
+        long long v;
+        if constexpr (NT) v = __builtin_nontemporal_load(p);
+        else v = *p;
+        ent[u] = make_int2(static_cast<int>(v & 0xffffffffll) & static_cast<int>(live), static_cast<int>(v >> 32));
     }
     RowOps<C> ops;
     if (t < nr) ops = row_ops<C>(a, r0 + t);
@@ -860,8 +873,7 @@ __device__ __forceinline__ void hop_row_block(const HopArgs& a, int blk) {
     }
     Vec<C> v[kRbUnroll];
 #pragma unroll
-    for (int u = 0; u < kRbUnroll; ++u)
-        if (t + u * kBT < e) v[u] = vload<C>(a.zin + static_cast<int64_t>(ent[u].x) * C);
+    for (int u = 0; u < kRbUnroll; ++u) v[u] = vload<C>(a.zin + static_cast<int64_t>(ent[u].x) * C);
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
         const int k = t + u * kBT;
