@@ -236,6 +236,7 @@ struct Graph {
 
     // filter work buffers
     DevBuf<float> z0, z1, acc;    // [n_tot * C]
+    DevBuf<float> zpk;            // first-hop records [n_tot][2, 4 or 8]: z, then the row scale
     DevBuf<float> zh[3];          // [n_tot * C] hops 1..3 of the learned path (scaled coordinates)
     DevBuf<float> ga, gb, gt;     // [n_inst * C] refinement rounds
 
@@ -308,6 +309,7 @@ struct ExpandArgs {
     const int32_t* perm;      // execution row -> instance
     const float* scale;
     float* z0;
+    float* zpk;               // or, when set, first-hop records: z then the row scale (replaces z0)
     float* acc;               // band at k = 0
     float alpha0;
     int32_t band0;

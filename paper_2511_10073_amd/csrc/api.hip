@@ -46,6 +46,7 @@ Graph::~Graph() {
     coef.release(s);
     rc.release(s);
     z0.release(s);
+    zpk.release(s);
     z1.release(s);
     acc.release(s);
     ga.release(s);

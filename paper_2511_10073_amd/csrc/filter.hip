@@ -71,6 +71,14 @@ __device__ __forceinline__ void vstore(float* p, const Vec<C>& r) {
     }
 }
 
+// A first-hop record: a row's C signal columns, then its scale, padded to a
+// power of two so that a record never straddles a cache line.
+template <int C>
+constexpr int pack_width() {
+    static_assert(C <= 4, "first-hop records hold at most 4 columns");
+    return C == 1 ? 2 : (C == 2 ? 4 : 8);
+}
+
 // ---------------------------------------------------------------- row classes
 
 __global__ void k_row_len(int32_t n, const int32_t* __restrict__ net_rp, const int32_t* __restrict__ hint_rp,
@@ -386,6 +394,17 @@ __device__ __forceinline__ void put_z(const ExpandArgs& a, int r, Vec<C> x) {
     for (int c = 0; c < C; ++c) {
         z.v[c] = s * x.v[c];
         t.v[c] = z.v[c] * a.alpha0;
+    }
+    if constexpr (C <= 4) {
+        if (a.zpk) {
+            constexpr int W = pack_width<C>();
+            Vec<W> rec;
+#pragma unroll
+            for (int c = 0; c < W; ++c) rec.v[c] = c < C ? z.v[c] : (c == C ? s : 0.f);
+            vstore<W>(a.zpk + row * W, rec);
+            if (a.band0) vstore<C>(a.acc + row * C, t);
+            return;
+        }
     }
     if (a.ct == C) {
         vstore<C>(a.z0 + row * C, z);
@@ -920,15 +939,32 @@ __global__ void __launch_bounds__(kBT) k_hop_rb(HopArgs a0) {
 //
 // When lambda_up is the Gershgorin bound and not yet known, the first hop
 // also forms every row's Gershgorin sum sum_j |A_ij| s_j while it streams
-// the entries (gathering s_j beside z_j), so the bound costs no pass of its
-// own.  The hop's epilogue needs lambda_up, so the rows' neighbour sums are
+// the entries, so the bound costs no pass of its own.  The expansion writes
+// each row's z and s side by side in one record, so that one cache line
+// serves both gathers.  The hop's epilogue needs lambda_up, so the rows' neighbour sums are
 // stored unscaled in zout and the epilogue runs after the bound is reduced
 // (k_hop1_epi).  Entry order, clamping and sums are those of k_hop and of
 // k_gersh_short / k_chunk_gersh, so the results are the same bits.
 
+// z_j and s_j of a first-hop record (one cache line).
+template <int C>
+__device__ __forceinline__ void load_record(const float* zpk, int j, Vec<C>& z, float& sc) {
+    constexpr int W = pack_width<C>();
+    const float* rec = zpk + static_cast<int64_t>(j) * W;
+    if constexpr (W <= 4) {
+        const Vec<W> r = vload<W>(rec);
+#pragma unroll
+        for (int c = 0; c < C; ++c) z.v[c] = r.v[c];
+        sc = r.v[C];
+    } else {
+        z = vload<C>(rec);
+        sc = rec[C];
+    }
+}
+
 template <int C, int U>
-__device__ __forceinline__ void gather_batch_gersh(const HopArgs& a, int n0, int ln, int h0, int len, int k0, int step,
-                                                   float* acc, double& ag) {
+__device__ __forceinline__ void gather_batch_gersh(const HopArgs& a, const float* zpk, int n0, int ln, int h0, int len,
+                                                   int k0, int step, float* acc, double& ag) {
     int2 e[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -940,10 +976,7 @@ __device__ __forceinline__ void gather_batch_gersh(const HopArgs& a, int n0, int
     Vec<C> v[U];
     float sc[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        v[u] = vload<C>(a.zin + static_cast<int64_t>(e[u].x) * C);
-        sc[u] = a.scale[e[u].x];
-    }
+    for (int u = 0; u < U; ++u) load_record<C>(zpk, e[u].x, v[u], sc[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         float w = bits_f(e[u].y);
@@ -956,7 +989,7 @@ __device__ __forceinline__ void gather_batch_gersh(const HopArgs& a, int n0, int
 // One chunk of a long row: float64 partials of the C neighbour sums at
 // partial[chunk * 8 + c] and of the Gershgorin sum at partial[chunk * 8 + C].
 template <int C>
-__device__ __forceinline__ void hop1_chunk(const HopArgs& a) {
+__device__ __forceinline__ void hop1_chunk(const HopArgs& a, const float* zpk) {
     __shared__ double red[kBT / kWave];
     int r, li, k0, k1, n0, ln, h0;
     chunk_range(blockIdx.x, a.long_rows, a.chunk_row, a.chunk0, a.m, r, li, k0, k1, n0, ln, h0);
@@ -977,10 +1010,7 @@ __device__ __forceinline__ void hop1_chunk(const HopArgs& a) {
         Vec<C> v[U];
         float sc[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            v[u] = vload<C>(a.zin + static_cast<int64_t>(e[u].x) * C);
-            sc[u] = a.scale[e[u].x];
-        }
+        for (int u = 0; u < U; ++u) load_record<C>(zpk, e[u].x, v[u], sc[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             double w = static_cast<double>(bits_f(e[u].y));
@@ -1004,11 +1034,11 @@ __device__ __forceinline__ void hop1_chunk(const HopArgs& a) {
 // as in k_hop); every thread reaches the workgroup's maximum, which goes to
 // wgmax[tile].
 template <int C, int G, int U>
-__global__ void __launch_bounds__(kBT) k_hop1_gersh(HopArgs a, const double* __restrict__ deg,
-                                                    double* __restrict__ wgmax) {
+__global__ void __launch_bounds__(kBT) k_hop1_gersh(HopArgs a, const float* __restrict__ zpk,
+                                                    const double* __restrict__ deg, double* __restrict__ wgmax) {
     __shared__ double red[kBT / kWave];
     if (static_cast<int>(blockIdx.x) < a.n_chunk_blocks) {
-        hop1_chunk<C>(a);
+        hop1_chunk<C>(a, zpk);
         return;
     }
     const int64_t nb = static_cast<int64_t>(gridDim.x) - a.n_chunk_blocks;     // a multiple of kXcds
@@ -1030,7 +1060,7 @@ __global__ void __launch_bounds__(kBT) k_hop1_gersh(HopArgs a, const double* __r
     for (int c = 0; c < C; ++c) acc[c] = 0.f;
     double ag = 0;
     if (valid)
-        for (int k0 = l; k0 < len; k0 += G * U) gather_batch_gersh<C, U>(a, n0, ln, h0, len, k0, G, acc, ag);
+        for (int k0 = l; k0 < len; k0 += G * U) gather_batch_gersh<C, U>(a, zpk, n0, ln, h0, len, k0, G, acc, ag);
     Vec<C> sum;
 #pragma unroll
     for (int c = 0; c < C; ++c) sum.v[c] = acc[c];
@@ -1109,13 +1139,19 @@ __global__ void __launch_bounds__(1024) k_lam_reduce(const double* __restrict__ 
 }
 
 // The first hop's epilogue once lambda_up and the coefficients are known:
-// zout holds the rows' unscaled neighbour sums.
+// zout holds the rows' unscaled neighbour sums, the records the rows' z.
 template <int C>
-__global__ void __launch_bounds__(kBT) k_hop1_epi(HopArgs a) {
+__global__ void __launch_bounds__(kBT) k_hop1_epi(HopArgs a, const float* __restrict__ zpk) {
     const int64_t r64 = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
     if (r64 >= a.n_rows) return;
     const int r = static_cast<int>(r64);
-    const RowOps<C> ops = row_ops<C>(a, r);
+    RowOps<C> ops;
+    ops.s = a.scale[r];
+    if (a.coef) ops.k = a.coef[r];
+    ops.z = vload<C>(zpk + static_cast<int64_t>(r) * pack_width<C>());
+    if (a.band == 2) ops.acc = vload<C>(a.acc + static_cast<int64_t>(r) * C);
+    ops.inst = r;          // never the last hop
+    ops.flag = 0;
     const Vec<C> sum = vload<C>(a.zout + static_cast<int64_t>(r) * C);
     epilogue<C>(a, r, ops, sum);
 }
@@ -1202,10 +1238,11 @@ void hop_dispatch(const HopArgs& a, int lanes, int32_t n_long_rows, double bytes
 }
 
 template <int C>
-void expand_signal(Graph& g, const float* in, bool band0, float alpha0, hipStream_t s) {
+void expand_signal(Graph& g, const float* in, bool band0, float alpha0, hipStream_t s, float* zpk = nullptr) {
     ExpandArgs e = expand_args(g);
     e.in = in;
     e.z0 = g.z0.p;
+    e.zpk = zpk;
     e.acc = g.acc.p;
     e.alpha0 = alpha0;
     e.band0 = band0 ? 1 : 0;
@@ -1341,6 +1378,7 @@ float alpha_at(const ahr_filter_spec& spec, int j, bool& is_band) {
 
 // What the first hop needs to form lambda_up itself (k_hop1_gersh).
 struct Hop1Gersh {
+    const float* zpk;   // the expanded signal as first-hop records
     const double* deg;
     double* gmax;       // one slot per short-row workgroup, then one per long row
     double* lam;
@@ -1354,7 +1392,7 @@ void hop1_gersh(const ChainView& v, HopArgs h, const Hop1Gersh& f, hipStream_t s
     int64_t tiles = grid_for(static_cast<int64_t>(h.n_rows) * G, kBT);
     tiles = (tiles + kXcds - 1) / kXcds * kXcds;                    // see xcd_tile
     hipLaunchKernelGGL((k_hop1_gersh<C, G, U>), dim3(static_cast<unsigned>(h.n_chunk_blocks + tiles)), dim3(kBT), 0,
-                       s, h, f.deg, f.gmax);
+                       s, h, f.zpk, f.deg, f.gmax);
     AHR_LAUNCHED("k_hop1_gersh");
     if (v.n_long > 0) {
         hipLaunchKernelGGL(k_hop1_long<C>, dim3(grid_for(static_cast<int64_t>(v.n_long) * kWave, kBT)), dim3(kBT), 0, s,
@@ -1364,7 +1402,7 @@ void hop1_gersh(const ChainView& v, HopArgs h, const Hop1Gersh& f, hipStream_t s
     hipLaunchKernelGGL(k_lam_reduce, dim3(1), dim3(1024), 0, s, f.gmax, tiles, f.gmax + tiles, v.n_long, f.lam);
     AHR_LAUNCHED("k_lam_reduce");
     hop_coefs(v.n_tot, v.scale, f.lam, v.sigma, f.coef, s);
-    hipLaunchKernelGGL(k_hop1_epi<C>, dim3(grid_for(h.n_rows, kBT)), dim3(kBT), 0, s, h);
+    hipLaunchKernelGGL(k_hop1_epi<C>, dim3(grid_for(h.n_rows, kBT)), dim3(kBT), 0, s, h, f.zpk);
     AHR_LAUNCHED("k_hop1_epi");
 }
 
@@ -1445,11 +1483,15 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
     g.acc.ensure(static_cast<size_t>(N) * C, s);
     bool b0;
     float a0 = alpha_at(spec, 0, b0);
-    expand_signal<C>(g, in, b0, a0, s);
     if (hop1_bound) {
-        const Hop1Gersh f{g.deg.p, g.gmax.p, g.lam.p, g.coef.p};
+        if constexpr (C <= 4) {
+            g.zpk.ensure(static_cast<size_t>(N) * pack_width<C>(), s);
+            expand_signal<C>(g, in, b0, a0, s, g.zpk.p);
+        }
+        const Hop1Gersh f{g.zpk.p, g.deg.p, g.gmax.p, g.lam.p, g.coef.p};
         chain_c<C, C>(chain_view(g, spec), spec, in, out, lanes, s, &f);
     } else {
+        expand_signal<C>(g, in, b0, a0, s);
         chain_c<C, C>(chain_view(g, spec), spec, in, out, lanes, s);
     }
 }
@@ -1563,6 +1605,7 @@ ExpandArgs expand_args(const Graph& g) {
     e.perm = g.perm.p;
     e.scale = g.scale.p;
     e.z0 = nullptr;
+    e.zpk = nullptr;
     e.acc = nullptr;
     e.alpha0 = 0.f;
     e.band0 = 0;
