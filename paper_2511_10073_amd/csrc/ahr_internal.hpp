@@ -207,9 +207,10 @@ struct Graph {
     DevBuf<double> gmax;          // first-hop Gershgorin maxima (per workgroup, then per long row)
     int32_t has_xcell = 0;
 
-    // execution layout: instance rows in spatial order (perm: exec -> id)
+    // execution layout: instance, macro pin and star rows each in spatial
+    // order inside their id range (perm: exec -> id); virtual rows unmoved
     int32_t has_layout = 0;
-    DevBuf<int32_t> perm, iperm;  // [n_inst]
+    DevBuf<int32_t> perm, iperm;  // [first_mvirt]
     DevBuf<int32_t> xnet_rp;      // [n_tot+1]
     DevBuf<int2> xnet_ent;        // [nnz_net]
     DevBuf<int64_t> xqdeg;        // [n_tot]
@@ -257,8 +258,8 @@ void build_netlist(Graph& g, hipStream_t s);
 // the count when read_total (one synchronisation), else -1.
 int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
                     DevBuf<int32_t>& start, hipStream_t s, bool read_total = true);
-// layout.hip: the execution order of instance rows (spatial) and the
-// permuted copy of the netlist rows the filter streams
+// layout.hip: the execution order of the instance, macro pin and star rows
+// (spatial) and the permuted copy of the netlist rows the filter streams
 void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
 // hints.hip
 void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
@@ -306,7 +307,8 @@ __host__ __device__ inline void hop_coef(float s, double lam, double sigma, floa
 struct ExpandArgs {
     const float* in;          // [n_inst][C], instance order (in_base + in_off in batched launches)
     int64_t in_off;
-    const int32_t* perm;      // execution row -> instance
+    const int32_t* perm;      // execution row -> node (instances, macro pins, stars)
+    const int32_t* iperm;     // node -> execution row (instances, macro pins, stars)
     const float* scale;
     float* z0;
     float* zpk;               // or, when set, first-hop records: z then the row scale (replaces z0)

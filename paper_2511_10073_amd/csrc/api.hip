@@ -210,28 +210,28 @@ ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* strea
         cp(dst->net_q, g->net_q.p, g->nnz_net * sizeof(int64_t));
         if (g->has_hints && (dst->hint_row_ptr || dst->hint_col || dst->hint_val)) {
             // hint rows live in execution order: return them in node order
-            std::vector<int32_t> xrp(N + 1), perm(g->n_inst);
+            const size_t np = static_cast<size_t>(g->first_mvirt);     // rows the layout permutes
+            std::vector<int32_t> xrp(N + 1), perm(np);
             std::vector<int2> ent(g->nnz_hint);
             AHR_HIP(hipMemcpyAsync(xrp.data(), g->xhint_rp.p, (N + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            AHR_HIP(hipMemcpyAsync(perm.data(), g->perm.p, g->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipMemcpyAsync(perm.data(), g->perm.p, np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             if (g->nnz_hint)
                 AHR_HIP(hipMemcpyAsync(ent.data(), g->xhint_ent.p, g->nnz_hint * sizeof(int2), hipMemcpyDeviceToHost, s));
             AHR_HIP(hipStreamSynchronize(s));
-            const size_t ni = static_cast<size_t>(g->n_inst);
-            std::vector<int32_t> iperm(ni);
-            for (size_t r = 0; r < ni; ++r) iperm[perm[r]] = static_cast<int32_t>(r);
+            std::vector<int32_t> iperm(np);
+            for (size_t r = 0; r < np; ++r) iperm[perm[r]] = static_cast<int32_t>(r);
             std::vector<int32_t> rp(N + 1, 0);
             for (size_t c = 0; c < N; ++c) {
-                size_t r = c < ni ? static_cast<size_t>(iperm[c]) : c;
+                size_t r = c < np ? static_cast<size_t>(iperm[c]) : c;
                 rp[c + 1] = rp[c] + (xrp[r + 1] - xrp[r]);
             }
             if (dst->hint_row_ptr) std::memcpy(dst->hint_row_ptr, rp.data(), (N + 1) * sizeof(int32_t));
             for (size_t c = 0; c < N; ++c) {
-                size_t r = c < ni ? static_cast<size_t>(iperm[c]) : c;
+                size_t r = c < np ? static_cast<size_t>(iperm[c]) : c;
                 for (int32_t k = xrp[r]; k < xrp[r + 1]; ++k) {
                     int32_t o = rp[c] + (k - xrp[r]);
                     int32_t col = ent[k].x;
-                    if (dst->hint_col) dst->hint_col[o] = col < g->n_inst ? perm[col] : col;
+                    if (dst->hint_col) dst->hint_col[o] = static_cast<size_t>(col) < np ? perm[col] : col;
                     if (dst->hint_val) std::memcpy(&dst->hint_val[o], &ent[k].y, sizeof(float));
                 }
             }
@@ -242,13 +242,14 @@ ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* strea
             // operator arrays live in execution order; return them in node order
             std::vector<double> d(N);
             std::vector<float> sc(N);
-            std::vector<int32_t> perm(g->n_inst);
+            const size_t np = static_cast<size_t>(g->first_mvirt);
+            std::vector<int32_t> perm(np);
             AHR_HIP(hipMemcpyAsync(d.data(), g->deg.p, N * sizeof(double), hipMemcpyDeviceToHost, s));
             AHR_HIP(hipMemcpyAsync(sc.data(), g->scale.p, N * sizeof(float), hipMemcpyDeviceToHost, s));
-            AHR_HIP(hipMemcpyAsync(perm.data(), g->perm.p, g->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipMemcpyAsync(perm.data(), g->perm.p, np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             AHR_HIP(hipStreamSynchronize(s));
             for (size_t r = 0; r < N; ++r) {
-                size_t c = r < static_cast<size_t>(g->n_inst) ? static_cast<size_t>(perm[r]) : r;
+                size_t c = r < np ? static_cast<size_t>(perm[r]) : r;
                 if (dst->degree) dst->degree[c] = d[r];
                 if (dst->scale) dst->scale[c] = sc[r];
             }

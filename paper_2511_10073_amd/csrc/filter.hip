@@ -428,10 +428,10 @@ __device__ __forceinline__ void expand_row(const ExpandArgs& a, int r) {
     if (r < a.n_inst) {
         x = vload<C>(a.in + static_cast<int64_t>(a.perm[r]) * C);
     } else if (r < a.first_star) {
-        int k = r - a.first_mpin;
+        int k = a.perm[r] - a.first_mpin;
         x = pin_value<C>(a, a.mpin_pin[k]);
     } else if (r < a.first_mvirt) {
-        int e = a.star_net[r - a.first_star];
+        int e = a.star_net[a.perm[r] - a.first_star];
         int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
         if (p1 - p0 > kStarInline) return;
         double acc[C];
@@ -489,7 +489,7 @@ __device__ __forceinline__ void expand_star(const ExpandArgs& a, int k) {
         for (int o = G / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
         x.v[c] = static_cast<float>(t / deg);
     }
-    if (l == 0) put_z<C>(a, a.first_star + k, x);
+    if (l == 0) put_z<C>(a, a.iperm[a.first_star + k], x);
 }
 
 // Mean over the pins of a big star (more than kStarMid pins): the whole
@@ -518,7 +518,7 @@ __device__ __forceinline__ void expand_big_star(const ExpandArgs& a, int k) {
     Vec<C> x;
 #pragma unroll
     for (int c = 0; c < C; ++c) x.v[c] = static_cast<float>(block_sum_f64<kBT>(acc[c], red) / (p1 - p0));
-    if (threadIdx.x == 0) put_z<C>(a, a.first_star + k, x);
+    if (threadIdx.x == 0) put_z<C>(a, a.iperm[a.first_star + k], x);
 }
 
 template <int C>
@@ -1603,6 +1603,7 @@ ExpandArgs expand_args(const Graph& g) {
     e.in = nullptr;
     e.in_off = 0;
     e.perm = g.perm.p;
+    e.iperm = g.iperm.p;
     e.scale = g.scale.p;
     e.z0 = nullptr;
     e.zpk = nullptr;

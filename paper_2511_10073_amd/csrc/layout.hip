@@ -3,8 +3,11 @@
 // touch a different cache line.  The filter therefore streams rows in an
 // execution order: instances sorted by a stable sort on the Hilbert-curve
 // index of their position on a 1024 x 1024 grid over the die, columns
-// renumbered to match; added nodes (macro pins, stars, virtual nodes) keep
-// their canonical ids.  Consecutive rows are then spatial neighbours, so the
+// renumbered to match.  The macro pin nodes and the star nodes stay in their
+// own id ranges but are ordered the same way inside them (a macro pin by its
+// pin position, a star by the position of its net's first pin), so that the
+// rows gathering a run of them, and their own rows, touch few cache lines;
+// the virtual nodes keep their canonical ids.  Consecutive rows are then spatial neighbours, so the
 // rows of one workgroup gather from few, shared cache lines, and every
 // aligned power-of-two block of the grid (a bin of a 2^k x 2^k bin grid) is
 // one contiguous range of rows.  Inside each aligned window of 64 rows (the
@@ -22,8 +25,9 @@ namespace ahr {
 namespace {
 
 constexpr int kBT = 256;
-constexpr int kGridBits = 10;    // 1024 x 1024 layout grid -> 20-bit keys
-constexpr int kDigitBits = 10;   // sorted as two stable 10-bit digit passes
+constexpr int kGridBits = 10;    // 1024 x 1024 layout grid -> 20-bit Hilbert keys
+constexpr int kKeyBits = 22;     // the node range (instance, macro pin, star) above them
+constexpr int kDigitBits = 11;   // sorted as two stable 11-bit digit passes
 
 // Hilbert-curve index of grid cell (x, y) on the 2^kGridBits square grid:
 // at each level the quadrant's position along the curve, then the cell's
@@ -46,16 +50,54 @@ __device__ __forceinline__ int hilbert_index(int x, int y) {
     return d;
 }
 
-__global__ void k_layout_keys(const float* __restrict__ pos, int ncols, int32_t n, float xl, float yl, float sx,
-                              float sy, int32_t* __restrict__ key, int32_t* __restrict__ lo) {
+struct KeyArgs {
+    const float* pos;            // instance positions, ncols per row
+    int ncols;
+    int32_t n_inst, first_star, first_mvirt;
+    const int32_t* mpin_pin;     // pin of each macro pin node
+    const int32_t* star_net;     // net of each star node
+    const int32_t* net_ptr;
+    const int32_t* pin_node;     // instance of each pin
+    const int32_t* pin_node_x;   // node of each pin (macro pins expanded)
+    const float* pin_off;
+    float xl, yl, sx, sy;
+};
+
+// Position of pin p: its instance's, plus the pin offset where the pin is
+// its own node.
+__device__ __forceinline__ float2 pin_pos(const KeyArgs& a, int p) {
+    const int v = a.pin_node[p];
+    float x = a.pos[static_cast<int64_t>(v) * a.ncols], y = a.pos[static_cast<int64_t>(v) * a.ncols + 1];
+    if (a.pin_node_x[p] >= a.n_inst) {
+        x += a.pin_off[2 * p];
+        y += a.pin_off[2 * p + 1];
+    }
+    return make_float2(x, y);
+}
+
+// Sort key of node i < first_mvirt: its range above the Hilbert index of
+// its position.
+__global__ void k_layout_keys(KeyArgs a, int32_t* __restrict__ key, int32_t* __restrict__ lo) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= a.first_mvirt) return;
+    float2 q;
+    int range;
+    if (i < a.n_inst) {
+        q = make_float2(a.pos[i * a.ncols], a.pos[i * a.ncols + 1]);
+        range = 0;
+    } else if (i < a.first_star) {
+        q = pin_pos(a, a.mpin_pin[i - a.n_inst]);
+        range = 1;
+    } else {
+        q = pin_pos(a, a.net_ptr[a.star_net[i - a.first_star]]);
+        range = 2;
+    }
     const int m = (1 << kGridBits) - 1;
-    float fx = floorf((pos[i * ncols] - xl) * sx);
-    float fy = floorf((pos[i * ncols + 1] - yl) * sy);
+    float fx = floorf((q.x - a.xl) * a.sx);
+    float fy = floorf((q.y - a.yl) * a.sy);
     int gx = !(fx > 0.f) ? 0 : (fx >= static_cast<float>(m) ? m : static_cast<int>(fx));
     int gy = !(fy > 0.f) ? 0 : (fy >= static_cast<float>(m) ? m : static_cast<int>(fy));
-    const int k = hilbert_index(gx, gy);
+    const int k = (range << (2 * kGridBits)) | hilbert_index(gx, gy);
     key[i] = k;
     lo[i] = k & ((1 << kDigitBits) - 1);
 }
@@ -106,14 +148,16 @@ __global__ void k_iperm(const int32_t* __restrict__ perm, int32_t n, int32_t* __
     if (r < n) iperm[perm[r]] = static_cast<int32_t>(r);
 }
 
-__device__ __forceinline__ int src_row(int r, int n_inst, const int32_t* perm) { return r < n_inst ? perm[r] : r; }
-__device__ __forceinline__ int map_col(int c, int n_inst, const int32_t* iperm) { return c < n_inst ? iperm[c] : c; }
+// The permutation covers the nodes below n_perm (instances, macro pins,
+// stars); the virtual nodes above keep their ids.
+__device__ __forceinline__ int src_row(int r, int n_perm, const int32_t* perm) { return r < n_perm ? perm[r] : r; }
+__device__ __forceinline__ int map_col(int c, int n_perm, const int32_t* iperm) { return c < n_perm ? iperm[c] : c; }
 
-__global__ void k_exec_lens(int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
+__global__ void k_exec_lens(int32_t n_tot, int32_t n_perm, const int32_t* __restrict__ perm,
                             const int32_t* __restrict__ rp, int32_t* __restrict__ len) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n_tot) return;
-    int s = src_row(static_cast<int>(r), n_inst, perm);
+    int s = src_row(static_cast<int>(r), n_perm, perm);
     len[r] = rp[s + 1] - rp[s];
 }
 
@@ -123,11 +167,11 @@ __global__ void k_exec_lens(int32_t n_tot, int32_t n_inst, const int32_t* __rest
 // row (k_exec_net_long).
 constexpr int kShortRow = 64;
 
-__device__ __forceinline__ int2 exec_entry(int32_t c, int64_t q, int n_inst, const int32_t* iperm) {
-    return make_int2(map_col(c, n_inst, iperm), f_bits(static_cast<float>(static_cast<double>(q) * 0x1p-32)));
+__device__ __forceinline__ int2 exec_entry(int32_t c, int64_t q, int n_perm, const int32_t* iperm) {
+    return make_int2(map_col(c, n_perm, iperm), f_bits(static_cast<float>(static_cast<double>(q) * 0x1p-32)));
 }
 
-__global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
+__global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_perm, const int32_t* __restrict__ perm,
                                                   const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, const int64_t* __restrict__ q,
                                                   const int32_t* __restrict__ xrp, int2* __restrict__ xent) {
@@ -137,8 +181,8 @@ __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_inst,
     if (r >= n_tot) return;
     int d = xrp[r], len = xrp[r + 1] - d;
     if (len > kShortRow) return;                           // group-uniform
-    int a = rp[src_row(static_cast<int>(r), n_inst, perm)];
-    for (int k = l; k < len; k += G) xent[d + k] = exec_entry(col[a + k], q[a + k], n_inst, iperm);
+    int a = rp[src_row(static_cast<int>(r), n_perm, perm)];
+    for (int k = l; k < len; k += G) xent[d + k] = exec_entry(col[a + k], q[a + k], n_perm, iperm);
 }
 
 // One workgroup per longer row; the workgroups stride over the list of
@@ -146,7 +190,7 @@ __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_inst,
 constexpr int kLongRowGrid = 512;
 
 __global__ void __launch_bounds__(kBT) k_exec_net_long(const int32_t* __restrict__ rows,
-                                                       const int32_t* __restrict__ n_long, int32_t n_inst,
+                                                       const int32_t* __restrict__ n_long, int32_t n_perm,
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ iperm,
                                                        const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -156,8 +200,8 @@ __global__ void __launch_bounds__(kBT) k_exec_net_long(const int32_t* __restrict
     for (int li = blockIdx.x; li < nl; li += gridDim.x) {
         const int r = rows[li];
         const int d = xrp[r], len = xrp[r + 1] - d;
-        const int a = rp[src_row(r, n_inst, perm)];
-        for (int k = threadIdx.x; k < len; k += kBT) xent[d + k] = exec_entry(col[a + k], q[a + k], n_inst, iperm);
+        const int a = rp[src_row(r, n_perm, perm)];
+        for (int k = threadIdx.x; k < len; k += kBT) xent[d + k] = exec_entry(col[a + k], q[a + k], n_perm, iperm);
     }
 }
 
@@ -166,48 +210,66 @@ __global__ void k_long_flags(int32_t n_tot, const int32_t* __restrict__ xrp, int
     if (r < n_tot) flag[r] = (xrp[r + 1] - xrp[r] > kShortRow) ? 1 : 0;
 }
 
-__global__ void k_exec_qdeg(int32_t n_tot, int32_t n_inst, const int32_t* __restrict__ perm,
+__global__ void k_exec_qdeg(int32_t n_tot, int32_t n_perm, const int32_t* __restrict__ perm,
                             const int64_t* __restrict__ qdeg, int64_t* __restrict__ xqdeg) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r < n_tot) xqdeg[r] = qdeg[src_row(static_cast<int>(r), n_inst, perm)];
+    if (r < n_tot) xqdeg[r] = qdeg[src_row(static_cast<int>(r), n_perm, perm)];
 }
 
 }  // namespace
 
 void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
-    const int32_t n = g.n_inst, N = g.n_tot;
+    const int32_t n = g.n_inst, N = g.n_tot, np = g.first_mvirt;
     DevBuf<int32_t> key, digit, first, second;
-    key.ensure(static_cast<size_t>(n) + 1, s);
-    digit.ensure(static_cast<size_t>(n) + 1, s);
+    key.ensure(static_cast<size_t>(np) + 1, s);
+    digit.ensure(static_cast<size_t>(np) + 1, s);
     const float side = static_cast<float>(1 << kGridBits);
-    float sx = side / (g.nl.die[2] - g.nl.die[0]);
-    float sy = side / (g.nl.die[3] - g.nl.die[1]);
-    hipLaunchKernelGGL(k_layout_keys, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, pos, ncols, n, g.nl.die[0],
-                       g.nl.die[1], sx, sy, key.p, digit.p);
+    KeyArgs ka;
+    ka.pos = pos;
+    ka.ncols = ncols;
+    ka.n_inst = n;
+    ka.first_star = g.first_star;
+    ka.first_mvirt = np;
+    ka.mpin_pin = g.mpin_pin.p;
+    ka.star_net = g.star_net.p;
+    ka.net_ptr = g.nl.net_ptr;
+    ka.pin_node = g.nl.pin_node;
+    ka.pin_node_x = g.pin_node_x.p;
+    ka.pin_off = g.nl.pin_off;
+    ka.xl = g.nl.die[0];
+    ka.yl = g.nl.die[1];
+    ka.sx = side / (g.nl.die[2] - g.nl.die[0]);
+    ka.sy = side / (g.nl.die[3] - g.nl.die[1]);
+    hipLaunchKernelGGL(k_layout_keys, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, ka, key.p, digit.p);
     AHR_LAUNCHED("k_layout_keys");
     // LSD radix sort, both passes stable: by the low digit, then by the high
-    // digit of that order; ties keep instance order
-    bucket_sort(g, digit.p, n, 1 << kDigitBits, first, g.lay_start, s, false);
-    hipLaunchKernelGGL(k_high_digit, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, n, key.p, first.p, digit.p);
+    // digit of that order; ties keep node order.  The range bits keep the
+    // instances, macro pins and stars in their own id ranges.
+    bucket_sort(g, digit.p, np, 1 << kDigitBits, first, g.lay_start, s, false);
+    hipLaunchKernelGGL(k_high_digit, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, key.p, first.p, digit.p);
     AHR_LAUNCHED("k_high_digit");
-    bucket_sort(g, digit.p, n, 1 << (2 * kGridBits - kDigitBits), second, g.lay_start, s, false);
-    g.perm.ensure(static_cast<size_t>(n) + 1, s);
-    hipLaunchKernelGGL(k_compose, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, n, first.p, second.p, key.p);
+    bucket_sort(g, digit.p, np, 1 << (kKeyBits - kDigitBits), second, g.lay_start, s, false);
+    g.perm.ensure(static_cast<size_t>(np) + 1, s);
+    hipLaunchKernelGGL(k_compose, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, first.p, second.p, key.p);
     AHR_LAUNCHED("k_compose");
+    // instance windows by row length; macro pins and stars as sorted
     hipLaunchKernelGGL(k_window_sort, dim3(grid_for(n, kLenWindow)), dim3(kLenWindow), 0, s, n, key.p, g.net_rp.p,
                        g.perm.p);
     AHR_LAUNCHED("k_window_sort");
+    if (np > n)
+        AHR_HIP(hipMemcpyAsync(g.perm.p + n, key.p + n, static_cast<size_t>(np - n) * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, s));
     key.release(s);
     digit.release(s);
     first.release(s);
     second.release(s);
-    g.iperm.ensure(static_cast<size_t>(n) + 1, s);
-    hipLaunchKernelGGL(k_iperm, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.perm.p, n, g.iperm.p);
+    g.iperm.ensure(static_cast<size_t>(np) + 1, s);
+    hipLaunchKernelGGL(k_iperm, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, g.perm.p, np, g.iperm.p);
     AHR_LAUNCHED("k_iperm");
 
     DevBuf<int32_t> len;
     len.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_exec_lens, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, n, g.perm.p, g.net_rp.p, len.p);
+    hipLaunchKernelGGL(k_exec_lens, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, np, g.perm.p, g.net_rp.p, len.p);
     AHR_LAUNCHED("k_exec_lens");
     g.xnet_rp.ensure(static_cast<size_t>(N) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(N), s);
@@ -216,7 +278,7 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.xnet_ent.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
     if (g.nnz_net) {
-        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N, n,
+        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N, np,
                            g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
         AHR_LAUNCHED("k_exec_net");
         DevBuf<int32_t> flag, rank, rows;
@@ -227,14 +289,14 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         scan_i32_to_i32(flag.p, rank.p, N, g.scan_tmp.p, s);
         rows.ensure(static_cast<size_t>(N) + 1, s);
         list_rows(flag.p, rank.p, N, rows.p, s);
-        hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s, rows.p, rank.p + N, n, g.perm.p,
+        hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s, rows.p, rank.p + N, np, g.perm.p,
                            g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
         AHR_LAUNCHED("k_exec_net_long");
         flag.release(s);
         rank.release(s);
         rows.release(s);
     }
-    hipLaunchKernelGGL(k_exec_qdeg, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, n, g.perm.p, g.qdeg.p, g.xqdeg.p);
+    hipLaunchKernelGGL(k_exec_qdeg, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, np, g.perm.p, g.qdeg.p, g.xqdeg.p);
     AHR_LAUNCHED("k_exec_qdeg");
     g.has_layout = 1;
 }
