@@ -237,13 +237,27 @@ __global__ void __launch_bounds__(kBT) k_chunk_absdeg(RowRef m, const int32_t* _
     __shared__ double red[kBT / kWave];
     int r, li, k0, k1, n0, ln, h0;
     chunk_range(blockIdx.x, long_rows, chunk_row, chunk0, m, r, li, k0, k1, n0, ln, h0);
+    // the lane's entries k0 + t + u kBT (ascending), all loaded at once: a
+    // net entry or a slot past the chunk reads the row's first hint slot (the
+    // hint array holds one more than its count) and adds nothing
+    constexpr int U = kChunk / kBT;
+    float wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = k0 + static_cast<int>(threadIdx.x) + u * kBT;
+        const int kh = k < k1 && k >= ln ? k - ln : 0;
+        wv[u] = bits_f(m.hint_ent[h0 + kh].y);
+    }
     double a = 0, sg = 0;
-    for (int k = k0 + threadIdx.x; k < k1; k += kBT)
-        if (k >= ln) {
-            double w = static_cast<double>(bits_f(m.hint_ent[h0 + k - ln].y));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = k0 + static_cast<int>(threadIdx.x) + u * kBT;
+        if (k < k1 && k >= ln) {
+            const double w = static_cast<double>(wv[u]);
             a += fabs(w);
             sg += w;
         }
+    }
     a = block_sum_f64<kBT>(a, red);
     sg = block_sum_f64<kBT>(sg, red);
     if (threadIdx.x == 0) {
@@ -1124,8 +1138,17 @@ __global__ void __launch_bounds__(1024) k_lam_reduce(const double* __restrict__ 
                                                      const double* __restrict__ lmax, int32_t n_long,
                                                      double* __restrict__ lam) {
     __shared__ double red[1024 / kWave];
+    // eight loads in flight per lane; indexes clamped to the last value (a
+    // maximum is exact in any order and repeats do not change it)
+    constexpr int U = 8;
     double b = 0;
-    for (int64_t i = threadIdx.x; i < nwg; i += 1024) b = wgmax[i] > b ? wgmax[i] : b;
+    for (int64_t i0 = threadIdx.x; i0 < nwg; i0 += U * 1024) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = wgmax[i0 + u * 1024 < nwg ? i0 + u * 1024 : nwg - 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) b = v[u] > b ? v[u] : b;
+    }
     for (int64_t i = threadIdx.x; i < n_long; i += 1024) b = lmax[i] > b ? lmax[i] : b;
     b = wave_max(b);
     __syncthreads();

@@ -143,21 +143,24 @@ __global__ void __launch_bounds__(kLenWindow) k_window_sort(int32_t n, const int
     if (j < n) out[static_cast<int64_t>(blockIdx.x) * kLenWindow + rank] = id;
 }
 
-__global__ void k_iperm(const int32_t* __restrict__ perm, int32_t n, int32_t* __restrict__ iperm) {
+// Both directions over all n_tot rows: the virtual rows (from n_perm on)
+// map to themselves.
+__global__ void k_iperm(int32_t* __restrict__ perm, int32_t n_perm, int32_t n_tot, int32_t* __restrict__ iperm) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r < n) iperm[perm[r]] = static_cast<int32_t>(r);
+    if (r < n_perm) {
+        iperm[perm[r]] = static_cast<int32_t>(r);
+    } else if (r < n_tot) {
+        perm[r] = static_cast<int32_t>(r);
+        iperm[r] = static_cast<int32_t>(r);
+    }
 }
 
-// The permutation covers the nodes below n_perm (instances, macro pins,
-// stars); the virtual nodes above keep their ids.
-__device__ __forceinline__ int src_row(int r, int n_perm, const int32_t* perm) { return r < n_perm ? perm[r] : r; }
-__device__ __forceinline__ int map_col(int c, int n_perm, const int32_t* iperm) { return c < n_perm ? iperm[c] : c; }
 
-__global__ void k_exec_lens(int32_t n_tot, int32_t n_perm, const int32_t* __restrict__ perm,
+__global__ void k_exec_lens(int32_t n_tot, const int32_t* __restrict__ perm,
                             const int32_t* __restrict__ rp, int32_t* __restrict__ len) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n_tot) return;
-    int s = src_row(static_cast<int>(r), n_perm, perm);
+    int s = perm[r];
     len[r] = rp[s + 1] - rp[s];
 }
 
@@ -167,22 +170,42 @@ __global__ void k_exec_lens(int32_t n_tot, int32_t n_perm, const int32_t* __rest
 // row (k_exec_net_long).
 constexpr int kShortRow = 64;
 
-__device__ __forceinline__ int2 exec_entry(int32_t c, int64_t q, int n_perm, const int32_t* iperm) {
-    return make_int2(map_col(c, n_perm, iperm), f_bits(static_cast<float>(static_cast<double>(q) * 0x1p-32)));
+__device__ __forceinline__ int2 exec_entry(int32_t c, int64_t q, const int32_t* iperm) {
+    return make_int2(iperm[c], f_bits(static_cast<float>(static_cast<double>(q) * 0x1p-32)));
 }
 
-__global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_perm, const int32_t* __restrict__ perm,
+__global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, const int32_t* __restrict__ perm,
                                                   const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, const int64_t* __restrict__ q,
-                                                  const int32_t* __restrict__ xrp, int2* __restrict__ xent) {
-    constexpr int G = 8;
+                                                  const int32_t* __restrict__ xrp, int2* __restrict__ xent,
+                                                  int64_t spare) {
+    constexpr int G = 8, U = kShortRow / G;
     int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
     int l = threadIdx.x & (G - 1);
     if (r >= n_tot) return;
     int d = xrp[r], len = xrp[r + 1] - d;
-    if (len > kShortRow) return;                           // group-uniform
-    int a = rp[src_row(static_cast<int>(r), n_perm, perm)];
-    for (int k = l; k < len; k += G) xent[d + k] = exec_entry(col[a + k], q[a + k], n_perm, iperm);
+    if (len > kShortRow || len == 0) return;               // group-uniform
+    int a = rp[perm[r]];
+    // No branch around any load or store, so that all of a lane's loads are
+    // in flight together: indexes are clamped to the row's last entry and
+    // slots past the row's end are stored to the spare entry after the
+    // array's last (never read).
+    int32_t c[U];
+    int64_t w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = l + u * G < len ? l + u * G : len - 1;
+        c[u] = col[a + k];
+        w[u] = q[a + k];
+    }
+    int32_t m[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) m[u] = iperm[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t at = l + u * G < len ? static_cast<int64_t>(d) + l + u * G : spare;
+        xent[at] = make_int2(m[u], f_bits(static_cast<float>(static_cast<double>(w[u]) * 0x1p-32)));
+    }
 }
 
 // One workgroup per longer row; the workgroups stride over the list of
@@ -190,7 +213,7 @@ __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, int32_t n_perm,
 constexpr int kLongRowGrid = 512;
 
 __global__ void __launch_bounds__(kBT) k_exec_net_long(const int32_t* __restrict__ rows,
-                                                       const int32_t* __restrict__ n_long, int32_t n_perm,
+                                                       const int32_t* __restrict__ n_long,
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ iperm,
                                                        const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -200,8 +223,8 @@ __global__ void __launch_bounds__(kBT) k_exec_net_long(const int32_t* __restrict
     for (int li = blockIdx.x; li < nl; li += gridDim.x) {
         const int r = rows[li];
         const int d = xrp[r], len = xrp[r + 1] - d;
-        const int a = rp[src_row(r, n_perm, perm)];
-        for (int k = threadIdx.x; k < len; k += kBT) xent[d + k] = exec_entry(col[a + k], q[a + k], n_perm, iperm);
+        const int a = rp[perm[r]];
+        for (int k = threadIdx.x; k < len; k += kBT) xent[d + k] = exec_entry(col[a + k], q[a + k], iperm);
     }
 }
 
@@ -210,10 +233,10 @@ __global__ void k_long_flags(int32_t n_tot, const int32_t* __restrict__ xrp, int
     if (r < n_tot) flag[r] = (xrp[r + 1] - xrp[r] > kShortRow) ? 1 : 0;
 }
 
-__global__ void k_exec_qdeg(int32_t n_tot, int32_t n_perm, const int32_t* __restrict__ perm,
+__global__ void k_exec_qdeg(int32_t n_tot, const int32_t* __restrict__ perm,
                             const int64_t* __restrict__ qdeg, int64_t* __restrict__ xqdeg) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r < n_tot) xqdeg[r] = qdeg[src_row(static_cast<int>(r), n_perm, perm)];
+    if (r < n_tot) xqdeg[r] = qdeg[perm[r]];
 }
 
 }  // namespace
@@ -249,7 +272,7 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     hipLaunchKernelGGL(k_high_digit, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, key.p, first.p, digit.p);
     AHR_LAUNCHED("k_high_digit");
     bucket_sort(g, digit.p, np, 1 << (kKeyBits - kDigitBits), second, g.lay_start, s, false);
-    g.perm.ensure(static_cast<size_t>(np) + 1, s);
+    g.perm.ensure(static_cast<size_t>(N) + 1, s);
     hipLaunchKernelGGL(k_compose, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, first.p, second.p, key.p);
     AHR_LAUNCHED("k_compose");
     // instance windows by row length; macro pins and stars as sorted
@@ -263,13 +286,13 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     digit.release(s);
     first.release(s);
     second.release(s);
-    g.iperm.ensure(static_cast<size_t>(np) + 1, s);
-    hipLaunchKernelGGL(k_iperm, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, g.perm.p, np, g.iperm.p);
+    g.iperm.ensure(static_cast<size_t>(N) + 1, s);
+    hipLaunchKernelGGL(k_iperm, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, g.perm.p, np, N, g.iperm.p);
     AHR_LAUNCHED("k_iperm");
 
     DevBuf<int32_t> len;
     len.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_exec_lens, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, np, g.perm.p, g.net_rp.p, len.p);
+    hipLaunchKernelGGL(k_exec_lens, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.perm.p, g.net_rp.p, len.p);
     AHR_LAUNCHED("k_exec_lens");
     g.xnet_rp.ensure(static_cast<size_t>(N) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(N), s);
@@ -278,8 +301,9 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.xnet_ent.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
     g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
     if (g.nnz_net) {
-        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N, np,
-                           g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
+        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N,
+                           g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p,
+                           static_cast<int64_t>(g.nnz_net));
         AHR_LAUNCHED("k_exec_net");
         DevBuf<int32_t> flag, rank, rows;
         flag.ensure(static_cast<size_t>(N) + 1, s);
@@ -289,14 +313,14 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         scan_i32_to_i32(flag.p, rank.p, N, g.scan_tmp.p, s);
         rows.ensure(static_cast<size_t>(N) + 1, s);
         list_rows(flag.p, rank.p, N, rows.p, s);
-        hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s, rows.p, rank.p + N, np, g.perm.p,
+        hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s, rows.p, rank.p + N, g.perm.p,
                            g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
         AHR_LAUNCHED("k_exec_net_long");
         flag.release(s);
         rank.release(s);
         rows.release(s);
     }
-    hipLaunchKernelGGL(k_exec_qdeg, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, np, g.perm.p, g.qdeg.p, g.xqdeg.p);
+    hipLaunchKernelGGL(k_exec_qdeg, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.perm.p, g.qdeg.p, g.xqdeg.p);
     AHR_LAUNCHED("k_exec_qdeg");
     g.has_layout = 1;
 }
