@@ -13,10 +13,13 @@
 // one contiguous range of rows.  Inside each aligned window of 64 rows (the
 // rows of one workgroup of the hop) the rows are then ordered by netlist
 // row length, so the rows that share a wave need about the same number of
-// entry batches and the window stays one spatial neighbourhood.  The netlist rows are copied into that order (entry
-// order within a row kept, so the summation order is fixed by the inputs);
-// the hint rows are built in it directly.  The canonical netlist CSR stays
-// for export; the order is set once per graph from the first placement seen.
+// entry batches and the window stays one spatial neighbourhood.  The
+// netlist rows are copied into that order, the entries of each short row
+// sorted by their renumbered column (so a row's gathers also walk the
+// layout in order; the summation order is fixed by the inputs and the first
+// placement); the hint rows are built in it directly.  The canonical netlist
+// CSR stays for export; the order is set once per graph from the first
+// placement seen.
 #include "ahr_internal.hpp"
 #include "device_util.hpp"
 
@@ -165,9 +168,12 @@ __global__ void k_exec_lens(int32_t n_tot, const int32_t* __restrict__ perm,
 }
 
 // Execution-order netlist rows: each row copies its canonical row's
-// entries (order kept) with columns renumbered and weights as float32.
-// G lanes per row of at most kShortRow entries; one workgroup per longer
-// row (k_exec_net_long).
+// entries with columns renumbered and weights as float32.  Rows of at most
+// kShortRow entries are put in ascending order of the renumbered column, so
+// that the lanes of a row gather neighbouring nodes in turn (a row's columns
+// are distinct, so an entry's place is the count of smaller ones); G lanes
+// per such row.  Longer rows keep their canonical entry order and have one
+// workgroup each (k_exec_net_long).
 constexpr int kShortRow = 64;
 
 __device__ __forceinline__ int2 exec_entry(int32_t c, int64_t q, const int32_t* iperm) {
@@ -180,31 +186,50 @@ __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, const int32_t* 
                                                   const int32_t* __restrict__ xrp, int2* __restrict__ xent,
                                                   int64_t spare) {
     constexpr int G = 8, U = kShortRow / G;
-    int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
-    int l = threadIdx.x & (G - 1);
-    if (r >= n_tot) return;
-    int d = xrp[r], len = xrp[r + 1] - d;
-    if (len > kShortRow || len == 0) return;               // group-uniform
-    int a = rp[perm[r]];
-    // No branch around any load or store, so that all of a lane's loads are
-    // in flight together: indexes are clamped to the row's last entry and
-    // slots past the row's end are stored to the spare entry after the
-    // array's last (never read).
-    int32_t c[U];
-    int64_t w[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int k = l + u * G < len ? l + u * G : len - 1;
-        c[u] = col[a + k];
-        w[u] = q[a + k];
+    __shared__ int32_t cols[kBT / G][kShortRow];
+    const int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
+    const int l = threadIdx.x & (G - 1);
+    int32_t* mine = cols[threadIdx.x / G];
+    int d = 0, len = 0;
+    if (r < n_tot) {
+        d = xrp[r];
+        len = xrp[r + 1] - d;
+        if (len > kShortRow) len = 0;                      // group-uniform: k_exec_net_long
     }
+    // No branch around any global load or store, so that all of a lane's
+    // loads are in flight together: indexes are clamped to the row's last
+    // entry and slots past the row's end store to the spare entry after the
+    // array's last (never read).
     int32_t m[U];
+    int2 e[U];
+    if (len > 0) {
+        const int a = rp[perm[r]];
+        int32_t c[U];
+        int64_t w[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) m[u] = iperm[c[u]];
+        for (int u = 0; u < U; ++u) {
+            const int k = l + u * G < len ? l + u * G : len - 1;
+            c[u] = col[a + k];
+            w[u] = q[a + k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) m[u] = iperm[c[u]];
+        // slots past the row's end hold repeats; the counts read below len only
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            mine[l + u * G] = m[u];
+            e[u] = make_int2(m[u], f_bits(static_cast<float>(static_cast<double>(w[u]) * 0x1p-32)));
+        }
+    }
+    __syncthreads();
+    if (len == 0) return;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int64_t at = l + u * G < len ? static_cast<int64_t>(d) + l + u * G : spare;
-        xent[at] = make_int2(m[u], f_bits(static_cast<float>(static_cast<double>(w[u]) * 0x1p-32)));
+        int rank = 0;
+        if (u * G < len)                                   // group-uniform
+            for (int j = 0; j < len; ++j) rank += mine[j] < m[u] ? 1 : 0;
+        const int64_t at = l + u * G < len ? static_cast<int64_t>(d) + rank : spare;
+        xent[at] = e[u];
     }
 }
 
