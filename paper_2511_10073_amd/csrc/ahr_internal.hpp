@@ -210,7 +210,9 @@ struct Graph {
     // execution layout: instance, macro pin and star rows each in spatial
     // order inside their id range (perm: exec -> id); virtual rows unmoved
     int32_t has_layout = 0;
-    DevBuf<int32_t> perm, iperm;  // [first_mvirt]
+    DevBuf<int32_t> perm, iperm;  // [n_tot]: identity on the virtual rows
+    DevBuf<int4> xmpin;           // [n_mpin] per execution macro pin row: owner, offset x, y (float bits)
+    DevBuf<int32_t> xstar_net;    // [n_star] per execution star row: its net
     DevBuf<int32_t> xnet_rp;      // [n_tot+1]
     DevBuf<int2> xnet_ent;        // [nnz_net]
     DevBuf<int64_t> xqdeg;        // [n_tot]
@@ -309,6 +311,8 @@ struct ExpandArgs {
     int64_t in_off;
     const int32_t* perm;      // execution row -> node (instances, macro pins, stars)
     const int32_t* iperm;     // node -> execution row (instances, macro pins, stars)
+    const int4* xmpin;        // per execution macro pin row: owner instance, pin offset x, y (float bits)
+    const int32_t* xstar_net; // per execution star row: its net
     const float* scale;
     float* z0;
     float* zpk;               // or, when set, first-hop records: z then the row scale (replaces z0)

@@ -20,6 +20,8 @@ Graph::~Graph() {
     net_q.release(s);
     perm.release(s);
     iperm.release(s);
+    xmpin.release(s);
+    xstar_net.release(s);
     xnet_rp.release(s);
     xnet_ent.release(s);
     xqdeg.release(s);

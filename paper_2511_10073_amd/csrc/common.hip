@@ -153,18 +153,43 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 
 size_t scan_tmp_elems(int64_t n) { return static_cast<size_t>((n + kScanTile - 1) / kScanTile) + 2; }
 
+// Loads here are unconditional, indexes clamped to the last element and the
+// values masked afterwards: a load under a per-lane branch is waited for
+// where the branch joins, which would run the loads one after another.
+
 template <class Tin>
 __global__ void __launch_bounds__(kScanThreads) k_tile_sums(const Tin* __restrict__ in, int64_t n,
                                                             int64_t* __restrict__ sums) {
     __shared__ int64_t red[kScanThreads / 64];
-    int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
-    int64_t v = 0;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x;
+    Tin x[kScanItems];
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + static_cast<int64_t>(k) * kScanThreads + threadIdx.x;
-        if (i < n) v += static_cast<int64_t>(in[i]);
+        const int64_t i = base + static_cast<int64_t>(k) * kScanThreads;
+        x[k] = in[i < n ? i : n - 1];
     }
+    int64_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        v += base + static_cast<int64_t>(k) * kScanThreads < n ? static_cast<int64_t>(x[k]) : 0;
     v = block_sum_i64<kScanThreads>(v, red);
     if (threadIdx.x == 0) sums[blockIdx.x] = v;
+}
+
+// The kScanItems elements of thread t of a tile (t kScanItems onwards), as
+// int64, zero past n.
+template <class Tin>
+__device__ __forceinline__ int64_t load_items(const Tin* __restrict__ in, int64_t n, int64_t base, int64_t* v) {
+    Tin x[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) x[k] = in[base + k < n ? base + k : n - 1];
+    int64_t local = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? static_cast<int64_t>(x[k]) : 0;
+        local += v[k];
+    }
+    return local;
 }
 
 // Exclusive scan of the tile sums by one block; sums[ntiles] = total.
@@ -194,12 +219,7 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_scan(const Tin* __restric
     __shared__ int64_t red[kScanThreads / 64];
     int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
     int64_t v[kScanItems];
-    int64_t local = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        v[k] = i < n ? static_cast<int64_t>(in[i]) : 0;
-        local += v[k];
-    }
+    const int64_t local = load_items(in, n, base, v);
     int64_t tot;
     int64_t ex = block_exclusive_scan_i64<kScanThreads>(local, red, &tot);
     int64_t run = sums[blockIdx.x] + ex;
@@ -222,19 +242,24 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_scan_direct(const Tin* __
                                                                    int64_t* __restrict__ sums, int64_t ntiles,
                                                                    Tout* __restrict__ out) {
     __shared__ int64_t red[kScanThreads / 64];
-    const int64_t upto = blockIdx.x == 0 ? ntiles : static_cast<int64_t>(blockIdx.x);
-    int64_t pre = 0;
-    for (int64_t j = threadIdx.x; j < upto; j += kScanThreads) pre += sums[j];
-    pre = block_sum_i64<kScanThreads>(pre, red);
-    const int64_t tile_off = blockIdx.x == 0 ? 0 : pre;
+    const int64_t upto = blockIdx.x == 0 ? ntiles : static_cast<int64_t>(blockIdx.x);   // >= 1
     int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
     int64_t v[kScanItems];
-    int64_t local = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        v[k] = i < n ? static_cast<int64_t>(in[i]) : 0;
-        local += v[k];
+    const int64_t local = load_items(in, n, base, v);
+    constexpr int U = 8;
+    int64_t pre = 0;
+    for (int64_t j0 = threadIdx.x; j0 < upto; j0 += U * kScanThreads) {
+        int64_t t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + u * kScanThreads;
+            t[u] = sums[j < upto ? j : upto - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) pre += j0 + u * kScanThreads < upto ? t[u] : 0;
     }
+    pre = block_sum_i64<kScanThreads>(pre, red);
+    const int64_t tile_off = blockIdx.x == 0 ? 0 : pre;
     int64_t tot;
     int64_t ex = block_exclusive_scan_i64<kScanThreads>(local, red, &tot);
     int64_t run = tile_off + ex;

@@ -399,8 +399,7 @@ __device__ __forceinline__ Vec<C> pin_value(const ExpandArgs& a, int p) {
 }
 
 template <int C>
-__device__ __forceinline__ void put_z(const ExpandArgs& a, int r, Vec<C> x) {
-    float s = a.scale[r];
+__device__ __forceinline__ void put_z(const ExpandArgs& a, int r, Vec<C> x, float s) {
     const int64_t row = r < a.n_inst ? static_cast<int64_t>(a.row_inst0) + r
                                      : static_cast<int64_t>(a.row_aux0) + (r - a.n_inst);
     Vec<C> z, t;
@@ -434,18 +433,23 @@ __device__ __forceinline__ void put_z(const ExpandArgs& a, int r, Vec<C> x) {
 }
 
 
-// One row of the extended graph.  Stars with more than kStarInline pins are
-// left to expand_bigstar.
+// One row of the extended graph (execution row r).  Stars with more than
+// kStarInline pins are left to expand_bigstar.
 template <int C>
 __device__ __forceinline__ void expand_row(const ExpandArgs& a, int r) {
+    const float sc = a.scale[r];
     Vec<C> x;
     if (r < a.n_inst) {
         x = vload<C>(a.in + static_cast<int64_t>(a.perm[r]) * C);
     } else if (r < a.first_star) {
-        int k = a.perm[r] - a.first_mpin;
-        x = pin_value<C>(a, a.mpin_pin[k]);
+        // the macro's position plus the pin offset
+        const int4 m = a.xmpin[r - a.first_mpin];
+        x = vload<C>(a.in + static_cast<int64_t>(m.x) * C);
+        const float dx = __int_as_float(m.y), dy = __int_as_float(m.z);
+#pragma unroll
+        for (int c = 0; c < C; ++c) x.v[c] += (c & 1) ? dy : dx;
     } else if (r < a.first_mvirt) {
-        int e = a.star_net[a.perm[r] - a.first_star];
+        int e = a.xstar_net[r - a.first_star];
         int p0 = a.net_ptr[e], p1 = a.net_ptr[e + 1];
         if (p1 - p0 > kStarInline) return;
         double acc[C];
@@ -467,7 +471,7 @@ __device__ __forceinline__ void expand_row(const ExpandArgs& a, int r) {
 #pragma unroll
         for (int c = 0; c < C; ++c) x.v[c] = (c & 1) ? cy : cx;
     }
-    put_z<C>(a, r, x);
+    put_z<C>(a, r, x, sc);
 }
 
 // Mean over the pins of star k (kStarInline < pins <= kStarMid): G lanes
@@ -503,7 +507,10 @@ __device__ __forceinline__ void expand_star(const ExpandArgs& a, int k) {
         for (int o = G / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
         x.v[c] = static_cast<float>(t / deg);
     }
-    if (l == 0) put_z<C>(a, a.iperm[a.first_star + k], x);
+    if (l == 0) {
+        const int r = a.iperm[a.first_star + k];
+        put_z<C>(a, r, x, a.scale[r]);
+    }
 }
 
 // Mean over the pins of a big star (more than kStarMid pins): the whole
@@ -532,7 +539,10 @@ __device__ __forceinline__ void expand_big_star(const ExpandArgs& a, int k) {
     Vec<C> x;
 #pragma unroll
     for (int c = 0; c < C; ++c) x.v[c] = static_cast<float>(block_sum_f64<kBT>(acc[c], red) / (p1 - p0));
-    if (threadIdx.x == 0) put_z<C>(a, a.iperm[a.first_star + k], x);
+    if (threadIdx.x == 0) {
+        const int r = a.iperm[a.first_star + k];
+        put_z<C>(a, r, x, a.scale[r]);
+    }
 }
 
 template <int C>
@@ -1627,6 +1637,8 @@ ExpandArgs expand_args(const Graph& g) {
     e.in_off = 0;
     e.perm = g.perm.p;
     e.iperm = g.iperm.p;
+    e.xmpin = g.xmpin.p;
+    e.xstar_net = g.xstar_net.p;
     e.scale = g.scale.p;
     e.z0 = nullptr;
     e.zpk = nullptr;

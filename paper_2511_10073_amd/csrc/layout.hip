@@ -146,6 +146,23 @@ __global__ void __launch_bounds__(kLenWindow) k_window_sort(int32_t n, const int
     if (j < n) out[static_cast<int64_t>(blockIdx.x) * kLenWindow + rank] = id;
 }
 
+// What the expansion reads for the macro pin and star rows, in execution
+// order: a macro pin row's owner instance and pin offset, a star row's net.
+__global__ void k_exec_aux(int32_t n_inst, int32_t first_star, int32_t first_mvirt, const int32_t* __restrict__ perm,
+                           const int32_t* __restrict__ mpin_pin, const int32_t* __restrict__ pin_node,
+                           const float* __restrict__ pin_off, const int32_t* __restrict__ star_net,
+                           int4* __restrict__ xmpin, int32_t* __restrict__ xstar_net) {
+    const int64_t r = n_inst + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= first_mvirt) return;
+    const int v = perm[r];
+    if (r < first_star) {
+        const int p = mpin_pin[v - n_inst];
+        xmpin[r - n_inst] = make_int4(pin_node[p], __float_as_int(pin_off[2 * p]), __float_as_int(pin_off[2 * p + 1]), 0);
+    } else {
+        xstar_net[r - first_star] = star_net[v - first_star];
+    }
+}
+
 // Both directions over all n_tot rows: the virtual rows (from n_perm on)
 // map to themselves.
 __global__ void k_iperm(int32_t* __restrict__ perm, int32_t n_perm, int32_t n_tot, int32_t* __restrict__ iperm) {
@@ -314,6 +331,13 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.iperm.ensure(static_cast<size_t>(N) + 1, s);
     hipLaunchKernelGGL(k_iperm, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, g.perm.p, np, N, g.iperm.p);
     AHR_LAUNCHED("k_iperm");
+    g.xmpin.ensure(static_cast<size_t>(g.first_star - n) + 1, s);
+    g.xstar_net.ensure(static_cast<size_t>(np - g.first_star) + 1, s);
+    if (np > n) {
+        hipLaunchKernelGGL(k_exec_aux, dim3(grid_for(np - n, kBT)), dim3(kBT), 0, s, n, g.first_star, np, g.perm.p,
+                           g.mpin_pin.p, g.nl.pin_node, g.nl.pin_off, g.star_net.p, g.xmpin.p, g.xstar_net.p);
+        AHR_LAUNCHED("k_exec_aux");
+    }
 
     DevBuf<int32_t> len;
     len.ensure(static_cast<size_t>(N) + 1, s);

@@ -136,6 +136,24 @@ struct NetArgs {
     int32_t n_nets, n_pins, clique_max, first_star;
 };
 
+// The nodes of the pins of a clique net of at most kNetUnroll pins, all
+// loaded at once (indexes clamped to the last pin; a loop one load at a time
+// would wait for each), and how many of them differ from v.
+constexpr int kNetUnroll = 16;
+
+__device__ __forceinline__ int clique_nodes(const int32_t* __restrict__ pin_x, int lo, int hi, int v, int* node) {
+    int c = 0;
+    if (hi - lo <= kNetUnroll) {
+#pragma unroll
+        for (int u = 0; u < kNetUnroll; ++u) node[u] = pin_x[lo + u < hi ? lo + u : hi - 1];
+#pragma unroll
+        for (int u = 0; u < kNetUnroll; ++u) c += (lo + u < hi && node[u] != v) ? 1 : 0;
+    } else {
+        for (int b = lo; b < hi; ++b) c += (pin_x[b] != v) ? 1 : 0;
+    }
+    return c;
+}
+
 // Entries each row receives (parallel edges counted separately).
 __global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt) {
     int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -146,8 +164,8 @@ __global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt) {
     if (deg < 2) return;
     int v = a.pin_x[p];
     if (deg <= a.clique_max) {
-        int c = 0;
-        for (int b = lo; b < hi; ++b) c += (a.pin_x[b] != v) ? 1 : 0;
+        int node[kNetUnroll];
+        const int c = clique_nodes(a.pin_x, lo, hi, v, node);
         if (c) atomicAdd(&cnt[v], c);
     } else {
         atomicAdd(&cnt[v], 1);
@@ -170,15 +188,24 @@ __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __
     float w = a.net_w ? a.net_w[e] : 1.0f;
     if (deg <= a.clique_max) {
         int64_t q = q_clique(w, deg);
-        int c = 0;
-        for (int b = lo; b < hi; ++b) c += (a.pin_x[b] != v) ? 1 : 0;
+        int node[kNetUnroll];
+        const int c = clique_nodes(a.pin_x, lo, hi, v, node);
         if (!c) return;
         int64_t k = rp[v] + atomicAdd(&cursor[v], c);
-        for (int b = lo; b < hi; ++b) {
-            int u = a.pin_x[b];
-            if (u == v) continue;
-            raw[k] = raw_ent(u, q);
-            ++k;
+        if (deg <= kNetUnroll) {
+#pragma unroll
+            for (int u = 0; u < kNetUnroll; ++u)
+                if (lo + u < hi && node[u] != v) {
+                    raw[k] = raw_ent(node[u], q);
+                    ++k;
+                }
+        } else {
+            for (int b = lo; b < hi; ++b) {
+                int u = a.pin_x[b];
+                if (u == v) continue;
+                raw[k] = raw_ent(u, q);
+                ++k;
+            }
         }
     } else {
         int64_t q = q_star(w, deg);
