@@ -178,7 +178,10 @@ ahr_status ahr_graph_get_info(const ahr_graph* gr, ahr_graph_info* info);
  * within a bin -- the order the filter sums them in. */
 ahr_status ahr_graph_export(const ahr_graph* gr, ahr_graph_host* dst, void* stream);
 
-/* Free a graph and its device memory (synchronises the device). */
+/* Free a graph and its device memory.  When all of the graph's work was
+ * enqueued on one stream, the memory is released in that stream's order
+ * (later work on any stream reuses it only after the graph's work) and the
+ * call does not wait; otherwise it synchronises the device. */
 void ahr_graph_destroy(ahr_graph* gr);
 
 /* Apply the polynomial filter of `spec` (Section V eq. "refine-filter";

@@ -165,6 +165,20 @@ struct Graph {
     int32_t has_hints = 0;
     int device = 0;
 
+    // The streams the graph's work was enqueued on: while there is one, the
+    // destructor releases the memory in that stream's order and does not
+    // wait for the device.
+    mutable hipStream_t work_stream = nullptr;
+    mutable int stream_uses = 0;   // 0 none, 1 one stream, 2 several
+    void use_stream(hipStream_t s) const {
+        if (stream_uses == 0) {
+            work_stream = s;
+            stream_uses = 1;
+        } else if (s != work_stream) {
+            stream_uses = 2;
+        }
+    }
+
     // netlist part (fixed for the life of the handle)
     DevBuf<int32_t> pin_node_x;   // [n_pins] pin node after macro pin expansion
     DevBuf<int32_t> mpin_owner;   // [n_mpin]

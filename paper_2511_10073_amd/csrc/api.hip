@@ -11,7 +11,9 @@ extern int g_hop_lanes;
 extern int g_hop_nt;
 
 Graph::~Graph() {
-    hipStream_t s = nullptr;
+    // one stream: its later work (and any other stream, through the block
+    // events) reuses the memory only after this graph's work; else wait
+    hipStream_t s = stream_uses == 1 ? work_stream : nullptr;
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_rp, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
                               &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart,
@@ -56,7 +58,7 @@ Graph::~Graph() {
     gt.release(s);
     scan_tmp.release(s);
     i64a.release(s);
-    (void)hipStreamSynchronize(s);
+    if (stream_uses != 1) (void)hipStreamSynchronize(s);
 }
 
 }  // namespace ahr
@@ -149,6 +151,7 @@ ahr_status ahr_graph_build(const ahr_netlist* nl, const ahr_hint_params* hp, con
     return guarded([&]() -> ahr_status {
         hipStream_t s = as_stream(stream);
         auto* gr = new ahr::Graph();
+        gr->use_stream(s);
         gr->nl = *nl;
         gr->hp = *hp;
         AHR_HIP(hipGetDevice(&gr->device));
@@ -174,6 +177,7 @@ ahr_status ahr_graph_update_hints(ahr_graph* h, const float* g, int32_t ncols, v
     return guarded([&]() -> ahr_status {
         auto* gr = reinterpret_cast<ahr::Graph*>(h);
         hipStream_t s = as_stream(stream);
+        gr->use_stream(s);
         ahr::build_hints(*gr, g, ncols, s);
         AHR_HIP(hipStreamSynchronize(s));
         return AHR_OK;
@@ -203,6 +207,7 @@ ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* strea
     return guarded([&]() -> ahr_status {
         const auto* g = reinterpret_cast<const ahr::Graph*>(h);
         hipStream_t s = as_stream(stream);
+        g->use_stream(s);
         const size_t N = static_cast<size_t>(g->n_tot);
         auto cp = [&](void* d, const void* src, size_t bytes) {
             if (d && bytes) AHR_HIP(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToHost, s));
@@ -287,6 +292,7 @@ ahr_status ahr_filter(ahr_graph* h, const ahr_filter_spec* spec, const float* in
     size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
     if (overlap(in, bytes, out, bytes)) return fail(AHR_EINVAL, "in and out overlap");
     return guarded([&]() -> ahr_status {
+        gr->use_stream(as_stream(stream));
         ahr::run_filter(*gr, *spec, in, out, ncols, as_stream(stream));
         return AHR_OK;
     });
@@ -306,6 +312,7 @@ ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0
     if (g0 != out && overlap(g0, bytes, out, bytes)) return fail(AHR_EINVAL, "g0 and out partially overlap");
     return guarded([&]() -> ahr_status {
         hipStream_t s = as_stream(stream);
+        gr->use_stream(s);
         size_t n = static_cast<size_t>(gr->n_inst) * ncols;
         if (T_hint == 0) {
             if (g0 != out) AHR_HIP(hipMemcpyAsync(out, g0, bytes, hipMemcpyDeviceToDevice, s));
@@ -342,6 +349,7 @@ ahr_status ahr_refine_learned(ahr_graph* h, const ahr_filter_spec* spec, const a
     if (g0 != out && overlap(g0, bytes, out, bytes)) return fail(AHR_EINVAL, "g0 and out partially overlap");
     return guarded([&]() -> ahr_status {
         hipStream_t s = as_stream(stream);
+        gr->use_stream(s);
         size_t n = static_cast<size_t>(gr->n_inst) * ncols;
         if (used_fallback) *used_fallback = model->validated ? 0 : 1;
         if (T_hint == 0) {
@@ -381,6 +389,7 @@ ahr_status ahr_filter_learned(ahr_graph* h, const ahr_filter_spec* spec, const a
     if (overlap(in, bytes, out, bytes)) return fail(AHR_EINVAL, "in and out overlap");
     return guarded([&]() -> ahr_status {
         hipStream_t s = as_stream(stream);
+        gr->use_stream(s);
         if (!model->validated) {
             ahr::run_filter(*gr, *spec, in, out, ncols, s);
             if (used_fallback) *used_fallback = 1;
@@ -405,6 +414,7 @@ ahr_status ahr_filter_features(ahr_graph* h, const ahr_filter_spec* spec, const 
         static const float zero_beta[3] = {0.f, 0.f, 0.f};
         ahr::DevBuf<float> p;
         hipStream_t s = as_stream(stream);
+        gr->use_stream(s);
         p.ensure(AHR_MLP_NPARAM, s);
         AHR_HIP(hipMemsetAsync(p.p, 0, AHR_MLP_NPARAM * sizeof(float), s));
         ahr::run_learned(*gr, *spec, p.p, zero_beta, in, nullptr, ncols, feats, hops, stats, s);
@@ -468,6 +478,7 @@ ahr_status ahr_hpwl(const ahr_graph* h, const float* g, int32_t ncols, double* o
     if (!g || !out) return fail(AHR_EINVAL, "g/out is NULL");
     if (ncols != 2 && ncols != 4 && ncols != 8) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
     return guarded([&]() -> ahr_status {
+        reinterpret_cast<const ahr::Graph*>(h)->use_stream(as_stream(stream));
         ahr::run_hpwl(*reinterpret_cast<const ahr::Graph*>(h), g, ncols, out, as_stream(stream));
         return AHR_OK;
     });
