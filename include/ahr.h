@@ -169,7 +169,9 @@ ahr_status ahr_graph_build(const ahr_netlist* nl, const ahr_hint_params* hp,
 ahr_status ahr_graph_update_hints(ahr_graph* gr, const float* g, int32_t ncols,
                                   void* stream);
 
-/* Sizes and node ranges (host struct; no device work). */
+/* Sizes and node ranges (host struct).  The entry counts are read from the
+ * device the first time they are asked for after a build or hint update
+ * (waiting for the stream the graph's work went to); no other device work. */
 ahr_status ahr_graph_get_info(const ahr_graph* gr, ahr_graph_info* info);
 
 /* Copy the graph to host buffers (synchronous; for tests).  Rows are in

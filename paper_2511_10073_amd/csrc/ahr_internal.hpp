@@ -146,6 +146,7 @@ struct RowClasses {
     int32_t n_rb = 0, n_rb_inst = 0;          // row blocks, those below n_inst
     int32_t has_rb = 0;                       // row blocks built (on first use of the row-block hop)
     int64_t nnz_inst = 0;                     // entries of rows below n_inst (netlist + hints)
+    int64_t nnz_net_all = 0, nnz_hint_all = 0; // entries of all rows
     void release(hipStream_t s) {
         long_rows.release(s);
         long_chunk0.release(s);
@@ -160,7 +161,11 @@ struct Graph {
     ahr_hint_params hp;
     int32_t n_inst = 0, n_mpin = 0, n_star = 0, n_macro = 0, n_bins = 0;
     int32_t first_mpin = 0, first_star = 0, first_mvirt = 0, first_bvirt = 0, n_tot = 0;
-    int32_t nnz_net = 0, nnz_hint = 0, n_hint_cells = 0;
+    // entry counts; -1 while not read yet (arrays are sized by a bound, the
+    // counts ride along with later reads: hint_count / net_count read them)
+    mutable int32_t nnz_net = 0, nnz_hint = 0;
+    int32_t nnz_cap = 0;        // capacity of the netlist entry arrays (>= nnz_net)
+    int32_t n_hint_cells = 0;
     int32_t hint_version = 0;
     int32_t has_hints = 0;
     int device = 0;
@@ -274,6 +279,9 @@ void build_netlist(Graph& g, hipStream_t s);
 // the count when read_total (one synchronisation), else -1.
 int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
                     DevBuf<int32_t>& start, hipStream_t s, bool read_total = true);
+// Exact entry counts of g, read from its row pointers when not known yet.
+int32_t net_count(const Graph& g, hipStream_t s);
+int32_t hint_count(const Graph& g, hipStream_t s);
 // layout.hip: the execution order of the instance, macro pin and star rows
 // (spatial) and the permuted copy of the netlist rows the filter streams
 void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s);

@@ -10,6 +10,16 @@ std::string& last_error_ref();
 extern int g_hop_lanes;
 extern int g_hop_nt;
 
+int32_t net_count(const Graph& g, hipStream_t s) {
+    if (g.nnz_net < 0) g.nnz_net = read_i32(g.net_rp.p + g.n_tot, s);
+    return g.nnz_net;
+}
+
+int32_t hint_count(const Graph& g, hipStream_t s) {
+    if (g.nnz_hint < 0) g.nnz_hint = read_i32(g.xhint_rp.p + g.n_tot, s);
+    return g.nnz_hint;
+}
+
 Graph::~Graph() {
     // one stream: its later work (and any other stream, through the block
     // events) reuses the memory only after this graph's work; else wait
@@ -186,20 +196,27 @@ ahr_status ahr_graph_update_hints(ahr_graph* h, const float* g, int32_t ncols, v
 
 ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
     if (!h || !info) return fail(AHR_EINVAL, "NULL argument");
-    const auto* g = reinterpret_cast<const ahr::Graph*>(h);
-    std::memset(info, 0, sizeof *info);
-    info->n_inst = g->n_inst;
-    info->n_tot = g->n_tot;
-    info->first_mpin = g->first_mpin;
-    info->first_star = g->first_star;
-    info->first_mvirt = g->first_mvirt;
-    info->first_bvirt = g->first_bvirt;
-    info->nnz_net = g->nnz_net;
-    info->nnz_hint = g->has_hints ? g->nnz_hint : 0;
-    info->n_hint_cells = g->n_hint_cells;
-    info->n_long_rows = g->rc.n_long;
-    info->hint_version = g->hint_version;
-    return AHR_OK;
+    return guarded([&]() -> ahr_status {
+        const auto* g = reinterpret_cast<const ahr::Graph*>(h);
+        // entry counts not read yet come from the row pointers, on the
+        // stream the graph's work went to
+        const hipStream_t s = g->stream_uses == 1 ? g->work_stream : nullptr;
+        const int32_t nnz_net = ahr::net_count(*g, s);
+        const int32_t nnz_hint = g->has_hints ? ahr::hint_count(*g, s) : 0;
+        std::memset(info, 0, sizeof *info);
+        info->n_inst = g->n_inst;
+        info->n_tot = g->n_tot;
+        info->first_mpin = g->first_mpin;
+        info->first_star = g->first_star;
+        info->first_mvirt = g->first_mvirt;
+        info->first_bvirt = g->first_bvirt;
+        info->nnz_net = nnz_net;
+        info->nnz_hint = nnz_hint;
+        info->n_hint_cells = g->n_hint_cells;
+        info->n_long_rows = g->rc.n_long;
+        info->hint_version = g->hint_version;
+        return AHR_OK;
+    });
 }
 
 ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* stream) {
@@ -213,17 +230,19 @@ ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* strea
             if (d && bytes) AHR_HIP(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToHost, s));
         };
         cp(dst->net_row_ptr, g->net_rp.p, (N + 1) * sizeof(int32_t));
-        cp(dst->net_col, g->net_col.p, g->nnz_net * sizeof(int32_t));
-        cp(dst->net_q, g->net_q.p, g->nnz_net * sizeof(int64_t));
+        const size_t nnz_net = static_cast<size_t>(ahr::net_count(*g, s));
+        cp(dst->net_col, g->net_col.p, nnz_net * sizeof(int32_t));
+        cp(dst->net_q, g->net_q.p, nnz_net * sizeof(int64_t));
         if (g->has_hints && (dst->hint_row_ptr || dst->hint_col || dst->hint_val)) {
             // hint rows live in execution order: return them in node order
             const size_t np = static_cast<size_t>(g->first_mvirt);     // rows the layout permutes
             std::vector<int32_t> xrp(N + 1), perm(np);
-            std::vector<int2> ent(g->nnz_hint);
+            const int32_t nnz_hint = ahr::hint_count(*g, s);
+            std::vector<int2> ent(nnz_hint);
             AHR_HIP(hipMemcpyAsync(xrp.data(), g->xhint_rp.p, (N + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             AHR_HIP(hipMemcpyAsync(perm.data(), g->perm.p, np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            if (g->nnz_hint)
-                AHR_HIP(hipMemcpyAsync(ent.data(), g->xhint_ent.p, g->nnz_hint * sizeof(int2), hipMemcpyDeviceToHost, s));
+            if (nnz_hint)
+                AHR_HIP(hipMemcpyAsync(ent.data(), g->xhint_ent.p, nnz_hint * sizeof(int2), hipMemcpyDeviceToHost, s));
             AHR_HIP(hipStreamSynchronize(s));
             std::vector<int32_t> iperm(np);
             for (size_t r = 0; r < np; ++r) iperm[perm[r]] = static_cast<int32_t>(r);

@@ -1322,7 +1322,7 @@ ChainView chain_view(Graph& g, const ahr_filter_spec& spec) {
     v.n_rb = g.rc.n_rb;
     v.n_rb_inst = g.rc.n_rb_inst;
     v.nnz_inst = g.rc.nnz_inst;
-    v.nnz_all = static_cast<int64_t>(g.nnz_net) + g.nnz_hint;
+    v.nnz_all = g.rc.nnz_net_all + g.rc.nnz_hint_all;
     v.z0 = g.z0.p;
     v.z1 = g.z1.p;
     v.acc = g.acc.p;
@@ -1563,8 +1563,12 @@ void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32
     scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i32(is_long.p, rank.p, N, scan_tmp.p, s);
     scan_i32_to_i32(nch.p, cscan.p, N, scan_tmp.p, s);
-    int32_t t[6];
-    read_scalars({rank.p + N, rank.p + n_inst, cscan.p + N, cscan.p + n_inst, net_rp + n_inst, hint_rp + n_inst}, t, s);
+    int32_t t[8];
+    read_scalars({rank.p + N, rank.p + n_inst, cscan.p + N, cscan.p + n_inst, net_rp + n_inst, hint_rp + n_inst,
+                  net_rp + N, hint_rp + N},
+                 t, s);
+    rc.nnz_net_all = t[6];
+    rc.nnz_hint_all = t[7];
     rc.n_long = t[0];
     rc.n_long_inst = t[1];
     rc.n_chunks = t[2];
@@ -1727,6 +1731,8 @@ void normalise_degrees(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     if (g.rows_version != g.hint_version) {
         row_classes(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, g.rc, g.scan_tmp, s);
         g.rows_version = g.hint_version;
+        g.nnz_net = static_cast<int32_t>(g.rc.nnz_net_all);
+        g.nnz_hint = static_cast<int32_t>(g.rc.nnz_hint_all);
     }
 
     const double sigma = spec.sigma;

@@ -706,10 +706,13 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.pair_off.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(std::max<int64_t>(N, n_inst)), s);
     scan_i32_to_i32(g.nmac.p, g.pair_off.p, n_inst, g.scan_tmp.p, s);
-    int32_t tot[2];
-    read_scalars({g.pair_off.p + n_inst, g.bin_start.p + nbins}, tot, s);
+    // (the netlist entry count rides along: the build sizes its arrays by a
+    // bound and leaves the exact count to this read)
+    int32_t tot[3];
+    read_scalars({g.pair_off.p + n_inst, g.bin_start.p + nbins, g.net_rp.p + N}, tot, s);
     const int32_t n_pairs = tot[0];
     g.n_hint_cells = tot[1];
+    g.nnz_net = tot[2];
     g.pair_row.ensure(static_cast<size_t>(n_pairs) + 1, s);
     g.pair_mac.ensure(static_cast<size_t>(n_pairs) + 1, s);
     if (n_pairs) {
@@ -734,14 +737,28 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         hipLaunchKernelGGL(k_bin_row_counts, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s, a, g.hint_cnt.p);
         AHR_LAUNCHED("k_bin_row_counts");
     }
-    const int64_t nnz = scan_i32_checked(g.hint_cnt.p, g.xhint_rp.p, N, g.scan_tmp.p, s);
-    if (nnz + static_cast<int64_t>(g.nnz_net) >= INT32_MAX)
-        throw Error{AHR_EUNSUPPORTED, "graph with hints has 2^31 or more entries"};
-    g.nnz_hint = static_cast<int32_t>(nnz);
-    g.xhint_ent.ensure(static_cast<size_t>(nnz) + 1, s);
+    // Every entry is one side of a (cell, macro) pair or of a (hint cell,
+    // window bin) pair, so the entries number at most twice the pairs plus
+    // twice the hint cells times the window slots: the entry array is sized
+    // by that bound without waiting for the count, which the normalisation
+    // reads with its own sizes.  Near the int32 limit the exact count is read.
+    const int wslots = (2 * gr.hx + 1) * (2 * gr.hy + 1);
+    const int64_t bound =
+        2 * (static_cast<int64_t>(n_pairs) + (bin_hints ? static_cast<int64_t>(g.n_hint_cells) * wslots : 0));
+    int64_t cap = bound;
+    g.nnz_hint = -1;
+    if (bound + static_cast<int64_t>(g.nnz_net) >= INT32_MAX) {
+        const int64_t nnz = scan_i32_checked(g.hint_cnt.p, g.xhint_rp.p, N, g.scan_tmp.p, s);
+        if (nnz + static_cast<int64_t>(g.nnz_net) >= INT32_MAX)
+            throw Error{AHR_EUNSUPPORTED, "graph with hints has 2^31 or more entries"};
+        g.nnz_hint = static_cast<int32_t>(nnz);
+        cap = nnz;
+    } else {
+        scan_i32_to_i32(g.hint_cnt.p, g.xhint_rp.p, N, g.scan_tmp.p, s);
+    }
+    g.xhint_ent.ensure(static_cast<size_t>(cap) + 1, s);
 
     // 7. entries: cell rows first (their weights are reused), then virtual rows
-    const int wslots = (2 * gr.hx + 1) * (2 * gr.hy + 1);
     if (bin_hints) {
         g.bin_rank.ensure(static_cast<size_t>(n_inst) + 1, s);
         g.wpre.ensure(static_cast<size_t>(nbins) * wslots + 1, s);

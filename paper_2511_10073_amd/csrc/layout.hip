@@ -347,12 +347,12 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i32(len.p, g.xnet_rp.p, N, g.scan_tmp.p, s);
     len.release(s);
-    g.xnet_ent.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
+    g.xnet_ent.ensure(static_cast<size_t>(g.nnz_cap) + 1, s);      // the netlist arrays' bound
     g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
-    if (g.nnz_net) {
+    if (g.nnz_cap) {
         hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N,
                            g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p,
-                           static_cast<int64_t>(g.nnz_net));
+                           static_cast<int64_t>(g.nnz_cap));
         AHR_LAUNCHED("k_exec_net");
         DevBuf<int32_t> flag, rank, rows;
         flag.ensure(static_cast<size_t>(N) + 1, s);

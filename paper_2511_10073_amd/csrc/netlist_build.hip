@@ -33,10 +33,11 @@ __global__ void k_validate(const int32_t* __restrict__ net_ptr, int32_t n_nets, 
 }
 
 __global__ void k_mark_mpin(const int32_t* __restrict__ pin_node, const uint8_t* __restrict__ flags, int32_t n_pins,
-                            int32_t expand, int32_t* __restrict__ is_mp) {
+                            int32_t n_inst, int32_t expand, int32_t* __restrict__ is_mp) {
     int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= n_pins) return;
-    uint8_t f = flags[pin_node[p]];
+    const int v = pin_node[p];
+    const uint8_t f = flags[v >= 0 && v < n_inst ? v : 0];      // clamped: runs before the netlist is verified
     is_mp[p] = (expand && (f & AHR_NODE_FIXED) && (f & AHR_NODE_MACRO)) ? 1 : 0;
 }
 
@@ -488,12 +489,9 @@ void build_netlist(Graph& g, hipStream_t s) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(nv, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets, nl.pin_node, n_pins,
                        n_inst, g.counter.p);
     AHR_LAUNCHED("k_validate");
-    int32_t bad = read_i32(g.counter.p, s);
-    if (bad) {
-        static const char* why[] = {"", "pin_node out of [0, n_inst)", "net_ptr[0] != 0",
-                                    "net_ptr[n_nets] != n_pins", "net_ptr decreasing"};
-        throw Error{AHR_EINVAL, std::string("invalid netlist: ") + why[bad]};
-    }
+    // The verdict is read together with the counts below: the kernels in
+    // between index only with clamped pin nodes, so an invalid netlist reads
+    // nothing out of bounds before it is rejected.
 
     // flags of macro pins, star nets, big nets, macros; their ranks; one read of the four counts
     DevBuf<int32_t> is_mp, mp_rank, is_star, star_rank, is_big, big_rank, is_mac, mac_rank, is_bs, bs_rank;
@@ -504,7 +502,7 @@ void build_netlist(Graph& g, hipStream_t s) {
     is_mac.ensure(static_cast<size_t>(n_inst) + 1, s);
     if (n_pins)
         hipLaunchKernelGGL(k_mark_mpin, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, nl.pin_node, nl.node_flags,
-                           n_pins, (hp.flags & AHR_EXPAND_MACRO_PINS) ? 1 : 0, is_mp.p);
+                           n_pins, n_inst, (hp.flags & AHR_EXPAND_MACRO_PINS) ? 1 : 0, is_mp.p);
     AHR_LAUNCHED("k_mark_mpin");
     if (n_nets)
         hipLaunchKernelGGL(k_mark_star, dim3(grid_for(n_nets, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets,
@@ -523,10 +521,15 @@ void build_netlist(Graph& g, hipStream_t s) {
     scan_i32_to_i32(is_big.p, big_rank.p, n_nets, g.scan_tmp.p, s);
     scan_i32_to_i32(is_mac.p, mac_rank.p, n_inst, g.scan_tmp.p, s);
     scan_i32_to_i32(is_bs.p, bs_rank.p, n_nets, g.scan_tmp.p, s);
-    int32_t cnt5[5];
+    int32_t cnt5[6];
     read_scalars({mp_rank.p + n_pins, star_rank.p + n_nets, big_rank.p + n_nets, mac_rank.p + n_inst,
-                  bs_rank.p + n_nets},
+                  bs_rank.p + n_nets, g.counter.p},
                  cnt5, s);
+    if (const int32_t bad = cnt5[5]) {
+        static const char* why[] = {"", "pin_node out of [0, n_inst)", "net_ptr[0] != 0",
+                                    "net_ptr[n_nets] != n_pins", "net_ptr decreasing"};
+        throw Error{AHR_EINVAL, std::string("invalid netlist: ") + why[bad]};
+    }
     g.n_mpin = cnt5[0];
     g.n_star = cnt5[1];
     g.n_big_nets = cnt5[2];
@@ -675,10 +678,14 @@ void build_netlist(Graph& g, hipStream_t s) {
     raw.release(s);
 
     // final CSR
+    // sized by the raw count (merging only removes entries); the exact count
+    // is read later with other sizes
     g.net_rp.ensure(static_cast<size_t>(N) + 1, s);
-    g.nnz_net = static_cast<int32_t>(scan_i32_checked(ucnt.p, g.net_rp.p, N, g.scan_tmp.p, s));
-    g.net_col.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
-    g.net_q.ensure(static_cast<size_t>(g.nnz_net) + 1, s);
+    scan_i32_to_i32(ucnt.p, g.net_rp.p, N, g.scan_tmp.p, s);
+    g.nnz_net = -1;
+    g.nnz_cap = static_cast<int32_t>(nnz_dup);
+    g.net_col.ensure(static_cast<size_t>(g.nnz_cap) + 1, s);
+    g.net_q.ensure(static_cast<size_t>(g.nnz_cap) + 1, s);
     g.qdeg.ensure(static_cast<size_t>(N) + 1, s);
     hipLaunchKernelGGL(k_compact, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N, cnt.p, rp.p,
                        ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
