@@ -12,7 +12,8 @@ namespace {
 
 constexpr int kBT = 256;
 constexpr int kLanes = 8;           // lanes per small net
-constexpr int kSmallGrid = 2048;    // workgroups of the small-net pass
+constexpr int kSmallGrid = 8192;    // workgroups of the small-net pass (enough nets in flight
+                                    // to hide the two dependent loads of each)
 constexpr int kBigGrid = 256;       // workgroups of the big-net pass
 constexpr int kMaxPairs = 4;
 
@@ -134,12 +135,25 @@ __global__ void __launch_bounds__(kBT) k_hpwl_big(const float* __restrict__ pos,
     }
 }
 
-__global__ void __launch_bounds__(kBT) k_hpwl_final(int npairs, double* __restrict__ out) {
-    __shared__ double red[kBT / kWave];
+// The workgroup partials in a fixed order: thread t adds partials t,
+// t + kFinalBT, ... (all loaded at once), then a fixed block reduction.
+constexpr int kFinalBT = 1024;
+constexpr int kFinalPer = (kSmallGrid + kBigGrid + kFinalBT - 1) / kFinalBT;
+
+__global__ void __launch_bounds__(kFinalBT) k_hpwl_final(int npairs, double* __restrict__ out) {
+    __shared__ double red[kFinalBT / kWave];
+    constexpr int nparts = kSmallGrid + kBigGrid;
     for (int c = 0; c < npairs; ++c) {
+        double v[kFinalPer];
+#pragma unroll
+        for (int u = 0; u < kFinalPer; ++u) {
+            const int b = static_cast<int>(threadIdx.x) + u * kFinalBT;
+            v[u] = g_hpwl_partial[(b < nparts ? b : nparts - 1) * kMaxPairs + c];
+        }
         double s = 0;
-        for (int b = threadIdx.x; b < kSmallGrid + kBigGrid; b += kBT) s += g_hpwl_partial[b * kMaxPairs + c];
-        s = block_sum_f64<kBT>(s, red);
+#pragma unroll
+        for (int u = 0; u < kFinalPer; ++u) s += static_cast<int>(threadIdx.x) + u * kFinalBT < nparts ? v[u] : 0.0;
+        s = block_sum_f64<kFinalBT>(s, red);
         if (threadIdx.x == 0) out[c] = s;
     }
 }
@@ -152,7 +166,7 @@ void hpwl_p(const Graph& g, const float* pos, int32_t ncols, double* out, hipStr
     hipLaunchKernelGGL(k_hpwl_big<P>, dim3(kBigGrid), dim3(kBT), 0, s, pos, ncols, g.nl.net_ptr, g.big_nets.p,
                        g.n_big_nets, g.nl.pin_node, g.nl.pin_off);
     AHR_LAUNCHED("k_hpwl_big");
-    hipLaunchKernelGGL(k_hpwl_final, dim3(1), dim3(kBT), 0, s, P, out);
+    hipLaunchKernelGGL(k_hpwl_final, dim3(1), dim3(kFinalBT), 0, s, P, out);
     AHR_LAUNCHED("k_hpwl_final");
 }
 

@@ -200,8 +200,7 @@ __device__ __forceinline__ int2 exec_entry(int32_t c, int64_t q, const int32_t* 
 __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, const int32_t* __restrict__ perm,
                                                   const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, const int64_t* __restrict__ q,
-                                                  const int32_t* __restrict__ xrp, int2* __restrict__ xent,
-                                                  int64_t spare) {
+                                                  const int32_t* __restrict__ xrp, int2* __restrict__ xent) {
     constexpr int G = 8, U = kShortRow / G;
     __shared__ int32_t cols[kBT / G][kShortRow];
     const int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
@@ -213,10 +212,8 @@ __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, const int32_t* 
         len = xrp[r + 1] - d;
         if (len > kShortRow) len = 0;                      // group-uniform: k_exec_net_long
     }
-    // No branch around any global load or store, so that all of a lane's
-    // loads are in flight together: indexes are clamped to the row's last
-    // entry and slots past the row's end store to the spare entry after the
-    // array's last (never read).
+    // No branch around any global load, so that all of a lane's loads are in
+    // flight together: indexes are clamped to the row's last entry.
     int32_t m[U];
     int2 e[U];
     if (len > 0) {
@@ -240,13 +237,14 @@ __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, const int32_t* 
     }
     __syncthreads();
     if (len == 0) return;
+    // (every load is consumed by now, so a guarded store waits for nothing)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        int rank = 0;
-        if (u * G < len)                                   // group-uniform
+        if (l + u * G < len) {
+            int rank = 0;
             for (int j = 0; j < len; ++j) rank += mine[j] < m[u] ? 1 : 0;
-        const int64_t at = l + u * G < len ? static_cast<int64_t>(d) + rank : spare;
-        xent[at] = e[u];
+            xent[static_cast<int64_t>(d) + rank] = e[u];
+        }
     }
 }
 
@@ -351,8 +349,7 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
     if (g.nnz_cap) {
         hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N,
-                           g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p,
-                           static_cast<int64_t>(g.nnz_cap));
+                           g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
         AHR_LAUNCHED("k_exec_net");
         DevBuf<int32_t> flag, rank, rows;
         flag.ensure(static_cast<size_t>(N) + 1, s);
