@@ -34,8 +34,8 @@ HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("fil
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "sources_sha256": "902cb14840d28169b97dee9bca776a4130180dc01e86be79f063abbc72300034",
-               "bytes_per_launch": 1647021900,
+               "sources_sha256": "ed5e1bccaf611c2fea85d58107d3d0a9f34f0514f354f9b7955a5a4ba734c33e",
+               "bytes_per_launch": 1419401868,
                "source": "profiles/k_hop_large-2.2M_hbm_traffic.md"}
 
 
