@@ -323,6 +323,71 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
 // equal columns.
 constexpr int kLongBT = 1024;
 
+// Merge sort of a long row's keys (unique 64-bit) by one workgroup, for rows
+// of at most kLongBT * kRunMax keys: thread t sorts the E keys from t E on
+// in registers (odd-even transposition, fixed indices), then log2(kLongBT)
+// merge rounds double the sorted runs.  In a round each thread finds where
+// its E outputs start on the merge path of its pair of runs (binary
+// search), merges them into registers, and after a barrier writes them back
+// in place.  Slots past n hold ~0 and sort last.  O(n log n) LDS traffic,
+// against O(n log^2 n) for the bitonic network used for longer rows.
+constexpr int kRunMax = 16;
+
+__device__ void block_merge_sort(const RawEnt* __restrict__ raw, int64_t base, int n, int E, uint64_t* key) {
+    const int t = threadIdx.x;
+    uint64_t v[kRunMax];
+#pragma unroll
+    for (int u = 0; u < kRunMax; ++u) {
+        const int k = t * E + u;
+        const bool ok = u < E && k < n;
+        const int32_t c = raw[base + (ok ? k : 0)].col;          // every load in flight at once
+        v[u] = ok ? (static_cast<uint64_t>(static_cast<uint32_t>(c)) << 32) | static_cast<uint32_t>(k) : ~0ull;
+    }
+#pragma unroll
+    for (int rnd = 0; rnd < kRunMax; ++rnd) {
+#pragma unroll
+        for (int u = rnd & 1; u + 1 < kRunMax; u += 2) {
+            const uint64_t x = v[u], y = v[u + 1];
+            v[u] = y < x ? y : x;
+            v[u + 1] = y < x ? x : y;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kRunMax; ++u)
+        if (u < E) key[t * E + u] = v[u];
+    __syncthreads();
+    const int total = kLongBT * E;
+    for (int w = E; w < total; w <<= 1) {
+        const int d0 = t * E;
+        const int s = d0 / (2 * w) * (2 * w);
+        const uint64_t* A = key + s;
+        const uint64_t* B = key + s + w;
+        const int d = d0 - s;
+        int lo = d > w ? d - w : 0, hi = d < w ? d : w;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (A[mid] <= B[d - mid - 1]) lo = mid + 1;
+            else hi = mid;
+        }
+        int i = lo, j = d - lo;
+#pragma unroll
+        for (int u = 0; u < kRunMax; ++u) {
+            if (u < E) {
+                const uint64_t a = i < w ? A[i] : ~0ull, b = j < w ? B[j] : ~0ull;
+                const bool ta = j >= w || (i < w && a <= b);
+                v[u] = ta ? a : b;
+                i += ta ? 1 : 0;
+                j += ta ? 0 : 1;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kRunMax; ++u)
+            if (u < E) key[t * E + u] = v[u];
+        __syncthreads();
+    }
+}
+
 __global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ cnt,
                                                    const int64_t* __restrict__ rp, const RawEnt* __restrict__ raw,
                                                    uint64_t* __restrict__ tkey,
@@ -334,13 +399,20 @@ __global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict
     int r = rows[blockIdx.x];
     int n = cnt[r];
     int64_t base = rp[r];
+    const int E = (n + kLongBT - 1) / kLongBT;
+    const bool merge = E <= kRunMax && kLongBT * E <= lds_keys;      // block-uniform
     int P = 1;
     while (P < n) P <<= 1;
-    uint64_t* key = P <= lds_keys ? lkey : tkey + base;
-    for (int k = threadIdx.x; k < n; k += kLongBT)
-        key[k] = (static_cast<uint64_t>(static_cast<uint32_t>(raw[base + k].col)) << 32) | static_cast<uint32_t>(k);
-    __threadfence_block();
-    __syncthreads();
+    uint64_t* key = merge || P <= lds_keys ? lkey : tkey + base;
+    if (merge) {
+        block_merge_sort(raw, base, n, E, key);
+        P = 0;                                                     // skips the network below
+    } else {
+        for (int k = threadIdx.x; k < n; k += kLongBT)
+            key[k] = (static_cast<uint64_t>(static_cast<uint32_t>(raw[base + k].col)) << 32) | static_cast<uint32_t>(k);
+        __threadfence_block();
+        __syncthreads();
+    }
     for (int size = 2; size <= P; size <<= 1) {
         int half = size >> 1;
         // first comparator layer of a merge: mirror pairs
