@@ -190,9 +190,13 @@ struct Graph {
     DevBuf<int32_t> mpin_pin;     // [n_mpin]
     DevBuf<int32_t> star_net;     // [n_star]
     DevBuf<int32_t> macro_ids;    // [n_macro] instance id of each macro (instance order)
-    DevBuf<int32_t> net_rp;       // [n_tot+1]
-    DevBuf<int32_t> net_col;      // [nnz_net]
-    DevBuf<int64_t> net_q;        // [nnz_net]
+    // merged netlist rows in node order, in place: row r holds net_len[r]
+    // entries from slot net_off[r] (columns ascending); slots up to the next
+    // row's offset are unused (parallel edges merged away)
+    DevBuf<int64_t> net_off;      // [n_tot+1]
+    DevBuf<int32_t> net_len;      // [n_tot]
+    DevBuf<int32_t> net_col;      // [nnz_cap]
+    DevBuf<int64_t> net_q;        // [nnz_cap]
     DevBuf<int64_t> qdeg;         // [n_tot]
     DevBuf<double> base_w;        // [n_inst] baseWeight
     DevBuf<int32_t> big_nets;     // nets with more than a wave's worth of pins (HPWL)

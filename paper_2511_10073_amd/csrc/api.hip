@@ -11,7 +11,18 @@ extern int g_hop_lanes;
 extern int g_hop_nt;
 
 int32_t net_count(const Graph& g, hipStream_t s) {
-    if (g.nnz_net < 0) g.nnz_net = read_i32(g.net_rp.p + g.n_tot, s);
+    if (g.nnz_net >= 0) return g.nnz_net;
+    if (g.has_layout) {
+        g.nnz_net = read_i32(g.xnet_rp.p + g.n_tot, s);
+    } else {       // before any placement: add up the merged row lengths
+        DevBuf<int32_t> pre;
+        DevBuf<int64_t> tmp;
+        pre.ensure(static_cast<size_t>(g.n_tot) + 1, s);
+        tmp.ensure(scan_tmp_elems(g.n_tot), s);
+        g.nnz_net = static_cast<int32_t>(scan_i32_checked(g.net_len.p, pre.p, g.n_tot, tmp.p, s));
+        pre.release(s);
+        tmp.release(s);
+    }
     return g.nnz_net;
 }
 
@@ -24,12 +35,13 @@ Graph::~Graph() {
     // one stream: its later work (and any other stream, through the block
     // events) reuses the memory only after this graph's work; else wait
     hipStream_t s = stream_uses == 1 ? work_stream : nullptr;
-    DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_rp, &net_col,
+    DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_len, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
                               &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart,
                               &big_stars, &i32a, &i32b, &counter};
     for (auto* b : i32) b->release(s);
     net_q.release(s);
+    net_off.release(s);
     perm.release(s);
     iperm.release(s);
     xmpin.release(s);
@@ -229,10 +241,32 @@ ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* strea
         auto cp = [&](void* d, const void* src, size_t bytes) {
             if (d && bytes) AHR_HIP(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToHost, s));
         };
-        cp(dst->net_row_ptr, g->net_rp.p, (N + 1) * sizeof(int32_t));
-        const size_t nnz_net = static_cast<size_t>(ahr::net_count(*g, s));
-        cp(dst->net_col, g->net_col.p, nnz_net * sizeof(int32_t));
-        cp(dst->net_q, g->net_q.p, nnz_net * sizeof(int64_t));
+        if (dst->net_row_ptr || dst->net_col || dst->net_q) {
+            // the merged rows sit in place on the device: pack them
+            std::vector<int64_t> off(N + 1);
+            std::vector<int32_t> len(N + 1);
+            AHR_HIP(hipMemcpyAsync(off.data(), g->net_off.p, (N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipMemcpyAsync(len.data(), g->net_len.p, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            AHR_HIP(hipStreamSynchronize(s));
+            std::vector<int32_t> rp(N + 1, 0);
+            for (size_t r = 0; r < N; ++r) rp[r + 1] = rp[r] + len[r];
+            if (dst->net_row_ptr) std::memcpy(dst->net_row_ptr, rp.data(), (N + 1) * sizeof(int32_t));
+            const size_t cap = static_cast<size_t>(off[N]);
+            if (dst->net_col && cap) {
+                std::vector<int32_t> col(cap);
+                AHR_HIP(hipMemcpyAsync(col.data(), g->net_col.p, cap * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                AHR_HIP(hipStreamSynchronize(s));
+                for (size_t r = 0; r < N; ++r)
+                    std::memcpy(dst->net_col + rp[r], col.data() + off[r], static_cast<size_t>(len[r]) * sizeof(int32_t));
+            }
+            if (dst->net_q && cap) {
+                std::vector<int64_t> q(cap);
+                AHR_HIP(hipMemcpyAsync(q.data(), g->net_q.p, cap * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+                AHR_HIP(hipStreamSynchronize(s));
+                for (size_t r = 0; r < N; ++r)
+                    std::memcpy(dst->net_q + rp[r], q.data() + off[r], static_cast<size_t>(len[r]) * sizeof(int64_t));
+            }
+        }
         if (g->has_hints && (dst->hint_row_ptr || dst->hint_col || dst->hint_val)) {
             // hint rows live in execution order: return them in node order
             const size_t np = static_cast<size_t>(g->first_mvirt);     // rows the layout permutes

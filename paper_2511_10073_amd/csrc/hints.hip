@@ -709,7 +709,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     // (the netlist entry count rides along: the build sizes its arrays by a
     // bound and leaves the exact count to this read)
     int32_t tot[3];
-    read_scalars({g.pair_off.p + n_inst, g.bin_start.p + nbins, g.net_rp.p + N}, tot, s);
+    read_scalars({g.pair_off.p + n_inst, g.bin_start.p + nbins, g.xnet_rp.p + N}, tot, s);
     const int32_t n_pairs = tot[0];
     g.n_hint_cells = tot[1];
     g.nnz_net = tot[2];

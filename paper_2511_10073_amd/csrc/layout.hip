@@ -126,7 +126,7 @@ __global__ void k_compose(int32_t n, const int32_t* __restrict__ first, const in
 constexpr int kLenWindow = 64;
 
 __global__ void __launch_bounds__(kLenWindow) k_window_sort(int32_t n, const int32_t* __restrict__ in,
-                                                            const int32_t* __restrict__ net_rp,
+                                                            const int32_t* __restrict__ net_len,
                                                             int32_t* __restrict__ out) {
     __shared__ int32_t wlen[kLenWindow];
     const int t = threadIdx.x;
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(kLenWindow) k_window_sort(int32_t n, const int
     int32_t id = 0, len = INT32_MAX;                 // positions past n sort last and are not written
     if (j < n) {
         id = in[j];
-        len = net_rp[id + 1] - net_rp[id];
+        len = net_len[id];
     }
     wlen[t] = len;
     __syncthreads();
@@ -177,11 +177,10 @@ __global__ void k_iperm(int32_t* __restrict__ perm, int32_t n_perm, int32_t n_to
 
 
 __global__ void k_exec_lens(int32_t n_tot, const int32_t* __restrict__ perm,
-                            const int32_t* __restrict__ rp, int32_t* __restrict__ len) {
+                            const int32_t* __restrict__ net_len, int32_t* __restrict__ len) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n_tot) return;
-    int s = perm[r];
-    len[r] = rp[s + 1] - rp[s];
+    len[r] = net_len[perm[r]];
 }
 
 // Execution-order netlist rows: each row copies its canonical row's
@@ -198,7 +197,7 @@ __device__ __forceinline__ int2 exec_entry(int32_t c, int64_t q, const int32_t* 
 }
 
 __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, const int32_t* __restrict__ perm,
-                                                  const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ iperm, const int64_t* __restrict__ off,
                                                   const int32_t* __restrict__ col, const int64_t* __restrict__ q,
                                                   const int32_t* __restrict__ xrp, int2* __restrict__ xent) {
     constexpr int G = 8, U = kShortRow / G;
@@ -217,7 +216,7 @@ __global__ void __launch_bounds__(kBT) k_exec_net(int32_t n_tot, const int32_t* 
     int32_t m[U];
     int2 e[U];
     if (len > 0) {
-        const int a = rp[perm[r]];
+        const int64_t a = off[perm[r]];
         int32_t c[U];
         int64_t w[U];
 #pragma unroll
@@ -256,14 +255,14 @@ __global__ void __launch_bounds__(kBT) k_exec_net_long(const int32_t* __restrict
                                                        const int32_t* __restrict__ n_long,
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ iperm,
-                                                       const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                       const int64_t* __restrict__ off, const int32_t* __restrict__ col,
                                                        const int64_t* __restrict__ q, const int32_t* __restrict__ xrp,
                                                        int2* __restrict__ xent) {
     const int nl = *n_long;
     for (int li = blockIdx.x; li < nl; li += gridDim.x) {
         const int r = rows[li];
         const int d = xrp[r], len = xrp[r + 1] - d;
-        const int a = rp[perm[r]];
+        const int64_t a = off[perm[r]];
         for (int k = threadIdx.x; k < len; k += kBT) xent[d + k] = exec_entry(col[a + k], q[a + k], iperm);
     }
 }
@@ -316,7 +315,7 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     hipLaunchKernelGGL(k_compose, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, first.p, second.p, key.p);
     AHR_LAUNCHED("k_compose");
     // instance windows by row length; macro pins and stars as sorted
-    hipLaunchKernelGGL(k_window_sort, dim3(grid_for(n, kLenWindow)), dim3(kLenWindow), 0, s, n, key.p, g.net_rp.p,
+    hipLaunchKernelGGL(k_window_sort, dim3(grid_for(n, kLenWindow)), dim3(kLenWindow), 0, s, n, key.p, g.net_len.p,
                        g.perm.p);
     AHR_LAUNCHED("k_window_sort");
     if (np > n)
@@ -339,7 +338,7 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
 
     DevBuf<int32_t> len;
     len.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_exec_lens, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.perm.p, g.net_rp.p, len.p);
+    hipLaunchKernelGGL(k_exec_lens, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.perm.p, g.net_len.p, len.p);
     AHR_LAUNCHED("k_exec_lens");
     g.xnet_rp.ensure(static_cast<size_t>(N) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(N), s);
@@ -349,7 +348,7 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
     if (g.nnz_cap) {
         hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N,
-                           g.perm.p, g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
+                           g.perm.p, g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
         AHR_LAUNCHED("k_exec_net");
         DevBuf<int32_t> flag, rank, rows;
         flag.ensure(static_cast<size_t>(N) + 1, s);
@@ -360,7 +359,7 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         rows.ensure(static_cast<size_t>(N) + 1, s);
         list_rows(flag.p, rank.p, N, rows.p, s);
         hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s, rows.p, rank.p + N, g.perm.p,
-                           g.iperm.p, g.net_rp.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
+                           g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
         AHR_LAUNCHED("k_exec_net_long");
         flag.release(s);
         rank.release(s);

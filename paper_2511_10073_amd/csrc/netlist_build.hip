@@ -234,17 +234,20 @@ __global__ void k_class_keys(const int32_t* __restrict__ cnt, int32_t n, int32_t
 __global__ void k_sort_trivial(const int32_t* __restrict__ rows, int32_t nrows, const int32_t* __restrict__ cnt,
                                const int64_t* __restrict__ rp, const RawEnt* __restrict__ raw,
                                int32_t* __restrict__ scol, int64_t* __restrict__ sq,
-                               int32_t* __restrict__ ucnt) {
+                               int32_t* __restrict__ ucnt, int64_t* __restrict__ qdeg) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= nrows) return;
     int r = rows[i];
     int c = cnt[r];
     ucnt[r] = c;
+    int64_t q = 0;
     if (c == 1) {
         const RawEnt e = raw[rp[r]];
         scol[rp[r]] = e.col;
         sq[rp[r]] = e.q;
+        q = e.q;
     }
+    qdeg[r] = q;
 }
 
 // G lanes per row (G = 16, 32 or 64): bitonic sort by column across the lanes,
@@ -254,7 +257,7 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ cnt, const int64_t* __restrict__ rp,
                                                     const RawEnt* __restrict__ raw,
                                                     int32_t* __restrict__ scol, int64_t* __restrict__ sq,
-                                                    int32_t* __restrict__ ucnt) {
+                                                    int32_t* __restrict__ ucnt, int64_t* __restrict__ qdeg) {
     int64_t gid = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
     int l = threadIdx.x & (G - 1);
     int lane = lane_id();
@@ -312,6 +315,7 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
         sq[base + idx] = sum;
     }
     if (valid_row && l == 0) ucnt[r] = __popcll(hm & gm);
+    if (valid_row && l == G - 1) qdeg[r] = pre;      // the inclusive scan's last lane: the row's weight sum
 }
 
 // One workgroup of kLongBT threads per long row (star rows reach 10^4
@@ -392,10 +396,12 @@ __global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict
                                                    const int64_t* __restrict__ rp, const RawEnt* __restrict__ raw,
                                                    uint64_t* __restrict__ tkey,
                                                    int32_t* __restrict__ scol, int64_t* __restrict__ sq,
-                                                   int32_t* __restrict__ ucnt, int lds_keys) {
+                                                   int32_t* __restrict__ ucnt, int64_t* __restrict__ qdeg,
+                                                   int lds_keys) {
     extern __shared__ uint64_t lkey[];
     __shared__ int red[kLongBT / kWave];
     __shared__ int carry;
+    __shared__ unsigned long long qtot;      // the row's weight sum (exact: integer adds)
     int r = rows[blockIdx.x];
     int n = cnt[r];
     int64_t base = rp[r];
@@ -440,7 +446,10 @@ __global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict
             __syncthreads();
         }
     }
-    if (threadIdx.x == 0) carry = 0;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        qtot = 0;
+    }
     __syncthreads();
     for (int t0 = 0; t0 < n; t0 += kLongBT) {
         int k = t0 + threadIdx.x;
@@ -458,76 +467,23 @@ __global__ void __launch_bounds__(kLongBT) k_sort_long(const int32_t* __restrict
                 s += raw[base + static_cast<uint32_t>(key[m] & 0xffffffffu)].q;
             scol[base + carry + idx] = static_cast<int32_t>(col);
             sq[base + carry + idx] = s;
+            atomicAdd(&qtot, static_cast<unsigned long long>(s));
         }
         __syncthreads();
         if (threadIdx.x == 0) carry += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) ucnt[r] = carry;
-}
-
-// Copy merged rows to their final place, with the row weight sums: G
-// lanes per row for rows of at most kShortRaw raw entries, one workgroup
-// per longer row (k_compact_long).
-constexpr int kShortRaw = 64;
-
-__global__ void __launch_bounds__(kBT) k_compact(int32_t n_rows, const int32_t* __restrict__ cnt,
-                                                 const int64_t* __restrict__ rp, const int32_t* __restrict__ ucnt,
-                                                 const int32_t* __restrict__ net_rp, const int32_t* __restrict__ scol,
-                                                 const int64_t* __restrict__ sq, int32_t* __restrict__ col,
-                                                 int64_t* __restrict__ qv, int64_t* __restrict__ qdeg) {
-    constexpr int G = 8;
-    int64_t r = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
-    int l = threadIdx.x & (G - 1);
-    if (r >= n_rows || cnt[r] > kShortRaw) return;     // group-uniform
-    int n = ucnt[r];
-    int64_t src = rp[r];
-    int64_t dst = net_rp[r];
-    int64_t s = 0;
-    for (int k = l; k < n; k += G) {
-        int c = scol[src + k];
-        int64_t q = sq[src + k];
-        col[dst + k] = c;
-        qv[dst + k] = q;
-        s += q;
-    }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (l == 0) qdeg[r] = s;
-}
-
-__global__ void __launch_bounds__(kBT) k_compact_long(const int32_t* __restrict__ rows,
-                                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ ucnt,
-                                                      const int32_t* __restrict__ net_rp,
-                                                      const int32_t* __restrict__ scol, const int64_t* __restrict__ sq,
-                                                      int32_t* __restrict__ col, int64_t* __restrict__ qv,
-                                                      int64_t* __restrict__ qdeg) {
-    __shared__ int64_t red[kBT / kWave];
-    const int r = rows[blockIdx.x];
-    const int n = ucnt[r];
-    const int64_t src = rp[r], dst = net_rp[r];
-    int64_t s = 0;
-    for (int k = threadIdx.x; k < n; k += kBT) {
-        int64_t q = sq[src + k];
-        col[dst + k] = scol[src + k];
-        qv[dst + k] = q;
-        s += q;
-    }
-    s = wave_sum(s);
-    if (lane_id() == 0) red[wave_id()] = s;
-    __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int w = 0; w < kBT / kWave; ++w) t += red[w];
-        qdeg[r] = t;
+        ucnt[r] = carry;
+        qdeg[r] = static_cast<int64_t>(qtot);
     }
 }
 
-__global__ void k_base_weight(int32_t n_inst, const int32_t* __restrict__ net_rp, const int64_t* __restrict__ qdeg,
+__global__ void k_base_weight(int32_t n_inst, const int32_t* __restrict__ net_len, const int64_t* __restrict__ qdeg,
                               double* __restrict__ bw) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n_inst) return;
-    int nnz = net_rp[i + 1] - net_rp[i];
+    int nnz = net_len[i];
     int64_t q = qdeg[i];
     bw[i] = (nnz > 0 && q != 0) ? (static_cast<double>(q) * 0x1p-32) / static_cast<double>(nnz) : 0.0;
 }
@@ -673,7 +629,9 @@ void build_netlist(Graph& g, hipStream_t s) {
     if (n_pins)
         hipLaunchKernelGGL(k_row_counts, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, cnt.p);
     AHR_LAUNCHED("k_row_counts");
-    DevBuf<int64_t> rp;
+    // the rows stay where the raw entries put them: net_off[r] is row r's
+    // first slot, net_len[r] its merged entry count (set by the sorts)
+    DevBuf<int64_t>& rp = g.net_off;
     rp.ensure(static_cast<size_t>(N) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i64(cnt.p, rp.p, N, g.scan_tmp.p, s);
@@ -700,9 +658,11 @@ void build_netlist(Graph& g, hipStream_t s) {
         cls[k] = lists.p + w[1 + k];
     }
 
-    DevBuf<int32_t> cursor, scol, ucnt;
+    DevBuf<int32_t> cursor;
+    DevBuf<int32_t>& scol = g.net_col;
+    DevBuf<int32_t>& ucnt = g.net_len;
     DevBuf<RawEnt> raw;
-    DevBuf<int64_t> sq;
+    DevBuf<int64_t>& sq = g.net_q;
     cursor.ensure(static_cast<size_t>(N) + 1, s);
     fill_i32(cursor.p, N + 1, 0, s);
     raw.ensure(static_cast<size_t>(nnz_dup) + 1, s);
@@ -719,65 +679,46 @@ void build_netlist(Graph& g, hipStream_t s) {
     sq.ensure(static_cast<size_t>(nnz_dup) + 1, s);
     ucnt.ensure(static_cast<size_t>(N) + 1, s);
     fill_i32(ucnt.p, N + 1, 0, s);
+    g.qdeg.ensure(static_cast<size_t>(N) + 1, s);
     if (ncls[0])
         hipLaunchKernelGGL(k_sort_trivial, dim3(grid_for(ncls[0], kBT)), dim3(kBT), 0, s, cls[0], ncls[0], cnt.p,
-                           rp.p, raw.p, scol.p, sq.p, ucnt.p);
+                           rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_trivial");
     if (ncls[1])
         hipLaunchKernelGGL(k_sort_group<16>, dim3(grid_for(static_cast<int64_t>(ncls[1]) * 16, kBT)), dim3(kBT), 0, s,
-                           cls[1], ncls[1], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p);
+                           cls[1], ncls[1], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_group16");
     if (ncls[2])
         hipLaunchKernelGGL(k_sort_group<32>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 32, kBT)), dim3(kBT), 0, s,
-                           cls[2], ncls[2], cnt.p, rp.p, raw.p, scol.p, sq.p,
-                           ucnt.p);
+                           cls[2], ncls[2], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_group32");
     if (ncls[3])
         hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[3]) * 64, kBT)), dim3(kBT), 0, s,
-                           cls[3], ncls[3], cnt.p, rp.p, raw.p, scol.p, sq.p,
-                           ucnt.p);
+                           cls[3], ncls[3], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_group64");
     if (ncls[4]) {
         DevBuf<uint64_t> tkey;
         tkey.ensure(static_cast<size_t>(nnz_dup) + 1, s);
         const int lds_keys = sort_lds_keys(g.device);
         hipLaunchKernelGGL(k_sort_long, dim3(ncls[4]), dim3(kLongBT), static_cast<size_t>(lds_keys) * sizeof(uint64_t), s,
-                           cls[4], cnt.p, rp.p, raw.p, tkey.p, scol.p, sq.p,
-                           ucnt.p, lds_keys);
+                           cls[4], cnt.p, rp.p, raw.p, tkey.p, scol.p, sq.p, ucnt.p, g.qdeg.p, lds_keys);
         AHR_LAUNCHED("k_sort_long");
         tkey.release(s);
     }
     raw.release(s);
 
-    // final CSR
-    // sized by the raw count (merging only removes entries); the exact count
-    // is read later with other sizes
-    g.net_rp.ensure(static_cast<size_t>(N) + 1, s);
-    scan_i32_to_i32(ucnt.p, g.net_rp.p, N, g.scan_tmp.p, s);
+    // The merged rows stay in place (no compaction): slots past a row's
+    // merged count are unused.  The arrays hold the raw count; the exact
+    // entry count is read later with other sizes.
     g.nnz_net = -1;
     g.nnz_cap = static_cast<int32_t>(nnz_dup);
-    g.net_col.ensure(static_cast<size_t>(g.nnz_cap) + 1, s);
-    g.net_q.ensure(static_cast<size_t>(g.nnz_cap) + 1, s);
-    g.qdeg.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N, cnt.p, rp.p,
-                       ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
-    AHR_LAUNCHED("k_compact");
-    if (ncls[4]) {
-        hipLaunchKernelGGL(k_compact_long, dim3(ncls[4]), dim3(kBT), 0, s, cls[4], rp.p,
-                           ucnt.p, g.net_rp.p, scol.p, sq.p, g.net_col.p, g.net_q.p, g.qdeg.p);
-        AHR_LAUNCHED("k_compact_long");
-    }
     lists.release(s);
     cstart.release(s);
     g.base_w.ensure(static_cast<size_t>(n_inst) + 1, s);
-    hipLaunchKernelGGL(k_base_weight, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.net_rp.p, g.qdeg.p,
+    hipLaunchKernelGGL(k_base_weight, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.net_len.p, g.qdeg.p,
                        g.base_w.p);
     AHR_LAUNCHED("k_base_weight");
-    scol.release(s);
-    sq.release(s);
-    ucnt.release(s);
     cnt.release(s);
-    rp.release(s);
 }
 
 }  // namespace ahr
