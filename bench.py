@@ -34,8 +34,8 @@ HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("fil
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "sources_sha256": "ed5e1bccaf611c2fea85d58107d3d0a9f34f0514f354f9b7955a5a4ba734c33e",
-               "bytes_per_launch": 1419401868,
+               "sources_sha256": "dfb7e9176709926fa80cba9b8fd5b62aac7ccf73e70555d8b9bfd6de16d049fe",
+               "bytes_per_launch": 1419305098,
                "source": "profiles/k_hop_large-2.2M_hbm_traffic.md"}
 
 
