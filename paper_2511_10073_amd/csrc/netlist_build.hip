@@ -155,8 +155,12 @@ __device__ __forceinline__ int clique_nodes(const int32_t* __restrict__ pin_x, i
     return c;
 }
 
-// Entries each row receives (parallel edges counted separately).
-__global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt) {
+// Entries each row receives (parallel edges counted separately).  Each pin
+// reserves its run of its row's slots here, with the atomic that counts it:
+// slot[p] = where the run starts inside the row (the run order inside a row
+// does not matter: rows are sorted by column and equal columns merged by
+// exact integer sums afterwards).
+__global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt, int32_t* __restrict__ slot) {
     int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_pins) return;
     int e = a.pin_net[p];
@@ -167,17 +171,16 @@ __global__ void k_row_counts(NetArgs a, int32_t* __restrict__ cnt) {
     if (deg <= a.clique_max) {
         int node[kNetUnroll];
         const int c = clique_nodes(a.pin_x, lo, hi, v, node);
-        if (c) atomicAdd(&cnt[v], c);
+        if (c) slot[p] = atomicAdd(&cnt[v], c);
     } else {
-        atomicAdd(&cnt[v], 1);
+        slot[p] = atomicAdd(&cnt[v], 1);
         if (p == lo) cnt[a.first_star + a.star_rank[e]] = deg;
     }
 }
 
-// Raw entries: each pin reserves its whole run of its row's slots with one
-// atomic (the run order inside a row does not matter: rows are sorted by
-// column and equal columns merged by exact integer sums afterwards).
-__global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __restrict__ cursor,
+// Raw entries: each pin writes its run at the slots it reserved while the
+// rows were counted.
+__global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, const int32_t* __restrict__ slot,
                           RawEnt* __restrict__ raw) {
     int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_pins) return;
@@ -192,7 +195,7 @@ __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __
         int node[kNetUnroll];
         const int c = clique_nodes(a.pin_x, lo, hi, v, node);
         if (!c) return;
-        int64_t k = rp[v] + atomicAdd(&cursor[v], c);
+        int64_t k = rp[v] + slot[p];
         if (deg <= kNetUnroll) {
 #pragma unroll
             for (int u = 0; u < kNetUnroll; ++u)
@@ -211,7 +214,7 @@ __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, int32_t* __
     } else {
         int64_t q = q_star(w, deg);
         int z = a.first_star + a.star_rank[e];
-        int64_t k = rp[v] + atomicAdd(&cursor[v], 1);
+        int64_t k = rp[v] + slot[p];
         raw[k] = raw_ent(z, q);
         int64_t kz = rp[z] + (p - lo);
         raw[kz] = raw_ent(v, q);
@@ -623,11 +626,12 @@ void build_netlist(Graph& g, hipStream_t s) {
     }
     NetArgs a{nl.net_ptr, pin_net.p, g.pin_node_x.p, nl.net_w, star_rank.p, n_nets, n_pins, hp.clique_max,
               g.first_star};
-    DevBuf<int32_t> cnt;
+    DevBuf<int32_t> cnt, slot;
     cnt.ensure(static_cast<size_t>(N) + 1, s);
     fill_i32(cnt.p, N + 1, 0, s);
+    slot.ensure(static_cast<size_t>(n_pins) + 1, s);
     if (n_pins)
-        hipLaunchKernelGGL(k_row_counts, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, cnt.p);
+        hipLaunchKernelGGL(k_row_counts, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, cnt.p, slot.p);
     AHR_LAUNCHED("k_row_counts");
     // the rows stay where the raw entries put them: net_off[r] is row r's
     // first slot, net_len[r] its merged entry count (set by the sorts)
@@ -658,18 +662,15 @@ void build_netlist(Graph& g, hipStream_t s) {
         cls[k] = lists.p + w[1 + k];
     }
 
-    DevBuf<int32_t> cursor;
     DevBuf<int32_t>& scol = g.net_col;
     DevBuf<int32_t>& ucnt = g.net_len;
     DevBuf<RawEnt> raw;
     DevBuf<int64_t>& sq = g.net_q;
-    cursor.ensure(static_cast<size_t>(N) + 1, s);
-    fill_i32(cursor.p, N + 1, 0, s);
     raw.ensure(static_cast<size_t>(nnz_dup) + 1, s);
     if (n_pins)
-        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, rp.p, cursor.p, raw.p);
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pins, kBT)), dim3(kBT), 0, s, a, rp.p, slot.p, raw.p);
     AHR_LAUNCHED("k_scatter");
-    cursor.release(s);
+    slot.release(s);
     pin_net.release(s);
     is_star.release(s);
     star_rank.release(s);
