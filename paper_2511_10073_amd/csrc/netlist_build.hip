@@ -221,11 +221,12 @@ __global__ void k_scatter(NetArgs a, const int64_t* __restrict__ rp, const int32
     }
 }
 
-// Row classes by entry count: 0 (<= 1), 1 (<= 16), 2 (<= 32), 3 (<= 64),
-// 4 (longer); classes 1-3 are sorted by 16, 32 and 64 lanes per row.
-constexpr int kSortClasses = 5;
+// Row classes by entry count: 0 (<= 1), 1 (<= 8), 2 (<= 16), 3 (<= 32),
+// 4 (<= 64), 5 (longer); classes 1-4 are sorted by 8, 16, 32 and 64 lanes
+// per row.
+constexpr int kSortClasses = 6;
 __device__ __forceinline__ int row_class(int c) {
-    return c <= 1 ? 0 : (c <= 16 ? 1 : (c <= 32 ? 2 : (c <= 64 ? 3 : 4)));
+    return c <= 1 ? 0 : (c <= 8 ? 1 : (c <= 16 ? 2 : (c <= 32 ? 3 : (c <= 64 ? 4 : 5))));
 }
 
 __global__ void k_class_keys(const int32_t* __restrict__ cnt, int32_t n, int32_t* __restrict__ key) {
@@ -253,7 +254,7 @@ __global__ void k_sort_trivial(const int32_t* __restrict__ rows, int32_t nrows, 
     qdeg[r] = q;
 }
 
-// G lanes per row (G = 16, 32 or 64): bitonic sort by column across the lanes,
+// G lanes per row (G = 8, 16, 32 or 64): bitonic sort by column across the lanes,
 // then merge equal columns by exact integer sums.
 template <int G>
 __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ rows, int32_t nrows,
@@ -650,9 +651,9 @@ void build_netlist(Graph& g, hipStream_t s) {
     ckey.release(s);
     int64_t w[K + 2];
     read_words({{rp.p + N, 1}, {cstart.p, 0}, {cstart.p + 1, 0}, {cstart.p + 2, 0}, {cstart.p + 3, 0},
-                {cstart.p + 4, 0}, {cstart.p + 5, 0}},
+                {cstart.p + 4, 0}, {cstart.p + 5, 0}, {cstart.p + 6, 0}},
                w, s);
-    static_assert(K == 5, "class starts read above");
+    static_assert(K == 6, "class starts read above");
     const int64_t nnz_dup = w[0];
     if (nnz_dup >= INT32_MAX) throw Error{AHR_EUNSUPPORTED, "netlist expands to 2^31 or more graph entries"};
     int32_t ncls[K];
@@ -686,23 +687,27 @@ void build_netlist(Graph& g, hipStream_t s) {
                            rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_trivial");
     if (ncls[1])
-        hipLaunchKernelGGL(k_sort_group<16>, dim3(grid_for(static_cast<int64_t>(ncls[1]) * 16, kBT)), dim3(kBT), 0, s,
+        hipLaunchKernelGGL(k_sort_group<8>, dim3(grid_for(static_cast<int64_t>(ncls[1]) * 8, kBT)), dim3(kBT), 0, s,
                            cls[1], ncls[1], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
-    AHR_LAUNCHED("k_sort_group16");
+    AHR_LAUNCHED("k_sort_group8");
     if (ncls[2])
-        hipLaunchKernelGGL(k_sort_group<32>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 32, kBT)), dim3(kBT), 0, s,
+        hipLaunchKernelGGL(k_sort_group<16>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 16, kBT)), dim3(kBT), 0, s,
                            cls[2], ncls[2], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
-    AHR_LAUNCHED("k_sort_group32");
+    AHR_LAUNCHED("k_sort_group16");
     if (ncls[3])
-        hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[3]) * 64, kBT)), dim3(kBT), 0, s,
+        hipLaunchKernelGGL(k_sort_group<32>, dim3(grid_for(static_cast<int64_t>(ncls[3]) * 32, kBT)), dim3(kBT), 0, s,
                            cls[3], ncls[3], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
+    AHR_LAUNCHED("k_sort_group32");
+    if (ncls[4])
+        hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[4]) * 64, kBT)), dim3(kBT), 0, s,
+                           cls[4], ncls[4], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_group64");
-    if (ncls[4]) {
+    if (ncls[5]) {
         DevBuf<uint64_t> tkey;
         tkey.ensure(static_cast<size_t>(nnz_dup) + 1, s);
         const int lds_keys = sort_lds_keys(g.device);
-        hipLaunchKernelGGL(k_sort_long, dim3(ncls[4]), dim3(kLongBT), static_cast<size_t>(lds_keys) * sizeof(uint64_t), s,
-                           cls[4], cnt.p, rp.p, raw.p, tkey.p, scol.p, sq.p, ucnt.p, g.qdeg.p, lds_keys);
+        hipLaunchKernelGGL(k_sort_long, dim3(ncls[5]), dim3(kLongBT), static_cast<size_t>(lds_keys) * sizeof(uint64_t), s,
+                           cls[5], cnt.p, rp.p, raw.p, tkey.p, scol.p, sq.p, ucnt.p, g.qdeg.p, lds_keys);
         AHR_LAUNCHED("k_sort_long");
         tkey.release(s);
     }
