@@ -146,23 +146,6 @@ __global__ void __launch_bounds__(kLenWindow) k_window_sort(int32_t n, const int
     if (j < n) out[static_cast<int64_t>(blockIdx.x) * kLenWindow + rank] = id;
 }
 
-// What the expansion reads for the macro pin and star rows, in execution
-// order: a macro pin row's owner instance and pin offset, a star row's net.
-__global__ void k_exec_aux(int32_t n_inst, int32_t first_star, int32_t first_mvirt, const int32_t* __restrict__ perm,
-                           const int32_t* __restrict__ mpin_pin, const int32_t* __restrict__ pin_node,
-                           const float* __restrict__ pin_off, const int32_t* __restrict__ star_net,
-                           int4* __restrict__ xmpin, int32_t* __restrict__ xstar_net) {
-    const int64_t r = n_inst + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= first_mvirt) return;
-    const int v = perm[r];
-    if (r < first_star) {
-        const int p = mpin_pin[v - n_inst];
-        xmpin[r - n_inst] = make_int4(pin_node[p], __float_as_int(pin_off[2 * p]), __float_as_int(pin_off[2 * p + 1]), 0);
-    } else {
-        xstar_net[r - first_star] = star_net[v - first_star];
-    }
-}
-
 // Both directions over all n_tot rows: the virtual rows (from n_perm on)
 // map to themselves.
 __global__ void k_iperm(int32_t* __restrict__ perm, int32_t n_perm, int32_t n_tot, int32_t* __restrict__ iperm) {
@@ -176,11 +159,37 @@ __global__ void k_iperm(int32_t* __restrict__ perm, int32_t n_perm, int32_t n_to
 }
 
 
-__global__ void k_exec_lens(int32_t n_tot, const int32_t* __restrict__ perm,
-                            const int32_t* __restrict__ net_len, int32_t* __restrict__ len) {
-    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n_tot) return;
-    len[r] = net_len[perm[r]];
+// Per execution row, from its node: the netlist row length, the row weight
+// sum, and for the macro pin and star rows what the expansion reads (a
+// macro pin's owner instance and pin offset, a star's net).
+struct ExecRowArgs {
+    int32_t n_tot, n_inst, first_star, first_mvirt;
+    const int32_t* perm;
+    const int32_t* net_len;
+    const int64_t* qdeg;
+    const int32_t* mpin_pin;
+    const int32_t* pin_node;
+    const float* pin_off;
+    const int32_t* star_net;
+    int32_t* len;
+    int64_t* xqdeg;
+    int4* xmpin;
+    int32_t* xstar_net;
+};
+
+__global__ void k_exec_rows(ExecRowArgs a) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= a.n_tot) return;
+    const int v = a.perm[r];
+    a.len[r] = a.net_len[v];
+    a.xqdeg[r] = a.qdeg[v];
+    if (r >= a.n_inst && r < a.first_star) {
+        const int p = a.mpin_pin[v - a.n_inst];
+        a.xmpin[r - a.n_inst] =
+            make_int4(a.pin_node[p], __float_as_int(a.pin_off[2 * p]), __float_as_int(a.pin_off[2 * p + 1]), 0);
+    } else if (r >= a.first_star && r < a.first_mvirt) {
+        a.xstar_net[r - a.first_star] = a.star_net[v - a.first_star];
+    }
 }
 
 // Execution-order netlist rows: each row copies its canonical row's
@@ -272,11 +281,6 @@ __global__ void k_long_flags(int32_t n_tot, const int32_t* __restrict__ xrp, int
     if (r < n_tot) flag[r] = (xrp[r + 1] - xrp[r] > kShortRow) ? 1 : 0;
 }
 
-__global__ void k_exec_qdeg(int32_t n_tot, const int32_t* __restrict__ perm,
-                            const int64_t* __restrict__ qdeg, int64_t* __restrict__ xqdeg) {
-    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r < n_tot) xqdeg[r] = qdeg[perm[r]];
-}
 
 }  // namespace
 
@@ -328,24 +332,21 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.iperm.ensure(static_cast<size_t>(N) + 1, s);
     hipLaunchKernelGGL(k_iperm, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, g.perm.p, np, N, g.iperm.p);
     AHR_LAUNCHED("k_iperm");
-    g.xmpin.ensure(static_cast<size_t>(g.first_star - n) + 1, s);
-    g.xstar_net.ensure(static_cast<size_t>(np - g.first_star) + 1, s);
-    if (np > n) {
-        hipLaunchKernelGGL(k_exec_aux, dim3(grid_for(np - n, kBT)), dim3(kBT), 0, s, n, g.first_star, np, g.perm.p,
-                           g.mpin_pin.p, g.nl.pin_node, g.nl.pin_off, g.star_net.p, g.xmpin.p, g.xstar_net.p);
-        AHR_LAUNCHED("k_exec_aux");
-    }
 
     DevBuf<int32_t> len;
     len.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_exec_lens, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.perm.p, g.net_len.p, len.p);
-    AHR_LAUNCHED("k_exec_lens");
+    g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
+    g.xmpin.ensure(static_cast<size_t>(g.first_star - n) + 1, s);
+    g.xstar_net.ensure(static_cast<size_t>(np - g.first_star) + 1, s);
+    ExecRowArgs ea{N, n, g.first_star, np, g.perm.p, g.net_len.p, g.qdeg.p, g.mpin_pin.p, g.nl.pin_node,
+                   g.nl.pin_off, g.star_net.p, len.p, g.xqdeg.p, g.xmpin.p, g.xstar_net.p};
+    hipLaunchKernelGGL(k_exec_rows, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, ea);
+    AHR_LAUNCHED("k_exec_rows");
     g.xnet_rp.ensure(static_cast<size_t>(N) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i32(len.p, g.xnet_rp.p, N, g.scan_tmp.p, s);
     len.release(s);
     g.xnet_ent.ensure(static_cast<size_t>(g.nnz_cap) + 1, s);      // the netlist arrays' bound
-    g.xqdeg.ensure(static_cast<size_t>(N) + 1, s);
     if (g.nnz_cap) {
         hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N,
                            g.perm.p, g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
@@ -365,8 +366,6 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         rank.release(s);
         rows.release(s);
     }
-    hipLaunchKernelGGL(k_exec_qdeg, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.perm.p, g.qdeg.p, g.xqdeg.p);
-    AHR_LAUNCHED("k_exec_qdeg");
     g.has_layout = 1;
 }
 
