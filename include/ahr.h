@@ -183,7 +183,8 @@ ahr_status ahr_graph_export(const ahr_graph* gr, ahr_graph_host* dst, void* stre
 /* Free a graph and its device memory.  When all of the graph's work was
  * enqueued on one stream, the memory is released in that stream's order
  * (later work on any stream reuses it only after the graph's work) and the
- * call does not wait; otherwise it synchronises the device. */
+ * call does not wait; otherwise it synchronises the device.  That stream must
+ * still exist when the graph is freed. */
 void ahr_graph_destroy(ahr_graph* gr);
 
 /* Apply the polynomial filter of `spec` (Section V eq. "refine-filter";
