@@ -9,7 +9,8 @@ oracle:
 - hints switched off;
 - a single instance;
 - lambda_up fixed at 0 (T = I);
-- a very high filter order.
+- a very high filter order;
+- a graph built with no placement, its sizes and CSR read before any hints.
 
 Bars as in the main parity tests: CSR bit-exact, filter within 1e-5
 centred relative error (exact where the result is an identity), fixed
@@ -21,6 +22,7 @@ import torch
 import gpu_common as U
 from netlists import make
 from oracle import ahr_oracle as O
+from synth import netlist as N
 
 pytestmark = pytest.mark.gpu
 
@@ -147,3 +149,34 @@ def test_high_order():
     out, ref, mov = run_case(nl, O.HintParams(nbx=6, nby=6, detection_ratio=0.3),
                              O.FilterSpec(ks=(16, 64), alphas=(0.5, 0.5)))
     check_close(out, ref, mov)
+
+
+def test_graph_without_placement_then_hints():
+    """A graph built with no placement holds only the netlist part: its sizes
+    and exported CSR are read from the in-place merged rows (no hints, no
+    execution layout yet).  Hints added afterwards give the same graph as a
+    build with the placement."""
+    nl = N.generate(N.TINY)
+    p = U.params32(O.HintParams(nbx=8, nby=8))
+    og = O.build_graph(nl, p, nl["g0"][:, :2])
+    net = A.Netlist(nl)
+    x = torch.as_tensor(nl["g0"]).cuda()
+    gr = A.Graph(net, U.to_c_params(A, p), None)
+    try:
+        inf = gr.info()
+        assert inf["nnz_net"] == og.net_col.size and inf["nnz_hint"] == 0
+        ex = gr.export()
+        assert np.array_equal(ex["net_row_ptr"], og.net_row_ptr.astype(np.int32))
+        assert np.array_equal(ex["net_col"], og.net_col.astype(np.int32))
+        assert np.array_equal(ex["net_q"], og.net_q)
+        gr.update_hints(x)
+        inf = gr.info()
+        assert inf["nnz_net"] == og.net_col.size and inf["nnz_hint"] == og.hint_col.size
+        ex = gr.export()
+        assert np.array_equal(ex["hint_row_ptr"], og.hint_row_ptr.astype(np.int32))
+        spec = U.spec32(BANK)
+        out = gr.filter(U.to_c_spec(A, spec), x).cpu().numpy()
+    finally:
+        gr.close()
+    ref = O.apply_filter(nl, og, spec, nl["g0"])
+    check_close(out, ref, U.movable_rows(nl))
