@@ -32,8 +32,12 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 // ---------------------------------------------------------------- memory
 
 // Stream-ordered device allocation from a pool that keeps freed memory.
+// Blocks may be freed on one stream and reused on another.
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+// A non-blocking stream per device, at the default priority, for work that
+// overlaps the caller's stream (joined to it by events); never destroyed.
+hipStream_t side_stream();
 
 template <class T>
 struct DevBuf {
@@ -237,7 +241,13 @@ struct Graph {
     DevBuf<int4> xmpin;           // [n_mpin] per execution macro pin row: owner, offset x, y (float bits)
     DevBuf<int32_t> xstar_net;    // [n_star] per execution star row: its net
     DevBuf<int32_t> xnet_rp;      // [n_tot+1]
-    DevBuf<int2> xnet_ent;        // [nnz_net]
+    DevBuf<int2> xnet_ent;        // [nnz_net]: read it through net_entries()
+    // The copy into xnet_ent runs on the device's side stream: xnet_fork
+    // orders it after the layout, xnet_ready is recorded after it.
+    // xnet_wait_stream is the last stream made to wait for it (if xnet_waited).
+    hipEvent_t xnet_fork = nullptr, xnet_ready = nullptr;
+    mutable hipStream_t xnet_wait_stream = nullptr;
+    mutable int32_t xnet_waited = 0;
     DevBuf<int64_t> xqdeg;        // [n_tot]
     DevBuf<int32_t> xhint_rp;     // [n_tot+1] hint rows, execution order
     DevBuf<int2> xhint_ent;       // [nnz_hint] (column, float bits of the weight)
@@ -289,6 +299,8 @@ int32_t hint_count(const Graph& g, hipStream_t s);
 // layout.hip: the execution order of the instance, macro pin and star rows
 // (spatial) and the permuted copy of the netlist rows the filter streams
 void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
+// The execution-order netlist entries, with stream s ordered after their copy.
+const int2* net_entries(const Graph& g, hipStream_t s);
 // hints.hip
 void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
 // filter.hip

@@ -35,6 +35,7 @@ Graph::~Graph() {
     // one stream: its later work (and any other stream, through the block
     // events) reuses the memory only after this graph's work; else wait
     hipStream_t s = stream_uses == 1 ? work_stream : nullptr;
+    if (xnet_ready) (void)hipStreamWaitEvent(s, xnet_ready, 0);   // the side stream's copy
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_len, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
                               &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart,
@@ -81,6 +82,8 @@ Graph::~Graph() {
     scan_tmp.release(s);
     i64a.release(s);
     if (stream_uses != 1) (void)hipStreamSynchronize(s);
+    if (xnet_fork) (void)hipEventDestroy(xnet_fork);
+    if (xnet_ready) (void)hipEventDestroy(xnet_ready);
 }
 
 }  // namespace ahr

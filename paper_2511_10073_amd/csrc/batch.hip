@@ -388,7 +388,7 @@ void batch_rows(Batch& b, bool hints, DevBuf<int32_t>& rp, DevBuf<int2>& ent, in
     for (size_t i = 0; i < b.g.size(); ++i) {
         Graph& g = *b.g[i];
         const int32_t* grp = hints ? g.xhint_rp.p : g.xnet_rp.p;
-        const int2* gent = hints ? g.xhint_ent.p : g.xnet_ent.p;
+        const int2* gent = hints ? g.xhint_ent.p : net_entries(g, s);
         hipLaunchKernelGGL(k_batch_copy_rows, dim3(grid_for(static_cast<int64_t>(g.n_tot) * kWave, kBT)), dim3(kBT), 0,
                            s, g.n_tot, g.n_inst, b.inst0[i], b.aux0[i], grp, gent, rp.p, ent.p);
         AHR_LAUNCHED("k_batch_copy_rows");

@@ -145,6 +145,20 @@ void dev_free(void* p, hipStream_t s) {
     g_free.emplace(b.bytes, b);
 }
 
+hipStream_t side_stream() {
+    static std::mutex mu;
+    static std::unordered_map<int, hipStream_t> streams;
+    int dev = 0;
+    AHR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t st = nullptr;
+    AHR_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    streams[dev] = st;
+    return st;
+}
+
 // ---------------------------------------------------------------- scan
 
 constexpr int kScanThreads = 256;

@@ -1296,10 +1296,10 @@ void expand_signal(Graph& g, const float* in, bool band0, float alpha0, hipStrea
     }
 }
 
-ChainView chain_view(Graph& g, const ahr_filter_spec& spec) {
+ChainView chain_view(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     ChainView v;
     v.net_rp = g.xnet_rp.p;
-    v.net_ent = g.xnet_ent.p;
+    v.net_ent = net_entries(g, s);
     v.hint_rp = g.xhint_rp.p;
     v.hint_ent = g.xhint_ent.p;
     v.scale = g.scale.p;
@@ -1382,7 +1382,7 @@ void hops_c(Graph& g, const ahr_filter_spec& spec, const float* in, int lanes, h
     g.acc.ensure(static_cast<size_t>(N) * C, s);
     for (auto& z : g.zh) z.ensure(static_cast<size_t>(N) * C, s);
     expand_signal<C>(g, in, false, 0.f, s);
-    const ChainView v = chain_view(g, spec);
+    const ChainView v = chain_view(g, spec, s);
     HopArgs h = hop_args(v, in, nullptr, C);
     const float* zin = g.z0.p;
     for (int j = 0; j < 3; ++j) {
@@ -1522,10 +1522,10 @@ void filter_c(Graph& g, const ahr_filter_spec& spec, const float* in, float* out
             expand_signal<C>(g, in, b0, a0, s, g.zpk.p);
         }
         const Hop1Gersh f{g.zpk.p, g.deg.p, g.gmax.p, g.lam.p, g.coef.p};
-        chain_c<C, C>(chain_view(g, spec), spec, in, out, lanes, s, &f);
+        chain_c<C, C>(chain_view(g, spec, s), spec, in, out, lanes, s, &f);
     } else {
         expand_signal<C>(g, in, b0, a0, s);
-        chain_c<C, C>(chain_view(g, spec), spec, in, out, lanes, s);
+        chain_c<C, C>(chain_view(g, spec, s), spec, in, out, lanes, s);
     }
 }
 
@@ -1726,7 +1726,9 @@ void norm_done(Graph& g, const ahr_filter_spec& spec) {
 // Row classes, degrees, scales and hint sums of the operator.
 void normalise_degrees(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     const int32_t N = g.n_tot;
-    RowRef m{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
+    // a netlist row's absolute degree is its qdeg: these kernels read the
+    // netlist rows' lengths and the hint entries only
+    RowRef m{g.xnet_rp.p, nullptr, g.xhint_rp.p, g.xhint_ent.p};
 
     if (g.rows_version != g.hint_version) {
         row_classes(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, g.rc, g.scan_tmp, s);
@@ -1771,7 +1773,6 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     if (norm_current(g, spec)) return;
     ProfScope ps(kStageNorm, s);
     const int32_t N = g.n_tot;
-    RowRef m{g.xnet_rp.p, g.xnet_ent.p, g.xhint_rp.p, g.xhint_ent.p};
     normalise_degrees(g, spec, s);
     const double sigma = spec.sigma;
     constexpr int G = 4;
@@ -1781,6 +1782,7 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     } else {
         hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, s, g.lam.p, 0.0);
         AHR_LAUNCHED("k_set_f64");
+        const RowRef m{g.xnet_rp.p, net_entries(g, s), g.xhint_rp.p, g.xhint_ent.p};
         hipLaunchKernelGGL(k_gersh_short<G>, dim3(kGershGrid), dim3(kBT), 0, s, N, m,
                            g.deg.p, g.scale.p, sigma, g.lam.p);
         AHR_LAUNCHED("k_gersh_short");

@@ -348,25 +348,48 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     len.release(s);
     g.xnet_ent.ensure(static_cast<size_t>(g.nnz_cap) + 1, s);      // the netlist arrays' bound
     if (g.nnz_cap) {
-        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s, N,
+        // Nothing reads the execution-order entries before the first hop, so
+        // their copy runs on the device's side stream, beside the hint build
+        // and the degree kernels that follow on s.  Readers take the entries
+        // through net_entries(), which orders their stream after the copy.
+        if (!g.xnet_fork) AHR_HIP(hipEventCreateWithFlags(&g.xnet_fork, hipEventDisableTiming));
+        if (!g.xnet_ready) AHR_HIP(hipEventCreateWithFlags(&g.xnet_ready, hipEventDisableTiming));
+        const hipStream_t s2 = side_stream();
+        AHR_HIP(hipEventRecord(g.xnet_fork, s));
+        AHR_HIP(hipStreamWaitEvent(s2, g.xnet_fork, 0));
+        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s2, N,
                            g.perm.p, g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
         AHR_LAUNCHED("k_exec_net");
         DevBuf<int32_t> flag, rank, rows;
-        flag.ensure(static_cast<size_t>(N) + 1, s);
-        rank.ensure(static_cast<size_t>(N) + 1, s);
-        hipLaunchKernelGGL(k_long_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, g.xnet_rp.p, flag.p);
+        DevBuf<int64_t> tmp;     // not g.scan_tmp: s uses that meanwhile
+        flag.ensure(static_cast<size_t>(N) + 1, s2);
+        rank.ensure(static_cast<size_t>(N) + 1, s2);
+        tmp.ensure(scan_tmp_elems(N), s2);
+        hipLaunchKernelGGL(k_long_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s2, N, g.xnet_rp.p, flag.p);
         AHR_LAUNCHED("k_long_flags");
-        scan_i32_to_i32(flag.p, rank.p, N, g.scan_tmp.p, s);
-        rows.ensure(static_cast<size_t>(N) + 1, s);
-        list_rows(flag.p, rank.p, N, rows.p, s);
-        hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s, rows.p, rank.p + N, g.perm.p,
+        scan_i32_to_i32(flag.p, rank.p, N, tmp.p, s2);
+        rows.ensure(static_cast<size_t>(N) + 1, s2);
+        list_rows(flag.p, rank.p, N, rows.p, s2);
+        hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s2, rows.p, rank.p + N, g.perm.p,
                            g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
         AHR_LAUNCHED("k_exec_net_long");
-        flag.release(s);
-        rank.release(s);
-        rows.release(s);
+        flag.release(s2);
+        rank.release(s2);
+        rows.release(s2);
+        tmp.release(s2);
+        AHR_HIP(hipEventRecord(g.xnet_ready, s2));
+        g.xnet_waited = 0;
     }
     g.has_layout = 1;
+}
+
+const int2* net_entries(const Graph& g, hipStream_t s) {
+    if (g.xnet_ready && !(g.xnet_waited && g.xnet_wait_stream == s)) {
+        AHR_HIP(hipStreamWaitEvent(s, g.xnet_ready, 0));
+        g.xnet_waited = 1;
+        g.xnet_wait_stream = s;
+    }
+    return g.xnet_ent.p;
 }
 
 }  // namespace ahr
