@@ -35,6 +35,10 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 // Blocks may be freed on one stream and reused on another.
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+// Records the events that order the blocks freed since the last call behind
+// their streams' work (one per stream).  Every entry point calls it before
+// it returns, while its stream is still known to exist.
+void flush_frees() noexcept;
 // A non-blocking stream per device, at the default priority, for work that
 // overlaps the caller's stream (joined to it by events); never destroyed.
 hipStream_t side_stream();
@@ -104,6 +108,13 @@ bool profiling();
 // While set (on this thread), ProfScope records nothing: used around HIP
 // graph capture, where event records would become graph nodes.
 void set_capture(bool on);
+
+// An event pair for one kernel launched with hipExtLaunchKernelGGL: the
+// launch binds the events to the kernel's own start and end, so no marker
+// packet sits between the kernels.  False (both null) when stage st is not
+// being timed; else hand the pair to prof_kernel_done after the launch.
+bool prof_kernel_events(Stage st, hipEvent_t* start, hipEvent_t* stop);
+void prof_kernel_done(Stage st, hipEvent_t start, hipEvent_t stop, double bytes);
 
 // Records an event pair around its lifetime on stream s when profiling is on.
 class ProfScope {

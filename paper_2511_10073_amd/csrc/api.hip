@@ -146,6 +146,9 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 template <class F>
 ahr_status guarded(F&& f) {
+    struct Flush {
+        ~Flush() { ahr::flush_frees(); }
+    } flush;
     try {
         ahr::set_error(AHR_OK, "");
         return f();
@@ -334,6 +337,7 @@ void ahr_graph_destroy(ahr_graph* h) {
         delete reinterpret_cast<ahr::Graph*>(h);
     } catch (...) {
     }
+    ahr::flush_frees();
 }
 
 ahr_status ahr_filter(ahr_graph* h, const ahr_filter_spec* spec, const float* in, float* out, int32_t ncols,

@@ -470,6 +470,9 @@ bool tile_ok(int32_t C, int32_t ct) { return ct >= 1 && ct <= C && C % ct == 0 &
 
 template <class F>
 ahr_status guarded_b(F&& f) {
+    struct Flush {
+        ~Flush() { ahr::flush_frees(); }
+    } flush;
     try {
         ahr::set_error(AHR_OK, "");
         return f();
@@ -668,6 +671,7 @@ void ahr_batch_destroy(ahr_batch* h) {
         delete reinterpret_cast<Batch*>(h);
     } catch (...) {
     }
+    ahr::flush_frees();
 }
 
 }  // extern "C"

@@ -32,19 +32,31 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 //
 // A caching allocator: freed device blocks are kept (per device, by size
 // class) and handed out again, so the graph builds of an initializer loop
-// allocate from the driver only the first time.  A block freed on one
-// stream and reused on another is ordered behind the frees' stream by an
-// event wait; the events are recycled through a per-device pool, so a free
-// and a reuse cost one event record and no event creation.
+// allocate from the driver only the first time.  A block reused on the
+// stream it was freed on needs nothing more.  A block reused on another
+// stream is ordered behind its free by an event wait.  Each event record
+// costs the GPU a few microseconds of queue processing, so frees do not
+// record one each: at the end of every entry point (flush_frees), one event
+// per stream covers all the blocks freed on it during the call.  A block
+// that another stream takes before that gets its stream's event at once.
+// The events are recycled through a per-device pool.
 // ahr_memory_trim() returns the cache to the driver.
 
 namespace {
+
+// An event recorded after the frees of one stream; the blocks it covers
+// share it and the last one reused returns it to the pool.
+struct FreeEvent {
+    hipEvent_t e;       // null: the frees are known to be complete
+    int refs;
+    int device;
+};
 
 struct Block {
     void* p;
     size_t bytes;
     hipStream_t stream;
-    hipEvent_t done;      // recorded on `stream` when the block was freed
+    FreeEvent* done;    // null while the free is pending (no event yet)
     int device;
 };
 
@@ -53,7 +65,7 @@ std::multimap<size_t, Block> g_free;                  // by size class
 std::unordered_map<void*, std::pair<size_t, int>> g_live;   // ptr -> (size class, device)
 std::unordered_map<int, std::vector<hipEvent_t>> g_events;  // idle events per device
 
-// Both under g_alloc_mu.  take_event returns null if no event can be made.
+// All under g_alloc_mu.  take_event returns null if no event can be made.
 hipEvent_t take_event(int dev) {
     auto& v = g_events[dev];
     if (!v.empty()) {
@@ -69,8 +81,50 @@ hipEvent_t take_event(int dev) {
     return e;
 }
 
-void give_event(int dev, hipEvent_t e) {
-    if (e) g_events[dev].push_back(e);
+void drop_ref(FreeEvent* fe) {
+    if (!fe || --fe->refs > 0) return;
+    if (fe->e) g_events[fe->device].push_back(fe->e);
+    delete fe;
+}
+
+// One event on (device, stream) for every pending block freed there; if
+// no event can be recorded, wait for the stream instead.
+void flush_stream_locked(int dev, hipStream_t s) {
+    auto* fe = new FreeEvent{take_event(dev), 0, dev};
+    if (!fe->e || hipEventRecord(fe->e, s) != hipSuccess) {
+        (void)hipGetLastError();
+        if (fe->e) g_events[dev].push_back(fe->e);
+        fe->e = nullptr;
+        (void)hipStreamSynchronize(s);
+    }
+    for (auto& kv : g_free) {
+        Block& b = kv.second;
+        if (!b.done && b.device == dev && b.stream == s) {
+            b.done = fe;
+            ++fe->refs;
+        }
+    }
+    if (fe->refs == 0) {
+        fe->refs = 1;
+        drop_ref(fe);
+    }
+}
+
+void flush_all_locked() {
+    for (;;) {
+        const Block* pending = nullptr;
+        for (auto& kv : g_free)
+            if (!kv.second.done) {
+                pending = &kv.second;
+                break;
+            }
+        if (!pending) return;
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (pending->device != cur) (void)hipSetDevice(pending->device);
+        flush_stream_locked(pending->device, pending->stream);
+        if (pending->device != cur) (void)hipSetDevice(cur);
+    }
 }
 
 size_t size_class(size_t b) {
@@ -97,12 +151,24 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     const size_t cls = size_class(bytes);
     {
         std::lock_guard<std::mutex> lk(g_alloc_mu);
+        // a block freed on this stream first (no wait), else any
+        auto pick = g_free.end();
         for (auto it = g_free.lower_bound(cls); it != g_free.end() && it->first == cls; ++it) {
             if (it->second.device != dev) continue;
-            Block b = it->second;
-            g_free.erase(it);
-            if (b.stream != s) AHR_HIP(hipStreamWaitEvent(s, b.done, 0));
-            give_event(dev, b.done);
+            if (pick == g_free.end()) pick = it;
+            if (it->second.stream == s) {
+                pick = it;
+                break;
+            }
+        }
+        if (pick != g_free.end()) {
+            if (pick->second.stream != s) {
+                if (!pick->second.done) flush_stream_locked(dev, pick->second.stream);
+                if (pick->second.done->e) AHR_HIP(hipStreamWaitEvent(s, pick->second.done->e, 0));
+            }
+            Block b = pick->second;
+            g_free.erase(pick);
+            drop_ref(b.done);
             g_live[b.p] = {cls, dev};
             return b.p;
         }
@@ -130,19 +196,16 @@ void dev_free(void* p, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
     auto it = g_live.find(p);
     if (it == g_live.end()) return;
-    Block b{p, it->second.first, s, nullptr, it->second.second};
+    g_free.emplace(it->second.first, Block{p, it->second.first, s, nullptr, it->second.second});
     g_live.erase(it);
-    int dev = b.device;
-    (void)hipGetDevice(&dev);
-    b.done = take_event(dev);
-    if (!b.done || hipEventRecord(b.done, s) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipStreamSynchronize(s);
-        if (b.done) (void)hipEventDestroy(b.done);
-        (void)hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
-        (void)hipEventRecord(b.done, nullptr);
+}
+
+void flush_frees() noexcept {
+    try {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        flush_all_locked();
+    } catch (...) {
     }
-    g_free.emplace(b.bytes, b);
 }
 
 hipStream_t side_stream() {
@@ -454,15 +517,17 @@ void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 
 extern "C" ahr_status ahr_memory_trim(void) {
     std::lock_guard<std::mutex> lk(ahr::g_alloc_mu);
+    ahr::flush_all_locked();
+    int cur = 0;
+    (void)hipGetDevice(&cur);
     for (auto& kv : ahr::g_free) {
-        (void)hipEventSynchronize(kv.second.done);
-        (void)hipEventDestroy(kv.second.done);
-        int cur = 0;
-        (void)hipGetDevice(&cur);
-        (void)hipSetDevice(kv.second.device);
-        (void)hipFree(kv.second.p);
-        (void)hipSetDevice(cur);
+        ahr::Block& b = kv.second;
+        if (b.done->e) (void)hipEventSynchronize(b.done->e);
+        ahr::drop_ref(b.done);
+        (void)hipSetDevice(b.device);
+        (void)hipFree(b.p);
     }
+    (void)hipSetDevice(cur);
     ahr::g_free.clear();
     for (auto& kv : ahr::g_events)
         for (hipEvent_t e : kv.second) (void)hipEventDestroy(e);

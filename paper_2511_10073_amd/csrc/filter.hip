@@ -17,6 +17,8 @@
 // (bin and macro virtual nodes, big-net stars) are split into kChunk-entry
 // chunks, one workgroup each, whose float64 partial sums a small kernel adds
 // after the hop in a fixed order -- deterministic for any schedule.
+#include <hip/hip_ext.h>
+
 #include "ahr_internal.hpp"
 #include "device_util.hpp"
 
@@ -1208,9 +1210,9 @@ __global__ void k_relax(int32_t n_inst, const uint8_t* __restrict__ flags, const
     gn[i] = (flags[i / C] & AHR_NODE_FIXED) ? a : (1.0f - gamma) * a + gamma * gt[i];
 }
 
-// The profiled hop time brackets the k_hop launch alone (the chunk
-// partials' k_hop_long is not part of it), so that it matches a kernel trace
-// of k_hop; `bytes` are the algorithmic bytes of the whole hop.  ntiles
+// The profiled hop time is the k_hop kernel's own (its launch carries the
+// event pair; the chunk partials' k_hop_long is not part of it), so that it
+// matches a kernel trace of k_hop; `bytes` are the algorithmic bytes of the whole hop.  ntiles
 // column tiles of C columns each run as blockIdx.y.
 template <int C, int G>
 void launch_hop(const HopArgs& a, int32_t n_long_rows, double bytes, int ntiles, hipStream_t s) {
@@ -1219,8 +1221,15 @@ void launch_hop(const HopArgs& a, int32_t n_long_rows, double bytes, int ntiles,
     tiles = (tiles + kXcds - 1) / kXcds * kXcds;                    // see xcd_tile
     int64_t blocks = a.n_chunk_blocks + tiles;
     const dim3 grid(static_cast<unsigned>(blocks), static_cast<unsigned>(ntiles));
-    {
-        ProfScope ps(kStageHop, s, bytes);
+    hipEvent_t e0, e1;
+    if (prof_kernel_events(kStageHop, &e0, &e1)) {
+        if (g_hop_nt)
+            hipExtLaunchKernelGGL((k_hop<C, G, U, true>), grid, dim3(kBT), 0, s, e0, e1, 0, a);
+        else
+            hipExtLaunchKernelGGL((k_hop<C, G, U, false>), grid, dim3(kBT), 0, s, e0, e1, 0, a);
+        AHR_LAUNCHED("k_hop");
+        prof_kernel_done(kStageHop, e0, e1, bytes);
+    } else {
         if (g_hop_nt)
             hipLaunchKernelGGL((k_hop<C, G, U, true>), grid, dim3(kBT), 0, s, a);
         else
@@ -1240,8 +1249,15 @@ void launch_hop_rb(const HopArgs& a, int32_t n_long_rows, double bytes, int ntil
     int64_t tiles = (static_cast<int64_t>(a.n_rb) + kXcds - 1) / kXcds * kXcds;   // see xcd_tile
     if (tiles < kXcds) tiles = kXcds;
     const dim3 grid(static_cast<unsigned>(a.n_chunk_blocks + tiles), static_cast<unsigned>(ntiles));
-    {
-        ProfScope ps(kStageHop, s, bytes);
+    hipEvent_t e0, e1;
+    if (prof_kernel_events(kStageHop, &e0, &e1)) {
+        if (g_hop_nt)
+            hipExtLaunchKernelGGL((k_hop_rb<C, true>), grid, dim3(kBT), 0, s, e0, e1, 0, a);
+        else
+            hipExtLaunchKernelGGL((k_hop_rb<C, false>), grid, dim3(kBT), 0, s, e0, e1, 0, a);
+        AHR_LAUNCHED("k_hop_rb");
+        prof_kernel_done(kStageHop, e0, e1, bytes);
+    } else {
         if (g_hop_nt)
             hipLaunchKernelGGL((k_hop_rb<C, true>), grid, dim3(kBT), 0, s, a);
         else

@@ -56,6 +56,21 @@ bool profiling() { return g_on != 0 && !t_capture; }
 
 void set_capture(bool on) { t_capture = on; }
 
+bool prof_kernel_events(Stage st, hipEvent_t* start, hipEvent_t* stop) {
+    *start = *stop = nullptr;
+    if (!g_on || t_capture || (g_on == 2 && st != kStageHop)) return false;
+    std::lock_guard<std::mutex> lk(g_mu);
+    *start = take_event();
+    *stop = take_event();
+    return true;
+}
+
+void prof_kernel_done(Stage st, hipEvent_t start, hipEvent_t stop, double bytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_pending.push_back(Pending{start, stop, st, bytes});
+    if (g_pending.size() > 4096) drain_locked();
+}
+
 ProfScope::ProfScope(Stage st, hipStream_t s, double bytes) : stage_(st), s_(s), bytes_(bytes) {
     if (!g_on || t_capture || (g_on == 2 && st != kStageHop)) return;
     std::lock_guard<std::mutex> lk(g_mu);
