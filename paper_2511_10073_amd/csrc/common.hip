@@ -254,9 +254,20 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_sums(const Tin* __restric
 }
 
 // The kScanItems elements of thread t of a tile (t kScanItems onwards), as
-// int64, zero past n.
-template <class Tin>
+// int64, zero past n.  With V (16-byte aligned int32 input), a thread whose
+// items all lie below n reads them as two 16-byte loads.
+template <bool V, class Tin>
 __device__ __forceinline__ int64_t load_items(const Tin* __restrict__ in, int64_t n, int64_t base, int64_t* v) {
+    if constexpr (V && sizeof(Tin) == 4) {
+        static_assert(kScanItems == 8, "two 16-byte loads per thread");
+        if (base + kScanItems <= n) {
+            const int4* p = reinterpret_cast<const int4*>(in + base);
+            const int4 a = p[0], b = p[1];
+            v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+            v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+            return v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6] + v[7];
+        }
+    }
     Tin x[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) x[k] = in[base + k < n ? base + k : n - 1];
@@ -267,6 +278,35 @@ __device__ __forceinline__ int64_t load_items(const Tin* __restrict__ in, int64_
         local += v[k];
     }
     return local;
+}
+
+// out[base + k] = run + v[0] + ... + v[k-1] for the items below n; with V
+// (16-byte aligned output) a thread whose items all lie below n writes them
+// with 16-byte stores.
+template <bool V, class Tout>
+__device__ __forceinline__ void store_items(Tout* __restrict__ out, int64_t n, int64_t base, int64_t run,
+                                            const int64_t* v) {
+    Tout o[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        o[k] = static_cast<Tout>(run);
+        run += v[k];
+    }
+    if constexpr (V) {
+        if (base + kScanItems <= n) {
+            int4* p = reinterpret_cast<int4*>(out + base);
+            constexpr int kVecs = kScanItems * sizeof(Tout) / sizeof(int4);
+#pragma unroll
+            for (int q = 0; q < kVecs; ++q) {
+                int4 w;
+                __builtin_memcpy(&w, reinterpret_cast<const char*>(o) + q * sizeof(int4), sizeof(int4));
+                p[q] = w;
+            }
+            return;
+        }
+    }
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) out[base + k] = o[k];
 }
 
 // Exclusive scan of the tile sums by one block; sums[ntiles] = total.
@@ -289,22 +329,17 @@ __global__ void __launch_bounds__(1024) k_scan_sums(int64_t* __restrict__ sums, 
     if (threadIdx.x == 0) sums[ntiles] = carry;
 }
 
-template <class Tin, class Tout>
+template <bool V, class Tin, class Tout>
 __global__ void __launch_bounds__(kScanThreads) k_tile_scan(const Tin* __restrict__ in, int64_t n,
                                                             const int64_t* __restrict__ sums,
                                                             int64_t ntiles, Tout* __restrict__ out) {
     __shared__ int64_t red[kScanThreads / 64];
     int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
     int64_t v[kScanItems];
-    const int64_t local = load_items(in, n, base, v);
+    const int64_t local = load_items<V>(in, n, base, v);
     int64_t tot;
     int64_t ex = block_exclusive_scan_i64<kScanThreads>(local, red, &tot);
-    int64_t run = sums[blockIdx.x] + ex;
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        if (i < n) out[i] = static_cast<Tout>(run);
-        run += v[k];
-    }
+    store_items<V>(out, n, base, sums[blockIdx.x] + ex, v);
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = static_cast<Tout>(sums[ntiles]);
 }
 
@@ -314,7 +349,7 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_scan(const Tin* __restric
 // the total.
 constexpr int64_t kDirectTiles = 4096;
 
-template <class Tin, class Tout>
+template <bool V, class Tin, class Tout>
 __global__ void __launch_bounds__(kScanThreads) k_tile_scan_direct(const Tin* __restrict__ in, int64_t n,
                                                                    int64_t* __restrict__ sums, int64_t ntiles,
                                                                    Tout* __restrict__ out) {
@@ -322,7 +357,7 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_scan_direct(const Tin* __
     const int64_t upto = blockIdx.x == 0 ? ntiles : static_cast<int64_t>(blockIdx.x);   // >= 1
     int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
     int64_t v[kScanItems];
-    const int64_t local = load_items(in, n, base, v);
+    const int64_t local = load_items<V>(in, n, base, v);
     constexpr int U = 8;
     int64_t pre = 0;
     for (int64_t j0 = threadIdx.x; j0 < upto; j0 += U * kScanThreads) {
@@ -339,16 +374,25 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_scan_direct(const Tin* __
     const int64_t tile_off = blockIdx.x == 0 ? 0 : pre;
     int64_t tot;
     int64_t ex = block_exclusive_scan_i64<kScanThreads>(local, red, &tot);
-    int64_t run = tile_off + ex;
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        if (i < n) out[i] = static_cast<Tout>(run);
-        run += v[k];
-    }
+    store_items<V>(out, n, base, tile_off + ex, v);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sums[ntiles] = pre;
         out[n] = static_cast<Tout>(pre);
     }
+}
+
+template <bool V, class Tin, class Tout>
+static void scan_launch(const Tin* in, Tout* out, int64_t n, int64_t* tmp, int64_t ntiles, hipStream_t s) {
+    if (ntiles <= kDirectTiles) {
+        hipLaunchKernelGGL((k_tile_scan_direct<V, Tin, Tout>), dim3(ntiles), dim3(kScanThreads), 0, s, in, n, tmp,
+                           ntiles, out);
+        AHR_LAUNCHED("k_tile_scan_direct");
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tmp, ntiles);
+    AHR_LAUNCHED("k_scan_sums");
+    hipLaunchKernelGGL((k_tile_scan<V, Tin, Tout>), dim3(ntiles), dim3(kScanThreads), 0, s, in, n, tmp, ntiles, out);
+    AHR_LAUNCHED("k_tile_scan");
 }
 
 template <class Tin, class Tout>
@@ -356,16 +400,13 @@ static void scan_impl(const Tin* in, Tout* out, int64_t n, int64_t* tmp, hipStre
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;   // n > 0
     hipLaunchKernelGGL((k_tile_sums<Tin>), dim3(ntiles), dim3(kScanThreads), 0, s, in, n, tmp);
     AHR_LAUNCHED("k_tile_sums");
-    if (ntiles <= kDirectTiles) {
-        hipLaunchKernelGGL((k_tile_scan_direct<Tin, Tout>), dim3(ntiles), dim3(kScanThreads), 0, s, in, n, tmp, ntiles,
-                           out);
-        AHR_LAUNCHED("k_tile_scan_direct");
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tmp, ntiles);
-    AHR_LAUNCHED("k_scan_sums");
-    hipLaunchKernelGGL((k_tile_scan<Tin, Tout>), dim3(ntiles), dim3(kScanThreads), 0, s, in, n, tmp, ntiles, out);
-    AHR_LAUNCHED("k_tile_scan");
+    // 16-byte accesses when both arrays allow them (the offsets inside a
+    // tile are multiples of 32 bytes)
+    const bool vec = (reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) % 16 == 0;
+    if (vec)
+        scan_launch<true>(in, out, n, tmp, ntiles, s);
+    else
+        scan_launch<false>(in, out, n, tmp, ntiles, s);
 }
 
 void scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
