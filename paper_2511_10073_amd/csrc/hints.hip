@@ -37,14 +37,24 @@ __device__ __forceinline__ int bin_coord(float v, float lo, float w, int nb) {
 
 __device__ __forceinline__ bool is_std_movable(uint8_t f) { return (f & (AHR_NODE_FIXED | AHR_NODE_MACRO)) == 0; }
 
-__device__ __forceinline__ float w_bin(const Grid& gr, float x, float y, int b, const double* phi, double bw_i) {
-    int bx = b % gr.nbx, by = b / gr.nbx;
-    double xb = gr.xl + (static_cast<double>(bx) + 0.5) * gr.bw;
-    double yb = gr.yl + (static_cast<double>(by) + 0.5) * gr.bh;
-    double rx = fabs(static_cast<double>(x) - xb) / (gr.bw / 2);
-    double ry = fabs(static_cast<double>(y) - yb) / (gr.bh / 2);
-    double r = rx > ry ? rx : ry;
-    return static_cast<float>(-exp(-r) * phi[b] * bw_i);
+// The bin-hint weight of a cell at (x, y) towards bin (bx, by) is
+// -exp(-max(rx, ry)) phi_b baseWeight_i, with rx and ry its distances from
+// the bin centre in half bin widths.  exp(-max(rx, ry)) is exp(-rx) or
+// exp(-ry), whichever argument is the maximum, so a cell's window needs one
+// exponential per window column and one per window row.
+__device__ __forceinline__ double bin_rx(const Grid& gr, float x, int bx) {
+    const double xb = gr.xl + (static_cast<double>(bx) + 0.5) * gr.bw;
+    return fabs(static_cast<double>(x) - xb) / (gr.bw / 2);
+}
+
+__device__ __forceinline__ double bin_ry(const Grid& gr, float y, int by) {
+    const double yb = gr.yl + (static_cast<double>(by) + 0.5) * gr.bh;
+    return fabs(static_cast<double>(y) - yb) / (gr.bh / 2);
+}
+
+__device__ __forceinline__ float w_bin_of(double rx, double ex, double ry, double ey, double phi_b, double bw_i) {
+    const double e = rx > ry ? ex : ey;     // exp(-max(rx, ry))
+    return static_cast<float>(-e * phi_b * bw_i);
 }
 
 __device__ __forceinline__ bool inside(float x, float y, float4 m) {
@@ -407,6 +417,7 @@ __global__ void k_bin_row_counts(HintArgs a, int32_t* __restrict__ cnt) {
 // of w over its hint entries (its hint degree and the signed hint sum) are
 // formed on the way, in float64.
 constexpr int kFillCap = 16 * kBT;
+constexpr int kWinCols = 5;      // windows up to this wide keep their column terms in registers
 
 __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ pair_off,
@@ -447,19 +458,42 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
                 const int my = rank[r] - a.bin_start[b];
                 int x0, x1, y0, y1;
                 window(a.gr, b, x0, x1, y0, y1);
-                for (int ty = y0; ty <= y1; ++ty)
-                    for (int tx = x0; tx <= x1; ++tx) {
-                        int bb = ty * a.gr.nbx + tx;
-                        const float wb = w_bin(a.gr, x, y, bb, a.phi, bwi);
-                        ha += fabs(static_cast<double>(wb));
-                        hs += static_cast<double>(wb);
-                        int w = f_bits(wb);
-                        put(make_int2(a.first_bvirt + bb, w));
-                        // slot of this cell's bin inside the window of bb
-                        int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
-                        int64_t q = rp[a.first_bvirt + bb] + wpre[static_cast<int64_t>(bb) * ww * wh + slot] + my;
-                        ent[q] = make_int2(static_cast<int>(r), w);
+                auto bin_entry = [&](int tx, int ty, double rx, double ex, double ry, double ey) {
+                    const int bb = ty * a.gr.nbx + tx;
+                    const float wb = w_bin_of(rx, ex, ry, ey, a.phi[bb], bwi);
+                    ha += fabs(static_cast<double>(wb));
+                    hs += static_cast<double>(wb);
+                    const int w = f_bits(wb);
+                    put(make_int2(a.first_bvirt + bb, w));
+                    // slot of this cell's bin inside the window of bb
+                    const int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
+                    const int64_t q = rp[a.first_bvirt + bb] + wpre[static_cast<int64_t>(bb) * ww * wh + slot] + my;
+                    ent[q] = make_int2(static_cast<int>(r), w);
+                };
+                const int nx = x1 - x0 + 1;
+                if (nx <= kWinCols) {
+                    // the window's column distances and exponentials, once
+                    double rxs[kWinCols], exs[kWinCols];
+#pragma unroll
+                    for (int i = 0; i < kWinCols; ++i) {
+                        rxs[i] = bin_rx(a.gr, x, i < nx ? x0 + i : x0);
+                        exs[i] = i < nx ? exp(-rxs[i]) : 0.0;
                     }
+                    for (int ty = y0; ty <= y1; ++ty) {
+                        const double ry = bin_ry(a.gr, y, ty), ey = exp(-ry);
+#pragma unroll
+                        for (int i = 0; i < kWinCols; ++i)
+                            if (i < nx) bin_entry(x0 + i, ty, rxs[i], exs[i], ry, ey);
+                    }
+                } else {
+                    for (int ty = y0; ty <= y1; ++ty) {
+                        const double ry = bin_ry(a.gr, y, ty), ey = exp(-ry);
+                        for (int tx = x0; tx <= x1; ++tx) {
+                            const double rx = bin_rx(a.gr, x, tx);
+                            bin_entry(tx, ty, rx, exp(-rx), ry, ey);
+                        }
+                    }
+                }
             }
         }
     }
