@@ -1176,13 +1176,22 @@ __global__ void __launch_bounds__(1024) k_lam_reduce(const double* __restrict__ 
 // The first hop's epilogue once lambda_up and the coefficients are known:
 // zout holds the rows' unscaled neighbour sums, the records the rows' z.
 template <int C>
-__global__ void __launch_bounds__(kBT) k_hop1_epi(HopArgs a, const float* __restrict__ zpk) {
+__global__ void __launch_bounds__(kBT) k_hop1_epi(HopArgs a, const float* __restrict__ zpk,
+                                                  const double* __restrict__ lam, double sigma,
+                                                  float2* __restrict__ coef_out) {
     const int64_t r64 = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
     if (r64 >= a.n_rows) return;
     const int r = static_cast<int>(r64);
     RowOps<C> ops;
     ops.s = a.scale[r];
-    if (a.coef) ops.k = a.coef[r];
+    if (coef_out) {        // the row's hop coefficients, formed here once lambda_up is known
+        float cr, kr;
+        hop_coef(ops.s, *lam, sigma, cr, kr);
+        ops.k = make_float2(cr, kr);
+        coef_out[r] = ops.k;
+    } else if (a.coef) {
+        ops.k = a.coef[r];
+    }
     ops.z = vload<C>(zpk + static_cast<int64_t>(r) * pack_width<C>());
     if (a.band == 2) ops.acc = vload<C>(a.acc + static_cast<int64_t>(r) * C);
     ops.inst = r;          // never the last hop
@@ -1450,8 +1459,11 @@ void hop1_gersh(const ChainView& v, HopArgs h, const Hop1Gersh& f, hipStream_t s
     }
     hipLaunchKernelGGL(k_lam_reduce, dim3(1), dim3(1024), 0, s, f.gmax, tiles, f.gmax + tiles, v.n_long, f.lam);
     AHR_LAUNCHED("k_lam_reduce");
-    hop_coefs(v.n_tot, v.scale, f.lam, v.sigma, f.coef, s);
-    hipLaunchKernelGGL(k_hop1_epi<C>, dim3(grid_for(h.n_rows, kBT)), dim3(kBT), 0, s, h, f.zpk);
+    // the epilogue forms every row's coefficients when it covers every row
+    const bool fused = h.n_rows == v.n_tot;
+    if (!fused) hop_coefs(v.n_tot, v.scale, f.lam, v.sigma, f.coef, s);
+    hipLaunchKernelGGL(k_hop1_epi<C>, dim3(grid_for(h.n_rows, kBT)), dim3(kBT), 0, s, h, f.zpk, f.lam, v.sigma,
+                       fused ? f.coef : nullptr);
     AHR_LAUNCHED("k_hop1_epi");
 }
 
