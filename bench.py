@@ -34,8 +34,8 @@ HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("fil
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "sources_sha256": "b1b231e4bb4c9698066e3d7d0cadbd61dc680d32f317b12391f8041bfab782c8",
-               "bytes_per_launch": 1419433384,
+               "sources_sha256": "6cc7b994916d4f14a3803124cd3bcf08fbdf68cce344db089a6a93b19f130828",
+               "bytes_per_launch": 1419490116,
                "source": "profiles/k_hop_large-2.2M_hbm_traffic.md"}
 
 
