@@ -255,8 +255,9 @@ __global__ void k_sort_trivial(const int32_t* __restrict__ rows, int32_t nrows, 
 }
 
 // G lanes per row (G = 8, 16, 32 or 64): bitonic sort by column across the lanes,
-// then merge equal columns by exact integer sums.
-template <int G>
+// then merge equal columns by exact integer sums.  Narrow: the column ids
+// leave room for a lane index beside them in 31 bits.
+template <int G, bool Narrow>
 __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ rows, int32_t nrows,
                                                     const int32_t* __restrict__ cnt, const int64_t* __restrict__ rp,
                                                     const RawEnt* __restrict__ raw,
@@ -277,18 +278,39 @@ __global__ void __launch_bounds__(kBT) k_sort_group(const int32_t* __restrict__ 
         key = e.col;
         q = e.q;
     }
+    if constexpr (Narrow) {
+        // one 32-bit key per lane, (column, lane) packed: unique, so the
+        // network moves the key alone and each lane then fetches the weight
+        // of the entry it ended up with
+        constexpr int LB = G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
+        int ck = l < len ? ((key << LB) | l) : 0x7fffffff;
 #pragma unroll
-    for (int k = 2; k <= G; k <<= 1) {
+        for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            int pk = __shfl_xor(key, j);
-            int64_t pq = __shfl_xor(q, j);
-            bool up = (l & k) == 0;
-            bool lower = (l & j) == 0;
-            bool take = lower ? (up ? (pk < key) : (pk > key)) : (up ? (pk > key) : (pk < key));
-            if (take) {
-                key = pk;
-                q = pq;
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int pk = __shfl_xor(ck, j);
+                const bool up = (l & k) == 0;
+                const bool lower = (l & j) == 0;
+                const bool take = lower ? (up ? (pk < ck) : (pk > ck)) : (up ? (pk > ck) : (pk < ck));
+                ck = take ? pk : ck;
+            }
+        }
+        q = __shfl(q, gbase + (ck & (G - 1)));
+        key = l < len ? (ck >> LB) : 0x7fffffff;
+    } else {
+#pragma unroll
+        for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                int pk = __shfl_xor(key, j);
+                int64_t pq = __shfl_xor(q, j);
+                bool up = (l & k) == 0;
+                bool lower = (l & j) == 0;
+                bool take = lower ? (up ? (pk < key) : (pk > key)) : (up ? (pk > key) : (pk < key));
+                if (take) {
+                    key = pk;
+                    q = pq;
+                }
             }
         }
     }
@@ -686,20 +708,26 @@ void build_netlist(Graph& g, hipStream_t s) {
         hipLaunchKernelGGL(k_sort_trivial, dim3(grid_for(ncls[0], kBT)), dim3(kBT), 0, s, cls[0], ncls[0], cnt.p,
                            rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_trivial");
+    // rows of up to 64 entries sort (column, lane) pairs packed in 32 bits
+    const bool narrow = N < (1 << 25);
     if (ncls[1])
-        hipLaunchKernelGGL(k_sort_group<8>, dim3(grid_for(static_cast<int64_t>(ncls[1]) * 8, kBT)), dim3(kBT), 0, s,
+        hipLaunchKernelGGL((narrow ? k_sort_group<8, true> : k_sort_group<8, false>),
+                           dim3(grid_for(static_cast<int64_t>(ncls[1]) * 8, kBT)), dim3(kBT), 0, s,
                            cls[1], ncls[1], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_group8");
     if (ncls[2])
-        hipLaunchKernelGGL(k_sort_group<16>, dim3(grid_for(static_cast<int64_t>(ncls[2]) * 16, kBT)), dim3(kBT), 0, s,
+        hipLaunchKernelGGL((narrow ? k_sort_group<16, true> : k_sort_group<16, false>),
+                           dim3(grid_for(static_cast<int64_t>(ncls[2]) * 16, kBT)), dim3(kBT), 0, s,
                            cls[2], ncls[2], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_group16");
     if (ncls[3])
-        hipLaunchKernelGGL(k_sort_group<32>, dim3(grid_for(static_cast<int64_t>(ncls[3]) * 32, kBT)), dim3(kBT), 0, s,
+        hipLaunchKernelGGL((narrow ? k_sort_group<32, true> : k_sort_group<32, false>),
+                           dim3(grid_for(static_cast<int64_t>(ncls[3]) * 32, kBT)), dim3(kBT), 0, s,
                            cls[3], ncls[3], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_group32");
     if (ncls[4])
-        hipLaunchKernelGGL(k_sort_group<64>, dim3(grid_for(static_cast<int64_t>(ncls[4]) * 64, kBT)), dim3(kBT), 0, s,
+        hipLaunchKernelGGL((narrow ? k_sort_group<64, true> : k_sort_group<64, false>),
+                           dim3(grid_for(static_cast<int64_t>(ncls[4]) * 64, kBT)), dim3(kBT), 0, s,
                            cls[4], ncls[4], cnt.p, rp.p, raw.p, scol.p, sq.p, ucnt.p, g.qdeg.p);
     AHR_LAUNCHED("k_sort_group64");
     if (ncls[5]) {
