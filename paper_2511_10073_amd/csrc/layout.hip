@@ -284,6 +284,8 @@ __global__ void k_long_flags(int32_t n_tot, const int32_t* __restrict__ xrp, int
 
 }  // namespace
 
+static void exec_net_copy(Graph& g, int32_t N, hipStream_t s2);
+
 void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     const int32_t n = g.n_inst, N = g.n_tot, np = g.first_mvirt;
     DevBuf<int32_t> key, digit, first, second;
@@ -357,30 +359,43 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
         const hipStream_t s2 = side_stream();
         AHR_HIP(hipEventRecord(g.xnet_fork, s));
         AHR_HIP(hipStreamWaitEvent(s2, g.xnet_fork, 0));
-        hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s2, N,
-                           g.perm.p, g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
-        AHR_LAUNCHED("k_exec_net");
-        DevBuf<int32_t> flag, rank, rows;
-        DevBuf<int64_t> tmp;     // not g.scan_tmp: s uses that meanwhile
-        flag.ensure(static_cast<size_t>(N) + 1, s2);
-        rank.ensure(static_cast<size_t>(N) + 1, s2);
-        tmp.ensure(scan_tmp_elems(N), s2);
-        hipLaunchKernelGGL(k_long_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s2, N, g.xnet_rp.p, flag.p);
-        AHR_LAUNCHED("k_long_flags");
-        scan_i32_to_i32(flag.p, rank.p, N, tmp.p, s2);
-        rows.ensure(static_cast<size_t>(N) + 1, s2);
-        list_rows(flag.p, rank.p, N, rows.p, s2);
-        hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s2, rows.p, rank.p + N, g.perm.p,
-                           g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
-        AHR_LAUNCHED("k_exec_net_long");
-        flag.release(s2);
-        rank.release(s2);
-        rows.release(s2);
-        tmp.release(s2);
+        try {
+            exec_net_copy(g, N, s2);
+        } catch (...) {
+            // readers and the destructor still order themselves after what
+            // did reach the side stream
+            (void)hipEventRecord(g.xnet_ready, s2);
+            throw;
+        }
         AHR_HIP(hipEventRecord(g.xnet_ready, s2));
         g.xnet_waited = 0;
     }
     g.has_layout = 1;
+}
+
+// The execution-order netlist entries: short rows by k_exec_net, long rows
+// by k_exec_net_long from a device-built list, all on stream s2.
+static void exec_net_copy(Graph& g, int32_t N, hipStream_t s2) {
+    hipLaunchKernelGGL(k_exec_net, dim3(grid_for(static_cast<int64_t>(N) * 8, kBT)), dim3(kBT), 0, s2, N,
+                       g.perm.p, g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
+    AHR_LAUNCHED("k_exec_net");
+    DevBuf<int32_t> flag, rank, rows;
+    DevBuf<int64_t> tmp;     // not g.scan_tmp: s uses that meanwhile
+    flag.ensure(static_cast<size_t>(N) + 1, s2);
+    rank.ensure(static_cast<size_t>(N) + 1, s2);
+    tmp.ensure(scan_tmp_elems(N), s2);
+    hipLaunchKernelGGL(k_long_flags, dim3(grid_for(N, kBT)), dim3(kBT), 0, s2, N, g.xnet_rp.p, flag.p);
+    AHR_LAUNCHED("k_long_flags");
+    scan_i32_to_i32(flag.p, rank.p, N, tmp.p, s2);
+    rows.ensure(static_cast<size_t>(N) + 1, s2);
+    list_rows(flag.p, rank.p, N, rows.p, s2);
+    hipLaunchKernelGGL(k_exec_net_long, dim3(kLongRowGrid), dim3(kBT), 0, s2, rows.p, rank.p + N, g.perm.p,
+                       g.iperm.p, g.net_off.p, g.net_col.p, g.net_q.p, g.xnet_rp.p, g.xnet_ent.p);
+    AHR_LAUNCHED("k_exec_net_long");
+    flag.release(s2);
+    rank.release(s2);
+    rows.release(s2);
+    tmp.release(s2);
 }
 
 const int2* net_entries(const Graph& g, hipStream_t s) {
