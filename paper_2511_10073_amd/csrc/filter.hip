@@ -547,23 +547,22 @@ __device__ __forceinline__ void expand_big_star(const ExpandArgs& a, int k) {
     }
 }
 
-template <int C>
-__global__ void __launch_bounds__(kBT) k_expand(ExpandArgs a) {
-    int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
-    if (r < a.n_tot) expand_row<C>(a, static_cast<int>(r));
-}
-
-// G lanes per star (mid-size stars; the others exit).
+// The whole expansion in one launch, its three parts side by side (they
+// write disjoint rows): first one workgroup per big star, then G lanes per
+// mid-size star, then one lane per row.
 template <int C, int G>
-__global__ void __launch_bounds__(kBT) k_expand_star(ExpandArgs a, int32_t n_star) {
-    const int64_t k = (static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x) / G;
-    if (k < n_star) expand_star<C, G>(a, static_cast<int>(k));
-}
-
-// One workgroup per listed big star.
-template <int C>
-__global__ void __launch_bounds__(kBT) k_expand_big_star(ExpandArgs a, const int32_t* __restrict__ big) {
-    expand_big_star<C>(a, big[blockIdx.x]);
+__global__ void __launch_bounds__(kBT) k_expand_all(ExpandArgs a, int32_t n_star, const int32_t* __restrict__ big,
+                                                    int32_t nbig, int32_t bstar) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x);
+    if (b < nbig) {
+        expand_big_star<C>(a, big[b]);
+    } else if (b < nbig + bstar) {
+        const int64_t k = (static_cast<int64_t>(b - nbig) * kBT + threadIdx.x) / G;
+        if (k < n_star) expand_star<C, G>(a, static_cast<int>(k));
+    } else {
+        const int64_t r = static_cast<int64_t>(b - nbig - bstar) * kBT + threadIdx.x;
+        if (r < a.n_tot) expand_row<C>(a, static_cast<int>(r));
+    }
 }
 
 // Graph of workgroup b in a batched launch: the last g with first[g] <= b.
@@ -1307,18 +1306,13 @@ void expand_signal(Graph& g, const float* in, bool band0, float alpha0, hipStrea
     e.ct = C;
     e.tile_stride = static_cast<int64_t>(g.n_tot) * C;
     ProfScope ps(kStageExpand, s);
-    hipLaunchKernelGGL((k_expand<C>), dim3(grid_for(g.n_tot, kBT)), dim3(kBT), 0, s, e);
-    AHR_LAUNCHED("k_expand");
-    if (g.n_star) {
-        hipLaunchKernelGGL((k_expand_star<C, kStarLanes>),
-                           dim3(grid_for(static_cast<int64_t>(g.n_star) * kStarLanes, kBT)), dim3(kBT), 0, s, e,
-                           g.n_star);
-        AHR_LAUNCHED("k_expand_star");
-        if (g.n_big_stars) {
-            hipLaunchKernelGGL((k_expand_big_star<C>), dim3(g.n_big_stars), dim3(kBT), 0, s, e, g.big_stars.p);
-            AHR_LAUNCHED("k_expand_big_star");
-        }
-    }
+    const int32_t nbig = g.n_star ? g.n_big_stars : 0;
+    const int32_t bstar =
+        g.n_star ? static_cast<int32_t>(grid_for(static_cast<int64_t>(g.n_star) * kStarLanes, kBT)) : 0;
+    const int64_t blocks = static_cast<int64_t>(nbig) + bstar + grid_for(g.n_tot, kBT);
+    hipLaunchKernelGGL((k_expand_all<C, kStarLanes>), dim3(static_cast<unsigned>(blocks)), dim3(kBT), 0, s, e,
+                       g.n_star, g.big_stars.p, nbig, bstar);
+    AHR_LAUNCHED("k_expand_all");
 }
 
 ChainView chain_view(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
