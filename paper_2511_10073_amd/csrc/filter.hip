@@ -175,11 +175,12 @@ __global__ void k_coef(int32_t n, const float* __restrict__ scale, const double*
 // Degree d_i = qdeg_i 2^-32 + sum_j |hint_ij| + sigma, scale s_i = d_i^-1/2,
 // and the signed sum of the row's hint weights (a feature of the learned
 // surrogate).
+// Lane t of the rows from r0 on, G lanes per row.
 template <int G>
-__global__ void __launch_bounds__(kBT) k_deg_short(int32_t r0, int32_t n, RowRef m, const int64_t* __restrict__ qdeg,
-                                                   double sigma, double* __restrict__ deg, float* __restrict__ scale,
-                                                   float* __restrict__ hsum) {
-    int64_t t = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+__device__ __forceinline__ void deg_short_row(int64_t t, int32_t r0, int32_t n, const RowRef& m,
+                                              const int64_t* __restrict__ qdeg, double sigma,
+                                              double* __restrict__ deg, float* __restrict__ scale,
+                                              float* __restrict__ hsum) {
     int64_t r = r0 + t / G;
     int l = static_cast<int>(t & (G - 1));
     if (r >= n) return;
@@ -207,10 +208,10 @@ __global__ void __launch_bounds__(kBT) k_deg_short(int32_t r0, int32_t n, RowRef
 
 // The same for the short cell rows, from the hint sums the hint build
 // formed for every cell.
-__global__ void k_deg_cells(int32_t n_inst, RowRef m, const int64_t* __restrict__ qdeg,
-                            const double* __restrict__ habs, const float* __restrict__ hsg, double sigma,
-                            double* __restrict__ deg, float* __restrict__ scale, float* __restrict__ hsum) {
-    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void deg_cell_row(int64_t r, int32_t n_inst, const RowRef& m,
+                                             const int64_t* __restrict__ qdeg, const double* __restrict__ habs,
+                                             const float* __restrict__ hsg, double sigma, double* __restrict__ deg,
+                                             float* __restrict__ scale, float* __restrict__ hsum) {
     if (r >= n_inst) return;
     int len = (m.net_rp[r + 1] - m.net_rp[r]) + (m.hint_rp[r + 1] - m.hint_rp[r]);
     if (len > kLongRow) return;
@@ -218,6 +219,22 @@ __global__ void k_deg_cells(int32_t n_inst, RowRef m, const int64_t* __restrict_
     deg[r] = d;
     scale[r] = d > 0 ? static_cast<float>(1.0 / sqrt(d)) : 0.f;
     hsum[r] = hsg[r];
+}
+
+// Both in one launch: the first cell_blocks workgroups take the cell rows
+// below r0 (one lane each), the rest G lanes per row from r0 to n.
+template <int G>
+__global__ void __launch_bounds__(kBT) k_deg_rows(int32_t r0, int32_t n, int32_t cell_blocks, RowRef m,
+                                                  const int64_t* __restrict__ qdeg, const double* __restrict__ habs,
+                                                  const float* __restrict__ hsg, double sigma,
+                                                  double* __restrict__ deg, float* __restrict__ scale,
+                                                  float* __restrict__ hsum) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x);
+    if (b < cell_blocks)
+        deg_cell_row(static_cast<int64_t>(b) * kBT + threadIdx.x, r0, m, qdeg, habs, hsg, sigma, deg, scale, hsum);
+    else
+        deg_short_row<G>(static_cast<int64_t>(b - cell_blocks) * kBT + threadIdx.x, r0, n, m, qdeg, sigma, deg,
+                         scale, hsum);
 }
 
 __device__ __forceinline__ void chunk_range(int c, const int32_t* long_rows, const int32_t* chunk_row,
@@ -1769,15 +1786,13 @@ void normalise_degrees(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     // cell rows from the hint build's sums when it formed them for this
     // hint version, then the other rows from their entries
     const int32_t r0 = g.habs_version == g.hint_version ? g.n_inst : 0;
-    if (r0) {
-        hipLaunchKernelGGL(k_deg_cells, dim3(grid_for(r0, kBT)), dim3(kBT), 0, s, r0, m, g.xqdeg.p, g.xhabs.p,
-                           g.xhsg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
-        AHR_LAUNCHED("k_deg_cells");
-    }
-    if (N > r0) {
-        hipLaunchKernelGGL(k_deg_short<G>, dim3(grid_for(static_cast<int64_t>(N - r0) * G, kBT)), dim3(kBT), 0, s, r0,
-                           N, m, g.xqdeg.p, sigma, g.deg.p, g.scale.p, g.hsum.p);
-        AHR_LAUNCHED("k_deg_short");
+    const int32_t cell_blocks = r0 ? static_cast<int32_t>(grid_for(r0, kBT)) : 0;
+    const int64_t short_blocks = N > r0 ? grid_for(static_cast<int64_t>(N - r0) * G, kBT) : 0;
+    if (cell_blocks + short_blocks) {
+        hipLaunchKernelGGL(k_deg_rows<G>, dim3(static_cast<unsigned>(cell_blocks + short_blocks)), dim3(kBT), 0, s,
+                           r0, N, cell_blocks, m, g.xqdeg.p, g.xhabs.p, g.xhsg.p, sigma, g.deg.p, g.scale.p,
+                           g.hsum.p);
+        AHR_LAUNCHED("k_deg_rows");
     }
     if (g.rc.n_long) {
         hipLaunchKernelGGL(k_chunk_absdeg, dim3(g.rc.n_chunks), dim3(kBT), 0, s, m, g.rc.long_rows.p, g.rc.chunk_row.p,
