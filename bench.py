@@ -34,8 +34,8 @@ HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("fil
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "sources_sha256": "cfeb1e59aabab123e0e7c5da5c3a4e0e9faea728abb02015a98d28944c76ad34",
-               "bytes_per_launch": 1419310055,
+               "sources_sha256": "646d488cda3753083e8519ebe50109b5c8bb9f8acb4cd2a65d4739fd09c61e49",
+               "bytes_per_launch": 1419239714,
                "source": "profiles/k_hop_large-2.2M_hbm_traffic.md"}
 
 
