@@ -379,30 +379,33 @@ __global__ void __launch_bounds__(kBT) k_cell_count(HintArgs a, int32_t* __restr
     }
 }
 
-__global__ void k_cell_hint_cnt(int32_t n_inst, const int32_t* __restrict__ nmac, const int32_t* __restrict__ nwin,
-                                int32_t* __restrict__ cnt) {
-    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r < n_inst) cnt[r] = nmac[r] + nwin[r];
-}
-
-__global__ void k_macro_row_cnt(int32_t n_macro, int32_t first_mvirt, const int32_t* __restrict__ mstart,
-                                int32_t* __restrict__ cnt) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n_macro) cnt[first_mvirt + k] = mstart[k + 1] - mstart[k];
-}
-
-__global__ void k_bin_row_counts(HintArgs a, int32_t* __restrict__ cnt) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.nbins) return;
-    int x0, x1, y0, y1;
-    window(a.gr, b, x0, x1, y0, y1);
-    int n = 0;
-    for (int by = y0; by <= y1; ++by)
-        for (int bx = x0; bx <= x1; ++bx) {
-            int bb = by * a.gr.nbx + bx;
-            n += a.bin_start[bb + 1] - a.bin_start[bb];
-        }
-    cnt[a.first_bvirt + b] = n;
+// The three row-count passes in one launch (they write disjoint rows of
+// cnt): cell rows, then macro rows (when mb > 0 workgroups), then bin rows.
+__global__ void k_hint_row_counts(HintArgs a, int32_t n_inst, const int32_t* __restrict__ nmac,
+                                  const int32_t* __restrict__ nwin, int32_t n_macro, int32_t first_mvirt,
+                                  const int32_t* __restrict__ mstart, int32_t cb, int32_t mb,
+                                  int32_t* __restrict__ cnt) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x);
+    const int64_t t = static_cast<int64_t>(threadIdx.x);
+    if (b < cb) {
+        const int64_t r = static_cast<int64_t>(b) * kBT + t;
+        if (r < n_inst) cnt[r] = nmac[r] + nwin[r];
+    } else if (b < cb + mb) {
+        const int64_t k = static_cast<int64_t>(b - cb) * kBT + t;
+        if (k < n_macro) cnt[first_mvirt + k] = mstart[k + 1] - mstart[k];
+    } else {
+        const int64_t bin = static_cast<int64_t>(b - cb - mb) * kBT + t;
+        if (bin >= a.nbins) return;
+        int x0, x1, y0, y1;
+        window(a.gr, static_cast<int>(bin), x0, x1, y0, y1);
+        int n = 0;
+        for (int by = y0; by <= y1; ++by)
+            for (int bx = x0; bx <= x1; ++bx) {
+                const int bb = by * a.gr.nbx + bx;
+                n += a.bin_start[bb + 1] - a.bin_start[bb];
+            }
+        cnt[a.first_bvirt + bin] = n;
+    }
 }
 
 // Cell rows: macro entries (ascending macro) then window bins (row-major).
@@ -759,17 +762,13 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     if (use_macros) bucket_sort(g, g.pair_mac.p, n_pairs, n_macro, g.mlist, g.mstart, s, false);
 
     // 6. row counts and offsets (execution order)
-    hipLaunchKernelGGL(k_cell_hint_cnt, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, n_inst, g.nmac.p, g.nwin.p,
-                       g.hint_cnt.p);
-    AHR_LAUNCHED("k_cell_hint_cnt");
-    if (use_macros) {
-        hipLaunchKernelGGL(k_macro_row_cnt, dim3(grid_for(n_macro, kBT)), dim3(kBT), 0, s, n_macro, g.first_mvirt,
-                           g.mstart.p, g.hint_cnt.p);
-        AHR_LAUNCHED("k_macro_row_cnt");
-    }
-    if (bin_hints) {
-        hipLaunchKernelGGL(k_bin_row_counts, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s, a, g.hint_cnt.p);
-        AHR_LAUNCHED("k_bin_row_counts");
+    {
+        const int32_t cb = static_cast<int32_t>(grid_for(n_inst, kBT));
+        const int32_t mb = use_macros ? static_cast<int32_t>(grid_for(n_macro, kBT)) : 0;
+        const int32_t bb = bin_hints ? static_cast<int32_t>(grid_for(nbins, kBT)) : 0;
+        hipLaunchKernelGGL(k_hint_row_counts, dim3(cb + mb + bb), dim3(kBT), 0, s, a, n_inst, g.nmac.p, g.nwin.p,
+                           n_macro, g.first_mvirt, g.mstart.p, cb, mb, g.hint_cnt.p);
+        AHR_LAUNCHED("k_hint_row_counts");
     }
     // Every entry is one side of a (cell, macro) pair or of a (hint cell,
     // window bin) pair, so the entries number at most twice the pairs plus
