@@ -293,6 +293,41 @@ def test_density_conserves_area_and_phi_sign():
     assert np.all(np.sign(g.phi) == np.sign(g.density - 1.0))
 
 
+def brute_density(nl, nbx, nby, pos):
+    """Per-bin density by loops: each movable std cell's area goes to the bin
+    holding its centre (float32 decision, clamped), each macro's footprint is
+    clipped against every bin rectangle."""
+    d = [float(v) for v in nl["die"]]
+    bw, bh = (d[2] - d[0]) / nbx, (d[3] - d[1]) / nby
+    bw32 = np.float32(np.float32(nl["die"][2] - nl["die"][0]) / np.float32(nbx))
+    bh32 = np.float32(np.float32(nl["die"][3] - nl["die"][1]) / np.float32(nby))
+    area = [0.0] * (nbx * nby)
+    for i in range(nl["n_inst"]):
+        f = int(nl["node_flags"][i])
+        w, h = float(nl["node_size"][i, 0]), float(nl["node_size"][i, 1])
+        x, y = np.float32(pos[i, 0]), np.float32(pos[i, 1])
+        if f == 0:
+            bx = min(max(int(math.floor(np.float32((x - nl["die"][0]) / bw32))), 0), nbx - 1)
+            by = min(max(int(math.floor(np.float32((y - nl["die"][1]) / bh32))), 0), nby - 1)
+            area[by * nbx + bx] += w * h
+        elif f & 2:
+            for by in range(nby):
+                for bx in range(nbx):
+                    x0, x1 = d[0] + bx * bw, d[0] + (bx + 1) * bw
+                    y0, y1 = d[1] + by * bh, d[1] + (by + 1) * bh
+                    ox = min(float(x) + w / 2, x1) - max(float(x) - w / 2, x0)
+                    oy = min(float(y) + h / 2, y1) - max(float(y) - h / 2, y0)
+                    if ox > 0 and oy > 0:
+                        area[by * nbx + bx] += ox * oy
+    return [a / (bw * bh) for a in area]
+
+
+def test_brute_density_matches_oracle():
+    nl, g = tiny_hint_graph(movable=True, nbx=10, nby=7)
+    ref = brute_density(nl, 10, 7, nl["g0"][:, :2])
+    assert np.allclose(g.density, ref, rtol=1e-12, atol=1e-15)
+
+
 def test_hint_edges_brute_force():
     nl, g = tiny_hint_graph(movable=True, nbx=10, nby=10, detection_ratio=0.3)
     gr = g.grid
@@ -302,12 +337,21 @@ def test_hint_edges_brute_force():
     A = dense(g)
     hx = O.window_half(0.3, 10)
     assert hx == 1
+    # phi_b and baseWeight from their definitions, not from the oracle's graph
+    dens = brute_density(nl, 10, 10, pos)
+    phis = [2.0 / (1.0 + math.exp(-4.0 * (D - 1.0))) - 1.0 for D in dens]
+    acc, _ = brute_netlist_q(nl, 10)
+    qsum, cnt = {}, {}
+    for (r, c), q in acc.items():
+        qsum[r] = qsum.get(r, 0) + q
+        cnt[r] = cnt.get(r, 0) + 1
     checked = 0
     for i in np.flatnonzero(std):
-        if g.qdeg[i] == 0:
+        if i not in cnt:
+            assert g.qdeg[i] == 0
             assert np.all(A[i, g.first_mvirt:] == 0)
             continue
-        bwi = g.base_weight[i]
+        bwi = qsum[i] / Q / cnt[i]
         x32, y32 = np.float32(pos[i, 0]), np.float32(pos[i, 1])
         bxi = min(max(int(math.floor(float(np.float32((x32 - gr.xl32) / gr.bw32)))), 0), gr.nbx - 1)
         byi = min(max(int(math.floor(float(np.float32((y32 - gr.yl32) / gr.bh32)))), 0), gr.nby - 1)
@@ -321,7 +365,7 @@ def test_hint_edges_brute_force():
             cx = gr.xl + (bx + 0.5) * gr.bw
             cy = gr.yl + (by + 0.5) * gr.bh
             mr = max(abs(float(x32) - cx) / (gr.bw / 2), abs(float(y32) - cy) / (gr.bh / 2))
-            ref = -math.exp(-mr) * g.phi[b] * bwi
+            ref = -math.exp(-mr) * phis[b] * bwi
             assert math.isclose(v, ref, rel_tol=1e-12, abs_tol=1e-300)
             checked += 1
         for k, m in enumerate(g.macro_ids):
