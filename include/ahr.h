@@ -210,15 +210,16 @@ ahr_status ahr_refine(ahr_graph* gr, const ahr_filter_spec* spec, const float* g
                       int32_t ncols, int32_t T_hint, float gamma, float* out,
                       void* stream);
 
-/* Half-perimeter wirelength of the graph's netlist for every placement held
- * in `g` ([n_inst][ncols], ncols even): for each column pair c,
- * out[c] = sum over nets of (max - min) pin x + (max - min) pin y, pin
- * position = instance position + pin offset, accumulated in float64 in a
- * fixed order.  `out` is a device array of ncols/2 doubles.  Calls that
- * overlap in time on one device race on a shared partial-sum buffer.
- * Asynchronous. */
-ahr_status ahr_hpwl(const ahr_graph* gr, const float* g, int32_t ncols, double* out,
-                    void* stream);
+/* Half-perimeter wirelength of the netlist `nl` (the paper's wirelength
+ * score; Section II-B names HPWL as what the WA model approximates) for
+ * every placement held in `g` ([n_inst][ncols], ncols 2, 4 or 8): for each
+ * column pair c, out[c] = sum over nets of (max - min) pin x + (max - min)
+ * pin y, pin position = instance position + pin offset, over the netlist's
+ * own pins (no macro pin expansion, no added nodes), accumulated in float64
+ * in a fixed order.  `out` is a device array of ncols/2 doubles.  Needs no
+ * graph.  Its partial sums come from the library's stream-ordered pool, so
+ * calls on different streams may overlap.  Asynchronous. */
+ahr_status ahr_hpwl(const ahr_netlist* nl, const float* g, int32_t ncols, double* out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of the filter (a project addition; the paper has no

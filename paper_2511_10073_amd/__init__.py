@@ -107,7 +107,7 @@ def load() -> ctypes.CDLL:
         "ahr_graph_export": [vp, ctypes.POINTER(_GraphHost), vp],
         "ahr_filter": [vp, ctypes.POINTER(_FilterSpec), vp, vp, i32, vp],
         "ahr_refine": [vp, ctypes.POINTER(_FilterSpec), vp, i32, i32, ctypes.c_float, vp, vp],
-        "ahr_hpwl": [vp, vp, i32, vp, vp],
+        "ahr_hpwl": [ctypes.POINTER(_Netlist), vp, i32, vp, vp],
         "ahr_filter_learned": [vp, ctypes.POINTER(_FilterSpec), ctypes.POINTER(_Mlp), vp, vp, i32,
                                ctypes.POINTER(i32), vp],
         "ahr_filter_features": [vp, ctypes.POINTER(_FilterSpec), vp, i32, vp, vp, vp, vp],
@@ -255,6 +255,14 @@ class Netlist:
                           self.node_flags.data_ptr(), self.node_size.data_ptr(), (ctypes.c_float * 4)(*self.die))
 
 
+def hpwl(netlist: Netlist, g, out=None, stream=None):
+    """Per column pair HPWL of the placements in g [n_inst, C] (device float64 [C/2])."""
+    if out is None:
+        out = torch.empty(g.shape[1] // 2, dtype=torch.float64, device=g.device)
+    _check(load().ahr_hpwl(ctypes.byref(netlist.c), _ptr(g), g.shape[1], _ptr(out), _stream(stream)))
+    return out
+
+
 def hint_params(nbx=8, nby=8, detection_ratio=0.1, bin_capacity=1.0, mu=4.0, clique_max=10, flags=ALL_HINTS):
     return _HintParams(nbx, nby, detection_ratio, bin_capacity, mu, clique_max, flags)
 
@@ -360,10 +368,8 @@ class Graph:
         return feats, hops, stats
 
     def hpwl(self, g, out=None, stream=None):
-        if out is None:
-            out = torch.empty(g.shape[1] // 2, dtype=torch.float64, device=g.device)
-        _check(load().ahr_hpwl(self.h, _ptr(g), g.shape[1], _ptr(out), _stream(stream)))
-        return out
+        """HPWL of the graph's netlist (ahr_hpwl needs only the netlist)."""
+        return hpwl(self.netlist, g, out, stream)
 
 
 class Batch:

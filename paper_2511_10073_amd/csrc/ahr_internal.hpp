@@ -322,8 +322,12 @@ void relax(Graph& g, const float* gcur, const float* gt, float* gnext, int32_t n
            float gamma, hipStream_t s);
 // normalise + the unpinned chain T X, T^2 X, T^3 X into g.zh (scaled coordinates)
 void run_hops(Graph& g, const ahr_filter_spec& spec, const float* in, int32_t ncols, hipStream_t s);
-// hpwl.hip
-void run_hpwl(const Graph& g, const float* pos, int32_t ncols, double* out, hipStream_t s);
+// hpwl.hip: run_hpwl draws its partial sums from the pool; hpwl_launch
+// takes a buffer of hpwl_partial_elems() doubles (enough for any netlist)
+void run_hpwl(const ahr_netlist& nl, const float* pos, int32_t ncols, double* out, hipStream_t s);
+void hpwl_launch(const ahr_netlist& nl, const float* pos, int32_t ncols, double* out, double* partial,
+                 hipStream_t s);
+size_t hpwl_partial_elems();
 // mlp.hip
 void run_learned(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[3], const float* in,
                  float* out, int32_t ncols, float* feats, float* hops, float* stats, hipStream_t s);

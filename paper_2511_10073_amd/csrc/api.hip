@@ -33,8 +33,11 @@ int32_t hint_count(const Graph& g, hipStream_t s) {
 
 Graph::~Graph() {
     // one stream: its later work (and any other stream, through the block
-    // events) reuses the memory only after this graph's work; else wait
+    // events) reuses the memory only after this graph's work.  Several
+    // streams: wait for the whole device first (a null-stream wait would not
+    // cover non-blocking streams), then release.
     hipStream_t s = stream_uses == 1 ? work_stream : nullptr;
+    if (stream_uses > 1) (void)hipDeviceSynchronize();
     if (xnet_ready) (void)hipStreamWaitEvent(s, xnet_ready, 0);   // the side stream's copy
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_len, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
@@ -81,7 +84,6 @@ Graph::~Graph() {
     gt.release(s);
     scan_tmp.release(s);
     i64a.release(s);
-    if (stream_uses != 1) (void)hipStreamSynchronize(s);
     if (xnet_fork) (void)hipEventDestroy(xnet_fork);
     if (xnet_ready) (void)hipEventDestroy(xnet_ready);
 }
@@ -217,8 +219,11 @@ ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
     return guarded([&]() -> ahr_status {
         const auto* g = reinterpret_cast<const ahr::Graph*>(h);
         // entry counts not read yet come from the row pointers, on the
-        // stream the graph's work went to
+        // stream the graph's work went to (after a device wait when it went
+        // to several: the null stream does not wait for non-blocking ones)
         const hipStream_t s = g->stream_uses == 1 ? g->work_stream : nullptr;
+        if (g->stream_uses > 1 && (g->nnz_net < 0 || (g->has_hints && g->nnz_hint < 0)))
+            AHR_HIP(hipDeviceSynchronize());
         const int32_t nnz_net = ahr::net_count(*g, s);
         const int32_t nnz_hint = g->has_hints ? ahr::hint_count(*g, s) : 0;
         std::memset(info, 0, sizeof *info);
@@ -533,13 +538,13 @@ ahr_status ahr_filter_get_tune(int32_t* lanes_per_row, int32_t* nontemporal) {
     return AHR_OK;
 }
 
-ahr_status ahr_hpwl(const ahr_graph* h, const float* g, int32_t ncols, double* out, void* stream) {
-    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+ahr_status ahr_hpwl(const ahr_netlist* nl, const float* g, int32_t ncols, double* out, void* stream) {
+    ahr_status st;
+    if ((st = check_netlist(nl)) != AHR_OK) return st;
     if (!g || !out) return fail(AHR_EINVAL, "g/out is NULL");
     if (ncols != 2 && ncols != 4 && ncols != 8) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
     return guarded([&]() -> ahr_status {
-        reinterpret_cast<const ahr::Graph*>(h)->use_stream(as_stream(stream));
-        ahr::run_hpwl(*reinterpret_cast<const ahr::Graph*>(h), g, ncols, out, as_stream(stream));
+        ahr::run_hpwl(*nl, g, ncols, out, as_stream(stream));
         return AHR_OK;
     });
 }

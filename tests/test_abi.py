@@ -55,7 +55,9 @@ def test_invalid_arguments_fail_before_any_device_work():
     assert lib.ahr_filter(ctypes.c_void_p(8), ctypes.byref(spec), 8, 16, 2, None) == A.EINVAL
     spec = A.filter_spec(ks=(4,), alphas=(1.0,))
     assert lib.ahr_filter(None, ctypes.byref(spec), 8, 16, 2, None) == A.EINVAL
-    assert lib.ahr_hpwl(ctypes.c_void_p(8), 8, 3, 8, None) == A.EINVAL
+    assert lib.ahr_hpwl(None, 8, 2, 8, None) == A.EINVAL
+    assert lib.ahr_hpwl(ctypes.byref(nl2), 8, 3, 8, None) == A.EINVAL
+    assert lib.ahr_hpwl(ctypes.byref(nl2), None, 2, 8, None) == A.EINVAL
     assert lib.ahr_refine(ctypes.c_void_p(8), ctypes.byref(spec), 8, 2, 1, 1.5, 16, None) == A.EINVAL
 
 

@@ -80,3 +80,50 @@ def test_graph_on_two_streams_freed_with_wait():
     torch.cuda.synchronize()
     for o in (o1, o2, o3):
         assert torch.equal(o, ref)
+
+
+def test_graph_on_two_streams_closed_without_join():
+    """close() of a graph whose last work went to a non-blocking stream that
+    was never joined back: the destructor waits for the device before the
+    memory can be taken by a graph on a third stream."""
+    net, x, p, spec = setup()
+    ref = refine_alone(net, x, p, spec)
+    side, third = torch.cuda.Stream(), torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    side.wait_stream(main)
+    third.wait_stream(main)
+    outs = []
+    for _ in range(3):
+        gr = A.Graph(net, p, x, stream=main)
+        outs.append(gr.refine(spec, x, 2, 0.5, stream=main))
+        side.wait_stream(main)
+        outs.append(gr.refine(spec, x, 2, 0.5, stream=side))
+        gr.close()                                      # side not joined: the close waits for the device
+        g2 = A.Graph(net, p, x, stream=third)
+        outs.append(g2.refine(spec, x, 2, 0.5, stream=third))
+        g2.close()
+    torch.cuda.synchronize()
+    for o in outs:
+        assert torch.equal(o, ref)
+
+
+def test_hpwl_calls_overlap_on_two_streams():
+    """ahr_hpwl's partial sums are per call: two streams computing HPWL of
+    different placements at the same time get what each gets alone."""
+    net, x, p, spec = setup()
+    y = x.clone()
+    y[:, 0] *= 0.5
+    ref_x = A.hpwl(net, x).clone()
+    ref_y = A.hpwl(net, y).clone()
+    torch.cuda.synchronize()
+    assert not torch.equal(ref_x, ref_y)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    ox, oy = [], []
+    for _ in range(50):
+        ox.append(A.hpwl(net, x, stream=s1))
+        oy.append(A.hpwl(net, y, stream=s2))
+    torch.cuda.synchronize()
+    for a, b in zip(ox, oy):
+        assert torch.equal(a, ref_x) and torch.equal(b, ref_y)
