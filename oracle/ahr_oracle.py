@@ -547,3 +547,54 @@ def hpwl(nl, G):
         hy = np.maximum.reduceat(py, starts) - np.minimum.reduceat(py, starts)
         per_net[nonempty, c] = hx + hy
     return per_net.sum(axis=0), per_net
+
+
+# ---------------------------------------------------------------------------
+# GiFt: the unsigned multi-band initializer that produces Algorithm 1's input
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class GiftBank:
+    """Section IV eq. "GiFt filter": H = sum_b alpha_b Atilde_{sigma_b}^{k_b}.
+    The paper's bands are Atilde_2^2 (high), Atilde_4^2 (mid) and Atilde_4^4
+    (low), i.e. (k, sigma) = (2, 2), (2, 4), (4, 4); the weights are tuning
+    parameters that sum to 1 (Table "Parameter space": the high-band weight is
+    1 - low - mid).  The default weights are a reading (none is printed)."""
+    ks: tuple = (2, 2, 4)
+    sigmas: tuple = (2.0, 4.0, 4.0)
+    alphas: tuple = (0.2, 0.3, 0.5)
+
+
+def gift_operator(g: Graph, sigma):
+    """Section IV: A_sigma = A + sigma I, D_sigma = D + sigma I and the
+    augmented normalised adjacency Atilde_sigma = D_sigma^-1/2 A_sigma
+    D_sigma^-1/2 (eq. "GiFt" for sigma = 0).  Reading R12: a row with
+    d_i + sigma = 0 (an isolated node without self-loop) is left unchanged,
+    which is also what Atilde_sigma does to an isolated node for sigma > 0."""
+    A = g.adjacency()
+    n = g.n_tot
+    d = np.asarray(A.sum(axis=1)).ravel() + sigma
+    s = np.zeros(n)
+    nz = d > 0
+    s[nz] = 1.0 / np.sqrt(d[nz])
+    At = sp.diags(s) @ (A + sigma * sp.identity(n)) @ sp.diags(s)
+    return (At + sp.diags((~nz).astype(np.float64))).tocsr()
+
+
+def gift(nl, g: Graph, bank: GiftBank, G, pin=True, return_full=False):
+    """GSP-based initialization (Section IV, steps 2-3): the bank applied to
+    the expanded signal (the instance graph's added star nodes carry the mean
+    of their pins, reading R10), then every fixed row reset to its input.
+    The graph must carry no area hints (GiFt runs before them)."""
+    assert g.hint_val.size == 0, "GiFt filters the netlist graph (no area hints)"
+    X = expand_signal(nl, g, G)
+    out = np.zeros_like(X)
+    for k, sigma, a in zip(bank.ks, bank.sigmas, bank.alphas):
+        At = gift_operator(g, sigma)
+        Y = X.copy()
+        for _ in range(k):
+            Y = At @ Y
+        out += a * Y
+    if pin:
+        out[g.pinned] = X[g.pinned]
+    return out if return_full else out[:g.n_inst]
