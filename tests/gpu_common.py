@@ -42,6 +42,24 @@ def rel_err(y, ref, rows):
     return float(np.linalg.norm(y - ref) / den)
 
 
+def row_err(y, ref, rows):
+    """Largest error of any single element over the given rows, relative to
+    the largest centred magnitude of the reference there (a per-row bound
+    next to the norm: a few rows off by a site cannot hide in it)."""
+    y = np.asarray(y, np.float64)[rows]
+    ref = np.asarray(ref, np.float64)[rows]
+    scale = np.max(np.abs(ref - ref.mean(axis=0)))
+    return float(np.max(np.abs(y - ref)) / scale) if y.size else 0.0
+
+
+def check_filter(y, ref, rows, tol=1e-5):
+    """Filter parity: centred relative Frobenius error and the per-element
+    error (row_err) both within tol.  Returns the Frobenius error."""
+    rel, row = rel_err(y, ref, rows), row_err(y, ref, rows)
+    assert rel <= tol and row <= tol, f"centred rel err {rel:.3e}, max element err {row:.3e} (bound {tol:g})"
+    return rel
+
+
 def sorted_rows(row_ptr, col, val):
     """Entries ordered by (row, col): the canonical order of a CSR."""
     n = row_ptr.size - 1

@@ -113,8 +113,7 @@ def test_specs_bit_exact_and_oracle(batch, name):
     for nl, p, lo, hi in zip(batch["nls"], batch["ps"], b.offsets[:-1], b.offsets[1:]):
         og = O.build_graph(nl, p, nl["g0"][:, :2])
         want = O.apply_filter(nl, og, so, nl["g0"])
-        err = U.rel_err(y[lo:hi], want, U.movable_rows(nl))
-        assert err <= FILTER_TOL, f"{nl['name'] if 'name' in nl else lo}: {err:.3e}"
+        U.check_filter(y[lo:hi], want, U.movable_rows(nl))
 
 
 def test_graph_replays_match_direct_launch(batch):

@@ -61,7 +61,7 @@ def check_close(out, ref, mov):
     if np.linalg.norm(ref[mov] - ref[mov].mean(axis=0)) == 0:
         assert np.allclose(out[mov], ref[mov], rtol=1e-6, atol=1e-6)
     else:
-        assert U.rel_err(out, ref, mov) <= FILTER_TOL
+        U.check_filter(out, ref, mov)
 
 
 BANK = O.FilterSpec(ks=(2, 4, 8), alphas=(0.2, 0.3, 0.5))

@@ -81,7 +81,7 @@ def test_full_size_matches_oracle(cfg_name):
     ref = O.apply_filter(nl, og, spec, nl["g0"])
     print(f"[{cfg.name}] oracle filter done", flush=True)
     mov = U.movable_rows(nl)
-    err = U.rel_err(out, ref, mov)
+    err = U.check_filter(out, ref, mov)
     print(f"[{cfg.name}] filter rel err {err:.3e}", flush=True)
     assert err <= FILTER_TOL
     assert np.array_equal(out[~mov], nl["g0"][~mov])
@@ -121,9 +121,56 @@ def test_full_batched_workload():
             nl, p = nls[i], ps[i]
             og = O.build_graph(nl, p, nl["g0"][:, :2])
             ref = O.apply_filter(nl, og, spec, nl["g0"])
-            err = U.rel_err(y[b.offsets[i]:b.offsets[i + 1]], ref, U.movable_rows(nl))
+            err = U.check_filter(y[b.offsets[i]:b.offsets[i + 1]], ref, U.movable_rows(nl))
             print(f"[batched] member {i} ({nl['n_inst']} instances) rel err {err:.3e}", flush=True)
             assert err <= FILTER_TOL
     finally:
         A.filter_tune(*saved)
         b.close()
+
+
+@pytest.fixture(scope="module")
+def large_rounds():
+    """large-2.2M: Algorithm 1 as the benchmark times it (T_hint = 3,
+    gamma = 0.5, the order-8 bank on 4 columns), one round per call so that
+    every round's GPU input placement is kept for the oracle."""
+    nl = N.generate(N.LARGE)
+    p = U.params32(O.HintParams(nbx=32, nby=32))
+    spec = U.spec32(BANK)
+    cs = U.to_c_spec(A, spec)
+    net = A.Netlist(nl)
+    x = torch.as_tensor(nl["g0"]).cuda()
+    gr = A.Graph(net, U.to_c_params(A, p), x)
+    try:
+        cur = [x]
+        for r in range(3):
+            cur.append(gr.refine(cs, cur[-1], 1, 0.5))
+        full = gr.refine(cs, x, 3, 0.5)
+        torch.cuda.synchronize()
+        placements = [c.cpu().numpy() for c in cur]
+        full = full.cpu().numpy()
+    finally:
+        gr.close()
+    print(f"[large refine] rounds done on the GPU", flush=True)
+    return dict(nl=nl, p=p, spec=spec, placements=placements, full=full)
+
+
+def test_large_refine_three_rounds_in_one_call_equal_chained_rounds(large_rounds):
+    lr = large_rounds
+    assert np.array_equal(lr["full"].view(np.uint32), lr["placements"][3].view(np.uint32))
+    fixed = ~U.movable_rows(lr["nl"])
+    for r in range(4):
+        assert np.array_equal(lr["placements"][r][fixed], lr["nl"]["g0"][fixed])
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_large_refine_round_matches_oracle(large_rounds, r):
+    """Round r of Algorithm 1 at large-2.2M: the oracle rebuilds the graph
+    from the GPU's round-r placement (structure is decided in float32 on
+    both sides) and relaxes; centred and per-element error within 1e-5."""
+    lr = large_rounds
+    nl, G = lr["nl"], lr["placements"][r]
+    ref = O.refine(nl, lr["p"], lr["spec"], G, 1, 0.5)
+    err = U.check_filter(lr["placements"][r + 1], ref, U.movable_rows(nl))
+    print(f"[large refine] round {r}: rel err {err:.3e}, element err "
+          f"{U.row_err(lr['placements'][r + 1], ref, U.movable_rows(nl)):.3e}", flush=True)

@@ -35,18 +35,27 @@ def rand_feats(n, seed):
     return F
 
 
-def test_mlp_forward_matches_oracle():
+@pytest.mark.parametrize("n", [20011, 16 * 97 + 1, 7])
+def test_mlp_forward_matches_oracle(n):
+    """Samples go 16 to a matrix-core tile; n leaves a partial last tile of
+    11, 1 and 7 (no full tile) samples, each checked on its own."""
     p = rand_params(1)
-    F = rand_feats(20011, 2)
+    F = rand_feats(n, 2)
     o = A.mlp_forward(torch.as_tensor(p).cuda(), torch.as_tensor(F).cuda()).cpu().numpy()
     ref, _ = M.forward(p, F[:, :M.NFEAT].astype(np.float64))
     d = np.abs(o - ref)
     scale = np.sqrt(np.mean(ref ** 2))
-    print("forward: max", d.max() / scale, "mean", d.mean() / scale)
+    tail = d[n - n % 16:] if n % 16 else d[-16:]
+    print(f"forward n={n}: max {d.max() / scale:.3e} mean {d.mean() / scale:.3e} tail max {tail.max() / scale:.3e}")
     # float32 accumulation order may move a hidden activation across a
-    # bfloat16 rounding boundary; such flips are rare and one ulp wide
-    assert np.mean(d) <= 1e-5 * scale
-    assert np.quantile(d, 0.999) <= 2e-3 * scale
+    # bfloat16 rounding boundary; such flips are rare and one ulp wide: a
+    # flip changes one hidden value by 2^-8 of itself, far below 1e-2 of the
+    # output scale
+    assert np.max(d) <= 1e-2 * scale
+    if n >= 1000:
+        assert np.mean(d) <= 1e-5 * scale
+        assert np.quantile(d, 0.999) <= 2e-3 * scale
+    assert np.max(tail) <= 2e-3 * scale
 
 
 def test_mlp_grad_matches_oracle():
