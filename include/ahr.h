@@ -113,6 +113,18 @@ typedef struct ahr_filter_spec {
     float lambda_fixed;         /* used when lambda_mode == AHR_LAMBDA_FIXED; >= 0 */
 } ahr_filter_spec;
 
+/* GiFt's multi-band bank (Section IV eq. "GiFt filter"):
+ * H = sum_b alpha[b] Atilde_{sigma[b]}^k[b] with the augmented normalised
+ * adjacency Atilde_sigma = D_sigma^-1/2 (A + sigma I) D_sigma^-1/2,
+ * D_sigma = D + sigma I (Section IV eq. "GiFt" and the self-loop amendment).
+ * The paper's bands are (k, sigma) = (2, 2) high, (2, 4) mid, (4, 4) low. */
+typedef struct ahr_gift_spec {
+    int32_t nbands;             /* 1..AHR_MAX_BANDS */
+    int32_t k[AHR_MAX_BANDS];   /* [0, 64] */
+    float alpha[AHR_MAX_BANDS];
+    float sigma[AHR_MAX_BANDS]; /* >= 0; bands with equal sigma share one chain of products */
+} ahr_gift_spec;
+
 typedef struct ahr_graph ahr_graph;   /* opaque; owns its device memory */
 
 /* Sizes and node ranges of a built graph (host struct).  Canonical node
@@ -200,6 +212,18 @@ void ahr_graph_destroy(ahr_graph* gr);
 ahr_status ahr_filter(ahr_graph* gr, const ahr_filter_spec* spec,
                       const float* in, float* out, int32_t ncols, void* stream);
 
+/* GSP-based initialization (Section IV, steps 2 and 3): apply the GiFt
+ * bank `spec` to `in` ([n_inst][ncols]; movable instances at sampled
+ * positions, fixed ones at theirs) on the graph's netlist part, then reset
+ * every fixed row to its input; the result is Algorithm 1's g^(0).  The
+ * graph must carry no area hints (built with AHR_MACRO_HINTS and
+ * AHR_BIN_HINTS off, with a placement for its execution order); the
+ * instance graph of Section IV treats macros as points, so
+ * AHR_EXPAND_MACRO_PINS is normally off too.  Added star nodes carry the mean
+ * of their pins.  in and out must not overlap.  Asynchronous. */
+ahr_status ahr_gift(ahr_graph* gr, const ahr_gift_spec* spec, const float* in, float* out, int32_t ncols,
+                    void* stream);
+
 /* Algorithm 1 (Section V): for r = 0 .. T_hint-1, rebuild the hints from
  * columns 0 and 1 of g^(r), filter all columns, and relax
  * g^(r+1) = (1 - gamma) g^(r) + gamma g~ on movable rows (fixed rows keep
@@ -220,6 +244,33 @@ ahr_status ahr_refine(ahr_graph* gr, const ahr_filter_spec* spec, const float* g
  * graph.  Its partial sums come from the library's stream-ordered pool, so
  * calls on different streams may overlap.  Asynchronous. */
 ahr_status ahr_hpwl(const ahr_netlist* nl, const float* g, int32_t ncols, double* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Weighted-average (WA) wirelength and its gradient (Section II-B,
+ * "Wirelength model"): the smooth wirelength of the electrostatic global
+ * placer the initializer hands its placement to.  For net e and axis x,
+ *   xbar+_e = sum_i x_i exp(x_i/gamma) / sum_i exp(x_i/gamma),
+ *   xbar-_e = sum_i x_i exp(-x_i/gamma) / sum_i exp(-x_i/gamma),
+ * over the netlist's own pins (pin = instance position + pin offset), and
+ *   W = sum_e (xbar+_e - xbar-_e) + (ybar+_e - ybar-_e)   (no net weights).
+ * Evaluated in float64 (each exponential taken relative to the net's
+ * extreme coordinate, which cancels in the ratio).  The gradient of an
+ * instance is the sum of its pins' gradients, added exactly in int64 fixed
+ * point (2^-40 units; instances with fewer than 2^20 pins), rounded once to
+ * float32: deterministic.
+ * ------------------------------------------------------------------------ */
+typedef struct ahr_wl ahr_wl;          /* opaque: a netlist's instance -> pin index */
+
+/* Index the pins of every instance of `nl` (device arrays, kept by the
+ * handle: they must outlive it).  Synchronises `stream`. */
+ahr_status ahr_wl_create(const ahr_netlist* nl, void* stream, ahr_wl** out);
+
+/* WA wirelength of every placement in g ([n_inst][ncols], ncols 2, 4 or 8;
+ * columns 2c, 2c+1 are placement c): wl (device, ncols/2 doubles) and, if
+ * grad is not NULL, dW/dg (device [n_inst][ncols] float32).  gamma > 0.
+ * Work buffers come from the library's pool.  Asynchronous. */
+ahr_status ahr_wa(ahr_wl* h, const float* g, int32_t ncols, float gamma, double* wl, float* grad, void* stream);
+void ahr_wl_destroy(ahr_wl* h);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of the filter (a project addition; the paper has no
@@ -377,6 +428,9 @@ typedef struct ahr_profile {
     double hop_bytes;           /* algorithmic bytes of every timed hop launch (see ahr_filter) */
     double mlp_ms;              /* learned-filter MLP kernel */
     int64_t mlp_calls;
+    double wa_ms;               /* WA wirelength (+ gradient) calls */
+    int64_t wa_calls;
+    double wa_bytes;            /* their algorithmic bytes (see ahr_wa) */
 } ahr_profile;
 
 /* Event timing for subsequent calls: 0 off, 1 every stage and hop launch

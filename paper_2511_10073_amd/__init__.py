@@ -53,6 +53,11 @@ class _FilterSpec(ctypes.Structure):
                 ("sigma", ctypes.c_float), ("lambda_mode", ctypes.c_int32), ("lambda_fixed", ctypes.c_float)]
 
 
+class _GiftSpec(ctypes.Structure):
+    _fields_ = [("nbands", ctypes.c_int32), ("k", ctypes.c_int32 * 4), ("alpha", ctypes.c_float * 4),
+                ("sigma", ctypes.c_float * 4)]
+
+
 class _GraphInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "n_inst", "n_tot", "first_mpin", "first_star", "first_mvirt", "first_bvirt", "nnz_net", "nnz_hint",
@@ -75,7 +80,8 @@ class _Profile(ctypes.Structure):
                                                  "relax_ms", "hpwl_ms")]
                 + [(n, ctypes.c_int64) for n in ("build_calls", "hints_calls", "norm_calls", "expand_calls",
                                                   "hop_launches", "relax_calls", "hpwl_calls")]
-                + [("hop_bytes", ctypes.c_double), ("mlp_ms", ctypes.c_double), ("mlp_calls", ctypes.c_int64)])
+                + [("hop_bytes", ctypes.c_double), ("mlp_ms", ctypes.c_double), ("mlp_calls", ctypes.c_int64),
+                   ("wa_ms", ctypes.c_double), ("wa_calls", ctypes.c_int64), ("wa_bytes", ctypes.c_double)])
 
 
 class _Mlp(ctypes.Structure):
@@ -106,8 +112,11 @@ def load() -> ctypes.CDLL:
         "ahr_graph_get_info": [vp, ctypes.POINTER(_GraphInfo)],
         "ahr_graph_export": [vp, ctypes.POINTER(_GraphHost), vp],
         "ahr_filter": [vp, ctypes.POINTER(_FilterSpec), vp, vp, i32, vp],
+        "ahr_gift": [vp, ctypes.POINTER(_GiftSpec), vp, vp, i32, vp],
         "ahr_refine": [vp, ctypes.POINTER(_FilterSpec), vp, i32, i32, ctypes.c_float, vp, vp],
         "ahr_hpwl": [ctypes.POINTER(_Netlist), vp, i32, vp, vp],
+        "ahr_wl_create": [ctypes.POINTER(_Netlist), vp, ctypes.POINTER(vp)],
+        "ahr_wa": [vp, vp, i32, ctypes.c_float, vp, vp, vp],
         "ahr_filter_learned": [vp, ctypes.POINTER(_FilterSpec), ctypes.POINTER(_Mlp), vp, vp, i32,
                                ctypes.POINTER(i32), vp],
         "ahr_filter_features": [vp, ctypes.POINTER(_FilterSpec), vp, i32, vp, vp, vp, vp],
@@ -136,6 +145,8 @@ def load() -> ctypes.CDLL:
     lib.ahr_profile_enable.restype = ctypes.c_int32
     lib.ahr_profile_read.argtypes = [ctypes.POINTER(_Profile), i32]
     lib.ahr_profile_read.restype = ctypes.c_int32
+    lib.ahr_wl_destroy.argtypes = [vp]
+    lib.ahr_wl_destroy.restype = None
     lib.ahr_graph_destroy.argtypes = [vp]
     lib.ahr_graph_destroy.restype = None
     lib.ahr_batch_destroy.argtypes = [vp]
@@ -275,6 +286,15 @@ def filter_spec(ks=(4,), alphas=(1.0,), sigma=0.0, lambda_mode=LAMBDA_GERSHGORIN
     return _FilterSpec(len(ks), k, a, sigma, lambda_mode, lambda_fixed)
 
 
+def gift_spec(ks=(2, 2, 4), sigmas=(2.0, 4.0, 4.0), alphas=(0.2, 0.3, 0.5)):
+    """GiFt bank: bands (k, sigma) with weights alpha (Section IV)."""
+    ks, sigmas, alphas = list(ks), list(sigmas), list(alphas)
+    assert len(ks) == len(sigmas) == len(alphas) and 1 <= len(ks) <= 4
+    pad = 4 - len(ks)
+    return _GiftSpec(len(ks), (ctypes.c_int32 * 4)(*(ks + [0] * pad)), (ctypes.c_float * 4)(*(alphas + [0.0] * pad)),
+                     (ctypes.c_float * 4)(*(sigmas + [0.0] * pad)))
+
+
 class Graph:
     """Owner of an ahr_graph handle (ahr_graph_build ... ahr_graph_destroy)."""
 
@@ -330,6 +350,13 @@ class Graph:
         _check(load().ahr_filter(self.h, ctypes.byref(spec), _ptr(x), _ptr(out), x.shape[1], _stream(stream)))
         return out
 
+    def gift(self, spec, x, out=None, stream=None):
+        """GiFt's bank on the netlist graph (no area hints), fixed rows reset."""
+        if out is None:
+            out = torch.empty_like(x)
+        _check(load().ahr_gift(self.h, ctypes.byref(spec), _ptr(x), _ptr(out), x.shape[1], _stream(stream)))
+        return out
+
     def refine(self, spec, g0, T_hint, gamma, out=None, stream=None):
         if out is None:
             out = torch.empty_like(g0)
@@ -370,6 +397,35 @@ class Graph:
     def hpwl(self, g, out=None, stream=None):
         """HPWL of the graph's netlist (ahr_hpwl needs only the netlist)."""
         return hpwl(self.netlist, g, out, stream)
+
+
+class Wirelength:
+    """Owner of an ahr_wl handle: the WA wirelength and its gradient
+    (ahr_wl_create ... ahr_wl_destroy)."""
+
+    def __init__(self, netlist: Netlist, stream=None):
+        self.netlist = netlist
+        h = ctypes.c_void_p()
+        _check(load().ahr_wl_create(ctypes.byref(netlist.c), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().ahr_wl_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def wa(self, g, gamma, grad=True, stream=None):
+        """(wl [C/2] float64, grad [n_inst, C] float32 or None) on the device."""
+        wl = torch.empty(g.shape[1] // 2, dtype=torch.float64, device=g.device)
+        gr = torch.empty_like(g) if grad else None
+        _check(load().ahr_wa(self.h, _ptr(g), g.shape[1], float(gamma), _ptr(wl), _ptr(gr), _stream(stream)))
+        return wl, gr
 
 
 class Batch:

@@ -102,7 +102,7 @@ double read_f64(const double* src, hipStream_t s);
 // ---------------------------------------------------------------- profiling
 
 enum Stage { kStageBuild, kStageHints, kStageNorm, kStageExpand, kStageHop, kStageRelax, kStageHpwl, kStageMlp,
-             kStageCount };
+             kStageWa, kStageCount };
 
 bool profiling();
 // While set (on this thread), ProfScope records nothing: used around HIP
@@ -322,6 +322,8 @@ void relax(Graph& g, const float* gcur, const float* gt, float* gnext, int32_t n
            float gamma, hipStream_t s);
 // normalise + the unpinned chain T X, T^2 X, T^3 X into g.zh (scaled coordinates)
 void run_hops(Graph& g, const ahr_filter_spec& spec, const float* in, int32_t ncols, hipStream_t s);
+// gift.hip: the GiFt bank on the graph (no area hints), fixed rows reset
+void run_gift(Graph& g, const ahr_gift_spec& spec, const float* in, float* out, int32_t ncols, hipStream_t s);
 // hpwl.hip: run_hpwl draws its partial sums from the pool; hpwl_launch
 // takes a buffer of hpwl_partial_elems() doubles (enough for any netlist)
 void run_hpwl(const ahr_netlist& nl, const float* pos, int32_t ncols, double* out, hipStream_t s);

@@ -363,6 +363,31 @@ ahr_status ahr_filter(ahr_graph* h, const ahr_filter_spec* spec, const float* in
     });
 }
 
+ahr_status ahr_gift(ahr_graph* h, const ahr_gift_spec* spec, const float* in, float* out, int32_t ncols,
+                    void* stream) {
+    if (!h) return fail(AHR_EINVAL, "graph is NULL");
+    if (!spec) return fail(AHR_EINVAL, "GiFt spec is NULL");
+    if (spec->nbands < 1 || spec->nbands > AHR_MAX_BANDS) return fail(AHR_EINVAL, "nbands in [1, 4]");
+    for (int b = 0; b < spec->nbands; ++b) {
+        if (spec->k[b] < 0 || spec->k[b] > 64) return fail(AHR_EINVAL, "k in [0, 64]");
+        if (!std::isfinite(spec->alpha[b])) return fail(AHR_EINVAL, "alpha must be finite");
+        if (!(spec->sigma[b] >= 0.f) || !std::isfinite(spec->sigma[b])) return fail(AHR_EINVAL, "sigma must be >= 0");
+    }
+    if (!in || !out) return fail(AHR_EINVAL, "in/out is NULL");
+    if (!ncols_ok(ncols)) return fail(AHR_EINVAL, "ncols must be 1, 2, 4 or 8");
+    auto* gr = reinterpret_cast<ahr::Graph*>(h);
+    if (gr->hp.flags & (AHR_MACRO_HINTS | AHR_BIN_HINTS))
+        return fail(AHR_EINVAL, "GiFt filters the netlist graph: build it with AHR_MACRO_HINTS and AHR_BIN_HINTS off");
+    if (!gr->has_hints) return fail(AHR_EINVAL, "graph has no execution order yet: build it with a placement");
+    size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
+    if (overlap(in, bytes, out, bytes)) return fail(AHR_EINVAL, "in and out overlap");
+    return guarded([&]() -> ahr_status {
+        gr->use_stream(as_stream(stream));
+        ahr::run_gift(*gr, *spec, in, out, ncols, as_stream(stream));
+        return AHR_OK;
+    });
+}
+
 ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0, int32_t ncols, int32_t T_hint,
                       float gamma, float* out, void* stream) {
     if (!h) return fail(AHR_EINVAL, "graph is NULL");

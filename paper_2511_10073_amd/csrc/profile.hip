@@ -109,16 +109,18 @@ ahr_status ahr_profile_read(ahr_profile* out, int32_t reset) {
         ahr::drain_locked();
         // one destination per stage, in Stage order
         double* ms[ahr::kStageCount] = {&out->build_ms, &out->hints_ms, &out->norm_ms, &out->expand_ms,
-                                        &out->hop_ms,   &out->relax_ms, &out->hpwl_ms, &out->mlp_ms};
+                                        &out->hop_ms,   &out->relax_ms, &out->hpwl_ms, &out->mlp_ms,
+                                        &out->wa_ms};
         int64_t* cnt[ahr::kStageCount] = {&out->build_calls,  &out->hints_calls, &out->norm_calls,
                                           &out->expand_calls, &out->hop_launches, &out->relax_calls,
-                                          &out->hpwl_calls,   &out->mlp_calls};
-        static_assert(ahr::kStageCount == 8, "one profile field per stage");
+                                          &out->hpwl_calls,   &out->mlp_calls,   &out->wa_calls};
+        static_assert(ahr::kStageCount == 9, "one profile field per stage");
         for (int k = 0; k < ahr::kStageCount; ++k) {
             *ms[k] = ahr::g_ms[k];
             *cnt[k] = ahr::g_count[k];
         }
         out->hop_bytes = ahr::g_bytes[ahr::kStageHop];
+        out->wa_bytes = ahr::g_bytes[ahr::kStageWa];
         if (reset) {
             for (int k = 0; k < ahr::kStageCount; ++k) ahr::g_ms[k] = 0, ahr::g_count[k] = 0, ahr::g_bytes[k] = 0;
         }

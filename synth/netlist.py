@@ -414,3 +414,19 @@ def summary(nl: dict) -> dict:
                 n_pins=int(nl["pin_node"].size), max_deg=int(deg.max()),
                 n_fixed=int(((f & FIXED) != 0).sum()), n_macro=int(((f & MACRO) != 0).sum()),
                 die_side=float(nl["die"][2] - nl["die"][0]))
+
+
+def uniform_signal(nl: dict, ncols: int, seed: int) -> np.ndarray:
+    """GSP initialization's starting signal (Section IV, step 1): movable
+    instances at independent uniform positions in the die (one draw per
+    column), fixed ones at their positions (taken from ``g0``)."""
+    rng = np.random.default_rng(seed)
+    die = nl["die"].astype(np.float64)
+    n = nl["n_inst"]
+    G = np.empty((n, ncols), np.float64)
+    for c in range(ncols):
+        lo, hi = (die[0], die[2]) if c % 2 == 0 else (die[1], die[3])
+        G[:, c] = rng.uniform(lo, hi, n)
+    fixed = (nl["node_flags"] & FIXED) != 0
+    G[fixed] = np.tile(nl["g0"][fixed, :2].astype(np.float64), (1, ncols // 2))
+    return G.astype(np.float32)
