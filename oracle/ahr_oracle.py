@@ -54,6 +54,7 @@ class HintParams:
     expand_macro_pins: bool = True
     macro_hints: bool = True
     bin_hints: bool = True
+    prune_tau: float = 0.0         # bin edges with exp(-maxRatio) |phi_b| below this are left out (0: none)
 
 
 @dataclasses.dataclass
@@ -255,12 +256,18 @@ def window_half(ratio, nb):
     return n // 2
 
 
-def bin_hint_edges(nl, grid: BinGrid, pos32, hint_cells, bw_cell, phis, ratio, first_bin_id):
+def bin_hint_edges(nl, grid: BinGrid, pos32, hint_cells, bw_cell, phis, ratio, first_bin_id, prune_tau=0.0):
     """Section V, "Bin virtual node with density-aware signed edges": every
     hint cell i and every bin b whose window holds i's bin get the edge
     w = -exp(-maxRatio_{i,b}) phi_b baseWeight_i, maxRatio measured from the
     bin centre in units of the half bin size (reading R5: hint cells are the
-    movable standard cells with a netlist edge)."""
+    movable standard cells with a netlist edge).
+
+    Section IX, "Further speedups", proposes sparsifying the signed
+    Laplacian down to its most salient edges.  Reading: an edge's salience is
+    its weight relative to the cell's baseWeight, exp(-maxRatio) |phi_b|, and
+    with prune_tau > 0 the bin edges of salience below prune_tau are left out
+    (macro edges, of salience at least e^-1, always stay)."""
     hx = window_half(ratio, grid.nbx)
     hy = window_half(ratio, grid.nby)
     bx, by = cell_bin(grid, pos32[hint_cells, 0], pos32[hint_cells, 1])
@@ -276,7 +283,11 @@ def bin_hint_edges(nl, grid: BinGrid, pos32, hint_cells, bw_cell, phis, ratio, f
             xb = grid.xl + (tx[ok] + 0.5) * grid.bw
             yb = grid.yl + (ty[ok] + 0.5) * grid.bh
             ratio_ib = np.maximum(np.abs(x[ok] - xb) / (grid.bw / 2), np.abs(y[ok] - yb) / (grid.bh / 2))
-            w = -np.exp(-ratio_ib) * phis[b] * bw_cell[i]
+            e = np.exp(-ratio_ib)
+            if prune_tau > 0:
+                keep = e * np.abs(phis[b]) >= prune_tau
+                i, b, e = i[keep], b[keep], e[keep]
+            w = -e * phis[b] * bw_cell[i]
             rows.append(i)
             cols.append(first_bin_id + b)
             vals.append(w)
@@ -391,7 +402,7 @@ def build_graph(nl, params: HintParams, pos32):
         dens = bin_density(nl, grid, pos32, all_macros)
         ph = phi(dens, params.bin_capacity, params.mu)
         r, c, v = bin_hint_edges(nl, grid, pos32, hint_cells, bw_cell, ph,
-                                 params.detection_ratio, first_bvirt)
+                                 params.detection_ratio, first_bvirt, params.prune_tau)
         hr += [r, c]; hc += [c, r]; hv += [v, v]
     if hr:
         hr, hc, hv = np.concatenate(hr), np.concatenate(hc), np.concatenate(hv)
