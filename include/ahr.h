@@ -272,6 +272,20 @@ ahr_status ahr_wl_create(const ahr_netlist* nl, void* stream, ahr_wl** out);
 ahr_status ahr_wa(ahr_wl* h, const float* g, int32_t ncols, float gamma, double* wl, float* grad, void* stream);
 void ahr_wl_destroy(ahr_wl* h);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ahr_hpwl
+ * with its partial sums in a fixed library-owned device buffer of
+ * ahr_hpwl_noalloc_bytes() bytes (256 KiB) per device, held until the
+ * process ends, instead of pool memory.  It calls no allocator.  The buffer
+ * holds the partials of any netlist size; ncols above 8 is rejected
+ * (AHR_EINVAL).  Every call on a device shares that device's buffer, and
+ * each call overwrites it completely before reading it, so calls that
+ * overlap in time on one device (on any streams) race and give wrong totals;
+ * calls ordered on one stream are safe.  Same result bits as ahr_hpwl.
+ * Asynchronous. */
+ahr_status ahr_hpwl_noalloc(const ahr_netlist* nl, const float* g, int32_t ncols, double* out, void* stream);
+size_t ahr_hpwl_noalloc_bytes(void);
+
 /* ------------------------------------------------------------------------
  * Learned surrogate of the filter (a project addition; the paper has no
  * learned component).  It approximates the polynomial filter of `spec` from

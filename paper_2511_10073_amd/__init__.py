@@ -115,6 +115,7 @@ def load() -> ctypes.CDLL:
         "ahr_gift": [vp, ctypes.POINTER(_GiftSpec), vp, vp, i32, vp],
         "ahr_refine": [vp, ctypes.POINTER(_FilterSpec), vp, i32, i32, ctypes.c_float, vp, vp],
         "ahr_hpwl": [ctypes.POINTER(_Netlist), vp, i32, vp, vp],
+        "ahr_hpwl_noalloc": [ctypes.POINTER(_Netlist), vp, i32, vp, vp],
         "ahr_wl_create": [ctypes.POINTER(_Netlist), vp, ctypes.POINTER(vp)],
         "ahr_wa": [vp, vp, i32, ctypes.c_float, vp, vp, vp],
         "ahr_filter_learned": [vp, ctypes.POINTER(_FilterSpec), ctypes.POINTER(_Mlp), vp, vp, i32,
@@ -145,6 +146,8 @@ def load() -> ctypes.CDLL:
     lib.ahr_profile_enable.restype = ctypes.c_int32
     lib.ahr_profile_read.argtypes = [ctypes.POINTER(_Profile), i32]
     lib.ahr_profile_read.restype = ctypes.c_int32
+    lib.ahr_hpwl_noalloc_bytes.argtypes = []
+    lib.ahr_hpwl_noalloc_bytes.restype = ctypes.c_size_t
     lib.ahr_wl_destroy.argtypes = [vp]
     lib.ahr_wl_destroy.restype = None
     lib.ahr_graph_destroy.argtypes = [vp]
@@ -271,6 +274,14 @@ def hpwl(netlist: Netlist, g, out=None, stream=None):
     if out is None:
         out = torch.empty(g.shape[1] // 2, dtype=torch.float64, device=g.device)
     _check(load().ahr_hpwl(ctypes.byref(netlist.c), _ptr(g), g.shape[1], _ptr(out), _stream(stream)))
+    return out
+
+
+def hpwl_noalloc(netlist: Netlist, g, out, stream=None):
+    """ahr_hpwl with the library's fixed partial-sum buffer: no allocation
+    (the caller passes `out`, device float64 [C/2]); calls that overlap on one
+    device race."""
+    _check(load().ahr_hpwl_noalloc(ctypes.byref(netlist.c), _ptr(g), g.shape[1], _ptr(out), _stream(stream)))
     return out
 
 
