@@ -53,7 +53,7 @@ extern "C" {
 typedef int32_t ahr_status;
 #define AHR_OK 0
 #define AHR_EINVAL (-1)          /* bad argument; nothing was launched        */
-#define AHR_ENOMEM (-2)          /* device allocation failed                   */
+#define AHR_ENOMEM (-2)          /* workspace too small, or device allocation failed */
 #define AHR_EDEVICE (-3)         /* a HIP call failed                          */
 #define AHR_EUNSUPPORTED (-4)    /* valid but outside what this build handles  */
 
@@ -94,6 +94,11 @@ typedef struct ahr_hint_params {
     float mu;                   /* mu > 0 */
     int32_t clique_max;         /* nets with 2 <= p <= clique_max are cliques, larger ones stars; >= 1 */
     uint32_t flags;             /* AHR_EXPAND_MACRO_PINS | AHR_MACRO_HINTS | AHR_BIN_HINTS */
+    float prune_tau;            /* sparsification (Section IX, "Further speedups"; reading: an edge's
+                                   salience is its weight over the cell's baseWeight): bin edges with
+                                   exp(-maxRatio) |phi_b| below prune_tau are left out, both directions,
+                                   decided in float64; macro edges always stay.  0 keeps every edge;
+                                   in [0, 1] */
 } ahr_hint_params;
 
 #define AHR_LAMBDA_GERSHGORIN 0
@@ -140,6 +145,8 @@ typedef struct ahr_graph_info {
     int32_t n_long_rows;        /* rows the filter splits over several workgroups */
     int32_t hint_version;       /* incremented by every hint (re)build */
     int32_t reserved;
+    int64_t ws_bytes;           /* the caller's workspace (0: the library's pool) */
+    int64_t ws_peak;            /* most of it in use at once so far */
 } ahr_graph_info;
 
 /* Host buffers for ahr_graph_export; each pointer may be NULL to skip it.
@@ -163,6 +170,20 @@ const char* ahr_last_error(void);
 /* Library version, e.g. "ahr 0.1 gfx950". */
 const char* ahr_version(void);
 
+/* Device memory of a graph (two-phase, so that the caller's allocator
+ * provides it): an upper bound on the bytes a graph of this netlist and
+ * these parameters holds at once through its build and every later call
+ * with at most `ncols` columns (ncols in {1, 2, 4, 8}).
+ * It counts the netlist's graph entries, star nets and macro pins exactly
+ * (one pass over the netlist on `stream`, which it synchronises; 40 bytes of
+ * pool memory for the counters) and bounds what the placement decides:
+ * hint entries by the detection window and at most four macro footprints
+ * holding any one movable standard cell (true when footprints do not
+ * overlap), with a 25 % margin for fragmentation.  A graph whose needs
+ * exceed its workspace fails with AHR_ENOMEM, its outputs untouched. */
+ahr_status ahr_graph_workspace_size(const ahr_netlist* nl, const ahr_hint_params* hp, int32_t ncols,
+                                    void* stream, size_t* bytes);
+
 /* Build the graph of a netlist (Section V: macro pin expansion, then the
  * clique/star net model -- reading: weight w/(p-1) per pin pair for
  * 2 <= p <= clique_max, else a star node with w p/(p-1) per spoke -- with
@@ -170,10 +191,18 @@ const char* ahr_version(void);
  * NULL, the area hints of the placement held in columns 0 and 1 of `g`
  * ([n_inst][ncols]).  The netlist arrays must stay valid and unchanged
  * while the handle lives.  On success *out receives a handle the caller
- * frees with ahr_graph_destroy.  Synchronises `stream`. */
+ * frees with ahr_graph_destroy.  Synchronises `stream`.
+ *   ws, ws_bytes: NULL for the library's stream-ordered pool, or a device
+ *   workspace of at least ahr_graph_workspace_size() bytes (for `ncols`
+ *   columns, or 8 when `g` is NULL) that every device
+ *   allocation of this graph (build and later calls) is carved from; the
+ *   caller owns it and may reuse it once the graph is destroyed and its work
+ *   on its stream is done.  A workspace below the netlist's fixed arrays
+ *   gives AHR_ENOMEM before any device work; below the full bound, after the
+ *   counting pass, with nothing built. */
 ahr_status ahr_graph_build(const ahr_netlist* nl, const ahr_hint_params* hp,
-                           const float* g, int32_t ncols, void* stream,
-                           ahr_graph** out);
+                           const float* g, int32_t ncols, void* ws, size_t ws_bytes,
+                           void* stream, ahr_graph** out);
 
 /* Rebuild the area hints (BuildLap of Algorithm 1: bin densities, phi_b,
  * bin-window and macro-footprint edges) for the placement in columns 0 and
@@ -224,15 +253,24 @@ ahr_status ahr_filter(ahr_graph* gr, const ahr_filter_spec* spec,
 ahr_status ahr_gift(ahr_graph* gr, const ahr_gift_spec* spec, const float* in, float* out, int32_t ncols,
                     void* stream);
 
-/* Algorithm 1 (Section V): for r = 0 .. T_hint-1, rebuild the hints from
- * columns 0 and 1 of g^(r), filter all columns, and relax
+/* Algorithm 1 (Section V) on a built graph: for r = 0 .. T_hint-1, rebuild
+ * the hints from columns 0 and 1 of g^(r), filter all columns, and relax
  * g^(r+1) = (1 - gamma) g^(r) + gamma g~ on movable rows (fixed rows keep
  * their input).  g0 and out are [n_inst][ncols] and may be the same
  * buffer.  gamma in [0, 1], T_hint >= 0.  Synchronises `stream` once per
  * round (hint sizes). */
-ahr_status ahr_refine(ahr_graph* gr, const ahr_filter_spec* spec, const float* g0,
-                      int32_t ncols, int32_t T_hint, float gamma, float* out,
-                      void* stream);
+ahr_status ahr_graph_refine(ahr_graph* gr, const ahr_filter_spec* spec, const float* g0,
+                            int32_t ncols, int32_t T_hint, float gamma, float* out,
+                            void* stream);
+
+/* Algorithm 1 end to end, the initializer (Section V; its inputs g^(0), the
+ * macros M, the bin capacity C, T_hint and gamma): build the graph of `nl`
+ * with `hp` (in the workspace `ws` when it is not NULL, as
+ * ahr_graph_build), run ahr_graph_refine, free the graph.  The workspace may
+ * be reused once the call's work on `stream` is done. */
+ahr_status ahr_refine(const ahr_netlist* nl, const ahr_hint_params* hp, const ahr_filter_spec* spec,
+                      const float* g0, int32_t ncols, int32_t T_hint, float gamma, float* out,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /* Half-perimeter wirelength of the netlist `nl` (the paper's wirelength
  * score; Section II-B names HPWL as what the WA model approximates) for
@@ -271,6 +309,46 @@ ahr_status ahr_wl_create(const ahr_netlist* nl, void* stream, ahr_wl** out);
  * Work buffers come from the library's pool.  Asynchronous. */
 ahr_status ahr_wa(ahr_wl* h, const float* g, int32_t ncols, float gamma, double* wl, float* grad, void* stream);
 void ahr_wl_destroy(ahr_wl* h);
+
+/* ------------------------------------------------------------------------
+ * Macro charge-density models (Section VI, "Macro-Schedule Global
+ * Placement"): each macro's footprint carries an iteration-dependent density
+ * rho_t(dx, dy) (offsets from its centre, |dx| <= w/2, |dy| <= h/2), and its
+ * contribution to bin b is the integral of rho_t over the part of b inside
+ * the footprint (the section's closing equation).
+ * ------------------------------------------------------------------------ */
+#define AHR_CHARGE_GAUSSIAN 0   /* Section VI-A eqs. "Gaussion_eta", "eta_t" (charge redistribution)   */
+#define AHR_CHARGE_EXP 1        /* Section VI-B eqs. "exp_sigma", "sigma_t" (restoration, the default) */
+#define AHR_CHARGE_LINEAR 2     /* eq. "linear_k", clipped below at 0 (reading)                        */
+#define AHR_CHARGE_SIGMOID 3    /* eq. "sigmoid_k"                                                      */
+
+typedef struct ahr_charge_params {
+    int32_t model;              /* AHR_CHARGE_* */
+    int32_t t, T;               /* iteration t in [0, T], T >= 1 (schedule_iteration) */
+    int32_t nbx, nby;           /* bins tiling the die, each in [1, 4096] */
+    float sigma_factor;         /* exponential model: sigma(t) = -sigma_factor T ln(1 - t/T); > 0 */
+    float k_factor;             /* linear, sigmoid: k(t) = k_factor / tan(pi t / 2T); > 0 */
+    float r0, r1;               /* Gaussian Scheme A: edge decay ratio at t = 0 and T, in (0, 1) */
+    float beta_min, beta_max;   /* Gaussian Scheme B: normalised FWHM at t = 0 and T, > 0 */
+    float alpha0, alpha1;       /* Gaussian blend: smoothstep from alpha0 to alpha1, 0 <= alpha0 < alpha1 <= 1 */
+} ahr_charge_params;
+
+/* The model's parameter at iteration t (host, float64): eta, sigma or k.
+ * The end points are limits: sigma(0) = 0 and k(0) = +inf (no charge),
+ * sigma(T) = +inf and k(T) = 0 (the flat footprint, rho = 1). */
+ahr_status ahr_charge_schedule(const ahr_charge_params* cp, double* param);
+
+/* Per bin b (row-major by (by, bx)): bin_mass[b] = the sum over every macro
+ * of the netlist (at columns 0 and 1 of `g`, [n_inst][ncols], ncols >= 2) of
+ * the integral of its rho_t over bin b inside its footprint, in area units.
+ * Footprint parts outside the die fall in no bin.  Float64; the Gaussian by
+ * erf differences, the others by fixed Gauss-Legendre rules on panels that
+ * follow each integrand's scales (within about 1e-13 of the exact integral
+ * relative to the macro area); per-bin sums in 2^-28 fixed point, so the
+ * result does not depend on summation order.  bin_mass is a device array of
+ * nbx * nby doubles.  Synchronises `stream` once (the pair count). */
+ahr_status ahr_macro_charge(const ahr_netlist* nl, const float* g, int32_t ncols, const ahr_charge_params* cp,
+                            double* bin_mass, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): ahr_hpwl

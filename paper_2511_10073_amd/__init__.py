@@ -45,7 +45,7 @@ class _Netlist(ctypes.Structure):
 class _HintParams(ctypes.Structure):
     _fields_ = [("nbx", ctypes.c_int32), ("nby", ctypes.c_int32), ("detection_ratio", ctypes.c_float),
                 ("bin_capacity", ctypes.c_float), ("mu", ctypes.c_float), ("clique_max", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("prune_tau", ctypes.c_float)]
 
 
 class _FilterSpec(ctypes.Structure):
@@ -58,10 +58,40 @@ class _GiftSpec(ctypes.Structure):
                 ("sigma", ctypes.c_float * 4)]
 
 
+class _ChargeParams(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int32) for n in ("model", "t", "T", "nbx", "nby")]
+                + [(n, ctypes.c_float) for n in ("sigma_factor", "k_factor", "r0", "r1", "beta_min", "beta_max",
+                                                 "alpha0", "alpha1")])
+
+
+CHARGE_GAUSSIAN, CHARGE_EXP, CHARGE_LINEAR, CHARGE_SIGMOID = 0, 1, 2, 3
+
+
+def charge_params(model=CHARGE_EXP, t=0, T=300, nbx=32, nby=32, sigma_factor=0.005, k_factor=1.0, r0=1e-3, r1=0.9,
+                  beta_min=0.1, beta_max=1.0, alpha0=0.2, alpha1=0.8):
+    return _ChargeParams(model, t, T, nbx, nby, sigma_factor, k_factor, r0, r1, beta_min, beta_max, alpha0, alpha1)
+
+
+def charge_schedule(cp) -> float:
+    v = ctypes.c_double()
+    _check(load().ahr_charge_schedule(ctypes.byref(cp), ctypes.byref(v)))
+    return v.value
+
+
+def macro_charge(netlist, g, cp, out=None, stream=None):
+    """Per-bin macro charge masses (device float64 [nby * nbx])."""
+    if out is None:
+        out = torch.empty(cp.nbx * cp.nby, dtype=torch.float64, device=g.device)
+    _check(load().ahr_macro_charge(ctypes.byref(netlist.c), _ptr(g), g.shape[1], ctypes.byref(cp), _ptr(out),
+                                   _stream(stream)))
+    return out
+
+
 class _GraphInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "n_inst", "n_tot", "first_mpin", "first_star", "first_mvirt", "first_bvirt", "nnz_net", "nnz_hint",
-        "n_hint_cells", "n_long_rows", "hint_version", "reserved")]
+        "n_hint_cells", "n_long_rows", "hint_version", "reserved")] + [("ws_bytes", ctypes.c_int64),
+                                                                        ("ws_peak", ctypes.c_int64)]
 
 
 class _GraphHost(ctypes.Structure):
@@ -107,16 +137,23 @@ def load() -> ctypes.CDLL:
     lib.ahr_last_error.restype = ctypes.c_char_p
     lib.ahr_version.restype = ctypes.c_char_p
     sigs = {
-        "ahr_graph_build": [ctypes.POINTER(_Netlist), ctypes.POINTER(_HintParams), vp, i32, vp, ctypes.POINTER(vp)],
+        "ahr_graph_build": [ctypes.POINTER(_Netlist), ctypes.POINTER(_HintParams), vp, i32, vp, ctypes.c_size_t, vp,
+                            ctypes.POINTER(vp)],
+        "ahr_graph_workspace_size": [ctypes.POINTER(_Netlist), ctypes.POINTER(_HintParams), i32, vp,
+                                     ctypes.POINTER(ctypes.c_size_t)],
         "ahr_graph_update_hints": [vp, vp, i32, vp],
         "ahr_graph_get_info": [vp, ctypes.POINTER(_GraphInfo)],
         "ahr_graph_export": [vp, ctypes.POINTER(_GraphHost), vp],
         "ahr_filter": [vp, ctypes.POINTER(_FilterSpec), vp, vp, i32, vp],
         "ahr_gift": [vp, ctypes.POINTER(_GiftSpec), vp, vp, i32, vp],
-        "ahr_refine": [vp, ctypes.POINTER(_FilterSpec), vp, i32, i32, ctypes.c_float, vp, vp],
+        "ahr_graph_refine": [vp, ctypes.POINTER(_FilterSpec), vp, i32, i32, ctypes.c_float, vp, vp],
+        "ahr_refine": [ctypes.POINTER(_Netlist), ctypes.POINTER(_HintParams), ctypes.POINTER(_FilterSpec), vp, i32, i32,
+                       ctypes.c_float, vp, vp, ctypes.c_size_t, vp],
         "ahr_hpwl": [ctypes.POINTER(_Netlist), vp, i32, vp, vp],
         "ahr_hpwl_noalloc": [ctypes.POINTER(_Netlist), vp, i32, vp, vp],
         "ahr_wl_create": [ctypes.POINTER(_Netlist), vp, ctypes.POINTER(vp)],
+        "ahr_charge_schedule": [ctypes.POINTER(_ChargeParams), ctypes.POINTER(ctypes.c_double)],
+        "ahr_macro_charge": [ctypes.POINTER(_Netlist), vp, i32, ctypes.POINTER(_ChargeParams), vp, vp],
         "ahr_wa": [vp, vp, i32, ctypes.c_float, vp, vp, vp],
         "ahr_filter_learned": [vp, ctypes.POINTER(_FilterSpec), ctypes.POINTER(_Mlp), vp, vp, i32,
                                ctypes.POINTER(i32), vp],
@@ -285,8 +322,9 @@ def hpwl_noalloc(netlist: Netlist, g, out, stream=None):
     return out
 
 
-def hint_params(nbx=8, nby=8, detection_ratio=0.1, bin_capacity=1.0, mu=4.0, clique_max=10, flags=ALL_HINTS):
-    return _HintParams(nbx, nby, detection_ratio, bin_capacity, mu, clique_max, flags)
+def hint_params(nbx=8, nby=8, detection_ratio=0.1, bin_capacity=1.0, mu=4.0, clique_max=10, flags=ALL_HINTS,
+                prune_tau=0.0):
+    return _HintParams(nbx, nby, detection_ratio, bin_capacity, mu, clique_max, flags, prune_tau)
 
 
 def filter_spec(ks=(4,), alphas=(1.0,), sigma=0.0, lambda_mode=LAMBDA_GERSHGORIN, lambda_fixed=2.0):
@@ -306,17 +344,38 @@ def gift_spec(ks=(2, 2, 4), sigmas=(2.0, 4.0, 4.0), alphas=(0.2, 0.3, 0.5)):
                      (ctypes.c_float * 4)(*(sigmas + [0.0] * pad)))
 
 
-class Graph:
-    """Owner of an ahr_graph handle (ahr_graph_build ... ahr_graph_destroy)."""
+def workspace_size(netlist: Netlist, params, ncols, stream=None) -> int:
+    """Bytes of device workspace a graph of this netlist needs (ahr_graph_workspace_size)."""
+    n = ctypes.c_size_t()
+    _check(load().ahr_graph_workspace_size(ctypes.byref(netlist.c), ctypes.byref(params), ncols, _stream(stream),
+                                           ctypes.byref(n)))
+    return n.value
 
-    def __init__(self, netlist: Netlist, params, g=None, stream=None):
+
+def refine(netlist: Netlist, params, spec, g0, T_hint, gamma, out=None, ws=None, stream=None):
+    """Algorithm 1 end to end (graph built, refined and freed in one call);
+    ws: an optional device workspace (uint8 tensor) for all its memory."""
+    if out is None:
+        out = torch.empty_like(g0)
+    _check(load().ahr_refine(ctypes.byref(netlist.c), ctypes.byref(params), ctypes.byref(spec), _ptr(g0), g0.shape[1],
+                             T_hint, gamma, _ptr(out), _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream)))
+    return out
+
+
+class Graph:
+    """Owner of an ahr_graph handle (ahr_graph_build ... ahr_graph_destroy).
+    ws: an optional device workspace (uint8 tensor, kept alive by the
+    handle) that all of the graph's device memory is carved from."""
+
+    def __init__(self, netlist: Netlist, params, g=None, stream=None, ws=None):
         lib = load()
         self.netlist = netlist
         self.params = params
+        self.ws = ws
         h = ctypes.c_void_p()
         ncols = 0 if g is None else g.shape[1]
-        _check(lib.ahr_graph_build(ctypes.byref(netlist.c), ctypes.byref(params), _ptr(g), ncols,
-                                   _stream(stream), ctypes.byref(h)))
+        _check(lib.ahr_graph_build(ctypes.byref(netlist.c), ctypes.byref(params), _ptr(g), ncols, _ptr(ws),
+                                   0 if ws is None else ws.numel(), _stream(stream), ctypes.byref(h)))
         self.h = h
 
     def close(self):
@@ -371,8 +430,8 @@ class Graph:
     def refine(self, spec, g0, T_hint, gamma, out=None, stream=None):
         if out is None:
             out = torch.empty_like(g0)
-        _check(load().ahr_refine(self.h, ctypes.byref(spec), _ptr(g0), g0.shape[1], T_hint, gamma, _ptr(out),
-                                 _stream(stream)))
+        _check(load().ahr_graph_refine(self.h, ctypes.byref(spec), _ptr(g0), g0.shape[1], T_hint, gamma, _ptr(out),
+                                       _stream(stream)))
         return out
 
     def refine_learned(self, spec, model, g0, T_hint, gamma, out=None, stream=None):

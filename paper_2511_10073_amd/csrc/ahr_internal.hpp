@@ -31,8 +31,30 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 
 // ---------------------------------------------------------------- memory
 
-// Stream-ordered device allocation from a pool that keeps freed memory.
-// Blocks may be freed on one stream and reused on another.
+// A caller-provided device workspace that one graph's memory is carved from
+// (first fit, 256-byte aligned, free neighbours merged).  While an
+// ArenaScope is active on a thread, dev_alloc draws from its arena; dev_free
+// returns a block to whichever arena holds its address.  A block freed on
+// one stream and taken again on another waits for the first stream.
+struct Arena;
+Arena* arena_create(void* base, size_t bytes);
+void arena_destroy(Arena* a) noexcept;
+size_t arena_peak(const Arena* a);
+size_t arena_size(const Arena* a);
+class ArenaScope {
+  public:
+    explicit ArenaScope(Arena* a);
+    ~ArenaScope();
+    ArenaScope(const ArenaScope&) = delete;
+    ArenaScope& operator=(const ArenaScope&) = delete;
+
+  private:
+    Arena* prev_;
+};
+
+// Stream-ordered device allocation from a pool that keeps freed memory (or
+// from the active arena, see above).  Blocks may be freed on one stream and
+// reused on another.
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
 // Records the events that order the blocks freed since the last call behind
@@ -172,6 +194,7 @@ struct RowClasses {
 };
 
 struct Graph {
+    Arena* arena = nullptr;    // the caller's workspace all device memory comes from (null: the pool)
     ahr_netlist nl;            // caller's device arrays (kept)
     ahr_hint_params hp;
     int32_t n_inst = 0, n_mpin = 0, n_star = 0, n_macro = 0, n_bins = 0;
@@ -296,6 +319,11 @@ struct Graph {
     ~Graph();
 };
 
+// workspace.hip: an upper bound on a graph's device memory (one counting
+// pass over the netlist on s, synchronised), and the part of it known from
+// the sizes alone
+size_t graph_workspace_bytes(const ahr_netlist& nl, const ahr_hint_params& hp, int32_t ncols, hipStream_t s);
+size_t graph_workspace_floor(const ahr_netlist& nl, int32_t ncols);
 // netlist_build.hip
 void build_netlist(Graph& g, hipStream_t s);
 // Stable bucket sort: list = indices i in [0, n) with key[i] >= 0, grouped by
@@ -324,6 +352,10 @@ void relax(Graph& g, const float* gcur, const float* gt, float* gnext, int32_t n
 void run_hops(Graph& g, const ahr_filter_spec& spec, const float* in, int32_t ncols, hipStream_t s);
 // gift.hip: the GiFt bank on the graph (no area hints), fixed rows reset
 void run_gift(Graph& g, const ahr_gift_spec& spec, const float* in, float* out, int32_t ncols, hipStream_t s);
+// charge.hip: the model parameter at iteration t; per-bin masses of every macro
+double charge_schedule(const ahr_charge_params& cp);
+void run_macro_charge(const ahr_netlist& nl, const float* pos, int32_t ncols, const ahr_charge_params& cp,
+                      double* out, hipStream_t s);
 // hpwl.hip: run_hpwl draws its partial sums from the pool; hpwl_launch
 // takes a buffer of hpwl_partial_elems() doubles (enough for any netlist)
 void run_hpwl(const ahr_netlist& nl, const float* pos, int32_t ncols, double* out, hipStream_t s);
@@ -346,6 +378,9 @@ void mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step
 //   z'_i = cr_i z_i + kr_i sum_j A_ij z_j,
 //   cr_i = 1 - (nz_i - sigma s_i^2) / lambda,  kr_i = s_i^2 / lambda,
 // evaluated in float64 and rounded once; T = I when lambda = 0.
+__host__ __device__ inline double fmax_d(double a, double b) { return a > b ? a : b; }
+__host__ __device__ inline double fmin_d(double a, double b) { return a < b ? a : b; }
+
 __host__ __device__ inline void hop_coef(float s, double lam, double sigma, float& cr, float& kr) {
     cr = 1.f;
     kr = 0.f;

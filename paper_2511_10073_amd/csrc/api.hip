@@ -84,6 +84,7 @@ Graph::~Graph() {
     gt.release(s);
     scan_tmp.release(s);
     i64a.release(s);
+    arena_destroy(arena);
     if (xnet_fork) (void)hipEventDestroy(xnet_fork);
     if (xnet_ready) (void)hipEventDestroy(xnet_ready);
 }
@@ -123,6 +124,7 @@ ahr_status check_hints(const ahr_hint_params* hp) {
     if (!std::isfinite(hp->bin_capacity)) return fail(AHR_EINVAL, "bin_capacity must be finite");
     if (hp->clique_max < 1) return fail(AHR_EINVAL, "clique_max must be >= 1");
     if (hp->flags & ~AHR_ALL_HINTS) return fail(AHR_EINVAL, "unknown hint flags");
+    if (!(hp->prune_tau >= 0.f && hp->prune_tau <= 1.f)) return fail(AHR_EINVAL, "prune_tau in [0, 1]");
     return AHR_OK;
 }
 
@@ -171,29 +173,80 @@ const char* ahr_version(void) { return "ahr 0.1 gfx950"; }
 
 const char* ahr_last_error(void) { return ahr::last_error_ref().c_str(); }
 
-ahr_status ahr_graph_build(const ahr_netlist* nl, const ahr_hint_params* hp, const float* g, int32_t ncols,
-                           void* stream, ahr_graph** out) {
+ahr_status ahr_graph_workspace_size(const ahr_netlist* nl, const ahr_hint_params* hp, int32_t ncols, void* stream,
+                                    size_t* bytes) {
+    ahr_status st;
+    if ((st = check_netlist(nl)) != AHR_OK) return st;
+    if ((st = check_hints(hp)) != AHR_OK) return st;
+    if (!bytes) return fail(AHR_EINVAL, "bytes is NULL");
+    if (!ncols_ok(ncols)) return fail(AHR_EINVAL, "ncols must be 1, 2, 4 or 8");
+    return guarded([&]() -> ahr_status {
+        *bytes = ahr::graph_workspace_bytes(*nl, *hp, ncols, as_stream(stream));
+        return AHR_OK;
+    });
+}
+
+namespace {
+
+// Build a graph (in the workspace when one is given): the body of
+// ahr_graph_build and of the netlist form of ahr_refine.
+// bound_cols: the most columns later calls will use (the workspace bound).
+ahr::Graph* new_graph(const ahr_netlist* nl, const ahr_hint_params* hp, const float* g, int32_t ncols,
+                      int32_t bound_cols, void* ws, size_t ws_bytes, hipStream_t s) {
+    ahr::Arena* arena = nullptr;
+    if (ws) {
+        arena = ahr::arena_create(ws, ws_bytes);
+        try {
+            ahr::ArenaScope scope(arena);
+            const size_t need = ahr::graph_workspace_bytes(*nl, *hp, bound_cols, s);
+            if (ws_bytes < need) {
+                char buf[160];
+                snprintf(buf, sizeof buf, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+                throw Error{AHR_ENOMEM, buf};
+            }
+        } catch (...) {
+            ahr::arena_destroy(arena);
+            throw;
+        }
+    }
+    auto* gr = new ahr::Graph();
+    gr->arena = arena;
+    ahr::ArenaScope scope(arena);
+    gr->use_stream(s);
+    gr->nl = *nl;
+    gr->hp = *hp;
+    try {
+        AHR_HIP(hipGetDevice(&gr->device));
+        ahr::build_netlist(*gr, s);
+        if (g) ahr::build_hints(*gr, g, ncols, s);
+    } catch (...) {
+        delete gr;
+        throw;
+    }
+    return gr;
+}
+
+}  // namespace
+
+ahr_status ahr_graph_build(const ahr_netlist* nl, const ahr_hint_params* hp, const float* g, int32_t ncols, void* ws,
+                           size_t ws_bytes, void* stream, ahr_graph** out) {
     ahr_status st;
     if ((st = check_netlist(nl)) != AHR_OK) return st;
     if ((st = check_hints(hp)) != AHR_OK) return st;
     if (!out) return fail(AHR_EINVAL, "out is NULL");
     if (g && (!ncols_ok(ncols) || ncols < 2)) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8 with a placement");
+    if (ws && ws_bytes < ahr::graph_workspace_floor(*nl, g ? ncols : 8))
+        return fail(AHR_ENOMEM, "workspace too small for the netlist's sizes (ask ahr_graph_workspace_size)");
     return guarded([&]() -> ahr_status {
         hipStream_t s = as_stream(stream);
-        auto* gr = new ahr::Graph();
-        gr->use_stream(s);
-        gr->nl = *nl;
-        gr->hp = *hp;
-        AHR_HIP(hipGetDevice(&gr->device));
-        try {
-            ahr::build_netlist(*gr, s);
-            if (g) {
-                ahr::build_hints(*gr, g, ncols, s);
+        auto* gr = new_graph(nl, hp, g, ncols, g ? ncols : 8, ws, ws_bytes, s);
+        if (g) {
+            try {
                 AHR_HIP(hipStreamSynchronize(s));
+            } catch (...) {
+                delete gr;
+                throw;
             }
-        } catch (...) {
-            delete gr;
-            throw;
         }
         *out = reinterpret_cast<ahr_graph*>(gr);
         return AHR_OK;
@@ -205,6 +258,7 @@ ahr_status ahr_graph_update_hints(ahr_graph* h, const float* g, int32_t ncols, v
     if (!g) return fail(AHR_EINVAL, "placement is NULL");
     if (!ncols_ok(ncols) || ncols < 2) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(reinterpret_cast<const ahr::Graph*>(h)->arena);
         auto* gr = reinterpret_cast<ahr::Graph*>(h);
         hipStream_t s = as_stream(stream);
         gr->use_stream(s);
@@ -217,6 +271,7 @@ ahr_status ahr_graph_update_hints(ahr_graph* h, const float* g, int32_t ncols, v
 ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
     if (!h || !info) return fail(AHR_EINVAL, "NULL argument");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(reinterpret_cast<const ahr::Graph*>(h)->arena);
         const auto* g = reinterpret_cast<const ahr::Graph*>(h);
         // entry counts not read yet come from the row pointers, on the
         // stream the graph's work went to (after a device wait when it went
@@ -238,6 +293,8 @@ ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
         info->n_hint_cells = g->n_hint_cells;
         info->n_long_rows = g->rc.n_long;
         info->hint_version = g->hint_version;
+        info->ws_bytes = static_cast<int64_t>(ahr::arena_size(g->arena));
+        info->ws_peak = static_cast<int64_t>(ahr::arena_peak(g->arena));
         return AHR_OK;
     });
 }
@@ -245,6 +302,7 @@ ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
 ahr_status ahr_graph_export(const ahr_graph* h, ahr_graph_host* dst, void* stream) {
     if (!h || !dst) return fail(AHR_EINVAL, "NULL argument");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(reinterpret_cast<const ahr::Graph*>(h)->arena);
         const auto* g = reinterpret_cast<const ahr::Graph*>(h);
         hipStream_t s = as_stream(stream);
         g->use_stream(s);
@@ -357,6 +415,7 @@ ahr_status ahr_filter(ahr_graph* h, const ahr_filter_spec* spec, const float* in
     size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
     if (overlap(in, bytes, out, bytes)) return fail(AHR_EINVAL, "in and out overlap");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(gr->arena);
         gr->use_stream(as_stream(stream));
         ahr::run_filter(*gr, *spec, in, out, ncols, as_stream(stream));
         return AHR_OK;
@@ -382,13 +441,14 @@ ahr_status ahr_gift(ahr_graph* h, const ahr_gift_spec* spec, const float* in, fl
     size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
     if (overlap(in, bytes, out, bytes)) return fail(AHR_EINVAL, "in and out overlap");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(gr->arena);
         gr->use_stream(as_stream(stream));
         ahr::run_gift(*gr, *spec, in, out, ncols, as_stream(stream));
         return AHR_OK;
     });
 }
 
-ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0, int32_t ncols, int32_t T_hint,
+ahr_status ahr_graph_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0, int32_t ncols, int32_t T_hint,
                       float gamma, float* out, void* stream) {
     if (!h) return fail(AHR_EINVAL, "graph is NULL");
     ahr_status st;
@@ -401,6 +461,7 @@ ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0
     size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
     if (g0 != out && overlap(g0, bytes, out, bytes)) return fail(AHR_EINVAL, "g0 and out partially overlap");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(gr->arena);
         hipStream_t s = as_stream(stream);
         gr->use_stream(s);
         size_t n = static_cast<size_t>(gr->n_inst) * ncols;
@@ -408,6 +469,48 @@ ahr_status ahr_refine(ahr_graph* h, const ahr_filter_spec* spec, const float* g0
             if (g0 != out) AHR_HIP(hipMemcpyAsync(out, g0, bytes, hipMemcpyDeviceToDevice, s));
             return AHR_OK;
         }
+        gr->ga.ensure(n, s);
+        gr->gb.ensure(n, s);
+        gr->gt.ensure(n, s);
+        const float* cur = g0;
+        for (int r = 0; r < T_hint; ++r) {
+            float* next = (r == T_hint - 1) ? out : ((r & 1) ? gr->gb.p : gr->ga.p);
+            ahr::build_hints(*gr, cur, ncols, s);
+            ahr::run_filter(*gr, *spec, cur, gr->gt.p, ncols, s);
+            ahr::relax(*gr, cur, gr->gt.p, next, ncols, gamma, s);
+            cur = next;
+        }
+        return AHR_OK;
+    });
+}
+
+ahr_status ahr_refine(const ahr_netlist* nl, const ahr_hint_params* hp, const ahr_filter_spec* spec, const float* g0,
+                      int32_t ncols, int32_t T_hint, float gamma, float* out, void* ws, size_t ws_bytes, void* stream) {
+    ahr_status st;
+    if ((st = check_netlist(nl)) != AHR_OK) return st;
+    if ((st = check_hints(hp)) != AHR_OK) return st;
+    if ((st = check_spec(spec)) != AHR_OK) return st;
+    if (!g0 || !out) return fail(AHR_EINVAL, "g0/out is NULL");
+    if (!ncols_ok(ncols) || ncols < 2) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
+    if (T_hint < 0) return fail(AHR_EINVAL, "T_hint must be >= 0");
+    if (!(gamma >= 0.f && gamma <= 1.f)) return fail(AHR_EINVAL, "gamma in [0, 1]");
+    size_t bytes = static_cast<size_t>(nl->n_inst) * ncols * sizeof(float);
+    if (g0 != out && overlap(g0, bytes, out, bytes)) return fail(AHR_EINVAL, "g0 and out partially overlap");
+    if (ws && ws_bytes < ahr::graph_workspace_floor(*nl, ncols))
+        return fail(AHR_ENOMEM, "workspace too small for the netlist's sizes (ask ahr_graph_workspace_size)");
+    return guarded([&]() -> ahr_status {
+        hipStream_t s = as_stream(stream);
+        ahr::Graph* gr = new_graph(nl, hp, nullptr, 0, ncols, ws, ws_bytes, s);
+        struct Drop {
+            ahr::Graph* g;
+            ~Drop() { delete g; }
+        } drop{gr};
+        ahr::ArenaScope scope(gr->arena);
+        if (T_hint == 0) {
+            if (g0 != out) AHR_HIP(hipMemcpyAsync(out, g0, bytes, hipMemcpyDeviceToDevice, s));
+            return AHR_OK;
+        }
+        const size_t n = static_cast<size_t>(gr->n_inst) * ncols;
         gr->ga.ensure(n, s);
         gr->gb.ensure(n, s);
         gr->gt.ensure(n, s);
@@ -438,6 +541,7 @@ ahr_status ahr_refine_learned(ahr_graph* h, const ahr_filter_spec* spec, const a
     size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
     if (g0 != out && overlap(g0, bytes, out, bytes)) return fail(AHR_EINVAL, "g0 and out partially overlap");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(gr->arena);
         hipStream_t s = as_stream(stream);
         gr->use_stream(s);
         size_t n = static_cast<size_t>(gr->n_inst) * ncols;
@@ -478,6 +582,7 @@ ahr_status ahr_filter_learned(ahr_graph* h, const ahr_filter_spec* spec, const a
     size_t bytes = static_cast<size_t>(gr->n_inst) * ncols * sizeof(float);
     if (overlap(in, bytes, out, bytes)) return fail(AHR_EINVAL, "in and out overlap");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(gr->arena);
         hipStream_t s = as_stream(stream);
         gr->use_stream(s);
         if (!model->validated) {
@@ -501,6 +606,7 @@ ahr_status ahr_filter_features(ahr_graph* h, const ahr_filter_spec* spec, const 
     auto* gr = reinterpret_cast<ahr::Graph*>(h);
     if (!gr->has_hints) return fail(AHR_EINVAL, "graph has no hints yet: build with a placement or update_hints");
     return guarded([&]() -> ahr_status {
+        ahr::ArenaScope arena_scope(gr->arena);
         static const float zero_beta[3] = {0.f, 0.f, 0.f};
         ahr::DevBuf<float> p;
         hipStream_t s = as_stream(stream);
@@ -561,6 +667,48 @@ ahr_status ahr_filter_get_tune(int32_t* lanes_per_row, int32_t* nontemporal) {
     *lanes_per_row = ahr::g_hop_lanes;
     *nontemporal = ahr::g_hop_nt;
     return AHR_OK;
+}
+
+ahr_status check_charge(const ahr_charge_params* cp) {
+    if (!cp) return fail(AHR_EINVAL, "charge params are NULL");
+    if (cp->model < AHR_CHARGE_GAUSSIAN || cp->model > AHR_CHARGE_SIGMOID) return fail(AHR_EINVAL, "unknown model");
+    if (cp->T < 1 || cp->t < 0 || cp->t > cp->T) return fail(AHR_EINVAL, "need 0 <= t <= T, T >= 1");
+    if (cp->nbx < 1 || cp->nby < 1 || cp->nbx > 4096 || cp->nby > 4096) return fail(AHR_EINVAL, "nbx, nby in [1, 4096]");
+    if (cp->model == AHR_CHARGE_EXP && !(cp->sigma_factor > 0.f && std::isfinite(cp->sigma_factor)))
+        return fail(AHR_EINVAL, "sigma_factor must be positive");
+    if ((cp->model == AHR_CHARGE_LINEAR || cp->model == AHR_CHARGE_SIGMOID) &&
+        !(cp->k_factor > 0.f && std::isfinite(cp->k_factor)))
+        return fail(AHR_EINVAL, "k_factor must be positive");
+    if (cp->model == AHR_CHARGE_GAUSSIAN) {
+        if (!(cp->r0 > 0.f && cp->r0 < 1.f) || !(cp->r1 > 0.f && cp->r1 < 1.f)) return fail(AHR_EINVAL, "r0, r1 in (0, 1)");
+        if (!(cp->beta_min > 0.f) || !(cp->beta_max > 0.f) || !std::isfinite(cp->beta_min) ||
+            !std::isfinite(cp->beta_max))
+            return fail(AHR_EINVAL, "beta_min, beta_max must be positive");
+        if (!(cp->alpha0 >= 0.f && cp->alpha0 < cp->alpha1 && cp->alpha1 <= 1.f))
+            return fail(AHR_EINVAL, "need 0 <= alpha0 < alpha1 <= 1");
+    }
+    return AHR_OK;
+}
+
+ahr_status ahr_charge_schedule(const ahr_charge_params* cp, double* param) {
+    ahr_status st;
+    if ((st = check_charge(cp)) != AHR_OK) return st;
+    if (!param) return fail(AHR_EINVAL, "param is NULL");
+    *param = ahr::charge_schedule(*cp);
+    return AHR_OK;
+}
+
+ahr_status ahr_macro_charge(const ahr_netlist* nl, const float* g, int32_t ncols, const ahr_charge_params* cp,
+                            double* bin_mass, void* stream) {
+    ahr_status st;
+    if ((st = check_netlist(nl)) != AHR_OK) return st;
+    if ((st = check_charge(cp)) != AHR_OK) return st;
+    if (!g || !bin_mass) return fail(AHR_EINVAL, "g/bin_mass is NULL");
+    if (!ncols_ok(ncols) || ncols < 2) return fail(AHR_EINVAL, "ncols must be 2, 4 or 8");
+    return guarded([&]() -> ahr_status {
+        ahr::run_macro_charge(*nl, g, ncols, *cp, bin_mass, as_stream(stream));
+        return AHR_OK;
+    });
 }
 
 ahr_status ahr_hpwl(const ahr_netlist* nl, const float* g, int32_t ncols, double* out, void* stream) {

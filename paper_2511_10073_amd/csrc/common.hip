@@ -145,7 +145,114 @@ size_t size_class(size_t b) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- arenas
+
+struct Arena {
+    char* base;
+    size_t size;
+    std::map<size_t, size_t> free_blocks;            // offset -> length
+    std::unordered_map<size_t, size_t> live;         // offset -> length
+    std::map<size_t, hipStream_t> freed_on;          // offset of a free block -> stream of its last free
+    size_t used = 0, peak = 0;
+};
+
+namespace {
+std::vector<Arena*> g_arenas;                        // under g_alloc_mu
+thread_local Arena* t_arena = nullptr;
+
+constexpr size_t kArenaAlign = 256;
+
+void* arena_alloc(Arena& a, size_t bytes, hipStream_t s) {
+    const size_t need = (bytes < 1 ? 1 : bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+    for (auto it = a.free_blocks.begin(); it != a.free_blocks.end(); ++it) {
+        if (it->second < need) continue;
+        const size_t off = it->first, len = it->second;
+        a.free_blocks.erase(it);
+        if (len > need) a.free_blocks[off + need] = len - need;
+        auto fs = a.freed_on.find(off);
+        if (fs != a.freed_on.end()) {
+            // freed on another stream: its last work there must be done
+            if (fs->second != s) AHR_HIP(hipStreamSynchronize(fs->second));
+            a.freed_on.erase(fs);
+        }
+        a.live[off] = need;
+        a.used += need;
+        if (a.used > a.peak) a.peak = a.used;
+        return a.base + off;
+    }
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "workspace too small: %zu more bytes needed with %zu of %zu in use (ask ahr_graph_workspace_size)",
+             need, a.used, a.size);
+    throw Error{AHR_ENOMEM, buf};
+}
+
+void arena_free(Arena& a, void* p, hipStream_t s) {
+    const size_t off = static_cast<size_t>(static_cast<char*>(p) - a.base);
+    auto it = a.live.find(off);
+    if (it == a.live.end()) return;
+    size_t start = off, len = it->second;
+    a.used -= len;
+    a.live.erase(it);
+    // the merged block remembers the stream of this free (the latest one)
+    auto nx = a.free_blocks.find(off + len);
+    if (nx != a.free_blocks.end()) {
+        len += nx->second;
+        a.freed_on.erase(nx->first);
+        a.free_blocks.erase(nx);
+    }
+    auto pv = a.free_blocks.lower_bound(off);
+    if (pv != a.free_blocks.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {
+            start = pv->first;
+            len += pv->second;
+            a.freed_on.erase(pv->first);
+            a.free_blocks.erase(pv);
+        }
+    }
+    a.free_blocks[start] = len;
+    a.freed_on[start] = s;
+}
+}  // namespace
+
+Arena* arena_create(void* base, size_t bytes) {
+    auto* a = new Arena();
+    const auto b = reinterpret_cast<uintptr_t>(base);
+    const uintptr_t aligned = (b + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+    const size_t skip = static_cast<size_t>(aligned - b);
+    a->base = reinterpret_cast<char*>(aligned);
+    a->size = bytes > skip ? (bytes - skip) / kArenaAlign * kArenaAlign : 0;
+    if (a->size) a->free_blocks[0] = a->size;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_arenas.push_back(a);
+    return a;
+}
+
+void arena_destroy(Arena* a) noexcept {
+    if (!a) return;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        for (size_t i = 0; i < g_arenas.size(); ++i)
+            if (g_arenas[i] == a) {
+                g_arenas.erase(g_arenas.begin() + static_cast<long>(i));
+                break;
+            }
+    }
+    delete a;
+}
+
+size_t arena_peak(const Arena* a) { return a ? a->peak : 0; }
+size_t arena_size(const Arena* a) { return a ? a->size : 0; }
+
+ArenaScope::ArenaScope(Arena* a) : prev_(t_arena) { t_arena = a; }
+ArenaScope::~ArenaScope() { t_arena = prev_; }
+
 void* dev_alloc(size_t bytes, hipStream_t s) {
+    if (t_arena) {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        return arena_alloc(*t_arena, bytes, s);
+    }
     int dev = 0;
     AHR_HIP(hipGetDevice(&dev));
     const size_t cls = size_class(bytes);
@@ -194,6 +301,12 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
 void dev_free(void* p, hipStream_t s) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(g_alloc_mu);
+    for (Arena* a : g_arenas) {
+        if (static_cast<char*>(p) >= a->base && static_cast<char*>(p) < a->base + a->size) {
+            arena_free(*a, p, s);
+            return;
+        }
+    }
     auto it = g_live.find(p);
     if (it == g_live.end()) return;
     g_free.emplace(it->second.first, Block{p, it->second.first, s, nullptr, it->second.second});

@@ -332,6 +332,7 @@ struct HintArgs {
     const double* xbase_w;        // by execution row
     double* habs;                 // by execution row: sum of |weight| of the cell's hint entries
     float* hsg;                   // by execution row: their signed sum
+    double prune_tau;             // bin edges of salience exp(-maxRatio) |phi_b| below it are dropped (0: none)
 };
 
 __device__ __forceinline__ void window(const Grid& gr, int b, int& x0, int& x1, int& y0, int& y1) {
@@ -463,14 +464,21 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
                 window(a.gr, b, x0, x1, y0, y1);
                 auto bin_entry = [&](int tx, int ty, double rx, double ex, double ry, double ey) {
                     const int bb = ty * a.gr.nbx + tx;
+                    const int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
+                    const int64_t q = rp[a.first_bvirt + bb] + wpre[static_cast<int64_t>(bb) * ww * wh + slot] + my;
+                    if (a.prune_tau > 0.0 && !((rx > ry ? ex : ey) * fabs(a.phi[bb]) >= a.prune_tau)) {
+                        // below the salience threshold: both sides become holes that
+                        // the compaction removes
+                        put(make_int2(-1, 0));
+                        ent[q] = make_int2(-1, 0);
+                        return;
+                    }
                     const float wb = w_bin_of(rx, ex, ry, ey, a.phi[bb], bwi);
                     ha += fabs(static_cast<double>(wb));
                     hs += static_cast<double>(wb);
                     const int w = f_bits(wb);
                     put(make_int2(a.first_bvirt + bb, w));
-                    // slot of this cell's bin inside the window of bb
-                    const int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
-                    const int64_t q = rp[a.first_bvirt + bb] + wpre[static_cast<int64_t>(bb) * ww * wh + slot] + my;
+                    // (q: the slot of this cell's bin inside the window of bb)
                     ent[q] = make_int2(static_cast<int>(r), w);
                 };
                 const int nx = x1 - x0 + 1;
@@ -603,6 +611,52 @@ int window_half(float ratio, int nb) {
 
 }  // namespace
 
+// Salience pruning: entries marked with column -1 by the fill are removed,
+// every row keeping its order.  keep[e] = 1 for a kept entry below the
+// entry count (read on the device), 0 otherwise.
+__global__ void k_keep_flags(const int2* __restrict__ ent, const int32_t* __restrict__ nnz, int64_t cap,
+                             int32_t* __restrict__ keep) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    if (e < cap) keep[e] = e < *nnz && ent[e].x >= 0 ? 1 : 0;
+}
+
+__global__ void k_compact(const int2* __restrict__ ent, const int32_t* __restrict__ nnz,
+                          const int32_t* __restrict__ keep, const int32_t* __restrict__ pos,
+                          const int32_t* __restrict__ rp, int32_t n_rows, int2* __restrict__ out,
+                          int32_t* __restrict__ out_rp, int64_t cap) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
+    if (e < cap && e < *nnz && keep[e]) out[pos[e]] = ent[e];
+    if (e <= n_rows) out_rp[e] = pos[rp[e]];
+}
+
+void prune_hints(Graph& g, int64_t cap, hipStream_t s) {
+    const int32_t N = g.n_tot;
+    const int64_t n = cap > N + 1 ? cap : N + 1;
+    DevBuf<int32_t> keep, pos, rp;
+    DevBuf<int2> ent;
+    keep.ensure(static_cast<size_t>(cap) + 1, s);
+    pos.ensure(static_cast<size_t>(cap) + 1, s);
+    rp.ensure(static_cast<size_t>(N) + 1, s);
+    ent.ensure(static_cast<size_t>(cap) + 1, s);
+    hipLaunchKernelGGL(k_keep_flags, dim3(grid_for(cap, kBT)), dim3(kBT), 0, s, g.xhint_ent.p, g.xhint_rp.p + N, cap,
+                       keep.p);
+    AHR_LAUNCHED("k_keep_flags");
+    g.scan_tmp.ensure(scan_tmp_elems(cap), s);
+    scan_i32_to_i32(keep.p, pos.p, cap, g.scan_tmp.p, s);
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, g.xhint_ent.p, g.xhint_rp.p + N, keep.p,
+                       pos.p, g.xhint_rp.p, N, ent.p, rp.p, cap);
+    AHR_LAUNCHED("k_compact");
+    std::swap(g.xhint_ent.p, ent.p);
+    std::swap(g.xhint_ent.n, ent.n);
+    std::swap(g.xhint_rp.p, rp.p);
+    std::swap(g.xhint_rp.n, rp.n);
+    keep.release(s);
+    pos.release(s);
+    rp.release(s);
+    ent.release(s);
+    g.nnz_hint = -1;
+}
+
 void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     ProfScope ps(kStageHints, s);
     const ahr_hint_params& hp = g.hp;
@@ -732,6 +786,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.xhsg.ensure(static_cast<size_t>(n_inst) + 1, s);
     a.habs = g.xhabs.p;
     a.hsg = g.xhsg.p;
+    a.prune_tau = bin_hints ? static_cast<double>(hp.prune_tau) : 0.0;
 
     // 5. per cell: macros holding it, window size; (cell, macro) pairs
     g.nmac.ensure(static_cast<size_t>(n_inst) + 1, s);
@@ -814,6 +869,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
                            g.xhint_ent.p);
         AHR_LAUNCHED("k_macro_fill");
     }
+    if (a.prune_tau > 0.0 && cap > 0) prune_hints(g, cap, s);
 }
 
 }  // namespace ahr

@@ -14,10 +14,13 @@
 // the node pass meets the pins does not change the result.
 //
 // Layout: an index built once per netlist (ahr_wl_create) lists every
-// instance's pins (node_ptr / node_pins).  One call is three kernels: the
-// net pass (net totals into workgroup partials, per-pin gradients into a
-// [pins][ncols] float64 buffer), the node pass (one thread per instance),
-// and the fixed-order reduction of the partials.
+// instance's pins (node_ptr / node_pins) and gives each pin its position in
+// that list (pin_slot).  One call is three kernels: the net pass (net totals
+// into workgroup partials; per-pin gradients written at the pin's position,
+// so every instance's pins lie together in a [pins][ncols] float64 buffer),
+// the node pass (one thread per instance, contiguous reads), and the
+// fixed-order reduction of the partials.  Nets of at most 8 pins keep one
+// pin per lane in registers (one gather); larger ones loop over their pins.
 #include <cmath>
 
 #include "ahr_internal.hpp"
@@ -40,6 +43,7 @@ struct WlIndex {
     ahr_netlist nl;
     DevBuf<int32_t> node_ptr;     // [n_inst + 1]
     DevBuf<int32_t> node_pins;    // [n_pins] pins of each instance (order within an instance unspecified)
+    DevBuf<int32_t> pin_slot;     // [n_pins] position of each pin in node_pins
     int device = 0;
     mutable hipStream_t work_stream = nullptr;
     mutable int stream_uses = 0;
@@ -56,6 +60,7 @@ struct WlIndex {
         if (stream_uses > 1) (void)hipDeviceSynchronize();
         node_ptr.release(s);
         node_pins.release(s);
+        pin_slot.release(s);
     }
 };
 
@@ -65,10 +70,14 @@ __global__ void k_pin_slots(const int32_t* __restrict__ pin_node, int32_t n_pins
     if (p < n_pins) slot[p] = atomicAdd(&cnt[pin_node[p]], 1);
 }
 
-__global__ void k_pin_scatter(const int32_t* __restrict__ pin_node, int32_t n_pins, const int32_t* __restrict__ slot,
+__global__ void k_pin_scatter(const int32_t* __restrict__ pin_node, int32_t n_pins, int32_t* __restrict__ slot,
                               const int32_t* __restrict__ node_ptr, int32_t* __restrict__ node_pins) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p < n_pins) node_pins[node_ptr[pin_node[p]] + slot[p]] = static_cast<int32_t>(p);
+    if (p < n_pins) {
+        const int32_t k = node_ptr[pin_node[p]] + slot[p];
+        node_pins[k] = static_cast<int32_t>(p);
+        slot[p] = k;          // from here on: the pin's position in node_pins
+    }
 }
 
 // Coordinate of pin p in column c: instance position + pin offset (x or y).
@@ -114,13 +123,15 @@ __device__ __forceinline__ void acc_sums(NetAcc<P>& a, const float* pos, int nco
 
 template <int P>
 __device__ __forceinline__ void pin_grads(const NetAcc<P>& a, const float* pos, int ncols, const int32_t* pin_node,
-                                          const float* pin_off, int p, double inv_g, double* pin_g) {
+                                          const float* pin_off, int p, double inv_g, double* pin_g,
+                                          const int32_t* pin_slot) {
+    const int64_t k = pin_slot[p];
 #pragma unroll
     for (int c = 0; c < 2 * P; ++c) {
         double x = pin_coord(pos, ncols, pin_node, pin_off, p, c);
         double xp = a.tp[c] / a.sp[c], xm = a.tm[c] / a.sm[c];
         double pp = exp((x - a.hi[c]) * inv_g) / a.sp[c], pm = exp((a.lo[c] - x) * inv_g) / a.sm[c];
-        pin_g[static_cast<int64_t>(p) * ncols + c] = pp * (1.0 + (x - xp) * inv_g) - pm * (1.0 - (x - xm) * inv_g);
+        pin_g[k * ncols + c] = pp * (1.0 + (x - xp) * inv_g) - pm * (1.0 - (x - xm) * inv_g);
     }
 }
 
@@ -191,7 +202,8 @@ __global__ void __launch_bounds__(kBT) k_wa_nets(const float* __restrict__ pos, 
                                                  const int32_t* __restrict__ net_ptr, int32_t n_nets, int32_t per,
                                                  const int32_t* __restrict__ pin_node,
                                                  const float* __restrict__ pin_off, double inv_g,
-                                                 double* __restrict__ partial, double* __restrict__ pin_g) {
+                                                 double* __restrict__ partial, double* __restrict__ pin_g,
+                                                 const int32_t* __restrict__ pin_slot) {
     __shared__ double red[kBT / kWave];
     __shared__ unsigned long long big_mask[kBT / kWave];
     const int64_t lo_net = static_cast<int64_t>(blockIdx.x) * per;
@@ -204,6 +216,64 @@ __global__ void __launch_bounds__(kBT) k_wa_nets(const float* __restrict__ pos, 
     for (int64_t e = lo_net + threadIdx.x / kLanes; e < hi_net; e += kGroups) {
         const int p0 = net_ptr[e], p1 = net_ptr[e + 1];
         if (p1 - p0 > kWave || p1 - p0 < 1) continue;   // group-uniform
+        if (p1 - p0 <= kLanes) {
+            // at most one pin per lane: its coordinates and weights stay in
+            // registers (one gather, two exponentials per column)
+            const bool has = p0 + l < p1;
+            const int p = has ? p0 + l : p0;
+            double x[2 * P], hi[2 * P], lo[2 * P];
+#pragma unroll
+            for (int c = 0; c < 2 * P; ++c) {
+                x[c] = pin_coord(pos, ncols, pin_node, pin_off, p, c);
+                hi[c] = has ? x[c] : -1e300;
+                lo[c] = has ? x[c] : 1e300;
+            }
+#pragma unroll
+            for (int o = kLanes / 2; o > 0; o >>= 1) {
+#pragma unroll
+                for (int c = 0; c < 2 * P; ++c) {
+                    const double h2 = __shfl_xor(hi[c], o), l2 = __shfl_xor(lo[c], o);
+                    hi[c] = h2 > hi[c] ? h2 : hi[c];
+                    lo[c] = l2 < lo[c] ? l2 : lo[c];
+                }
+            }
+            double ep[2 * P], em[2 * P], sp[2 * P], tp[2 * P], sm[2 * P], tm[2 * P];
+#pragma unroll
+            for (int c = 0; c < 2 * P; ++c) {
+                ep[c] = has ? exp((x[c] - hi[c]) * inv_g) : 0.0;
+                em[c] = has ? exp((lo[c] - x[c]) * inv_g) : 0.0;
+                sp[c] = ep[c];
+                tp[c] = x[c] * ep[c];
+                sm[c] = em[c];
+                tm[c] = x[c] * em[c];
+            }
+#pragma unroll
+            for (int o = kLanes / 2; o > 0; o >>= 1) {
+#pragma unroll
+                for (int c = 0; c < 2 * P; ++c) {
+                    sp[c] += __shfl_xor(sp[c], o);
+                    tp[c] += __shfl_xor(tp[c], o);
+                    sm[c] += __shfl_xor(sm[c], o);
+                    tm[c] += __shfl_xor(tm[c], o);
+                }
+            }
+            if (pin_g && has) {
+                const int64_t k = pin_slot[p];
+#pragma unroll
+                for (int c = 0; c < 2 * P; ++c) {
+                    const double xp = tp[c] / sp[c], xm = tm[c] / sm[c];
+                    pin_g[k * ncols + c] =
+                        ep[c] / sp[c] * (1.0 + (x[c] - xp) * inv_g) - em[c] / sm[c] * (1.0 - (x[c] - xm) * inv_g);
+                }
+            }
+            if (l == 0) {
+#pragma unroll
+                for (int c = 0; c < P; ++c)
+                    tot[c] += (tp[2 * c] / sp[2 * c] - tm[2 * c] / sm[2 * c]) +
+                              (tp[2 * c + 1] / sp[2 * c + 1] - tm[2 * c + 1] / sm[2 * c + 1]);
+            }
+            continue;
+        }
         NetAcc<P> a;
         init_acc(a);
         for (int p = p0 + l; p < p1; p += kLanes) acc_bounds<P>(a, pos, ncols, pin_node, pin_off, p);
@@ -211,7 +281,7 @@ __global__ void __launch_bounds__(kBT) k_wa_nets(const float* __restrict__ pos, 
         for (int p = p0 + l; p < p1; p += kLanes) acc_sums<P>(a, pos, ncols, pin_node, pin_off, p, inv_g);
         group_sums<P>(a);
         if (pin_g)
-            for (int p = p0 + l; p < p1; p += kLanes) pin_grads<P>(a, pos, ncols, pin_node, pin_off, p, inv_g, pin_g);
+            for (int p = p0 + l; p < p1; p += kLanes) pin_grads<P>(a, pos, ncols, pin_node, pin_off, p, inv_g, pin_g, pin_slot);
         if (l == 0) {
 #pragma unroll
             for (int c = 0; c < P; ++c) tot[c] += net_wa<P>(a, c);
@@ -251,7 +321,7 @@ __global__ void __launch_bounds__(kBT) k_wa_nets(const float* __restrict__ pos, 
                 }
                 if (pin_g)
                     for (int p = p0 + threadIdx.x; p < p1; p += kBT)
-                        pin_grads<P>(a, pos, ncols, pin_node, pin_off, p, inv_g, pin_g);
+                        pin_grads<P>(a, pos, ncols, pin_node, pin_off, p, inv_g, pin_g, pin_slot);
                 if (threadIdx.x == 0) {
 #pragma unroll
                     for (int c = 0; c < P; ++c) tot[c] += net_wa<P>(a, c);
@@ -270,7 +340,6 @@ __global__ void __launch_bounds__(kBT) k_wa_nets(const float* __restrict__ pos, 
 // pins' gradients, rounded once to float32.
 template <int C>
 __global__ void __launch_bounds__(kBT) k_wa_nodes(const int32_t* __restrict__ node_ptr,
-                                                  const int32_t* __restrict__ node_pins,
                                                   const double* __restrict__ pin_g, int32_t n_inst,
                                                   float* __restrict__ grad) {
     const int64_t v = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
@@ -279,8 +348,8 @@ __global__ void __launch_bounds__(kBT) k_wa_nodes(const int32_t* __restrict__ no
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0;
     const int k0 = node_ptr[v], k1 = node_ptr[v + 1];
-    for (int k = k0; k < k1; ++k) {
-        const double* g = pin_g + static_cast<int64_t>(node_pins[k]) * C;
+    for (int k = k0; k < k1; ++k) {         // the instance's pins, stored contiguously
+        const double* g = pin_g + static_cast<int64_t>(k) * C;
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] += llrint(g[c] * kFix);
     }
@@ -329,11 +398,11 @@ void wa_p(const WlIndex& w, const float* pos, double inv_g, double* wl, float* g
     {
         ProfScope ps(kStageWa, s, bytes);
         hipLaunchKernelGGL(k_wa_nets<P>, dim3(grid), dim3(kBT), 0, s, pos, C, nl.net_ptr, nl.n_nets, per,
-                           nl.pin_node, nl.pin_off, inv_g, partial.p, grad ? pin_g.p : nullptr);
+                           nl.pin_node, nl.pin_off, inv_g, partial.p, grad ? pin_g.p : nullptr, w.pin_slot.p);
         AHR_LAUNCHED("k_wa_nets");
         if (grad) {
             hipLaunchKernelGGL(k_wa_nodes<C>, dim3(grid_for(nl.n_inst, kBT)), dim3(kBT), 0, s, w.node_ptr.p,
-                               w.node_pins.p, pin_g.p, nl.n_inst, grad);
+                               pin_g.p, nl.n_inst, grad);
             AHR_LAUNCHED("k_wa_nodes");
         }
         hipLaunchKernelGGL(k_wa_final, dim3(1), dim3(kFinalBT), 0, s, partial.p, grid, P, wl);
@@ -366,7 +435,8 @@ ahr_status ahr_wl_create(const ahr_netlist* nl, void* stream, ahr_wl** out) {
         try {
             AHR_HIP(hipGetDevice(&w->device));
             const int32_t n = nl->n_inst, P = nl->n_pins;
-            ahr::DevBuf<int32_t> cnt, slot;
+            ahr::DevBuf<int32_t> cnt;
+            ahr::DevBuf<int32_t>& slot = w->pin_slot;
             ahr::DevBuf<int64_t> tmp;
             cnt.ensure(static_cast<size_t>(n) + 1, s);
             slot.ensure(static_cast<size_t>(P > 0 ? P : 1), s);
@@ -386,7 +456,6 @@ ahr_status ahr_wl_create(const ahr_netlist* nl, void* stream, ahr_wl** out) {
                 AHR_LAUNCHED("k_pin_scatter");
             }
             cnt.release(s);
-            slot.release(s);
             tmp.release(s);
             AHR_HIP(hipStreamSynchronize(s));
         } catch (...) {

@@ -11,7 +11,7 @@ def f32(x):
 def params32(p: O.HintParams) -> O.HintParams:
     """The boundary takes float32 parameters; give the oracle the same values."""
     return O.HintParams(p.nbx, p.nby, f32(p.detection_ratio), f32(p.bin_capacity), f32(p.mu), p.clique_max,
-                        p.expand_macro_pins, p.macro_hints, p.bin_hints)
+                        p.expand_macro_pins, p.macro_hints, p.bin_hints, f32(p.prune_tau))
 
 
 def spec32(s: O.FilterSpec) -> O.FilterSpec:
@@ -22,7 +22,7 @@ def spec32(s: O.FilterSpec) -> O.FilterSpec:
 def to_c_params(A, p: O.HintParams):
     flags = ((A.EXPAND_MACRO_PINS if p.expand_macro_pins else 0) | (A.MACRO_HINTS if p.macro_hints else 0)
              | (A.BIN_HINTS if p.bin_hints else 0))
-    return A.hint_params(p.nbx, p.nby, p.detection_ratio, p.bin_capacity, p.mu, p.clique_max, flags)
+    return A.hint_params(p.nbx, p.nby, p.detection_ratio, p.bin_capacity, p.mu, p.clique_max, flags, p.prune_tau)
 
 
 def to_c_spec(A, s: O.FilterSpec):
