@@ -332,6 +332,10 @@ void build_netlist(Graph& g, hipStream_t s);
 // the count when read_total (one synchronisation), else -1.
 int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
                     DevBuf<int32_t>& start, hipStream_t s, bool read_total = true);
+// The same with its scratch given (i32a, i32b, scan_tmp: grown as needed).
+int32_t bucket_sort(const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list, DevBuf<int32_t>& start,
+                    DevBuf<int32_t>& i32a, DevBuf<int32_t>& i32b, DevBuf<int64_t>& scan_tmp, hipStream_t s,
+                    bool read_total = true);
 // Exact entry counts of g, read from its row pointers when not known yet.
 int32_t net_count(const Graph& g, hipStream_t s);
 int32_t hint_count(const Graph& g, hipStream_t s);

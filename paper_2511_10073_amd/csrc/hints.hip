@@ -561,8 +561,9 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n) {
 
 }  // namespace
 
-int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
-                    DevBuf<int32_t>& start, hipStream_t s, bool read_total) {
+int32_t bucket_sort(const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list, DevBuf<int32_t>& start,
+                    DevBuf<int32_t>& i32a, DevBuf<int32_t>& i32b, DevBuf<int64_t>& scan_tmp, hipStream_t s,
+                    bool read_total) {
     if (nkeys > kMaxBins) throw Error{AHR_EUNSUPPORTED, "too many buckets (at most 16384 bins or macros)"};
     list.ensure(static_cast<size_t>(n) + 1, s);
     start.ensure(static_cast<size_t>(nkeys) + 1, s);
@@ -572,31 +573,36 @@ int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<i
     }
     int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(n) + kTileCells - 1) / kTileCells);
     int64_t hn = static_cast<int64_t>(nkeys) * ntiles;
-    g.i32a.ensure(static_cast<size_t>(hn) + 1, s);
-    g.i32b.ensure(static_cast<size_t>(hn) + 1, s);
+    i32a.ensure(static_cast<size_t>(hn) + 1, s);
+    i32b.ensure(static_cast<size_t>(hn) + 1, s);
     const size_t lds = static_cast<size_t>(nkeys) * sizeof(int32_t);
     // counts tile-major (i32a) -> bucket-major (i32b) -> exclusive scan in
     // bucket-then-tile order (i32a, total at [hn]) -> tile-major offsets (i32b)
-    hipLaunchKernelGGL(k_bucket_count, dim3(ntiles), dim3(kWave), lds, s, key, n, nkeys, ntiles, g.i32a.p);
+    hipLaunchKernelGGL(k_bucket_count, dim3(ntiles), dim3(kWave), lds, s, key, n, nkeys, ntiles, i32a.p);
     AHR_LAUNCHED("k_bucket_count");
     hipLaunchKernelGGL(k_transpose_i32, dim3((nkeys + kTr - 1) / kTr, (ntiles + kTr - 1) / kTr), dim3(kTr * 8), 0, s,
-                       g.i32a.p, static_cast<int64_t>(ntiles), static_cast<int64_t>(nkeys), g.i32b.p);
+                       i32a.p, static_cast<int64_t>(ntiles), static_cast<int64_t>(nkeys), i32b.p);
     AHR_LAUNCHED("k_transpose_i32");
-    g.scan_tmp.ensure(scan_tmp_elems(hn), s);
-    scan_i32_to_i32(g.i32b.p, g.i32a.p, hn, g.scan_tmp.p, s);
+    scan_tmp.ensure(scan_tmp_elems(hn), s);
+    scan_i32_to_i32(i32b.p, i32a.p, hn, scan_tmp.p, s);
     hipLaunchKernelGGL(k_transpose_i32, dim3((ntiles + kTr - 1) / kTr, (nkeys + kTr - 1) / kTr), dim3(kTr * 8), 0, s,
-                       g.i32a.p, static_cast<int64_t>(nkeys), static_cast<int64_t>(ntiles), g.i32b.p);
+                       i32a.p, static_cast<int64_t>(nkeys), static_cast<int64_t>(ntiles), i32b.p);
     AHR_LAUNCHED("k_transpose_i32");
     int bits = 0;
     while ((1 << bits) < nkeys) ++bits;
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(ntiles), dim3(kWave), lds, s, key, n, nkeys, bits, ntiles, g.i32b.p,
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(ntiles), dim3(kWave), lds, s, key, n, nkeys, bits, ntiles, i32b.p,
                        list.p);
     AHR_LAUNCHED("k_bucket_scatter");
-    hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nkeys + 1, kBT)), dim3(kBT), 0, s, g.i32a.p, nkeys, ntiles,
-                       g.i32a.p + hn, start.p);
+    hipLaunchKernelGGL(k_bin_start, dim3(grid_for(nkeys + 1, kBT)), dim3(kBT), 0, s, i32a.p, nkeys, ntiles,
+                       i32a.p + hn, start.p);
     AHR_LAUNCHED("k_bin_start");
     if (!read_total) return -1;
     return read_i32(start.p + nkeys, s);
+}
+
+int32_t bucket_sort(Graph& g, const int32_t* key, int32_t n, int nkeys, DevBuf<int32_t>& list,
+                    DevBuf<int32_t>& start, hipStream_t s, bool read_total) {
+    return bucket_sort(key, n, nkeys, list, start, g.i32a, g.i32b, g.scan_tmp, s, read_total);
 }
 
 namespace {

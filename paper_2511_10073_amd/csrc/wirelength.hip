@@ -5,22 +5,28 @@
 // nets and both axes.  This is the wirelength term of the electrostatic
 // global placer that consumes the initializer's placement.
 //
-// Numbers: float64 throughout; each weight is taken relative to the net's
-// extreme coordinate (exp((x - max)/gamma), exp((min - x)/gamma)), which
-// cancels in every ratio.  Gradient of pin i:
+// Numbers: coordinates, sums and ratios in float64; each weight is taken
+// relative to the net's extreme coordinate (exp((x - max)/gamma),
+// exp((min - x)/gamma), which cancels in every ratio) and exponentiated in
+// float32 (arguments <= 0, values in (0, 1], relative error ~1e-7): the
+// weights are what the placer's gradient step needs, and float64
+// exponentials cost the pass several times its memory time.  Gradient of pin i:
 //   p+_i (1 + (x_i - xbar+)/gamma) - p-_i (1 - (x_i - xbar-)/gamma),
 // p+-_i the pin's normalised weight.  An instance's gradient is the sum over
 // its pins, added in int64 fixed point (2^-40 units), so the order in which
 // the node pass meets the pins does not change the result.
 //
 // Layout: an index built once per netlist (ahr_wl_create) lists every
-// instance's pins (node_ptr / node_pins) and gives each pin its position in
-// that list (pin_slot).  One call is three kernels: the net pass (net totals
-// into workgroup partials; per-pin gradients written at the pin's position,
-// so every instance's pins lie together in a [pins][ncols] float64 buffer),
-// the node pass (one thread per instance, contiguous reads), and the
-// fixed-order reduction of the partials.  Nets of at most 8 pins keep one
-// pin per lane in registers (one gather); larger ones loop over their pins.
+// instance's pins (node_ptr / node_pins), the nets of at most 64 pins in
+// ascending degree (a stable bucket sort, so the lanes of a wave mostly
+// meet nets of one degree and run the same trip counts) and the larger nets.
+// One call is four kernels: the small-net pass (one thread per net: no lane
+// idles on a short net and no cross-lane reduction; nets of at most 8 pins
+// keep their pins in registers), the big-net pass (one workgroup per net),
+// both writing net totals into workgroup partials and per-pin gradients into
+// a [pins][ncols] float64 buffer in pin order; the node pass (one thread per
+// instance gathers its pins' rows); and the fixed-order reduction of the
+// partials.
 #include <cmath>
 
 #include "ahr_internal.hpp"
@@ -31,10 +37,7 @@ namespace ahr {
 namespace {
 
 constexpr int kBT = 256;
-constexpr int kLanes = 8;
-constexpr int kGroups = kBT / kLanes;
-constexpr int kMaxGrid = 8192;
-constexpr int kNetsPerWg = 256;
+constexpr int kReg = 8;             // nets of up to kReg pins keep their pins in registers
 constexpr int kMaxPairs = 4;
 constexpr double kFix = 1099511627776.0;          // 2^40
 constexpr double kUnfix = 1.0 / 1099511627776.0;
@@ -43,7 +46,10 @@ struct WlIndex {
     ahr_netlist nl;
     DevBuf<int32_t> node_ptr;     // [n_inst + 1]
     DevBuf<int32_t> node_pins;    // [n_pins] pins of each instance (order within an instance unspecified)
-    DevBuf<int32_t> pin_slot;     // [n_pins] position of each pin in node_pins
+    DevBuf<int32_t> small;        // nets of 1..kWave pins, by ascending degree, ascending within a degree
+    int32_t n_small = 0;
+    DevBuf<int32_t> big;          // nets of more than kWave pins, ascending
+    int32_t n_big = 0;
     int device = 0;
     mutable hipStream_t work_stream = nullptr;
     mutable int stream_uses = 0;
@@ -60,9 +66,22 @@ struct WlIndex {
         if (stream_uses > 1) (void)hipDeviceSynchronize();
         node_ptr.release(s);
         node_pins.release(s);
-        pin_slot.release(s);
+        small.release(s);
+        big.release(s);
     }
 };
+
+// flag[e] = 1 for a net of more than kWave pins; key[e] = its degree for
+// one of 1..kWave pins, -1 otherwise (the bucket sort's key).
+__global__ void k_net_classes(const int32_t* __restrict__ net_ptr, int32_t n_nets, int32_t* __restrict__ flag,
+                              int32_t* __restrict__ key) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < n_nets) {
+        const int32_t d = net_ptr[e + 1] - net_ptr[e];
+        flag[e] = d > kWave ? 1 : 0;
+        key[e] = d >= 1 && d <= kWave ? d : -1;
+    }
+}
 
 __global__ void k_pin_slots(const int32_t* __restrict__ pin_node, int32_t n_pins, int32_t* __restrict__ cnt,
                             int32_t* __restrict__ slot) {
@@ -70,15 +89,15 @@ __global__ void k_pin_slots(const int32_t* __restrict__ pin_node, int32_t n_pins
     if (p < n_pins) slot[p] = atomicAdd(&cnt[pin_node[p]], 1);
 }
 
-__global__ void k_pin_scatter(const int32_t* __restrict__ pin_node, int32_t n_pins, int32_t* __restrict__ slot,
-                              const int32_t* __restrict__ node_ptr, int32_t* __restrict__ node_pins) {
+__global__ void k_pin_scatter(const int32_t* __restrict__ pin_node, int32_t n_pins,
+                              const int32_t* __restrict__ slot, const int32_t* __restrict__ node_ptr,
+                              int32_t* __restrict__ node_pins) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p < n_pins) {
-        const int32_t k = node_ptr[pin_node[p]] + slot[p];
-        node_pins[k] = static_cast<int32_t>(p);
-        slot[p] = k;          // from here on: the pin's position in node_pins
-    }
+    if (p < n_pins) node_pins[node_ptr[pin_node[p]] + slot[p]] = static_cast<int32_t>(p);
 }
+
+// exp(a) for a <= 0, in float32.
+__device__ __forceinline__ double wexp(double a) { return static_cast<double>(expf(static_cast<float>(a))); }
 
 // Coordinate of pin p in column c: instance position + pin offset (x or y).
 __device__ __forceinline__ double pin_coord(const float* pos, int ncols, const int32_t* pin_node, const float* pin_off,
@@ -87,252 +106,238 @@ __device__ __forceinline__ double pin_coord(const float* pos, int ncols, const i
            static_cast<double>(pin_off[2 * p + (c & 1)]);
 }
 
-// Per-net WA over the column range [0, 2P): the caller reduces the lane
-// partials (RED: lanes of one group or a whole workgroup) between passes.
-template <int P>
-struct NetAcc {
-    double hi[2 * P], lo[2 * P];      // extremes
-    double sp[2 * P], tp[2 * P];      // sum exp((x-hi)/g), sum x exp((x-hi)/g)
-    double sm[2 * P], tm[2 * P];      // sum exp((lo-x)/g), sum x exp((lo-x)/g)
+// One net and one column at a time (only that column's sums are live, so the
+// kernel keeps its registers few and its occupancy high).
+struct ColAcc {
+    double hi, lo;      // extremes
+    double sp, tp;      // sum exp((x-hi)/g), sum x exp((x-hi)/g)
+    double sm, tm;      // sum exp((lo-x)/g), sum x exp((lo-x)/g)
 };
 
-template <int P>
-__device__ __forceinline__ void acc_bounds(NetAcc<P>& a, const float* pos, int ncols, const int32_t* pin_node,
-                                           const float* pin_off, int p) {
-#pragma unroll
-    for (int c = 0; c < 2 * P; ++c) {
-        double x = pin_coord(pos, ncols, pin_node, pin_off, p, c);
-        a.hi[c] = x > a.hi[c] ? x : a.hi[c];
-        a.lo[c] = x < a.lo[c] ? x : a.lo[c];
-    }
+__device__ __forceinline__ double gpin(double x, const ColAcc& a, double inv_g) {
+    const double xp = a.tp / a.sp, xm = a.tm / a.sm;
+    const double pp = wexp((x - a.hi) * inv_g) / a.sp, pm = wexp((a.lo - x) * inv_g) / a.sm;
+    return pp * (1.0 + (x - xp) * inv_g) - pm * (1.0 - (x - xm) * inv_g);
 }
 
+// One net per thread, one column pair (x, y) at a time: extremes, shifted
+// sums, then each pin's gradient.  Nets of at most kReg pins gather their
+// pins once into registers (the degree checks are wave-uniform in the
+// sorted list); larger ones re-read their pins in each of the three passes.
+// Workgroup totals to partial[blockIdx.x].
 template <int P>
-__device__ __forceinline__ void acc_sums(NetAcc<P>& a, const float* pos, int ncols, const int32_t* pin_node,
-                                         const float* pin_off, int p, double inv_g) {
-#pragma unroll
-    for (int c = 0; c < 2 * P; ++c) {
-        double x = pin_coord(pos, ncols, pin_node, pin_off, p, c);
-        double ep = exp((x - a.hi[c]) * inv_g), em = exp((a.lo[c] - x) * inv_g);
-        a.sp[c] += ep;
-        a.tp[c] += x * ep;
-        a.sm[c] += em;
-        a.tm[c] += x * em;
-    }
-}
-
-template <int P>
-__device__ __forceinline__ void pin_grads(const NetAcc<P>& a, const float* pos, int ncols, const int32_t* pin_node,
-                                          const float* pin_off, int p, double inv_g, double* pin_g,
-                                          const int32_t* pin_slot) {
-    const int64_t k = pin_slot[p];
-#pragma unroll
-    for (int c = 0; c < 2 * P; ++c) {
-        double x = pin_coord(pos, ncols, pin_node, pin_off, p, c);
-        double xp = a.tp[c] / a.sp[c], xm = a.tm[c] / a.sm[c];
-        double pp = exp((x - a.hi[c]) * inv_g) / a.sp[c], pm = exp((a.lo[c] - x) * inv_g) / a.sm[c];
-        pin_g[k * ncols + c] = pp * (1.0 + (x - xp) * inv_g) - pm * (1.0 - (x - xm) * inv_g);
-    }
-}
-
-template <int P>
-__device__ __forceinline__ void init_acc(NetAcc<P>& a) {
-#pragma unroll
-    for (int c = 0; c < 2 * P; ++c) {
-        a.hi[c] = -1e300;
-        a.lo[c] = 1e300;
-        a.sp[c] = a.tp[c] = a.sm[c] = a.tm[c] = 0.0;
-    }
-}
-
-template <int P>
-__device__ __forceinline__ double net_wa(const NetAcc<P>& a, int pair) {
-    double w = 0;
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-        const int c = 2 * pair + d;
-        w += a.tp[c] / a.sp[c] - a.tm[c] / a.sm[c];
-    }
-    return w;
-}
-
-// Reduction of the kLanes lanes of a group (shuffles, fixed order).
-template <int P>
-__device__ __forceinline__ void group_bounds(NetAcc<P>& a) {
-#pragma unroll
-    for (int o = kLanes / 2; o > 0; o >>= 1) {
-#pragma unroll
-        for (int c = 0; c < 2 * P; ++c) {
-            double h = __shfl_xor(a.hi[c], o), l = __shfl_xor(a.lo[c], o);
-            a.hi[c] = h > a.hi[c] ? h : a.hi[c];
-            a.lo[c] = l < a.lo[c] ? l : a.lo[c];
-        }
-    }
-}
-
-template <int P>
-__device__ __forceinline__ void group_sums(NetAcc<P>& a) {
-#pragma unroll
-    for (int o = kLanes / 2; o > 0; o >>= 1) {
-#pragma unroll
-        for (int c = 0; c < 2 * P; ++c) {
-            a.sp[c] += __shfl_xor(a.sp[c], o);
-            a.tp[c] += __shfl_xor(a.tp[c], o);
-            a.sm[c] += __shfl_xor(a.sm[c], o);
-            a.tm[c] += __shfl_xor(a.tm[c], o);
-        }
-    }
-}
-
-// Whole-workgroup reductions of one net's values (every thread gets them);
-// red holds kBT / kWave doubles and is reused after a barrier.
-__device__ __forceinline__ double block_max_f64(double v, double* red) {
-    v = wave_max(v);
-    __syncthreads();
-    if (lane_id() == 0) red[wave_id()] = v;
-    __syncthreads();
-    double t = red[0];
-#pragma unroll
-    for (int w = 1; w < kBT / kWave; ++w) t = red[w] > t ? red[w] : t;
-    return t;
-}
-
-template <int P>
-__global__ void __launch_bounds__(kBT) k_wa_nets(const float* __restrict__ pos, int ncols,
-                                                 const int32_t* __restrict__ net_ptr, int32_t n_nets, int32_t per,
-                                                 const int32_t* __restrict__ pin_node,
-                                                 const float* __restrict__ pin_off, double inv_g,
-                                                 double* __restrict__ partial, double* __restrict__ pin_g,
-                                                 const int32_t* __restrict__ pin_slot) {
+__global__ void __launch_bounds__(kBT) k_wa_small(const float* __restrict__ pos, int ncols,
+                                                  const int32_t* __restrict__ net_ptr,
+                                                  const int32_t* __restrict__ list, int32_t n_list,
+                                                  const int32_t* __restrict__ pin_node,
+                                                  const float* __restrict__ pin_off, double inv_g,
+                                                  double* __restrict__ partial, double* __restrict__ pin_g) {
     __shared__ double red[kBT / kWave];
-    __shared__ unsigned long long big_mask[kBT / kWave];
-    const int64_t lo_net = static_cast<int64_t>(blockIdx.x) * per;
-    const int64_t hi_net = lo_net + per < n_nets ? lo_net + per : n_nets;
-    const int l = threadIdx.x & (kLanes - 1);
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
     double tot[P];
 #pragma unroll
-    for (int c = 0; c < P; ++c) tot[c] = 0;
-
-    for (int64_t e = lo_net + threadIdx.x / kLanes; e < hi_net; e += kGroups) {
-        const int p0 = net_ptr[e], p1 = net_ptr[e + 1];
-        if (p1 - p0 > kWave || p1 - p0 < 1) continue;   // group-uniform
-        if (p1 - p0 <= kLanes) {
-            // at most one pin per lane: its coordinates and weights stay in
-            // registers (one gather, two exponentials per column)
-            const bool has = p0 + l < p1;
-            const int p = has ? p0 + l : p0;
-            double x[2 * P], hi[2 * P], lo[2 * P];
+    for (int q = 0; q < P; ++q) tot[q] = 0;
+    if (i < n_list) {
+        const int e = list[i];
+        const int p0 = net_ptr[e], d = net_ptr[e + 1] - p0;
+        if (d <= kReg) {
+            int node[kReg];
+            float off[kReg][2], v[kReg][2];
 #pragma unroll
-            for (int c = 0; c < 2 * P; ++c) {
-                x[c] = pin_coord(pos, ncols, pin_node, pin_off, p, c);
-                hi[c] = has ? x[c] : -1e300;
-                lo[c] = has ? x[c] : 1e300;
-            }
+            for (int k = 0; k < kReg; ++k)
+                if (k < d) {
+                    node[k] = pin_node[p0 + k];
+                    off[k][0] = pin_off[2 * (p0 + k)];
+                    off[k][1] = pin_off[2 * (p0 + k) + 1];
+                }
+#pragma unroll 1
+            for (int q = 0; q < P; ++q) {
+                ColAcc a[2] = {{-1e300, 1e300, 0, 0, 0, 0}, {-1e300, 1e300, 0, 0, 0, 0}};
 #pragma unroll
-            for (int o = kLanes / 2; o > 0; o >>= 1) {
+                for (int k = 0; k < kReg; ++k)
+                    if (k < d) {
+                        const float* r = pos + static_cast<int64_t>(node[k]) * ncols + 2 * q;
+                        v[k][0] = r[0];
+                        v[k][1] = r[1];
 #pragma unroll
-                for (int c = 0; c < 2 * P; ++c) {
-                    const double h2 = __shfl_xor(hi[c], o), l2 = __shfl_xor(lo[c], o);
-                    hi[c] = h2 > hi[c] ? h2 : hi[c];
-                    lo[c] = l2 < lo[c] ? l2 : lo[c];
+                        for (int c = 0; c < 2; ++c) {
+                            const double x = static_cast<double>(v[k][c]) + static_cast<double>(off[k][c]);
+                            a[c].hi = x > a[c].hi ? x : a[c].hi;
+                            a[c].lo = x < a[c].lo ? x : a[c].lo;
+                        }
+                    }
+#pragma unroll
+                for (int k = 0; k < kReg; ++k)
+                    if (k < d) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const double x = static_cast<double>(v[k][c]) + static_cast<double>(off[k][c]);
+                            const double ep = wexp((x - a[c].hi) * inv_g), em = wexp((a[c].lo - x) * inv_g);
+                            a[c].sp += ep;
+                            a[c].tp += x * ep;
+                            a[c].sm += em;
+                            a[c].tm += x * em;
+                        }
+                    }
+                const double wq = (a[0].tp / a[0].sp - a[0].tm / a[0].sm) + (a[1].tp / a[1].sp - a[1].tm / a[1].sm);
+#pragma unroll
+                for (int j = 0; j < P; ++j) tot[j] += j == q ? wq : 0.0;
+                if (pin_g) {
+#pragma unroll
+                    for (int k = 0; k < kReg; ++k)
+                        if (k < d) {
+                            const double x0 = static_cast<double>(v[k][0]) + static_cast<double>(off[k][0]);
+                            const double x1 = static_cast<double>(v[k][1]) + static_cast<double>(off[k][1]);
+                            *reinterpret_cast<double2*>(pin_g + static_cast<int64_t>(p0 + k) * ncols + 2 * q) =
+                                make_double2(gpin(x0, a[0], inv_g), gpin(x1, a[1], inv_g));
+                        }
                 }
             }
-            double ep[2 * P], em[2 * P], sp[2 * P], tp[2 * P], sm[2 * P], tm[2 * P];
+        } else {
 #pragma unroll
-            for (int c = 0; c < 2 * P; ++c) {
-                ep[c] = has ? exp((x[c] - hi[c]) * inv_g) : 0.0;
-                em[c] = has ? exp((lo[c] - x[c]) * inv_g) : 0.0;
-                sp[c] = ep[c];
-                tp[c] = x[c] * ep[c];
-                sm[c] = em[c];
-                tm[c] = x[c] * em[c];
-            }
+            for (int q = 0; q < P; ++q) {
+                ColAcc a[2] = {{-1e300, 1e300, 0, 0, 0, 0}, {-1e300, 1e300, 0, 0, 0, 0}};
+                for (int p = p0; p < p0 + d; ++p)
 #pragma unroll
-            for (int o = kLanes / 2; o > 0; o >>= 1) {
+                    for (int c = 0; c < 2; ++c) {
+                        const double x = pin_coord(pos, ncols, pin_node, pin_off, p, 2 * q + c);
+                        a[c].hi = x > a[c].hi ? x : a[c].hi;
+                        a[c].lo = x < a[c].lo ? x : a[c].lo;
+                    }
+                for (int p = p0; p < p0 + d; ++p)
 #pragma unroll
-                for (int c = 0; c < 2 * P; ++c) {
-                    sp[c] += __shfl_xor(sp[c], o);
-                    tp[c] += __shfl_xor(tp[c], o);
-                    sm[c] += __shfl_xor(sm[c], o);
-                    tm[c] += __shfl_xor(tm[c], o);
-                }
-            }
-            if (pin_g && has) {
-                const int64_t k = pin_slot[p];
-#pragma unroll
-                for (int c = 0; c < 2 * P; ++c) {
-                    const double xp = tp[c] / sp[c], xm = tm[c] / sm[c];
-                    pin_g[k * ncols + c] =
-                        ep[c] / sp[c] * (1.0 + (x[c] - xp) * inv_g) - em[c] / sm[c] * (1.0 - (x[c] - xm) * inv_g);
-                }
-            }
-            if (l == 0) {
-#pragma unroll
-                for (int c = 0; c < P; ++c)
-                    tot[c] += (tp[2 * c] / sp[2 * c] - tm[2 * c] / sm[2 * c]) +
-                              (tp[2 * c + 1] / sp[2 * c + 1] - tm[2 * c + 1] / sm[2 * c + 1]);
-            }
-            continue;
-        }
-        NetAcc<P> a;
-        init_acc(a);
-        for (int p = p0 + l; p < p1; p += kLanes) acc_bounds<P>(a, pos, ncols, pin_node, pin_off, p);
-        group_bounds<P>(a);
-        for (int p = p0 + l; p < p1; p += kLanes) acc_sums<P>(a, pos, ncols, pin_node, pin_off, p, inv_g);
-        group_sums<P>(a);
-        if (pin_g)
-            for (int p = p0 + l; p < p1; p += kLanes) pin_grads<P>(a, pos, ncols, pin_node, pin_off, p, inv_g, pin_g, pin_slot);
-        if (l == 0) {
-#pragma unroll
-            for (int c = 0; c < P; ++c) tot[c] += net_wa<P>(a, c);
-        }
-    }
-
-    // the range's nets above kWave pins, one after another, by the whole workgroup
-    for (int64_t c0 = lo_net; c0 < hi_net; c0 += kBT) {
-        const int64_t e = c0 + threadIdx.x;
-        const bool big = e < hi_net && net_ptr[e + 1] - net_ptr[e] > kWave;
-        const unsigned long long m = __ballot(big);
-        __syncthreads();
-        if (lane_id() == 0) big_mask[wave_id()] = m;
-        __syncthreads();
-        for (int w = 0; w < kBT / kWave; ++w) {
-            unsigned long long mm = big_mask[w];
-            while (mm) {
-                const int b = __ffsll(static_cast<long long>(mm)) - 1;
-                mm &= mm - 1;
-                const int64_t net = c0 + w * kWave + b;
-                const int p0 = net_ptr[net], p1 = net_ptr[net + 1];
-                NetAcc<P> a;
-                init_acc(a);
-                for (int p = p0 + threadIdx.x; p < p1; p += kBT) acc_bounds<P>(a, pos, ncols, pin_node, pin_off, p);
-#pragma unroll
-                for (int c = 0; c < 2 * P; ++c) {
-                    a.hi[c] = block_max_f64(a.hi[c], red);
-                    a.lo[c] = -block_max_f64(-a.lo[c], red);
-                }
-                for (int p = p0 + threadIdx.x; p < p1; p += kBT) acc_sums<P>(a, pos, ncols, pin_node, pin_off, p, inv_g);
-#pragma unroll
-                for (int c = 0; c < 2 * P; ++c) {
-                    a.sp[c] = block_sum_f64<kBT>(a.sp[c], red);
-                    a.tp[c] = block_sum_f64<kBT>(a.tp[c], red);
-                    a.sm[c] = block_sum_f64<kBT>(a.sm[c], red);
-                    a.tm[c] = block_sum_f64<kBT>(a.tm[c], red);
-                }
+                    for (int c = 0; c < 2; ++c) {
+                        const double x = pin_coord(pos, ncols, pin_node, pin_off, p, 2 * q + c);
+                        const double ep = wexp((x - a[c].hi) * inv_g), em = wexp((a[c].lo - x) * inv_g);
+                        a[c].sp += ep;
+                        a[c].tp += x * ep;
+                        a[c].sm += em;
+                        a[c].tm += x * em;
+                    }
+                tot[q] += (a[0].tp / a[0].sp - a[0].tm / a[0].sm) + (a[1].tp / a[1].sp - a[1].tm / a[1].sm);
                 if (pin_g)
-                    for (int p = p0 + threadIdx.x; p < p1; p += kBT)
-                        pin_grads<P>(a, pos, ncols, pin_node, pin_off, p, inv_g, pin_g, pin_slot);
-                if (threadIdx.x == 0) {
-#pragma unroll
-                    for (int c = 0; c < P; ++c) tot[c] += net_wa<P>(a, c);
-                }
+                    for (int p = p0; p < p0 + d; ++p)
+                        *reinterpret_cast<double2*>(pin_g + static_cast<int64_t>(p) * ncols + 2 * q) =
+                            make_double2(gpin(pin_coord(pos, ncols, pin_node, pin_off, p, 2 * q), a[0], inv_g),
+                                         gpin(pin_coord(pos, ncols, pin_node, pin_off, p, 2 * q + 1), a[1], inv_g));
             }
         }
     }
 #pragma unroll
-    for (int c = 0; c < P; ++c) {
-        double s = block_sum_f64<kBT>(tot[c], red);
-        if (threadIdx.x == 0) partial[static_cast<int64_t>(blockIdx.x) * kMaxPairs + c] = s;
+    for (int q = 0; q < P; ++q) {
+        const double s2 = block_sum_f64<kBT>(tot[q], red);
+        if (threadIdx.x == 0) partial[static_cast<int64_t>(blockIdx.x) * kMaxPairs + q] = s2;
+    }
+}
+
+// Running (shifted) exponential sums: value m (the shift: the largest x so
+// far for the maximum side, the smallest for the minimum side), sum of
+// exp(+-(x - m)/g) and of x times it; merging rescales the side with the
+// smaller (larger) shift.  One pass gives what the three-pass form gives.
+struct Run {
+    double m, s, t;
+};
+
+__device__ __forceinline__ void run_add(Run& r, double x, double sgn_inv_g) {
+    // sgn_inv_g = +1/g (maximum side) or -1/g (minimum side)
+    const double q = (x - r.m) * sgn_inv_g;
+    if (q > 0) {            // new extreme: rescale what is there
+        const double f = wexp(-q);
+        r.s = r.s * f + 1.0;
+        r.t = r.t * f + x;
+        r.m = x;
+    } else {
+        const double e = wexp(q);
+        r.s += e;
+        r.t += x * e;
+    }
+}
+
+__device__ __forceinline__ Run run_merge(Run a, Run b, double sgn_inv_g) {
+    if (b.s == 0) return a;
+    if (a.s == 0) return b;
+    if ((b.m - a.m) * sgn_inv_g > 0) {
+        Run t = a;
+        a = b;
+        b = t;
+    }
+    const double f = wexp((b.m - a.m) * sgn_inv_g);
+    return Run{a.m, a.s + b.s * f, a.t + b.t * f};
+}
+
+// The nets above kWave pins, one workgroup each (listed once per index):
+// one pass for the shifted sums of every column, one for the gradients.
+template <int P>
+__global__ void __launch_bounds__(kBT) k_wa_big(const float* __restrict__ pos, int ncols,
+                                                const int32_t* __restrict__ net_ptr, const int32_t* __restrict__ big,
+                                                const int32_t* __restrict__ pin_node,
+                                                const float* __restrict__ pin_off, double inv_g,
+                                                double* __restrict__ partial, double* __restrict__ pin_g) {
+    __shared__ Run red[2 * P][2][kBT / kWave];
+    const int e = big[blockIdx.x];
+    const int p0 = net_ptr[e], p1 = net_ptr[e + 1];
+    Run rp[2 * P], rm[2 * P];
+#pragma unroll
+    for (int c = 0; c < 2 * P; ++c) {
+        rp[c] = Run{-1e300, 0, 0};
+        rm[c] = Run{1e300, 0, 0};
+    }
+    for (int p = p0 + threadIdx.x; p < p1; p += kBT) {
+#pragma unroll
+        for (int c = 0; c < 2 * P; ++c) {
+            const double x = pin_coord(pos, ncols, pin_node, pin_off, p, c);
+            if (rp[c].s == 0) {
+                rp[c] = Run{x, 1.0, x};
+                rm[c] = Run{x, 1.0, x};
+            } else {
+                run_add(rp[c], x, inv_g);
+                run_add(rm[c], x, -inv_g);
+            }
+        }
+    }
+    // wave then workgroup merges, in a fixed order
+#pragma unroll
+    for (int c = 0; c < 2 * P; ++c) {
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            Run a{__shfl_xor(rp[c].m, o), __shfl_xor(rp[c].s, o), __shfl_xor(rp[c].t, o)};
+            Run b{__shfl_xor(rm[c].m, o), __shfl_xor(rm[c].s, o), __shfl_xor(rm[c].t, o)};
+            // lane pairs merge in lane order so both lanes hold the same bits
+            rp[c] = (lane_id() & o) ? run_merge(a, rp[c], inv_g) : run_merge(rp[c], a, inv_g);
+            rm[c] = (lane_id() & o) ? run_merge(b, rm[c], -inv_g) : run_merge(rm[c], b, -inv_g);
+        }
+        if (lane_id() == 0) {
+            red[c][0][wave_id()] = rp[c];
+            red[c][1][wave_id()] = rm[c];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2 * P; ++c) {
+        rp[c] = red[c][0][0];
+        rm[c] = red[c][1][0];
+        for (int w = 1; w < kBT / kWave; ++w) {
+            rp[c] = run_merge(rp[c], red[c][0][w], inv_g);
+            rm[c] = run_merge(rm[c], red[c][1][w], -inv_g);
+        }
+    }
+    if (pin_g) {
+        for (int p = p0 + threadIdx.x; p < p1; p += kBT) {
+            const int64_t k = static_cast<int64_t>(p) * ncols;
+#pragma unroll
+            for (int c = 0; c < 2 * P; ++c) {
+                const double x = pin_coord(pos, ncols, pin_node, pin_off, p, c);
+                const ColAcc a{rp[c].m, rm[c].m, rp[c].s, rp[c].t, rm[c].s, rm[c].t};
+                pin_g[k + c] = gpin(x, a, inv_g);
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < P; ++c)
+            partial[static_cast<int64_t>(blockIdx.x) * kMaxPairs + c] =
+                (rp[2 * c].t / rp[2 * c].s - rm[2 * c].t / rm[2 * c].s) +
+                (rp[2 * c + 1].t / rp[2 * c + 1].s - rm[2 * c + 1].t / rm[2 * c + 1].s);
     }
 }
 
@@ -340,6 +345,7 @@ __global__ void __launch_bounds__(kBT) k_wa_nets(const float* __restrict__ pos, 
 // pins' gradients, rounded once to float32.
 template <int C>
 __global__ void __launch_bounds__(kBT) k_wa_nodes(const int32_t* __restrict__ node_ptr,
+                                                  const int32_t* __restrict__ node_pins,
                                                   const double* __restrict__ pin_g, int32_t n_inst,
                                                   float* __restrict__ grad) {
     const int64_t v = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x;
@@ -348,8 +354,8 @@ __global__ void __launch_bounds__(kBT) k_wa_nodes(const int32_t* __restrict__ no
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0;
     const int k0 = node_ptr[v], k1 = node_ptr[v + 1];
-    for (int k = k0; k < k1; ++k) {         // the instance's pins, stored contiguously
-        const double* g = pin_g + static_cast<int64_t>(k) * C;
+    for (int k = k0; k < k1; ++k) {
+        const double* g = pin_g + static_cast<int64_t>(node_pins[k]) * C;
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] += llrint(g[c] * kFix);
     }
@@ -358,54 +364,50 @@ __global__ void __launch_bounds__(kBT) k_wa_nodes(const int32_t* __restrict__ no
 }
 
 constexpr int kFinalBT = 1024;
-constexpr int kFinalPer = (kMaxGrid + kFinalBT - 1) / kFinalBT;
 
+// The partials in a fixed order: thread t adds partials t, t + kFinalBT, ...
+// in turn, then a fixed block reduction.
 __global__ void __launch_bounds__(kFinalBT) k_wa_final(const double* __restrict__ partial, int nparts, int npairs,
                                                        double* __restrict__ out) {
     __shared__ double red[kFinalBT / kWave];
     for (int c = 0; c < npairs; ++c) {
-        double v[kFinalPer];
-#pragma unroll
-        for (int u = 0; u < kFinalPer; ++u) {
-            const int b = static_cast<int>(threadIdx.x) + u * kFinalBT;
-            v[u] = partial[(b < nparts ? b : nparts - 1) * kMaxPairs + c];
-        }
         double s = 0;
-#pragma unroll
-        for (int u = 0; u < kFinalPer; ++u) s += static_cast<int>(threadIdx.x) + u * kFinalBT < nparts ? v[u] : 0.0;
+        for (int b = threadIdx.x; b < nparts; b += kFinalBT) s += partial[static_cast<int64_t>(b) * kMaxPairs + c];
         s = block_sum_f64<kFinalBT>(s, red);
         if (threadIdx.x == 0) out[c] = s;
     }
-}
-
-int wa_grid(int32_t n_nets) {
-    int64_t g = (static_cast<int64_t>(n_nets) + kNetsPerWg - 1) / kNetsPerWg;
-    return static_cast<int>(g < 1 ? 1 : (g > kMaxGrid ? kMaxGrid : g));
 }
 
 template <int P>
 void wa_p(const WlIndex& w, const float* pos, double inv_g, double* wl, float* grad, hipStream_t s) {
     const ahr_netlist& nl = w.nl;
     constexpr int C = 2 * P;
-    const int grid = wa_grid(nl.n_nets);
-    const int32_t per = static_cast<int32_t>((static_cast<int64_t>(nl.n_nets) + grid - 1) / grid);
+    const int grid = static_cast<int>((static_cast<int64_t>(w.n_small) + kBT - 1) / kBT);
     DevBuf<double> partial, pin_g;
-    partial.ensure(static_cast<size_t>(grid) * kMaxPairs, s);
+    partial.ensure(static_cast<size_t>(grid + w.n_big + 1) * kMaxPairs, s);
     if (grad) pin_g.ensure(static_cast<size_t>(nl.n_pins > 0 ? nl.n_pins : 1) * C, s);
     const double bytes = static_cast<double>(nl.n_pins) * (4 + 8 + 4 * C + (grad ? 8 * C * 2 + 4 : 0)) +
                          static_cast<double>(nl.n_nets + 1) * 4 +
                          (grad ? static_cast<double>(nl.n_inst) * (4 + 4 * C) : 0.0);
     {
         ProfScope ps(kStageWa, s, bytes);
-        hipLaunchKernelGGL(k_wa_nets<P>, dim3(grid), dim3(kBT), 0, s, pos, C, nl.net_ptr, nl.n_nets, per,
-                           nl.pin_node, nl.pin_off, inv_g, partial.p, grad ? pin_g.p : nullptr, w.pin_slot.p);
-        AHR_LAUNCHED("k_wa_nets");
+        if (grid) {
+            hipLaunchKernelGGL(k_wa_small<P>, dim3(grid), dim3(kBT), 0, s, pos, C, nl.net_ptr, w.small.p, w.n_small,
+                               nl.pin_node, nl.pin_off, inv_g, partial.p, grad ? pin_g.p : nullptr);
+            AHR_LAUNCHED("k_wa_small");
+        }
+        if (w.n_big) {
+            hipLaunchKernelGGL(k_wa_big<P>, dim3(w.n_big), dim3(kBT), 0, s, pos, C, nl.net_ptr, w.big.p, nl.pin_node,
+                               nl.pin_off, inv_g, partial.p + static_cast<int64_t>(grid) * kMaxPairs,
+                               grad ? pin_g.p : nullptr);
+            AHR_LAUNCHED("k_wa_big");
+        }
         if (grad) {
             hipLaunchKernelGGL(k_wa_nodes<C>, dim3(grid_for(nl.n_inst, kBT)), dim3(kBT), 0, s, w.node_ptr.p,
-                               pin_g.p, nl.n_inst, grad);
+                               w.node_pins.p, pin_g.p, nl.n_inst, grad);
             AHR_LAUNCHED("k_wa_nodes");
         }
-        hipLaunchKernelGGL(k_wa_final, dim3(1), dim3(kFinalBT), 0, s, partial.p, grid, P, wl);
+        hipLaunchKernelGGL(k_wa_final, dim3(1), dim3(kFinalBT), 0, s, partial.p, grid + w.n_big, P, wl);
         AHR_LAUNCHED("k_wa_final");
     }
     partial.release(s);
@@ -435,8 +437,7 @@ ahr_status ahr_wl_create(const ahr_netlist* nl, void* stream, ahr_wl** out) {
         try {
             AHR_HIP(hipGetDevice(&w->device));
             const int32_t n = nl->n_inst, P = nl->n_pins;
-            ahr::DevBuf<int32_t> cnt;
-            ahr::DevBuf<int32_t>& slot = w->pin_slot;
+            ahr::DevBuf<int32_t> cnt, slot;
             ahr::DevBuf<int64_t> tmp;
             cnt.ensure(static_cast<size_t>(n) + 1, s);
             slot.ensure(static_cast<size_t>(P > 0 ? P : 1), s);
@@ -454,6 +455,28 @@ ahr_status ahr_wl_create(const ahr_netlist* nl, void* stream, ahr_wl** out) {
                 hipLaunchKernelGGL(ahr::k_pin_scatter, dim3(ahr::grid_for(P, ahr::kBT)), dim3(ahr::kBT), 0, s,
                                    nl->pin_node, P, slot.p, w->node_ptr.p, w->node_pins.p);
                 AHR_LAUNCHED("k_pin_scatter");
+            }
+            slot.release(s);
+            // nets above kWave pins, ascending (a flag scan); the others by degree
+            if (nl->n_nets > 0) {
+                ahr::DevBuf<int32_t> flag, rank, key, start, a, b;
+                flag.ensure(static_cast<size_t>(nl->n_nets) + 1, s);
+                rank.ensure(static_cast<size_t>(nl->n_nets) + 1, s);
+                key.ensure(static_cast<size_t>(nl->n_nets) + 1, s);
+                tmp.ensure(ahr::scan_tmp_elems(nl->n_nets), s);
+                hipLaunchKernelGGL(ahr::k_net_classes, dim3(ahr::grid_for(nl->n_nets, ahr::kBT)), dim3(ahr::kBT), 0,
+                                   s, nl->net_ptr, nl->n_nets, flag.p, key.p);
+                AHR_LAUNCHED("k_net_classes");
+                w->n_big = static_cast<int32_t>(ahr::scan_i32_checked(flag.p, rank.p, nl->n_nets, tmp.p, s));
+                w->big.ensure(static_cast<size_t>(w->n_big) + 1, s);
+                ahr::list_rows(flag.p, rank.p, nl->n_nets, w->big.p, s);
+                flag.release(s);
+                rank.release(s);
+                w->n_small = ahr::bucket_sort(key.p, nl->n_nets, ahr::kWave + 1, w->small, start, a, b, tmp, s);
+                key.release(s);
+                start.release(s);
+                a.release(s);
+                b.release(s);
             }
             cnt.release(s);
             tmp.release(s);

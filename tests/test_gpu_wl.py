@@ -1,11 +1,14 @@
 """GPU parity of the WA wirelength and its gradient (ahr_wl_create /
 ahr_wa) against the FP64 oracle, through the C ABI.
 
-Bars (derived from the arithmetic): totals are float64 on both sides, so
-within 1e-12 relative; an instance gradient is float64 per pin, summed
-exactly in 2^-40 fixed point and rounded once to float32, so within
-2^-23 relative of the oracle's plus 1e-9 absolute (the fixed-point rounding
-of up to a few thousand pins)."""
+Bars (derived from the arithmetic): the device takes every exponential
+weight in float32 (relative error below 2^-22 with `expf`), the rest in
+float64.  A net's smooth maximum is a weighted mean, so a relative error of
+e in every weight moves it by at most e times the net's spread: totals
+within 4e-7 relative of the oracle's.  A pin's gradient p (1 +- (x - xbar)/g)
+moves by at most a few e times (1 + spread/g); its instance sums a few
+pins exactly in 2^-40 fixed point and rounds once to float32: within 2e-6
+(1 + |ref|) plus 2^-23 relative."""
 import numpy as np
 import pytest
 import torch
@@ -39,9 +42,9 @@ def check(nl, G, gamma):
     assert torch.equal(tot, tot2) and torch.equal(grad, grad2) and torch.equal(tot, only)
     # the boundary takes gamma in float32: give the oracle the same value
     rt, _, rg = W.wa_wirelength(nl, G, float(np.float32(gamma)))
-    assert np.allclose(tot.cpu().numpy(), rt, rtol=1e-12, atol=0)
+    assert np.allclose(tot.cpu().numpy(), rt, rtol=4e-7, atol=0)
     g = grad.cpu().numpy().astype(np.float64)
-    assert np.all(np.abs(g - rg) <= 2.0 ** -23 * np.abs(rg) + 1e-9), np.max(np.abs(g - rg))
+    assert np.all(np.abs(g - rg) <= 2e-6 * (1 + np.abs(rg)) + 2.0 ** -23 * np.abs(rg)), np.max(np.abs(g - rg))
 
 
 @pytest.mark.parametrize("name,cfg", CASES, ids=[c[0] for c in CASES])
