@@ -421,9 +421,10 @@ def prune_line(A, torch, np, nl, net, bins, spec, g0, rounds, gamma, plain_out, 
 
     y_ref, ms_ref, nnz_ref = filter_call(0.0)
     rows = []
+    ims_ref = None
     out = torch.empty_like(g0)
     hp = torch.empty_like(plain_hpwl)
-    for tau in taus:
+    for tau in (0.0,) + tuple(taus):
         y, fms, nnz = filter_call(tau)
         p = A.hint_params(nbx=bins, nby=bins, prune_tau=tau)
 
@@ -440,11 +441,15 @@ def prune_line(A, torch, np, nl, net, bins, spec, g0, rounds, gamma, plain_out, 
             step()
         torch.cuda.synchronize()
         ims = 1e3 * (time.perf_counter() - t0) / reps
+        if tau == 0.0:
+            ims_ref = ims       # the same step, timed the same way, unpruned
+            continue
         h, h0 = hp.cpu().numpy(), plain_hpwl.cpu().numpy()
         rows.append({"tau": tau, "nnz_hint": nnz, "filter_ms": round(fms, 4), "filter_rel_err": rel(y, y_ref),
                      "initializer_ms": round(ims, 3), "initializer_rel_err": rel(out, plain_out),
                      "hpwl_delta": float(np.max(np.abs(h - h0) / h0))})
-    return {"unpruned": {"nnz_hint": nnz_ref, "filter_ms": round(ms_ref, 4)}, "by_tau": rows}
+    return {"unpruned": {"nnz_hint": nnz_ref, "filter_ms": round(ms_ref, 4), "initializer_ms": round(ims_ref, 3)},
+            "by_tau": rows}
 
 
 def charge_line(A, torch, net, g, reps, bins=32):

@@ -259,6 +259,8 @@ struct Graph {
     DevBuf<int32_t> mlist, mstart; // pairs grouped by macro
     DevBuf<int32_t> bin_rank;     // [n_inst] position of a hint cell in bin_cells
     DevBuf<int32_t> wpre;         // [n_bins * window slots] offsets of the slots in bin rows
+    DevBuf<unsigned long long> keep_mask;  // [n_inst] per execution row: window slots whose bin edge is kept
+    DevBuf<int32_t> kept;         // [n_bins * window slots] cells of a bin keeping the edge to each window slot
     DevBuf<int64_t> xcell;        // [n_inst] per execution row: cell area (2^-28 units) * 4 + cell class
     DevBuf<double> xbase_w;       // [n_inst] per execution row: baseWeight
     DevBuf<float2> xpos;          // [n_inst] per execution row: the current placement's (x, y)

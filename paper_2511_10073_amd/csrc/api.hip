@@ -42,8 +42,9 @@ Graph::~Graph() {
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_len, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
                               &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart,
-                              &big_stars, &i32a, &i32b, &counter};
+                              &big_stars, &i32a, &i32b, &counter, &kept};
     for (auto* b : i32) b->release(s);
+    keep_mask.release(s);
     net_q.release(s);
     net_off.release(s);
     perm.release(s);

@@ -333,7 +333,20 @@ struct HintArgs {
     double* habs;                 // by execution row: sum of |weight| of the cell's hint entries
     float* hsg;                   // by execution row: their signed sum
     double prune_tau;             // bin edges of salience exp(-maxRatio) |phi_b| below it are dropped (0: none)
+    // Pruning decided in the count pass (windows of at most 64 slots): the
+    // kept window slots of each cell (bit j: slot j of the cell's own window,
+    // row-major), the kept cells per (bin, slot), and the cells' macro counts.
+    unsigned long long* keep_mask;
+    const int32_t* kept;
+    const int32_t* nmac;
 };
+
+// A cell's window slot j (row-major over its own window) holds bin
+// (bx + j % ww - hx, by + j / ww - hy); seen from that bin, the cell's bin is
+// slot wslots - 1 - j of the bin's window.
+__device__ __forceinline__ bool keep_bin_edge(double rx, double ex, double ry, double ey, double phi_b, double tau) {
+    return (rx > ry ? ex : ey) * fabs(phi_b) >= tau;
+}
 
 __device__ __forceinline__ void window(const Grid& gr, int b, int& x0, int& x1, int& y0, int& y1) {
     int bx = b % gr.nbx, by = b / gr.nbx;
@@ -376,8 +389,83 @@ __global__ void __launch_bounds__(kBT) k_cell_count(HintArgs a, int32_t* __restr
         nmac[r] = n;
         int x0, x1, y0, y1;
         window(a.gr, b, x0, x1, y0, y1);
-        nwin[r] = a.bin_hints ? (x1 - x0 + 1) * (y1 - y0 + 1) : 0;
+        if (a.keep_mask) {
+            // the salience test of every window bin, as the fill takes it
+            const float2 xy = a.xpos[r];
+            const int ww = 2 * a.gr.hx + 1, bx = b % a.gr.nbx, by = b / a.gr.nbx;
+            unsigned long long m = 0ull;
+            for (int ty = y0; ty <= y1; ++ty) {
+                const double ry = bin_ry(a.gr, xy.y, ty), ey = exp(-ry);
+                for (int tx = x0; tx <= x1; ++tx) {
+                    const double rx = bin_rx(a.gr, xy.x, tx);
+                    if (keep_bin_edge(rx, exp(-rx), ry, ey, a.phi[ty * a.gr.nbx + tx], a.prune_tau))
+                        m |= 1ull << ((ty - by + a.gr.hy) * ww + (tx - bx + a.gr.hx));
+                }
+            }
+            a.keep_mask[r] = m;
+            nwin[r] = __popcll(m);
+        } else {
+            nwin[r] = a.bin_hints ? (x1 - x0 + 1) * (y1 - y0 + 1) : 0;
+        }
     }
+}
+
+// Pruned bin rows are built over tiles: each bin's cells (bin_cells order)
+// cut into runs of kBT, tile_start[b] the first tile of bin b.  The tile of
+// workgroup `tile`, or false past the last one.
+__device__ __forceinline__ bool tile_of(const int32_t* tile_start, int nbins, int tile, int& b, int& k) {
+    if (tile >= tile_start[nbins]) return false;
+    int lo = 0, hi = nbins - 1;          // the last bin whose first tile is <= tile
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    b = lo;
+    k = tile - tile_start[lo];
+    return true;
+}
+
+__global__ void k_bin_tile_counts(const int32_t* __restrict__ bin_start, int nbins, int32_t* __restrict__ ntiles) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nbins) ntiles[b] = (bin_start[b + 1] - bin_start[b] + kBT - 1) / kBT;
+}
+
+// tcnt[tile * wslots + j]: the tile's cells keeping window slot j (wave
+// ballots, integer sums).
+__global__ void __launch_bounds__(kBT) k_tile_keep_counts(HintArgs a, const int32_t* __restrict__ tile_start,
+                                                          int wslots, int32_t* __restrict__ tcnt) {
+    __shared__ int wtot[kBT / kWave][64];
+    int b, k;
+    if (!tile_of(tile_start, a.nbins, blockIdx.x, b, k)) return;
+    const int t = a.bin_start[b] + k * kBT + static_cast<int>(threadIdx.x);
+    const unsigned long long m = t < a.bin_start[b + 1] ? a.keep_mask[a.bin_cells[t]] : 0ull;
+    for (int j = 0; j < wslots; ++j) {
+        const unsigned long long bal = __ballot((m >> j) & 1ull);
+        if (lane_id() == 0) wtot[wave_id()][j] = __popcll(bal);
+    }
+    __syncthreads();
+    if (threadIdx.x < wslots) {
+        int n = 0;
+        for (int w = 0; w < kBT / kWave; ++w) n += wtot[w][threadIdx.x];
+        tcnt[static_cast<int64_t>(blockIdx.x) * wslots + threadIdx.x] = n;
+    }
+}
+
+// Per (bin, slot): each tile's carry (kept cells of the bin's earlier tiles)
+// in place of its count, and kept[b * wslots + j], the bin's total.
+__global__ void k_tile_carry(const int32_t* __restrict__ tile_start, int nbins, int wslots,
+                             int32_t* __restrict__ tcnt, int32_t* __restrict__ kept) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= static_cast<int64_t>(nbins) * wslots) return;
+    const int b = static_cast<int>(i / wslots), j = static_cast<int>(i % wslots);
+    int acc = 0;
+    for (int t = tile_start[b]; t < tile_start[b + 1]; ++t) {
+        const int64_t q = static_cast<int64_t>(t) * wslots + j;
+        const int c = tcnt[q];
+        tcnt[q] = acc;
+        acc += c;
+    }
+    kept[i] = acc;
 }
 
 // The three row-count passes in one launch (they write disjoint rows of
@@ -400,10 +488,15 @@ __global__ void k_hint_row_counts(HintArgs a, int32_t n_inst, const int32_t* __r
         int x0, x1, y0, y1;
         window(a.gr, static_cast<int>(bin), x0, x1, y0, y1);
         int n = 0;
+        const int ww = 2 * a.gr.hx + 1, wslots = ww * (2 * a.gr.hy + 1);
+        const int tbx = static_cast<int>(bin % a.gr.nbx), tby = static_cast<int>(bin / a.gr.nbx);
         for (int by = y0; by <= y1; ++by)
             for (int bx = x0; bx <= x1; ++bx) {
                 const int bb = by * a.gr.nbx + bx;
-                n += a.bin_start[bb + 1] - a.bin_start[bb];
+                if (a.kept)     // the cells of bb keeping their edge to this bin
+                    n += a.kept[static_cast<int64_t>(bb) * wslots + (tby - by + a.gr.hy) * ww + (tbx - bx + a.gr.hx)];
+                else
+                    n += a.bin_start[bb + 1] - a.bin_start[bb];
             }
         cnt[a.first_bvirt + bin] = n;
     }
@@ -462,11 +555,22 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
                 const int my = rank[r] - a.bin_start[b];
                 int x0, x1, y0, y1;
                 window(a.gr, b, x0, x1, y0, y1);
+                const unsigned long long kmask = a.keep_mask ? a.keep_mask[r] : 0ull;
                 auto bin_entry = [&](int tx, int ty, double rx, double ex, double ry, double ey) {
                     const int bb = ty * a.gr.nbx + tx;
+                    if (a.keep_mask) {
+                        // pruning decided by the count pass: kept edges only, and the
+                        // bin rows are written by k_bin_side_fill
+                        if (!((kmask >> ((ty - by + a.gr.hy) * ww + (tx - bx + a.gr.hx))) & 1ull)) return;
+                        const float wb = w_bin_of(rx, ex, ry, ey, a.phi[bb], bwi);
+                        ha += fabs(static_cast<double>(wb));
+                        hs += static_cast<double>(wb);
+                        put(make_int2(a.first_bvirt + bb, f_bits(wb)));
+                        return;
+                    }
                     const int slot = (by - ty + a.gr.hy) * ww + (bx - tx + a.gr.hx);
                     const int64_t q = rp[a.first_bvirt + bb] + wpre[static_cast<int64_t>(bb) * ww * wh + slot] + my;
-                    if (a.prune_tau > 0.0 && !((rx > ry ? ex : ey) * fabs(a.phi[bb]) >= a.prune_tau)) {
+                    if (a.prune_tau > 0.0 && !keep_bin_edge(rx, ex, ry, ey, a.phi[bb], a.prune_tau)) {
                         // below the salience threshold: both sides become holes that
                         // the compaction removes
                         put(make_int2(-1, 0));
@@ -517,6 +621,51 @@ __global__ void __launch_bounds__(kBT) k_cell_fill(HintArgs a, const int32_t* __
     for (int64_t k = threadIdx.x; k < nst; k += kBT) ent[e0 + k] = stage[k];
 }
 
+// The bin rows of a pruned graph, one tile of a bin's cells per workgroup:
+// a cell's kept window slot j goes to bin row bb (the slot's bin), at that
+// row's offset for this bin's slot, after the kept cells of the bin's
+// earlier tiles (carry) and of this tile before it (wave ballots, the waves
+// in order), i.e. in ascending execution rows.  The weight is the one the
+// cell's own row holds for bb.
+__global__ void __launch_bounds__(kBT) k_bin_side_fill(HintArgs a, const int32_t* __restrict__ tile_start,
+                                                       const int32_t* __restrict__ carry,
+                                                       const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ wpre, int2* __restrict__ ent) {
+    __shared__ int wtot[kBT / kWave][64];
+    int b, kt;
+    if (!tile_of(tile_start, a.nbins, blockIdx.x, b, kt)) return;
+    const int ww = 2 * a.gr.hx + 1, wslots = ww * (2 * a.gr.hy + 1);
+    const int bx = b % a.gr.nbx, by = b / a.gr.nbx;
+    const int l = lane_id(), wv = wave_id();
+    const unsigned long long lt = l ? (~0ull >> (kWave - l)) : 0ull;
+    const int t = a.bin_start[b] + kt * kBT + static_cast<int>(threadIdx.x);
+    const int r = t < a.bin_start[b + 1] ? a.bin_cells[t] : -1;
+    const unsigned long long m = r >= 0 ? a.keep_mask[r] : 0ull;
+    for (int j = 0; j < wslots; ++j) {
+        const unsigned long long bal = __ballot((m >> j) & 1ull);
+        if (l == 0) wtot[wv][j] = __popcll(bal);
+    }
+    __syncthreads();
+    const int64_t own = r >= 0 ? static_cast<int64_t>(rp[r]) + a.nmac[r] : 0;
+    const int32_t* c0 = carry + static_cast<int64_t>(blockIdx.x) * wslots;
+    for (int j = 0; j < wslots; ++j) {
+        const bool set = (m >> j) & 1ull;
+        const unsigned long long bal = __ballot(set);    // (every lane takes part)
+        if (set) {
+            // the bin's kept cells before this one: earlier tiles, earlier
+            // waves of this tile, earlier lanes of this wave
+            int rank = c0[j] + __popcll(bal & lt);
+            for (int w = 0; w < wv; ++w) rank += wtot[w][j];
+            const int tx = bx + j % ww - a.gr.hx, ty = by + j / ww - a.gr.hy;
+            const int bb = ty * a.gr.nbx + tx;
+            const int k = __popcll(m & ((1ull << j) - 1ull));   // this edge's place among the cell's
+            const int64_t q = static_cast<int64_t>(rp[a.first_bvirt + bb]) +
+                              wpre[static_cast<int64_t>(bb) * wslots + (wslots - 1 - j)] + rank;
+            ent[q] = make_int2(r, ent[own + k].y);
+        }
+    }
+}
+
 __global__ void k_bin_rank(int32_t n, const int32_t* __restrict__ bin_cells, int32_t* __restrict__ rank) {
     int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t < n) rank[bin_cells[t]] = static_cast<int32_t>(t);
@@ -535,7 +684,8 @@ __global__ void k_window_prefix(HintArgs a, int32_t* __restrict__ wpre) {
         int tx = bx + w % ww - a.gr.hx, ty = by + w / ww - a.gr.hy;
         if (tx < 0 || tx >= a.gr.nbx || ty < 0 || ty >= a.gr.nby) continue;
         int bb = ty * a.gr.nbx + tx;
-        acc += a.bin_start[bb + 1] - a.bin_start[bb];
+        acc += a.kept ? a.kept[static_cast<int64_t>(bb) * ww * wh + (ww * wh - 1 - w)]
+                      : a.bin_start[bb + 1] - a.bin_start[bb];
     }
 }
 
@@ -793,6 +943,14 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     a.habs = g.xhabs.p;
     a.hsg = g.xhsg.p;
     a.prune_tau = bin_hints ? static_cast<double>(hp.prune_tau) : 0.0;
+    const int wslots = (2 * gr.hx + 1) * (2 * gr.hy + 1);
+    // Pruning is decided in the count pass when a window has at most 64
+    // slots (one bit each); wider windows mark holes in the fill and compact.
+    const bool direct_prune = a.prune_tau > 0.0 && wslots <= 64;
+    if (direct_prune) g.keep_mask.ensure(static_cast<size_t>(n_inst) + 1, s);
+    a.keep_mask = direct_prune ? g.keep_mask.p : nullptr;
+    a.kept = nullptr;
+    a.nmac = nullptr;
 
     // 5. per cell: macros holding it, window size; (cell, macro) pairs
     g.nmac.ensure(static_cast<size_t>(n_inst) + 1, s);
@@ -801,6 +959,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
                        static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
                        static_cast<int32_t*>(nullptr));
     AHR_LAUNCHED("k_cell_count");
+    a.nmac = g.nmac.p;
     g.pair_off.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.scan_tmp.ensure(scan_tmp_elems(std::max<int64_t>(N, n_inst)), s);
     scan_i32_to_i32(g.nmac.p, g.pair_off.p, n_inst, g.scan_tmp.p, s);
@@ -811,6 +970,29 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     const int32_t n_pairs = tot[0];
     g.n_hint_cells = tot[1];
     g.nnz_net = tot[2];
+    // pruned bin rows: tiles of kBT cells within each bin, the kept cells per
+    // (tile, slot) turned into carries, and per (bin, slot) totals
+    DevBuf<int32_t> tile_start, tile_carry;
+    const int32_t max_tiles = direct_prune ? g.n_hint_cells / kBT + nbins : 0;
+    if (direct_prune) {
+        DevBuf<int32_t> ntiles;
+        ntiles.ensure(static_cast<size_t>(nbins) + 1, s);
+        tile_start.ensure(static_cast<size_t>(nbins) + 1, s);
+        tile_carry.ensure(static_cast<size_t>(max_tiles) * wslots + 1, s);
+        g.kept.ensure(static_cast<size_t>(nbins) * wslots + 1, s);
+        hipLaunchKernelGGL(k_bin_tile_counts, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s, g.bin_start.p, nbins,
+                           ntiles.p);
+        AHR_LAUNCHED("k_bin_tile_counts");
+        scan_i32_to_i32(ntiles.p, tile_start.p, nbins, g.scan_tmp.p, s);
+        ntiles.release(s);
+        hipLaunchKernelGGL(k_tile_keep_counts, dim3(max_tiles), dim3(kBT), 0, s, a, tile_start.p, wslots,
+                           tile_carry.p);
+        AHR_LAUNCHED("k_tile_keep_counts");
+        hipLaunchKernelGGL(k_tile_carry, dim3(grid_for(static_cast<int64_t>(nbins) * wslots, kBT)), dim3(kBT), 0, s,
+                           tile_start.p, nbins, wslots, tile_carry.p, g.kept.p);
+        AHR_LAUNCHED("k_tile_carry");
+        a.kept = g.kept.p;
+    }
     g.pair_row.ensure(static_cast<size_t>(n_pairs) + 1, s);
     g.pair_mac.ensure(static_cast<size_t>(n_pairs) + 1, s);
     if (n_pairs) {
@@ -836,7 +1018,6 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     // twice the hint cells times the window slots: the entry array is sized
     // by that bound without waiting for the count, which the normalisation
     // reads with its own sizes.  Near the int32 limit the exact count is read.
-    const int wslots = (2 * gr.hx + 1) * (2 * gr.hy + 1);
     const int64_t bound =
         2 * (static_cast<int64_t>(n_pairs) + (bin_hints ? static_cast<int64_t>(g.n_hint_cells) * wslots : 0));
     int64_t cap = bound;
@@ -856,7 +1037,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     if (bin_hints) {
         g.bin_rank.ensure(static_cast<size_t>(n_inst) + 1, s);
         g.wpre.ensure(static_cast<size_t>(nbins) * wslots + 1, s);
-        if (g.n_hint_cells)
+        if (g.n_hint_cells && !direct_prune)
             hipLaunchKernelGGL(k_bin_rank, dim3(grid_for(g.n_hint_cells, kBT)), dim3(kBT), 0, s, g.n_hint_cells,
                                g.bin_cells.p, g.bin_rank.p);
         AHR_LAUNCHED("k_bin_rank");
@@ -868,6 +1049,15 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
                        static_cast<const int32_t*>(g.pair_mac.p), static_cast<const int32_t*>(g.bin_rank.p),
                        static_cast<const int32_t*>(g.wpre.p), g.xhint_ent.p);
     AHR_LAUNCHED("k_cell_fill");
+    if (direct_prune) {
+        hipLaunchKernelGGL(k_bin_side_fill, dim3(max_tiles), dim3(kBT), 0, s, a,
+                           static_cast<const int32_t*>(tile_start.p), static_cast<const int32_t*>(tile_carry.p),
+                           static_cast<const int32_t*>(g.xhint_rp.p), static_cast<const int32_t*>(g.wpre.p),
+                           g.xhint_ent.p);
+        AHR_LAUNCHED("k_bin_side_fill");
+        tile_start.release(s);
+        tile_carry.release(s);
+    }
     g.habs_version = g.hint_version;
     if (use_macros && n_pairs) {
         hipLaunchKernelGGL(k_macro_fill, dim3(grid_for(n_pairs, kBT)), dim3(kBT), 0, s, n_pairs, g.first_mvirt,
@@ -875,7 +1065,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
                            g.xhint_ent.p);
         AHR_LAUNCHED("k_macro_fill");
     }
-    if (a.prune_tau > 0.0 && cap > 0) prune_hints(g, cap, s);
+    if (a.prune_tau > 0.0 && !direct_prune && cap > 0) prune_hints(g, cap, s);
 }
 
 }  // namespace ahr

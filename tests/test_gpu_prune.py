@@ -2,7 +2,9 @@
 hint edges, prune_tau > 0) through the C ABI against the FP64 oracle: the
 hint structure exact and its weights within float32 rounding, the filter
 and Algorithm 1 within the FP32 bound (centred and per element), at small
-sizes and at the full mid-210k and large-2.2M workloads."""
+sizes and at the full mid-210k and large-2.2M workloads, for windows of up
+to 64 slots (pruning decided in the count pass) and wider ones (pruned
+entries compacted after the fill)."""
 import numpy as np
 import pytest
 import torch
@@ -22,6 +24,10 @@ CASES = [
     ("small-movable", N.small(5000, 3, movable_macros=True, ncols=2), dict(nbx=10, nby=10, detection_ratio=0.3)),
     ("small-4col", N.small(7000, 4, ncols=4, big_frac=0.01), dict(nbx=16, nby=12, detection_ratio=0.2)),
     ("long-rows", BIG_NETS, dict(nbx=4, nby=4, detection_ratio=0.75)),
+    # a 7 x 9 window (63 slots, the pruning decided in the count pass with the
+    # mask's high bits in use) and a 9 x 9 one (81 slots: holes and compaction)
+    ("window-63", N.small(5000, 3, ncols=2), dict(nbx=12, nby=16, detection_ratio=0.5)),
+    ("window-81", N.small(5000, 3, ncols=2), dict(nbx=16, nby=16, detection_ratio=0.6)),
 ]
 
 
