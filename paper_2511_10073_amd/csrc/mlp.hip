@@ -6,11 +6,16 @@
 //   y = beta_1 h1 + beta_2 h2 + beta_3 h3 + s_c o   (fixed rows keep their input).
 //
 // Inference runs the three layers on the matrix cores: 16 samples per
-// wavefront, bfloat16 operands, float32 accumulation
-// (v_mfma_f32_16x16x16_bf16).  Every layer is computed transposed
-// (hidden x samples), so the accumulator layout of one layer -- lane l holds
-// rows 4(l/16)..4(l/16)+3 of column l%16 -- is exactly the B-operand layout of
-// the next, and no data moves between lanes.  Training runs forward and
+// wavefront, bfloat16 operands, float32 accumulation.  Every layer is
+// computed transposed (hidden x samples): the accumulator of one 16-row
+// output tile leaves lane l with rows 4(l/16)..4(l/16)+3 of sample l%16.
+// Layer 1 (5 features padded to K = 16) uses v_mfma_f32_16x16x16_bf16, whose
+// B operand has exactly that layout.  Layers 2 and 3 contract over the 64
+// hidden units with gfx950's v_mfma_f32_16x16x32_bf16, whose B operand gives
+// lane l eight K slots 8(l/16)..8(l/16)+7: the lane's rows of two output
+// tiles fill them (slots 8g..8g+3 hold hidden units 32p+4g..+3, slots
+// 8g+4..8g+7 hold 32p+16+4g..+3), and the weights are loaded into the A
+// operand with the same permutation of K, so no data moves between lanes.  Training runs forward and
 // backward in float32 with the same bfloat16 rounding points (weights,
 // features and hidden activations), gradients straight through the
 // rounding, accumulated per workgroup in a fixed order and reduced in a
@@ -31,8 +36,21 @@ constexpr int kNP = AHR_MLP_NPARAM;     // 4801
 constexpr int oW1 = 0, oB1 = kH * kFP, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH, oB3 = oW3 + kH;
 static_assert(oB3 + 1 == kNP, "parameter layout");
 
+typedef short v2s __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Hidden unit of K slot q (0..31) of chunk p in the layers contracting over
+// the hidden units (see above).
+__device__ __forceinline__ int hid(int p, int q) { return 32 * p + ((q & 4) ? 16 : 0) + 4 * (q >> 3) + (q & 3); }
+
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0,
+                                                  0);
+}
 
 // float32 -> bfloat16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
 __device__ __forceinline__ short bf16_bits(float x) { return __builtin_bit_cast(short, static_cast<__bf16>(x)); }
@@ -40,10 +58,25 @@ __device__ __forceinline__ float bf16_round(float x) { return static_cast<float>
 
 // ---------------------------------------------------------------- inference
 
+// relu then bfloat16 of two values, as relu of the bfloat16 values (rounding
+// keeps the sign): one packed conversion, then one packed signed 16-bit max
+// with 0, since a negative bfloat16 has its sign bit set.
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ v2s relu_bf16x2(float a, float b) {
+    const v2bf t = __builtin_convertvector((v2f{a, b}), v2bf);
+    return __builtin_elementwise_max(__builtin_bit_cast(v2s, t), v2s{0, 0});
+}
+
+__device__ __forceinline__ v4s relu_bf16x4(v4f acc) {
+    const v2s lo = relu_bf16x2(acc[0], acc[1]), hi = relu_bf16x2(acc[2], acc[3]);
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3);
+}
+
 struct MlpRegs {
     v4s w1[4];        // A tiles of W1 (hidden 16m.., features 0..15)
-    v4s w2[16];       // A tiles of W2 (out 16n.., in 16m..), index 4n + m
-    v4s w3[4];        // A tiles with w3 in row 0
+    v8s w2[8];        // A tiles of W2 (out 16n.., in chunk p of 32, K permuted), index 2n + p
+    v8s w3[2];        // A tiles with w3 in row 0 (chunk p, K permuted)
     float b1[16], b2[16];
     float b3;
 };
@@ -56,45 +89,61 @@ __device__ __forceinline__ void load_mlp(const float* __restrict__ P, MlpRegs& R
         for (int j = 0; j < 4; ++j) {
             int k = 4 * g + j;
             R.w1[m][j] = k < kFP ? bf16_bits(P[oW1 + (16 * m + i) * kFP + k]) : static_cast<short>(0);
-            R.w3[m][j] = i == 0 ? bf16_bits(P[oW3 + 16 * m + k]) : static_cast<short>(0);
             R.b1[4 * m + j] = P[oB1 + 16 * m + k];
             R.b2[4 * m + j] = P[oB2 + 16 * m + k];
         }
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int j = 0; j < 8; ++j) {
+            const int h = hid(p, 8 * g + j);
+            R.w3[p][j] = i == 0 ? bf16_bits(P[oW3 + h]) : static_cast<short>(0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) R.w2[4 * n + m][j] = bf16_bits(P[oW2 + (16 * n + i) * kH + 16 * m + 4 * g + j]);
+            for (int n = 0; n < 4; ++n) R.w2[2 * n + p][j] = bf16_bits(P[oW2 + (16 * n + i) * kH + h]);
+        }
     R.b3 = P[oB3];
 }
 
 // One tile of 16 samples.  f holds features 4(l/16)..4(l/16)+3 of sample
 // l%16; the result is valid in lanes 0..15 (sample = lane).
 __device__ __forceinline__ float mlp_tile(const MlpRegs& R, const float f[4]) {
-    v4s x;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) x[j] = bf16_bits(f[j]);
+    const v2bf x01 = __builtin_convertvector((v2f{f[0], f[1]}), v2bf);
+    const v2bf x23 = __builtin_convertvector((v2f{f[2], f[3]}), v2bf);
+    const v4s x = __builtin_shufflevector(__builtin_bit_cast(v2s, x01), __builtin_bit_cast(v2s, x23), 0, 1, 2, 3);
     v4s a1[4], a2[4];
     // each layer's accumulator starts at its bias (float32)
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         v4f acc = {R.b1[4 * m], R.b1[4 * m + 1], R.b1[4 * m + 2], R.b1[4 * m + 3]};
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[m], x, acc, 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a1[m][j] = bf16_bits(acc[j] > 0.f ? acc[j] : 0.f);
+        a1[m] = relu_bf16x4(acc);
     }
+    // the lane's rows of output tiles 2p and 2p+1: the B operand of chunk p
+    v8s b1[2], b2[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            b1[p][j] = a1[2 * p][j];
+            b1[p][4 + j] = a1[2 * p + 1][j];
+        }
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         v4f acc = {R.b2[4 * n], R.b2[4 * n + 1], R.b2[4 * n + 2], R.b2[4 * n + 3]};
 #pragma unroll
-        for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w2[4 * n + m], a1[m], acc, 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a2[n][j] = bf16_bits(acc[j] > 0.f ? acc[j] : 0.f);
+        for (int p = 0; p < 2; ++p) acc = mfma32(R.w2[2 * n + p], b1[p], acc);
+        a2[n] = relu_bf16x4(acc);
     }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            b2[p][j] = a2[2 * p][j];
+            b2[p][4 + j] = a2[2 * p + 1][j];
+        }
     v4f acc = {R.b3, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w3[m], a2[m], acc, 0, 0, 0);
+    for (int p = 0; p < 2; ++p) acc = mfma32(R.w3[p], b2[p], acc);
     return acc[0];
 }
 
@@ -133,7 +182,7 @@ struct LearnArgs {
     const double* deg;
     const float* hsum;
     const float* stats;     // [2][C]: mean, std of h3
-    const float4* rowf;     // [n_inst] per execution row: 1/s, log1p(d), hsum/d
+    const float4* rowf;     // [n_inst] per execution row: 1/s, log1p(d), hsum/d, row code (bits)
     const float* in;
     float* out;
     float* feats;           // optional [n_inst * C][8], instance order
@@ -147,15 +196,23 @@ struct LearnArgs {
 };
 
 // Per-row inputs of the features, once per row instead of once per column:
-// 1/s, log1p(d), hsum/d (the last two in float64, then rounded).
+// 1/s, log1p(d), hsum/d (the last two in float64, then rounded), and the
+// row's instance with its fixed flag in the sign bit (the bits of w), so the
+// network's epilogue needs no dependent load to find where its result goes.
+__device__ __forceinline__ int row_inst(int code) { return code & 0x7fffffff; }
+__device__ __forceinline__ bool row_fixed(int code) { return code < 0; }
+
 __global__ void k_row_feat(int32_t n, const float* __restrict__ scale, const double* __restrict__ deg,
-                           const float* __restrict__ hsum, float4* __restrict__ rowf) {
+                           const float* __restrict__ hsum, const int32_t* __restrict__ perm,
+                           const uint8_t* __restrict__ flags, float4* __restrict__ rowf) {
     int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const float s = scale[r];
     const double d = deg[r];
+    const int inst = perm[r];
+    const int code = inst | ((flags[inst] & AHR_NODE_FIXED) ? static_cast<int>(0x80000000u) : 0);
     rowf[r] = make_float4(s > 0.f ? 1.f / s : 0.f, static_cast<float>(log1p(d)),
-                          d > 0 ? static_cast<float>(static_cast<double>(hsum[r]) / d) : 0.f, 0.f);
+                          d > 0 ? static_cast<float>(static_cast<double>(hsum[r]) / d) : 0.f, __int_as_float(code));
 }
 
 // Inputs of one tile's sample for lane group 0 (the hops, for features
@@ -166,29 +223,47 @@ struct TileIn {
     float4 rf;
 };
 
+// The loads only: the scaled hops z_j (h = z_j / s once the row's 1/s is
+// known) and the row inputs, none depending on another, so a tile's loads
+// are all in flight while the previous tile runs through the network.
 template <int C>
 __device__ __forceinline__ TileIn tile_load(const LearnArgs& a, int64_t smp, int g) {
     TileIn t;
     const int64_t r = smp / C;
-    const int c = static_cast<int>(smp % C);
     t.h[0] = t.h[1] = t.h[2] = 0.f;
     t.rf = make_float4(0.f, 0.f, 0.f, 0.f);
     if (r < a.n_inst && g < 2) {
         t.rf = a.rowf[r];
         if (g == 0) {
-            const int rr = static_cast<int>(r);
-            t.h[0] = unscale(a.z1, C, rr, c, t.rf.x, a.in, a.perm);
-            t.h[1] = unscale(a.z2, C, rr, c, t.rf.x, a.in, a.perm);
-            t.h[2] = unscale(a.z3, C, rr, c, t.rf.x, a.in, a.perm);
+            t.h[0] = a.z1[smp];
+            t.h[1] = a.z2[smp];
+            t.h[2] = a.z3[smp];
         }
     }
     return t;
 }
 
+// The hops' values from the loaded z: h = z / s, or the input for a row
+// with s = 0 (isolated: every power of the operator keeps its value), which
+// is rare, so its dependent load sits in a branch of its own.
+template <int C>
+__device__ __forceinline__ void tile_unscale(const LearnArgs& a, TileIn& t, int64_t smp, int g) {
+    if (g != 0) return;
+    const float inv_s = t.rf.x;
+    if (inv_s > 0.f) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) t.h[j] *= inv_s;
+    } else if (smp / C < a.n_inst) {
+        const float v = a.in[static_cast<int64_t>(row_inst(__float_as_int(t.rf.w))) * C + smp % C];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) t.h[j] = v;
+    }
+}
+
 // The learned filter over the instance rows: 16 samples (16/C rows x C
 // columns) per wavefront tile.  A lane's column is the same in every tile
 // (16 % C == 0), so its column statistics are loaded once; the next tile's
-// inputs are loaded while the current one runs through the network.
+// inputs are in flight while the current one runs through the network.
 template <int C>
 __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
     MlpRegs R;
@@ -202,6 +277,7 @@ __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
     TileIn cur = tile_load<C>(a, t * 16 + sl, g);
     for (; t < ntiles; t += waves) {
         const TileIn nxt = tile_load<C>(a, (t + waves) * 16 + sl, g);
+        tile_unscale<C>(a, cur, t * 16 + sl, g);
         float f[4];
         if (g == 0) {
             f[0] = (cur.h[0] - cur.h[2]) * inv_sc;
@@ -215,7 +291,7 @@ __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
         const float o = mlp_tile(R, f);
         const int64_t r = (t * 16 + sl) / C;
         if (l < 16 && r < a.n_inst) {
-            const int inst = a.perm[r];
+            const int code = __float_as_int(cur.rf.w), inst = row_inst(code);
             const int64_t oc = static_cast<int64_t>(inst) * C + c;
             if (a.feats) {
                 float* fp = a.feats + oc * kFP;
@@ -230,7 +306,7 @@ __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
             }
             if (a.write_out) {
                 float y = a.beta0 * cur.h[0] + a.beta1 * cur.h[1] + a.beta2 * cur.h[2] + sc * o;
-                a.out[oc] = (a.flags[inst] & AHR_NODE_FIXED) ? a.in[oc] : y;
+                a.out[oc] = row_fixed(code) ? a.in[oc] : y;
             }
         }
         cur = nxt;
@@ -258,9 +334,9 @@ __global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, const float* __res
     for (int c = 0; c <= C; ++c) acc[c] = 0;
     for (int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x; r < a.n_inst;
          r += static_cast<int64_t>(kStatGrid) * kBT) {
-        int inst = a.perm[r];
-        if (a.flags[inst] & AHR_NODE_FIXED) continue;
-        const float inv_s = a.rowf[r].x;
+        const float4 rf = a.rowf[r];
+        if (row_fixed(__float_as_int(rf.w))) continue;
+        const float inv_s = rf.x;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             double h = unscale(a.z3, C, static_cast<int>(r), c, inv_s, a.in, a.perm);
@@ -475,7 +551,7 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     a.stats = stats.p;
     a.rowf = rowf.p;
     hipLaunchKernelGGL(k_row_feat, dim3(grid_for(g.n_inst, kBT)), dim3(kBT), 0, s, g.n_inst, g.scale.p, g.deg.p,
-                       g.hsum.p, rowf.p);
+                       g.hsum.p, g.perm.p, g.nl.node_flags, rowf.p);
     AHR_LAUNCHED("k_row_feat");
     hipLaunchKernelGGL((k_colstat<C>), dim3(kStatGrid), dim3(kBT), 0, s, a, static_cast<const float*>(nullptr), part.p);
     AHR_LAUNCHED("k_colstat");
@@ -488,8 +564,16 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     if (stats_out) AHR_HIP(hipMemcpyAsync(stats_out, stats.p, 2 * C * sizeof(float), hipMemcpyDeviceToDevice, s));
     {
         ProfScope ps(kStageMlp, s);
+        // one resident set of workgroups, each wave walking its tiles with
+        // the prefetch running: workgroups per CU at this kernel's occupancy
+        // times the CUs
         const int64_t ntiles = (static_cast<int64_t>(g.n_inst) * C + 15) / 16;
-        const int64_t blocks = std::min<int64_t>((ntiles + 3) / 4, 256 * 16);
+        int dev = 0, cus = 0, per_cu = 0;
+        AHR_HIP(hipGetDevice(&dev));
+        AHR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        AHR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_learned<C>, kBT, 0));
+        const int64_t resident = static_cast<int64_t>(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+        const int64_t blocks = std::min<int64_t>((ntiles + 3) / 4, resident);
         hipLaunchKernelGGL((k_mlp_learned<C>), dim3(static_cast<unsigned>(blocks < 1 ? 1 : blocks)), dim3(kBT), 0, s,
                            a);
         AHR_LAUNCHED("k_mlp_learned");
