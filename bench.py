@@ -252,7 +252,7 @@ def learned_vs_plain(A, torch, np, nl, net, params, spec, g0, reps):
         return {"ms": round(ms, 4), "hop_launches": prof["hop_launches"], "hop_bytes": int(prof["hop_bytes"]),
                 "hop_gbs": round(prof["hop_bytes"] / (ms * 1e-3) / 1e9, 1), "mlp_ms": round(prof["mlp_ms"], 4)}
 
-    # the linear-only baseline: the same three hops and beta, network output zero
+    # the linear-only baseline: the same input, three hops and beta, network output zero
     linear = A.Mlp(torch.zeros_like(model.params), model.beta, True)
     ylin = torch.empty_like(g0)
 
@@ -276,12 +276,12 @@ def learned_vs_plain(A, torch, np, nl, net, params, spec, g0, reps):
     return {"plain": tp, "learned": tl, "speedup": round(tp["ms"] / tl["ms"], 3), "rel_err": rel,
             "hpwl_plain": [float(v) for v in h_p], "hpwl_learned": [float(v) for v in h_l],
             "hpwl_delta": hd, "used_fallback": bool(fb[-1]),
-            "linear_only": {"what": "the same 3 hops combined by beta alone (network output zero)",
+            "linear_only": {"what": "the input and the same 3 hops combined by beta alone (network output zero)",
                             "ms": tlin["ms"], "rel_err": rel_lin,
                             "hpwl_delta": float(np.max(np.abs(h_lin - h_p) / h_p))},
             "network_gain": {"rel_err_linear_minus_learned": rel_lin - rel},
             "model": {"file": os.path.relpath(MODEL, ROOT), "validated": model.validated,
-                      "heldout_rel_err_mean": model.summary.get("rel_err_mean")},
+                      "heldout": {k: model.summary.get(k) for k in ("mid", "large") if k in model.summary}},
             "bounds": bounds,
             "pass": bool(rel <= bounds["rel_err"] and hd <= bounds["hpwl_delta"] and tl["ms"] < tp["ms"])}
 

@@ -367,26 +367,30 @@ size_t ahr_hpwl_noalloc_bytes(void);
 /* ------------------------------------------------------------------------
  * Learned surrogate of the filter (a project addition; the paper has no
  * learned component).  It approximates the polynomial filter of `spec` from
- * three powers of the same operator: for every instance row i and column c,
- *   h_j = (T^j X)[i,c] (j = 1, 2, 3, unpinned), m_c / s_c = mean / standard
- *   deviation of h_3 over movable rows,
- *   f = [(h1-h3)/s_c, (h2-h3)/s_c, (h3-m_c)/s_c, log1p(d_i), hsum_i/d_i]
+ * the input and three powers of the same operator: for every instance row i
+ * and column c,
+ *   h_j = (T^j X)[i,c] (j = 0..3, unpinned; h_0 = X), m_c / s_c = mean /
+ *   standard deviation of h_3 over movable rows, r_c = root mean square of
+ *   h_0 - h_3 over movable rows (a zero s_c or r_c becomes 1),
+ *   f = [(h0-h3)/r_c, (h1-h3)/r_c, (h2-h3)/r_c, (h3-m_c)/s_c, log1p(d_i),
+ *        hsum_i/d_i, log(s_c/r_c)]
  *   (d_i the absolute degree, hsum_i the signed sum of the row's hint weights),
  *   o = w3 . relu(W2 relu(W1 f + b1) + b2) + b3,
- *   y = beta[0] h1 + beta[1] h2 + beta[2] h3 + s_c o; fixed rows keep their input.
+ *   y = beta[0] h0 + beta[1] h1 + beta[2] h2 + beta[3] h3 + r_c o; fixed rows
+ *   keep their input.
  * The network is evaluated with bfloat16 operands (features, weights, hidden
  * activations; round to nearest even) and float32 accumulation on the matrix
  * cores.  Parameters are one float32 device vector of AHR_MLP_NPARAM values:
- * W1[64][8] (features 5..7 unused), b1[64], W2[64][64], b2[64], w3[64], b3.
+ * W1[64][8] (feature 7 unused), b1[64], W2[64][64], b2[64], w3[64], b3.
  * ------------------------------------------------------------------------ */
 #define AHR_MLP_HIDDEN 64
-#define AHR_MLP_FEATURES 5
+#define AHR_MLP_FEATURES 7
 #define AHR_MLP_FEATURE_STRIDE 8
 #define AHR_MLP_NPARAM 4801
 
 typedef struct ahr_mlp {
     const float* params;        /* device [AHR_MLP_NPARAM] */
-    float beta[3];              /* weights of h1, h2, h3 */
+    float beta[4];              /* weights of h0 (the input), h1, h2, h3 */
     int32_t validated;          /* 0: the model missed its validation bound; the plain filter runs */
 } ahr_mlp;
 
@@ -410,8 +414,8 @@ ahr_status ahr_refine_learned(ahr_graph* gr, const ahr_filter_spec* spec, const 
 
 /* Training data of the surrogate: for the signal `in` ([n_inst][ncols]),
  * writes feats [n_inst*ncols][AHR_MLP_FEATURE_STRIDE] (instance order, row
- * i*ncols + c), hops [3][n_inst][ncols] (h1, h2, h3) and stats [2][ncols]
- * (m_c, s_c).  Any output may be NULL. */
+ * i*ncols + c), hops [4][n_inst][ncols] (h0, h1, h2, h3) and stats [3][ncols]
+ * (m_c, s_c, r_c).  Any output may be NULL. */
 ahr_status ahr_filter_features(ahr_graph* gr, const ahr_filter_spec* spec, const float* in, int32_t ncols,
                                float* feats, float* hops, float* stats, void* stream);
 

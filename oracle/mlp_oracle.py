@@ -5,21 +5,29 @@ imports it.
 
 The surrogate is a project addition, not part of the paper: it approximates
 the order-K signed filter of Section V (eq. "refine-filter", banked as in
-Section IV eq. "GiFt filter") from three low-order powers of the same
-operator T.  For every movable instance row i and column c:
+Section IV eq. "GiFt filter") from the input and three low-order powers of
+the same operator T.  For every movable instance row i and column c:
 
-    h_j   = (T^j X)[i, c],  j = 1, 2, 3          (the unpinned chain)
+    h_j   = (T^j X)[i, c],  j = 0, 1, 2, 3       (the unpinned chain; h_0 = X)
     m_c, s_c = mean and standard deviation of h_3[:, c] over movable rows
-    f     = [(h_1 - h_3)/s_c, (h_2 - h_3)/s_c, (h_3 - m_c)/s_c,
-             log1p(d_i), hsum_i / d_i]           (hsum_i = sum of row i's hint weights)
+    r_c   = root mean square of (h_0 - h_3)[:, c] over movable rows
+    f     = [(h_0 - h_3)/r_c, (h_1 - h_3)/r_c, (h_2 - h_3)/r_c, (h_3 - m_c)/s_c,
+             log1p(d_i), hsum_i / d_i, log(s_c / r_c)]
+                                                 (hsum_i = sum of row i's hint weights)
     o     = w3 . relu(W2 relu(W1 f + b1) + b2) + b3
-    y_hat = beta_1 h_1 + beta_2 h_2 + beta_3 h_3 + s_c o
+    y_hat = beta_0 h_0 + beta_1 h_1 + beta_2 h_2 + beta_3 h_3 + r_c o
+
+r_c is the displacement of three hops, a length set by the graph's local
+neighbourhoods; s_c grows with the die.  Scaling the differences of hops and
+the network's output by r_c keeps them the same size on netlists of any
+size, and log(s_c / r_c), one value per column, tells the network how the
+two lengths compare.  A column with s_c = 0 or r_c = 0 takes 1 in its place.
 
 The GPU evaluates the network with bfloat16 operands (features, weights and
 hidden activations rounded to nearest-even bfloat16) and float32
 accumulation; this oracle rounds at the same points and accumulates in
 float64.  Training minimises the mean of (o - r)^2 with
-r = (y_ref - sum_j beta_j h_j) / s_c; gradients pass straight through the
+r = (y_ref - sum_j beta_j h_j) / r_c; gradients pass straight through the
 rounding.
 """
 from __future__ import annotations
@@ -29,7 +37,8 @@ import numpy as np
 from . import ahr_oracle as O
 
 HIDDEN = 64
-NFEAT = 5
+NFEAT = 7
+NHOPS = 4        # h_0 .. h_3
 FEAT_PAD = 8
 
 
@@ -79,10 +88,10 @@ def bf16(x):
 
 
 def hops(nl, g: O.Graph, G, sigma=0.0, lambda_mode="gershgorin", lambda_fixed=2.0, k=3):
-    """h_j = T^j X for j = 1..k on the extended signal (no pinning)."""
+    """h_j = T^j X for j = 0..k on the extended signal (no pinning; h_0 = X)."""
     _, T, d, _, _ = O.operator(g, sigma, lambda_mode, lambda_fixed)
-    X = O.expand_signal(nl, g, G)
-    out, Y = [], X
+    Y = O.expand_signal(nl, g, G)
+    out = [Y]
     for _ in range(k):
         Y = T @ Y
         out.append(Y)
@@ -96,27 +105,36 @@ def hint_sum(g: O.Graph):
     return np.bincount(rows, weights=g.hint_val, minlength=n)
 
 
+def column_stats(h0, h3, mov):
+    """m_c and s_c (mean and standard deviation of h_3) and r_c (root mean
+    square of h_0 - h_3), over the movable rows; a zero s_c or r_c becomes 1."""
+    m = h3[mov].mean(axis=0)
+    s = h3[mov].std(axis=0)
+    r = np.sqrt(np.mean((h0[mov] - h3[mov]) ** 2, axis=0))
+    return m, np.where(s > 0, s, 1.0), np.where(r > 0, r, 1.0)
+
+
 def features(nl, g: O.Graph, G, sigma=0.0, lambda_mode="gershgorin", lambda_fixed=2.0):
     """Features of every (instance row, column) and the column statistics.
 
-    Returns (F [n_inst, C, 5], (h1, h2, h3) [n_inst, C], m [C], s [C])."""
-    (h1, h2, h3), d = hops(nl, g, G, sigma, lambda_mode, lambda_fixed)
+    Returns (F [n_inst, C, 7], (h0, h1, h2, h3) [n_inst, C], (m, s, r) [C])."""
+    hs, d = hops(nl, g, G, sigma, lambda_mode, lambda_fixed)
     n = g.n_inst
-    h1, h2, h3 = h1[:n], h2[:n], h3[:n]
+    h0, h1, h2, h3 = (h[:n] for h in hs)
     mov = (nl["node_flags"] & O.FLAG_FIXED) == 0
-    m = h3[mov].mean(axis=0)
-    s = h3[mov].std(axis=0)
-    s = np.where(s > 0, s, 1.0)
+    m, s, r = column_stats(h0, h3, mov)
     dd = d[:n]
-    hs = hint_sum(g)[:n]
+    hs_ = hint_sum(g)[:n]
     C = h1.shape[1]
     F = np.zeros((n, C, NFEAT))
-    F[:, :, 0] = (h1 - h3) / s
-    F[:, :, 1] = (h2 - h3) / s
-    F[:, :, 2] = (h3 - m) / s
-    F[:, :, 3] = np.log1p(dd)[:, None]
-    F[:, :, 4] = np.where(dd > 0, hs / np.where(dd > 0, dd, 1.0), 0.0)[:, None]
-    return F, (h1, h2, h3), m, s
+    F[:, :, 0] = (h0 - h3) / r
+    F[:, :, 1] = (h1 - h3) / r
+    F[:, :, 2] = (h2 - h3) / r
+    F[:, :, 3] = (h3 - m) / s
+    F[:, :, 4] = np.log1p(dd)[:, None]
+    F[:, :, 5] = np.where(dd > 0, hs_ / np.where(dd > 0, dd, 1.0), 0.0)[:, None]
+    F[:, :, 6] = np.log(s / r)[None, :]
+    return F, (h0, h1, h2, h3), (m, s, r)
 
 
 def forward(params, F, rounding=True):
@@ -160,19 +178,19 @@ def loss_grad(params, F, r, rounding=True):
     return loss, pack(gW1, gb1, gW2, gb2, gw3, gb3)
 
 
-def predict(params, beta, F, h, s):
-    """y_hat [n_inst, C] from features F [n_inst, C, 5] and hops h."""
+def predict(params, beta, F, h, r):
+    """y_hat [n_inst, C] from features F [n_inst, C, 7], hops h = (h0..h3)
+    and the local scale r [C]."""
     n, C, _ = F.shape
     o, _ = forward(params, F.reshape(n * C, NFEAT))
     o = o.reshape(n, C)
-    h1, h2, h3 = h
-    return beta[0] * h1 + beta[1] * h2 + beta[2] * h3 + s[None, :] * o
+    return sum(beta[j] * h[j] for j in range(NHOPS)) + r[None, :] * o
 
 
 def learned_filter(nl, g, params, beta, G, sigma=0.0, lambda_mode="gershgorin", lambda_fixed=2.0):
     """The surrogate's output on the instance rows (fixed rows keep their input)."""
-    F, h, m, s = features(nl, g, G, sigma, lambda_mode, lambda_fixed)
-    y = predict(params, beta, F, h, s)
+    F, h, (m, s, r) = features(nl, g, G, sigma, lambda_mode, lambda_fixed)
+    y = predict(params, beta, F, h, r)
     fixed = (nl["node_flags"] & O.FLAG_FIXED) != 0
     y[fixed] = np.asarray(G, np.float64)[fixed]
     return y

@@ -115,7 +115,7 @@ class _Profile(ctypes.Structure):
 
 
 class _Mlp(ctypes.Structure):
-    _fields_ = [("params", ctypes.c_void_p), ("beta", ctypes.c_float * 3), ("validated", ctypes.c_int32)]
+    _fields_ = [("params", ctypes.c_void_p), ("beta", ctypes.c_float * 4), ("validated", ctypes.c_int32)]
 
 
 MLP_NPARAM = 4801
@@ -261,15 +261,18 @@ def mlp_adam(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
 
 class Mlp:
     """A learned-filter model: float32 parameters on the device, the linear
-    weights beta of the three hops, and whether it met its validation bound."""
+    weights beta of the input and the three hops (h0..h3), and whether it met
+    its validation bound."""
 
-    def __init__(self, params, beta=(0.0, 0.0, 1.0), validated=True):
+    def __init__(self, params, beta=(0.0, 0.0, 0.0, 1.0), validated=True):
         self.params = params
         self.beta = tuple(float(b) for b in beta)
+        if len(self.beta) != 4:
+            raise ValueError("beta holds the weights of h0, h1, h2, h3")
         self.validated = bool(validated)
 
     def c(self):
-        return _Mlp(self.params.data_ptr(), (ctypes.c_float * 3)(*self.beta), 1 if self.validated else 0)
+        return _Mlp(self.params.data_ptr(), (ctypes.c_float * 4)(*self.beta), 1 if self.validated else 0)
 
     @classmethod
     def load(cls, path, device="cuda"):
@@ -277,7 +280,7 @@ class Mlp:
         import json
         with open(path) as f:
             doc = json.load(f)
-        if doc.get("format") != "ahr-mlp-1" or int(doc["nparam"]) != MLP_NPARAM:
+        if doc.get("format") != "ahr-mlp-2" or int(doc["nparam"]) != MLP_NPARAM:
             raise ValueError(f"{path}: not a model of this network shape")
         p = torch.tensor(np.asarray(doc["params"], np.float32)).to(device)
         m = cls(p, doc["beta"], doc["validated"])
@@ -455,11 +458,12 @@ class Graph:
         return out, bool(fb.value)
 
     def features(self, spec, x, stream=None):
-        """(feats [n*C, 8], hops [3, n, C], stats [2, C]) of the surrogate for signal x."""
+        """(feats [n*C, 8], hops [4, n, C] (h0..h3), stats [3, C] (m, s, r)) of the
+        surrogate for signal x."""
         n, C = x.shape
         feats = torch.empty((n * C, MLP_FEATURE_STRIDE), dtype=torch.float32, device=x.device)
-        hops = torch.empty((3, n, C), dtype=torch.float32, device=x.device)
-        stats = torch.empty((2, C), dtype=torch.float32, device=x.device)
+        hops = torch.empty((4, n, C), dtype=torch.float32, device=x.device)
+        stats = torch.empty((3, C), dtype=torch.float32, device=x.device)
         _check(load().ahr_filter_features(self.h, ctypes.byref(spec), _ptr(x), C, _ptr(feats), _ptr(hops),
                                           _ptr(stats), _stream(stream)))
         return feats, hops, stats

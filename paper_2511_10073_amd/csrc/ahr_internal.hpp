@@ -369,7 +369,7 @@ void hpwl_launch(const ahr_netlist& nl, const float* pos, int32_t ncols, double*
                  hipStream_t s);
 size_t hpwl_partial_elems();
 // mlp.hip
-void run_learned(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[3], const float* in,
+void run_learned(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[4], const float* in,
                  float* out, int32_t ncols, float* feats, float* hops, float* stats, hipStream_t s);
 void mlp_forward(const float* params, const float* feats, int64_t n, float* o, hipStream_t s);
 void mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n, float* grad,

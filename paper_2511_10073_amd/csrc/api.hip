@@ -608,7 +608,7 @@ ahr_status ahr_filter_features(ahr_graph* h, const ahr_filter_spec* spec, const 
     if (!gr->has_hints) return fail(AHR_EINVAL, "graph has no hints yet: build with a placement or update_hints");
     return guarded([&]() -> ahr_status {
         ahr::ArenaScope arena_scope(gr->arena);
-        static const float zero_beta[3] = {0.f, 0.f, 0.f};
+        static const float zero_beta[4] = {0.f, 0.f, 0.f, 0.f};
         ahr::DevBuf<float> p;
         hipStream_t s = as_stream(stream);
         gr->use_stream(s);

@@ -1,15 +1,20 @@
 // Learned surrogate of the refinement filter (a project addition; the
 // paper has no learned component).  For every (instance row, column):
-//   h_j = (T^j X) for j = 1..3, m_c / s_c = mean / std of h_3 over movable rows,
-//   f = [(h1 - h3)/s_c, (h2 - h3)/s_c, (h3 - m_c)/s_c, log1p(d), hsum/d],
+//   h_j = (T^j X) for j = 0..3 (h_0 = X), m_c / s_c = mean / std of h_3 over
+//   movable rows, r_c = root mean square of h_0 - h_3 over movable rows,
+//   f = [(h0 - h3)/r_c, (h1 - h3)/r_c, (h2 - h3)/r_c, (h3 - m_c)/s_c,
+//        log1p(d), hsum/d, log(s_c / r_c)],
 //   o = w3 . relu(W2 relu(W1 f + b1) + b2) + b3,
-//   y = beta_1 h1 + beta_2 h2 + beta_3 h3 + s_c o   (fixed rows keep their input).
+//   y = beta_0 h0 + beta_1 h1 + beta_2 h2 + beta_3 h3 + r_c o   (fixed rows keep their input).
+// r_c, the displacement of three hops, is a length of the graph's local
+// neighbourhoods while s_c grows with the die, so the scaled differences and
+// the output correction keep their size on netlists of any size.
 //
 // Inference runs the three layers on the matrix cores: 16 samples per
 // wavefront, bfloat16 operands, float32 accumulation.  Every layer is
 // computed transposed (hidden x samples): the accumulator of one 16-row
 // output tile leaves lane l with rows 4(l/16)..4(l/16)+3 of sample l%16.
-// Layer 1 (5 features padded to K = 16) uses v_mfma_f32_16x16x16_bf16, whose
+// Layer 1 (7 features padded to K = 16) uses v_mfma_f32_16x16x16_bf16, whose
 // B operand has exactly that layout.  Layers 2 and 3 contract over the 64
 // hidden units with gfx950's v_mfma_f32_16x16x32_bf16, whose B operand gives
 // lane l eight K slots 8(l/16)..8(l/16)+7: the lane's rows of two output
@@ -175,22 +180,23 @@ __device__ __forceinline__ float unscale(const float* z, int C, int r, int c, fl
 }
 
 struct LearnArgs {
+    const float* z0;        // the expanded input, scaled like the hops
     const float* z1;
     const float* z2;
     const float* z3;
     const float* scale;
     const double* deg;
     const float* hsum;
-    const float* stats;     // [2][C]: mean, std of h3
+    const float* stats;     // [3][C]: mean and std of h3, rms of h0 - h3
     const float4* rowf;     // [n_inst] per execution row: 1/s, log1p(d), hsum/d, row code (bits)
     const float* in;
     float* out;
     float* feats;           // optional [n_inst * C][8], instance order
-    float* hops;            // optional [3][n_inst][C], instance order
+    float* hops;            // optional [4][n_inst][C], instance order
     const uint8_t* flags;
     const int32_t* perm;
     const float* params;
-    float beta0, beta1, beta2;
+    float beta[4];
     int32_t n_inst;
     int write_out;
 };
@@ -216,10 +222,10 @@ __global__ void k_row_feat(int32_t n, const float* __restrict__ scale, const dou
 }
 
 // Inputs of one tile's sample for lane group 0 (the hops, for features
-// 0..3 and the epilogue) or group 1 (the row values, for feature 4); the
-// other groups feed zeros.
+// 0..3 and the epilogue) or group 1 (the row values, for features 4..6);
+// the other groups feed zeros.
 struct TileIn {
-    float h[3];
+    float h[4];
     float4 rf;
 };
 
@@ -230,14 +236,15 @@ template <int C>
 __device__ __forceinline__ TileIn tile_load(const LearnArgs& a, int64_t smp, int g) {
     TileIn t;
     const int64_t r = smp / C;
-    t.h[0] = t.h[1] = t.h[2] = 0.f;
+    t.h[0] = t.h[1] = t.h[2] = t.h[3] = 0.f;
     t.rf = make_float4(0.f, 0.f, 0.f, 0.f);
     if (r < a.n_inst && g < 2) {
         t.rf = a.rowf[r];
         if (g == 0) {
-            t.h[0] = a.z1[smp];
-            t.h[1] = a.z2[smp];
-            t.h[2] = a.z3[smp];
+            t.h[0] = a.z0[smp];
+            t.h[1] = a.z1[smp];
+            t.h[2] = a.z2[smp];
+            t.h[3] = a.z3[smp];
         }
     }
     return t;
@@ -252,11 +259,11 @@ __device__ __forceinline__ void tile_unscale(const LearnArgs& a, TileIn& t, int6
     const float inv_s = t.rf.x;
     if (inv_s > 0.f) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) t.h[j] *= inv_s;
+        for (int j = 0; j < 4; ++j) t.h[j] *= inv_s;
     } else if (smp / C < a.n_inst) {
         const float v = a.in[static_cast<int64_t>(row_inst(__float_as_int(t.rf.w))) * C + smp % C];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) t.h[j] = v;
+        for (int j = 0; j < 4; ++j) t.h[j] = v;
     }
 }
 
@@ -270,7 +277,9 @@ __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
     load_mlp(a.params, R);
     const int l = lane_id(), g = l >> 4, sl = l & 15;
     const int c = sl % C;
-    const float mc = a.stats[c], sc = a.stats[C + c], inv_sc = 1.f / sc;
+    const float mc = a.stats[c], sc = a.stats[C + c], rc = a.stats[2 * C + c];
+    const float inv_sc = 1.f / sc, inv_rc = 1.f / rc;
+    const float lsr = static_cast<float>(log(static_cast<double>(sc) / static_cast<double>(rc)));
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBT / kWave);
     const int64_t ntiles = (static_cast<int64_t>(a.n_inst) * C + 15) / 16;
     int64_t t = static_cast<int64_t>(blockIdx.x) * (kBT / kWave) + wave_id();
@@ -280,13 +289,17 @@ __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
         tile_unscale<C>(a, cur, t * 16 + sl, g);
         float f[4];
         if (g == 0) {
-            f[0] = (cur.h[0] - cur.h[2]) * inv_sc;
-            f[1] = (cur.h[1] - cur.h[2]) * inv_sc;
-            f[2] = (cur.h[2] - mc) * inv_sc;
-            f[3] = cur.rf.y;
+            f[0] = (cur.h[0] - cur.h[3]) * inv_rc;
+            f[1] = (cur.h[1] - cur.h[3]) * inv_rc;
+            f[2] = (cur.h[2] - cur.h[3]) * inv_rc;
+            f[3] = (cur.h[3] - mc) * inv_sc;
+        } else if (g == 1) {
+            f[0] = cur.rf.y;
+            f[1] = cur.rf.z;
+            f[2] = lsr;
+            f[3] = 0.f;
         } else {
-            f[0] = g == 1 ? cur.rf.z : 0.f;
-            f[1] = f[2] = f[3] = 0.f;
+            f[0] = f[1] = f[2] = f[3] = 0.f;
         }
         const float o = mlp_tile(R, f);
         const int64_t r = (t * 16 + sl) / C;
@@ -296,16 +309,15 @@ __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
             if (a.feats) {
                 float* fp = a.feats + oc * kFP;
                 fp[0] = f[0], fp[1] = f[1], fp[2] = f[2], fp[3] = f[3];
-                fp[5] = fp[6] = fp[7] = 0.f;
             }
             if (a.hops) {
                 const int64_t nc = static_cast<int64_t>(a.n_inst) * C;
-                a.hops[oc] = cur.h[0];
-                a.hops[nc + oc] = cur.h[1];
-                a.hops[2 * nc + oc] = cur.h[2];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a.hops[j * nc + oc] = cur.h[j];
             }
             if (a.write_out) {
-                float y = a.beta0 * cur.h[0] + a.beta1 * cur.h[1] + a.beta2 * cur.h[2] + sc * o;
+                float y = a.beta[0] * cur.h[0] + a.beta[1] * cur.h[1] + a.beta[2] * cur.h[2] + a.beta[3] * cur.h[3] +
+                          rc * o;
                 a.out[oc] = row_fixed(code) ? a.in[oc] : y;
             }
         }
@@ -313,25 +325,31 @@ __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
     }
 }
 
-// Feature 4 of every sample, for the exported feature rows.
+// Features 4..7 of every sample (the row values, the column's log(s/r) and
+// the padding), for the exported feature rows.
 template <int C>
-__global__ void k_feature4(LearnArgs a) {
+__global__ void k_feature_row(LearnArgs a) {
     int64_t smp = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (smp >= static_cast<int64_t>(a.n_inst) * C) return;
     const int r = static_cast<int>(smp / C), c = static_cast<int>(smp % C);
-    a.feats[(static_cast<int64_t>(a.perm[r]) * C + c) * kFP + 4] = a.rowf[r].z;
+    const float4 rf = a.rowf[r];
+    const double lsr = log(static_cast<double>(a.stats[C + c]) / static_cast<double>(a.stats[2 * C + c]));
+    *reinterpret_cast<float4*>(a.feats + (static_cast<int64_t>(a.perm[r]) * C + c) * kFP + 4) =
+        make_float4(rf.y, rf.z, static_cast<float>(lsr), 0.f);
 }
 
-// Column statistics of h3 over movable instance rows (two passes, fixed
-// grid, float64 partials added in a fixed order).
+// Column statistics over movable instance rows (two passes, fixed grid,
+// float64 partials added in a fixed order).  The first pass sums h3 and
+// (h0 - h3)^2 (mean of h3, rms of h0 - h3), the second (h3 - mean)^2.
 constexpr int kStatGrid = 512;
 
 template <int C>
 __global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, const float* __restrict__ mean, double* __restrict__ part) {
     __shared__ double red[kBT / kWave];
-    double acc[C + 1];
+    constexpr int W = 2 * C + 1;
+    double acc[W];
 #pragma unroll
-    for (int c = 0; c <= C; ++c) acc[c] = 0;
+    for (int c = 0; c < W; ++c) acc[c] = 0;
     for (int64_t r = static_cast<int64_t>(blockIdx.x) * kBT + threadIdx.x; r < a.n_inst;
          r += static_cast<int64_t>(kStatGrid) * kBT) {
         const float4 rf = a.rowf[r];
@@ -339,36 +357,45 @@ __global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, const float* __res
         const float inv_s = rf.x;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            double h = unscale(a.z3, C, static_cast<int>(r), c, inv_s, a.in, a.perm);
+            const double h = unscale(a.z3, C, static_cast<int>(r), c, inv_s, a.in, a.perm);
             if (mean) {
-                double d = h - mean[c];
+                const double d = h - mean[c];
                 acc[c] += d * d;
             } else {
+                const double d0 = unscale(a.z0, C, static_cast<int>(r), c, inv_s, a.in, a.perm) - h;
                 acc[c] += h;
+                acc[C + c] += d0 * d0;
             }
         }
-        acc[C] += 1.0;
+        acc[2 * C] += 1.0;
     }
 #pragma unroll
-    for (int c = 0; c <= C; ++c) {
+    for (int c = 0; c < W; ++c) {
         double v = block_sum_f64<kBT>(acc[c], red);
-        if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * (C + 1) + c] = v;
+        if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * W + c] = v;
     }
 }
 
+// stats [3][C]: the first pass gives the mean (row 0) and the rms of h0 - h3
+// (row 2), the second the standard deviation (row 1); a zero deviation or
+// rms becomes 1.
 template <int C>
 __global__ void k_colstat_final(const double* __restrict__ part, float* __restrict__ stats, int second) {
+    constexpr int W = 2 * C + 1;
     int c = threadIdx.x;
     if (c >= C) return;
-    double s = 0, n = 0;
+    double s = 0, q = 0, n = 0;
     for (int b = 0; b < kStatGrid; ++b) {
-        s += part[b * (C + 1) + c];
-        n += part[b * (C + 1) + C];
+        s += part[b * W + c];
+        q += part[b * W + C + c];
+        n += part[b * W + 2 * C];
     }
     if (!second) {
         stats[c] = n > 0 ? static_cast<float>(s / n) : 0.f;
+        const double rms = n > 0 ? sqrt(q / n) : 0.0;
+        stats[2 * C + c] = rms > 0 ? static_cast<float>(rms) : 1.f;
     } else {
-        double sd = n > 0 ? sqrt(s / n) : 0.0;
+        const double sd = n > 0 ? sqrt(s / n) : 0.0;
         stats[C + c] = sd > 0 ? static_cast<float>(sd) : 1.f;
     }
 }
@@ -520,10 +547,11 @@ __global__ void k_adam(float* __restrict__ P, float* __restrict__ m, float* __re
 }
 
 template <int C>
-void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[3], const float* in,
+void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[4], const float* in,
                float* out, float* feats, float* hops, float* stats_out, hipStream_t s) {
     run_hops(g, spec, in, C, s);
     LearnArgs a;
+    a.z0 = g.z0.p;
     a.z1 = g.zh[0].p;
     a.z2 = g.zh[1].p;
     a.z3 = g.zh[2].p;
@@ -537,16 +565,14 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     a.flags = g.nl.node_flags;
     a.perm = g.perm.p;
     a.params = params;
-    a.beta0 = beta[0];
-    a.beta1 = beta[1];
-    a.beta2 = beta[2];
+    for (int j = 0; j < 4; ++j) a.beta[j] = beta[j];
     a.n_inst = g.n_inst;
     a.write_out = out != nullptr;
     DevBuf<double> part;
     DevBuf<float> stats;
     DevBuf<float4> rowf;
-    part.ensure(static_cast<size_t>(kStatGrid) * (C + 1), s);
-    stats.ensure(2 * C, s);
+    part.ensure(static_cast<size_t>(kStatGrid) * (2 * C + 1), s);
+    stats.ensure(3 * C, s);
     rowf.ensure(static_cast<size_t>(g.n_inst) + 1, s);
     a.stats = stats.p;
     a.rowf = rowf.p;
@@ -561,7 +587,7 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     AHR_LAUNCHED("k_colstat");
     hipLaunchKernelGGL((k_colstat_final<C>), dim3(1), dim3(64), 0, s, part.p, stats.p, 1);
     AHR_LAUNCHED("k_colstat_final");
-    if (stats_out) AHR_HIP(hipMemcpyAsync(stats_out, stats.p, 2 * C * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (stats_out) AHR_HIP(hipMemcpyAsync(stats_out, stats.p, 3 * C * sizeof(float), hipMemcpyDeviceToDevice, s));
     {
         ProfScope ps(kStageMlp, s);
         // one resident set of workgroups, each wave walking its tiles with
@@ -580,8 +606,8 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     }
     if (feats) {
         const int64_t ns = static_cast<int64_t>(g.n_inst) * C;
-        hipLaunchKernelGGL((k_feature4<C>), dim3(grid_for(ns, kBT)), dim3(kBT), 0, s, a);
-        AHR_LAUNCHED("k_feature4");
+        hipLaunchKernelGGL((k_feature_row<C>), dim3(grid_for(ns, kBT)), dim3(kBT), 0, s, a);
+        AHR_LAUNCHED("k_feature_row");
     }
     part.release(s);
     stats.release(s);
@@ -590,7 +616,7 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
 
 }  // namespace
 
-void run_learned(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[3], const float* in,
+void run_learned(Graph& g, const ahr_filter_spec& spec, const float* params, const float beta[4], const float* in,
                  float* out, int32_t ncols, float* feats, float* hops, float* stats, hipStream_t s) {
     switch (ncols) {
         case 1: learned_c<1>(g, spec, params, beta, in, out, feats, hops, stats, s); break;

@@ -2,13 +2,17 @@
 
 Every numeric step runs in libahr: the plain filter (targets), the
 features and hops, the float32 forward/backward, Adam.  The host only fits
-the three linear weights beta (a 3x3 least-squares system) and drives the
-loop.
+the four linear weights beta of h0..h3 (a 4x4 least-squares system) and
+drives the loop.
 
-Usage (the workload this was built for, 200 training and 20 held-out
-netlists of the mid-210k shape):
+The training set spans netlist sizes, so that the scale-free features and
+the log(s_c / r_c) feature see the sizes the filter is served at:
+`--train` netlists of the mid-210k shape plus `--train-sized` netlists whose
+sizes are log-uniform between 300k and 2.2M cells (`synth.netlist.sized`).
+Held out: `--heldout` mid-210k netlists and `--heldout-large` netlists of the
+large-2.2M shape, reported separately.
 
-    python -m paper_2511_10073_amd.train --train 200 --heldout 20
+    python -m paper_2511_10073_amd.train --train 160 --train-sized 40 --heldout 16 --heldout-large 4
 
 The result is written as JSON (parameters, beta, the validation flag and a
 summary of the held-out evaluation) and read back with `Mlp.load`.
@@ -16,6 +20,7 @@ summary of the held-out evaluation) and read back with `Mlp.load`.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -28,6 +33,8 @@ from . import (MLP_NPARAM, Graph, Mlp, Netlist, filter_spec, hint_params, mlp_ad
 
 HIDDEN = 64
 FEAT_PAD = 8
+NFEAT = 7
+NHOPS = 4       # h0 (the input) .. h3
 DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate_bank248.json")
 W3_OFF = HIDDEN * FEAT_PAD + HIDDEN + HIDDEN * HIDDEN + HIDDEN
 B3_OFF = W3_OFF + HIDDEN
@@ -38,9 +45,9 @@ def init_params(seed: int) -> torch.Tensor:
     exactly the linear combination of the hops."""
     g = torch.Generator().manual_seed(seed)
     p = torch.zeros(MLP_NPARAM)
-    w1 = torch.randn(HIDDEN, 5, generator=g) * math.sqrt(2.0 / 5)
+    w1 = torch.randn(HIDDEN, NFEAT, generator=g) * math.sqrt(2.0 / NFEAT)
     W1 = torch.zeros(HIDDEN, FEAT_PAD)
-    W1[:, :5] = w1
+    W1[:, :NFEAT] = w1
     p[:HIDDEN * FEAT_PAD] = W1.reshape(-1)
     o2 = HIDDEN * FEAT_PAD + HIDDEN
     p[o2:o2 + HIDDEN * HIDDEN] = (torch.randn(HIDDEN, HIDDEN, generator=g) * math.sqrt(2.0 / HIDDEN)).reshape(-1)
@@ -67,24 +74,24 @@ def collect(nl: dict, params, spec, rows=None, seed=0, device="cuda"):
 
 
 def fit_beta(data: list) -> np.ndarray:
-    """Least-squares weights of h1, h2, h3 over the collected rows (3x3
-    normal equations in float64)."""
-    G = np.zeros((3, 3))
-    b = np.zeros(3)
+    """Least-squares weights of h0..h3 over the collected rows (4x4 normal
+    equations in float64)."""
+    G = np.zeros((NHOPS, NHOPS))
+    b = np.zeros(NHOPS)
     for d in data:
-        H = d["hops"].reshape(3, -1)
+        H = d["hops"].reshape(NHOPS, -1)
         G += H @ H.T
         b += H @ d["y"].reshape(-1)
     return np.linalg.solve(G, b)
 
 
 def residual_samples(data: list, beta, device="cuda") -> tuple:
-    """Feature rows and residual targets r = (y - sum beta h) / s_c, moved to
+    """Feature rows and residual targets r = (y - sum beta h) / r_c, moved to
     the device once."""
     feats, targets = [], []
     for d in data:
-        lin = sum(beta[j] * d["hops"][j] for j in range(3))
-        r = (d["y"] - lin) / d["stats"][1][None, :]
+        lin = sum(beta[j] * d["hops"][j] for j in range(NHOPS))
+        r = (d["y"] - lin) / d["stats"][2][None, :]
         feats.append(d["feats"])
         targets.append(r.reshape(-1))
     F = torch.as_tensor(np.concatenate(feats).astype(np.float32)).to(device)
@@ -143,11 +150,14 @@ def main():
     from synth import netlist as N
 
     ap = argparse.ArgumentParser(description="train the learned filter surrogate")
-    ap.add_argument("--train", type=int, default=200)
-    ap.add_argument("--heldout", type=int, default=20)
+    ap.add_argument("--train", type=int, default=160, help="mid-210k training netlists")
+    ap.add_argument("--train-sized", type=int, default=40, help="training netlists of 300k-2.2M cells")
+    ap.add_argument("--heldout", type=int, default=16, help="mid-210k held-out netlists")
+    ap.add_argument("--heldout-large", type=int, default=4, help="large-2.2M held-out netlists")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=3e-3)
-    ap.add_argument("--rows", type=int, default=20000, help="movable rows sampled per training netlist")
+    ap.add_argument("--rows", type=int, default=20000, help="movable rows sampled per mid-210k training netlist")
+    ap.add_argument("--rows-sized", type=int, default=60000, help="movable rows sampled per sized training netlist")
     ap.add_argument("--tol", type=float, default=1e-3, help="validation bound on the mean held-out error")
     ap.add_argument("--out", default=DEFAULT_MODEL)
     args = ap.parse_args()
@@ -156,30 +166,44 @@ def main():
     t0 = time.time()
     data = []
     for s in range(4000, 4000 + args.train):
-        nl = N.generate(N.NetlistConfig(f"mid-{s}", 210_000, 500, 1200, 220_000, False, 10, 200, 0.40,
-                                        0.005, 51, 2000, 4, s))
-        data.append(collect(nl, params, spec, rows=args.rows, seed=s))
-        print(f"collected {s} ({time.time() - t0:.0f} s)", flush=True)
+        data.append(collect(N.generate(N.sized(N.MID.n_std, s)), params, spec, rows=args.rows, seed=s))
+        print(f"collected mid {s} ({time.time() - t0:.0f} s)", flush=True)
+    rng = np.random.default_rng(4600)
+    sizes = np.exp(rng.uniform(math.log(300_000), math.log(N.LARGE.n_std), args.train_sized)).astype(int)
+    for k, n in enumerate(sizes):
+        s = 4600 + k
+        data.append(collect(N.generate(N.sized(int(n), s)), params, spec, rows=args.rows_sized, seed=s))
+        print(f"collected sized {s} ({n} cells, {time.time() - t0:.0f} s)", flush=True)
     beta = fit_beta(data)
     F, R = residual_samples(data, beta)
     del data
     P, loss = train_mlp(F, R, args.steps, args.lr, log=lambda m: print(m, flush=True))
     del F, R
-    res = []
+    model = Mlp(P, beta, True)
+    res = {"mid": [], "large": []}
     for s in range(4200, 4200 + args.heldout):
-        nl = N.generate(N.NetlistConfig(f"mid-{s}", 210_000, 500, 1200, 220_000, False, 10, 200, 0.40,
-                                        0.005, 51, 2000, 4, s))
-        res.append(evaluate(nl, params, spec, Mlp(P, beta, True)))
-        print(json.dumps(res[-1]), flush=True)
-    e = np.array([r["rel_err"] for r in res])
-    el = np.array([r["rel_err_linear"] for r in res])
-    hd = np.array([r["hpwl_delta"] for r in res])
-    validated = bool(e.mean() <= args.tol and hd.max() <= 2e-3)
-    summary = dict(train=args.train, heldout=args.heldout, steps=args.steps, loss=loss, beta=list(map(float, beta)),
-                   rel_err_mean=float(e.mean()), rel_err_max=float(e.max()),
-                   rel_err_linear_mean=float(el.mean()), gain=float(el.mean() - e.mean()),
-                   hpwl_delta_max=float(hd.max()), validated=validated, tol=args.tol)
-    save_model(args.out, P, beta, validated, summary)
+        res["mid"].append(evaluate(N.generate(N.sized(N.MID.n_std, s)), params, spec, model))
+        print("mid", json.dumps(res["mid"][-1]), flush=True)
+    for s in range(4700, 4700 + args.heldout_large):
+        cfg = dataclasses.replace(N.LARGE, name=f"large-{s}", seed=s)
+        res["large"].append(evaluate(N.generate(cfg), params, spec, model))
+        print("large", json.dumps(res["large"][-1]), flush=True)
+    summary = dict(train=args.train, train_sized=args.train_sized, sized_cells=[int(v) for v in sizes],
+                   heldout=args.heldout, heldout_large=args.heldout_large, steps=args.steps, loss=loss,
+                   beta=list(map(float, beta)), tol=args.tol)
+    ok = True
+    for k, rs in res.items():
+        if not rs:
+            continue
+        e = np.array([r["rel_err"] for r in rs])
+        el = np.array([r["rel_err_linear"] for r in rs])
+        hd = np.array([r["hpwl_delta"] for r in rs])
+        summary[k] = dict(rel_err_mean=float(e.mean()), rel_err_max=float(e.max()),
+                          rel_err_linear_mean=float(el.mean()), gain=float(el.mean() - e.mean()),
+                          hpwl_delta_max=float(hd.max()))
+        ok = ok and bool(e.mean() <= args.tol and hd.max() <= 2e-3)
+    summary["validated"] = ok
+    save_model(args.out, P, beta, ok, summary)
     print(json.dumps(summary), flush=True)
 
 
@@ -187,7 +211,7 @@ def save_model(path, P, beta, validated, summary):
     """Write a model as JSON: float32 parameters (exact decimal round trip),
     beta, the validation flag and the training summary."""
     p = P.cpu().numpy().astype(np.float32)
-    doc = dict(format="ahr-mlp-1", hidden=HIDDEN, feat_pad=FEAT_PAD, nparam=int(p.size),
+    doc = dict(format="ahr-mlp-2", hidden=HIDDEN, feat_pad=FEAT_PAD, nparam=int(p.size),
                params=[float(v) for v in p], beta=[float(np.float32(b)) for b in beta], validated=bool(validated),
                summary=summary)
     with open(path, "w") as f:

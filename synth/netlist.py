@@ -78,6 +78,22 @@ def batch_member(n_std: int, seed: int, macro_pct: float) -> NetlistConfig:
                          0.002, 51, max(52, min(2000, n_std // 50)), 4, seed)
 
 
+def sized(n_std: int, seed: int) -> NetlistConfig:
+    """A netlist of any size between the mid-210k and large-2.2M shapes: the
+    per-cell rates of macros, I/O pins and nets and the big-net mix are
+    interpolated in log(size) between the two (clamped outside them)."""
+    t = (math.log(n_std) - math.log(MID.n_std)) / (math.log(LARGE.n_std) - math.log(MID.n_std))
+    t = min(1.0, max(0.0, t))
+    lerp = lambda a, b: (1.0 - t) * a + t * b
+    n_macro = int(round(n_std * lerp(MID.n_macro / MID.n_std, LARGE.n_macro / LARGE.n_std)))
+    n_io = int(round(n_std * lerp(MID.n_io / MID.n_std, LARGE.n_io / LARGE.n_std)))
+    n_nets = int(round(n_std * lerp(MID.n_nets / MID.n_std, LARGE.n_nets / LARGE.n_std)))
+    return NetlistConfig(f"sized-{n_std}-{seed}", n_std, max(2, n_macro), max(8, n_io), n_nets, False,
+                         MID.macro_side_min, MID.macro_side_max, MID.macro_area_frac,
+                         lerp(MID.big_frac, LARGE.big_frac), MID.big_min,
+                         int(round(lerp(MID.big_max, LARGE.big_max))), 4, seed)
+
+
 def batch_sizes(n_graphs: int = 64, lo: int = 5000, hi: int = 200_000,
                 seed: int = 3000) -> list[tuple[int, int, float]]:
     """(n_std, seed, macro_pct) of each member of the batched workload."""

@@ -90,14 +90,15 @@ def small():
 def test_features_match_oracle(small):
     nl, og, gr, x = small["nl"], small["og"], small["gr"], small["x"]
     feats, hops, stats = gr.features(U.to_c_spec(A, BANK), x)
-    F, (h1, h2, h3), m, s = M.features(nl, og, nl["g0"])
+    F, hs, (m, s, r) = M.features(nl, og, nl["g0"])
     n, C = x.shape
     mov = U.movable_rows(nl)
-    for j, h in enumerate((h1, h2, h3)):
+    for j, h in enumerate(hs):
         assert U.rel_err(hops[j].cpu().numpy(), h, mov) <= 1e-5
     st = stats.cpu().numpy()
     assert np.allclose(st[0], m, rtol=0, atol=1e-5 * s.max())
     assert np.allclose(st[1], s, rtol=1e-5)
+    assert np.allclose(st[2], r, rtol=1e-4)
     f = feats.cpu().numpy().reshape(n, C, M.FEAT_PAD)
     for k in range(M.NFEAT):
         d = np.abs(f[mov, :, k] - F[mov, :, k])
@@ -107,7 +108,7 @@ def test_features_match_oracle(small):
 def test_learned_filter_matches_oracle(small):
     nl, og, gr, x = small["nl"], small["og"], small["gr"], small["x"]
     p = rand_params(7, 0.3)
-    beta = (0.1, 0.3, 0.6)
+    beta = (-2.0, 4.5, -3.1, 1.6)
     model = A.Mlp(torch.as_tensor(p).cuda(), beta, True)
     out, fb = gr.filter_learned(U.to_c_spec(A, BANK), model, x)
     assert not fb
@@ -123,7 +124,7 @@ def test_learned_filter_matches_oracle(small):
 def test_unvalidated_model_falls_back_to_plain_filter(small):
     gr, x = small["gr"], small["x"]
     spec = U.to_c_spec(A, BANK)
-    model = A.Mlp(torch.zeros(A.MLP_NPARAM, device="cuda"), (1, 1, 1), validated=False)
+    model = A.Mlp(torch.zeros(A.MLP_NPARAM, device="cuda"), (1, 1, 1, 1), validated=False)
     out, fb = gr.filter_learned(spec, model, x)
     plain = gr.filter(spec, x)
     assert fb
@@ -155,7 +156,7 @@ def test_training_is_reproducible():
 def test_network_gains_over_linear_hops():
     """Train on three netlists, evaluate on a held-out fourth: the network's
     centred relative error is below that of the best linear combination of
-    the three hops (least squares on the same training data)."""
+    the input and the three hops (least squares on the same training data)."""
     from paper_2511_10073_amd import train as T
     spec = U.to_c_spec(A, BANK)
     hp = U.to_c_params(A, O.HintParams(nbx=16, nby=16, detection_ratio=0.2))
@@ -175,7 +176,7 @@ def test_refine_learned_round_by_round(small):
     relaxation; an unvalidated model reproduces the plain refinement."""
     nl, gr, x, p = small["nl"], small["gr"], small["x"], small["p"]
     params = rand_params(11, 0.3)
-    beta = (0.1, 0.3, 0.6)
+    beta = (-2.0, 4.5, -3.1, 1.6)
     model = A.Mlp(torch.as_tensor(params).cuda(), beta, True)
     spec = U.to_c_spec(A, BANK)
     gamma = 0.5

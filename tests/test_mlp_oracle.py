@@ -62,17 +62,54 @@ def test_forward_closed_forms():
 def test_features_follow_their_definitions():
     nl = N.generate(N.small(400, 21, ncols=4))
     g = O.build_graph(nl, O.HintParams(nbx=8, nby=8), nl["g0"][:, :2])
-    F, (h1, h2, h3), m, s = M.features(nl, g, nl["g0"])
-    # h_j equal single-band filters without pinning
+    F, (h0, h1, h2, h3), (m, s, r) = M.features(nl, g, nl["g0"])
+    # h_0 is the input; h_j equal single-band filters without pinning
+    assert np.array_equal(h0, np.asarray(nl["g0"], np.float64))
     for j, h in ((1, h1), (2, h2), (3, h3)):
         ref, _ = O.apply_filter(nl, g, O.FilterSpec(ks=(j,), alphas=(1.0,)), nl["g0"], return_full=True, pin=False)
         assert np.allclose(h, ref[:g.n_inst], rtol=0, atol=1e-12 * np.abs(ref).max())
     mov = (nl["node_flags"] & 1) == 0
-    assert np.allclose(F[mov, :, 2].mean(axis=0), 0, atol=1e-9)
-    assert np.allclose(F[mov, :, 2].std(axis=0), 1, atol=1e-9)
+    # feature 3 is standardised h_3; feature 0 has unit root mean square (r_c's definition)
+    assert np.allclose(F[mov, :, 3].mean(axis=0), 0, atol=1e-9)
+    assert np.allclose(F[mov, :, 3].std(axis=0), 1, atol=1e-9)
+    assert np.allclose(np.sqrt(np.mean(F[mov, :, 0] ** 2, axis=0)), 1, atol=1e-12)
+    # features 1 and 2 share feature 0's scale: their ratios to it are the hops' own
+    i = np.flatnonzero(mov)[:20]
+    for k, h in ((1, h1), (2, h2)):
+        assert np.allclose(F[i, :, k] * r, h[i] - h3[i], rtol=1e-12, atol=1e-9 * np.abs(h3).max())
+    assert np.allclose(F[:, :, 6], np.log(s / r)[None, :])
     A = g.adjacency().toarray()
     d = np.abs(A).sum(1)
     hint = A[:, g.first_mvirt:].sum(1)
     i = np.flatnonzero(mov & (d[:g.n_inst] > 0))[:50]
-    assert np.allclose(F[i, 0, 4], hint[i] / d[i])
-    assert np.allclose(F[i, 0, 3], np.log1p(d[i]))
+    assert np.allclose(F[i, 0, 5], hint[i] / d[i])
+    assert np.allclose(F[i, 0, 4], np.log1p(d[i]))
+
+
+def test_zero_network_with_the_bank_coefficients_is_the_filter():
+    """A bank of order at most 3 lies in the span of h_0..h_3: with a zero
+    network and beta set to the bank's weights, the surrogate is the plain
+    filter of Section V (fixed rows pinned as there)."""
+    nl = N.generate(N.small(500, 23, ncols=4))
+    g = O.build_graph(nl, O.HintParams(nbx=8, nby=8), nl["g0"][:, :2])
+    spec = O.FilterSpec(ks=(0, 1, 3), alphas=(0.1, 0.25, 0.65))
+    ref = O.apply_filter(nl, g, spec, nl["g0"])
+    zero = np.zeros(M.NPARAM)
+    y = M.learned_filter(nl, g, zero, (0.1, 0.25, 0.0, 0.65), nl["g0"])
+    assert np.allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # the network's output enters scaled by r_c
+    b3 = np.zeros(M.NPARAM)
+    b3[M.OFFSETS["b3"][0]] = 0.5
+    F, h, (m, s, r) = M.features(nl, g, nl["g0"])
+    y2 = M.learned_filter(nl, g, b3, (0.1, 0.25, 0.0, 0.65), nl["g0"])
+    mov = (nl["node_flags"] & 1) == 0
+    assert np.allclose(y2[mov] - y[mov], 0.5 * r[None, :], rtol=1e-12)
+
+
+def test_column_stats_fall_back_to_one():
+    h0 = np.array([[1.0, 2.0], [3.0, 2.0]])
+    h3 = np.array([[5.0, 2.0], [5.0, 2.0]])
+    m, s, r = M.column_stats(h0, h3, np.array([True, True]))
+    assert np.array_equal(m, [5.0, 2.0])
+    assert np.array_equal(s, [1.0, 1.0])          # h_3 constant
+    assert np.allclose(r, [np.sqrt(10.0), 1.0])   # RMS of (-4, -2); zero in column 1
