@@ -247,6 +247,7 @@ struct Graph {
     DevBuf<int32_t> bin_start;    // [n_bins+1]
     DevBuf<int32_t> bin_cells;    // [n_hint_cells] execution rows of hint cells by bin, ascending
     DevBuf<int64_t> bin_area_q;   // [n_bins] fixed-point area (2^-28 units)
+    DevBuf<int64_t> macro_area_q; // [n_bins] the macros' part of bin_area_q (kept for the next round)
     DevBuf<double> phi;           // [n_bins]
     DevBuf<int32_t> bm_start;     // [n_bins+1] macros whose bin span covers a bin
     DevBuf<int32_t> bm_list;
@@ -269,6 +270,8 @@ struct Graph {
     int32_t habs_version = -1;
     DevBuf<double> gmax;          // first-hop Gershgorin maxima (per workgroup, then per long row)
     int32_t has_xcell = 0;
+    int32_t n_movable_macro = 0;  // macros without AHR_NODE_FIXED
+    int32_t macro_cache = 0;      // macro_rect/_span, bm_start/_list and macro_area_q hold the fixed macros' values
 
     // execution layout: instance, macro pin and star rows each in spatial
     // order inside their id range (perm: exec -> id); virtual rows unmoved
@@ -347,7 +350,11 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
 // The execution-order netlist entries, with stream s ordered after their copy.
 const int2* net_entries(const Graph& g, hipStream_t s);
 // hints.hip
-void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s);
+// macros_unchanged: the macros sit where the previous call on this graph
+// put them (the rounds of Algorithm 1 after the first, whose relaxation
+// keeps fixed rows); with every macro fixed, their footprints, per-bin
+// areas and bin lists are then reused.
+void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s, bool macros_unchanged = false);
 // filter.hip
 void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s);
 void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* out,

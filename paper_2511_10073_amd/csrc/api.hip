@@ -66,6 +66,7 @@ Graph::~Graph() {
     xhsg.release(s);
     gmax.release(s);
     bin_area_q.release(s);
+    macro_area_q.release(s);
     phi.release(s);
     macro_span.release(s);
     macro_rect.release(s);
@@ -476,7 +477,7 @@ ahr_status ahr_graph_refine(ahr_graph* h, const ahr_filter_spec* spec, const flo
         const float* cur = g0;
         for (int r = 0; r < T_hint; ++r) {
             float* next = (r == T_hint - 1) ? out : ((r & 1) ? gr->gb.p : gr->ga.p);
-            ahr::build_hints(*gr, cur, ncols, s);
+            ahr::build_hints(*gr, cur, ncols, s, r > 0);     // later rounds: fixed macros stay put
             ahr::run_filter(*gr, *spec, cur, gr->gt.p, ncols, s);
             ahr::relax(*gr, cur, gr->gt.p, next, ncols, gamma, s);
             cur = next;
@@ -518,7 +519,7 @@ ahr_status ahr_refine(const ahr_netlist* nl, const ahr_hint_params* hp, const ah
         const float* cur = g0;
         for (int r = 0; r < T_hint; ++r) {
             float* next = (r == T_hint - 1) ? out : ((r & 1) ? gr->gb.p : gr->ga.p);
-            ahr::build_hints(*gr, cur, ncols, s);
+            ahr::build_hints(*gr, cur, ncols, s, r > 0);     // later rounds: fixed macros stay put
             ahr::run_filter(*gr, *spec, cur, gr->gt.p, ncols, s);
             ahr::relax(*gr, cur, gr->gt.p, next, ncols, gamma, s);
             cur = next;
@@ -557,7 +558,7 @@ ahr_status ahr_refine_learned(ahr_graph* h, const ahr_filter_spec* spec, const a
         const float* cur = g0;
         for (int r = 0; r < T_hint; ++r) {
             float* next = (r == T_hint - 1) ? out : ((r & 1) ? gr->gb.p : gr->ga.p);
-            ahr::build_hints(*gr, cur, ncols, s);
+            ahr::build_hints(*gr, cur, ncols, s, r > 0);     // later rounds: fixed macros stay put
             if (model->validated)
                 ahr::run_learned(*gr, *spec, model->params, model->beta, cur, gr->gt.p, ncols, nullptr, nullptr,
                                  nullptr, s);

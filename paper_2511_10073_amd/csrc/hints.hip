@@ -108,19 +108,38 @@ __global__ void __launch_bounds__(kBT) k_cell_bins(Grid gr, const float* __restr
                                                    int32_t* __restrict__ cell_bin, float2* __restrict__ xpos,
                                                    unsigned long long* __restrict__ area_q) {
     extern __shared__ unsigned long long area_lds[];
+    if (n_inst <= 0) return;     // (the launch has one workgroup even then; nothing to read)
     const int nbins = gr.nbx * gr.nby;
     const bool lds = nbins <= kLdsBins;
     if (lds && with_density)
         for (int b = threadIdx.x; b < nbins; b += kBT) area_lds[b] = 0ull;
     __syncthreads();
-    int64_t base = static_cast<int64_t>(blockIdx.x) * kBT * kCellBinRows;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kBT * kCellBinRows;
+    // every row's loads first (the instance, then its position and class),
+    // so the thread's kCellBinRows dependent pairs are in flight together;
+    // rows past the end read row 0 and are dropped below
+    int inst[kCellBinRows];
+#pragma unroll
     for (int t = 0; t < kCellBinRows; ++t) {
-        int64_t r = base + static_cast<int64_t>(t) * kBT + threadIdx.x;
+        const int64_t r = base + static_cast<int64_t>(t) * kBT + threadIdx.x;
+        inst[t] = perm[r < n_inst ? r : 0];
+    }
+    float px[kCellBinRows], py[kCellBinRows];
+    int64_t cls[kCellBinRows];
+#pragma unroll
+    for (int t = 0; t < kCellBinRows; ++t) {
+        const int64_t r = base + static_cast<int64_t>(t) * kBT + threadIdx.x;
+        px[t] = pos[static_cast<int64_t>(inst[t]) * ncols];
+        py[t] = pos[static_cast<int64_t>(inst[t]) * ncols + 1];
+        cls[t] = xcell[r < n_inst ? r : 0];
+    }
+#pragma unroll
+    for (int t = 0; t < kCellBinRows; ++t) {
+        const int64_t r = base + static_cast<int64_t>(t) * kBT + threadIdx.x;
         if (r >= n_inst) break;
-        const int i = perm[r];
-        const float x = pos[static_cast<int64_t>(i) * ncols], y = pos[static_cast<int64_t>(i) * ncols + 1];
+        const float x = px[t], y = py[t];
         xpos[r] = make_float2(x, y);
-        const int64_t c = xcell[r];
+        const int64_t c = cls[t];
         int b = -1;
         if ((c & 3) != kCellOther) {
             int bx = bin_coord(x, gr.xl32, gr.bw32, gr.nbx);
@@ -704,6 +723,18 @@ __global__ void k_macro_fill(int32_t n_pairs, int32_t first_mvirt, const int32_t
     ent[rp[first_mvirt + k] + (t - mstart[k])] = make_int2(row, w);
 }
 
+__global__ void k_copy_u64(const unsigned long long* __restrict__ src, unsigned long long* __restrict__ dst,
+                           int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_add_u64(const unsigned long long* __restrict__ src, unsigned long long* __restrict__ dst,
+                          int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] += src[i];
+}
+
 __global__ void k_fill_u64(unsigned long long* p, int64_t n) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
@@ -813,7 +844,7 @@ void prune_hints(Graph& g, int64_t cap, hipStream_t s) {
     g.nnz_hint = -1;
 }
 
-void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
+void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s, bool macros_unchanged) {
     ProfScope ps(kStageHints, s);
     const ahr_hint_params& hp = g.hp;
     const int macro_hints = (hp.flags & AHR_MACRO_HINTS) ? 1 : 0;
@@ -861,9 +892,20 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     g.xpos.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.cell_bin.ensure(static_cast<size_t>(n_inst) + 1, s);
     g.bin_area_q.ensure(static_cast<size_t>(nbins) + 1, s);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s,
-                       reinterpret_cast<unsigned long long*>(g.bin_area_q.p), static_cast<int64_t>(nbins));
-    AHR_LAUNCHED("k_fill_u64");
+    // With every macro fixed and where the last call put them, their
+    // footprints, spans, per-bin areas and bin lists are those of that call.
+    const bool reuse = macros_unchanged && g.macro_cache && g.n_movable_macro == 0;
+    g.macro_cache = 0;
+    if (reuse && bin_hints) {     // the density starts from the macros' areas
+        hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s,
+                           reinterpret_cast<const unsigned long long*>(g.macro_area_q.p),
+                           reinterpret_cast<unsigned long long*>(g.bin_area_q.p), static_cast<int64_t>(nbins));
+        AHR_LAUNCHED("k_copy_u64");
+    } else {
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s,
+                           reinterpret_cast<unsigned long long*>(g.bin_area_q.p), static_cast<int64_t>(nbins));
+        AHR_LAUNCHED("k_fill_u64");
+    }
     const size_t bins_lds = nbins <= kLdsBins ? static_cast<size_t>(nbins) * sizeof(unsigned long long) : 0;
     hipLaunchKernelGGL(k_cell_bins, dim3(grid_for(n_inst, kBT * kCellBinRows)), dim3(kBT), bins_lds, s, gr, pos, ncols,
                        n_inst, g.perm.p, g.xcell.p, bin_hints, g.cell_bin.p, g.xpos.p,
@@ -877,11 +919,23 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     const int32_t n_macro = g.n_macro;
     g.macro_rect.ensure(static_cast<size_t>(n_macro) + 1, s);
     g.macro_span.ensure(static_cast<size_t>(n_macro) + 1, s);
-    if (n_macro)
+    if (n_macro && !reuse) {
+        // the macros' areas go to macro_area_q (kept), then into the density
+        g.macro_area_q.ensure(static_cast<size_t>(nbins) + 1, s);
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s,
+                           reinterpret_cast<unsigned long long*>(g.macro_area_q.p), static_cast<int64_t>(nbins));
+        AHR_LAUNCHED("k_fill_u64");
         hipLaunchKernelGGL(k_macros, dim3(grid_for(n_macro, kBT)), dim3(kBT), 0, s, gr, pos, ncols, g.macro_ids.p,
                            n_macro, g.nl.node_size, bin_hints, g.macro_rect.p, g.macro_span.p,
-                           reinterpret_cast<unsigned long long*>(g.bin_area_q.p));
-    AHR_LAUNCHED("k_macros");
+                           reinterpret_cast<unsigned long long*>(g.macro_area_q.p));
+        AHR_LAUNCHED("k_macros");
+        if (bin_hints) {
+            hipLaunchKernelGGL(k_add_u64, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s,
+                               reinterpret_cast<const unsigned long long*>(g.macro_area_q.p),
+                               reinterpret_cast<unsigned long long*>(g.bin_area_q.p), static_cast<int64_t>(nbins));
+            AHR_LAUNCHED("k_add_u64");
+        }
+    }
     g.phi.ensure(static_cast<size_t>(nbins) + 1, s);
     if (bin_hints) {
         hipLaunchKernelGGL(k_phi, dim3(grid_for(nbins, kBT)), dim3(kBT), 0, s, nbins, gr.bw * gr.bh,
@@ -893,7 +947,7 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     // 4. macros per bin
     const int use_macros = macro_hints && n_macro > 0;
     g.bm_start.ensure(static_cast<size_t>(nbins) + 1, s);
-    if (use_macros) {
+    if (use_macros && !reuse) {
         DevBuf<int32_t> bmc;
         bmc.ensure(static_cast<size_t>(nbins) + 1, s);
         hipLaunchKernelGGL(k_bin_macros, dim3(nbins), dim3(kBT), 0, s, hp.nbx, g.macro_span.p, n_macro,
@@ -910,10 +964,11 @@ void build_hints(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
                            static_cast<const int32_t*>(g.bm_start.p), static_cast<int32_t*>(nullptr), g.bm_list.p);
         AHR_LAUNCHED("k_bin_macros fill");
         bmc.release(s);
-    } else {
+    } else if (!use_macros) {
         fill_i32(g.bm_start.p, nbins + 1, 0, s);
         g.bm_list.ensure(1, s);
     }
+    g.macro_cache = g.n_movable_macro == 0 ? 1 : 0;
 
     HintArgs a;
     a.gr = gr;

@@ -78,9 +78,14 @@ __global__ void k_list_big_stars(const int32_t* __restrict__ flag, const int32_t
     if (e < n_nets && flag[e]) out[rank[e]] = star_rank[e];
 }
 
-__global__ void k_mark_macro(const uint8_t* __restrict__ flags, int32_t n, int32_t* __restrict__ out) {
+// Macro flags, and the count of movable macros in *movable.
+__global__ void k_mark_macro(const uint8_t* __restrict__ flags, int32_t n, int32_t* __restrict__ out,
+                             int32_t* __restrict__ movable) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (flags[i] & AHR_NODE_MACRO) ? 1 : 0;
+    if (i >= n) return;
+    const uint8_t f = flags[i];
+    out[i] = (f & AHR_NODE_MACRO) ? 1 : 0;
+    if ((f & AHR_NODE_MACRO) && !(f & AHR_NODE_FIXED)) atomicAdd(movable, 1);
 }
 
 // Net of every pin: one thread per net of at most a wave's worth of pins,
@@ -562,7 +567,8 @@ void build_netlist(Graph& g, hipStream_t s) {
         hipLaunchKernelGGL(k_mark_star, dim3(grid_for(n_nets, kBT)), dim3(kBT), 0, s, nl.net_ptr, n_nets,
                            hp.clique_max, is_star.p, is_big.p, is_bs.p);
     AHR_LAUNCHED("k_mark_star");
-    hipLaunchKernelGGL(k_mark_macro, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, nl.node_flags, n_inst, is_mac.p);
+    hipLaunchKernelGGL(k_mark_macro, dim3(grid_for(n_inst, kBT)), dim3(kBT), 0, s, nl.node_flags, n_inst, is_mac.p,
+                       g.counter.p + 1);
     AHR_LAUNCHED("k_mark_macro");
     mp_rank.ensure(static_cast<size_t>(n_pins) + 1, s);
     star_rank.ensure(static_cast<size_t>(n_nets) + 1, s);
@@ -575,9 +581,9 @@ void build_netlist(Graph& g, hipStream_t s) {
     scan_i32_to_i32(is_big.p, big_rank.p, n_nets, g.scan_tmp.p, s);
     scan_i32_to_i32(is_mac.p, mac_rank.p, n_inst, g.scan_tmp.p, s);
     scan_i32_to_i32(is_bs.p, bs_rank.p, n_nets, g.scan_tmp.p, s);
-    int32_t cnt5[6];
+    int32_t cnt5[7];
     read_scalars({mp_rank.p + n_pins, star_rank.p + n_nets, big_rank.p + n_nets, mac_rank.p + n_inst,
-                  bs_rank.p + n_nets, g.counter.p},
+                  bs_rank.p + n_nets, g.counter.p, g.counter.p + 1},
                  cnt5, s);
     if (const int32_t bad = cnt5[5]) {
         static const char* why[] = {"", "pin_node out of [0, n_inst)", "net_ptr[0] != 0",
@@ -589,6 +595,7 @@ void build_netlist(Graph& g, hipStream_t s) {
     g.n_big_nets = cnt5[2];
     g.n_macro = cnt5[3];
     g.n_big_stars = cnt5[4];
+    g.n_movable_macro = cnt5[6];
     if ((hp.flags & AHR_MACRO_HINTS) && g.n_macro > 16384)
         throw Error{AHR_EUNSUPPORTED, "macro hints support at most 16384 macros"};
     g.star_net.ensure(static_cast<size_t>(g.n_star) + 1, s);

@@ -12,6 +12,7 @@
 //        standard cell (a point lies in at most four footprints that do not
 //        overlap), plus twice the cells times the detection window's slots;
 //        each an 8-byte entry, with the sparsification's compaction copy;
+//   B    per bin: densities, phi, the macros' kept areas, bin lists;
 //   rows N + macro pin nodes + star nodes + macro and bin virtual nodes:
 //        row pointers, layout, degrees, scales, hop coefficients, row
 //        classes and the filter's signal buffers (about 11 C floats a row);
@@ -105,7 +106,7 @@ size_t graph_workspace_bytes(const ahr_netlist& nl, const ahr_hint_params& hp, i
     const double rows = static_cast<double>(N) + mpin + stars + (mh ? macros : 0.0) + B;
     const double C = ncols > 0 ? ncols : 8;
     const double bytes = 48 * raw + 40 * H + (176 + 44 * C) * rows + (264 + 12 * C) * static_cast<double>(N) +
-                         64 * static_cast<double>(P) + 48 * static_cast<double>(E) + 16 * B * wslots + 32 * B;
+                         64 * static_cast<double>(P) + 48 * static_cast<double>(E) + 16 * B * wslots + 40 * B;
     return static_cast<size_t>(1.25 * bytes) + (size_t(32) << 20);
 }
 
