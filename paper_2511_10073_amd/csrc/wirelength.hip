@@ -120,11 +120,180 @@ __device__ __forceinline__ double gpin(double x, const ColAcc& a, double inv_g) 
     return pp * (1.0 + (x - xp) * inv_g) - pm * (1.0 - (x - xm) * inv_g);
 }
 
-// One net per thread, one column pair (x, y) at a time: extremes, shifted
-// sums, then each pin's gradient.  Nets of at most kReg pins gather their
-// pins once into registers (the degree checks are wave-uniform in the
-// sorted list); larger ones re-read their pins in each of the three passes.
-// Workgroup totals to partial[blockIdx.x].
+// One row of C float32 coordinates.
+template <int C>
+__device__ __forceinline__ void load_row(const float* p, float* v) {
+    if constexpr (C == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int h = 0; h < C / 4; ++h) {
+            const float4 t = reinterpret_cast<const float4*>(p)[h];
+            v[4 * h] = t.x;
+            v[4 * h + 1] = t.y;
+            v[4 * h + 2] = t.z;
+            v[4 * h + 3] = t.w;
+        }
+    }
+}
+
+// The D pins from p0 (indexes past the net's last pin p1 - 1 are clamped to
+// it) of a net: node rows and offsets, every load issued before any is used.
+template <int C, int D>
+__device__ __forceinline__ void gather_pins(const float* __restrict__ pos, const int32_t* __restrict__ pin_node,
+                                            const float* __restrict__ pin_off, int p0, int p1, float (&v)[D][C],
+                                            float2 (&off)[D]) {
+    int node[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int p = p0 + k < p1 ? p0 + k : p1 - 1;
+        node[k] = pin_node[p];
+        off[k] = reinterpret_cast<const float2*>(pin_off)[p];
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) load_row<C>(pos + static_cast<int64_t>(node[k]) * C, v[k]);
+}
+
+__device__ __forceinline__ double coord(const float (&v), float2 off, int c) {
+    return static_cast<double>(v) + static_cast<double>((c & 1) ? off.y : off.x);
+}
+
+// A net of d <= D pins (D the wave's bound), its pins in registers: per
+// column pair the extremes (clamped repeats of the last pin change no
+// extreme), the shifted sums over its d pins, the pair's WA term, and each
+// pin's gradient from the weights already taken (1/sp and 1/sm once per net
+// and column).
+template <int P, int D>
+__device__ __forceinline__ void wa_net_regs(const float* __restrict__ pos, const int32_t* __restrict__ pin_node,
+                                            const float* __restrict__ pin_off, int p0, int d, double inv_g,
+                                            double* tot, double* __restrict__ pin_g) {
+    constexpr int C = 2 * P;
+    float v[D][C];
+    float2 off[D];
+    gather_pins<C, D>(pos, pin_node, pin_off, p0, p0 + d, v, off);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        double hi[2], lo[2], sp[2], tp[2], sm[2], tm[2];
+        float ep[D][2], em[D][2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            hi[c] = -1e300;
+            lo[c] = 1e300;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double x = coord(v[k][2 * q + c], off[k], c);
+                hi[c] = x > hi[c] ? x : hi[c];
+                lo[c] = x < lo[c] ? x : lo[c];
+            }
+            sp[c] = tp[c] = sm[c] = tm[c] = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double x = coord(v[k][2 * q + c], off[k], c);
+                ep[k][c] = expf(static_cast<float>((x - hi[c]) * inv_g));
+                em[k][c] = expf(static_cast<float>((lo[c] - x) * inv_g));
+                if (k < d) {
+                    sp[c] += ep[k][c];
+                    tp[c] += x * ep[k][c];
+                    sm[c] += em[k][c];
+                    tm[c] += x * em[k][c];
+                }
+            }
+        }
+        tot[q] += (tp[0] / sp[0] - tm[0] / sm[0]) + (tp[1] / sp[1] - tm[1] / sm[1]);
+        if (!pin_g) continue;
+        double rsp[2], rsm[2], xp[2], xm[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            rsp[c] = 1.0 / sp[c];
+            rsm[c] = 1.0 / sm[c];
+            xp[c] = tp[c] * rsp[c];
+            xm[c] = tm[c] * rsm[c];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            if (k < d) {
+                double g[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const double x = coord(v[k][2 * q + c], off[k], c);
+                    const double pp = static_cast<double>(ep[k][c]) * rsp[c], pm = static_cast<double>(em[k][c]) * rsm[c];
+                    g[c] = pp * (1.0 + (x - xp[c]) * inv_g) - pm * (1.0 - (x - xm[c]) * inv_g);
+                }
+                *reinterpret_cast<double2*>(pin_g + static_cast<int64_t>(p0 + k) * C + 2 * q) = make_double2(g[0], g[1]);
+            }
+    }
+}
+
+// A net of more than kReg pins (up to a wave's worth): kReg pins at a time
+// (loads clamped and all in flight), three passes per column pair --
+// extremes, shifted sums, gradients.
+template <int P>
+__device__ __forceinline__ void wa_net_loop(const float* __restrict__ pos, const int32_t* __restrict__ pin_node,
+                                            const float* __restrict__ pin_off, int p0, int d, double inv_g,
+                                            double* tot, double* __restrict__ pin_g) {
+    constexpr int C = 2 * P, D = kReg;
+    const int p1 = p0 + d;
+    double hi[C], lo[C], sp[C], tp[C], sm[C], tm[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        hi[c] = -1e300;
+        lo[c] = 1e300;
+        sp[c] = tp[c] = sm[c] = tm[c] = 0;
+    }
+    float v[D][C];
+    float2 off[D];
+    for (int b = p0; b < p1; b += D) {
+        gather_pins<C, D>(pos, pin_node, pin_off, b, p1, v, off);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double x = coord(v[k][c], off[k], c);
+                hi[c] = x > hi[c] ? x : hi[c];
+                lo[c] = x < lo[c] ? x : lo[c];
+            }
+    }
+    for (int b = p0; b < p1; b += D) {
+        gather_pins<C, D>(pos, pin_node, pin_off, b, p1, v, off);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            if (b + k < p1)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const double x = coord(v[k][c], off[k], c);
+                    const double ep = wexp((x - hi[c]) * inv_g), em = wexp((lo[c] - x) * inv_g);
+                    sp[c] += ep;
+                    tp[c] += x * ep;
+                    sm[c] += em;
+                    tm[c] += x * em;
+                }
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        tot[q] += (tp[2 * q] / sp[2 * q] - tm[2 * q] / sm[2 * q]) + (tp[2 * q + 1] / sp[2 * q + 1] - tm[2 * q + 1] / sm[2 * q + 1]);
+    if (!pin_g) return;
+    ColAcc a[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[c] = ColAcc{hi[c], lo[c], sp[c], tp[c], sm[c], tm[c]};
+    for (int b = p0; b < p1; b += D) {
+        gather_pins<C, D>(pos, pin_node, pin_off, b, p1, v, off);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            if (b + k < p1)
+#pragma unroll
+                for (int q = 0; q < P; ++q)
+                    *reinterpret_cast<double2*>(pin_g + static_cast<int64_t>(b + k) * C + 2 * q) =
+                        make_double2(gpin(coord(v[k][2 * q], off[k], 0), a[2 * q], inv_g),
+                                     gpin(coord(v[k][2 * q + 1], off[k], 1), a[2 * q + 1], inv_g));
+    }
+}
+
+// One net per thread.  The list is sorted by degree, so the lanes of a wave
+// hold nets of about one degree: the wave's largest degree picks how many
+// pins each lane gathers at once (2, 3, 4 or kReg in registers; more than
+// kReg in passes).  Workgroup totals to partial[blockIdx.x].
 template <int P>
 __global__ void __launch_bounds__(kBT) k_wa_small(const float* __restrict__ pos, int ncols,
                                                   const int32_t* __restrict__ net_ptr,
@@ -137,91 +306,19 @@ __global__ void __launch_bounds__(kBT) k_wa_small(const float* __restrict__ pos,
     double tot[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) tot[q] = 0;
+    int p0 = 0, d = 0;
     if (i < n_list) {
         const int e = list[i];
-        const int p0 = net_ptr[e], d = net_ptr[e + 1] - p0;
-        if (d <= kReg) {
-            int node[kReg];
-            float off[kReg][2], v[kReg][2];
-#pragma unroll
-            for (int k = 0; k < kReg; ++k)
-                if (k < d) {
-                    node[k] = pin_node[p0 + k];
-                    off[k][0] = pin_off[2 * (p0 + k)];
-                    off[k][1] = pin_off[2 * (p0 + k) + 1];
-                }
-#pragma unroll 1
-            for (int q = 0; q < P; ++q) {
-                ColAcc a[2] = {{-1e300, 1e300, 0, 0, 0, 0}, {-1e300, 1e300, 0, 0, 0, 0}};
-#pragma unroll
-                for (int k = 0; k < kReg; ++k)
-                    if (k < d) {
-                        const float* r = pos + static_cast<int64_t>(node[k]) * ncols + 2 * q;
-                        v[k][0] = r[0];
-                        v[k][1] = r[1];
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) {
-                            const double x = static_cast<double>(v[k][c]) + static_cast<double>(off[k][c]);
-                            a[c].hi = x > a[c].hi ? x : a[c].hi;
-                            a[c].lo = x < a[c].lo ? x : a[c].lo;
-                        }
-                    }
-#pragma unroll
-                for (int k = 0; k < kReg; ++k)
-                    if (k < d) {
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) {
-                            const double x = static_cast<double>(v[k][c]) + static_cast<double>(off[k][c]);
-                            const double ep = wexp((x - a[c].hi) * inv_g), em = wexp((a[c].lo - x) * inv_g);
-                            a[c].sp += ep;
-                            a[c].tp += x * ep;
-                            a[c].sm += em;
-                            a[c].tm += x * em;
-                        }
-                    }
-                const double wq = (a[0].tp / a[0].sp - a[0].tm / a[0].sm) + (a[1].tp / a[1].sp - a[1].tm / a[1].sm);
-#pragma unroll
-                for (int j = 0; j < P; ++j) tot[j] += j == q ? wq : 0.0;
-                if (pin_g) {
-#pragma unroll
-                    for (int k = 0; k < kReg; ++k)
-                        if (k < d) {
-                            const double x0 = static_cast<double>(v[k][0]) + static_cast<double>(off[k][0]);
-                            const double x1 = static_cast<double>(v[k][1]) + static_cast<double>(off[k][1]);
-                            *reinterpret_cast<double2*>(pin_g + static_cast<int64_t>(p0 + k) * ncols + 2 * q) =
-                                make_double2(gpin(x0, a[0], inv_g), gpin(x1, a[1], inv_g));
-                        }
-                }
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < P; ++q) {
-                ColAcc a[2] = {{-1e300, 1e300, 0, 0, 0, 0}, {-1e300, 1e300, 0, 0, 0, 0}};
-                for (int p = p0; p < p0 + d; ++p)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const double x = pin_coord(pos, ncols, pin_node, pin_off, p, 2 * q + c);
-                        a[c].hi = x > a[c].hi ? x : a[c].hi;
-                        a[c].lo = x < a[c].lo ? x : a[c].lo;
-                    }
-                for (int p = p0; p < p0 + d; ++p)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const double x = pin_coord(pos, ncols, pin_node, pin_off, p, 2 * q + c);
-                        const double ep = wexp((x - a[c].hi) * inv_g), em = wexp((a[c].lo - x) * inv_g);
-                        a[c].sp += ep;
-                        a[c].tp += x * ep;
-                        a[c].sm += em;
-                        a[c].tm += x * em;
-                    }
-                tot[q] += (a[0].tp / a[0].sp - a[0].tm / a[0].sm) + (a[1].tp / a[1].sp - a[1].tm / a[1].sm);
-                if (pin_g)
-                    for (int p = p0; p < p0 + d; ++p)
-                        *reinterpret_cast<double2*>(pin_g + static_cast<int64_t>(p) * ncols + 2 * q) =
-                            make_double2(gpin(pin_coord(pos, ncols, pin_node, pin_off, p, 2 * q), a[0], inv_g),
-                                         gpin(pin_coord(pos, ncols, pin_node, pin_off, p, 2 * q + 1), a[1], inv_g));
-            }
-        }
+        p0 = net_ptr[e];
+        d = net_ptr[e + 1] - p0;
+    }
+    const int dmax = wave_max(d);
+    if (d > 0) {
+        if (dmax <= 2) wa_net_regs<P, 2>(pos, pin_node, pin_off, p0, d, inv_g, tot, pin_g);
+        else if (dmax <= 3) wa_net_regs<P, 3>(pos, pin_node, pin_off, p0, d, inv_g, tot, pin_g);
+        else if (dmax <= 4) wa_net_regs<P, 4>(pos, pin_node, pin_off, p0, d, inv_g, tot, pin_g);
+        else if (dmax <= kReg) wa_net_regs<P, kReg>(pos, pin_node, pin_off, p0, d, inv_g, tot, pin_g);
+        else wa_net_loop<P>(pos, pin_node, pin_off, p0, d, inv_g, tot, pin_g);
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -354,10 +451,29 @@ __global__ void __launch_bounds__(kBT) k_wa_nodes(const int32_t* __restrict__ no
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0;
     const int k0 = node_ptr[v], k1 = node_ptr[v + 1];
-    for (int k = k0; k < k1; ++k) {
-        const double* g = pin_g + static_cast<int64_t>(node_pins[k]) * C;
+    // kB pins at a time, every load in flight (indexes clamped to the last
+    // pin; the repeats are not added)
+    constexpr int kB = 4;
+    for (int b = k0; b < k1; b += kB) {
+        int pin[kB];
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] += llrint(g[c] * kFix);
+        for (int u = 0; u < kB; ++u) pin[u] = node_pins[b + u < k1 ? b + u : k1 - 1];
+        double g[kB][C];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const double2* r = reinterpret_cast<const double2*>(pin_g + static_cast<int64_t>(pin[u]) * C);
+#pragma unroll
+            for (int h = 0; h < C / 2; ++h) {
+                const double2 t = r[h];
+                g[u][2 * h] = t.x;
+                g[u][2 * h + 1] = t.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u)
+            if (b + u < k1)
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] += llrint(g[u][c] * kFix);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) grad[v * C + c] = static_cast<float>(static_cast<double>(acc[c]) * kUnfix);
