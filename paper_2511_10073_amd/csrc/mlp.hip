@@ -338,15 +338,25 @@ __global__ void k_feature_row(LearnArgs a) {
         make_float4(rf.y, rf.z, static_cast<float>(lsr), 0.f);
 }
 
-// Column statistics over movable instance rows (two passes, fixed grid,
-// float64 partials added in a fixed order).  The first pass sums h3 and
-// (h0 - h3)^2 (mean of h3, rms of h0 - h3), the second (h3 - mean)^2.
+// Column statistics over movable instance rows in one pass (fixed grid,
+// float64 partials added in a fixed order): per column the sums of h3 - c
+// and (h3 - c)^2, with c the column's value at execution row 0 (a shift that
+// lies inside the data, so the variance E[(h3-c)^2] - E[h3-c]^2 loses few
+// digits), and of (h0 - h3)^2.
 constexpr int kStatGrid = 512;
 
 template <int C>
-__global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, const float* __restrict__ mean, double* __restrict__ part) {
+__global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, double* __restrict__ part) {
     __shared__ double red[kBT / kWave];
-    constexpr int W = 2 * C + 1;
+    constexpr int W = 3 * C + 1;
+    double shift[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) shift[c] = 0;
+    if (a.n_inst > 0) {
+        const float inv_s0 = a.rowf[0].x;
+#pragma unroll
+        for (int c = 0; c < C; ++c) shift[c] = unscale(a.z3, C, 0, c, inv_s0, a.in, a.perm);
+    }
     double acc[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) acc[c] = 0;
@@ -358,16 +368,13 @@ __global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, const float* __res
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const double h = unscale(a.z3, C, static_cast<int>(r), c, inv_s, a.in, a.perm);
-            if (mean) {
-                const double d = h - mean[c];
-                acc[c] += d * d;
-            } else {
-                const double d0 = unscale(a.z0, C, static_cast<int>(r), c, inv_s, a.in, a.perm) - h;
-                acc[c] += h;
-                acc[C + c] += d0 * d0;
-            }
+            const double d = h - shift[c];
+            const double d0 = unscale(a.z0, C, static_cast<int>(r), c, inv_s, a.in, a.perm) - h;
+            acc[c] += d;
+            acc[C + c] += d * d;
+            acc[2 * C + c] += d0 * d0;
         }
-        acc[2 * C] += 1.0;
+        acc[3 * C] += 1.0;
     }
 #pragma unroll
     for (int c = 0; c < W; ++c) {
@@ -376,27 +383,35 @@ __global__ void __launch_bounds__(kBT) k_colstat(LearnArgs a, const float* __res
     }
 }
 
-// stats [3][C]: the first pass gives the mean (row 0) and the rms of h0 - h3
-// (row 2), the second the standard deviation (row 1); a zero deviation or
-// rms becomes 1.
+// stats [3][C]: mean and standard deviation of h3, rms of h0 - h3 (a zero
+// deviation or rms becomes 1).  One workgroup: each thread adds a fixed
+// stride of the partials in order, then a fixed block reduction.
 template <int C>
-__global__ void k_colstat_final(const double* __restrict__ part, float* __restrict__ stats, int second) {
-    constexpr int W = 2 * C + 1;
-    int c = threadIdx.x;
-    if (c >= C) return;
-    double s = 0, q = 0, n = 0;
-    for (int b = 0; b < kStatGrid; ++b) {
-        s += part[b * W + c];
-        q += part[b * W + C + c];
-        n += part[b * W + 2 * C];
-    }
-    if (!second) {
-        stats[c] = n > 0 ? static_cast<float>(s / n) : 0.f;
-        const double rms = n > 0 ? sqrt(q / n) : 0.0;
-        stats[2 * C + c] = rms > 0 ? static_cast<float>(rms) : 1.f;
-    } else {
-        const double sd = n > 0 ? sqrt(s / n) : 0.0;
+__global__ void __launch_bounds__(kBT) k_colstat_final(LearnArgs a, const double* __restrict__ part,
+                                                       float* __restrict__ stats) {
+    __shared__ double red[kBT / kWave];
+    constexpr int W = 3 * C + 1;
+    double tot[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) tot[c] = 0;
+    for (int b = threadIdx.x; b < kStatGrid; b += kBT)
+#pragma unroll
+        for (int c = 0; c < W; ++c) tot[c] += part[static_cast<int64_t>(b) * W + c];
+#pragma unroll
+    for (int c = 0; c < W; ++c) tot[c] = block_sum_f64<kBT>(tot[c], red);
+    if (threadIdx.x != 0) return;
+    const double n = tot[3 * C];
+    const float inv_s0 = a.n_inst > 0 ? a.rowf[0].x : 0.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double shift = a.n_inst > 0 ? unscale(a.z3, C, 0, c, inv_s0, a.in, a.perm) : 0.0;
+        const double m1 = n > 0 ? tot[c] / n : 0.0;
+        const double var = n > 0 ? tot[C + c] / n - m1 * m1 : 0.0;
+        const double sd = var > 0 ? sqrt(var) : 0.0;
+        const double rms = n > 0 ? sqrt(tot[2 * C + c] / n) : 0.0;
+        stats[c] = n > 0 ? static_cast<float>(shift + m1) : 0.f;
         stats[C + c] = sd > 0 ? static_cast<float>(sd) : 1.f;
+        stats[2 * C + c] = rms > 0 ? static_cast<float>(rms) : 1.f;
     }
 }
 
@@ -571,7 +586,7 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     DevBuf<double> part;
     DevBuf<float> stats;
     DevBuf<float4> rowf;
-    part.ensure(static_cast<size_t>(kStatGrid) * (2 * C + 1), s);
+    part.ensure(static_cast<size_t>(kStatGrid) * (3 * C + 1), s);
     stats.ensure(3 * C, s);
     rowf.ensure(static_cast<size_t>(g.n_inst) + 1, s);
     a.stats = stats.p;
@@ -579,13 +594,9 @@ void learned_c(Graph& g, const ahr_filter_spec& spec, const float* params, const
     hipLaunchKernelGGL(k_row_feat, dim3(grid_for(g.n_inst, kBT)), dim3(kBT), 0, s, g.n_inst, g.scale.p, g.deg.p,
                        g.hsum.p, g.perm.p, g.nl.node_flags, rowf.p);
     AHR_LAUNCHED("k_row_feat");
-    hipLaunchKernelGGL((k_colstat<C>), dim3(kStatGrid), dim3(kBT), 0, s, a, static_cast<const float*>(nullptr), part.p);
+    hipLaunchKernelGGL((k_colstat<C>), dim3(kStatGrid), dim3(kBT), 0, s, a, part.p);
     AHR_LAUNCHED("k_colstat");
-    hipLaunchKernelGGL((k_colstat_final<C>), dim3(1), dim3(64), 0, s, part.p, stats.p, 0);
-    AHR_LAUNCHED("k_colstat_final");
-    hipLaunchKernelGGL((k_colstat<C>), dim3(kStatGrid), dim3(kBT), 0, s, a, static_cast<const float*>(stats.p), part.p);
-    AHR_LAUNCHED("k_colstat");
-    hipLaunchKernelGGL((k_colstat_final<C>), dim3(1), dim3(64), 0, s, part.p, stats.p, 1);
+    hipLaunchKernelGGL((k_colstat_final<C>), dim3(1), dim3(kBT), 0, s, a, part.p, stats.p);
     AHR_LAUNCHED("k_colstat_final");
     if (stats_out) AHR_HIP(hipMemcpyAsync(stats_out, stats.p, 3 * C * sizeof(float), hipMemcpyDeviceToDevice, s));
     {
