@@ -116,6 +116,14 @@ struct DevWord {
     int wide;
 };
 void read_words(std::initializer_list<DevWord> src, int64_t* out, hipStream_t s);
+// The same read split in two, so that work queued between the halves runs
+// while the host waits: read_scalars_begin gathers up to 8 int32 values on
+// stream s into the device's pinned words (a second set, kept apart from
+// the synchronous reads) and records an event; read_scalars_end waits for
+// that event alone and copies the values out.  One read in flight per
+// device and host thread.
+void read_scalars_begin(const std::vector<const int32_t*>& src, hipStream_t s);
+void read_scalars_end(int32_t* host, int n);
 // One device scalar (synchronises the stream).
 int32_t read_i32(const int32_t* src, hipStream_t s);
 int64_t read_i64(const int64_t* src, hipStream_t s);

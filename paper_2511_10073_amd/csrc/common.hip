@@ -591,13 +591,22 @@ __global__ void k_gather_scalars(PtrPack src, int n, int64_t* dst) {
 
 namespace {
 
+// 16 pinned words per device and host thread: 0..7 for synchronous reads,
+// 8..15 for the split read.
 int64_t* host_words(int dev) {
     static thread_local int64_t* buf[64] = {nullptr};
     if (dev < 0 || dev >= 64) throw Error{AHR_EDEVICE, "device ordinal out of range"};
-    if (!buf[dev]) AHR_HIP(hipHostMalloc(reinterpret_cast<void**>(&buf[dev]), 8 * sizeof(int64_t),
+    if (!buf[dev]) AHR_HIP(hipHostMalloc(reinterpret_cast<void**>(&buf[dev]), 16 * sizeof(int64_t),
                                          hipHostMallocCoherent));
     return buf[dev];
 }
+
+struct SplitRead {
+    int dev = -1;
+    hipEvent_t ev = nullptr;
+    int n = 0;
+};
+thread_local SplitRead g_split;
 
 void read_words(const PtrPack& pk, int n, int64_t* out, hipStream_t s) {
     int dev = 0;
@@ -610,6 +619,32 @@ void read_words(const PtrPack& pk, int n, int64_t* out, hipStream_t s) {
 }
 
 }  // namespace
+
+void read_scalars_begin(const std::vector<const int32_t*>& src, hipStream_t s) {
+    if (src.size() > 8) throw Error{AHR_EDEVICE, "read_scalars_begin: at most 8"};
+    int dev = 0;
+    AHR_HIP(hipGetDevice(&dev));
+    if (g_split.ev && g_split.dev != dev) {
+        AHR_HIP(hipEventDestroy(g_split.ev));
+        g_split.ev = nullptr;
+    }
+    if (!g_split.ev)     // a system-scope release: the host reads what the gather wrote
+        AHR_HIP(hipEventCreateWithFlags(&g_split.ev, hipEventDisableTiming | hipEventReleaseToSystem));
+    g_split.dev = dev;
+    PtrPack pk{};
+    for (size_t k = 0; k < src.size(); ++k) pk.p[k] = src[k];
+    g_split.n = static_cast<int>(src.size());
+    hipLaunchKernelGGL(k_gather_scalars, dim3(1), dim3(64), 0, s, pk, g_split.n, host_words(dev) + 8);
+    AHR_LAUNCHED("k_gather_scalars");
+    AHR_HIP(hipEventRecord(g_split.ev, s));
+}
+
+void read_scalars_end(int32_t* host, int n) {
+    if (!g_split.ev || n > g_split.n) throw Error{AHR_EDEVICE, "read_scalars_end without its begin"};
+    AHR_HIP(hipEventSynchronize(g_split.ev));
+    const int64_t* hw = host_words(g_split.dev) + 8;
+    for (int k = 0; k < n; ++k) host[k] = static_cast<int32_t>(hw[k]);
+}
 
 void read_words(std::initializer_list<DevWord> src, int64_t* out, hipStream_t s) {
     if (src.size() == 0) return;

@@ -1589,36 +1589,47 @@ void expand_batch_c(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, 
 
 }  // namespace
 
-void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,
-                 DevBuf<int64_t>& scan_tmp, hipStream_t s) {
+// Row classes in two halves around the read of their counts: the first
+// launches the flags, scans and the read; whatever the caller queues before
+// the second runs while the host waits for the counts.
+struct RowClassScratch {
     DevBuf<int32_t> is_long, rank, nch, cscan;
+};
+
+static void row_classes_begin(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst,
+                              RowClassScratch& t, DevBuf<int64_t>& scan_tmp, hipStream_t s) {
     const size_t n1 = static_cast<size_t>(N) + 1;
-    is_long.ensure(n1, s);
-    nch.ensure(n1, s);
-    hipLaunchKernelGGL(k_row_chunks, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, net_rp, hint_rp, is_long.p, nch.p);
+    t.is_long.ensure(n1, s);
+    t.nch.ensure(n1, s);
+    hipLaunchKernelGGL(k_row_chunks, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, N, net_rp, hint_rp, t.is_long.p,
+                       t.nch.p);
     AHR_LAUNCHED("k_row_chunks");
-    rank.ensure(n1, s);
-    cscan.ensure(n1, s);
+    t.rank.ensure(n1, s);
+    t.cscan.ensure(n1, s);
     scan_tmp.ensure(scan_tmp_elems(N), s);
-    scan_i32_to_i32(is_long.p, rank.p, N, scan_tmp.p, s);
-    scan_i32_to_i32(nch.p, cscan.p, N, scan_tmp.p, s);
-    int32_t t[8];
-    read_scalars({rank.p + N, rank.p + n_inst, cscan.p + N, cscan.p + n_inst, net_rp + n_inst, hint_rp + n_inst,
-                  net_rp + N, hint_rp + N},
-                 t, s);
-    rc.nnz_net_all = t[6];
-    rc.nnz_hint_all = t[7];
-    rc.n_long = t[0];
-    rc.n_long_inst = t[1];
-    rc.n_chunks = t[2];
-    rc.n_chunks_inst = t[3];
-    rc.nnz_inst = static_cast<int64_t>(t[4]) + t[5];
+    scan_i32_to_i32(t.is_long.p, t.rank.p, N, scan_tmp.p, s);
+    scan_i32_to_i32(t.nch.p, t.cscan.p, N, scan_tmp.p, s);
+    read_scalars_begin({t.rank.p + N, t.rank.p + n_inst, t.cscan.p + N, t.cscan.p + n_inst, net_rp + n_inst,
+                        hint_rp + n_inst, net_rp + N, hint_rp + N},
+                       s);
+}
+
+static void row_classes_end(int32_t N, RowClasses& rc, RowClassScratch& t, hipStream_t s) {
+    int32_t v[8];
+    read_scalars_end(v, 8);
+    rc.nnz_net_all = v[6];
+    rc.nnz_hint_all = v[7];
+    rc.n_long = v[0];
+    rc.n_long_inst = v[1];
+    rc.n_chunks = v[2];
+    rc.n_chunks_inst = v[3];
+    rc.nnz_inst = static_cast<int64_t>(v[4]) + v[5];
     rc.has_rb = 0;
     rc.long_rows.ensure(static_cast<size_t>(rc.n_long) + 1, s);
-    list_rows(is_long.p, rank.p, N, rc.long_rows.p, s);
+    list_rows(t.is_long.p, t.rank.p, N, rc.long_rows.p, s);
     rc.long_chunk0.ensure(static_cast<size_t>(rc.n_long) + 1, s);
     hipLaunchKernelGGL(k_long_chunk0, dim3(grid_for(static_cast<int64_t>(rc.n_long) + 1, kBT)), dim3(kBT), 0, s,
-                       rc.n_long, rc.long_rows.p, cscan.p, rc.n_chunks, rc.long_chunk0.p);
+                       rc.n_long, rc.long_rows.p, t.cscan.p, rc.n_chunks, rc.long_chunk0.p);
     AHR_LAUNCHED("k_long_chunk0");
     rc.chunk_row.ensure(static_cast<size_t>(rc.n_chunks) + 1, s);
     if (rc.n_long) {
@@ -1627,10 +1638,17 @@ void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32
         AHR_LAUNCHED("k_chunk_rows");
     }
     rc.partial.ensure(static_cast<size_t>(rc.n_chunks) * 8 + 8, s);
-    is_long.release(s);
-    rank.release(s);
-    nch.release(s);
-    cscan.release(s);
+    t.is_long.release(s);
+    t.rank.release(s);
+    t.nch.release(s);
+    t.cscan.release(s);
+}
+
+void row_classes(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,
+                 DevBuf<int64_t>& scan_tmp, hipStream_t s) {
+    RowClassScratch t;
+    row_classes_begin(net_rp, hint_rp, N, n_inst, t, scan_tmp, s);
+    row_classes_end(N, rc, t, s);
 }
 
 void row_blocks(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst, RowClasses& rc,
@@ -1769,12 +1787,10 @@ void normalise_degrees(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     // netlist rows' lengths and the hint entries only
     RowRef m{g.xnet_rp.p, nullptr, g.xhint_rp.p, g.xhint_ent.p};
 
-    if (g.rows_version != g.hint_version) {
-        row_classes(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, g.rc, g.scan_tmp, s);
-        g.rows_version = g.hint_version;
-        g.nnz_net = static_cast<int32_t>(g.rc.nnz_net_all);
-        g.nnz_hint = static_cast<int32_t>(g.rc.nnz_hint_all);
-    }
+    // the row classes' counts are read while the short rows' degrees run
+    RowClassScratch rct;
+    const bool new_rows = g.rows_version != g.hint_version;
+    if (new_rows) row_classes_begin(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, rct, g.scan_tmp, s);
 
     const double sigma = spec.sigma;
     g.deg.ensure(static_cast<size_t>(N) + 1, s);
@@ -1793,6 +1809,12 @@ void normalise_degrees(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
                            r0, N, cell_blocks, m, g.xqdeg.p, g.xhabs.p, g.xhsg.p, sigma, g.deg.p, g.scale.p,
                            g.hsum.p);
         AHR_LAUNCHED("k_deg_rows");
+    }
+    if (new_rows) {
+        row_classes_end(N, g.rc, rct, s);
+        g.rows_version = g.hint_version;
+        g.nnz_net = static_cast<int32_t>(g.rc.nnz_net_all);
+        g.nnz_hint = static_cast<int32_t>(g.rc.nnz_hint_all);
     }
     if (g.rc.n_long) {
         hipLaunchKernelGGL(k_chunk_absdeg, dim3(g.rc.n_chunks), dim3(kBT), 0, s, m, g.rc.long_rows.p, g.rc.chunk_row.p,
