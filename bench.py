@@ -330,7 +330,8 @@ def gift_line(A, torch, np, N, nl, net, reps):
     (k, sigma) = (2, 2), (2, 4), (4, 4) on the netlist graph from uniformly
     sampled movable positions, as one initializer would start.  Times one
     graph build (no hints, execution order from the sampled placement) and
-    the bank call; hop bytes from the profiled call."""
+    the bank call; hop bytes from the profiled call.  Then the same in the
+    netlist's execution order, which such a placement cannot give."""
     G = torch.as_tensor(N.uniform_signal(nl, nl["g0"].shape[1], 1505)).cuda()
     p = A.hint_params(flags=0)
     spec = A.gift_spec()
@@ -358,10 +359,29 @@ def gift_line(A, torch, np, N, nl, net, reps):
     torch.cuda.synchronize()
     build_ms = 1e3 * (time.perf_counter() - t0) / 3
     ms = ev[0].elapsed_time(ev[1]) / reps
+    # the same call in the netlist's Cuthill-McKee order (AHR_LAYOUT_NETLIST)
+    pn = A.hint_params(flags=A.LAYOUT_NETLIST)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        g2 = A.Graph(net, pn, G)
+        g2.close()
+    torch.cuda.synchronize()
+    nbuild_ms = 1e3 * (time.perf_counter() - t0) / 3
+    gr = A.Graph(net, pn, G)
+    gr.gift(spec, G, out=out)
+    ev[2].record()
+    for _ in range(reps):
+        gr.gift(spec, G, out=out)
+    ev[3].record()
+    torch.cuda.synchronize()
+    gr.close()
+    nms = ev[2].elapsed_time(ev[3]) / reps
     return {"bank": {"k": [2, 2, 4], "sigma": [2.0, 4.0, 4.0], "alpha": [0.2, 0.3, 0.5]},
             "ms": round(ms, 4), "graph_build_ms": round(build_ms, 3), "hop_launches": prof["hop_launches"],
             "hop_bytes": int(prof["hop_bytes"]), "hop_gbs": round(prof["hop_bytes"] / (ms * 1e-3) / 1e9, 1),
-            "hop_only_gbs": round(prof["hop_bytes"] / (prof["hop_ms"] * 1e-3) / 1e9, 1) if prof["hop_ms"] else None}
+            "hop_only_gbs": round(prof["hop_bytes"] / (prof["hop_ms"] * 1e-3) / 1e9, 1) if prof["hop_ms"] else None,
+            "netlist_order": {"ms": round(nms, 4), "graph_build_ms": round(nbuild_ms, 3),
+                              "hop_gbs": round(prof["hop_bytes"] / (nms * 1e-3) / 1e9, 1)}}
 
 
 def pipeline_line(A, torch, np, N, nl, net, params, spec, rounds, gamma, steps):

@@ -84,6 +84,20 @@ typedef struct ahr_netlist {
 #define AHR_MACRO_HINTS 2u        /* Section V, macro virtual nodes               */
 #define AHR_BIN_HINTS 4u          /* Section V, bin virtual nodes                 */
 #define AHR_ALL_HINTS 7u
+/* Execution order of the filter (performance only; results do not depend on
+ * it beyond float32 summation order).  By default the instances follow the
+ * Hilbert curve of the first placement the graph sees.  AHR_LAYOUT_NETLIST
+ * makes them follow a Cuthill-McKee order of the netlist's
+ * instance-to-instance edges instead (graphs with n_inst < 2^22; larger ones
+ * keep the Hilbert order); AHR_LAYOUT_AUTO takes that order only where fewer
+ * than a quarter of a sample of those edges join rows within n_inst/64 rows
+ * (at least 256) of each other in the Hilbert order.  The netlist order costs
+ * about 2 ms per graph build at 2.2M cells and halves the hop's time where
+ * the placement carries no locality, so it pays where one graph is filtered
+ * several times from such a placement.  ahr_graph_info.layout reports the
+ * order taken. */
+#define AHR_LAYOUT_AUTO 8u
+#define AHR_LAYOUT_NETLIST 16u
 
 /* Area-hint parameters (Section V; the refinement block of the paper's
  * parameter table: refine_num_bin_xy, detection_ratio, bin_capacity). */
@@ -93,7 +107,8 @@ typedef struct ahr_hint_params {
     float bin_capacity;         /* C in phi_b = 2 sigmoid(mu (D_b - C)) - 1 */
     float mu;                   /* mu > 0 */
     int32_t clique_max;         /* nets with 2 <= p <= clique_max are cliques, larger ones stars; >= 1 */
-    uint32_t flags;             /* AHR_EXPAND_MACRO_PINS | AHR_MACRO_HINTS | AHR_BIN_HINTS */
+    uint32_t flags;             /* AHR_EXPAND_MACRO_PINS | AHR_MACRO_HINTS | AHR_BIN_HINTS,
+                                   at most one of AHR_LAYOUT_AUTO, AHR_LAYOUT_NETLIST */
     float prune_tau;            /* sparsification (Section IX, "Further speedups"; reading: an edge's
                                    salience is its weight over the cell's baseWeight): bin edges with
                                    exp(-maxRatio) |phi_b| below prune_tau are left out, both directions,
@@ -144,7 +159,7 @@ typedef struct ahr_graph_info {
     int32_t n_hint_cells;       /* movable standard cells that carry hint edges */
     int32_t n_long_rows;        /* rows the filter splits over several workgroups */
     int32_t hint_version;       /* incremented by every hint (re)build */
-    int32_t reserved;
+    int32_t layout;             /* execution order: 0 positions (Hilbert), 1 netlist (Cuthill-McKee) */
     int64_t ws_bytes;           /* the caller's workspace (0: the library's pool) */
     int64_t ws_peak;            /* most of it in use at once so far */
 } ahr_graph_info;

@@ -284,6 +284,7 @@ struct Graph {
     // execution layout: instance, macro pin and star rows each in spatial
     // order inside their id range (perm: exec -> id); virtual rows unmoved
     int32_t has_layout = 0;
+    int32_t layout_netlist = 0;   // the instances took the netlist (Cuthill-McKee) order
     DevBuf<int32_t> perm, iperm;  // [n_tot]: identity on the virtual rows
     DevBuf<int4> xmpin;           // [n_mpin] per execution macro pin row: owner, offset x, y (float bits)
     DevBuf<int32_t> xstar_net;    // [n_star] per execution star row: its net

@@ -125,7 +125,10 @@ ahr_status check_hints(const ahr_hint_params* hp) {
     if (!(hp->mu > 0.f) || !std::isfinite(hp->mu)) return fail(AHR_EINVAL, "mu must be positive");
     if (!std::isfinite(hp->bin_capacity)) return fail(AHR_EINVAL, "bin_capacity must be finite");
     if (hp->clique_max < 1) return fail(AHR_EINVAL, "clique_max must be >= 1");
-    if (hp->flags & ~AHR_ALL_HINTS) return fail(AHR_EINVAL, "unknown hint flags");
+    if (hp->flags & ~(AHR_ALL_HINTS | AHR_LAYOUT_AUTO | AHR_LAYOUT_NETLIST))
+        return fail(AHR_EINVAL, "unknown hint flags");
+    if ((hp->flags & AHR_LAYOUT_AUTO) && (hp->flags & AHR_LAYOUT_NETLIST))
+        return fail(AHR_EINVAL, "AHR_LAYOUT_AUTO and AHR_LAYOUT_NETLIST exclude each other");
     if (!(hp->prune_tau >= 0.f && hp->prune_tau <= 1.f)) return fail(AHR_EINVAL, "prune_tau in [0, 1]");
     return AHR_OK;
 }
@@ -295,6 +298,7 @@ ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
         info->n_hint_cells = g->n_hint_cells;
         info->n_long_rows = g->rc.n_long;
         info->hint_version = g->hint_version;
+        info->layout = g->layout_netlist;
         info->ws_bytes = static_cast<int64_t>(ahr::arena_size(g->arena));
         info->ws_peak = static_cast<int64_t>(ahr::arena_peak(g->arena));
         return AHR_OK;

@@ -35,6 +35,16 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+template <class T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
 // Inclusive scan over the wave.
 __device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t v) {
     int l = lane_id();

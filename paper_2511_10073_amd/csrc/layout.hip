@@ -20,6 +20,18 @@
 // placement); the hint rows are built in it directly.  The canonical netlist
 // CSR stays for export; the order is set once per graph from the first
 // placement seen.
+//
+// A placement whose positions say little about the netlist (uniformly
+// drawn ones, or a low-order smoothing of them) gives a Hilbert order with
+// no locality.  On request (AHR_LAYOUT_NETLIST) the instances take a
+// netlist order instead: Cuthill-McKee levels over the instance-to-instance
+// netlist edges (star and macro pin nodes left out, since a big net reaches
+// across the die), a node's rank following its lowest-ranked parent,
+// siblings in id order; macro pin and star rows follow the lowest rank among
+// their instance neighbours.  With AHR_LAYOUT_AUTO the Hilbert order is kept
+// when at least a quarter of a sample of its instance-to-instance entries lie
+// within n_inst/64 rows (at least 256) of their row (a random order puts
+// about 1/32 of them there), else the netlist order is taken.
 #include "ahr_internal.hpp"
 #include "device_util.hpp"
 
@@ -282,13 +294,302 @@ __global__ void k_long_flags(int32_t n_tot, const int32_t* __restrict__ xrp, int
 }
 
 
+// ---------------------------------------------------------------- netlist order
+
+constexpr int kCmGrid = 1024;       // workgroups of the level kernels (grid-stride over the level)
+constexpr int kSample = 16;         // every kSample-th instance row is tested
+
+struct CmArgs {
+    int32_t n_inst;
+    const int64_t* off;    // canonical netlist rows: off, merged length, columns
+    const int32_t* len;
+    const int32_t* col;
+    unsigned long long* lk;  // [n_inst] BFS level (high word) above the rank of the
+                             // lowest-ranked parent; all ones while unvisited
+    int32_t* rank;         // [n_inst] position in the order, -1 unplaced
+    int32_t* order;        // [n_inst] rank -> instance
+    int32_t* cnt;          // [n_inst] children per rank (the current level's ranks)
+    const int32_t* scn;    // exclusive scan of cnt ([n_inst] + total)
+    int32_t* bnd;          // [0] lo, [1] hi: ranks of the current level; [2] start node
+};
+
+__global__ void k_cm_init(CmArgs a) {
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v < a.n_inst) {
+        a.lk[v] = ~0ull;
+        a.rank[v] = -1;
+        a.cnt[v] = 0;
+    }
+    if (v == 0) a.bnd[2] = INT32_MAX;
+}
+
+// The start: the lowest instance with an instance neighbour (one atomic per
+// wave).
+__global__ void __launch_bounds__(kBT) k_cm_start(CmArgs a) {
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int best = INT32_MAX;
+    if (v < a.n_inst) {
+        const int64_t o = a.off[v];
+        const int l = a.len[v];
+        for (int k = 0; k < l; ++k)
+            if (a.col[o + k] < a.n_inst) {
+                best = static_cast<int>(v);
+                break;
+            }
+    }
+    best = wave_min(best);
+    // (a wave whose candidate cannot lower the current one skips the atomic:
+    // the start is nearly always among the first ids)
+    if (lane_id() == 0 && best < __hip_atomic_load(&a.bnd[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin(&a.bnd[2], best);
+}
+
+__global__ void k_cm_seed(CmArgs a) {
+    int v0 = a.bnd[2];
+    if (v0 == INT32_MAX) v0 = 0;            // no instance edges: the order is the id order
+    a.lk[v0] = 0ull;
+    a.rank[v0] = 0;
+    a.order[0] = v0;
+    a.bnd[0] = 0;
+    a.bnd[1] = 1;
+}
+
+// The level kernels give each row of the level kCmLanes lanes, which take
+// its entries in turn; the rows of a level are strided over the grid.
+constexpr int kCmLanes = 8;
+
+// The packed word of a node of level k + 1 whose lowest-ranked parent is rank i.
+__device__ __forceinline__ unsigned long long cm_word(int32_t k, int64_t i) {
+    return (static_cast<unsigned long long>(k + 1) << 32) | static_cast<unsigned>(i);
+}
+
+__device__ __forceinline__ bool cm_child(const CmArgs& a, int c, int32_t k, int64_t i) {
+    return c < a.n_inst && a.lk[c] == cm_word(k, i);
+}
+
+// Level k (ranks [lo, hi)): every unvisited instance neighbour joins level
+// k + 1 and keeps the lowest rank among its parents, both by one 64-bit
+// minimum (an earlier level's word is below every level k + 1 word, an
+// unvisited node's above).
+__global__ void __launch_bounds__(256) k_cm_expand(CmArgs a, int32_t k) {
+    const int lo = a.bnd[0], hi = a.bnd[1];
+    const int ln = threadIdx.x & (kCmLanes - 1);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * (blockDim.x / kCmLanes);
+    for (int64_t i = lo + (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kCmLanes; i < hi;
+         i += stride) {
+        const int u = a.order[i];
+        const int64_t o = a.off[u];
+        const int l = a.len[u];
+        const unsigned long long w = cm_word(k, i);
+        for (int j = ln; j < l; j += kCmLanes) {
+            const int c = a.col[o + j];
+            if (c < a.n_inst && a.lk[c] > w) atomicMin(&a.lk[c], w);
+        }
+    }
+}
+
+// Children of each rank of the level: its neighbours whose lowest parent it is.
+__global__ void __launch_bounds__(256) k_cm_count(CmArgs a, int32_t k) {
+    const int lo = a.bnd[0], hi = a.bnd[1];
+    const int ln = threadIdx.x & (kCmLanes - 1);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * (blockDim.x / kCmLanes);
+    for (int64_t i = lo + (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kCmLanes; i < hi;
+         i += stride) {
+        const int u = a.order[i];
+        const int64_t o = a.off[u];
+        const int l = a.len[u];
+        int n = 0;
+        for (int j = ln; j < l; j += kCmLanes) n += cm_child(a, a.col[o + j], k, i) ? 1 : 0;
+#pragma unroll
+        for (int m = kCmLanes / 2; m > 0; m >>= 1) n += __shfl_xor(n, m);   // the row's lanes
+        if (ln == 0) a.cnt[i] = n;
+    }
+}
+
+// Ranks of level k + 1: the children of rank i follow those of the ranks
+// before it, each parent's in ascending id (its row is column-sorted; the
+// row's lanes place each batch of kCmLanes entries by a ballot).
+__global__ void __launch_bounds__(256) k_cm_assign(CmArgs a, int32_t k) {
+    const int lo = a.bnd[0], hi = a.bnd[1];
+    const int base0 = a.scn[lo];
+    const int ln = threadIdx.x & (kCmLanes - 1);
+    const int gb = lane_id() & ~(kCmLanes - 1);              // the row's first lane in the wave
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * (blockDim.x / kCmLanes);
+    for (int64_t i = lo + (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kCmLanes; i < hi;
+         i += stride) {
+        const int u = a.order[i];
+        const int64_t o = a.off[u];
+        const int l = a.len[u];
+        int r = hi + (a.scn[i] - base0);
+        for (int j0 = 0; j0 < l; j0 += kCmLanes) {
+            const int j = j0 + ln;
+            int c = 0;
+            bool f = false;
+            if (j < l) {
+                c = a.col[o + j];
+                f = cm_child(a, c, k, i);
+            }
+            const unsigned gm = static_cast<unsigned>(__ballot(f) >> gb) & ((1u << kCmLanes) - 1u);
+            if (f) {
+                const int p = r + __popc(gm & ((1u << ln) - 1u));
+                a.rank[c] = p;
+                a.order[p] = c;
+            }
+            r += __popc(gm);
+        }
+    }
+}
+
+// The next level's rank range.
+__global__ void k_cm_next(CmArgs a) {
+    const int lo = a.bnd[0], hi = a.bnd[1];
+    const int nchild = a.scn[hi] - a.scn[lo];
+    a.bnd[0] = hi;
+    a.bnd[1] = hi + nchild;
+}
+
+// Instances the levels never reached (other components, isolated ones):
+// after the reached ones, in id order.
+__global__ void k_cm_unplaced(int32_t n, const int32_t* __restrict__ rank, int32_t* __restrict__ flag) {
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v < n) flag[v] = rank[v] < 0 ? 1 : 0;
+}
+
+__global__ void k_cm_append(int32_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                            const int32_t* __restrict__ bnd, int32_t* __restrict__ rank) {
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v < n && flag[v]) rank[v] = bnd[1] + pos[v];
+}
+
+// Sort keys of the netlist order (24 bits: range above the rank): an
+// instance's own rank, a macro pin's or star's lowest instance-neighbour
+// rank (n_inst if none; one wave per such row); low 12 bits to `lo`.
+__global__ void k_cm_keys(int32_t n_inst, const int32_t* __restrict__ rank, int32_t* __restrict__ key,
+                          int32_t* __restrict__ lo) {
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= n_inst) return;
+    const int k = rank[v];
+    key[v] = k;
+    lo[v] = k & 0xfff;
+}
+
+__global__ void __launch_bounds__(kBT) k_cm_keys_aux(int32_t n_inst, int32_t np, int32_t first_star,
+                                                     const int64_t* __restrict__ off,
+                                                     const int32_t* __restrict__ len,
+                                                     const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ rank, int32_t* __restrict__ key,
+                                                     int32_t* __restrict__ lo) {
+    const int64_t v = n_inst + (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+    if (v >= np) return;                                   // wave-uniform
+    const int64_t o = off[v];
+    const int l = len[v];
+    int r = n_inst;
+    for (int j = lane_id(); j < l; j += kWave) {
+        const int c = col[o + j];
+        if (c < n_inst) r = rank[c] < r ? rank[c] : r;
+    }
+    r = wave_min(r);
+    if (lane_id() == 0) {
+        const int k = ((v < first_star ? 1 : 2) << 22) | r;
+        key[v] = k;
+        lo[v] = k & 0xfff;
+    }
+}
+
+__global__ void k_hi12(int32_t n, const int32_t* __restrict__ key, const int32_t* __restrict__ order,
+                       int32_t* __restrict__ hi) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j < n) hi[j] = key[order[j]] >> 12;
+}
+
+// Locality of a layout: of a sample of instance rows (every kSample-th
+// instance), how many instance-to-instance entries lie within `near`
+// execution rows of their row; [0] near, [1] all.
+__global__ void __launch_bounds__(kBT) k_near_count(int32_t n_inst, int32_t nearw, const int64_t* __restrict__ off,
+                             const int32_t* __restrict__ len,
+                             const int32_t* __restrict__ col, const int32_t* __restrict__ iperm,
+                             unsigned long long* __restrict__ tally) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t v = t * kSample;
+    unsigned long long near = 0, all = 0;
+    if (v < n_inst) {
+        const int rv = iperm[v];
+        const int64_t o = off[v];
+        const int l = len[v];
+        for (int j = 0; j < l; ++j) {
+            const int c = col[o + j];
+            if (c >= n_inst) continue;
+            const int d = iperm[c] - rv;
+            near += (d <= nearw && d >= -nearw) ? 1 : 0;
+            ++all;
+        }
+    }
+    __shared__ unsigned long long red[2][kBT / kWave];
+    near = wave_sum(near);
+    all = wave_sum(all);
+    if (lane_id() == 0) {
+        red[0][wave_id()] = near;
+        red[1][wave_id()] = all;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBT / kWave; ++w) {
+            near += red[0][w];
+            all += red[1][w];
+        }
+        if (all) {
+            atomicAdd(&tally[0], near);
+            atomicAdd(&tally[1], all);
+        }
+    }
+}
+
+__global__ void k_fill_u64_2(unsigned long long* p) {
+    if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
+}
+
 }  // namespace
 
 static void exec_net_copy(Graph& g, int32_t N, hipStream_t s2);
 
-void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
+// Two stable LSD passes over np keys (low digit `digit`, then key >> lo_bits
+// of that order) into `out`; ties keep node order.
+static void sort_keys(Graph& g, DevBuf<int32_t>& key, DevBuf<int32_t>& digit, int32_t np, int lo_bits, int hi_bits,
+                      hipStream_t s) {
+    DevBuf<int32_t> first, second;
+    bucket_sort(g, digit.p, np, 1 << lo_bits, first, g.lay_start, s, false);
+    if (lo_bits == kDigitBits)
+        hipLaunchKernelGGL(k_high_digit, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, key.p, first.p, digit.p);
+    else
+        hipLaunchKernelGGL(k_hi12, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, key.p, first.p, digit.p);
+    AHR_LAUNCHED("k_high_digit");
+    bucket_sort(g, digit.p, np, 1 << hi_bits, second, g.lay_start, s, false);
+    hipLaunchKernelGGL(k_compose, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, first.p, second.p, key.p);
+    AHR_LAUNCHED("k_compose");
+    first.release(s);
+    second.release(s);
+}
+
+// perm from the sorted order in `key` (instance windows by row length,
+// macro pins and stars as sorted), then iperm.
+static void finish_perm(Graph& g, DevBuf<int32_t>& key, hipStream_t s) {
     const int32_t n = g.n_inst, N = g.n_tot, np = g.first_mvirt;
-    DevBuf<int32_t> key, digit, first, second;
+    g.perm.ensure(static_cast<size_t>(N) + 1, s);
+    hipLaunchKernelGGL(k_window_sort, dim3(grid_for(n, kLenWindow)), dim3(kLenWindow), 0, s, n, key.p, g.net_len.p,
+                       g.perm.p);
+    AHR_LAUNCHED("k_window_sort");
+    if (np > n)
+        AHR_HIP(hipMemcpyAsync(g.perm.p + n, key.p + n, static_cast<size_t>(np - n) * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, s));
+    g.iperm.ensure(static_cast<size_t>(N) + 1, s);
+    hipLaunchKernelGGL(k_iperm, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, g.perm.p, np, N, g.iperm.p);
+    AHR_LAUNCHED("k_iperm");
+}
+
+// The Hilbert order of the placement's positions.
+static void position_order(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
+    const int32_t n = g.n_inst, np = g.first_mvirt;
+    DevBuf<int32_t> key, digit;
     key.ensure(static_cast<size_t>(np) + 1, s);
     digit.ensure(static_cast<size_t>(np) + 1, s);
     const float side = static_cast<float>(1 << kGridBits);
@@ -310,30 +611,113 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     ka.sy = side / (g.nl.die[3] - g.nl.die[1]);
     hipLaunchKernelGGL(k_layout_keys, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, ka, key.p, digit.p);
     AHR_LAUNCHED("k_layout_keys");
-    // LSD radix sort, both passes stable: by the low digit, then by the high
-    // digit of that order; ties keep node order.  The range bits keep the
-    // instances, macro pins and stars in their own id ranges.
-    bucket_sort(g, digit.p, np, 1 << kDigitBits, first, g.lay_start, s, false);
-    hipLaunchKernelGGL(k_high_digit, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, key.p, first.p, digit.p);
-    AHR_LAUNCHED("k_high_digit");
-    bucket_sort(g, digit.p, np, 1 << (kKeyBits - kDigitBits), second, g.lay_start, s, false);
-    g.perm.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_compose, dim3(grid_for(np, kBT)), dim3(kBT), 0, s, np, first.p, second.p, key.p);
-    AHR_LAUNCHED("k_compose");
-    // instance windows by row length; macro pins and stars as sorted
-    hipLaunchKernelGGL(k_window_sort, dim3(grid_for(n, kLenWindow)), dim3(kLenWindow), 0, s, n, key.p, g.net_len.p,
-                       g.perm.p);
-    AHR_LAUNCHED("k_window_sort");
-    if (np > n)
-        AHR_HIP(hipMemcpyAsync(g.perm.p + n, key.p + n, static_cast<size_t>(np - n) * sizeof(int32_t),
-                               hipMemcpyDeviceToDevice, s));
+    // the range bits keep the instances, macro pins and stars in their own id ranges
+    sort_keys(g, key, digit, np, kDigitBits, kKeyBits - kDigitBits, s);
+    finish_perm(g, key, s);
     key.release(s);
     digit.release(s);
-    first.release(s);
-    second.release(s);
-    g.iperm.ensure(static_cast<size_t>(N) + 1, s);
-    hipLaunchKernelGGL(k_iperm, dim3(grid_for(N, kBT)), dim3(kBT), 0, s, g.perm.p, np, N, g.iperm.p);
-    AHR_LAUNCHED("k_iperm");
+}
+
+// Whether the current layout's instance rows sit near their instance
+// neighbours: at least a quarter of a sample of entries within n/64 rows.
+static bool layout_is_local(Graph& g, hipStream_t s) {
+    const int32_t n = g.n_inst;
+    DevBuf<unsigned long long> tally;
+    tally.ensure(2, s);
+    hipLaunchKernelGGL(k_fill_u64_2, dim3(1), dim3(64), 0, s, tally.p);
+    AHR_LAUNCHED("k_fill_u64_2");
+    const int64_t nt = (static_cast<int64_t>(n) + kSample - 1) / kSample;
+    const int32_t nearw = n / 64 > 256 ? n / 64 : 256;
+    hipLaunchKernelGGL(k_near_count, dim3(grid_for(nt, kBT)), dim3(kBT), 0, s, n, nearw, g.net_off.p, g.net_len.p,
+                       g.net_col.p, g.iperm.p, tally.p);
+    AHR_LAUNCHED("k_near_count");
+    int64_t w[2];
+    read_words({{reinterpret_cast<const int64_t*>(tally.p), 1}, {reinterpret_cast<const int64_t*>(tally.p) + 1, 1}},
+               w, s);
+    tally.release(s);
+    return w[1] == 0 || 4 * w[0] >= w[1];
+}
+
+// Cuthill-McKee ranks of the instances (see the file's comment), then the
+// netlist order of all instance, macro pin and star rows.
+constexpr int kCmMaxLevels = 256;     // beyond that, the rest is appended in id order
+constexpr int kCmCheck = 8;           // levels between reads of the level range
+
+static void netlist_order(Graph& g, hipStream_t s) {
+    const int32_t n = g.n_inst, np = g.first_mvirt;
+    DevBuf<unsigned long long> lk;
+    DevBuf<int32_t> rank, order, cnt, scn, bnd;
+    const size_t n1 = static_cast<size_t>(n) + 1;
+    lk.ensure(n1, s);
+    rank.ensure(n1, s);
+    order.ensure(n1, s);
+    cnt.ensure(n1, s);
+    scn.ensure(n1, s);
+    bnd.ensure(4, s);
+    g.scan_tmp.ensure(scan_tmp_elems(n), s);
+    CmArgs a{n, g.net_off.p, g.net_len.p, g.net_col.p, lk.p, rank.p, order.p, cnt.p, scn.p, bnd.p};
+    hipLaunchKernelGGL(k_cm_init, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, a);
+    AHR_LAUNCHED("k_cm_init");
+    hipLaunchKernelGGL(k_cm_start, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, a);
+    AHR_LAUNCHED("k_cm_start");
+    hipLaunchKernelGGL(k_cm_seed, dim3(1), dim3(1), 0, s, a);
+    AHR_LAUNCHED("k_cm_seed");
+    for (int k = 0; k < kCmMaxLevels; ++k) {
+        hipLaunchKernelGGL(k_cm_expand, dim3(kCmGrid), dim3(256), 0, s, a, k);
+        AHR_LAUNCHED("k_cm_expand");
+        hipLaunchKernelGGL(k_cm_count, dim3(kCmGrid), dim3(256), 0, s, a, k);
+        AHR_LAUNCHED("k_cm_count");
+        scan_i32_to_i32(cnt.p, scn.p, n, g.scan_tmp.p, s);
+        hipLaunchKernelGGL(k_cm_assign, dim3(kCmGrid), dim3(256), 0, s, a, k);
+        AHR_LAUNCHED("k_cm_assign");
+        hipLaunchKernelGGL(k_cm_next, dim3(1), dim3(1), 0, s, a);
+        AHR_LAUNCHED("k_cm_next");
+        if ((k + 1) % kCmCheck == 0) {
+            int32_t lh[2];
+            read_scalars({bnd.p, bnd.p + 1}, lh, s);
+            if (lh[0] == lh[1]) break;
+        }
+    }
+    // the unreached instances after the reached ones
+    hipLaunchKernelGGL(k_cm_unplaced, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, n, rank.p, cnt.p);
+    AHR_LAUNCHED("k_cm_unplaced");
+    scan_i32_to_i32(cnt.p, scn.p, n, g.scan_tmp.p, s);
+    hipLaunchKernelGGL(k_cm_append, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, n, cnt.p, scn.p, bnd.p, rank.p);
+    AHR_LAUNCHED("k_cm_append");
+    lk.release(s);
+    order.release(s);
+    cnt.release(s);
+    scn.release(s);
+    bnd.release(s);
+    // sort keys: range, then rank (24 bits, two 12-bit passes)
+    DevBuf<int32_t> skey, digit;
+    skey.ensure(static_cast<size_t>(np) + 1, s);
+    digit.ensure(static_cast<size_t>(np) + 1, s);
+    hipLaunchKernelGGL(k_cm_keys, dim3(grid_for(n, kBT)), dim3(kBT), 0, s, n, rank.p, skey.p, digit.p);
+    AHR_LAUNCHED("k_cm_keys");
+    if (np > n) {
+        hipLaunchKernelGGL(k_cm_keys_aux, dim3(grid_for(static_cast<int64_t>(np - n) * kWave, kBT)), dim3(kBT), 0,
+                           s, n, np, g.first_star, g.net_off.p, g.net_len.p, g.net_col.p, rank.p, skey.p, digit.p);
+        AHR_LAUNCHED("k_cm_keys_aux");
+    }
+    rank.release(s);
+    sort_keys(g, skey, digit, np, 12, 12, s);
+    finish_perm(g, skey, s);
+    skey.release(s);
+    digit.release(s);
+}
+
+void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
+    const int32_t n = g.n_inst, N = g.n_tot, np = g.first_mvirt;
+    const uint32_t fl = g.hp.flags;
+    const bool cm_ok = n < (1 << 22);           // ranks fit the netlist order's 22-bit keys
+    bool netlist = cm_ok && (fl & AHR_LAYOUT_NETLIST);
+    if (!netlist) {
+        position_order(g, pos, ncols, s);
+        if (cm_ok && (fl & AHR_LAYOUT_AUTO) && !layout_is_local(g, s)) netlist = true;
+    }
+    if (netlist) netlist_order(g, s);
+    g.layout_netlist = netlist ? 1 : 0;
 
     DevBuf<int32_t> len;
     len.ensure(static_cast<size_t>(N) + 1, s);

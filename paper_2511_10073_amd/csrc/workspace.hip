@@ -16,9 +16,9 @@
 //   rows N + macro pin nodes + star nodes + macro and bin virtual nodes:
 //        row pointers, layout, degrees, scales, hop coefficients, row
 //        classes and the filter's signal buffers (about 11 C floats a row);
-//   per instance, pin and net: the hint build's per-cell arrays (with the
-//        pruning's kept-slot mask), the refinement's three placements, pin
-//        maps and net lists.
+//   per instance, pin and net: the netlist order's level arrays, the hint
+//        build's per-cell arrays (with the pruning's kept-slot mask), the
+//        refinement's three placements, pin maps and net lists.
 // A 25 % margin covers the sub-allocator's fragmentation.
 #include <cmath>
 
@@ -105,7 +105,7 @@ size_t graph_workspace_bytes(const ahr_netlist& nl, const ahr_hint_params& hp, i
     const double H = 2 * ((mh ? 4 * cells : 0.0) + (bh ? cells * wslots : 0.0));
     const double rows = static_cast<double>(N) + mpin + stars + (mh ? macros : 0.0) + B;
     const double C = ncols > 0 ? ncols : 8;
-    const double bytes = 48 * raw + 40 * H + (176 + 44 * C) * rows + (264 + 12 * C) * static_cast<double>(N) +
+    const double bytes = 48 * raw + 40 * H + (176 + 44 * C) * rows + (296 + 12 * C) * static_cast<double>(N) +
                          64 * static_cast<double>(P) + 48 * static_cast<double>(E) + 16 * B * wslots + 40 * B;
     return static_cast<size_t>(1.25 * bytes) + (size_t(32) << 20);
 }
