@@ -73,12 +73,26 @@ __device__ __forceinline__ void vstore(float* p, const Vec<C>& r) {
     }
 }
 
-// A first-hop record: a row's C signal columns, then its scale, padded to a
-// power of two so that a record never straddles a cache line.
+// A first-hop record: a row's C signal columns, then its scale, with no
+// padding (C + 1 floats, 4-byte aligned).  Padding to a power of two kept
+// every record inside one cache line but made the records' footprint, which
+// the first hop gathers from, nearly twice the signal's; the tight records
+// cost a second line for a few of them and fewer lines in all.
 template <int C>
 constexpr int pack_width() {
     static_assert(C <= 4, "first-hop records hold at most 4 columns");
-    return C == 1 ? 2 : (C == 2 ? 4 : 8);
+    return C + 1;
+}
+
+// W floats at a 4-byte aligned address (a record, or its columns).
+template <int W>
+struct alignas(4) Floats {
+    float v[W];
+};
+
+template <int W>
+__device__ __forceinline__ Floats<W> load_floats(const float* p) {
+    return *reinterpret_cast<const Floats<W>*>(p);
 }
 
 // ---------------------------------------------------------------- row classes
@@ -430,10 +444,11 @@ __device__ __forceinline__ void put_z(const ExpandArgs& a, int r, Vec<C> x, floa
     if constexpr (C <= 4) {
         if (a.zpk) {
             constexpr int W = pack_width<C>();
-            Vec<W> rec;
+            Floats<W> rec;
 #pragma unroll
-            for (int c = 0; c < W; ++c) rec.v[c] = c < C ? z.v[c] : (c == C ? s : 0.f);
-            vstore<W>(a.zpk + row * W, rec);
+            for (int c = 0; c < C; ++c) rec.v[c] = z.v[c];
+            rec.v[C] = s;
+            *reinterpret_cast<Floats<W>*>(a.zpk + row * W) = rec;
             if (a.band0) vstore<C>(a.acc + row * C, t);
             return;
         }
@@ -982,26 +997,20 @@ __global__ void __launch_bounds__(kBT) k_hop_rb(HopArgs a0) {
 // When lambda_up is the Gershgorin bound and not yet known, the first hop
 // also forms every row's Gershgorin sum sum_j |A_ij| s_j while it streams
 // the entries, so the bound costs no pass of its own.  The expansion writes
-// each row's z and s side by side in one record, so that one cache line
-// serves both gathers.  The hop's epilogue needs lambda_up, so the rows' neighbour sums are
+// each row's z and s side by side in one record, so that one gather (nearly
+// always one cache line) serves both.  The hop's epilogue needs lambda_up, so the rows' neighbour sums are
 // stored unscaled in zout and the epilogue runs after the bound is reduced
 // (k_hop1_epi).  Entry order, clamping and sums are those of k_hop and of
 // k_gersh_short / k_chunk_gersh, so the results are the same bits.
 
-// z_j and s_j of a first-hop record (one cache line).
+// z_j and s_j of a first-hop record.
 template <int C>
 __device__ __forceinline__ void load_record(const float* zpk, int j, Vec<C>& z, float& sc) {
     constexpr int W = pack_width<C>();
-    const float* rec = zpk + static_cast<int64_t>(j) * W;
-    if constexpr (W <= 4) {
-        const Vec<W> r = vload<W>(rec);
+    const Floats<W> r = load_floats<W>(zpk + static_cast<int64_t>(j) * W);
 #pragma unroll
-        for (int c = 0; c < C; ++c) z.v[c] = r.v[c];
-        sc = r.v[C];
-    } else {
-        z = vload<C>(rec);
-        sc = rec[C];
-    }
+    for (int c = 0; c < C; ++c) z.v[c] = r.v[c];
+    sc = r.v[C];
 }
 
 template <int C, int U>
@@ -1208,7 +1217,11 @@ __global__ void __launch_bounds__(kBT) k_hop1_epi(HopArgs a, const float* __rest
     } else if (a.coef) {
         ops.k = a.coef[r];
     }
-    ops.z = vload<C>(zpk + static_cast<int64_t>(r) * pack_width<C>());
+    {
+        const Floats<C> zr = load_floats<C>(zpk + static_cast<int64_t>(r) * pack_width<C>());
+#pragma unroll
+        for (int c = 0; c < C; ++c) ops.z.v[c] = zr.v[c];
+    }
     if (a.band == 2) ops.acc = vload<C>(a.acc + static_cast<int64_t>(r) * C);
     ops.inst = r;          // never the last hop
     ops.flag = 0;
