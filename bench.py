@@ -35,8 +35,8 @@ HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("fil
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "sources_sha256": "646d488cda3753083e8519ebe50109b5c8bb9f8acb4cd2a65d4739fd09c61e49",
-               "bytes_per_launch": 1419239714,
+               "sources_sha256": "1a8c5943121874dee90fc47392f33549cf0bbeb39d8b2550b458cac9241e15d7",
+               "bytes_per_launch": 1419304608,
                "source": "profiles/k_hop_large-2.2M_l2_fabric_traffic.md"}
 
 
