@@ -160,6 +160,9 @@ typedef struct ahr_graph_info {
     int32_t n_long_rows;        /* rows the filter splits over several workgroups */
     int32_t hint_version;       /* incremented by every hint (re)build */
     int32_t layout;             /* execution order: 0 positions (Hilbert), 1 netlist (Cuthill-McKee) */
+    int32_t hop_lanes;          /* the hop's launch shape for this graph under AHR_HOP_AUTO (4 or
+                                   AHR_HOP_ROW_BLOCK); 0 until its first filter call */
+    int32_t reserved;
     int64_t ws_bytes;           /* the caller's workspace (0: the library's pool) */
     int64_t ws_peak;            /* most of it in use at once so far */
 } ahr_graph_info;
@@ -465,8 +468,17 @@ ahr_status ahr_memory_trim(void);
  * 1151 entries) streams the block's entries with coalesced loads, stages
  * the weighted products in LDS and adds each row's products in entry
  * order.  Each setting is deterministic; settings differ from each other
- * in the last bits only (the summation order of a row changes). */
+ * in the last bits only (the summation order of a row changes).
+ * lanes_per_row = AHR_HOP_AUTO (the default) picks per graph: 4 lanes where
+ * the execution order is local (at least a quarter of a sample of the
+ * instance-to-instance entries lie within n_inst/64 rows, at least 256, of
+ * their row), else the row-block form, which keeps more of the gathers in
+ * flight when most of them miss the caches (at 2.2M cells, 521 against 597
+ * us per hop in the order of GiFt's output, 268 against 254 us in a local
+ * order).  The first hop of a filter call that forms the Gershgorin bound
+ * always uses 4 lanes. */
 #define AHR_HOP_ROW_BLOCK 256     /* lanes_per_row value selecting the row-block hop */
+#define AHR_HOP_AUTO 1024         /* lanes_per_row value: the shape follows each graph's order */
 ahr_status ahr_filter_tune(int32_t lanes_per_row, int32_t nontemporal);
 ahr_status ahr_filter_get_tune(int32_t* lanes_per_row, int32_t* nontemporal);
 

@@ -25,6 +25,7 @@ ALL_HINTS = 7
 LAYOUT_AUTO = 8             # netlist order where the placement's Hilbert order has no locality
 LAYOUT_NETLIST = 16         # the Cuthill-McKee order of the netlist
 HOP_ROW_BLOCK = 256       # lanes_per_row value selecting the row-block hop
+HOP_AUTO = 1024           # lanes_per_row value: the shape follows each graph's execution order
 LAMBDA_GERSHGORIN = 0
 LAMBDA_FIXED = 1
 
@@ -92,7 +93,8 @@ def macro_charge(netlist, g, cp, out=None, stream=None):
 class _GraphInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "n_inst", "n_tot", "first_mpin", "first_star", "first_mvirt", "first_bvirt", "nnz_net", "nnz_hint",
-        "n_hint_cells", "n_long_rows", "hint_version", "layout")] + [("ws_bytes", ctypes.c_int64),
+        "n_hint_cells", "n_long_rows", "hint_version", "layout", "hop_lanes", "reserved")] + [
+            ("ws_bytes", ctypes.c_int64),
                                                                         ("ws_peak", ctypes.c_int64)]
 
 

@@ -285,6 +285,11 @@ struct Graph {
     // order inside their id range (perm: exec -> id); virtual rows unmoved
     int32_t has_layout = 0;
     int32_t layout_netlist = 0;   // the instances took the netlist (Cuthill-McKee) order
+    // locality of the execution order (set with the layout, read with the
+    // first row classes): 1 local, 0 not, -1 not read yet
+    int32_t hop_local = -1;
+    DevBuf<unsigned long long> loc_tally;   // [2] sampled entries near their row, all sampled entries
+    DevBuf<int32_t> loc_flag;               // [1] the verdict on the device
     DevBuf<int32_t> perm, iperm;  // [n_tot]: identity on the virtual rows
     DevBuf<int4> xmpin;           // [n_mpin] per execution macro pin row: owner, offset x, y (float bits)
     DevBuf<int32_t> xstar_net;    // [n_star] per execution star row: its net

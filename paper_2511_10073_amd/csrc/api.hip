@@ -42,8 +42,9 @@ Graph::~Graph() {
     DevBuf<int32_t>* i32[] = {&pin_node_x, &mpin_owner, &mpin_pin, &star_net, &macro_ids, &net_len, &net_col,
                               &big_nets, &cell_bin, &bin_start, &bin_cells, &bm_start, &bm_list, &hint_cnt,
                               &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart,
-                              &big_stars, &i32a, &i32b, &counter, &kept};
+                              &big_stars, &i32a, &i32b, &counter, &kept, &loc_flag};
     for (auto* b : i32) b->release(s);
+    loc_tally.release(s);
     keep_mask.release(s);
     net_q.release(s);
     net_off.release(s);
@@ -299,6 +300,8 @@ ahr_status ahr_graph_get_info(const ahr_graph* h, ahr_graph_info* info) {
         info->n_long_rows = g->rc.n_long;
         info->hint_version = g->hint_version;
         info->layout = g->layout_netlist;
+        info->hop_lanes = g->hop_local < 0 ? 0 : (g->hop_local ? 4 : AHR_HOP_ROW_BLOCK);
+        info->reserved = 0;
         info->ws_bytes = static_cast<int64_t>(ahr::arena_size(g->arena));
         info->ws_peak = static_cast<int64_t>(ahr::arena_peak(g->arena));
         return AHR_OK;
@@ -658,10 +661,11 @@ ahr_status ahr_mlp_adam(float* params, float* m, float* v, const float* grad, in
 
 ahr_status ahr_filter_tune(int32_t lanes_per_row, int32_t nontemporal) {
     if (lanes_per_row != 0) {
-        if (lanes_per_row != AHR_HOP_ROW_BLOCK &&
+        if (lanes_per_row != AHR_HOP_ROW_BLOCK && lanes_per_row != AHR_HOP_AUTO &&
             (lanes_per_row < 1 || lanes_per_row > 64 || (lanes_per_row & (lanes_per_row - 1))))
             return fail(AHR_EINVAL,
-                        "lanes_per_row must be a power of two in [1, 64], AHR_HOP_ROW_BLOCK, or 0 to keep it");
+                        "lanes_per_row must be a power of two in [1, 64], AHR_HOP_ROW_BLOCK, AHR_HOP_AUTO, "
+                        "or 0 to keep it");
         ahr::g_hop_lanes = lanes_per_row;
     }
     if (nontemporal >= 0) ahr::g_hop_nt = nontemporal ? 1 : 0;

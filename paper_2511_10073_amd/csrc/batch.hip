@@ -251,7 +251,7 @@ void enqueue(Batch& b, const ExpandArgs* desc, const ahr_filter_spec& spec, cons
 }
 
 void config_for(const Batch& b, int32_t C, int& lanes, int& ct) {
-    lanes = b.lanes[C] ? b.lanes[C] : g_hop_lanes;
+    lanes = b.lanes[C] ? b.lanes[C] : (g_hop_lanes == AHR_HOP_AUTO ? 4 : g_hop_lanes);
     ct = b.ct[C] ? b.ct[C] : C;
 }
 

@@ -576,8 +576,8 @@ void list_rows(const int32_t* flags, const int32_t* rank, int32_t n, int32_t* li
 }
 
 struct PtrPack {
-    const void* p[8];
-    int wide[8];    // 8-byte source word
+    const void* p[12];
+    int wide[12];   // 8-byte source word
 };
 
 // Small reads go straight into pinned, coherent host memory: one gather
@@ -591,12 +591,12 @@ __global__ void k_gather_scalars(PtrPack src, int n, int64_t* dst) {
 
 namespace {
 
-// 16 pinned words per device and host thread: 0..7 for synchronous reads,
-// 8..15 for the split read.
+// 20 pinned words per device and host thread: 0..7 for synchronous reads,
+// 8..19 for the split read.
 int64_t* host_words(int dev) {
     static thread_local int64_t* buf[64] = {nullptr};
     if (dev < 0 || dev >= 64) throw Error{AHR_EDEVICE, "device ordinal out of range"};
-    if (!buf[dev]) AHR_HIP(hipHostMalloc(reinterpret_cast<void**>(&buf[dev]), 16 * sizeof(int64_t),
+    if (!buf[dev]) AHR_HIP(hipHostMalloc(reinterpret_cast<void**>(&buf[dev]), 20 * sizeof(int64_t),
                                          hipHostMallocCoherent));
     return buf[dev];
 }
@@ -621,7 +621,7 @@ void read_words(const PtrPack& pk, int n, int64_t* out, hipStream_t s) {
 }  // namespace
 
 void read_scalars_begin(const std::vector<const int32_t*>& src, hipStream_t s) {
-    if (src.size() > 8) throw Error{AHR_EDEVICE, "read_scalars_begin: at most 8"};
+    if (src.size() > 12) throw Error{AHR_EDEVICE, "read_scalars_begin: at most 12"};
     int dev = 0;
     AHR_HIP(hipGetDevice(&dev));
     if (g_split.ev && g_split.dev != dev) {

@@ -1604,13 +1604,15 @@ void expand_batch_c(const ExpandArgs* d, const int32_t* blk0, int32_t n_blocks, 
 
 // Row classes in two halves around the read of their counts: the first
 // launches the flags, scans and the read; whatever the caller queues before
-// the second runs while the host waits for the counts.
+// the second runs while the host waits for the counts.  `extra`, when given,
+// is one more device word read with them (to *extra_out).
 struct RowClassScratch {
     DevBuf<int32_t> is_long, rank, nch, cscan;
 };
 
 static void row_classes_begin(const int32_t* net_rp, const int32_t* hint_rp, int32_t N, int32_t n_inst,
-                              RowClassScratch& t, DevBuf<int64_t>& scan_tmp, hipStream_t s) {
+                              RowClassScratch& t, DevBuf<int64_t>& scan_tmp, hipStream_t s,
+                              const int32_t* extra = nullptr) {
     const size_t n1 = static_cast<size_t>(N) + 1;
     t.is_long.ensure(n1, s);
     t.nch.ensure(n1, s);
@@ -1622,14 +1624,17 @@ static void row_classes_begin(const int32_t* net_rp, const int32_t* hint_rp, int
     scan_tmp.ensure(scan_tmp_elems(N), s);
     scan_i32_to_i32(t.is_long.p, t.rank.p, N, scan_tmp.p, s);
     scan_i32_to_i32(t.nch.p, t.cscan.p, N, scan_tmp.p, s);
-    read_scalars_begin({t.rank.p + N, t.rank.p + n_inst, t.cscan.p + N, t.cscan.p + n_inst, net_rp + n_inst,
-                        hint_rp + n_inst, net_rp + N, hint_rp + N},
-                       s);
+    std::vector<const int32_t*> words{t.rank.p + N,  t.rank.p + n_inst, t.cscan.p + N, t.cscan.p + n_inst,
+                                      net_rp + n_inst, hint_rp + n_inst, net_rp + N, hint_rp + N};
+    if (extra) words.push_back(extra);
+    read_scalars_begin(words, s);
 }
 
-static void row_classes_end(int32_t N, RowClasses& rc, RowClassScratch& t, hipStream_t s) {
-    int32_t v[8];
-    read_scalars_end(v, 8);
+static void row_classes_end(int32_t N, RowClasses& rc, RowClassScratch& t, hipStream_t s,
+                            int32_t* extra_out = nullptr) {
+    int32_t v[9];
+    read_scalars_end(v, extra_out ? 9 : 8);
+    if (extra_out) *extra_out = v[8];
     rc.nnz_net_all = v[6];
     rc.nnz_hint_all = v[7];
     rc.n_long = v[0];
@@ -1803,7 +1808,11 @@ void normalise_degrees(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     // the row classes' counts are read while the short rows' degrees run
     RowClassScratch rct;
     const bool new_rows = g.rows_version != g.hint_version;
-    if (new_rows) row_classes_begin(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, rct, g.scan_tmp, s);
+    // the layout's locality verdict rides along with the first counts
+    const bool want_loc = new_rows && g.hop_local < 0 && g.loc_flag.p;
+    if (new_rows)
+        row_classes_begin(g.xnet_rp.p, g.xhint_rp.p, N, g.n_inst, rct, g.scan_tmp, s,
+                          want_loc ? g.loc_flag.p : nullptr);
 
     const double sigma = spec.sigma;
     g.deg.ensure(static_cast<size_t>(N) + 1, s);
@@ -1824,7 +1833,9 @@ void normalise_degrees(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
         AHR_LAUNCHED("k_deg_rows");
     }
     if (new_rows) {
-        row_classes_end(N, g.rc, rct, s);
+        int32_t loc = 1;
+        row_classes_end(N, g.rc, rct, s, want_loc ? &loc : nullptr);
+        if (want_loc) g.hop_local = loc ? 1 : 0;
         g.rows_version = g.hint_version;
         g.nnz_net = static_cast<int32_t>(g.rc.nnz_net_all);
         g.nnz_hint = static_cast<int32_t>(g.rc.nnz_hint_all);
@@ -1871,15 +1882,23 @@ void normalise(Graph& g, const ahr_filter_spec& spec, hipStream_t s) {
     norm_done(g, spec);
 }
 
-int g_hop_lanes = 4;   // lanes per short row (set by the tuner)
-int g_hop_nt = 0;      // non-temporal entry loads
+int g_hop_lanes = AHR_HOP_AUTO;   // lanes per short row (set by the tuner)
+int g_hop_nt = 0;                 // non-temporal entry loads
+
+// The hop's launch shape on graph g: the tuned one, or under AHR_HOP_AUTO 4
+// lanes in a local order and the row-block form in one whose gathers mostly
+// miss (read with the first row classes, so known once g is normalised).
+static int hop_lanes(const Graph& g) {
+    if (g_hop_lanes != AHR_HOP_AUTO) return g_hop_lanes;
+    return g.hop_local == 0 ? AHR_HOP_ROW_BLOCK : 4;
+}
 
 void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* out, int32_t ncols, hipStream_t s) {
-    int lanes = g_hop_lanes;
     // a first filter on new hints with the Gershgorin bound forms the bound
     // in its first hop (4-lane form, at most 4 columns, order >= 2)
-    const bool hop1_bound = !norm_current(g, spec) && spec.lambda_mode != AHR_LAMBDA_FIXED && lanes == 4 &&
-                            ncols <= 4 && spec_kmax(spec, nullptr) >= 2;
+    const bool hop1_bound = !norm_current(g, spec) && spec.lambda_mode != AHR_LAMBDA_FIXED &&
+                            (g_hop_lanes == 4 || g_hop_lanes == AHR_HOP_AUTO) && ncols <= 4 &&
+                            spec_kmax(spec, nullptr) >= 2;
     if (hop1_bound) {
         {
             ProfScope ps(kStageNorm, s);
@@ -1890,6 +1909,7 @@ void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* o
     } else {
         normalise(g, spec, s);
     }
+    const int lanes = hop_lanes(g);
     if (lanes == AHR_HOP_ROW_BLOCK) row_blocks(g.xnet_rp.p, g.xhint_rp.p, g.n_tot, g.n_inst, g.rc, g.scan_tmp, s);
     switch (ncols) {
         case 1: filter_c<1>(g, spec, in, out, lanes, s, hop1_bound); break;
@@ -1903,7 +1923,7 @@ void run_filter(Graph& g, const ahr_filter_spec& spec, const float* in, float* o
 
 void run_hops(Graph& g, const ahr_filter_spec& spec, const float* in, int32_t ncols, hipStream_t s) {
     normalise(g, spec, s);
-    int lanes = g_hop_lanes;
+    const int lanes = hop_lanes(g);
     if (lanes == AHR_HOP_ROW_BLOCK) row_blocks(g.xnet_rp.p, g.xhint_rp.p, g.n_tot, g.n_inst, g.rc, g.scan_tmp, s);
     switch (ncols) {
         case 1: hops_c<1>(g, spec, in, lanes, s); break;

@@ -297,7 +297,7 @@ __global__ void k_long_flags(int32_t n_tot, const int32_t* __restrict__ xrp, int
 // ---------------------------------------------------------------- netlist order
 
 constexpr int kCmGrid = 1024;       // workgroups of the level kernels (grid-stride over the level)
-constexpr int kSample = 16;         // every kSample-th instance row is tested
+constexpr int kSample = 64;         // every kSample-th instance row is tested
 
 struct CmArgs {
     int32_t n_inst;
@@ -548,6 +548,12 @@ __global__ void k_fill_u64_2(unsigned long long* p) {
     if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
 }
 
+// The verdict: local when at least a quarter of the sampled entries are near
+// their row (or nothing was sampled).
+__global__ void k_loc_flag(const unsigned long long* __restrict__ tally, int32_t* __restrict__ flag) {
+    if (threadIdx.x == 0) flag[0] = (tally[1] == 0ull || 4ull * tally[0] >= tally[1]) ? 1 : 0;
+}
+
 }  // namespace
 
 static void exec_net_copy(Graph& g, int32_t N, hipStream_t s2);
@@ -618,24 +624,33 @@ static void position_order(Graph& g, const float* pos, int32_t ncols, hipStream_
     digit.release(s);
 }
 
-// Whether the current layout's instance rows sit near their instance
-// neighbours: at least a quarter of a sample of entries within n/64 rows.
-static bool layout_is_local(Graph& g, hipStream_t s) {
+// The locality test of the current layout, left on the device (g.loc_flag):
+// of a sample of instance rows, the share of instance-to-instance entries
+// within n/64 rows (at least 256) of their row.  g.hop_local is read later.
+static void locality_begin(Graph& g, hipStream_t s) {
     const int32_t n = g.n_inst;
-    DevBuf<unsigned long long> tally;
-    tally.ensure(2, s);
-    hipLaunchKernelGGL(k_fill_u64_2, dim3(1), dim3(64), 0, s, tally.p);
+    g.loc_tally.ensure(2, s);
+    g.loc_flag.ensure(1, s);
+    hipLaunchKernelGGL(k_fill_u64_2, dim3(1), dim3(64), 0, s, g.loc_tally.p);
     AHR_LAUNCHED("k_fill_u64_2");
     const int64_t nt = (static_cast<int64_t>(n) + kSample - 1) / kSample;
     const int32_t nearw = n / 64 > 256 ? n / 64 : 256;
     hipLaunchKernelGGL(k_near_count, dim3(grid_for(nt, kBT)), dim3(kBT), 0, s, n, nearw, g.net_off.p, g.net_len.p,
-                       g.net_col.p, g.iperm.p, tally.p);
+                       g.net_col.p, g.iperm.p, g.loc_tally.p);
     AHR_LAUNCHED("k_near_count");
-    int64_t w[2];
-    read_words({{reinterpret_cast<const int64_t*>(tally.p), 1}, {reinterpret_cast<const int64_t*>(tally.p) + 1, 1}},
-               w, s);
-    tally.release(s);
-    return w[1] == 0 || 4 * w[0] >= w[1];
+    hipLaunchKernelGGL(k_loc_flag, dim3(1), dim3(64), 0, s, g.loc_tally.p, g.loc_flag.p);
+    AHR_LAUNCHED("k_loc_flag");
+    g.hop_local = -1;
+}
+
+// Whether the current layout's instance rows sit near their instance
+// neighbours (the locality test, read now).
+static bool layout_is_local(Graph& g, hipStream_t s) {
+    locality_begin(g, s);
+    int32_t f = 1;
+    read_scalars({g.loc_flag.p}, &f, s);
+    g.hop_local = f ? 1 : 0;
+    return f != 0;
 }
 
 // Cuthill-McKee ranks of the instances (see the file's comment), then the
@@ -712,12 +727,19 @@ void set_layout(Graph& g, const float* pos, int32_t ncols, hipStream_t s) {
     const uint32_t fl = g.hp.flags;
     const bool cm_ok = n < (1 << 22);           // ranks fit the netlist order's 22-bit keys
     bool netlist = cm_ok && (fl & AHR_LAYOUT_NETLIST);
+    bool tested = false;      // the locality test already covers the order taken
     if (!netlist) {
         position_order(g, pos, ncols, s);
-        if (cm_ok && (fl & AHR_LAYOUT_AUTO) && !layout_is_local(g, s)) netlist = true;
+        if (cm_ok && (fl & AHR_LAYOUT_AUTO)) {
+            tested = layout_is_local(g, s);
+            netlist = !tested;
+        }
     }
     if (netlist) netlist_order(g, s);
     g.layout_netlist = netlist ? 1 : 0;
+    // the hop's launch shape follows the order's locality (AHR_HOP_AUTO); the
+    // verdict is read with the first row classes
+    if (!tested) locality_begin(g, s);
 
     DevBuf<int32_t> len;
     len.ensure(static_cast<size_t>(N) + 1, s);

@@ -116,6 +116,30 @@ def test_automatic_choice():
         g.close()
 
 
+def test_hop_shape_follows_locality():
+    """Under AHR_HOP_AUTO (the default) a graph whose execution order is
+    local runs the 4-lane hop, one whose order has no locality (uniformly
+    drawn positions) the row-block hop; either way the filter is the
+    oracle's within 1e-5."""
+    nl = N.generate(N.small(20000, 62, ncols=4))
+    net = A.Netlist(nl)
+    p = U.params32(O.HintParams(nbx=16, nby=16, detection_ratio=0.2))
+    mov = U.movable_rows(nl)
+    assert A.filter_get_tune()[0] == A.HOP_AUTO
+    u = N.uniform_signal(nl, 4, 7)
+    for pos, lanes in ((nl["g0"], 4), (u, A.HOP_ROW_BLOCK)):
+        g = A.Graph(net, U.to_c_params(A, p), torch.as_tensor(pos).cuda())
+        try:
+            assert g.info()["hop_lanes"] == 0              # read with the first normalisation
+            out = g.filter(U.to_c_spec(A, BANK), torch.as_tensor(pos).cuda()).cpu().numpy()
+            assert g.info()["hop_lanes"] == lanes
+        finally:
+            g.close()
+        og = O.build_graph(nl, p, pos[:, :2])
+        err = U.check_filter(out, O.apply_filter(nl, og, BANK, pos), mov)
+        print(f"[hop shape {lanes}] filter rel err {err:.3e}")
+
+
 def test_conflicting_layout_flags_rejected():
     nl = N.generate(N.TINY)
     net = A.Netlist(nl)
