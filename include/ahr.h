@@ -458,8 +458,9 @@ ahr_status ahr_mlp_adam(float* params, float* m, float* v, const float* grad, in
  * frees still in flight. */
 ahr_status ahr_memory_trim(void);
 
-/* Launch shape of the filter's SpMM hop (process-wide; the batched path's
- * autotuner sets it): lanes_per_row in {1, 2, 4, 8, 16, 32, 64} lanes of a
+/* Launch shape of the filter's SpMM hop (process-wide; a batch's own
+ * configuration, ahr_batch_set_config / ahr_batch_autotune, overrides it
+ * for that batch): lanes_per_row in {1, 2, 4, 8, 16, 32, 64} lanes of a
  * wavefront share one row of up to 128 entries (0 keeps the current
  * value); nontemporal = 1 streams the adjacency with non-temporal loads so
  * the L2 keeps the gathered signal rows (-1 keeps the current value).
@@ -529,16 +530,18 @@ ahr_status ahr_batch_get_info(const ahr_batch* b, ahr_batch_info* info);
 ahr_status ahr_batch_filter(ahr_batch* b, const ahr_filter_spec* spec, const float* in, float* out, int32_t ncols,
                             int32_t use_graph, void* stream);
 
-/* Launch shape for ncols columns: lanes_per_row (power of two in [1, 64];
- * 0 = the process-wide ahr_filter_tune value) and col_tile (columns per
- * hop pass: a power of two dividing ncols; 0 = ncols). */
+/* Launch shape for ncols columns: lanes_per_row (power of two in [1, 64] or
+ * AHR_HOP_ROW_BLOCK; 0 = the process-wide ahr_filter_tune value, 4 lanes
+ * when that is AHR_HOP_AUTO) and col_tile (columns per hop pass: a power of
+ * two dividing ncols; 0 = ncols). */
 ahr_status ahr_batch_set_config(ahr_batch* b, int32_t ncols, int32_t lanes_per_row, int32_t col_tile);
 ahr_status ahr_batch_get_config(const ahr_batch* b, int32_t ncols, int32_t* lanes_per_row, int32_t* col_tile);
 
-/* Time every (lanes_per_row in {1..32}, col_tile dividing ncols) on a
- * library-owned input (captured, warmed, mean of 3 replays), keep the
- * fastest as the batch's configuration for ncols and return it (each
- * output pointer may be NULL).  Synchronises on `stream`. */
+/* Time every (lanes_per_row in {1, 2, 4, 8, 16, 32, AHR_HOP_ROW_BLOCK},
+ * col_tile dividing ncols) on a library-owned input (captured, warmed, mean
+ * of 3 replays), keep the fastest as the batch's configuration for ncols
+ * and return it (each output pointer may be NULL).  Synchronises on
+ * `stream`. */
 ahr_status ahr_batch_autotune(ahr_batch* b, const ahr_filter_spec* spec, int32_t ncols, void* stream,
                               int32_t* lanes_per_row, int32_t* col_tile, float* best_ms);
 void ahr_batch_destroy(ahr_batch* b);

@@ -551,7 +551,8 @@ ahr_status ahr_batch_set_config(ahr_batch* h, int32_t ncols, int32_t lanes_per_r
     if (!h) return fail(AHR_EINVAL, "batch is NULL");
     if (!ncols_ok(ncols)) return fail(AHR_EINVAL, "ncols must be 1, 2, 4 or 8");
     if (lanes_per_row != 0 && !pow2_lanes(lanes_per_row))
-        return fail(AHR_EINVAL, "lanes_per_row must be a power of two in [1, 64], or 0 for the default");
+        return fail(AHR_EINVAL,
+                    "lanes_per_row must be a power of two in [1, 64], AHR_HOP_ROW_BLOCK, or 0 for the default");
     if (col_tile != 0 && !tile_ok(ncols, col_tile))
         return fail(AHR_EINVAL, "col_tile must be a power of two dividing ncols, or 0 for ncols");
     auto* b = reinterpret_cast<Batch*>(h);
