@@ -136,3 +136,34 @@ def test_failed_hip_call_gives_edevice_and_no_handle():
     size = ctypes.c_size_t(7)
     assert lib.ahr_graph_workspace_size(ctypes.byref(nl), ctypes.byref(hp), 4, None, ctypes.byref(size)) == A.EDEVICE
     assert size.value == 7
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libahr.so not built")
+def test_hop_tune_values():
+    """The hop launch shape: AHR_HOP_AUTO by default, every documented value
+    accepted and read back, anything else refused with the setting kept
+    (host-only calls)."""
+    import paper_2511_10073_amd as A
+    lib = A.load()
+    saved = A.filter_get_tune()
+    try:
+        A.filter_tune(A.HOP_AUTO, 0)
+        for lanes in (1, 2, 4, 8, 16, 32, 64, A.HOP_ROW_BLOCK, A.HOP_AUTO):
+            A.filter_tune(lanes, -1)
+            assert A.filter_get_tune() == (lanes, 0)
+        A.filter_tune(0, 1)                                   # 0 keeps the shape
+        assert A.filter_get_tune() == (A.HOP_AUTO, 1)
+        for bad in (3, 128, -2, 512, 2048):
+            assert lib.ahr_filter_tune(bad, -1) == A.EINVAL
+            assert b"AHR_HOP_AUTO" in lib.ahr_last_error()
+            assert A.filter_get_tune() == (A.HOP_AUTO, 1)
+    finally:
+        A.filter_tune(*saved)
+
+
+def test_hop_auto_constants_match_the_header():
+    import paper_2511_10073_amd as A
+    src = open(HEADER).read()
+    for name in ("AHR_HOP_AUTO", "AHR_HOP_ROW_BLOCK", "AHR_LAYOUT_AUTO", "AHR_LAYOUT_NETLIST"):
+        v = int(re.search(r"#define\s+%s\s+(\d+)" % name, src).group(1))
+        assert getattr(A, name[4:]) == v, name
