@@ -35,8 +35,8 @@ HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("fil
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "sources_sha256": "1a8c5943121874dee90fc47392f33549cf0bbeb39d8b2550b458cac9241e15d7",
-               "bytes_per_launch": 1419304608,
+               "sources_sha256": "db6198cde266750c6f901f70bdd66a3a5d7f77369420a7d71ae2d08e60a2ec79",
+               "bytes_per_launch": 1419265731,
                "source": "profiles/k_hop_large-2.2M_l2_fabric_traffic.md"}
 
 
