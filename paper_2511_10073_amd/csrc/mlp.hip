@@ -221,31 +221,27 @@ __global__ void k_row_feat(int32_t n, const float* __restrict__ scale, const dou
                           d > 0 ? static_cast<float>(static_cast<double>(hsum[r]) / d) : 0.f, __int_as_float(code));
 }
 
-// Inputs of one tile's sample for lane group 0 (the hops, for features
-// 0..3 and the epilogue) or group 1 (the row values, for features 4..6);
-// the other groups feed zeros.
-struct TileIn {
+// One sample's inputs: the scaled hops z_j (h = z_j / s once the row's 1/s
+// is known) and the row inputs, none depending on another, so the next
+// group's loads are in flight while the current one runs through the
+// network.
+struct SampleIn {
     float h[4];
     float4 rf;
 };
 
-// The loads only: the scaled hops z_j (h = z_j / s once the row's 1/s is
-// known) and the row inputs, none depending on another, so a tile's loads
-// are all in flight while the previous tile runs through the network.
 template <int C>
-__device__ __forceinline__ TileIn tile_load(const LearnArgs& a, int64_t smp, int g) {
-    TileIn t;
+__device__ __forceinline__ SampleIn sample_load(const LearnArgs& a, int64_t smp) {
+    SampleIn t;
     const int64_t r = smp / C;
     t.h[0] = t.h[1] = t.h[2] = t.h[3] = 0.f;
     t.rf = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (r < a.n_inst && g < 2) {
+    if (r < a.n_inst) {
         t.rf = a.rowf[r];
-        if (g == 0) {
-            t.h[0] = a.z0[smp];
-            t.h[1] = a.z1[smp];
-            t.h[2] = a.z2[smp];
-            t.h[3] = a.z3[smp];
-        }
+        t.h[0] = a.z0[smp];
+        t.h[1] = a.z1[smp];
+        t.h[2] = a.z2[smp];
+        t.h[3] = a.z3[smp];
     }
     return t;
 }
@@ -254,8 +250,7 @@ __device__ __forceinline__ TileIn tile_load(const LearnArgs& a, int64_t smp, int
 // with s = 0 (isolated: every power of the operator keeps its value), which
 // is rare, so its dependent load sits in a branch of its own.
 template <int C>
-__device__ __forceinline__ void tile_unscale(const LearnArgs& a, TileIn& t, int64_t smp, int g) {
-    if (g != 0) return;
+__device__ __forceinline__ void sample_unscale(const LearnArgs& a, SampleIn& t, int64_t smp) {
     const float inv_s = t.rf.x;
     if (inv_s > 0.f) {
 #pragma unroll
@@ -267,48 +262,60 @@ __device__ __forceinline__ void tile_unscale(const LearnArgs& a, TileIn& t, int6
     }
 }
 
-// The learned filter over the instance rows: 16 samples (16/C rows x C
-// columns) per wavefront tile.  A lane's column is the same in every tile
-// (16 % C == 0), so its column statistics are loaded once; the next tile's
-// inputs are in flight while the current one runs through the network.
+// The learned filter over the instance rows, 64 samples (64/C rows x C
+// columns) per wavefront and step: each lane loads and featurises its own
+// sample (its column is the same at every step, as 64 % C == 0, so its
+// column statistics are loaded once), then the network runs the four
+// 16-sample matrix-core tiles in turn, each fed by shuffles (features 0..3
+// to lanes 0..15, features 4..7 to lanes 16..31), and every lane takes its
+// sample's result back and writes it.  The next step's loads are in flight
+// meanwhile.  A sample's result does not depend on its tile's other samples.
 template <int C>
 __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
     MlpRegs R;
     load_mlp(a.params, R);
-    const int l = lane_id(), g = l >> 4, sl = l & 15;
-    const int c = sl % C;
+    const int l = lane_id(), g = l >> 4, i = l & 15;
+    const int c = l % C;
     const float mc = a.stats[c], sc = a.stats[C + c], rc = a.stats[2 * C + c];
     const float inv_sc = 1.f / sc, inv_rc = 1.f / rc;
     const float lsr = static_cast<float>(log(static_cast<double>(sc) / static_cast<double>(rc)));
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBT / kWave);
-    const int64_t ntiles = (static_cast<int64_t>(a.n_inst) * C + 15) / 16;
+    const int64_t nsteps = (static_cast<int64_t>(a.n_inst) * C + kWave - 1) / kWave;
     int64_t t = static_cast<int64_t>(blockIdx.x) * (kBT / kWave) + wave_id();
-    TileIn cur = tile_load<C>(a, t * 16 + sl, g);
-    for (; t < ntiles; t += waves) {
-        const TileIn nxt = tile_load<C>(a, (t + waves) * 16 + sl, g);
-        tile_unscale<C>(a, cur, t * 16 + sl, g);
-        float f[4];
-        if (g == 0) {
-            f[0] = (cur.h[0] - cur.h[3]) * inv_rc;
-            f[1] = (cur.h[1] - cur.h[3]) * inv_rc;
-            f[2] = (cur.h[2] - cur.h[3]) * inv_rc;
-            f[3] = (cur.h[3] - mc) * inv_sc;
-        } else if (g == 1) {
-            f[0] = cur.rf.y;
-            f[1] = cur.rf.z;
-            f[2] = lsr;
-            f[3] = 0.f;
-        } else {
-            f[0] = f[1] = f[2] = f[3] = 0.f;
+    SampleIn cur = sample_load<C>(a, t * kWave + l);
+    for (; t < nsteps; t += waves) {
+        const SampleIn nxt = sample_load<C>(a, (t + waves) * kWave + l);
+        const int64_t smp = t * kWave + l;
+        sample_unscale<C>(a, cur, smp);
+        float F[8];
+        F[0] = (cur.h[0] - cur.h[3]) * inv_rc;
+        F[1] = (cur.h[1] - cur.h[3]) * inv_rc;
+        F[2] = (cur.h[2] - cur.h[3]) * inv_rc;
+        F[3] = (cur.h[3] - mc) * inv_sc;
+        F[4] = cur.rf.y;
+        F[5] = cur.rf.z;
+        F[6] = lsr;
+        F[7] = 0.f;
+        float mine = 0.f;
+#pragma unroll
+        for (int j = 0; j < kWave / 16; ++j) {
+            const int src = 16 * j + i;
+            float f[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float lo = __shfl(F[k], src), hi = __shfl(F[4 + k], src);
+                f[k] = g == 0 ? lo : (g == 1 ? hi : 0.f);
+            }
+            const float o = __shfl(mlp_tile(R, f), i);     // tile j's result for sample 16 j + i
+            if (g == j) mine = o;
         }
-        const float o = mlp_tile(R, f);
-        const int64_t r = (t * 16 + sl) / C;
-        if (l < 16 && r < a.n_inst) {
+        const int64_t r = smp / C;
+        if (r < a.n_inst) {
             const int code = __float_as_int(cur.rf.w), inst = row_inst(code);
             const int64_t oc = static_cast<int64_t>(inst) * C + c;
             if (a.feats) {
                 float* fp = a.feats + oc * kFP;
-                fp[0] = f[0], fp[1] = f[1], fp[2] = f[2], fp[3] = f[3];
+                fp[0] = F[0], fp[1] = F[1], fp[2] = F[2], fp[3] = F[3];
             }
             if (a.hops) {
                 const int64_t nc = static_cast<int64_t>(a.n_inst) * C;
@@ -317,7 +324,7 @@ __global__ void __launch_bounds__(kBT) k_mlp_learned(LearnArgs a) {
             }
             if (a.write_out) {
                 float y = a.beta[0] * cur.h[0] + a.beta[1] * cur.h[1] + a.beta[2] * cur.h[2] + a.beta[3] * cur.h[3] +
-                          rc * o;
+                          rc * mine;
                 a.out[oc] = row_fixed(code) ? a.in[oc] : y;
             }
         }
