@@ -443,10 +443,13 @@ ahr_status ahr_mlp_forward(const float* params, const float* feats, int64_t n, f
 
 /* Training: *loss (device double, may be NULL) = mean_k (MLP(feats[k]) -
  * target[k])^2 and grad (device [AHR_MLP_NPARAM]) its gradient, float32
- * forward with the inference's bfloat16 rounding points, straight-through
- * gradients, fixed-order (deterministic) reductions. */
+ * arithmetic, fixed-order (deterministic) reductions.  rounding = 1: the
+ * inference's bfloat16 rounding points (weights, features, hidden
+ * activations) with straight-through gradients, as training uses;
+ * rounding = 0: float32 operands throughout (for checking the gradient
+ * against a float64 reference without rounding).  Other values: AHR_EINVAL. */
 ahr_status ahr_mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n,
-                             float* grad, double* loss, void* stream);
+                             float* grad, double* loss, int32_t rounding, void* stream);
 
 /* One Adam step (step >= 1) on params with moments m, v (all device
  * [AHR_MLP_NPARAM]). */

@@ -165,7 +165,7 @@ def load() -> ctypes.CDLL:
         "ahr_refine_learned": [vp, ctypes.POINTER(_FilterSpec), ctypes.POINTER(_Mlp), vp, i32, i32, ctypes.c_float, vp,
                                ctypes.POINTER(i32), vp],
         "ahr_mlp_forward": [vp, vp, ctypes.c_int64, vp, vp],
-        "ahr_mlp_loss_grad": [vp, vp, vp, ctypes.c_int64, vp, vp, vp],
+        "ahr_mlp_loss_grad": [vp, vp, vp, ctypes.c_int64, vp, vp, i32, vp],
         "ahr_mlp_adam": [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp],
         "ahr_batch_build": [vp, vp, i32, vp, i32, vp, ctypes.POINTER(vp)],
         "ahr_batch_get_info": [vp, ctypes.POINTER(_BatchInfo)],
@@ -246,15 +246,16 @@ def mlp_forward(params, feats, out=None, stream=None):
     return out
 
 
-def mlp_loss_grad(params, feats, target, grad=None, loss=None, stream=None):
-    """(grad, loss) of mean (MLP(feats) - target)^2; both stay on the device."""
+def mlp_loss_grad(params, feats, target, grad=None, loss=None, rounding=True, stream=None):
+    """(grad, loss) of mean (MLP(feats) - target)^2; both stay on the device.
+    rounding=False: float32 operands instead of the bfloat16 rounding points."""
     n = feats.shape[0]
     if grad is None:
         grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=params.device)
     if loss is None:
         loss = torch.empty(1, dtype=torch.float64, device=params.device)
     _check(load().ahr_mlp_loss_grad(_ptr(params), _ptr(feats), _ptr(target), n, _ptr(grad), _ptr(loss),
-                                    _stream(stream)))
+                                    1 if rounding else 0, _stream(stream)))
     return grad, loss
 
 

@@ -394,7 +394,7 @@ void run_learned(Graph& g, const ahr_filter_spec& spec, const float* params, con
                  float* out, int32_t ncols, float* feats, float* hops, float* stats, hipStream_t s);
 void mlp_forward(const float* params, const float* feats, int64_t n, float* o, hipStream_t s);
 void mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n, float* grad,
-                   double* loss, hipStream_t s);
+                   double* loss, bool rounding, hipStream_t s);
 void mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr, float b1, float b2,
               float eps, hipStream_t s);
 

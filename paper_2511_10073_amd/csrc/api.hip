@@ -638,11 +638,12 @@ ahr_status ahr_mlp_forward(const float* params, const float* feats, int64_t n, f
 }
 
 ahr_status ahr_mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n, float* grad,
-                             double* loss, void* stream) {
+                             double* loss, int32_t rounding, void* stream) {
     if (!params || !grad || (n > 0 && (!feats || !target))) return fail(AHR_EINVAL, "NULL argument");
     if (n < 0) return fail(AHR_EINVAL, "n must be >= 0");
+    if (rounding != 0 && rounding != 1) return fail(AHR_EINVAL, "rounding must be 0 or 1");
     return guarded([&]() -> ahr_status {
-        ahr::mlp_loss_grad(params, feats, target, n, grad, loss, as_stream(stream));
+        ahr::mlp_loss_grad(params, feats, target, n, grad, loss, rounding != 0, as_stream(stream));
         return AHR_OK;
     });
 }

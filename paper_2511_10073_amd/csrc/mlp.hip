@@ -427,6 +427,15 @@ __global__ void __launch_bounds__(kBT) k_colstat_final(LearnArgs a, const double
 constexpr int kTS = 32;           // samples per tile
 constexpr int kGradGrid = 240;    // workgroups (fixed: fixes the summation order)
 
+// Q: the inference's bfloat16 rounding points (weights, features, hidden
+// activations); without, float32 operands throughout.
+template <bool Q>
+__device__ __forceinline__ float qround(float x) {
+    if constexpr (Q) return bf16_round(x);
+    else return x;
+}
+
+template <bool Q>
 __global__ void __launch_bounds__(kBT) k_mlp_grad(const float* __restrict__ P, const float* __restrict__ feats,
                                                   const float* __restrict__ target, int64_t n, float inv_n,
                                                   float* __restrict__ part, double* __restrict__ loss_part) {
@@ -436,10 +445,10 @@ __global__ void __launch_bounds__(kBT) k_mlp_grad(const float* __restrict__ P, c
     __shared__ float dO[kTS];
     __shared__ double red[kBT / kWave];
     const int t = threadIdx.x;
-    for (int e = t; e < kH * kFP; e += kBT) W1q[e] = bf16_round(P[oW1 + e]);
-    for (int e = t; e < kH * kH; e += kBT) W2q[e] = bf16_round(P[oW2 + e]);
+    for (int e = t; e < kH * kFP; e += kBT) W1q[e] = qround<Q>(P[oW1 + e]);
+    for (int e = t; e < kH * kH; e += kBT) W2q[e] = qround<Q>(P[oW2 + e]);
     if (t < kH) {
-        w3q[t] = bf16_round(P[oW3 + t]);
+        w3q[t] = qround<Q>(P[oW3 + t]);
         b1[t] = P[oB1 + t];
         b2[t] = P[oB2 + t];
     }
@@ -455,7 +464,7 @@ __global__ void __launch_bounds__(kBT) k_mlp_grad(const float* __restrict__ P, c
         {
             int s = t / kFP, f = t % kFP;
             int64_t smp = s0 + s;
-            X[s][f] = smp < n ? bf16_round(feats[smp * kFP + f]) : 0.f;
+            X[s][f] = smp < n ? qround<Q>(feats[smp * kFP + f]) : 0.f;
         }
         __syncthreads();
         for (int q = 0; q < 8; ++q) {
@@ -463,7 +472,7 @@ __global__ void __launch_bounds__(kBT) k_mlp_grad(const float* __restrict__ P, c
             float z = b1[h];
             for (int f = 0; f < kFP; ++f) z = __fmaf_rn(X[s][f], W1q[h * kFP + f], z);
             Z1[s][h] = z;
-            A1[s][h] = bf16_round(z > 0.f ? z : 0.f);
+            A1[s][h] = qround<Q>(z > 0.f ? z : 0.f);
         }
         __syncthreads();
         for (int q = 0; q < 8; ++q) {
@@ -478,7 +487,7 @@ __global__ void __launch_bounds__(kBT) k_mlp_grad(const float* __restrict__ P, c
             float o = b3;
             for (int h = 0; h < kH; ++h) {
                 float z = Z2[t][h];
-                o = __fmaf_rn(bf16_round(z > 0.f ? z : 0.f), w3q[h], o);
+                o = __fmaf_rn(qround<Q>(z > 0.f ? z : 0.f), w3q[h], o);
             }
             if (smp < n) {
                 float e = o - target[smp];
@@ -506,7 +515,7 @@ __global__ void __launch_bounds__(kBT) k_mlp_grad(const float* __restrict__ P, c
             int h = t - 2 * kH;
             for (int s = 0; s < kTS; ++s) {
                 float z = Z2[s][h];
-                gv = __fmaf_rn(dO[s], bf16_round(z > 0.f ? z : 0.f), gv);
+                gv = __fmaf_rn(dO[s], qround<Q>(z > 0.f ? z : 0.f), gv);
             }
         } else if (t == 3 * kH) {
             for (int s = 0; s < kTS; ++s) gv += dO[s];
@@ -654,13 +663,18 @@ void mlp_forward(const float* params, const float* feats, int64_t n, float* o, h
 }
 
 void mlp_loss_grad(const float* params, const float* feats, const float* target, int64_t n, float* grad,
-                   double* loss, hipStream_t s) {
+                   double* loss, bool rounding, hipStream_t s) {
     DevBuf<float> part;
     DevBuf<double> lpart;
     part.ensure(static_cast<size_t>(kGradGrid) * kNP, s);
     lpart.ensure(kGradGrid, s);
-    hipLaunchKernelGGL(k_mlp_grad, dim3(kGradGrid), dim3(kBT), 0, s, params, feats, target, n,
-                       n > 0 ? 1.f / static_cast<float>(n) : 0.f, part.p, lpart.p);
+    const float inv_n = n > 0 ? 1.f / static_cast<float>(n) : 0.f;
+    if (rounding)
+        hipLaunchKernelGGL(k_mlp_grad<true>, dim3(kGradGrid), dim3(kBT), 0, s, params, feats, target, n, inv_n,
+                           part.p, lpart.p);
+    else
+        hipLaunchKernelGGL(k_mlp_grad<false>, dim3(kGradGrid), dim3(kBT), 0, s, params, feats, target, n, inv_n,
+                           part.p, lpart.p);
     AHR_LAUNCHED("k_mlp_grad");
     hipLaunchKernelGGL(k_mlp_grad_final, dim3(grid_for(kNP, kBT)), dim3(kBT), 0, s, part.p, lpart.p,
                        n > 0 ? 1.0 / static_cast<double>(n) : 0.0, grad, loss);

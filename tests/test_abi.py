@@ -63,6 +63,9 @@ def test_invalid_arguments_fail_before_any_device_work():
     assert lib.ahr_refine(ctypes.byref(nl2), ctypes.byref(hp), ctypes.byref(spec), 8, 2, 1, 1.5, 16, None, 0,
                           None) == A.EINVAL
     assert h.value is None
+    # the gradient's rounding mode is 0 or 1
+    assert lib.ahr_mlp_loss_grad(8, 8, 8, 4, 8, None, 2, None) == A.EINVAL
+    assert b"rounding" in lib.ahr_last_error()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libahr.so not built")

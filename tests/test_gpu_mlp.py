@@ -75,6 +75,28 @@ def test_mlp_grad_matches_oracle():
         assert e <= 1e-3, (name, e)
 
 
+def test_mlp_grad_float32_mode_matches_oracle():
+    """Without the bfloat16 rounding points both sides compute the same
+    function; the float32 gradient then matches the float64 one to 1e-5,
+    overall and per parameter block."""
+    p = rand_params(7)
+    F = rand_feats(4099, 8)
+    r = np.random.default_rng(9).normal(0, 1, 4099).astype(np.float32)
+    g, loss = A.mlp_loss_grad(torch.as_tensor(p).cuda(), torch.as_tensor(F).cuda(), torch.as_tensor(r).cuda(),
+                              rounding=False)
+    g = g.cpu().numpy().astype(np.float64)
+    loss_ref, g_ref = M.loss_grad(p.astype(np.float64), F[:, :M.NFEAT].astype(np.float64), r.astype(np.float64),
+                                  rounding=False)
+    assert abs(float(loss.cpu()) - loss_ref) <= 1e-6 * loss_ref
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print("float32-mode grad rel err", err)
+    assert err <= 1e-5
+    for name in ("W1", "b1", "W2", "b2", "w3", "b3"):
+        o, n = M.OFFSETS[name]
+        e = np.linalg.norm(g[o:o + n] - g_ref[o:o + n]) / max(np.linalg.norm(g_ref[o:o + n]), 1e-30)
+        assert e <= 1e-5, (name, e)
+
+
 @pytest.fixture(scope="module")
 def small():
     nl = N.generate(N.small(6000, 31, ncols=4))
