@@ -35,8 +35,8 @@ HOP_SRCS = [os.path.join(ROOT, "paper_2511_10073_amd", "csrc", f) for f in ("fil
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters for a 1 GiB device
 # copy; valid only for the hop and layout sources they were taken with.
 HOP_TRAFFIC = {"workload": "large-2.2M",
-               "sources_sha256": "db6198cde266750c6f901f70bdd66a3a5d7f77369420a7d71ae2d08e60a2ec79",
-               "bytes_per_launch": 1419265731,
+               "sources_sha256": "987462926ef64ed24c05d786a7f7b76961cceff49a418d359935575d049beb3b",
+               "bytes_per_launch": 1419557188,
                "source": "profiles/k_hop_large-2.2M_l2_fabric_traffic.md"}
 
 

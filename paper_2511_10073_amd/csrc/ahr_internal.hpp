@@ -288,7 +288,7 @@ struct Graph {
     // locality of the execution order (set with the layout, read with the
     // first row classes): 1 local, 0 not, -1 not read yet
     int32_t hop_local = -1;
-    DevBuf<unsigned long long> loc_tally;   // [2] sampled entries near their row, all sampled entries
+    DevBuf<int64_t> loc_part;               // [2 per workgroup] sampled entries near their row, all sampled
     DevBuf<int32_t> loc_flag;               // [1] the verdict on the device
     DevBuf<int32_t> perm, iperm;  // [n_tot]: identity on the virtual rows
     DevBuf<int4> xmpin;           // [n_mpin] per execution macro pin row: owner, offset x, y (float bits)

@@ -44,7 +44,7 @@ Graph::~Graph() {
                               &nmac, &nwin, &bin_rank, &wpre, &pair_off, &pair_row, &pair_mac, &mlist, &mstart,
                               &big_stars, &i32a, &i32b, &counter, &kept, &loc_flag};
     for (auto* b : i32) b->release(s);
-    loc_tally.release(s);
+    loc_part.release(s);
     keep_mask.release(s);
     net_q.release(s);
     net_off.release(s);

@@ -503,20 +503,25 @@ __global__ void k_hi12(int32_t n, const int32_t* __restrict__ key, const int32_t
 }
 
 // Locality of a layout: of a sample of instance rows (every kSample-th
-// instance), how many instance-to-instance entries lie within `near`
-// execution rows of their row; [0] near, [1] all.
+// instance, kNearLanes lanes each), how many instance-to-instance entries
+// lie within `near` execution rows of their row.  Each workgroup writes its
+// counts (near, all) to part[2 b], part[2 b + 1].
+constexpr int kNearLanes = 8;
+
 __global__ void __launch_bounds__(kBT) k_near_count(int32_t n_inst, int32_t nearw, const int64_t* __restrict__ off,
-                             const int32_t* __restrict__ len,
-                             const int32_t* __restrict__ col, const int32_t* __restrict__ iperm,
-                             unsigned long long* __restrict__ tally) {
+                                                    const int32_t* __restrict__ len,
+                                                    const int32_t* __restrict__ col, const int32_t* __restrict__ iperm,
+                                                    int64_t* __restrict__ part) {
+    __shared__ int64_t red[kBT / kWave];
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t v = t * kSample;
-    unsigned long long near = 0, all = 0;
+    const int64_t v = (t / kNearLanes) * kSample;
+    const int ln = threadIdx.x & (kNearLanes - 1);
+    int64_t near = 0, all = 0;
     if (v < n_inst) {
         const int rv = iperm[v];
         const int64_t o = off[v];
         const int l = len[v];
-        for (int j = 0; j < l; ++j) {
+        for (int j = ln; j < l; j += kNearLanes) {
             const int c = col[o + j];
             if (c >= n_inst) continue;
             const int d = iperm[c] - rv;
@@ -524,34 +529,27 @@ __global__ void __launch_bounds__(kBT) k_near_count(int32_t n_inst, int32_t near
             ++all;
         }
     }
-    __shared__ unsigned long long red[2][kBT / kWave];
-    near = wave_sum(near);
-    all = wave_sum(all);
-    if (lane_id() == 0) {
-        red[0][wave_id()] = near;
-        red[1][wave_id()] = all;
-    }
-    __syncthreads();
+    near = block_sum_i64<kBT>(near, red);
+    all = block_sum_i64<kBT>(all, red);
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kBT / kWave; ++w) {
-            near += red[0][w];
-            all += red[1][w];
-        }
-        if (all) {
-            atomicAdd(&tally[0], near);
-            atomicAdd(&tally[1], all);
-        }
+        part[2 * blockIdx.x] = near;
+        part[2 * blockIdx.x + 1] = all;
     }
 }
 
-__global__ void k_fill_u64_2(unsigned long long* p) {
-    if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
-}
-
-// The verdict: local when at least a quarter of the sampled entries are near
-// their row (or nothing was sampled).
-__global__ void k_loc_flag(const unsigned long long* __restrict__ tally, int32_t* __restrict__ flag) {
-    if (threadIdx.x == 0) flag[0] = (tally[1] == 0ull || 4ull * tally[0] >= tally[1]) ? 1 : 0;
+// The verdict from the workgroups' counts: local when at least a quarter of
+// the sampled entries are near their row (or nothing was sampled).
+__global__ void __launch_bounds__(kBT) k_loc_flag(const int64_t* __restrict__ part, int32_t nparts,
+                                                  int32_t* __restrict__ flag) {
+    __shared__ int64_t red[kBT / kWave];
+    int64_t near = 0, all = 0;
+    for (int b = threadIdx.x; b < nparts; b += kBT) {
+        near += part[2 * b];
+        all += part[2 * b + 1];
+    }
+    near = block_sum_i64<kBT>(near, red);
+    all = block_sum_i64<kBT>(all, red);
+    if (threadIdx.x == 0) flag[0] = (all == 0 || 4 * near >= all) ? 1 : 0;
 }
 
 }  // namespace
@@ -629,16 +627,16 @@ static void position_order(Graph& g, const float* pos, int32_t ncols, hipStream_
 // within n/64 rows (at least 256) of their row.  g.hop_local is read later.
 static void locality_begin(Graph& g, hipStream_t s) {
     const int32_t n = g.n_inst;
-    g.loc_tally.ensure(2, s);
-    g.loc_flag.ensure(1, s);
-    hipLaunchKernelGGL(k_fill_u64_2, dim3(1), dim3(64), 0, s, g.loc_tally.p);
-    AHR_LAUNCHED("k_fill_u64_2");
     const int64_t nt = (static_cast<int64_t>(n) + kSample - 1) / kSample;
+    const unsigned blocks = grid_for(nt * kNearLanes, kBT);
+    g.loc_part.ensure(2 * static_cast<size_t>(blocks), s);
+    g.loc_flag.ensure(1, s);
     const int32_t nearw = n / 64 > 256 ? n / 64 : 256;
-    hipLaunchKernelGGL(k_near_count, dim3(grid_for(nt, kBT)), dim3(kBT), 0, s, n, nearw, g.net_off.p, g.net_len.p,
-                       g.net_col.p, g.iperm.p, g.loc_tally.p);
+    hipLaunchKernelGGL(k_near_count, dim3(blocks), dim3(kBT), 0, s, n, nearw, g.net_off.p, g.net_len.p,
+                       g.net_col.p, g.iperm.p, g.loc_part.p);
     AHR_LAUNCHED("k_near_count");
-    hipLaunchKernelGGL(k_loc_flag, dim3(1), dim3(64), 0, s, g.loc_tally.p, g.loc_flag.p);
+    hipLaunchKernelGGL(k_loc_flag, dim3(1), dim3(kBT), 0, s, g.loc_part.p, static_cast<int32_t>(blocks),
+                       g.loc_flag.p);
     AHR_LAUNCHED("k_loc_flag");
     g.hop_local = -1;
 }
