@@ -92,9 +92,10 @@ typedef struct ahr_netlist {
  * keep the Hilbert order); AHR_LAYOUT_AUTO takes that order only where fewer
  * than a quarter of a sample of those edges join rows within n_inst/64 rows
  * (at least 256) of each other in the Hilbert order.  The netlist order costs
- * about 2 ms per graph build at 2.2M cells and halves the hop's time where
- * the placement carries no locality, so it pays where one graph is filtered
- * several times from such a placement.  ahr_graph_info.layout reports the
+ * about 2 ms per graph build at 2.2M cells and cuts the hop's time by about
+ * a third where the placement carries no locality (uniformly drawn
+ * positions), so it pays where one graph is filtered several times from
+ * such a placement.  ahr_graph_info.layout reports the
  * order taken. */
 #define AHR_LAYOUT_AUTO 8u
 #define AHR_LAYOUT_NETLIST 16u
