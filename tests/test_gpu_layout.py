@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import gpu_common as U
+from netlists import make
 from oracle import ahr_oracle as O
 from synth import netlist as N
 
@@ -89,6 +90,44 @@ def test_filter_same_bits_across_calls_under_netlist_order(case):
     a = gr.filter(U.to_c_spec(A, BANK), gpos)
     b = gr.filter(U.to_c_spec(A, BANK), gpos)
     assert torch.equal(a, b)
+
+
+def components():
+    """Two rings, a path, a 14-pin net (a star: no instance-to-instance
+    edge) and isolated cells: the netlist order reaches one component from
+    its start and appends the other instances in id order."""
+    nets = [[i, (i + 1) % 10] for i in range(10)] + [[10 + i, 10 + (i + 1) % 10] for i in range(10)]
+    nets += [[20 + i, 21 + i] for i in range(5)] + [list(range(26, 40))]
+    return make(nets, 45, ncols=4)
+
+
+@pytest.mark.parametrize("which", ["components", "no-nets", "one-instance"])
+def test_netlist_order_on_degenerate_netlists(which):
+    nl = {"components": components, "no-nets": lambda: make([], 30, ncols=4),
+          "one-instance": lambda: make([[0]], 1, ncols=2)}[which]()
+    p = U.params32(O.HintParams(nbx=3, nby=3, detection_ratio=0.5))
+    og = O.build_graph(nl, p, nl["g0"][:, :2])
+    net = A.Netlist(nl)
+    x = torch.as_tensor(nl["g0"]).cuda()
+    gr = A.Graph(net, params(A, p, A.LAYOUT_NETLIST), x)
+    try:
+        assert gr.info()["layout"] == 1
+        ex = gr.export()
+        assert np.array_equal(ex["net_row_ptr"], og.net_row_ptr.astype(np.int32))
+        assert np.array_equal(ex["hint_row_ptr"], og.hint_row_ptr.astype(np.int32))
+        out = gr.filter(U.to_c_spec(A, BANK), x).cpu().numpy()
+        again = gr.filter(U.to_c_spec(A, BANK), x).cpu().numpy()
+    finally:
+        gr.close()
+    assert np.array_equal(out, again)
+    mov = U.movable_rows(nl)
+    assert np.array_equal(out[~mov], nl["g0"][~mov])
+    ref = np.asarray(O.apply_filter(nl, og, BANK, nl["g0"]), np.float64)
+    if np.linalg.norm(ref[mov] - ref[mov].mean(axis=0)) == 0:      # one row: no centred scale
+        assert np.allclose(out[mov], ref[mov], rtol=1e-6, atol=1e-6)
+    else:
+        err = U.check_filter(out, ref, mov)
+        print(f"[{which}] filter rel err {err:.3e}")
 
 
 def test_automatic_choice():
